@@ -1,0 +1,121 @@
+/*
+ * boruta_oracle.h -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, single-definition CPU reference of one Boruta feature
+ * selection run (Boruta main loop, Algorithm 1; impurity importance,
+ * Algorithm 2 of Sec. 2.1; out-of-bag permutation importance in Kursa's
+ * sense, Sec. 2), written to check the HIP implementation against.  Only the
+ * test suite, the smoke check and the CPU-baseline leg of the benchmark may
+ * load it.  It shares no code, header or constant table with the GPU
+ * library; both are written independently from the same stated definitions.
+ *
+ * All functions are thread-safe; none keeps global state.  Return codes:
+ * 0 ok, -1 invalid argument, -2 non-finite value in X.
+ */
+#ifndef BORUTA_ORACLE_H
+#define BORUTA_ORACLE_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Per-iteration record handed to a trace callback (host memory, valid only
+ * during the call).  Nodes are listed in (tree, heap id) order. */
+typedef struct {
+    int32_t t;              /* iteration, 1-based                                  */
+    int32_t p_cur;          /* active original columns (state >= 0)                */
+    int32_t n_sha;          /* shadow columns                                      */
+    int32_t p_w;            /* widened width p_cur + n_sha                         */
+    int32_t mtry;           /* features drawn per node this iteration              */
+    int32_t n_trees;        /* trees grown (all, or the requested subset)          */
+    const int32_t* col_src; /* [p_w] original feature index behind widened column  */
+    const int64_t* imp_int; /* [p_w] integer importance: TreeImp sum of per-tree
+                               fixed-point shares, or Permut accuracy-drop count   */
+    const int32_t* hits;    /* [p] hit counts after this iteration                 */
+    const int8_t* state;    /* [p] decisions after this iteration                  */
+    const int64_t* tree_stats; /* [n_trees][5]: tree id, distinct in-bag rows,
+                                  OOB rows, OOB correct, node count               */
+    int64_t n_nodes;
+    const int64_t* nodes;   /* [n_nodes][6]: tree, heap id, feature (-1 = leaf),
+                               threshold bin (leaf: predicted class), weighted
+                               count N, Gini decrease in 2^-32 units (0 leaf)      */
+} oracle_iter_trace;
+
+typedef void (*oracle_trace_fn)(void* user, const oracle_iter_trace* tr);
+
+/* Philox4x32-10 block function: out = Philox(ctr, key). */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Keyed bijection of [0, m) (Feistel over Philox, cycle walking). */
+uint64_t oracle_keyed_perm(uint64_t seed, uint32_t stream, uint32_t t, uint32_t a,
+                           uint32_t b, uint32_t c_hi, uint64_t m, uint64_t x);
+
+/* Quantile binning of row-major X[n][p] into column-major bins[p][n]. */
+int oracle_bin(const float* X, int64_t n, int64_t p, int32_t n_bins,
+               uint8_t* bins_out, float* cuts_out /* [p][n_bins-1], nullable */,
+               int32_t* ncuts_out /* [p], nullable */);
+
+/* Bootstrap multiplicities of tree `tree` at iteration t: w_out[n]. */
+void oracle_bootstrap(uint64_t seed, uint32_t t, uint32_t tree, int64_t n, uint32_t* w_out);
+
+/* Best split of one node (exact rule, draw-order tie-break).  rows: the
+ * node's distinct rows ascending; w: per-row multiplicity (indexed by row);
+ * feats: candidate widened columns in draw order.  bins column-major
+ * [p_w][n].  Writes {found, q, b, N_L, S_L, N_R, S_R, gain_fix} to out[8]
+ * (found = 1 iff a valid candidate with strictly positive gain exists; q is
+ * the position in feats; gain_fix = floor(2^32 * Gini decrease)). */
+int oracle_best_split(const uint8_t* bins, int64_t n, const int32_t* y,
+                      const uint32_t* w, const uint32_t* rows, int64_t n_rows,
+                      const int32_t* feats, int32_t n_feats, int32_t n_classes,
+                      int32_t n_bins, uint64_t out[8]);
+
+/* Grow one tree on explicit binned data with explicit multiplicities w[n]
+ * (rows with w = 0 are out of bag).  Feature draws use the MTRY stream
+ * keyed by (seed, t, tree, heap id) over [0, p_w).  Writes up to
+ * max_nodes rows of 6 int64 like oracle_iter_trace.nodes; returns the node
+ * count (or a negative error).  gain_sum_out[p_w] (nullable) receives the
+ * per-feature sum of fixed-point Gini decreases. */
+int64_t oracle_grow_tree(const uint8_t* bins, int64_t n, int64_t p_w, const int32_t* y,
+                         const uint32_t* w, int32_t n_classes, int32_t n_bins,
+                         int32_t max_depth, int32_t mtry, uint64_t seed, uint32_t t,
+                         uint32_t tree, int64_t* nodes_out, int64_t max_nodes,
+                         uint64_t* gain_sum_out);
+
+/* Exact Bonferroni binomial decision for one feature: returns 1 (confirm),
+ * -1 (reject) or 0, for `hits` hits in t trials, p features, level alpha. */
+int oracle_binom_decide(int32_t hits, int32_t t, int64_t p, double alpha);
+
+/* Full run.  mode 0 = TreeImp, 1 = Permut.  n_threads 0 = all cores.
+ * permut_naive = 1 re-traverses every (tree, column, replica, OOB row) in
+ * full instead of only the columns on the row's path (same integers).
+ * imp_history_out is [max_iter][p]; rows past n_iter are left untouched. */
+int oracle_boruta_fit(const float* X, const int32_t* y, int64_t n, int64_t p,
+                      int32_t n_classes, int32_t n_trees, int32_t max_depth,
+                      int32_t mtry, int32_t importance_mode, int32_t max_iter,
+                      double alpha, uint64_t seed, int32_t n_bins, int32_t n_perm,
+                      int32_t n_threads, int32_t permut_naive,
+                      int8_t* decision_out, double* imp_history_out,
+                      int32_t* hits_out, double* shadow_max_out, int32_t* n_iter_out,
+                      oracle_trace_fn trace, void* trace_user);
+
+/* One iteration t from a given (state, hits): the state machine of Algorithm
+ * 1 is memoryless apart from these two vectors, so any iteration of a run
+ * can be recomputed alone.  state/hits are updated in place.  tree_subset
+ * (nullable) restricts growth to the listed trees; importances, hits and
+ * the decision are then left untouched and only the trace's trees are
+ * meaningful.  imp_row_out[p] / shadow_max_out[1] are nullable. */
+int oracle_boruta_step(const float* X, const int32_t* y, int64_t n, int64_t p,
+                       int32_t n_classes, int32_t n_trees, int32_t max_depth,
+                       int32_t mtry, int32_t importance_mode, double alpha,
+                       uint64_t seed, int32_t n_bins, int32_t n_perm, int32_t t,
+                       int8_t* state, int32_t* hits, const int32_t* tree_subset,
+                       int32_t n_subset, int32_t n_threads, int32_t permut_naive,
+                       double* imp_row_out, double* shadow_max_out,
+                       oracle_trace_fn trace, void* trace_user);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

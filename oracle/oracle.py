@@ -1,0 +1,214 @@
+"""TEST INFRASTRUCTURE ONLY: ctypes bindings to the CPU oracle.
+
+The oracle (``boruta_oracle.cpp``) is a plain, slow CPU reference of one
+Boruta run (Algorithm 1; impurity importance of Algorithm 2, Sec. 2.1;
+out-of-bag permutation importance, Sec. 2 and 2.2).  Only the tests, the
+smoke check and the CPU-baseline leg of the benchmark may import this module.
+It shares no code with the HIP library.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "boruta_oracle.cpp")
+LIB = os.path.join(HERE, "liboracle_boruta.so")
+
+STREAM_BOOT, STREAM_MTRY, STREAM_SHADOW, STREAM_OOBPERM = 1, 2, 3, 4
+
+
+def build():
+    """Compile the oracle with g++ (plain C++17, no fused multiply-add)."""
+    cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-shared", "-fPIC",
+           "-pthread", SRC, "-o", LIB + ".tmp"]
+    subprocess.check_call(cmd)
+    os.replace(LIB + ".tmp", LIB)
+
+
+class IterTrace(ctypes.Structure):
+    _fields_ = [
+        ("t", ctypes.c_int32), ("p_cur", ctypes.c_int32), ("n_sha", ctypes.c_int32),
+        ("p_w", ctypes.c_int32), ("mtry", ctypes.c_int32), ("n_trees", ctypes.c_int32),
+        ("col_src", ctypes.POINTER(ctypes.c_int32)),
+        ("imp_int", ctypes.POINTER(ctypes.c_int64)),
+        ("hits", ctypes.POINTER(ctypes.c_int32)),
+        ("state", ctypes.POINTER(ctypes.c_int8)),
+        ("tree_stats", ctypes.POINTER(ctypes.c_int64)),
+        ("n_nodes", ctypes.c_int64),
+        ("nodes", ctypes.POINTER(ctypes.c_int64)),
+    ]
+
+
+TRACE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.POINTER(IterTrace))
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        i32, i64, u32, u64, f64 = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                   ctypes.c_uint64, ctypes.c_double)
+        L.oracle_philox4x32_10.argtypes = [P, P, P]
+        L.oracle_philox4x32_10.restype = None
+        L.oracle_keyed_perm.argtypes = [u64, u32, u32, u32, u32, u32, u64, u64]
+        L.oracle_keyed_perm.restype = u64
+        L.oracle_bin.argtypes = [P, i64, i64, i32, P, P, P]
+        L.oracle_bin.restype = i32
+        L.oracle_bootstrap.argtypes = [u64, u32, u32, i64, P]
+        L.oracle_bootstrap.restype = None
+        L.oracle_best_split.argtypes = [P, i64, P, P, P, i64, P, i32, i32, i32, P]
+        L.oracle_best_split.restype = i32
+        L.oracle_grow_tree.argtypes = [P, i64, i64, P, P, i32, i32, i32, i32, u64, u32, u32,
+                                       P, i64, P]
+        L.oracle_grow_tree.restype = i64
+        L.oracle_binom_decide.argtypes = [i32, i32, i64, f64]
+        L.oracle_binom_decide.restype = i32
+        L.oracle_boruta_fit.argtypes = [P, P, i64, i64, i32, i32, i32, i32, i32, i32, f64, u64,
+                                        i32, i32, i32, i32, P, P, P, P, P, TRACE_FN, P]
+        L.oracle_boruta_fit.restype = i32
+        L.oracle_boruta_step.argtypes = [P, P, i64, i64, i32, i32, i32, i32, i32, f64, u64, i32,
+                                         i32, i32, P, P, P, i32, i32, i32, P, P, TRACE_FN, P]
+        L.oracle_boruta_step.restype = i32
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().oracle_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def keyed_perm(seed, stream, t, a, b, c_hi, m, x):
+    return int(lib().oracle_keyed_perm(seed, stream, t, a, b, c_hi, m, x))
+
+
+def bin_matrix(X, n_bins):
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    n, p = X.shape
+    bins = np.zeros((p, n), dtype=np.uint8)
+    cuts = np.zeros((p, n_bins - 1), dtype=np.float32)
+    ncuts = np.zeros(p, dtype=np.int32)
+    rc = lib().oracle_bin(_ptr(X), n, p, n_bins, _ptr(bins), _ptr(cuts), _ptr(ncuts))
+    if rc:
+        raise ValueError(f"oracle_bin failed: {rc}")
+    return bins, cuts, ncuts
+
+
+def bootstrap(seed, t, tree, n):
+    w = np.zeros(n, dtype=np.uint32)
+    lib().oracle_bootstrap(seed, t, tree, n, _ptr(w))
+    return w
+
+
+def best_split(bins, y, w, rows, feats, n_classes, n_bins):
+    bins = np.ascontiguousarray(bins, dtype=np.uint8)
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    w = np.ascontiguousarray(w, dtype=np.uint32)
+    rows = np.ascontiguousarray(rows, dtype=np.uint32)
+    feats = np.ascontiguousarray(feats, dtype=np.int32)
+    out = np.zeros(8, dtype=np.uint64)
+    rc = lib().oracle_best_split(_ptr(bins), bins.shape[1], _ptr(y), _ptr(w), _ptr(rows),
+                                 len(rows), _ptr(feats), len(feats), n_classes, n_bins, _ptr(out))
+    if rc:
+        raise ValueError("oracle_best_split failed")
+    keys = ["found", "q", "b", "nl", "sl", "nr", "sr", "gain_fix"]
+    return {k: int(v) for k, v in zip(keys, out)}
+
+
+def grow_tree(bins, y, w, n_classes, n_bins, max_depth, mtry, seed, t, tree):
+    bins = np.ascontiguousarray(bins, dtype=np.uint8)
+    p_w, n = bins.shape
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    w = np.ascontiguousarray(w, dtype=np.uint32)
+    cap = 2 * n + 2
+    nodes = np.zeros((cap, 6), dtype=np.int64)
+    gains = np.zeros(p_w, dtype=np.uint64)
+    cnt = lib().oracle_grow_tree(_ptr(bins), n, p_w, _ptr(y), _ptr(w), n_classes, n_bins,
+                                 max_depth, mtry, seed, t, tree, _ptr(nodes), cap, _ptr(gains))
+    if cnt < 0:
+        raise ValueError("oracle_grow_tree failed")
+    return nodes[:cnt].copy(), gains
+
+
+def binom_decide(hits, t, p, alpha):
+    return int(lib().oracle_binom_decide(hits, t, p, alpha))
+
+
+def _trace_collector(store):
+    def cb(_user, trp):
+        tr = trp.contents
+        p_w, nt, nn = tr.p_w, tr.n_trees, tr.n_nodes
+        rec = {
+            "t": tr.t, "p_cur": tr.p_cur, "n_sha": tr.n_sha, "p_w": p_w, "mtry": tr.mtry,
+            "col_src": np.ctypeslib.as_array(tr.col_src, (p_w,)).copy(),
+            "imp_int": np.ctypeslib.as_array(tr.imp_int, (p_w,)).copy(),
+            "tree_stats": np.ctypeslib.as_array(tr.tree_stats, (nt, 5)).copy() if nt else
+            np.zeros((0, 5), np.int64),
+            "nodes": np.ctypeslib.as_array(tr.nodes, (nn, 6)).copy() if nn else
+            np.zeros((0, 6), np.int64),
+        }
+        store.append(rec)
+    return TRACE_FN(cb)
+
+
+def boruta_fit(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=0, max_iter=20,
+               alpha=0.05, seed=0, n_bins=256, n_perm=1, n_threads=0, permut_naive=False,
+               trace=False):
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    n, p = X.shape
+    dec = np.zeros(p, dtype=np.int8)
+    hist = np.full((max_iter, p), np.nan)
+    hits = np.zeros(p, dtype=np.int32)
+    smax = np.full(max_iter, np.nan)
+    n_iter = ctypes.c_int32(0)
+    traces = []
+    cb = _trace_collector(traces) if trace else TRACE_FN()
+    rc = lib().oracle_boruta_fit(_ptr(X), _ptr(y), n, p, n_classes, n_trees, max_depth, mtry,
+                                 importance_mode, max_iter, alpha, seed, n_bins, n_perm,
+                                 n_threads, int(permut_naive), _ptr(dec), _ptr(hist), _ptr(hits),
+                                 _ptr(smax), ctypes.cast(ctypes.byref(n_iter), ctypes.c_void_p),
+                                 cb, None)
+    if rc:
+        raise ValueError(f"oracle_boruta_fit failed: {rc}")
+    return {"decision": dec, "imp_history": hist, "hits": hits, "shadow_max": smax,
+            "n_iter": n_iter.value, "traces": traces, "rc": rc}
+
+
+def boruta_step(X, y, n_classes, n_trees, max_depth, t, state, hits, mtry=0,
+                importance_mode=0, alpha=0.05, seed=0, n_bins=256, n_perm=1, tree_subset=None,
+                n_threads=0, permut_naive=False, trace=True):
+    """Iteration t of Algorithm 1 from the given (state, hits); returns the
+    updated vectors, the importance row and the trace record."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    n, p = X.shape
+    st = np.array(state, dtype=np.int8, copy=True)
+    ht = np.array(hits, dtype=np.int32, copy=True)
+    row = np.full(p, np.nan)
+    smax = np.zeros(1)
+    sub = None if tree_subset is None else np.ascontiguousarray(tree_subset, dtype=np.int32)
+    traces = []
+    cb = _trace_collector(traces) if trace else TRACE_FN()
+    rc = lib().oracle_boruta_step(_ptr(X), _ptr(y), n, p, n_classes, n_trees, max_depth, mtry,
+                                  importance_mode, alpha, seed, n_bins, n_perm, t, _ptr(st),
+                                  _ptr(ht), _ptr(sub), 0 if sub is None else len(sub), n_threads,
+                                  int(permut_naive), _ptr(row), _ptr(smax), cb, None)
+    if rc:
+        raise ValueError(f"oracle_boruta_step failed: {rc}")
+    return {"state": st, "hits": ht, "imp_row": row, "shadow_max": float(smax[0]),
+            "trace": traces[0] if traces else None}

@@ -1,0 +1,66 @@
+"""Pins of the oracle's Bonferroni binomial decision: exact rational tails
+(math.comb), scipy's binomial survival/cumulative functions, and the closed
+form of the earliest possible decision."""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import oracle as O
+
+
+def exact(h, t, p, alpha):
+    a = Fraction(alpha)
+    up = Fraction(sum(math.comb(t, k) for k in range(h, t + 1)), 2**t)
+    lo = Fraction(sum(math.comb(t, k) for k in range(0, h + 1)), 2**t)
+    if p * up < a:
+        return 1
+    if p * lo < a:
+        return -1
+    return 0
+
+
+def test_exhaustive_small_t():
+    for t in range(1, 41):
+        for h in range(t + 1):
+            for p in (1, 3, 20, 500):
+                for alpha in (0.05, 0.01, 0.3):
+                    assert O.binom_decide(h, t, p, alpha) == exact(h, t, p, alpha)
+
+
+def test_random_large_t_exact_and_scipy():
+    rng = np.random.default_rng(0)
+    for _ in range(400):
+        t = int(rng.integers(1, 1001))
+        h = int(rng.integers(0, t + 1))
+        if rng.random() < 0.5:  # concentrate near the decision boundaries
+            h = int(np.clip(round(t / 2 + rng.normal(0, 2) * math.sqrt(t)), 0, t))
+        p = int(rng.integers(1, 30000))
+        alpha = float(rng.uniform(1e-4, 0.49))
+        got = O.binom_decide(h, t, p, alpha)
+        assert got == exact(h, t, p, alpha)
+        up = p * stats.binom.sf(h - 1, t, 0.5)
+        lo = p * stats.binom.cdf(h, t, 0.5)
+        if abs(up - alpha) > 1e-9 * alpha and abs(lo - alpha) > 1e-9 * alpha:
+            want = 1 if up < alpha else (-1 if lo < alpha else 0)
+            assert got == want
+
+
+@pytest.mark.parametrize("p,t_star", [(20, 9), (500, 14), (20000, 19), (50, 10), (2000, 16)])
+def test_earliest_decision_closed_form(p, t_star):
+    alpha = 0.05
+    assert t_star == min(t for t in range(1, 100) if 2**t > p / alpha)
+    for t in range(1, t_star):
+        assert O.binom_decide(t, t, p, alpha) == 0
+        assert O.binom_decide(0, t, p, alpha) == 0
+    assert O.binom_decide(t_star, t_star, p, alpha) == 1
+    assert O.binom_decide(0, t_star, p, alpha) == -1
+
+
+def test_monotone_thresholds():
+    for t in (15, 60, 300):
+        d = [O.binom_decide(h, t, 100, 0.05) for h in range(t + 1)]
+        # -1 ... -1, 0 ... 0, 1 ... 1
+        assert d == sorted(d)
