@@ -1,0 +1,197 @@
+/*
+ * boruta.h -- C ABI of libboruta.so, a HIP (gfx950) implementation of the
+ * Boruta feature-selection loop with GPU random forests, after
+ * "Novel GPU Boruta algorithms for feature selection from high-dimensional
+ * data" (arxiv 2605.09950).
+ *
+ * What one call computes (Algorithm 1, Sec. 2): starting from all features
+ * undecided, each iteration t = 1, 2, ... while t <= max_iter and some
+ * feature is undecided
+ *   1. widens the quantile-binned matrix with shadow copies of the columns
+ *      that are not rejected, doubled until there are at least five, each
+ *      copy shuffled over the rows by its own keyed permutation;
+ *   2. fits a random forest (bootstrap, per-node random feature draw, Gini
+ *      split on bin thresholds) on the widened matrix;
+ *   3. scores every widened column:
+ *        TreeImp -- normalised mean impurity decrease (Algorithm 2, Sec. 2.1),
+ *        Permut  -- out-of-bag accuracy drop when the column is permuted among
+ *                   each tree's out-of-bag rows (Kursa's importance, Sec. 2;
+ *                   permutation importance, Sec. 2.2);
+ *   4. adds a hit to each feature scoring strictly above the best shadow;
+ *   5. confirms / rejects undecided features with a Bonferroni-corrected
+ *      exact binomial test at level alpha.
+ * Results are a deterministic function of (inputs, seed, n_bins, n_perm):
+ * identical across the plain and batched forms, the two split-ranking modes
+ * and batch composition.
+ *
+ * Conventions: the caller owns every buffer; the library never frees caller
+ * memory.  Host pointers unless stated otherwise.  All entry points are
+ * blocking.  On error the return value is negative and boruta_last_error()
+ * (thread-local) describes it; output buffers are then unspecified.
+ */
+#ifndef BORUTA_H
+#define BORUTA_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BORUTA_OK 0
+#define BORUTA_E_INVALID_ARG -1 /* argument outside the ranges listed below           */
+#define BORUTA_E_NONFINITE -2   /* NaN or Inf in X                                      */
+#define BORUTA_E_OOM -3         /* device allocation failed or workspace too small      */
+#define BORUTA_E_DEVICE -4      /* HIP runtime error or internal capacity check failed */
+#define BORUTA_E_UNSUPPORTED -5 /* no usable gfx950 device                              */
+
+enum { BORUTA_TREEIMP = 0, BORUTA_PERMUT = 1 };
+enum { BORUTA_REJECTED = -1, BORUTA_TENTATIVE = 0, BORUTA_CONFIRMED = 1 };
+enum { BORUTA_FORM_PLAIN = 0, BORUTA_FORM_BATCHED = 1 };
+enum { BORUTA_RANK_EXACT = 0, BORUTA_RANK_FP32 = 1 };
+
+/* Per-iteration record for the optional trace callback (host memory, valid
+ * only during the call).  Nodes are listed in (tree, heap id) order; heap id
+ * of the root is 1 and the children of h are 2h (left) and 2h+1. */
+typedef struct {
+    int32_t job;            /* index of the job in the batch (0 for boruta_fit)  */
+    int32_t t;              /* iteration, 1-based                                */
+    int32_t p_cur;          /* active original columns (state >= 0)              */
+    int32_t n_sha;          /* shadow columns                                    */
+    int32_t p_w;            /* widened width p_cur + n_sha                       */
+    int32_t mtry;           /* features drawn per node this iteration            */
+    int32_t n_trees;
+    const int32_t* col_src; /* [p_w] original feature behind each widened column  */
+    const int64_t* imp_int; /* [p_w] integer importance (see boruta_fit)         */
+    const int32_t* hits;    /* [p] after this iteration                          */
+    const int8_t* state;    /* [p] after this iteration's decision               */
+    const int64_t* tree_stats; /* [n_trees][5]: tree, distinct in-bag rows, OOB
+                                  rows, OOB correct (Permut only, else 0), nodes */
+    int64_t n_nodes;
+    const int64_t* nodes;   /* [n_nodes][6]: tree, heap id, widened feature (-1
+                               leaf), threshold bin (leaf: class), weighted
+                               count, Gini decrease in 2^-32 units (0 leaf)     */
+} boruta_iter_trace;
+
+typedef void (*boruta_trace_fn)(void* user, const boruta_iter_trace* tr);
+
+/* Kernel timing of the dominant kernels, filled when boruta_options.stats is
+ * non-null (times from HIP events recorded on the library's stream around
+ * every launch of the kernel, so they include no host gaps). */
+typedef struct {
+    int64_t launches;       /* launches of the kernel                               */
+    double ms;              /* summed event time                                    */
+    double alg_bytes;       /* algorithmic bytes: sum over searched nodes of
+                               rows x (features drawn + 6)                          */
+} boruta_kernel_stat;
+
+typedef struct {
+    boruta_kernel_stat hist_large; /* node histogram + split scan, > 64 rows      */
+    boruta_kernel_stat hist_small; /* wave-per-node split search, <= 64 rows      */
+    boruta_kernel_stat permut;     /* OOB traversal for permutation importance    */
+    double iter_ms;                /* device time of all iterations               */
+    int64_t iterations;            /* job-iterations run                          */
+    int64_t nodes;                 /* tree nodes grown                            */
+} boruta_stats;
+
+typedef struct {
+    int32_t n_bins;       /* quantile bins, [2, 256]; default 256                  */
+    int32_t n_perm;       /* Permut replicas per column, [1, 65535]; default 1     */
+    int32_t split_rank;   /* BORUTA_RANK_EXACT or BORUTA_RANK_FP32 (FP32 ranking
+                             with an exact recheck near the maximum); default FP32 */
+    int32_t form;         /* BORUTA_FORM_PLAIN (one launch per tree node) or
+                             BORUTA_FORM_BATCHED (all nodes of a tree level of all
+                             trees and jobs per launch); default BATCHED           */
+    boruta_trace_fn trace;/* nullable                                              */
+    void* trace_user;
+    boruta_stats* stats;  /* nullable                                              */
+} boruta_options;
+
+/* Fills *opt with the defaults above. */
+void boruta_default_options(boruta_options* opt);
+
+/* One Boruta run (Algorithm 1).
+ *   X          [n][p] row-major float32, finite.  n in [2, 2^24], p in [1, 2^24].
+ *   y          [n] class labels in [0, n_classes), n_classes in [2, 16].
+ *   n_trees    [1, 65535]; max_depth in [1, 30] (root = depth 0).
+ *   mtry       features drawn per node; 0 = floor(sqrt(p_w)) recomputed each
+ *              iteration, otherwise min(mtry, p_w).
+ *   importance_mode  BORUTA_TREEIMP or BORUTA_PERMUT.
+ *   max_iter   [1, 1000]; alpha in (0, 0.5); seed keys every random draw.
+ * Outputs (caller-allocated):
+ *   decision_out    [p]  -1 rejected / 0 tentative / 1 confirmed.
+ *   imp_history_out [max_iter][p]: row t-1 = reported importance of each
+ *                   feature at iteration t (TreeImp: its share of the
+ *                   renormalised impurity importance over all widened
+ *                   columns; Permut: accuracy drop / (n_perm x OOB rows of
+ *                   all trees)), NaN for features rejected before t; rows
+ *                   at and past n_iter are left untouched.
+ *   hits_out [p], shadow_max_out [max_iter]: nullable.
+ *   n_iter_out      iterations run. */
+int boruta_fit(const float* X, const int32_t* y, int64_t n, int64_t p, int32_t n_classes,
+               int32_t n_trees, int32_t max_depth, int32_t mtry, int32_t importance_mode,
+               int32_t max_iter, double alpha, uint64_t seed, int8_t* decision_out,
+               double* imp_history_out, int32_t* hits_out, double* shadow_max_out,
+               int32_t* n_iter_out);
+
+/* boruta_fit with options (opt nullable = defaults). */
+int boruta_fit_ex(const float* X, const int32_t* y, int64_t n, int64_t p, int32_t n_classes,
+                  int32_t n_trees, int32_t max_depth, int32_t mtry, int32_t importance_mode,
+                  int32_t max_iter, double alpha, uint64_t seed, const boruta_options* opt,
+                  int8_t* decision_out, double* imp_history_out, int32_t* hits_out,
+                  double* shadow_max_out, int32_t* n_iter_out);
+
+/* One job of a batch: the problem arguments of boruta_fit. */
+typedef struct {
+    const float* X;
+    const int32_t* y;
+    int64_t n, p;
+    int32_t n_classes, n_trees, max_depth, mtry, importance_mode, max_iter;
+    double alpha;
+    uint64_t seed;
+} boruta_job;
+
+/* Caller-allocated outputs of one job (same meaning as boruta_fit). */
+typedef struct {
+    int8_t* decision;
+    double* imp_history;
+    int32_t* hits;       /* nullable */
+    double* shadow_max;  /* nullable */
+    int32_t n_iter;      /* out */
+    int32_t status;      /* out: BORUTA_OK or the job's own error code */
+} boruta_result;
+
+/* Many independent runs advanced together: every launch of an iteration step
+ * covers the live jobs' trees and nodes.  Each job keeps its own seed, so its
+ * results equal a boruta_fit of that job alone.  Returns the first error. */
+int boruta_fit_batch(const boruta_job* jobs, int32_t n_jobs, const boruta_options* opt,
+                     boruta_result* results);
+
+/* Device bytes a call with these jobs needs (for boruta_fit_device). */
+int boruta_workspace_size(const boruta_job* jobs, int32_t n_jobs, const boruta_options* opt,
+                          size_t* bytes);
+
+/* boruta_fit on device-resident inputs: dX [n][p] float32 and dy [n] int32 are
+ * DEVICE pointers; workspace is a device buffer of at least the size that
+ * boruta_workspace_size reports for this problem (256-byte aligned); all
+ * work is ordered on hip_stream (a hipStream_t, nullable = default stream).
+ * The library allocates no device memory in this call.  Outputs are host
+ * pointers as in boruta_fit. */
+int boruta_fit_device(const float* dX, const int32_t* dy, int64_t n, int64_t p,
+                      int32_t n_classes, int32_t n_trees, int32_t max_depth, int32_t mtry,
+                      int32_t importance_mode, int32_t max_iter, double alpha, uint64_t seed,
+                      const boruta_options* opt, void* workspace, size_t ws_bytes,
+                      void* hip_stream, int8_t* decision_out, double* imp_history_out,
+                      int32_t* hits_out, double* shadow_max_out, int32_t* n_iter_out);
+
+/* Streaming copy of `bytes` bytes between device buffers (calibration of
+ * hardware byte counters); returns BORUTA_OK or an error code. */
+int boruta_probe_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* boruta_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,310 @@
+"""ctypes binding of libboruta.so (include/boruta.h): same entry-point names,
+argument marshalling only.  Every step of the method runs in the library's
+HIP kernels; there is no Python or CPU fallback, and loading fails loudly
+when the library has not been built."""
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libboruta.so")
+
+BORUTA_OK, BORUTA_E_INVALID_ARG, BORUTA_E_NONFINITE, BORUTA_E_OOM, BORUTA_E_DEVICE, \
+    BORUTA_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+TREEIMP, PERMUT = 0, 1
+FORM_PLAIN, FORM_BATCHED = 0, 1
+RANK_EXACT, RANK_FP32 = 0, 1
+
+
+class BorutaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libboruta error {code}: {msg}")
+        self.code = code
+
+
+class IterTrace(ctypes.Structure):
+    _fields_ = [
+        ("job", ctypes.c_int32), ("t", ctypes.c_int32), ("p_cur", ctypes.c_int32),
+        ("n_sha", ctypes.c_int32), ("p_w", ctypes.c_int32), ("mtry", ctypes.c_int32),
+        ("n_trees", ctypes.c_int32),
+        ("col_src", ctypes.POINTER(ctypes.c_int32)),
+        ("imp_int", ctypes.POINTER(ctypes.c_int64)),
+        ("hits", ctypes.POINTER(ctypes.c_int32)),
+        ("state", ctypes.POINTER(ctypes.c_int8)),
+        ("tree_stats", ctypes.POINTER(ctypes.c_int64)),
+        ("n_nodes", ctypes.c_int64),
+        ("nodes", ctypes.POINTER(ctypes.c_int64)),
+    ]
+
+
+TRACE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.POINTER(IterTrace))
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("alg_bytes", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("hist_large", KernelStat), ("hist_small", KernelStat), ("permut", KernelStat),
+                ("iter_ms", ctypes.c_double), ("iterations", ctypes.c_int64),
+                ("nodes", ctypes.c_int64)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("n_bins", ctypes.c_int32), ("n_perm", ctypes.c_int32),
+                ("split_rank", ctypes.c_int32), ("form", ctypes.c_int32),
+                ("trace", TRACE_FN), ("trace_user", ctypes.c_void_p),
+                ("stats", ctypes.POINTER(Stats))]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("y", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("p", ctypes.c_int64), ("n_classes", ctypes.c_int32),
+                ("n_trees", ctypes.c_int32), ("max_depth", ctypes.c_int32),
+                ("mtry", ctypes.c_int32), ("importance_mode", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("alpha", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("decision", ctypes.c_void_p), ("imp_history", ctypes.c_void_p),
+                ("hits", ctypes.c_void_p), ("shadow_max", ctypes.c_void_p),
+                ("n_iter", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
+EXPORTS = ["boruta_default_options", "boruta_fit", "boruta_fit_ex", "boruta_fit_batch",
+           "boruta_workspace_size", "boruta_fit_device", "boruta_probe_copy",
+           "boruta_last_error"]
+
+_lib = None
+
+
+def lib():
+    """Load libboruta.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2605_09950_amd.csrc.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, u64, f64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                 ctypes.c_uint64, ctypes.c_double)
+        prob = [P, P, i64, i64, i32, i32, i32, i32, i32, i32, f64, u64]
+        L.boruta_default_options.argtypes = [ctypes.POINTER(Options)]
+        L.boruta_default_options.restype = None
+        L.boruta_fit.argtypes = prob + [P, P, P, P, P]
+        L.boruta_fit.restype = ctypes.c_int
+        L.boruta_fit_ex.argtypes = prob + [ctypes.POINTER(Options), P, P, P, P, P]
+        L.boruta_fit_ex.restype = ctypes.c_int
+        L.boruta_fit_batch.argtypes = [ctypes.POINTER(Job), i32, ctypes.POINTER(Options),
+                                       ctypes.POINTER(Result)]
+        L.boruta_fit_batch.restype = ctypes.c_int
+        L.boruta_workspace_size.argtypes = [ctypes.POINTER(Job), i32, ctypes.POINTER(Options),
+                                            ctypes.POINTER(ctypes.c_size_t)]
+        L.boruta_workspace_size.restype = ctypes.c_int
+        L.boruta_fit_device.argtypes = prob + [ctypes.POINTER(Options), P, ctypes.c_size_t, P,
+                                               P, P, P, P, P]
+        L.boruta_fit_device.restype = ctypes.c_int
+        L.boruta_probe_copy.argtypes = [P, P, ctypes.c_size_t, P]
+        L.boruta_probe_copy.restype = ctypes.c_int
+        L.boruta_last_error.argtypes = []
+        L.boruta_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def boruta_last_error():
+    return lib().boruta_last_error().decode()
+
+
+def _check(rc):
+    if rc != BORUTA_OK:
+        raise BorutaError(rc, boruta_last_error())
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def boruta_default_options():
+    o = Options()
+    lib().boruta_default_options(ctypes.byref(o))
+    return o
+
+
+def _trace_collector(store, p, keep_iters=None):
+    """Copies each iteration record into store["iters"] (only iterations in
+    keep_iters when given)."""
+    def cb(_user, trp):
+        tr = trp.contents
+        p_w, nt, nn = tr.p_w, tr.n_trees, tr.n_nodes
+        if keep_iters is not None and tr.t not in keep_iters:
+            return
+        store["iters"].append({
+            "hits": np.ctypeslib.as_array(tr.hits, (p,)).copy(),
+            "state": np.ctypeslib.as_array(tr.state, (p,)).copy(),
+            "job": tr.job, "t": tr.t, "p_cur": tr.p_cur, "n_sha": tr.n_sha, "p_w": p_w,
+            "mtry": tr.mtry,
+            "col_src": np.ctypeslib.as_array(tr.col_src, (p_w,)).copy(),
+            "imp_int": np.ctypeslib.as_array(tr.imp_int, (p_w,)).copy(),
+            "tree_stats": np.ctypeslib.as_array(tr.tree_stats, (nt, 5)).copy(),
+            "nodes": np.ctypeslib.as_array(tr.nodes, (nn, 6)).copy() if nn else
+            np.zeros((0, 6), np.int64),
+        })
+    return TRACE_FN(cb)
+
+
+def make_options(n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED, trace=False,
+                 stats=False, p=0):
+    """Options plus the Python objects that must stay alive during the call.
+    trace: False, True (every iteration) or a set of iterations to keep."""
+    o = boruta_default_options()
+    o.n_bins, o.n_perm, o.split_rank, o.form = n_bins, n_perm, split_rank, form
+    keep = {"iters": []}
+    if trace is not False:
+        keep["cb"] = _trace_collector(keep, p, None if trace is True else set(trace))
+        o.trace = keep["cb"]
+    if stats:
+        keep["stats"] = Stats()
+        o.stats = ctypes.pointer(keep["stats"])
+    return o, keep
+
+
+def boruta_fit_ex(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=TREEIMP,
+                  max_iter=20, alpha=0.05, seed=0, n_bins=256, n_perm=1, split_rank=RANK_FP32,
+                  form=FORM_BATCHED, trace=False, stats=False):
+    """Host arrays in, host arrays out (see boruta_fit in include/boruta.h)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    n, p = X.shape
+    dec = np.zeros(p, np.int8)
+    hist = np.full((max_iter, p), np.nan)
+    hits = np.zeros(p, np.int32)
+    smax = np.full(max_iter, np.nan)
+    n_iter = np.zeros(1, np.int32)
+    o, keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p)
+    rc = lib().boruta_fit_ex(_ptr(X), _ptr(y), n, p, n_classes, n_trees, max_depth, mtry,
+                             importance_mode, max_iter, alpha, seed, ctypes.byref(o), _ptr(dec),
+                             _ptr(hist), _ptr(hits), _ptr(smax), _ptr(n_iter))
+    _check(rc)
+    out = {"decision": dec, "imp_history": hist, "hits": hits, "shadow_max": smax,
+           "n_iter": int(n_iter[0]), "traces": keep["iters"]}
+    if stats:
+        out["stats"] = keep["stats"]
+    return out
+
+
+def boruta_fit(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=TREEIMP,
+               max_iter=20, alpha=0.05, seed=0):
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    n, p = X.shape
+    dec = np.zeros(p, np.int8)
+    hist = np.full((max_iter, p), np.nan)
+    hits = np.zeros(p, np.int32)
+    smax = np.full(max_iter, np.nan)
+    n_iter = np.zeros(1, np.int32)
+    rc = lib().boruta_fit(_ptr(X), _ptr(y), n, p, n_classes, n_trees, max_depth, mtry,
+                          importance_mode, max_iter, alpha, seed, _ptr(dec), _ptr(hist),
+                          _ptr(hits), _ptr(smax), _ptr(n_iter))
+    _check(rc)
+    return {"decision": dec, "imp_history": hist, "hits": hits, "shadow_max": smax,
+            "n_iter": int(n_iter[0])}
+
+
+def _job(X, y, n_classes, n_trees, max_depth, mtry, importance_mode, max_iter, alpha, seed):
+    j = Job()
+    j.X, j.y = X.ctypes.data, y.ctypes.data
+    j.n, j.p = X.shape
+    j.n_classes, j.n_trees, j.max_depth, j.mtry = n_classes, n_trees, max_depth, mtry
+    j.importance_mode, j.max_iter, j.alpha, j.seed = importance_mode, max_iter, alpha, seed
+    return j
+
+
+def boruta_fit_batch(jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED,
+                     trace=False, stats=False):
+    """jobs: list of dicts with X, y, n_classes, n_trees, max_depth and optional mtry,
+    importance_mode, max_iter, alpha, seed."""
+    arrs, cj, res, outs = [], (Job * len(jobs))(), (Result * len(jobs))(), []
+    for i, jd in enumerate(jobs):
+        X = np.ascontiguousarray(jd["X"], dtype=np.float32)
+        y = np.ascontiguousarray(jd["y"], dtype=np.int32)
+        max_iter = jd.get("max_iter", 20)
+        p = X.shape[1]
+        cj[i] = _job(X, y, jd["n_classes"], jd["n_trees"], jd["max_depth"], jd.get("mtry", 0),
+                     jd.get("importance_mode", TREEIMP), max_iter, jd.get("alpha", 0.05),
+                     jd.get("seed", 0))
+        o = {"decision": np.zeros(p, np.int8), "imp_history": np.full((max_iter, p), np.nan),
+             "hits": np.zeros(p, np.int32), "shadow_max": np.full(max_iter, np.nan)}
+        res[i].decision = o["decision"].ctypes.data
+        res[i].imp_history = o["imp_history"].ctypes.data
+        res[i].hits = o["hits"].ctypes.data
+        res[i].shadow_max = o["shadow_max"].ctypes.data
+        arrs.append((X, y))
+        outs.append(o)
+    p_max = max(np.shape(jd["X"])[1] for jd in jobs)
+    if trace is not False and len({np.shape(jd["X"])[1] for jd in jobs}) > 1:
+        raise ValueError("batch traces need jobs of equal p")
+    opt, keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p_max)
+    rc = lib().boruta_fit_batch(cj, len(jobs), ctypes.byref(opt), res)
+    for i, o in enumerate(outs):
+        o["n_iter"], o["status"] = res[i].n_iter, res[i].status
+    _check(rc)
+    return {"results": outs, "traces": keep["iters"], "stats": keep.get("stats")}
+
+
+def boruta_workspace_size(jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32,
+                          form=FORM_BATCHED):
+    """jobs: list of dicts with shapes (X may be any array with .shape)."""
+    cj = (Job * len(jobs))()
+    for i, jd in enumerate(jobs):
+        j = Job()
+        j.X, j.y = 1, 1
+        j.n, j.p = jd["n"], jd["p"]
+        j.n_classes, j.n_trees, j.max_depth = jd["n_classes"], jd["n_trees"], jd["max_depth"]
+        j.mtry, j.importance_mode = jd.get("mtry", 0), jd.get("importance_mode", TREEIMP)
+        j.max_iter, j.alpha, j.seed = jd.get("max_iter", 20), jd.get("alpha", 0.05), 0
+        cj[i] = j
+    opt, _ = make_options(n_bins, n_perm, split_rank, form)
+    out = ctypes.c_size_t(0)
+    _check(lib().boruta_workspace_size(cj, len(jobs), ctypes.byref(opt), ctypes.byref(out)))
+    return int(out.value)
+
+
+def boruta_fit_device(dX, dy, n_classes, n_trees, max_depth, workspace, stream=None, mtry=0,
+                      importance_mode=TREEIMP, max_iter=20, alpha=0.05, seed=0, n_bins=256,
+                      n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED, trace=False,
+                      stats=False):
+    """dX [n][p] float32, dy [n] int32 and workspace (uint8) are torch CUDA tensors; stream a
+    torch.cuda.Stream (default: the current stream)."""
+    import torch
+    assert dX.is_cuda and dy.is_cuda and workspace.is_cuda
+    assert dX.dtype == torch.float32 and dy.dtype == torch.int32 and dX.is_contiguous()
+    n, p = dX.shape
+    st = stream if stream is not None else torch.cuda.current_stream(dX.device)
+    dec = np.zeros(p, np.int8)
+    hist = np.full((max_iter, p), np.nan)
+    hits = np.zeros(p, np.int32)
+    smax = np.full(max_iter, np.nan)
+    n_iter = np.zeros(1, np.int32)
+    opt, keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p)
+    rc = lib().boruta_fit_device(dX.data_ptr(), dy.data_ptr(), n, p, n_classes, n_trees,
+                                 max_depth, mtry, importance_mode, max_iter, alpha, seed,
+                                 ctypes.byref(opt), workspace.data_ptr(), workspace.numel(),
+                                 st.cuda_stream, _ptr(dec), _ptr(hist), _ptr(hits), _ptr(smax),
+                                 _ptr(n_iter))
+    _check(rc)
+    out = {"decision": dec, "imp_history": hist, "hits": hits, "shadow_max": smax,
+           "n_iter": int(n_iter[0]), "traces": keep["iters"]}
+    if stats:
+        out["stats"] = keep["stats"]
+    return out
+
+
+def boruta_probe_copy(dst, src, nbytes, stream=None):
+    """Device-to-device streaming copy of torch tensors (counter calibration)."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(dst.device)
+    _check(lib().boruta_probe_copy(dst.data_ptr(), src.data_ptr(), nbytes, st.cuda_stream))

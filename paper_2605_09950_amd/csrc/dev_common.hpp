@@ -1,0 +1,267 @@
+// dev_common.hpp -- types and device helpers shared by the HIP kernels and
+// the host engine of libboruta.so (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace boruta {
+
+typedef unsigned __int128 u128;
+
+// ---------------------------------------------------------------------------
+// Random streams.  Every random draw of a run is Philox4x32-10 (Salmon et al.,
+// SC'11) keyed by the job's 64-bit seed, at a counter that names what is
+// drawn: word0 = stream<<28 | feistel_round<<24 | iteration, then (a, b, c).
+enum : uint32_t { kBoot = 1, kMtry = 2, kShadow = 3, kOobPerm = 4 };
+
+struct Philox4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                 uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Philox4{c0, c1, c2, c3};
+}
+
+__host__ __device__ __forceinline__ uint32_t ctr_word0(uint32_t stream, uint32_t round,
+                                                       uint32_t t) {
+    return (stream << 28) | (round << 24) | (t & 0xFFFFFFu);
+}
+
+// Keyed bijection of [0, m): balanced Feistel network over the smallest even
+// bit width k >= 2 with 2^k >= m, halves of h = k/2 bits, max(6, ceil(24/h))
+// rounds with round function word 0 of Philox(word0(stream, r, t), a, b,
+// c_hi | R) masked to h bits, cycle-walked back into [0, m).
+struct KeyedPerm {
+    uint32_t k0, k1, w0, a, b, c_hi;
+    uint32_t half, mask, rounds;
+    uint64_t m;
+};
+
+__host__ __device__ __forceinline__ KeyedPerm make_perm(uint32_t k0, uint32_t k1,
+                                                        uint32_t stream, uint32_t t, uint32_t a,
+                                                        uint32_t b, uint32_t c_hi, uint64_t m) {
+    KeyedPerm P;
+    P.k0 = k0;
+    P.k1 = k1;
+    P.w0 = ctr_word0(stream, 0, t);
+    P.a = a;
+    P.b = b;
+    P.c_hi = c_hi;
+    P.m = m;
+    uint32_t k = 0;
+    while ((uint64_t(1) << k) < m) ++k;
+    if (k < 2) k = 2;
+    k += k & 1u;
+    P.half = k >> 1;
+    P.mask = (1u << P.half) - 1u;
+    const uint32_t r = (24u + P.half - 1u) / P.half;
+    P.rounds = r > 6u ? r : 6u;
+    return P;
+}
+
+__device__ __forceinline__ uint32_t perm_round(const KeyedPerm& P, uint32_t r, uint32_t right) {
+    return philox4x32_10(P.w0 | (r << 24), P.a, P.b, P.c_hi | right, P.k0, P.k1).x & P.mask;
+}
+
+__device__ __forceinline__ uint32_t perm_apply(const KeyedPerm& P, uint32_t x) {
+    if (P.m <= 1) return 0;
+    do {
+        uint32_t left = x >> P.half, right = x & P.mask;
+        for (uint32_t r = 0; r < P.rounds; ++r) {
+            const uint32_t f = perm_round(P, r, right);
+            const uint32_t nl = right;
+            right = left ^ f;
+            left = nl;
+        }
+        x = (left << P.half) | right;
+    } while ((uint64_t)x >= P.m);
+    return x;
+}
+
+// Same bijection with the round functions tabulated: tab[r << half | R].
+__device__ __forceinline__ uint32_t perm_apply_tab(const KeyedPerm& P, const uint16_t* tab,
+                                                   uint32_t x) {
+    if (P.m <= 1) return 0;
+    do {
+        uint32_t left = x >> P.half, right = x & P.mask;
+        for (uint32_t r = 0; r < P.rounds; ++r) {
+            const uint32_t f = tab[(r << P.half) | right];
+            const uint32_t nl = right;
+            right = left ^ f;
+            left = nl;
+        }
+        x = (left << P.half) | right;
+    } while ((uint64_t)x >= P.m);
+    return x;
+}
+
+// ---------------------------------------------------------------------------
+// Exact integer helpers.
+__device__ __forceinline__ int clz128(u128 v) {
+    const uint64_t hi = (uint64_t)(v >> 64), lo = (uint64_t)v;
+    return hi ? __clzll(hi) : 64 + (lo ? __clzll(lo) : 64);
+}
+
+// floor(num / den) for a quotient known to fit 64 bits (shift-subtract).
+__device__ __forceinline__ uint64_t udiv128(u128 num, u128 den) {
+    if (den == 0 || num < den) return 0;
+    const int shift = clz128(den) - clz128(num);
+    den <<= shift;
+    uint64_t q = 0;
+    for (int i = 0; i <= shift; ++i) {
+        q <<= 1;
+        if (num >= den) {
+            num -= den;
+            q |= 1;
+        }
+        den >>= 1;
+    }
+    return q;
+}
+
+// ---------------------------------------------------------------------------
+// Split candidate: threshold b of the feature at draw position q (widened
+// column f); left/right weighted counts N and sums of squared class counts S.
+struct Cand {
+    int32_t q, f, b;
+    uint32_t nl, nr, pad;
+    uint64_t sl, sr;
+};
+
+// Q_a > Q_b exactly, with Q = S_L/N_L + S_R/N_R (cross-multiplied in 128 bits;
+// every product stays below 2^121 for N < 2^24).
+__device__ __forceinline__ bool cand_better(const Cand& a, const Cand& b) {
+    const u128 na = (u128)a.sl * a.nr + (u128)a.sr * a.nl;
+    const u128 nb = (u128)b.sl * b.nr + (u128)b.sr * b.nl;
+    const uint64_t da = (uint64_t)a.nl * a.nr, db = (uint64_t)b.nl * b.nr;
+    return na * db > nb * da;
+}
+
+// Q > S/N exactly (strictly positive Gini decrease).
+__device__ __forceinline__ bool cand_positive(const Cand& c, uint64_t s, uint64_t n) {
+    const u128 num = (u128)c.sl * c.nr + (u128)c.sr * c.nl;
+    return num * n > (u128)s * ((uint64_t)c.nl * c.nr);
+}
+
+// floor(2^32 * (Q - S/N)).
+__device__ __forceinline__ uint64_t cand_gain_fix(const Cand& c, uint64_t s, uint64_t n) {
+    const uint64_t lr = (uint64_t)c.nl * c.nr;
+    const u128 num = ((u128)c.sl * c.nr + (u128)c.sr * c.nl) * n - (u128)s * lr;
+    const u128 den = (u128)lr * n;
+    return udiv128(num << 32, den);
+}
+
+__device__ __forceinline__ float cand_q32(const Cand& c) {
+    return (float)c.sl / (float)c.nl + (float)c.sr / (float)c.nr;
+}
+
+// ---------------------------------------------------------------------------
+// Device-resident run state.
+struct JobDev {
+    // fixed for the run
+    int32_t n, n_pad, p, K, B, T, D, mtry_opt, mode, R, max_iter;
+    uint32_t seed_lo, seed_hi;
+    int32_t max_sha;       // shadow column capacity
+    int32_t pw_cap;        // p + max_sha
+    const uint8_t* y;      // [n]
+    uint8_t* orig;         // [p][n_pad] binned originals
+    uint8_t* sha;          // [max_sha][n_pad] shadows of the current iteration
+    const uint8_t** colptr;// [pw_cap] widened column -> bins
+    int32_t* col_src;      // [pw_cap]
+    int32_t* act;          // [p] active originals, ascending
+    int8_t* state;         // [p]
+    int32_t* hits;         // [p]
+    double* hist;          // [max_iter][p]
+    double* shadow_max;    // [max_iter]
+    int32_t* h_conf;       // [max_iter + 1] smallest hit count that confirms at t
+    int32_t* h_rej;        // [max_iter + 1] largest hit count that rejects at t
+    uint64_t* G;           // [T][pw_cap] per-tree fixed-point Gini decreases
+    int64_t* imp;          // [pw_cap] integer importance of the iteration
+    uint32_t* wbuf;        // [T][n] bootstrap multiplicities
+    uint64_t* rec[2];      // [T][n] row records, ping-pong by level parity
+    uint32_t* oob;         // [T][n] out-of-bag rows, ascending
+    int32_t* tstat;        // [T][4] distinct in-bag, OOB rows, OOB correct, spare
+    // per iteration, written on the device
+    int32_t t, p_cur, n_sha, p_w, mtry, ntiles, n_undecided, live;
+};
+
+struct TreeDev {
+    int32_t job, tau;
+};
+
+// One tree node.  Roots of the iteration's trees are nodes [0, n_trees).
+struct NodeDev {
+    uint32_t tree;   // global tree index of the iteration
+    uint32_t heap;   // heap id: root 1, children 2h, 2h+1
+    uint32_t seg;    // first row record (within the tree's record block)
+    uint32_t len;    // distinct rows
+    uint32_t n;      // weighted rows
+    int32_t feat;    // widened column, -1 for a leaf
+    uint32_t left;   // index of the left child; the right one is left + 1
+    uint16_t thr;    // threshold bin (left iff bin <= thr)
+    uint8_t leaf_class;
+    uint8_t depth;
+};
+
+struct Item {
+    uint32_t node, slot, tile, pad;
+};
+
+// Per-level append counters (reset before each level).
+struct LevelCtr {
+    uint32_t n_nodes;   // children appended to the next level
+    uint32_t n_items;   // (large node, feature tile) items
+    uint32_t n_slots;   // large nodes
+    uint32_t n_small;   // small nodes
+    uint32_t overflow;  // a capacity check failed
+    uint32_t pad[3];
+};
+
+// Row record: row | weight << 32 | label << 48.
+__device__ __forceinline__ uint64_t rec_pack(uint32_t row, uint32_t w, uint32_t y) {
+    return (uint64_t)row | ((uint64_t)w << 32) | ((uint64_t)y << 48);
+}
+__device__ __forceinline__ uint32_t rec_row(uint64_t r) { return (uint32_t)r; }
+__device__ __forceinline__ uint32_t rec_w(uint64_t r) { return (uint32_t)(r >> 32) & 0xFFFFu; }
+__device__ __forceinline__ uint32_t rec_y(uint64_t r) { return (uint32_t)(r >> 48) & 0xFFu; }
+
+constexpr int kSmallRows = 64;  // nodes with at most this many distinct rows take the wave path
+constexpr int kWave = 64;
+
+struct ForestDev {
+    JobDev* jobs;
+    const TreeDev* trees;
+    NodeDev* nodes;
+    uint32_t* cls;        // [node][kmax] weighted class counts
+    uint64_t* ngain;      // [node] fixed-point Gini decrease of a split node
+    Cand* cand;           // [slot][max_tiles]
+    uint32_t* done;       // [slot] tiles finished
+    const Item* items_in;
+    const uint32_t* small_in;
+    Item* items_out;
+    uint32_t* small_out;
+    LevelCtr* ctr;
+    uint64_t* alg_bytes;  // [2] algorithmic bytes (large, small), nullable
+    uint32_t node_cap, item_cap, slot_cap, small_cap;
+    uint32_t next_base;   // first node index of the next level
+    int32_t kmax, ft, max_tiles, parity, split_rank, pad;
+};
+
+}  // namespace boruta

@@ -1,0 +1,875 @@
+// engine.hip -- host orchestration of the Boruta loop and the C ABI of
+// libboruta.so.  Every step of an iteration runs in the HIP kernels of
+// k_prep.hip, k_forest.hip and k_importance.hip; this file plans device
+// memory, launches them in order on one stream and reads back the few
+// counters the host needs to size the next launch.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "boruta.h"
+#include "dev_common.hpp"
+
+namespace boruta {
+
+// launchers (k_prep.hip)
+void launch_validate(const float*, size_t, const int32_t*, size_t, int, uint32_t*, hipStream_t);
+void launch_labels(const int32_t*, size_t, uint8_t*, hipStream_t);
+void launch_binning(const float*, int64_t, int64_t, int, uint8_t*, int64_t, uint32_t*, int64_t,
+                    hipStream_t);
+void launch_thresholds(int32_t, int64_t, uint64_t, int32_t, int32_t*, int32_t*, hipStream_t);
+void launch_active(JobDev*, int, int, hipStream_t);
+void launch_shadow(JobDev*, const int32_t*, int, int64_t, int, hipStream_t);
+void launch_boot_draw(JobDev*, const TreeDev*, int, int64_t, hipStream_t);
+void launch_fill_u32(uint32_t*, size_t, uint32_t, hipStream_t);
+// k_forest.hip
+void launch_boot_compact(const ForestDev&, uint32_t, hipStream_t);
+void launch_split_small(const ForestDev&, uint32_t, hipStream_t);
+void launch_split_large(const ForestDev&, uint32_t, int, hipStream_t);
+// k_importance.hip
+void launch_tree_totals(JobDev*, const TreeDev*, int, uint64_t*, hipStream_t);
+void launch_treeimp(JobDev*, const int32_t*, int, const int32_t*, const uint64_t*, int,
+                    hipStream_t);
+void launch_permut(JobDev*, const TreeDev*, const NodeDev*, int, int64_t, int, hipStream_t);
+void launch_hits_decide(JobDev*, int, hipStream_t);
+void launch_copy(void*, const void*, size_t, hipStream_t);
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPC(x)                                                                          \
+    do {                                                                                 \
+        const hipError_t e_ = (x);                                                       \
+        if (e_ != hipSuccess)                                                            \
+            throw Error(BORUTA_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct Spec {
+    const float* X;
+    const int32_t* y;
+    int64_t n, p;
+    int K, T, D, mtry, mode, max_iter;
+    double alpha;
+    uint64_t seed;
+};
+
+struct Opts {
+    int B = 256, R = 1, split_rank = 1, form = 1;
+    boruta_trace_fn trace = nullptr;
+    void* trace_user = nullptr;
+    boruta_stats* stats = nullptr;
+};
+
+Opts read_opts(const boruta_options* o) {
+    Opts r;
+    if (o) {
+        r.B = o->n_bins;
+        r.R = o->n_perm;
+        r.split_rank = o->split_rank;
+        r.form = o->form;
+        r.trace = o->trace;
+        r.trace_user = o->trace_user;
+        r.stats = o->stats;
+    }
+    if (r.B < 2 || r.B > 256) throw Error(BORUTA_E_INVALID_ARG, "n_bins outside [2, 256]");
+    if (r.R < 1 || r.R > 65535) throw Error(BORUTA_E_INVALID_ARG, "n_perm outside [1, 65535]");
+    if (r.split_rank != 0 && r.split_rank != 1)
+        throw Error(BORUTA_E_INVALID_ARG, "split_rank must be 0 or 1");
+    if (r.form != 0 && r.form != 1) throw Error(BORUTA_E_INVALID_ARG, "form must be 0 or 1");
+    return r;
+}
+
+void check_spec(const Spec& s) {
+    auto bad = [](const char* m) { throw Error(BORUTA_E_INVALID_ARG, m); };
+    if (!s.X || !s.y) bad("X and y must be non-null");
+    if (s.n < 2 || s.n > (int64_t(1) << 24)) bad("n outside [2, 2^24]");
+    if (s.p < 1 || s.p > (int64_t(1) << 24)) bad("p outside [1, 2^24]");
+    if (s.K < 2 || s.K > 16) bad("n_classes outside [2, 16]");
+    if (s.T < 1 || s.T > 65535) bad("n_trees outside [1, 65535]");
+    if (s.D < 1 || s.D > 30) bad("max_depth outside [1, 30]");
+    if (s.mtry < 0) bad("mtry < 0");
+    if (s.mode != 0 && s.mode != 1) bad("importance_mode must be 0 or 1");
+    if (s.max_iter < 1 || s.max_iter > 1000) bad("max_iter outside [1, 1000]");
+    if (!(s.alpha > 0.0 && s.alpha < 0.5)) bad("alpha outside (0, 0.5)");
+}
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+int64_t pow2_at_least(int64_t v) {
+    int64_t P = 1;
+    while (P < v) P <<= 1;
+    return P;
+}
+int isqrt_i(int64_t v) {
+    int64_t r = (int64_t)std::sqrt((double)v);
+    while (r * r > v) --r;
+    while ((r + 1) * (r + 1) <= v) ++r;
+    return (int)std::max<int64_t>(1, r);
+}
+
+// ---------------------------------------------------------------------------
+// Device memory plan: one region, every buffer at a 256-byte aligned offset.
+struct Region {
+    size_t total = 0;
+    size_t take(size_t bytes) {
+        const size_t off = (total + 255) & ~size_t(255);
+        total = off + std::max<size_t>(bytes, 1);
+        return off;
+    }
+};
+
+struct JobPlan {
+    int64_t n_pad, P;
+    int max_sha, pw_cap, mtry_max, ntiles_max;
+    size_t X, y32, y8, orig, sha, colptr, colsrc, act, state, hits, hist, smax, hconf, hrej, G,
+        imp, wbuf, rec0, rec1, oob, tstat;
+};
+
+struct Plan {
+    std::vector<JobPlan> jp;
+    size_t keys, jobs, trees, live, tree_base, flags, nodes, cls, ngain, items0, items1, small0,
+        small1, cand, done, ctr, alg, tot;
+    uint32_t node_cap = 0, item_cap = 0, slot_cap = 0, small_cap = 0;
+    int kmax = 4, ft = 8, max_tiles = 1, max_sha = 1, max_pw = 1, max_D = 1, T_total = 0;
+    int64_t max_n = 0;
+    size_t total = 0;
+};
+
+Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_device) {
+    Plan pl;
+    Region r;
+    int maxK = 2;
+    int64_t keys_words = 0;
+    for (const Spec& s : specs) {
+        maxK = std::max(maxK, s.K);
+        keys_words = std::max<int64_t>(keys_words, s.p * pow2_at_least(s.n));
+    }
+    pl.kmax = maxK <= 4 ? 4 : (maxK <= 8 ? 8 : 16);
+    pl.ft = (int)std::max<int64_t>(1, std::min<int64_t>(16, 8192 / ((int64_t)o.B * pl.kmax)));
+    pl.keys = r.take((size_t)keys_words * 4);
+    uint64_t node_cap = 0, item_cap = 0, slot_cap = 0, small_cap = 0;
+    for (const Spec& s : specs) {
+        JobPlan j;
+        j.n_pad = round_up(s.n, 256);
+        j.P = pow2_at_least(s.n);
+        j.max_sha = (int)std::max<int64_t>(s.p, 8);
+        j.pw_cap = (int)(s.p + j.max_sha);
+        j.mtry_max = s.mtry > 0 ? std::min(s.mtry, j.pw_cap) : isqrt_i(j.pw_cap);
+        j.ntiles_max = (j.mtry_max + pl.ft - 1) / pl.ft;
+        const size_t n = (size_t)s.n, p = (size_t)s.p, T = (size_t)s.T;
+        j.X = inputs_on_device ? 0 : r.take(n * p * 4);
+        j.y32 = inputs_on_device ? 0 : r.take(n * 4);
+        j.y8 = r.take(n);
+        j.orig = r.take(p * j.n_pad);
+        j.sha = r.take((size_t)j.max_sha * j.n_pad);
+        j.colptr = r.take((size_t)j.pw_cap * 8);
+        j.colsrc = r.take((size_t)j.pw_cap * 4);
+        j.act = r.take(p * 4);
+        j.state = r.take(p);
+        j.hits = r.take(p * 4);
+        j.hist = r.take((size_t)s.max_iter * p * 8);
+        j.smax = r.take((size_t)s.max_iter * 8);
+        j.hconf = r.take((size_t)(s.max_iter + 1) * 4);
+        j.hrej = r.take((size_t)(s.max_iter + 1) * 4);
+        j.G = s.mode == 0 ? r.take(T * j.pw_cap * 8) : 0;
+        j.imp = r.take((size_t)j.pw_cap * 8);
+        j.wbuf = r.take(T * n * 4);
+        j.rec0 = r.take(T * n * 8);
+        j.rec1 = r.take(T * n * 8);
+        j.oob = r.take(T * n * 4);
+        j.tstat = r.take(T * 16);
+        pl.jp.push_back(j);
+        const uint64_t per_tree_nodes =
+            std::min<uint64_t>((uint64_t(1) << (s.D + 1)) - 1, 2 * (uint64_t)s.n - 1);
+        node_cap += T * per_tree_nodes;
+        const uint64_t large_per_tree = (uint64_t)(s.n + kSmallRows) / (kSmallRows + 1);
+        slot_cap += T * large_per_tree;
+        item_cap += T * large_per_tree * (uint64_t)j.ntiles_max;
+        small_cap += T * (uint64_t)((s.n + 1) / 2);
+        pl.max_tiles = std::max(pl.max_tiles, j.ntiles_max);
+        pl.max_sha = std::max(pl.max_sha, j.max_sha);
+        pl.max_pw = std::max(pl.max_pw, j.pw_cap);
+        pl.max_D = std::max(pl.max_D, s.D);
+        pl.max_n = std::max(pl.max_n, s.n);
+        pl.T_total += s.T;
+    }
+    if (node_cap >= 0xFFFFFFF0ull || item_cap >= 0xFFFFFFF0ull || small_cap >= 0xFFFFFFF0ull)
+        throw Error(BORUTA_E_INVALID_ARG, "problem too large: more than 2^32 tree nodes");
+    pl.node_cap = (uint32_t)node_cap;
+    pl.item_cap = (uint32_t)item_cap;
+    pl.slot_cap = (uint32_t)slot_cap;
+    pl.small_cap = (uint32_t)small_cap;
+    pl.jobs = r.take(specs.size() * sizeof(JobDev));
+    pl.trees = r.take((size_t)pl.T_total * sizeof(TreeDev));
+    pl.live = r.take(specs.size() * 4);
+    pl.tree_base = r.take(specs.size() * 4);
+    pl.flags = r.take(64);
+    pl.nodes = r.take((size_t)pl.node_cap * sizeof(NodeDev));
+    pl.cls = r.take((size_t)pl.node_cap * pl.kmax * 4);
+    pl.ngain = r.take((size_t)pl.node_cap * 8);
+    pl.items0 = r.take((size_t)pl.item_cap * sizeof(Item));
+    pl.items1 = r.take((size_t)pl.item_cap * sizeof(Item));
+    pl.small0 = r.take((size_t)pl.small_cap * 4);
+    pl.small1 = r.take((size_t)pl.small_cap * 4);
+    pl.cand = r.take((size_t)pl.slot_cap * pl.max_tiles * sizeof(Cand));
+    pl.done = r.take((size_t)pl.slot_cap * 4);
+    pl.ctr = r.take(sizeof(LevelCtr));
+    pl.alg = r.take(16);
+    pl.tot = r.take((size_t)pl.T_total * 8);
+    pl.total = r.total + 256;
+    return pl;
+}
+
+struct Out {
+    int8_t* decision;
+    double* hist;
+    int32_t* hits;
+    double* smax;
+    int32_t n_iter = 0;
+};
+
+struct EventTimer {
+    hipEvent_t a = nullptr, b = nullptr;
+    bool on = false;
+    explicit EventTimer(bool enable) : on(enable) {
+        if (on) {
+            HIPC(hipEventCreate(&a));
+            HIPC(hipEventCreate(&b));
+        }
+    }
+    ~EventTimer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+    void start(hipStream_t st) {
+        if (on) HIPC(hipEventRecord(a, st));
+    }
+    // stop and return elapsed ms (synchronises on the stop event)
+    double stop(hipStream_t st) {
+        if (!on) return 0.0;
+        HIPC(hipEventRecord(b, st));
+        HIPC(hipEventSynchronize(b));
+        float ms = 0.f;
+        HIPC(hipEventElapsedTime(&ms, a, b));
+        return ms;
+    }
+};
+
+// ---------------------------------------------------------------------------
+class Engine {
+public:
+    Engine(const std::vector<Spec>& specs, const Opts& o, bool dev_inputs, char* base,
+           hipStream_t st)
+        : S(specs), O(o), dev_in(dev_inputs), base(base), st(st) {
+        pl = make_plan(specs, o, dev_inputs);
+    }
+
+    template <class T>
+    T* at(size_t off) const {
+        return reinterpret_cast<T*>(base + off);
+    }
+
+    void d2h(void* dst, const void* src, size_t bytes) {
+        HIPC(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+    }
+    void h2d(void* dst, const void* src, size_t bytes) {
+        HIPC(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    }
+
+    // Returns per-job status; throws on device errors.
+    void run(std::vector<Out>& outs, std::vector<int>& status);
+
+private:
+    void setup(std::vector<int>& status);
+    void iteration(const std::vector<int>& live, std::vector<Out>& outs);
+    void grow_level_plain(ForestDev F, uint32_t n_items, uint32_t n_small);
+    void emit_trace(const std::vector<int>& live, const std::vector<int>& tree_base,
+                    uint32_t n_nodes);
+
+    const std::vector<Spec>& S;
+    Opts O;
+    bool dev_in;
+    char* base;
+    hipStream_t st;
+    Plan pl;
+    std::vector<JobDev> hj;  // host mirror of the job records
+};
+
+void Engine::setup(std::vector<int>& status) {
+    const int nj = (int)S.size();
+    hj.assign(nj, JobDev{});
+    uint32_t* flags = at<uint32_t>(pl.flags);
+    for (int j = 0; j < nj; ++j) {
+        const Spec& s = S[j];
+        const JobPlan& jp = pl.jp[j];
+        const float* X = dev_in ? s.X : at<float>(jp.X);
+        const int32_t* y = dev_in ? s.y : at<int32_t>(jp.y32);
+        if (!dev_in) {
+            h2d((void*)X, s.X, (size_t)s.n * s.p * 4);
+            h2d((void*)y, s.y, (size_t)s.n * 4);
+        }
+        launch_fill_u32(flags, 1, 0u, st);
+        launch_validate(X, (size_t)s.n * s.p, y, (size_t)s.n, s.K, flags, st);
+        uint32_t f = 0;
+        d2h(&f, flags, 4);
+        if (f & 1u) {
+            status[j] = BORUTA_E_NONFINITE;
+            continue;
+        }
+        if (f & 2u) {
+            status[j] = BORUTA_E_INVALID_ARG;
+            continue;
+        }
+        launch_labels(y, (size_t)s.n, at<uint8_t>(jp.y8), st);
+        launch_binning(X, s.n, s.p, O.B, at<uint8_t>(jp.orig), jp.n_pad, at<uint32_t>(pl.keys),
+                       jp.P, st);
+        int ex = 0;
+        const double fr = std::frexp(s.alpha, &ex);
+        const uint64_t am = (uint64_t)std::ldexp(fr, 53);
+        launch_thresholds(s.max_iter, s.p, am, ex - 53, at<int32_t>(jp.hconf),
+                          at<int32_t>(jp.hrej), st);
+        JobDev& J = hj[j];
+        J.n = (int32_t)s.n;
+        J.n_pad = (int32_t)jp.n_pad;
+        J.p = (int32_t)s.p;
+        J.K = s.K;
+        J.B = O.B;
+        J.T = s.T;
+        J.D = s.D;
+        J.mtry_opt = s.mtry;
+        J.mode = s.mode;
+        J.R = O.R;
+        J.max_iter = s.max_iter;
+        J.seed_lo = (uint32_t)s.seed;
+        J.seed_hi = (uint32_t)(s.seed >> 32);
+        J.max_sha = jp.max_sha;
+        J.pw_cap = jp.pw_cap;
+        J.y = at<uint8_t>(jp.y8);
+        J.orig = at<uint8_t>(jp.orig);
+        J.sha = at<uint8_t>(jp.sha);
+        J.colptr = at<const uint8_t*>(jp.colptr);
+        J.col_src = at<int32_t>(jp.colsrc);
+        J.act = at<int32_t>(jp.act);
+        J.state = at<int8_t>(jp.state);
+        J.hits = at<int32_t>(jp.hits);
+        J.hist = at<double>(jp.hist);
+        J.shadow_max = at<double>(jp.smax);
+        J.h_conf = at<int32_t>(jp.hconf);
+        J.h_rej = at<int32_t>(jp.hrej);
+        J.G = s.mode == 0 ? at<uint64_t>(jp.G) : nullptr;
+        J.imp = at<int64_t>(jp.imp);
+        J.wbuf = at<uint32_t>(jp.wbuf);
+        J.rec[0] = at<uint64_t>(jp.rec0);
+        J.rec[1] = at<uint64_t>(jp.rec1);
+        J.oob = at<uint32_t>(jp.oob);
+        J.tstat = at<int32_t>(jp.tstat);
+        J.t = 0;
+        J.live = 1;
+        launch_fill_u32((uint32_t*)J.state, ((size_t)s.p + 3) / 4, 0u, st);
+        launch_fill_u32((uint32_t*)J.hits, (size_t)s.p, 0u, st);
+        if (s.mode == 0)
+            launch_fill_u32((uint32_t*)J.G, (size_t)s.T * jp.pw_cap * 2, 0u, st);
+        status[j] = BORUTA_OK;
+    }
+    for (int j = 0; j < nj; ++j)
+        if (status[j] != BORUTA_OK) hj[j].live = 0;
+    launch_fill_u32(at<uint32_t>(pl.done), pl.slot_cap, 0u, st);
+    h2d(at<JobDev>(pl.jobs), hj.data(), hj.size() * sizeof(JobDev));
+    HIPC(hipStreamSynchronize(st));
+}
+
+void Engine::grow_level_plain(ForestDev F, uint32_t n_items, uint32_t n_small) {
+    // One launch per node: the node lists are read back and each node's
+    // split search is its own launch.
+    std::vector<uint32_t> small(n_small);
+    std::vector<Item> items(n_items);
+    if (n_small) d2h(small.data(), F.small_in, n_small * 4);
+    if (n_items) d2h(items.data(), F.items_in, n_items * sizeof(Item));
+    const uint32_t* small_base = F.small_in;
+    for (uint32_t i = 0; i < n_small; ++i) {
+        F.small_in = small_base + i;
+        launch_split_small(F, 1, st);
+    }
+    const Item* item_base = F.items_in;
+    for (uint32_t a = 0; a < n_items;) {
+        uint32_t b = a + 1;
+        while (b < n_items && items[b].node == items[a].node) ++b;
+        F.items_in = item_base + a;
+        launch_split_large(F, b - a, O.B, st);
+        a = b;
+    }
+}
+
+void Engine::iteration(const std::vector<int>& live, std::vector<Out>& outs) {
+    const int nj = (int)S.size();
+    // trees of the live jobs, in job order
+    std::vector<TreeDev> trees;
+    std::vector<int> tree_base;
+    for (int j : live) {
+        tree_base.push_back((int)trees.size());
+        for (int tau = 0; tau < S[j].T; ++tau) trees.push_back(TreeDev{j, tau});
+    }
+    const int n_trees = (int)trees.size();
+    const int n_live = (int)live.size();
+    h2d(at<TreeDev>(pl.trees), trees.data(), trees.size() * sizeof(TreeDev));
+    h2d(at<int32_t>(pl.live), live.data(), live.size() * 4);
+    h2d(at<int32_t>(pl.tree_base), tree_base.data(), tree_base.size() * 4);
+    JobDev* djobs = at<JobDev>(pl.jobs);
+    launch_active(djobs, nj, pl.ft, st);
+    d2h(hj.data(), djobs, hj.size() * sizeof(JobDev));
+    int64_t max_n = 0;
+    int max_sha = 1, max_pw = 1, max_D = 1;
+    bool any_permut = false;
+    for (int j : live) {
+        const JobDev& J = hj[j];
+        max_n = std::max<int64_t>(max_n, J.n);
+        max_sha = std::max(max_sha, J.n_sha);
+        max_pw = std::max(max_pw, J.p_w);
+        max_D = std::max(max_D, J.D);
+        any_permut |= J.mode == 1;
+        launch_fill_u32(J.wbuf, (size_t)J.T * J.n, 0u, st);
+        if (J.mode == 1) launch_fill_u32((uint32_t*)J.imp, (size_t)J.p_w * 2, 0u, st);
+    }
+    launch_shadow(djobs, at<int32_t>(pl.live), n_live, max_n, max_sha, st);
+    launch_boot_draw(djobs, at<TreeDev>(pl.trees), n_trees, max_n, st);
+
+    ForestDev F;
+    F.jobs = djobs;
+    F.trees = at<TreeDev>(pl.trees);
+    F.nodes = at<NodeDev>(pl.nodes);
+    F.cls = at<uint32_t>(pl.cls);
+    F.ngain = at<uint64_t>(pl.ngain);
+    F.cand = at<Cand>(pl.cand);
+    F.done = at<uint32_t>(pl.done);
+    Item* items[2] = {at<Item>(pl.items0), at<Item>(pl.items1)};
+    uint32_t* small[2] = {at<uint32_t>(pl.small0), at<uint32_t>(pl.small1)};
+    F.ctr = at<LevelCtr>(pl.ctr);
+    F.alg_bytes = O.stats ? at<uint64_t>(pl.alg) : nullptr;
+    F.node_cap = pl.node_cap;
+    F.item_cap = pl.item_cap;
+    F.slot_cap = pl.slot_cap;
+    F.small_cap = pl.small_cap;
+    F.kmax = pl.kmax;
+    F.ft = pl.ft;
+    F.max_tiles = pl.max_tiles;
+    F.split_rank = O.split_rank;
+    F.pad = 0;
+    F.items_in = items[1];
+    F.small_in = small[1];
+    F.items_out = items[0];
+    F.small_out = small[0];
+    F.next_base = (uint32_t)n_trees;
+    F.parity = 0;
+    if ((uint32_t)n_trees > pl.node_cap) throw Error(BORUTA_E_DEVICE, "node pool too small");
+    launch_fill_u32((uint32_t*)F.ctr, sizeof(LevelCtr) / 4, 0u, st);
+    launch_boot_compact(F, (uint32_t)n_trees, st);
+    LevelCtr c;
+    d2h(&c, F.ctr, sizeof(c));
+    uint32_t n_nodes = (uint32_t)n_trees;
+    uint32_t work_items = c.n_items, work_small = c.n_small;
+    if (c.overflow) throw Error(BORUTA_E_DEVICE, "internal capacity exceeded (roots)");
+    EventTimer tl(O.stats != nullptr), ts(O.stats != nullptr);
+    for (int d = 0; work_items || work_small; ++d) {
+        F.items_in = items[d & 1];
+        F.small_in = small[d & 1];
+        F.items_out = items[(d + 1) & 1];
+        F.small_out = small[(d + 1) & 1];
+        F.next_base = n_nodes;
+        F.parity = d & 1;
+        launch_fill_u32((uint32_t*)F.ctr, sizeof(LevelCtr) / 4, 0u, st);
+        if (O.form == BORUTA_FORM_PLAIN) {
+            grow_level_plain(F, work_items, work_small);
+        } else {
+            if (work_small) {
+                ts.start(st);
+                launch_split_small(F, work_small, st);
+                if (O.stats) {
+                    O.stats->hist_small.ms += ts.stop(st);
+                    O.stats->hist_small.launches += 1;
+                }
+            }
+            if (work_items) {
+                tl.start(st);
+                launch_split_large(F, work_items, O.B, st);
+                if (O.stats) {
+                    O.stats->hist_large.ms += tl.stop(st);
+                    O.stats->hist_large.launches += 1;
+                }
+            }
+        }
+        d2h(&c, F.ctr, sizeof(c));
+        if (c.overflow) throw Error(BORUTA_E_DEVICE, "internal capacity exceeded (tree level)");
+        n_nodes += c.n_nodes;
+        work_items = c.n_items;
+        work_small = c.n_small;
+    }
+    if (O.stats) O.stats->nodes += n_nodes;
+
+    // importance
+    bool any_treeimp = false;
+    for (int j : live) any_treeimp |= hj[j].mode == 0;
+    if (any_treeimp) {
+        launch_tree_totals(djobs, at<TreeDev>(pl.trees), n_trees, at<uint64_t>(pl.tot), st);
+        launch_treeimp(djobs, at<int32_t>(pl.live), n_live, at<int32_t>(pl.tree_base),
+                       at<uint64_t>(pl.tot), max_pw, st);
+    }
+    if (any_permut) {
+        EventTimer tp(O.stats != nullptr);
+        tp.start(st);
+        launch_permut(djobs, at<TreeDev>(pl.trees), F.nodes, n_trees, max_n, max_D, st);
+        if (O.stats) {
+            O.stats->permut.ms += tp.stop(st);
+            O.stats->permut.launches += 1;
+        }
+    }
+    launch_hits_decide(djobs, nj, st);
+    d2h(hj.data(), djobs, hj.size() * sizeof(JobDev));
+    if (O.trace) emit_trace(live, tree_base, n_nodes);
+    for (int j : live) outs[j].n_iter = hj[j].t;
+    if (O.stats) O.stats->iterations += n_live;
+}
+
+void Engine::emit_trace(const std::vector<int>& live, const std::vector<int>& tree_base,
+                        uint32_t n_nodes) {
+    // Called after the decision kernel: importances and trees are those of
+    // this iteration, hits and states already include its decision.
+    std::vector<NodeDev> nodes(n_nodes);
+    std::vector<uint64_t> gains(n_nodes);
+    d2h(nodes.data(), at<NodeDev>(pl.nodes), (size_t)n_nodes * sizeof(NodeDev));
+    d2h(gains.data(), at<uint64_t>(pl.ngain), (size_t)n_nodes * 8);
+    for (size_t li = 0; li < live.size(); ++li) {
+        const int j = live[li];
+        const JobDev& J = hj[j];
+        std::vector<int32_t> col_src(J.p_w), hits(J.p), tstat((size_t)J.T * 4);
+        std::vector<int64_t> imp(J.p_w);
+        std::vector<int8_t> state(J.p);
+        d2h(col_src.data(), J.col_src, (size_t)J.p_w * 4);
+        d2h(imp.data(), J.imp, (size_t)J.p_w * 8);
+        d2h(hits.data(), J.hits, (size_t)J.p * 4);
+        d2h(state.data(), J.state, (size_t)J.p);
+        d2h(tstat.data(), J.tstat, tstat.size() * 4);
+        const int g0 = tree_base[li];
+        std::vector<std::vector<uint32_t>> idx(J.T);
+        for (uint32_t i = 0; i < n_nodes; ++i) {
+            const int g = (int)nodes[i].tree;
+            if (g >= g0 && g < g0 + J.T) idx[g - g0].push_back(i);
+        }
+        std::vector<int64_t> rows, stats;
+        for (int tau = 0; tau < J.T; ++tau) {
+            auto& v = idx[tau];
+            std::sort(v.begin(), v.end(),
+                      [&](uint32_t a, uint32_t b) { return nodes[a].heap < nodes[b].heap; });
+            for (uint32_t i : v) {
+                const NodeDev& nd = nodes[i];
+                rows.insert(rows.end(), {(int64_t)tau, (int64_t)nd.heap, (int64_t)nd.feat,
+                                         (int64_t)(nd.feat >= 0 ? nd.thr : nd.leaf_class),
+                                         (int64_t)nd.n, (int64_t)gains[i]});
+            }
+            stats.insert(stats.end(), {(int64_t)tau, (int64_t)tstat[tau * 4 + 0],
+                                       (int64_t)tstat[tau * 4 + 1],
+                                       (int64_t)(J.mode == 1 ? tstat[tau * 4 + 2] : 0),
+                                       (int64_t)v.size()});
+        }
+        boruta_iter_trace tr;
+        tr.job = j;
+        tr.t = J.t;
+        tr.p_cur = J.p_cur;
+        tr.n_sha = J.n_sha;
+        tr.p_w = J.p_w;
+        tr.mtry = J.mtry;
+        tr.n_trees = J.T;
+        tr.col_src = col_src.data();
+        tr.imp_int = imp.data();
+        tr.hits = hits.data();
+        tr.state = state.data();
+        tr.tree_stats = stats.data();
+        tr.n_nodes = (int64_t)(rows.size() / 6);
+        tr.nodes = rows.data();
+        O.trace(O.trace_user, &tr);
+    }
+}
+
+void Engine::run(std::vector<Out>& outs, std::vector<int>& status) {
+    setup(status);
+    EventTimer ti(O.stats != nullptr);
+    ti.start(st);
+    for (;;) {
+        std::vector<int> live;
+        for (int j = 0; j < (int)S.size(); ++j)
+            if (hj[j].live) live.push_back(j);
+        if (live.empty()) break;
+        iteration(live, outs);
+    }
+    if (O.stats) O.stats->iter_ms += ti.stop(st);
+    if (O.stats) {
+        uint64_t ab[2];
+        d2h(ab, at<uint64_t>(pl.alg), 16);
+        O.stats->hist_large.alg_bytes += (double)ab[0];
+        O.stats->hist_small.alg_bytes += (double)ab[1];
+    }
+    for (int j = 0; j < (int)S.size(); ++j) {
+        if (status[j] != BORUTA_OK) continue;
+        const Spec& s = S[j];
+        const JobDev& J = hj[j];
+        Out& o = outs[j];
+        d2h(o.decision, J.state, (size_t)s.p);
+        if (J.t > 0) d2h(o.hist, J.hist, (size_t)J.t * s.p * 8);
+        if (o.hits) d2h(o.hits, J.hits, (size_t)s.p * 4);
+        if (o.smax && J.t > 0) d2h(o.smax, J.shadow_max, (size_t)J.t * 8);
+        o.n_iter = J.t;
+    }
+}
+
+struct DeviceRegion {
+    char* p = nullptr;
+    ~DeviceRegion() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+void require_device() {
+    int count = 0;
+    const hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count < 1)
+        throw Error(BORUTA_E_UNSUPPORTED, std::string("no HIP device available (") +
+                                              hipGetErrorName(e) + ", " + std::to_string(count) +
+                                              " devices)");
+    int dev = 0;
+    HIPC(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPC(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        throw Error(BORUTA_E_UNSUPPORTED, std::string("device is ") + prop.gcnArchName +
+                                              ", this library is built for gfx950");
+}
+
+int run_jobs(const std::vector<Spec>& specs, const boruta_options* opt, std::vector<Out>& outs,
+             std::vector<int>& status, bool dev_inputs, void* ws, size_t ws_bytes,
+             hipStream_t user_stream) {
+    g_err.clear();
+    try {
+        const Opts o = read_opts(opt);
+        for (const Spec& s : specs) check_spec(s);
+        require_device();
+        hipStream_t st = user_stream;
+        bool own_stream = false;
+        if (!ws) {
+            if (!st) {
+                HIPC(hipStreamCreate(&st));
+                own_stream = true;
+            }
+        }
+        struct StreamGuard {
+            hipStream_t s;
+            bool own;
+            ~StreamGuard() {
+                if (own) (void)hipStreamDestroy(s);
+            }
+        } sg{st, own_stream};
+        const size_t need = make_plan(specs, o, dev_inputs).total;
+        DeviceRegion reg;
+        char* base = nullptr;
+        if (ws) {
+            if (ws_bytes < need)
+                throw Error(BORUTA_E_OOM, "workspace smaller than boruta_workspace_size");
+            base = (char*)ws;
+        } else {
+            if (hipMalloc(&reg.p, need) != hipSuccess) {
+                (void)hipGetLastError();
+                throw Error(BORUTA_E_OOM, "hipMalloc of " + std::to_string(need) + " bytes failed");
+            }
+            base = reg.p;
+        }
+        base = (char*)(((uintptr_t)base + 255) & ~uintptr_t(255));
+        Engine eng(specs, o, dev_inputs, base, st);
+        eng.run(outs, status);
+        HIPC(hipStreamSynchronize(st));
+        for (int s : status)
+            if (s != BORUTA_OK) {
+                g_err = "a job failed validation";
+                return s;
+            }
+        return BORUTA_OK;
+    } catch (const Error& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return BORUTA_E_DEVICE;
+    }
+}
+
+
+Spec spec_from(const float* X, const int32_t* y, int64_t n, int64_t p, int32_t K, int32_t T,
+               int32_t D, int32_t mtry, int32_t mode, int32_t max_iter, double alpha,
+               uint64_t seed) {
+    return Spec{X, y, n, p, K, T, D, mtry, mode, max_iter, alpha, seed};
+}
+
+int finish_single(int rc, const std::vector<Out>& outs, int32_t* n_iter_out) {
+    if (n_iter_out) *n_iter_out = outs[0].n_iter;
+    return rc;
+}
+
+}  // namespace
+}  // namespace boruta
+
+using namespace boruta;
+
+extern "C" {
+
+void boruta_default_options(boruta_options* opt) {
+    if (!opt) return;
+    opt->n_bins = 256;
+    opt->n_perm = 1;
+    opt->split_rank = BORUTA_RANK_FP32;
+    opt->form = BORUTA_FORM_BATCHED;
+    opt->trace = nullptr;
+    opt->trace_user = nullptr;
+    opt->stats = nullptr;
+}
+
+int boruta_fit_ex(const float* X, const int32_t* y, int64_t n, int64_t p, int32_t n_classes,
+                  int32_t n_trees, int32_t max_depth, int32_t mtry, int32_t importance_mode,
+                  int32_t max_iter, double alpha, uint64_t seed, const boruta_options* opt,
+                  int8_t* decision_out, double* imp_history_out, int32_t* hits_out,
+                  double* shadow_max_out, int32_t* n_iter_out) {
+    if (!decision_out || !imp_history_out || !n_iter_out) {
+        g_err = "decision_out, imp_history_out and n_iter_out must be non-null";
+        return BORUTA_E_INVALID_ARG;
+    }
+    std::vector<Spec> specs{spec_from(X, y, n, p, n_classes, n_trees, max_depth, mtry,
+                                      importance_mode, max_iter, alpha, seed)};
+    std::vector<Out> outs(1);
+    outs[0].decision = decision_out;
+    outs[0].hist = imp_history_out;
+    outs[0].hits = hits_out;
+    outs[0].smax = shadow_max_out;
+    std::vector<int> status(1, BORUTA_OK);
+    const int rc = run_jobs(specs, opt, outs, status, false, nullptr, 0, nullptr);
+    return finish_single(rc, outs, n_iter_out);
+}
+
+int boruta_fit(const float* X, const int32_t* y, int64_t n, int64_t p, int32_t n_classes,
+               int32_t n_trees, int32_t max_depth, int32_t mtry, int32_t importance_mode,
+               int32_t max_iter, double alpha, uint64_t seed, int8_t* decision_out,
+               double* imp_history_out, int32_t* hits_out, double* shadow_max_out,
+               int32_t* n_iter_out) {
+    return boruta_fit_ex(X, y, n, p, n_classes, n_trees, max_depth, mtry, importance_mode,
+                         max_iter, alpha, seed, nullptr, decision_out, imp_history_out, hits_out,
+                         shadow_max_out, n_iter_out);
+}
+
+static std::vector<Spec> specs_of(const boruta_job* jobs, int32_t n_jobs) {
+    std::vector<Spec> specs;
+    for (int i = 0; i < n_jobs; ++i) {
+        const boruta_job& b = jobs[i];
+        specs.push_back(spec_from(b.X, b.y, b.n, b.p, b.n_classes, b.n_trees, b.max_depth,
+                                  b.mtry, b.importance_mode, b.max_iter, b.alpha, b.seed));
+    }
+    return specs;
+}
+
+int boruta_fit_batch(const boruta_job* jobs, int32_t n_jobs, const boruta_options* opt,
+                     boruta_result* results) {
+    g_err.clear();
+    if (!jobs || !results || n_jobs < 1) {
+        g_err = "jobs/results must be non-null and n_jobs >= 1";
+        return BORUTA_E_INVALID_ARG;
+    }
+    std::vector<Spec> specs = specs_of(jobs, n_jobs);
+    std::vector<Out> outs(n_jobs);
+    for (int i = 0; i < n_jobs; ++i) {
+        if (!results[i].decision || !results[i].imp_history) {
+            g_err = "every result needs decision and imp_history buffers";
+            return BORUTA_E_INVALID_ARG;
+        }
+        outs[i].decision = results[i].decision;
+        outs[i].hist = results[i].imp_history;
+        outs[i].hits = results[i].hits;
+        outs[i].smax = results[i].shadow_max;
+    }
+    std::vector<int> status(n_jobs, BORUTA_OK);
+    const int rc = run_jobs(specs, opt, outs, status, false, nullptr, 0, nullptr);
+    for (int i = 0; i < n_jobs; ++i) {
+        results[i].n_iter = outs[i].n_iter;
+        results[i].status = rc == BORUTA_OK ? status[i] : (status[i] != BORUTA_OK ? status[i] : rc);
+    }
+    return rc;
+}
+
+int boruta_workspace_size(const boruta_job* jobs, int32_t n_jobs, const boruta_options* opt,
+                          size_t* bytes) {
+    g_err.clear();
+    if (!jobs || n_jobs < 1 || !bytes) {
+        g_err = "jobs and bytes must be non-null, n_jobs >= 1";
+        return BORUTA_E_INVALID_ARG;
+    }
+    try {
+        const Opts o = read_opts(opt);
+        std::vector<Spec> specs = specs_of(jobs, n_jobs);
+        for (const Spec& s : specs) {
+            if (s.n < 2 || s.n > (int64_t(1) << 24) || s.p < 1 || s.p > (int64_t(1) << 24) ||
+                s.T < 1 || s.D < 1 || s.D > 30 || s.max_iter < 1 || s.max_iter > 1000 ||
+                s.K < 2 || s.K > 16 || s.mode < 0 || s.mode > 1 || s.mtry < 0)
+                throw Error(BORUTA_E_INVALID_ARG, "job arguments out of range");
+        }
+        *bytes = make_plan(specs, o, true).total;
+        return BORUTA_OK;
+    } catch (const Error& e) {
+        g_err = e.what();
+        return e.code;
+    }
+}
+
+int boruta_fit_device(const float* dX, const int32_t* dy, int64_t n, int64_t p,
+                      int32_t n_classes, int32_t n_trees, int32_t max_depth, int32_t mtry,
+                      int32_t importance_mode, int32_t max_iter, double alpha, uint64_t seed,
+                      const boruta_options* opt, void* workspace, size_t ws_bytes,
+                      void* hip_stream, int8_t* decision_out, double* imp_history_out,
+                      int32_t* hits_out, double* shadow_max_out, int32_t* n_iter_out) {
+    if (!decision_out || !imp_history_out || !n_iter_out || !workspace) {
+        g_err = "decision_out, imp_history_out, n_iter_out and workspace must be non-null";
+        return BORUTA_E_INVALID_ARG;
+    }
+    std::vector<Spec> specs{spec_from(dX, dy, n, p, n_classes, n_trees, max_depth, mtry,
+                                      importance_mode, max_iter, alpha, seed)};
+    std::vector<Out> outs(1);
+    outs[0].decision = decision_out;
+    outs[0].hist = imp_history_out;
+    outs[0].hits = hits_out;
+    outs[0].smax = shadow_max_out;
+    std::vector<int> status(1, BORUTA_OK);
+    const int rc = run_jobs(specs, opt, outs, status, true, workspace, ws_bytes,
+                            (hipStream_t)hip_stream);
+    return finish_single(rc, outs, n_iter_out);
+}
+
+int boruta_probe_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
+    g_err.clear();
+    if (!dst || !src || bytes % 16) {
+        g_err = "dst/src must be non-null and bytes a multiple of 16";
+        return BORUTA_E_INVALID_ARG;
+    }
+    launch_copy(dst, src, bytes, (hipStream_t)hip_stream);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        g_err = hipGetErrorString(e);
+        return BORUTA_E_DEVICE;
+    }
+    return BORUTA_OK;
+}
+
+const char* boruta_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+// forest_dev.hpp -- device functions shared by the tree-growth kernels:
+// node creation / classification and wave-level candidate reductions.
+#pragma once
+
+#include "dev_common.hpp"
+
+namespace boruta {
+
+// Lane-ordered comparison of two candidates of ONE feature: higher Q first,
+// then the smaller threshold (the smallest b of an equal-score partition).
+// Invalid candidates (nl == 0) lose to everything.
+__device__ __forceinline__ bool cand_wins_same_feature(const Cand& a, const Cand& b) {
+    if (b.nl == 0) return a.nl != 0 || a.b < b.b;
+    if (a.nl == 0) return false;
+    if (cand_better(a, b)) return true;
+    if (cand_better(b, a)) return false;
+    return a.b < b.b;
+}
+
+__device__ __forceinline__ Cand shfl_cand(const Cand& c, int src) {
+    Cand o;
+    o.q = __shfl(c.q, src);
+    o.f = __shfl(c.f, src);
+    o.b = __shfl(c.b, src);
+    o.nl = __shfl(c.nl, src);
+    o.nr = __shfl(c.nr, src);
+    o.pad = 0;
+    o.sl = __shfl(c.sl, src);
+    o.sr = __shfl(c.sr, src);
+    return o;
+}
+
+__device__ __forceinline__ Cand shfl_xor_cand(const Cand& c, int m) {
+    return shfl_cand(c, (int)((threadIdx.x & 63) ^ m));
+}
+
+// Exact wave-wide best of one feature's candidates (all lanes get it).
+__device__ __forceinline__ Cand wave_best_exact(Cand c) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        const Cand o = shfl_xor_cand(c, m);
+        if (cand_wins_same_feature(o, c)) c = o;
+    }
+    return c;
+}
+
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v = fmaxf(v, __shfl_xor(v, m));
+    return v;
+}
+
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v = min(v, __shfl_xor(v, m));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v = max(v, __shfl_xor(v, m));
+    return v;
+}
+
+// Relative margin of the FP32 ranking: every lane's FP32 score is within
+// 3 ulp (2^-24 each) of its exact value, so the exact best scores at least
+// (1 - 6 * 2^-24) * FP32 max; candidates at or above (1 - 2^-20) * FP32 max
+// are re-ranked exactly.
+__device__ __forceinline__ float fp32_floor(float qmax) { return qmax * (1.0f - 0x1.0p-20f); }
+
+// Best of one feature's candidates with FP32 ranking and exact recheck of the
+// finalists.  q32 < 0 marks an invalid candidate.
+__device__ __forceinline__ Cand wave_best_fp32(const Cand& c, float q32) {
+    const float qmax = wave_max_f(q32);
+    Cand out;
+    out.nl = 0;
+    out.b = 0x7FFFFFFF;
+    if (qmax < 0.0f) return out;  // no valid candidate in the wave
+    const bool fin = q32 >= fp32_floor(qmax);
+    const int bmin = wave_min_i(fin ? c.b : 0x7FFFFFFF);
+    const int bmax = wave_max_i(fin ? c.b : -1);
+    if (bmin == bmax) {
+        // one threshold among the finalists: the same candidate in every finalist lane
+        const unsigned long long mask = __ballot(fin && c.b == bmin);
+        return shfl_cand(c, (int)__ffsll(mask) - 1);
+    }
+    Cand f = c;
+    if (!fin) {
+        f.nl = 0;
+        f.b = 0x7FFFFFFF;
+    }
+    return wave_best_exact(f);
+}
+
+// Fill a new node record and queue it for a split search, or finalise it
+// as a leaf.  counts[k] are its weighted class counts.
+__device__ inline void init_node(const ForestDev& F, const JobDev& J, uint32_t idx, uint32_t tree,
+                                 uint32_t heap, uint32_t seg, uint32_t len, uint32_t n,
+                                 uint32_t depth, const uint32_t* counts) {
+    uint32_t arg = 0, nonzero = 0;
+    for (int k = 0; k < J.K; ++k) {
+        F.cls[(size_t)idx * F.kmax + k] = counts[k];
+        if (counts[k] > counts[arg]) arg = k;
+        nonzero += counts[k] != 0;
+    }
+    NodeDev nd;
+    nd.tree = tree;
+    nd.heap = heap;
+    nd.seg = seg;
+    nd.len = len;
+    nd.n = n;
+    nd.feat = -1;
+    nd.left = 0;
+    nd.thr = 0;
+    nd.leaf_class = (uint8_t)arg;
+    nd.depth = (uint8_t)depth;
+    F.nodes[idx] = nd;
+    F.ngain[idx] = 0;
+    if ((int)depth >= J.D || len < 2 || nonzero <= 1) return;  // leaf
+    if (len <= (uint32_t)kSmallRows && n < 65536u) {
+        const uint32_t s = atomicAdd(&F.ctr->n_small, 1u);
+        if (s < F.small_cap)
+            F.small_out[s] = idx;
+        else
+            atomicOr(&F.ctr->overflow, 1u);
+        return;
+    }
+    const uint32_t ntiles = (uint32_t)J.ntiles;
+    const uint32_t slot = atomicAdd(&F.ctr->n_slots, 1u);
+    const uint32_t it = atomicAdd(&F.ctr->n_items, ntiles);
+    if (slot >= F.slot_cap || it + ntiles > F.item_cap) {
+        atomicOr(&F.ctr->overflow, 2u);
+        return;
+    }
+    for (uint32_t tl = 0; tl < ntiles; ++tl) F.items_out[it + tl] = Item{idx, slot, tl, 0};
+}
+
+// Turn node `id` into a split on (best.f, best.b) with the given child row
+// counts / class counts, and create both children in the next level.
+__device__ inline void split_node(const ForestDev& F, JobDev& J, const TreeDev& tr, uint32_t id,
+                                  const NodeDev& nd, const Cand& best, uint32_t nl_rows,
+                                  const uint32_t* cl, const uint32_t* cr, uint64_t gain) {
+    const uint32_t off = atomicAdd(&F.ctr->n_nodes, 2u);
+    const uint32_t child = F.next_base + off;
+    if (child + 2 > F.node_cap) {
+        atomicOr(&F.ctr->overflow, 4u);
+        return;  // stays a leaf; the host reports the failure
+    }
+    F.nodes[id].feat = best.f;
+    F.nodes[id].thr = (uint16_t)best.b;
+    F.nodes[id].left = child;
+    F.ngain[id] = gain;
+    if (J.mode == 0)
+        atomicAdd((unsigned long long*)&J.G[(size_t)tr.tau * J.pw_cap + best.f],
+                  (unsigned long long)gain);
+    init_node(F, J, child, nd.tree, 2 * nd.heap, nd.seg, nl_rows, best.nl, nd.depth + 1u, cl);
+    init_node(F, J, child + 1, nd.tree, 2 * nd.heap + 1, nd.seg + nl_rows, nd.len - nl_rows,
+              best.nr, nd.depth + 1u, cr);
+}
+
+}  // namespace boruta

@@ -1,0 +1,472 @@
+// k_forest.hip -- random-forest growth kernels (gfx950).
+//
+// Trees grow level by level, all trees of all live jobs in the same launch:
+//   * k_boot_compact  per tree: in-bag row records and OOB rows from the
+//                     bootstrap multiplicities, root node;
+//   * k_split_small   one wavefront per node with <= 64 distinct rows: the
+//                     rows sit in lanes and every threshold's left class
+//                     counts come from an in-register all-pairs sum;
+//   * k_split_large   one workgroup per (node, tile of drawn features):
+//                     LDS class-count histogram [feature][bin][class] built
+//                     with LDS atomics, then a wave prefix scan over the bins
+//                     per feature.  The last tile of a node to finish picks the
+//                     node's split and stably partitions its rows.
+// The split rule (reading of the Gini forest of Sec. 2.1): maximise
+// Q = S_L/N_L + S_R/N_R over drawn features and thresholds "bin <= b",
+// exact rational comparison, ties to the earlier draw then the smaller b;
+// split only on a strictly positive decrease Q - S/N.
+#include "forest_dev.hpp"
+
+namespace boruta {
+
+// ---------------------------------------------------------------------------
+// Per tree: compact the in-bag rows (multiplicity > 0, ascending) into row
+// records and the out-of-bag rows into a list; create the root node.
+__global__ __launch_bounds__(1024) void k_boot_compact(ForestDev F) {
+    __shared__ uint32_t s_win[16], s_wout[16];
+    __shared__ uint32_t s_cls[16];
+    __shared__ uint32_t s_base_in, s_base_out;
+    const uint32_t g = blockIdx.x;
+    const TreeDev tr = F.trees[g];
+    JobDev& J = F.jobs[tr.job];
+    const uint32_t n = (uint32_t)J.n;
+    const uint32_t* w = J.wbuf + (size_t)tr.tau * n;
+    uint64_t* recs = J.rec[0] + (size_t)tr.tau * n;
+    uint32_t* oob = J.oob + (size_t)tr.tau * n;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < 16) s_cls[tid] = 0;
+    if (tid == 0) {
+        s_base_in = 0;
+        s_base_out = 0;
+    }
+    __syncthreads();
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (uint32_t base = 0; base < n; base += 1024) {
+        const uint32_t i = base + tid;
+        const uint32_t wi = i < n ? w[i] : 0u;
+        const bool inb = i < n && wi > 0, isoob = i < n && wi == 0;
+        const uint64_t mi = __ballot(inb), mo = __ballot(isoob);
+        if (lane == 0) {
+            s_win[wave] = __popcll(mi);
+            s_wout[wave] = __popcll(mo);
+        }
+        __syncthreads();
+        uint32_t pin = s_base_in, pout = s_base_out;
+        for (int v = 0; v < wave; ++v) {
+            pin += s_win[v];
+            pout += s_wout[v];
+        }
+        if (inb) {
+            const uint32_t yi = J.y[i];
+            if (wi > 0xFFFFu) atomicOr(&F.ctr->overflow, 8u);
+            recs[pin + __popcll(mi & below)] = rec_pack(i, wi, yi);
+            atomicAdd(&s_cls[yi], wi);
+        }
+        if (isoob) oob[pout + __popcll(mo & below)] = i;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t ti = 0, to = 0;
+            for (int v = 0; v < 16; ++v) {
+                ti += s_win[v];
+                to += s_wout[v];
+            }
+            s_base_in += ti;
+            s_base_out += to;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        J.tstat[tr.tau * 4 + 0] = (int32_t)s_base_in;
+        J.tstat[tr.tau * 4 + 1] = (int32_t)s_base_out;
+        J.tstat[tr.tau * 4 + 2] = 0;
+        uint32_t counts[16], tot = 0;
+        for (int k = 0; k < 16; ++k) {
+            counts[k] = s_cls[k];
+            tot += s_cls[k];
+        }
+        init_node(F, J, g, g, 1u, 0u, s_base_in, tot, 0u, counts);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Small nodes: one wavefront per node, one row per lane.
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_split_small(ForestDev F, uint32_t n_small) {
+    constexpr int NW = (KMAX + 3) / 4;  // 16-bit class counters packed four per u64
+    const int lane = threadIdx.x & 63;
+    const uint32_t idx = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (idx >= n_small) return;
+    const uint32_t id = F.small_in[idx];
+    const NodeDev nd = F.nodes[id];
+    const TreeDev tr = F.trees[nd.tree];
+    JobDev& J = F.jobs[tr.job];
+    const int B = J.B;
+    const size_t tbase = (size_t)tr.tau * J.n + nd.seg;
+    const uint64_t* rin = J.rec[F.parity] + tbase;
+    uint64_t* rout = J.rec[F.parity ^ 1] + tbase;
+    const int len = (int)nd.len;
+    const bool valid = lane < len;
+    const uint64_t rec = valid ? rin[lane] : 0ull;
+    const uint32_t row = rec_row(rec), wt = rec_w(rec), yv = rec_y(rec);
+    uint64_t cv[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i)
+        cv[i] = (valid && (int)(yv >> 2) == i) ? ((uint64_t)wt << (16 * (yv & 3))) : 0ull;
+    uint32_t cnode[KMAX];
+    uint64_t S = 0;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        cnode[k] = k < J.K ? F.cls[(size_t)id * F.kmax + k] : 0u;
+        S += (uint64_t)cnode[k] * cnode[k];
+    }
+    const uint32_t N = nd.n;
+    const KeyedPerm P = make_perm(J.seed_lo, J.seed_hi, kMtry, (uint32_t)J.t, (uint32_t)tr.tau,
+                                  nd.heap, 0u, (uint64_t)J.p_w);
+    Cand best;
+    best.nl = 0;
+    best.q = -1;
+    best.b = 0x7FFFFFFF;
+    for (int q0 = 0; q0 < J.mtry; q0 += 64) {
+        const int nq = min(64, J.mtry - q0);
+        const int myf = lane < nq ? (int)perm_apply(P, (uint32_t)(q0 + lane)) : 0;
+        for (int qq = 0; qq < nq; ++qq) {
+            const int f = __shfl(myf, qq);
+            const uint8_t* col = J.colptr[f];
+            const int b = valid ? (int)col[row] : 0x7FFF;
+            uint64_t acc[NW];
+#pragma unroll
+            for (int i = 0; i < NW; ++i) acc[i] = 0;
+            for (int j = 0; j < len; ++j) {
+                const bool take = __shfl(b, j) <= b;
+#pragma unroll
+                for (int i = 0; i < NW; ++i) {
+                    const uint64_t o = __shfl(cv[i], j);
+                    acc[i] += take ? o : 0ull;
+                }
+            }
+            Cand c;
+            c.q = q0 + qq;
+            c.f = f;
+            c.b = b;
+            c.pad = 0;
+            uint32_t nl = 0;
+            uint64_t sl = 0, sr = 0;
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                const uint32_t l = (uint32_t)(acc[k >> 2] >> (16 * (k & 3))) & 0xFFFFu;
+                const uint32_t r = cnode[k] - l;
+                nl += l;
+                sl += (uint64_t)l * l;
+                sr += (uint64_t)r * r;
+            }
+            c.nl = nl;
+            c.nr = N - nl;
+            c.sl = sl;
+            c.sr = sr;
+            const bool ok = valid && b <= B - 2 && nl > 0 && nl < N;
+            if (!ok) {
+                c.nl = 0;
+                c.b = 0x7FFFFFFF;
+            }
+            const Cand fb =
+                F.split_rank ? wave_best_fp32(c, ok ? cand_q32(c) : -1.0f) : wave_best_exact(c);
+            if (fb.nl != 0 && (best.nl == 0 || cand_better(fb, best))) best = fb;
+        }
+    }
+    if (F.alg_bytes && lane == 0)
+        atomicAdd((unsigned long long*)&F.alg_bytes[1],
+                  (unsigned long long)len * (unsigned long long)(J.mtry + 6));
+    if (best.nl == 0 || !cand_positive(best, S, N)) return;  // stays the leaf it was created as
+    const uint8_t* col = J.colptr[best.f];
+    const bool left = valid && (int)col[row] <= best.b;
+    const uint64_t lm = __ballot(left), vm = __ballot(valid);
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t nl_rows = (uint32_t)__popcll(lm);
+    if (valid) {
+        const uint32_t pos = left ? (uint32_t)__popcll(lm & below)
+                                  : nl_rows + (uint32_t)__popcll(vm & ~lm & below);
+        rout[pos] = rec;
+    }
+    uint64_t lc[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        uint64_t v = left ? cv[i] : 0ull;
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
+        lc[i] = v;
+    }
+    if (lane == 0) {
+        uint32_t cl[16], cr[16];
+        for (int k = 0; k < 16; ++k) {
+            cl[k] = k < KMAX ? (uint32_t)(lc[k >> 2] >> (16 * (k & 3))) & 0xFFFFu : 0u;
+            cr[k] = (k < KMAX ? cnode[k] : 0u) - cl[k];
+        }
+        split_node(F, J, tr, id, nd, best, nl_rows, cl, cr, cand_gain_fix(best, S, N));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Best threshold of one feature from its LDS histogram h[B][KMAX]: each lane
+// owns ceil(B/64) consecutive bins; class prefix sums come from a wave scan.
+template <int KMAX>
+__device__ Cand feature_best(const uint32_t* h, int B, int q, int f, const uint32_t* cnode,
+                             uint32_t N, int split_rank) {
+    const int lane = threadIdx.x & 63;
+    const int bpl = (B + 63) >> 6;
+    const int b0 = lane * bpl;
+    uint32_t acc[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) acc[k] = 0;
+    for (int u = 0; u < bpl; ++u) {
+        const int b = b0 + u;
+        if (b < B) {
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) acc[k] += h[b * KMAX + k];
+        }
+    }
+    uint32_t excl[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        uint32_t v = acc[k];
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t t = __shfl_up(v, off);
+            if (lane >= off) v += t;
+        }
+        excl[k] = v - acc[k];
+    }
+    // candidates of this lane, in ascending threshold order
+    auto make = [&](int b, const uint32_t* cl) {
+        Cand c;
+        c.q = q;
+        c.f = f;
+        c.b = b;
+        c.pad = 0;
+        uint32_t nl = 0;
+        uint64_t sl = 0, sr = 0;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const uint32_t r = cnode[k] - cl[k];
+            nl += cl[k];
+            sl += (uint64_t)cl[k] * cl[k];
+            sr += (uint64_t)r * r;
+        }
+        c.nl = nl;
+        c.nr = N - nl;
+        c.sl = sl;
+        c.sr = sr;
+        return c;
+    };
+    Cand lb;
+    lb.nl = 0;
+    lb.b = 0x7FFFFFFF;
+    lb.q = q;
+    lb.f = f;
+    uint32_t cl[KMAX];
+    if (!split_rank) {
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) cl[k] = excl[k];
+        for (int u = 0; u < bpl; ++u) {
+            const int b = b0 + u;
+            if (b >= B - 1) break;
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) cl[k] += h[b * KMAX + k];
+            const Cand c = make(b, cl);
+            if (c.nl == 0 || c.nl == N) continue;
+            if (lb.nl == 0 || cand_better(c, lb)) lb = c;
+        }
+        return wave_best_exact(lb);
+    }
+    // FP32 ranking: pass 1 finds the wave's FP32 maximum, pass 2 re-ranks the
+    // candidates within the margin exactly.
+    float lq = -1.0f;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) cl[k] = excl[k];
+    for (int u = 0; u < bpl; ++u) {
+        const int b = b0 + u;
+        if (b >= B - 1) break;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) cl[k] += h[b * KMAX + k];
+        const Cand c = make(b, cl);
+        if (c.nl == 0 || c.nl == N) continue;
+        lq = fmaxf(lq, cand_q32(c));
+    }
+    const float qmax = wave_max_f(lq);
+    if (qmax < 0.0f) return lb;
+    const float floor32 = fp32_floor(qmax);
+    if (lq >= floor32) {
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) cl[k] = excl[k];
+        for (int u = 0; u < bpl; ++u) {
+            const int b = b0 + u;
+            if (b >= B - 1) break;
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) cl[k] += h[b * KMAX + k];
+            const Cand c = make(b, cl);
+            if (c.nl == 0 || c.nl == N) continue;
+            if (cand_q32(c) < floor32) continue;
+            if (lb.nl == 0 || cand_better(c, lb)) lb = c;
+        }
+    }
+    const unsigned long long fin = __ballot(lb.nl != 0);
+    if (__popcll(fin) == 1) return shfl_cand(lb, (int)__ffsll(fin) - 1);
+    return wave_best_exact(lb);
+}
+
+// Large nodes: one workgroup per (node, feature tile).
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_split_large(ForestDev F) {
+    extern __shared__ uint32_t hist[];  // [ft][B][KMAX]
+    __shared__ const uint8_t* s_col[16];
+    __shared__ int s_feat[16];
+    __shared__ Cand s_fbest[16];
+    __shared__ Cand s_best;
+    __shared__ int s_last, s_split;
+    __shared__ uint32_t s_cl[KMAX];
+    __shared__ uint32_t s_wcnt[4];
+    __shared__ uint32_t s_run;
+    const Item it = F.items_in[blockIdx.x];
+    const NodeDev nd = F.nodes[it.node];
+    const TreeDev tr = F.trees[nd.tree];
+    JobDev& J = F.jobs[tr.job];
+    const int B = J.B, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int q0 = (int)it.tile * F.ft;
+    const int nf = min(F.ft, J.mtry - q0);
+    if (tid < nf) {
+        const KeyedPerm P = make_perm(J.seed_lo, J.seed_hi, kMtry, (uint32_t)J.t,
+                                      (uint32_t)tr.tau, nd.heap, 0u, (uint64_t)J.p_w);
+        const int f = (int)perm_apply(P, (uint32_t)(q0 + tid));
+        s_feat[tid] = f;
+        s_col[tid] = J.colptr[f];
+    }
+    for (int i = tid; i < nf * B * KMAX; i += 256) hist[i] = 0;
+    if (tid < KMAX) s_cl[tid] = 0;
+    __syncthreads();
+    const uint64_t* recs = J.rec[F.parity] + (size_t)tr.tau * J.n + nd.seg;
+    for (uint32_t i = tid; i < nd.len; i += 256) {
+        const uint64_t r = recs[i];
+        const uint32_t row = rec_row(r), wt = rec_w(r), yv = rec_y(r);
+        for (int q = 0; q < nf; ++q) atomicAdd(&hist[(q * B + s_col[q][row]) * KMAX + yv], wt);
+    }
+    __syncthreads();
+    uint32_t cnode[KMAX];
+    uint64_t S = 0;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        cnode[k] = k < J.K ? F.cls[(size_t)it.node * F.kmax + k] : 0u;
+        S += (uint64_t)cnode[k] * cnode[k];
+    }
+    const uint32_t N = nd.n;
+    for (int q = wave; q < nf; q += 4) {
+        const Cand fb =
+            feature_best<KMAX>(hist + q * B * KMAX, B, q0 + q, s_feat[q], cnode, N, F.split_rank);
+        if (lane == 0) s_fbest[q] = fb;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        Cand tb = s_fbest[0];
+        for (int q = 1; q < nf; ++q)
+            if (s_fbest[q].nl != 0 && (tb.nl == 0 || cand_better(s_fbest[q], tb))) tb = s_fbest[q];
+        F.cand[(size_t)it.slot * F.max_tiles + it.tile] = tb;
+        if (F.alg_bytes)
+            atomicAdd((unsigned long long*)&F.alg_bytes[0],
+                      (unsigned long long)nd.len * (unsigned long long)(nf + (it.tile == 0 ? 6 : 0)));
+        __threadfence();
+        const uint32_t prev = atomicAdd(&F.done[it.slot], 1u);
+        s_last = prev == (uint32_t)J.ntiles - 1u;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    // ---- last tile of the node: choose the split over all tiles
+    if (tid == 0) {
+        __threadfence();
+        Cand best;
+        best.nl = 0;
+        for (int tl = 0; tl < J.ntiles; ++tl) {
+            const Cand c = F.cand[(size_t)it.slot * F.max_tiles + tl];
+            if (c.nl != 0 && (best.nl == 0 || cand_better(c, best))) best = c;
+        }
+        F.done[it.slot] = 0;
+        s_best = best;
+        s_split = best.nl != 0 && cand_positive(best, S, N);
+        s_run = 0;
+    }
+    __syncthreads();
+    if (!s_split) return;
+    const Cand best = s_best;
+    const uint8_t* col = J.colptr[best.f];
+    uint64_t* rout = J.rec[F.parity ^ 1] + (size_t)tr.tau * J.n + nd.seg;
+    // pass 1: distinct rows going left
+    uint32_t cnt = 0;
+    for (uint32_t i = tid; i < nd.len; i += 256) cnt += (int)col[rec_row(recs[i])] <= best.b;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) cnt += __shfl_xor(cnt, m);
+    if (lane == 0) s_wcnt[wave] = cnt;
+    __syncthreads();
+    const uint32_t nl_rows = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
+    __syncthreads();
+    // pass 2: stable scatter, left rows first
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (uint32_t base = 0; base < nd.len; base += 256) {
+        const uint32_t i = base + tid;
+        const bool valid = i < nd.len;
+        const uint64_t r = valid ? recs[i] : 0ull;
+        const bool left = valid && (int)col[rec_row(r)] <= best.b;
+        const uint64_t lm = __ballot(left), vm = __ballot(valid);
+        if (lane == 0) s_wcnt[wave] = (uint32_t)__popcll(lm);
+        __syncthreads();
+        uint32_t lpre = s_run;
+        for (int v = 0; v < wave; ++v) lpre += s_wcnt[v];
+        const uint32_t lrow = lpre + (uint32_t)__popcll(lm & below);
+        if (valid) {
+            if (left) {
+                rout[lrow] = r;
+                atomicAdd(&s_cl[rec_y(r)], rec_w(r));
+            } else {
+                // rows before i that go right = i - (left rows before i)
+                rout[nl_rows + (i - lrow)] = r;
+            }
+        }
+        (void)vm;
+        __syncthreads();
+        if (tid == 0) s_run += s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        uint32_t cl[16], cr[16];
+        for (int k = 0; k < 16; ++k) {
+            cl[k] = k < KMAX ? s_cl[k] : 0u;
+            cr[k] = (k < KMAX ? cnode[k] : 0u) - cl[k];
+        }
+        split_node(F, J, tr, it.node, nd, best, nl_rows, cl, cr, cand_gain_fix(best, S, N));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+void launch_boot_compact(const ForestDev& F, uint32_t n_trees, hipStream_t st) {
+    hipLaunchKernelGGL(k_boot_compact, dim3(n_trees), dim3(1024), 0, st, F);
+}
+
+void launch_split_small(const ForestDev& F, uint32_t n_small, hipStream_t st) {
+    if (!n_small) return;
+    const dim3 grid((n_small + 3) / 4);
+    switch (F.kmax) {
+        case 4: hipLaunchKernelGGL(k_split_small<4>, grid, dim3(256), 0, st, F, n_small); break;
+        case 8: hipLaunchKernelGGL(k_split_small<8>, grid, dim3(256), 0, st, F, n_small); break;
+        default: hipLaunchKernelGGL(k_split_small<16>, grid, dim3(256), 0, st, F, n_small); break;
+    }
+}
+
+void launch_split_large(const ForestDev& F, uint32_t n_items, int B, hipStream_t st) {
+    if (!n_items) return;
+    const size_t lds = (size_t)F.ft * B * F.kmax * sizeof(uint32_t);
+    const dim3 grid(n_items);
+    switch (F.kmax) {
+        case 4: hipLaunchKernelGGL(k_split_large<4>, grid, dim3(256), lds, st, F); break;
+        case 8: hipLaunchKernelGGL(k_split_large<8>, grid, dim3(256), lds, st, F); break;
+        default: hipLaunchKernelGGL(k_split_large<16>, grid, dim3(256), lds, st, F); break;
+    }
+}
+
+}  // namespace boruta

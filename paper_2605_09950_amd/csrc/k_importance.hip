@@ -1,0 +1,226 @@
+// k_importance.hip -- importance scores, hits and decisions (gfx950).
+//
+//   * TreeImp (Algorithm 2, Sec. 2.1): per tree, each widened column's summed
+//     fixed-point Gini decrease G (accumulated at split time) is normalised
+//     to floor(2^44 G / sum_f G) and the shares are summed over trees; the
+//     mean's 1/T cancels in the final renormalisation.
+//   * Permut (Kursa's accuracy drop, Sec. 2; Sec. 2.2): for every tree, OOB
+//     row j, column f on the row's path and replica r, the row is re-routed
+//     with f's bin taken from OOB row pi(j), pi the keyed permutation of the
+//     tree's OOB rows for (t, tree, f, r); the drop in correct predictions is
+//     summed per column.  Columns off the path cannot change the prediction,
+//     so only path columns are re-routed, from their first node on the path.
+//   * hits (strictly above the best shadow) and the binomial decision.
+#include "dev_common.hpp"
+
+namespace boruta {
+
+// Per tree: total fixed-point decrease over its columns.
+__global__ __launch_bounds__(256) void k_tree_totals(JobDev* jobs, const TreeDev* trees,
+                                                     uint64_t* tot) {
+    __shared__ unsigned long long s[4];
+    const TreeDev tr = trees[blockIdx.x];
+    const JobDev& J = jobs[tr.job];
+    if (J.mode != 0) return;  // Permut job of a mixed batch: no G
+    const uint64_t* G = J.G + (size_t)tr.tau * J.pw_cap;
+    unsigned long long v = 0;
+    for (int f = threadIdx.x; f < J.p_w; f += 256) v += G[f];
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) tot[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
+}
+
+// Per (column, job): I_f = sum over trees of floor(2^44 G[tree][f] / total).
+// G is cleared behind the read, ready for the next iteration.
+__global__ __launch_bounds__(256) void k_treeimp(JobDev* jobs, const int32_t* live,
+                                                 const int32_t* tree_base, const uint64_t* tot) {
+    JobDev& J = jobs[live[blockIdx.y]];
+    const int f = blockIdx.x * 256 + threadIdx.x;
+    if (J.mode != 0 || f >= J.p_w) return;
+    const int g0 = tree_base[blockIdx.y];
+    int64_t s = 0;
+    for (int tau = 0; tau < J.T; ++tau) {
+        uint64_t* gp = J.G + (size_t)tau * J.pw_cap + f;
+        const uint64_t g = *gp;
+        if (g == 0) continue;
+        *gp = 0;
+        s += (int64_t)udiv128((u128)g << 44, (u128)tot[g0 + tau]);
+    }
+    J.imp[f] = s;
+}
+
+// Permut: one thread per (tree, OOB row).
+__global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* trees,
+                                                const NodeDev* nodes, int max_depth) {
+    extern __shared__ uint32_t s_path[];  // [2][max_depth][256]: node, feature
+    const uint32_t g = blockIdx.y;
+    const TreeDev tr = trees[g];
+    JobDev& J = jobs[tr.job];
+    if (J.mode != 1) return;  // TreeImp job of a mixed batch
+    const int tid = threadIdx.x;
+    const uint32_t m = (uint32_t)J.tstat[tr.tau * 4 + 1];
+    const uint32_t j = blockIdx.x * 256u + tid;
+    if (blockIdx.x * 256u >= m) return;
+    const bool active = j < m;
+    const uint32_t* oob = J.oob + (size_t)tr.tau * J.n;
+    const uint32_t row = active ? oob[j] : 0u;
+    const uint32_t yv = J.y[row];
+    uint32_t* pn = s_path;
+    uint32_t* pf = s_path + max_depth * 256;
+    int len = 0;
+    uint32_t node = g;
+    bool base_ok = false;
+    if (active) {
+        NodeDev nd = nodes[node];
+        while (nd.feat >= 0) {
+            pn[len * 256 + tid] = node;
+            pf[len * 256 + tid] = (uint32_t)nd.feat;
+            ++len;
+            node = (int)J.colptr[nd.feat][row] <= (int)nd.thr ? nd.left : nd.left + 1;
+            nd = nodes[node];
+        }
+        base_ok = nd.leaf_class == yv;
+    }
+    const unsigned long long okm = __ballot(active && base_ok);
+    if ((tid & 63) == 0 && okm) atomicAdd(&J.tstat[tr.tau * 4 + 2], (int)__popcll(okm));
+    if (!active) return;
+    for (int pi = 0; pi < len; ++pi) {
+        const uint32_t f = pf[pi * 256 + tid];
+        bool dup = false;
+        for (int pj = 0; pj < pi; ++pj) dup |= pf[pj * 256 + tid] == f;
+        if (dup) continue;
+        const uint8_t* fcol = J.colptr[f];
+        const uint32_t start = pn[pi * 256 + tid];
+        int drop = 0;
+        for (int r = 0; r < J.R; ++r) {
+            const KeyedPerm P = make_perm(J.seed_lo, J.seed_hi, kOobPerm, (uint32_t)J.t,
+                                          (uint32_t)tr.tau, f, (uint32_t)r << 16, (uint64_t)m);
+            const int sb = fcol[oob[perm_apply(P, j)]];
+            uint32_t nd_i = start;
+            NodeDev nd = nodes[nd_i];
+            while (nd.feat >= 0) {
+                const int b = (uint32_t)nd.feat == f ? sb : (int)J.colptr[nd.feat][row];
+                nd_i = b <= (int)nd.thr ? nd.left : nd.left + 1;
+                nd = nodes[nd_i];
+            }
+            drop += (int)base_ok - (int)(nd.leaf_class == yv);
+        }
+        if (drop) atomicAdd((unsigned long long*)&J.imp[f], (unsigned long long)(int64_t)drop);
+    }
+}
+
+// Per job: hits, history row, shadow maximum, decisions, liveness.
+__global__ __launch_bounds__(256) void k_hits_decide(JobDev* jobs) {
+    __shared__ long long s_max[4], s_sum[4];
+    __shared__ int s_und[4];
+    JobDev& J = jobs[blockIdx.x];
+    if (!J.live) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int t = J.t, p_cur = J.p_cur, p_w = J.p_w;
+    long long mx = LLONG_MIN, sum = 0;
+    for (int c = tid; c < p_w; c += 256) {
+        const long long v = J.imp[c];
+        if (c >= p_cur) mx = v > mx ? v : mx;
+        sum += v;
+    }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        const long long o = __shfl_xor(mx, m);
+        mx = o > mx ? o : mx;
+        sum += __shfl_xor(sum, m);
+    }
+    if (lane == 0) {
+        s_max[wave] = mx;
+        s_sum[wave] = sum;
+    }
+    __syncthreads();
+    long long best = s_max[0], total = s_sum[0];
+    for (int v = 1; v < 4; ++v) {
+        best = s_max[v] > best ? s_max[v] : best;
+        total += s_sum[v];
+    }
+    double denom;
+    if (J.mode == 0) {
+        denom = (double)total;
+    } else {
+        long long oob = 0;
+        for (int tau = 0; tau < J.T; ++tau) oob += J.tstat[tau * 4 + 1];
+        denom = (double)((long long)J.R * oob);
+    }
+    double* hrow = J.hist + (size_t)(t - 1) * J.p;
+    for (int j = tid; j < J.p; j += 256)
+        if (J.state[j] < 0) hrow[j] = __longlong_as_double(0x7FF8000000000000ll);
+    for (int c = tid; c < p_cur; c += 256) {
+        const int j = J.act[c];
+        const long long v = J.imp[c];
+        hrow[j] = denom > 0.0 ? (double)v / denom : 0.0;
+        if (v > best) J.hits[j] += 1;
+    }
+    if (tid == 0) J.shadow_max[t - 1] = denom > 0.0 ? (double)best / denom : 0.0;
+    __syncthreads();
+    int und = 0;
+    const int hc = J.h_conf[t], hr = J.h_rej[t];
+    for (int j = tid; j < J.p; j += 256) {
+        int8_t s = J.state[j];
+        if (s == 0) {
+            const int h = J.hits[j];
+            if (h >= hc)
+                s = 1;
+            else if (h <= hr)
+                s = -1;
+            J.state[j] = s;
+        }
+        und += s == 0;
+    }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) und += __shfl_xor(und, m);
+    if (lane == 0) s_und[wave] = und;
+    __syncthreads();
+    if (tid == 0) {
+        const int u = s_und[0] + s_und[1] + s_und[2] + s_und[3];
+        J.n_undecided = u;
+        J.live = (u > 0 && t < J.max_iter) ? 1 : 0;
+    }
+}
+
+// Streaming copy used to calibrate hardware byte counters.
+__global__ void k_copy(uint4* dst, const uint4* src, size_t n16) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+        dst[i] = src[i];
+}
+
+void launch_tree_totals(JobDev* jobs, const TreeDev* trees, int n_trees, uint64_t* tot,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_tree_totals, dim3(n_trees), dim3(256), 0, st, jobs, trees, tot);
+}
+
+void launch_treeimp(JobDev* jobs, const int32_t* live, int n_live, const int32_t* tree_base,
+                    const uint64_t* tot, int max_pw, hipStream_t st) {
+    hipLaunchKernelGGL(k_treeimp, dim3((unsigned)((max_pw + 255) / 256), (unsigned)n_live),
+                       dim3(256), 0, st, jobs, live, tree_base, tot);
+}
+
+void launch_permut(JobDev* jobs, const TreeDev* trees, const NodeDev* nodes, int n_trees,
+                   int64_t max_n, int max_depth, hipStream_t st) {
+    const size_t lds = (size_t)2 * max_depth * 256 * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_permut, dim3((unsigned)((max_n + 255) / 256), (unsigned)n_trees),
+                       dim3(256), lds, st, jobs, trees, nodes, max_depth);
+}
+
+void launch_hits_decide(JobDev* jobs, int n_jobs, hipStream_t st) {
+    hipLaunchKernelGGL(k_hits_decide, dim3(n_jobs), dim3(256), 0, st, jobs);
+}
+
+void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    const size_t n16 = bytes / 16;
+    size_t blocks = (n16 + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st, (uint4*)dst,
+                       (const uint4*)src, n16);
+}
+
+}  // namespace boruta

@@ -1,0 +1,78 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point that
+include/boruta.h declares, validates arguments on the host, sizes workspaces,
+and fails loudly (no CPU fallback) when no GPU is present."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2605_09950_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "boruta.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(boruta_[a-z_]+)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_lists_the_binding_exports():
+    assert header_functions() == sorted(B.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    for name in header_functions():
+        assert hasattr(L, name), name
+        assert ctypes.cast(getattr(L, name), ctypes.c_void_p).value
+
+
+def test_default_options():
+    o = B.boruta_default_options()
+    assert (o.n_bins, o.n_perm, o.split_rank, o.form) == (256, 1, B.RANK_FP32, B.FORM_BATCHED)
+
+
+def _call(**kw):
+    args = dict(X=np.zeros((10, 3), np.float32), y=np.zeros(10, np.int32), n_classes=2,
+                n_trees=2, max_depth=2, max_iter=3)
+    args.update(kw)
+    return B.boruta_fit_ex(**args)
+
+
+@pytest.mark.parametrize("kw", [dict(n_classes=1), dict(n_classes=17), dict(n_trees=0),
+                                dict(max_depth=0), dict(max_depth=31), dict(max_iter=0),
+                                dict(max_iter=1001), dict(alpha=0.5), dict(alpha=0.0),
+                                dict(mtry=-1), dict(importance_mode=2), dict(n_bins=1),
+                                dict(n_bins=257), dict(n_perm=0), dict(split_rank=2),
+                                dict(form=3), dict(X=np.zeros((1, 3), np.float32),
+                                                   y=np.zeros(1, np.int32))])
+def test_invalid_arguments_rejected_on_host(kw):
+    with pytest.raises(B.BorutaError) as e:
+        _call(**kw)
+    assert e.value.code == B.BORUTA_E_INVALID_ARG
+    assert B.boruta_last_error()
+
+
+def test_workspace_size_is_host_only():
+    small = B.boruta_workspace_size([dict(n=500, p=20, n_classes=2, n_trees=50, max_depth=8)])
+    big = B.boruta_workspace_size([dict(n=10000, p=500, n_classes=3, n_trees=200,
+                                        max_depth=12, max_iter=100)])
+    assert 0 < small < big
+    two = B.boruta_workspace_size([dict(n=500, p=20, n_classes=2, n_trees=50, max_depth=8)] * 2)
+    assert two > small
+    with pytest.raises(B.BorutaError):
+        B.boruta_workspace_size([dict(n=1, p=20, n_classes=2, n_trees=50, max_depth=8)])
+
+
+def test_no_cpu_fallback_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(B.BorutaError) as e:
+        _call()
+    assert e.value.code == B.BORUTA_E_UNSUPPORTED

@@ -1,0 +1,147 @@
+"""HIP path vs CPU oracle, element by element, on seeded inputs small enough
+for the oracle to finish in seconds (several histogram tiles, ragged row
+counts, both node paths) and on the edge cases of the method.  Tree
+structure, OOB counts, integer importances, hits and decisions must be
+identical; reported importances are exactly equal."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2605_09950_amd import binding as B
+from paper_2605_09950_amd import synth
+from tests.parity_helpers import assert_same_run
+
+pytestmark = pytest.mark.gpu
+
+
+def both(X, y, K, T, D, **kw):
+    kw = dict(kw)
+    split_rank = kw.pop("split_rank", B.RANK_FP32)
+    form = kw.pop("form", B.FORM_BATCHED)
+    print(f"case n={X.shape[0]} p={X.shape[1]} K={K} T={T} D={D} {kw} rank={split_rank} "
+          f"form={form}", flush=True)
+    g = B.boruta_fit_ex(X, y, K, T, D, split_rank=split_rank, form=form, trace=True, **kw)
+    o = O.boruta_fit(X, y, K, T, D, trace=True, **kw)
+    return g, o
+
+
+def problem(seed, n, p, K, kind="normal"):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, p)).astype(np.float32)
+    if kind == "mixed":
+        X[:, ::3] = rng.integers(0, 4, size=X[:, ::3].shape)
+        X[:, 1] = 0.25
+    s = X[:, 0] + (X[:, min(1, p - 1)] > 0.3) - 0.5 * X[:, -1] + 0.5 * rng.standard_normal(n)
+    y = np.digitize(s, np.quantile(s, np.linspace(0, 1, K + 1)[1:-1])).astype(np.int32)
+    return X, y
+
+
+def test_planted_small_workload():
+    c = synth.config(0)
+    pr = c["params"]
+    g, o = both(c["X"], c["y"], 2, pr["n_trees"], pr["max_depth"], max_iter=pr["max_iter"],
+                seed=c["seed"], n_bins=pr["n_bins"])
+    assert_same_run(g, o)
+
+
+CASES = [
+    # (seed, n, p, K, T, D, extra kwargs)
+    (1, 300, 7, 2, 12, 6, dict(max_iter=8, n_bins=32)),
+    (2, 777, 13, 3, 9, 9, dict(max_iter=6, n_bins=256)),
+    (3, 2500, 40, 4, 6, 12, dict(max_iter=4)),                    # large nodes, 2 tiles
+    (4, 1200, 30, 5, 5, 8, dict(max_iter=3, mtry=20)),             # K=5 -> 8-class path
+    (5, 400, 1, 2, 7, 5, dict(max_iter=10, n_bins=16)),            # p=1 -> 8 shadows
+    (6, 400, 2, 3, 7, 5, dict(max_iter=10, n_bins=16)),
+    (7, 400, 3, 2, 7, 5, dict(max_iter=10, n_bins=16)),            # 3 -> 6 shadows
+    (8, 300, 9, 2, 8, 1, dict(max_iter=5)),                        # stumps
+    (9, 600, 12, 2, 8, 7, dict(max_iter=5, n_bins=2)),             # two bins
+    (10, 500, 10, 3, 8, 7, dict(max_iter=5, mtry=500)),            # mtry clamps to p_w
+    (11, 900, 15, 2, 10, 10, dict(max_iter=5, kind="mixed")),      # ties, constant column
+]
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("case", CASES, ids=[str(c[0]) for c in CASES])
+def test_parity_cases(case, mode):
+    seed, n, p, K, T, D, kw = case
+    kw = dict(kw)
+    X, y = problem(seed, n, p, K, kw.pop("kind", "normal"))
+    extra = dict(n_perm=2) if mode == 1 else {}
+    g, o = both(X, y, K, T, D, importance_mode=mode, seed=100 + seed, **extra, **kw)
+    assert_same_run(g, o)
+
+
+def test_many_classes_and_tiny_n():
+    X, y = problem(12, 3000, 20, 16)
+    g, o = both(X, y, 16, 4, 10, max_iter=3, seed=3)
+    assert_same_run(g, o)
+    rng = np.random.default_rng(0)
+    for n in (2, 3, 5):
+        X = rng.standard_normal((n, 4)).astype(np.float32)
+        y = (np.arange(n) % 2).astype(np.int32)
+        for mode in (0, 1):
+            g, o = both(X, y, 2, 5, 3, max_iter=4, seed=n, importance_mode=mode)
+            assert_same_run(g, o)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_exact_and_fp32_ranking_give_identical_runs(mode):
+    X, y = problem(21, 3000, 60, 3)
+    kw = dict(importance_mode=mode, max_iter=4, seed=5, trace=True)
+    a = B.boruta_fit_ex(X, y, 3, 10, 10, split_rank=B.RANK_EXACT, **kw)
+    b = B.boruta_fit_ex(X, y, 3, 10, 10, split_rank=B.RANK_FP32, **kw)
+    assert_same_run(a, b)
+
+
+def test_plain_and_batched_forms_identical():
+    X, y = problem(22, 1500, 25, 3)
+    kw = dict(max_iter=3, seed=6, trace=True)
+    a = B.boruta_fit_ex(X, y, 3, 6, 8, form=B.FORM_PLAIN, **kw)
+    b = B.boruta_fit_ex(X, y, 3, 6, 8, form=B.FORM_BATCHED, **kw)
+    assert_same_run(a, b)
+
+
+def test_batch_equals_single_jobs():
+    jobs = []
+    for j in range(5):
+        X, y = problem(30 + j, 200 + 300 * j, 15, 2 + j % 3)
+        jobs.append(dict(X=X, y=y, n_classes=2 + j % 3, n_trees=4 + j, max_depth=6 + j,
+                         importance_mode=j % 2, max_iter=3 + j, seed=40 + j))
+    batch = B.boruta_fit_batch(jobs, trace=True)
+    for j, jd in enumerate(jobs):
+        single = B.boruta_fit_ex(jd["X"], jd["y"], jd["n_classes"], jd["n_trees"],
+                                 jd["max_depth"], importance_mode=jd["importance_mode"],
+                                 max_iter=jd["max_iter"], seed=jd["seed"], trace=True)
+        r = dict(batch["results"][j])
+        r["traces"] = [t for t in batch["traces"] if t["job"] == j]
+        assert r["status"] == 0
+        assert_same_run(r, single)
+
+
+def test_device_entry_point_matches_host_entry_point():
+    import torch
+    X, y = problem(23, 1000, 12, 2)
+    ws = B.boruta_workspace_size([dict(n=1000, p=12, n_classes=2, n_trees=8, max_depth=8,
+                                       max_iter=5)])
+    dX = torch.from_numpy(X).cuda()
+    dy = torch.from_numpy(y).cuda()
+    w = torch.empty(ws, dtype=torch.uint8, device="cuda")
+    d = B.boruta_fit_device(dX, dy, 2, 8, 8, w, max_iter=5, seed=9, trace=True)
+    h = B.boruta_fit_ex(X, y, 2, 8, 8, max_iter=5, seed=9, trace=True)
+    assert_same_run(d, h)
+    with pytest.raises(B.BorutaError) as e:
+        B.boruta_fit_device(dX, dy, 2, 8, 8, w[: ws // 2], max_iter=5, seed=9)
+    assert e.value.code == B.BORUTA_E_OOM
+
+
+def test_nonfinite_and_bad_labels_detected_on_device():
+    X, y = problem(24, 100, 4, 2)
+    X[7, 2] = np.inf
+    with pytest.raises(B.BorutaError) as e:
+        B.boruta_fit_ex(X, y, 2, 3, 3)
+    assert e.value.code == B.BORUTA_E_NONFINITE
+    X, y = problem(24, 100, 4, 2)
+    y[3] = 2
+    with pytest.raises(B.BorutaError) as e:
+        B.boruta_fit_ex(X, y, 2, 3, 3)
+    assert e.value.code == B.BORUTA_E_INVALID_ARG
