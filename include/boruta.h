@@ -184,6 +184,34 @@ int boruta_fit_device(const float* dX, const int32_t* dy, int64_t n, int64_t p,
                       void* hip_stream, int8_t* decision_out, double* imp_history_out,
                       int32_t* hits_out, double* shadow_max_out, int32_t* n_iter_out);
 
+/* Incremental form of the same computation: create a session (upload,
+ * validation, binning, decision thresholds), then advance every live job
+ * one Boruta iteration per boruta_session_step, read results at any time,
+ * and continue a job from a checkpoint (t, state, hits) with
+ * boruta_session_resume -- Algorithm 1 keeps no other state between
+ * iterations, and every random draw is keyed by (seed, t, ...), so a resumed
+ * job reproduces an uninterrupted one exactly.
+ *   inputs_on_device: X/y of the jobs are device pointers (see
+ *   boruta_fit_device); workspace (nullable = allocated by the library, else
+ *   at least boruta_workspace_size bytes) and hip_stream as there.  The
+ *   options' trace/stats targets must outlive the session.  Returns the
+ *   first job's error if any job fails validation (no session then). */
+typedef struct boruta_session boruta_session;
+int boruta_session_create(const boruta_job* jobs, int32_t n_jobs, const boruta_options* opt,
+                          int32_t inputs_on_device, void* workspace, size_t ws_bytes,
+                          void* hip_stream, boruta_session** out);
+/* One iteration of every live job; *n_live_out (nullable) = jobs still live. */
+int boruta_session_step(boruta_session* s, int32_t* n_live_out);
+/* Current decision/history/hits/shadow maximum of one job (caller buffers as
+ * in boruta_result; n_iter = iterations done so far). */
+int boruta_session_result(boruta_session* s, int32_t job, boruta_result* out);
+/* Set job's state after iteration t (0 <= t < max_iter): state[p] in
+ * {-1,0,1}, hits[p] in [0, t].  The next step runs iteration t + 1;
+ * history rows before t are the caller's. */
+int boruta_session_resume(boruta_session* s, int32_t job, int32_t t, const int8_t* state,
+                          const int32_t* hits);
+void boruta_session_destroy(boruta_session* s);
+
 /* Streaming copy of `bytes` bytes between device buffers (calibration of
  * hardware byte counters); returns BORUTA_OK or an error code. */
 int boruta_probe_copy(void* dst, const void* src, size_t bytes, void* hip_stream);

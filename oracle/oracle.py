@@ -202,11 +202,14 @@ def boruta_step(X, y, n_classes, n_trees, max_depth, t, state, hits, mtry=0,
     row = np.full(p, np.nan)
     smax = np.zeros(1)
     sub = None if tree_subset is None else np.ascontiguousarray(tree_subset, dtype=np.int32)
+    n_sub = 0 if sub is None else len(sub)
+    if sub is not None and n_sub == 0:
+        sub = np.zeros(1, np.int32)  # non-null pointer, zero trees: widening only
     traces = []
     cb = _trace_collector(traces) if trace else TRACE_FN()
     rc = lib().oracle_boruta_step(_ptr(X), _ptr(y), n, p, n_classes, n_trees, max_depth, mtry,
                                   importance_mode, alpha, seed, n_bins, n_perm, t, _ptr(st),
-                                  _ptr(ht), _ptr(sub), 0 if sub is None else len(sub), n_threads,
+                                  _ptr(ht), _ptr(sub), n_sub, n_threads,
                                   int(permut_naive), _ptr(row), _ptr(smax), cb, None)
     if rc:
         raise ValueError(f"oracle_boruta_step failed: {rc}")

@@ -75,8 +75,9 @@ class Result(ctypes.Structure):
 
 
 EXPORTS = ["boruta_default_options", "boruta_fit", "boruta_fit_ex", "boruta_fit_batch",
-           "boruta_workspace_size", "boruta_fit_device", "boruta_probe_copy",
-           "boruta_last_error"]
+           "boruta_workspace_size", "boruta_fit_device", "boruta_session_create",
+           "boruta_session_step", "boruta_session_result", "boruta_session_resume",
+           "boruta_session_destroy", "boruta_probe_copy", "boruta_last_error"]
 
 _lib = None
 
@@ -85,6 +86,14 @@ def lib():
     """Load libboruta.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # One HIP runtime per process: PyTorch ships its own libamdhip64.so.7,
+        # and a second copy loaded next to it cannot initialise the device.
+        # Importing torch first lets libboruta bind to torch's runtime (same
+        # SONAME), so torch tensors/streams and the library share it.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2605_09950_amd.csrc.build`")
@@ -107,6 +116,18 @@ def lib():
         L.boruta_fit_device.argtypes = prob + [ctypes.POINTER(Options), P, ctypes.c_size_t, P,
                                                P, P, P, P, P]
         L.boruta_fit_device.restype = ctypes.c_int
+        L.boruta_session_create.argtypes = [ctypes.POINTER(Job), i32, ctypes.POINTER(Options),
+                                            i32, P, ctypes.c_size_t, P,
+                                            ctypes.POINTER(ctypes.c_void_p)]
+        L.boruta_session_create.restype = ctypes.c_int
+        L.boruta_session_step.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+        L.boruta_session_step.restype = ctypes.c_int
+        L.boruta_session_result.argtypes = [P, i32, ctypes.POINTER(Result)]
+        L.boruta_session_result.restype = ctypes.c_int
+        L.boruta_session_resume.argtypes = [P, i32, i32, P, P]
+        L.boruta_session_resume.restype = ctypes.c_int
+        L.boruta_session_destroy.argtypes = [P]
+        L.boruta_session_destroy.restype = None
         L.boruta_probe_copy.argtypes = [P, P, ctypes.c_size_t, P]
         L.boruta_probe_copy.restype = ctypes.c_int
         L.boruta_last_error.argtypes = []
@@ -308,3 +329,94 @@ def boruta_probe_copy(dst, src, nbytes, stream=None):
     import torch
     st = stream if stream is not None else torch.cuda.current_stream(dst.device)
     _check(lib().boruta_probe_copy(dst.data_ptr(), src.data_ptr(), nbytes, st.cuda_stream))
+
+
+class Session:
+    """boruta_session_* wrapper.  jobs as for boruta_fit_batch; with
+    inputs_on_device, X/y are torch CUDA tensors (float32 [n][p], int32 [n])."""
+
+    def __init__(self, jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED,
+                 trace=False, stats=False, inputs_on_device=False, workspace=None, stream=None):
+        self._arrays, cj = [], (Job * len(jobs))()
+        self._shapes = []
+        for i, jd in enumerate(jobs):
+            if inputs_on_device:
+                X, y = jd["X"], jd["y"]
+                xp, yp = X.data_ptr(), y.data_ptr()
+                n, p = X.shape
+            else:
+                X = np.ascontiguousarray(jd["X"], dtype=np.float32)
+                y = np.ascontiguousarray(jd["y"], dtype=np.int32)
+                xp, yp = X.ctypes.data, y.ctypes.data
+                n, p = X.shape
+            self._arrays.append((X, y))
+            j = Job()
+            j.X, j.y, j.n, j.p = xp, yp, n, p
+            j.n_classes, j.n_trees, j.max_depth = jd["n_classes"], jd["n_trees"], jd["max_depth"]
+            j.mtry, j.importance_mode = jd.get("mtry", 0), jd.get("importance_mode", TREEIMP)
+            j.max_iter, j.alpha, j.seed = jd.get("max_iter", 20), jd.get("alpha", 0.05), \
+                jd.get("seed", 0)
+            cj[i] = j
+            self._shapes.append((p, j.max_iter))
+        p0 = self._shapes[0][0]
+        self.opt, self.keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p0)
+        self._jobs = cj
+        self._ws = workspace
+        ws_ptr = workspace.data_ptr() if workspace is not None else None
+        ws_len = workspace.numel() if workspace is not None else 0
+        st = None
+        if stream is not None:
+            st = stream.cuda_stream
+        h = ctypes.c_void_p()
+        _check(lib().boruta_session_create(cj, len(jobs), ctypes.byref(self.opt),
+                                           int(inputs_on_device), ws_ptr, ws_len, st,
+                                           ctypes.byref(h)))
+        self.h = h
+
+    @property
+    def stats(self):
+        return self.keep.get("stats")
+
+    @property
+    def traces(self):
+        return self.keep["iters"]
+
+    def step(self):
+        n = ctypes.c_int32(0)
+        _check(lib().boruta_session_step(self.h, ctypes.byref(n)))
+        return n.value
+
+    def result(self, job=0):
+        p, max_iter = self._shapes[job]
+        o = {"decision": np.zeros(p, np.int8), "imp_history": np.full((max_iter, p), np.nan),
+             "hits": np.zeros(p, np.int32), "shadow_max": np.full(max_iter, np.nan)}
+        r = Result()
+        r.decision = o["decision"].ctypes.data
+        r.imp_history = o["imp_history"].ctypes.data
+        r.hits = o["hits"].ctypes.data
+        r.shadow_max = o["shadow_max"].ctypes.data
+        _check(lib().boruta_session_result(self.h, job, ctypes.byref(r)))
+        o["n_iter"] = r.n_iter
+        return o
+
+    def resume(self, job, t, state, hits):
+        st = np.ascontiguousarray(state, dtype=np.int8)
+        ht = np.ascontiguousarray(hits, dtype=np.int32)
+        _check(lib().boruta_session_resume(self.h, job, t, _ptr(st), _ptr(ht)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().boruta_session_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -5,6 +5,7 @@
 // counters the host needs to size the next launch.
 #include <algorithm>
 #include <climits>
+#include <memory>
 #include <cmath>
 #include <cstring>
 #include <stdexcept>
@@ -286,17 +287,25 @@ public:
         HIPC(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
     }
 
-    // Returns per-job status; throws on device errors.
+    // Whole run: setup, iterations until no job is live, results.
     void run(std::vector<Out>& outs, std::vector<int>& status);
+    // Upload/validate/bin every job; status[j] receives each job's code.
+    void setup(std::vector<int>& status);
+    // One iteration of every live job; returns the number still live.
+    int step();
+    void result(int j, Out& o);
+    // Continue job j from a checkpoint: the next iteration is t + 1.
+    void resume(int j, int t, const int8_t* state, const int32_t* hits);
+    void flush_stats();
+    const JobDev& job(int j) const { return hj[j]; }
 
 private:
-    void setup(std::vector<int>& status);
-    void iteration(const std::vector<int>& live, std::vector<Out>& outs);
+    void iteration(const std::vector<int>& live);
     void grow_level_plain(ForestDev F, uint32_t n_items, uint32_t n_small);
     void emit_trace(const std::vector<int>& live, const std::vector<int>& tree_base,
                     uint32_t n_nodes);
 
-    const std::vector<Spec>& S;
+    std::vector<Spec> S;
     Opts O;
     bool dev_in;
     char* base;
@@ -384,6 +393,7 @@ void Engine::setup(std::vector<int>& status) {
     for (int j = 0; j < nj; ++j)
         if (status[j] != BORUTA_OK) hj[j].live = 0;
     launch_fill_u32(at<uint32_t>(pl.done), pl.slot_cap, 0u, st);
+    launch_fill_u32(at<uint32_t>(pl.alg), 4, 0u, st);
     h2d(at<JobDev>(pl.jobs), hj.data(), hj.size() * sizeof(JobDev));
     HIPC(hipStreamSynchronize(st));
 }
@@ -410,7 +420,7 @@ void Engine::grow_level_plain(ForestDev F, uint32_t n_items, uint32_t n_small) {
     }
 }
 
-void Engine::iteration(const std::vector<int>& live, std::vector<Out>& outs) {
+void Engine::iteration(const std::vector<int>& live) {
     const int nj = (int)S.size();
     // trees of the live jobs, in job order
     std::vector<TreeDev> trees;
@@ -535,7 +545,6 @@ void Engine::iteration(const std::vector<int>& live, std::vector<Out>& outs) {
     launch_hits_decide(djobs, nj, st);
     d2h(hj.data(), djobs, hj.size() * sizeof(JobDev));
     if (O.trace) emit_trace(live, tree_base, n_nodes);
-    for (int j : live) outs[j].n_iter = hj[j].t;
     if (O.stats) O.stats->iterations += n_live;
 }
 
@@ -599,35 +608,65 @@ void Engine::emit_trace(const std::vector<int>& live, const std::vector<int>& tr
     }
 }
 
-void Engine::run(std::vector<Out>& outs, std::vector<int>& status) {
-    setup(status);
+int Engine::step() {
+    std::vector<int> live;
+    for (int j = 0; j < (int)S.size(); ++j)
+        if (hj[j].live) live.push_back(j);
+    if (live.empty()) return 0;
     EventTimer ti(O.stats != nullptr);
     ti.start(st);
-    for (;;) {
-        std::vector<int> live;
-        for (int j = 0; j < (int)S.size(); ++j)
-            if (hj[j].live) live.push_back(j);
-        if (live.empty()) break;
-        iteration(live, outs);
-    }
+    iteration(live);
     if (O.stats) O.stats->iter_ms += ti.stop(st);
-    if (O.stats) {
-        uint64_t ab[2];
-        d2h(ab, at<uint64_t>(pl.alg), 16);
-        O.stats->hist_large.alg_bytes += (double)ab[0];
-        O.stats->hist_small.alg_bytes += (double)ab[1];
+    int n = 0;
+    for (const JobDev& J : hj) n += J.live != 0;
+    return n;
+}
+
+void Engine::flush_stats() {
+    if (!O.stats) return;
+    uint64_t ab[2];
+    d2h(ab, at<uint64_t>(pl.alg), 16);
+    O.stats->hist_large.alg_bytes += (double)ab[0];
+    O.stats->hist_small.alg_bytes += (double)ab[1];
+    launch_fill_u32(at<uint32_t>(pl.alg), 4, 0u, st);
+}
+
+void Engine::result(int j, Out& o) {
+    const Spec& s = S[j];
+    const JobDev& J = hj[j];
+    HIPC(hipStreamSynchronize(st));
+    d2h(o.decision, J.state, (size_t)s.p);
+    if (J.t > 0 && o.hist) d2h(o.hist, J.hist, (size_t)J.t * s.p * 8);
+    if (o.hits) d2h(o.hits, J.hits, (size_t)s.p * 4);
+    if (o.smax && J.t > 0) d2h(o.smax, J.shadow_max, (size_t)J.t * 8);
+    o.n_iter = J.t;
+}
+
+void Engine::resume(int j, int t, const int8_t* state, const int32_t* hits) {
+    const Spec& s = S[j];
+    if (t < 0 || t >= s.max_iter) throw Error(BORUTA_E_INVALID_ARG, "resume: t outside [0, max_iter)");
+    for (int64_t i = 0; i < s.p; ++i) {
+        if (state[i] < -1 || state[i] > 1) throw Error(BORUTA_E_INVALID_ARG, "resume: bad state");
+        if (hits[i] < 0 || hits[i] > t) throw Error(BORUTA_E_INVALID_ARG, "resume: bad hits");
     }
-    for (int j = 0; j < (int)S.size(); ++j) {
-        if (status[j] != BORUTA_OK) continue;
-        const Spec& s = S[j];
-        const JobDev& J = hj[j];
-        Out& o = outs[j];
-        d2h(o.decision, J.state, (size_t)s.p);
-        if (J.t > 0) d2h(o.hist, J.hist, (size_t)J.t * s.p * 8);
-        if (o.hits) d2h(o.hits, J.hits, (size_t)s.p * 4);
-        if (o.smax && J.t > 0) d2h(o.smax, J.shadow_max, (size_t)J.t * 8);
-        o.n_iter = J.t;
+    JobDev& J = hj[j];
+    h2d(J.state, state, (size_t)s.p);
+    h2d(J.hits, hits, (size_t)s.p * 4);
+    bool und = false;
+    for (int64_t i = 0; i < s.p; ++i) und |= state[i] == 0;
+    J.t = t;
+    J.live = und ? 1 : 0;
+    h2d(at<JobDev>(pl.jobs) + j, &J, sizeof(JobDev));
+    HIPC(hipStreamSynchronize(st));
+}
+
+void Engine::run(std::vector<Out>& outs, std::vector<int>& status) {
+    setup(status);
+    while (step() > 0) {
     }
+    flush_stats();
+    for (int j = 0; j < (int)S.size(); ++j)
+        if (status[j] == BORUTA_OK) result(j, outs[j]);
 }
 
 struct DeviceRegion {
@@ -653,47 +692,60 @@ void require_device() {
                                               ", this library is built for gfx950");
 }
 
+// Device region, stream and engine of one set of jobs (a boruta_fit call or
+// a session).
+struct Context {
+    std::vector<Spec> specs;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    DeviceRegion reg;
+    std::unique_ptr<Engine> eng;
+    std::vector<int> status;
+    ~Context() {
+        eng.reset();
+        if (own_stream && st) (void)hipStreamDestroy(st);
+    }
+};
+
+std::unique_ptr<Context> prepare(const std::vector<Spec>& specs, const boruta_options* opt,
+                                 bool dev_inputs, void* ws, size_t ws_bytes,
+                                 hipStream_t user_stream) {
+    const Opts o = read_opts(opt);
+    for (const Spec& s : specs) check_spec(s);
+    require_device();
+    std::unique_ptr<Context> c(new Context);
+    c->specs = specs;
+    c->st = user_stream;
+    if (!ws && !c->st) {
+        HIPC(hipStreamCreate(&c->st));
+        c->own_stream = true;
+    }
+    const size_t need = make_plan(specs, o, dev_inputs).total;
+    char* base = nullptr;
+    if (ws) {
+        if (ws_bytes < need) throw Error(BORUTA_E_OOM, "workspace smaller than boruta_workspace_size");
+        base = (char*)ws;
+    } else {
+        if (hipMalloc(&c->reg.p, need) != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(BORUTA_E_OOM, "hipMalloc of " + std::to_string(need) + " bytes failed");
+        }
+        base = c->reg.p;
+    }
+    base = (char*)(((uintptr_t)base + 255) & ~uintptr_t(255));
+    c->eng.reset(new Engine(c->specs, o, dev_inputs, base, c->st));
+    c->status.assign(specs.size(), BORUTA_OK);
+    return c;
+}
+
 int run_jobs(const std::vector<Spec>& specs, const boruta_options* opt, std::vector<Out>& outs,
              std::vector<int>& status, bool dev_inputs, void* ws, size_t ws_bytes,
              hipStream_t user_stream) {
     g_err.clear();
     try {
-        const Opts o = read_opts(opt);
-        for (const Spec& s : specs) check_spec(s);
-        require_device();
-        hipStream_t st = user_stream;
-        bool own_stream = false;
-        if (!ws) {
-            if (!st) {
-                HIPC(hipStreamCreate(&st));
-                own_stream = true;
-            }
-        }
-        struct StreamGuard {
-            hipStream_t s;
-            bool own;
-            ~StreamGuard() {
-                if (own) (void)hipStreamDestroy(s);
-            }
-        } sg{st, own_stream};
-        const size_t need = make_plan(specs, o, dev_inputs).total;
-        DeviceRegion reg;
-        char* base = nullptr;
-        if (ws) {
-            if (ws_bytes < need)
-                throw Error(BORUTA_E_OOM, "workspace smaller than boruta_workspace_size");
-            base = (char*)ws;
-        } else {
-            if (hipMalloc(&reg.p, need) != hipSuccess) {
-                (void)hipGetLastError();
-                throw Error(BORUTA_E_OOM, "hipMalloc of " + std::to_string(need) + " bytes failed");
-            }
-            base = reg.p;
-        }
-        base = (char*)(((uintptr_t)base + 255) & ~uintptr_t(255));
-        Engine eng(specs, o, dev_inputs, base, st);
-        eng.run(outs, status);
-        HIPC(hipStreamSynchronize(st));
+        std::unique_ptr<Context> c = prepare(specs, opt, dev_inputs, ws, ws_bytes, user_stream);
+        c->eng->run(outs, status);
+        HIPC(hipStreamSynchronize(c->st));
         for (int s : status)
             if (s != BORUTA_OK) {
                 g_err = "a job failed validation";
@@ -708,7 +760,6 @@ int run_jobs(const std::vector<Spec>& specs, const boruta_options* opt, std::vec
         return BORUTA_E_DEVICE;
     }
 }
-
 
 Spec spec_from(const float* X, const int32_t* y, int64_t n, int64_t p, int32_t K, int32_t T,
                int32_t D, int32_t mtry, int32_t mode, int32_t max_iter, double alpha,
@@ -869,6 +920,110 @@ int boruta_probe_copy(void* dst, const void* src, size_t bytes, void* hip_stream
     }
     return BORUTA_OK;
 }
+
+}  // extern "C"
+
+struct boruta_session {
+    std::unique_ptr<boruta::Context> ctx;
+};
+
+extern "C" {
+
+int boruta_session_create(const boruta_job* jobs, int32_t n_jobs, const boruta_options* opt,
+                          int32_t inputs_on_device, void* workspace, size_t ws_bytes,
+                          void* hip_stream, boruta_session** out) {
+    g_err.clear();
+    if (!jobs || n_jobs < 1 || !out) {
+        g_err = "jobs and out must be non-null, n_jobs >= 1";
+        return BORUTA_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    try {
+        std::unique_ptr<boruta_session> s(new boruta_session);
+        s->ctx = prepare(specs_of(jobs, n_jobs), opt, inputs_on_device != 0, workspace, ws_bytes,
+                         (hipStream_t)hip_stream);
+        s->ctx->eng->setup(s->ctx->status);
+        for (int32_t j = 0; j < n_jobs; ++j)
+            if (s->ctx->status[j] != BORUTA_OK) {
+                g_err = "job " + std::to_string(j) + " failed validation";
+                return s->ctx->status[j];
+            }
+        *out = s.release();
+        return BORUTA_OK;
+    } catch (const Error& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return BORUTA_E_DEVICE;
+    }
+}
+
+int boruta_session_step(boruta_session* s, int32_t* n_live_out) {
+    g_err.clear();
+    if (!s) {
+        g_err = "null session";
+        return BORUTA_E_INVALID_ARG;
+    }
+    try {
+        const int n = s->ctx->eng->step();
+        s->ctx->eng->flush_stats();
+        if (n_live_out) *n_live_out = n;
+        return BORUTA_OK;
+    } catch (const Error& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return BORUTA_E_DEVICE;
+    }
+}
+
+int boruta_session_result(boruta_session* s, int32_t job, boruta_result* out) {
+    g_err.clear();
+    if (!s || !out || job < 0 || job >= (int32_t)s->ctx->specs.size() || !out->decision) {
+        g_err = "bad session, job index or result buffers";
+        return BORUTA_E_INVALID_ARG;
+    }
+    try {
+        Out o;
+        o.decision = out->decision;
+        o.hist = out->imp_history;
+        o.hits = out->hits;
+        o.smax = out->shadow_max;
+        s->ctx->eng->result(job, o);
+        out->n_iter = o.n_iter;
+        out->status = BORUTA_OK;
+        return BORUTA_OK;
+    } catch (const Error& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return BORUTA_E_DEVICE;
+    }
+}
+
+int boruta_session_resume(boruta_session* s, int32_t job, int32_t t, const int8_t* state,
+                          const int32_t* hits) {
+    g_err.clear();
+    if (!s || !state || !hits || job < 0 || job >= (int32_t)s->ctx->specs.size()) {
+        g_err = "bad session, job index or checkpoint buffers";
+        return BORUTA_E_INVALID_ARG;
+    }
+    try {
+        s->ctx->eng->resume(job, t, state, hits);
+        return BORUTA_OK;
+    } catch (const Error& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return BORUTA_E_DEVICE;
+    }
+}
+
+void boruta_session_destroy(boruta_session* s) { delete s; }
 
 const char* boruta_last_error(void) { return g_err.c_str(); }
 

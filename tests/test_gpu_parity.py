@@ -145,3 +145,31 @@ def test_nonfinite_and_bad_labels_detected_on_device():
     with pytest.raises(B.BorutaError) as e:
         B.boruta_fit_ex(X, y, 2, 3, 3)
     assert e.value.code == B.BORUTA_E_INVALID_ARG
+
+
+def test_session_steps_and_resume_reproduce_a_run():
+    X, y = problem(25, 800, 14, 3)
+    kw = dict(n_classes=3, n_trees=6, max_depth=7, max_iter=12, seed=11)
+    full = B.boruta_fit_ex(X, y, 3, 6, 7, max_iter=12, seed=11)
+    with B.Session([dict(X=X, y=y, **kw)]) as s:
+        for _ in range(5):
+            s.step()
+        mid = s.result(0)
+        while s.step():
+            pass
+        end = s.result(0)
+    assert mid["n_iter"] == 5
+    for key in ("decision", "hits", "n_iter"):
+        assert np.array_equal(np.asarray(end[key]), np.asarray(full[key]))
+    k = full["n_iter"]
+    np.testing.assert_array_equal(end["imp_history"][:k], full["imp_history"][:k])
+    # a fresh session resumed from the iteration-5 checkpoint finishes identically
+    with B.Session([dict(X=X, y=y, **kw)]) as s:
+        s.resume(0, 5, mid["decision"], mid["hits"])
+        while s.step():
+            pass
+        res = s.result(0)
+    assert np.array_equal(res["decision"], full["decision"])
+    assert np.array_equal(res["hits"], full["hits"])
+    assert res["n_iter"] == full["n_iter"]
+    np.testing.assert_array_equal(res["imp_history"][5:k], full["imp_history"][5:k])
