@@ -73,7 +73,7 @@ def run_gpu(c, pr, mode, steps, warmup, form, rank, stats):
         sess.step()
     torch.cuda.synchronize()
     if sess.stats is not None:  # count only the timed iterations
-        for f in ("hist_large", "hist_small", "permut"):
+        for f in ("hist_large", "hist_small", "finalize", "permut"):
             k = getattr(sess.stats, f)
             k.launches, k.ms, k.alg_bytes = 0, 0.0, 0.0
         sess.stats.iter_ms, sess.stats.iterations, sess.stats.nodes = 0.0, 0, 0
@@ -108,7 +108,7 @@ def roofline(stats):
             "launches": int(k.launches)}, {
         f: {"launches": int(getattr(stats, f).launches), "ms": round(getattr(stats, f).ms, 3),
             "alg_GB": round(getattr(stats, f).alg_bytes / 1e9, 4)}
-        for f in ("hist_large", "hist_small", "permut")}
+        for f in ("hist_large", "hist_small", "finalize", "permut")}
 
 
 def cpu_baseline(c, pr, mode):

@@ -88,6 +88,7 @@ typedef struct {
 typedef struct {
     boruta_kernel_stat hist_large; /* node histogram + split scan, > 64 rows      */
     boruta_kernel_stat hist_small; /* wave-per-node split search, <= 64 rows      */
+    boruta_kernel_stat finalize;   /* split choice + row partition, > 64 rows     */
     boruta_kernel_stat permut;     /* OOB traversal for permutation importance    */
     double iter_ms;                /* device time of all iterations               */
     int64_t iterations;            /* job-iterations run                          */

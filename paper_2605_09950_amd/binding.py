@@ -47,7 +47,8 @@ class KernelStat(ctypes.Structure):
 
 
 class Stats(ctypes.Structure):
-    _fields_ = [("hist_large", KernelStat), ("hist_small", KernelStat), ("permut", KernelStat),
+    _fields_ = [("hist_large", KernelStat), ("hist_small", KernelStat), ("finalize", KernelStat),
+                ("permut", KernelStat),
                 ("iter_ms", ctypes.c_double), ("iterations", ctypes.c_int64),
                 ("nodes", ctypes.c_int64)]
 

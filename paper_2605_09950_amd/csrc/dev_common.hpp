@@ -112,6 +112,14 @@ __device__ __forceinline__ uint32_t perm_apply_tab(const KeyedPerm& P, const uin
     return x;
 }
 
+// Load through the global address space (the pointers here are generic; the
+// cast lets the compiler issue global loads that overlap instead of flat
+// loads that also wait on LDS traffic).
+template <class T>
+__device__ __forceinline__ T ldg(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+
 // ---------------------------------------------------------------------------
 // Exact integer helpers.
 __device__ __forceinline__ int clz128(u128 v) {
@@ -119,19 +127,42 @@ __device__ __forceinline__ int clz128(u128 v) {
     return hi ? __clzll(hi) : 64 + (lo ? __clzll(lo) : 64);
 }
 
-// floor(num / den) for a quotient known to fit 64 bits (shift-subtract).
+__device__ __forceinline__ double u128_to_double(u128 v) {
+    return (double)(uint64_t)(v >> 64) * 18446744073709551616.0 + (double)(uint64_t)v;
+}
+
+// floor(num / den), exact, for quotients below 2^62 (larger ones saturate).
+// A double-precision estimate (relative error ~2^-51: a few units for the
+// quotients used here) is corrected with 128-bit remainders; if it is off by
+// more than 64 units, shift-subtract long division is used instead, so the
+// loop count is bounded for every input.
 __device__ __forceinline__ uint64_t udiv128(u128 num, u128 den) {
     if (den == 0 || num < den) return 0;
+    if ((num >> 62) >= den) return (uint64_t)1 << 62;  // quotient >= 2^62: saturate
+    const double qd = u128_to_double(num) / u128_to_double(den);
+    uint64_t q = (uint64_t)(qd < 4.0e18 ? qd : 4.0e18);
+    u128 prod = (u128)q * den;  // q < 2^62 and den <= num < 2^62 den: no overflow
+    for (int step = 0; step < 64; ++step) {
+        if (prod > num) {
+            --q;
+            prod -= den;
+        } else if (num - prod >= den) {
+            ++q;
+            prod += den;
+        } else {
+            return q;
+        }
+    }
     const int shift = clz128(den) - clz128(num);
-    den <<= shift;
-    uint64_t q = 0;
+    u128 d = den << shift, r = num;
+    q = 0;
     for (int i = 0; i <= shift; ++i) {
         q <<= 1;
-        if (num >= den) {
-            num -= den;
+        if (r >= d) {
+            r -= d;
             q |= 1;
         }
-        den >>= 1;
+        d >>= 1;
     }
     return q;
 }
@@ -251,8 +282,9 @@ struct ForestDev {
     NodeDev* nodes;
     uint32_t* cls;        // [node][kmax] weighted class counts
     uint64_t* ngain;      // [node] fixed-point Gini decrease of a split node
-    Cand* cand;           // [slot][max_tiles]
-    uint32_t* done;       // [slot] tiles finished
+    Cand* cand;           // [slot][max_tiles] best candidate of each feature tile
+    const uint32_t* slot_node_in;  // [slot] node of each large-node slot of this level
+    uint32_t* slot_node_out;       // [slot] the same for the next level
     const Item* items_in;
     const uint32_t* small_in;
     Item* items_out;

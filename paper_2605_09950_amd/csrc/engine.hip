@@ -30,7 +30,8 @@ void launch_fill_u32(uint32_t*, size_t, uint32_t, hipStream_t);
 // k_forest.hip
 void launch_boot_compact(const ForestDev&, uint32_t, hipStream_t);
 void launch_split_small(const ForestDev&, uint32_t, hipStream_t);
-void launch_split_large(const ForestDev&, uint32_t, int, hipStream_t);
+void launch_hist_tile(const ForestDev&, uint32_t, int, hipStream_t);
+void launch_split_finalize(const ForestDev&, uint32_t, uint32_t, hipStream_t);
 // k_importance.hip
 void launch_tree_totals(JobDev*, const TreeDev*, int, uint64_t*, hipStream_t);
 void launch_treeimp(JobDev*, const int32_t*, int, const int32_t*, const uint64_t*, int,
@@ -138,7 +139,7 @@ struct JobPlan {
 struct Plan {
     std::vector<JobPlan> jp;
     size_t keys, jobs, trees, live, tree_base, flags, nodes, cls, ngain, items0, items1, small0,
-        small1, cand, done, ctr, alg, tot;
+        small1, cand, slot0, slot1, ctr, alg, tot;
     uint32_t node_cap = 0, item_cap = 0, slot_cap = 0, small_cap = 0;
     int kmax = 4, ft = 8, max_tiles = 1, max_sha = 1, max_pw = 1, max_D = 1, T_total = 0;
     int64_t max_n = 0;
@@ -155,7 +156,7 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
         keys_words = std::max<int64_t>(keys_words, s.p * pow2_at_least(s.n));
     }
     pl.kmax = maxK <= 4 ? 4 : (maxK <= 8 ? 8 : 16);
-    pl.ft = (int)std::max<int64_t>(1, std::min<int64_t>(16, 8192 / ((int64_t)o.B * pl.kmax)));
+    pl.ft = 32 / pl.kmax;  // feature columns per histogram tile (32 KB of LDS at 256 bins)
     pl.keys = r.take((size_t)keys_words * 4);
     uint64_t node_cap = 0, item_cap = 0, slot_cap = 0, small_cap = 0;
     for (const Spec& s : specs) {
@@ -222,7 +223,8 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     pl.small0 = r.take((size_t)pl.small_cap * 4);
     pl.small1 = r.take((size_t)pl.small_cap * 4);
     pl.cand = r.take((size_t)pl.slot_cap * pl.max_tiles * sizeof(Cand));
-    pl.done = r.take((size_t)pl.slot_cap * 4);
+    pl.slot0 = r.take((size_t)pl.slot_cap * 4);
+    pl.slot1 = r.take((size_t)pl.slot_cap * 4);
     pl.ctr = r.take(sizeof(LevelCtr));
     pl.alg = r.take(16);
     pl.tot = r.take((size_t)pl.T_total * 8);
@@ -392,15 +394,15 @@ void Engine::setup(std::vector<int>& status) {
     }
     for (int j = 0; j < nj; ++j)
         if (status[j] != BORUTA_OK) hj[j].live = 0;
-    launch_fill_u32(at<uint32_t>(pl.done), pl.slot_cap, 0u, st);
     launch_fill_u32(at<uint32_t>(pl.alg), 4, 0u, st);
     h2d(at<JobDev>(pl.jobs), hj.data(), hj.size() * sizeof(JobDev));
     HIPC(hipStreamSynchronize(st));
 }
 
 void Engine::grow_level_plain(ForestDev F, uint32_t n_items, uint32_t n_small) {
-    // One launch per node: the node lists are read back and each node's
-    // split search is its own launch.
+    // One launch (or, for a large node, one histogram launch over its tiles
+    // and one finalize launch) per node: the node lists are read back and
+    // each node is its own launch.
     std::vector<uint32_t> small(n_small);
     std::vector<Item> items(n_items);
     if (n_small) d2h(small.data(), F.small_in, n_small * 4);
@@ -415,7 +417,8 @@ void Engine::grow_level_plain(ForestDev F, uint32_t n_items, uint32_t n_small) {
         uint32_t b = a + 1;
         while (b < n_items && items[b].node == items[a].node) ++b;
         F.items_in = item_base + a;
-        launch_split_large(F, b - a, O.B, st);
+        launch_hist_tile(F, b - a, O.B, st);
+        launch_split_finalize(F, items[a].slot, 1, st);
         a = b;
     }
 }
@@ -460,7 +463,7 @@ void Engine::iteration(const std::vector<int>& live) {
     F.cls = at<uint32_t>(pl.cls);
     F.ngain = at<uint64_t>(pl.ngain);
     F.cand = at<Cand>(pl.cand);
-    F.done = at<uint32_t>(pl.done);
+    uint32_t* slots[2] = {at<uint32_t>(pl.slot0), at<uint32_t>(pl.slot1)};
     Item* items[2] = {at<Item>(pl.items0), at<Item>(pl.items1)};
     uint32_t* small[2] = {at<uint32_t>(pl.small0), at<uint32_t>(pl.small1)};
     F.ctr = at<LevelCtr>(pl.ctr);
@@ -476,8 +479,10 @@ void Engine::iteration(const std::vector<int>& live) {
     F.pad = 0;
     F.items_in = items[1];
     F.small_in = small[1];
+    F.slot_node_in = slots[1];
     F.items_out = items[0];
     F.small_out = small[0];
+    F.slot_node_out = slots[0];
     F.next_base = (uint32_t)n_trees;
     F.parity = 0;
     if ((uint32_t)n_trees > pl.node_cap) throw Error(BORUTA_E_DEVICE, "node pool too small");
@@ -486,14 +491,18 @@ void Engine::iteration(const std::vector<int>& live) {
     LevelCtr c;
     d2h(&c, F.ctr, sizeof(c));
     uint32_t n_nodes = (uint32_t)n_trees;
-    uint32_t work_items = c.n_items, work_small = c.n_small;
+    uint32_t work_items = c.n_items, work_small = c.n_small, work_slots = c.n_slots;
     if (c.overflow) throw Error(BORUTA_E_DEVICE, "internal capacity exceeded (roots)");
-    EventTimer tl(O.stats != nullptr), ts(O.stats != nullptr);
+    EventTimer tl(O.stats != nullptr), ts(O.stats != nullptr), tf(O.stats != nullptr);
     for (int d = 0; work_items || work_small; ++d) {
+        // lists, slots and row records of level d are read from parity d & 1
+        // and the children of level d go to the other parity
         F.items_in = items[d & 1];
         F.small_in = small[d & 1];
+        F.slot_node_in = slots[d & 1];
         F.items_out = items[(d + 1) & 1];
         F.small_out = small[(d + 1) & 1];
+        F.slot_node_out = slots[(d + 1) & 1];
         F.next_base = n_nodes;
         F.parity = d & 1;
         launch_fill_u32((uint32_t*)F.ctr, sizeof(LevelCtr) / 4, 0u, st);
@@ -510,10 +519,16 @@ void Engine::iteration(const std::vector<int>& live) {
             }
             if (work_items) {
                 tl.start(st);
-                launch_split_large(F, work_items, O.B, st);
+                launch_hist_tile(F, work_items, O.B, st);
                 if (O.stats) {
                     O.stats->hist_large.ms += tl.stop(st);
                     O.stats->hist_large.launches += 1;
+                }
+                tf.start(st);
+                launch_split_finalize(F, 0, work_slots, st);
+                if (O.stats) {
+                    O.stats->finalize.ms += tf.stop(st);
+                    O.stats->finalize.launches += 1;
                 }
             }
         }
@@ -522,6 +537,7 @@ void Engine::iteration(const std::vector<int>& live) {
         n_nodes += c.n_nodes;
         work_items = c.n_items;
         work_small = c.n_small;
+        work_slots = c.n_slots;
     }
     if (O.stats) O.stats->nodes += n_nodes;
 

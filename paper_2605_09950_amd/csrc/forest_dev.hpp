@@ -132,6 +132,7 @@ __device__ inline void init_node(const ForestDev& F, const JobDev& J, uint32_t i
         atomicOr(&F.ctr->overflow, 2u);
         return;
     }
+    F.slot_node_out[slot] = idx;
     for (uint32_t tl = 0; tl < ntiles; ++tl) F.items_out[it + tl] = Item{idx, slot, tl, 0};
 }
 

@@ -6,11 +6,13 @@
 //   * k_split_small   one wavefront per node with <= 64 distinct rows: the
 //                     rows sit in lanes and every threshold's left class
 //                     counts come from an in-register all-pairs sum;
-//   * k_split_large   one workgroup per (node, tile of drawn features):
+//   * k_hist_tile     one workgroup per (node, tile of drawn features):
 //                     LDS class-count histogram [feature][bin][class] built
-//                     with LDS atomics, then a wave prefix scan over the bins
-//                     per feature.  The last tile of a node to finish picks the
-//                     node's split and stably partitions its rows.
+//                     with LDS atomics from batched global gathers, then a
+//                     wave prefix scan over the bins per feature; writes the
+//                     tile's best candidate;
+//   * k_split_finalize one workgroup per large node: best over the node's
+//                     tiles, then a stable partition of its rows.
 // The split rule (reading of the Gini forest of Sec. 2.1): maximise
 // Q = S_L/N_L + S_R/N_R over drawn features and thresholds "bin <= b",
 // exact rational comparison, ties to the earlier draw then the smaller b;
@@ -126,59 +128,71 @@ __global__ __launch_bounds__(256) void k_split_small(ForestDev F, uint32_t n_sma
     best.nl = 0;
     best.q = -1;
     best.b = 0x7FFFFFFF;
+    constexpr int kPre = 8;  // feature bins gathered ahead, to keep loads in flight
     for (int q0 = 0; q0 < J.mtry; q0 += 64) {
         const int nq = min(64, J.mtry - q0);
         const int myf = lane < nq ? (int)perm_apply(P, (uint32_t)(q0 + lane)) : 0;
-        for (int qq = 0; qq < nq; ++qq) {
-            const int f = __shfl(myf, qq);
-            const uint8_t* col = J.colptr[f];
-            const int b = valid ? (int)col[row] : 0x7FFF;
-            uint64_t acc[NW];
+        const uint8_t* mycol = lane < nq ? ldg(J.colptr + myf) : nullptr;
+        for (int qc = 0; qc < nq; qc += kPre) {
+            int bq[kPre];
 #pragma unroll
-            for (int i = 0; i < NW; ++i) acc[i] = 0;
-            for (int j = 0; j < len; ++j) {
-                const bool take = __shfl(b, j) <= b;
+            for (int u = 0; u < kPre; ++u) {
+                const int src = min(qc + u, nq - 1);
+                const uint8_t* col = (const uint8_t*)__shfl((unsigned long long)mycol, src);
+                bq[u] = (valid && qc + u < nq) ? (int)ldg(col + row) : 0x7FFF;
+            }
 #pragma unroll
-                for (int i = 0; i < NW; ++i) {
-                    const uint64_t o = __shfl(cv[i], j);
-                    acc[i] += take ? o : 0ull;
+            for (int u = 0; u < kPre; ++u) {
+                if (qc + u >= nq) break;
+                const int f = __shfl(myf, qc + u);
+                const int b = bq[u];
+                uint64_t acc[NW];
+#pragma unroll
+                for (int i = 0; i < NW; ++i) acc[i] = 0;
+                for (int j = 0; j < len; ++j) {
+                    const bool take = __shfl(b, j) <= b;
+#pragma unroll
+                    for (int i = 0; i < NW; ++i) {
+                        const uint64_t o = __shfl(cv[i], j);
+                        acc[i] += take ? o : 0ull;
+                    }
                 }
-            }
-            Cand c;
-            c.q = q0 + qq;
-            c.f = f;
-            c.b = b;
-            c.pad = 0;
-            uint32_t nl = 0;
-            uint64_t sl = 0, sr = 0;
+                Cand c;
+                c.q = q0 + qc + u;
+                c.f = f;
+                c.b = b;
+                c.pad = 0;
+                uint32_t nl = 0;
+                uint64_t sl = 0, sr = 0;
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k) {
-                const uint32_t l = (uint32_t)(acc[k >> 2] >> (16 * (k & 3))) & 0xFFFFu;
-                const uint32_t r = cnode[k] - l;
-                nl += l;
-                sl += (uint64_t)l * l;
-                sr += (uint64_t)r * r;
+                for (int k = 0; k < KMAX; ++k) {
+                    const uint32_t l = (uint32_t)(acc[k >> 2] >> (16 * (k & 3))) & 0xFFFFu;
+                    const uint32_t r = cnode[k] - l;
+                    nl += l;
+                    sl += (uint64_t)l * l;
+                    sr += (uint64_t)r * r;
+                }
+                c.nl = nl;
+                c.nr = N - nl;
+                c.sl = sl;
+                c.sr = sr;
+                const bool ok = valid && b <= B - 2 && nl > 0 && nl < N;
+                if (!ok) {
+                    c.nl = 0;
+                    c.b = 0x7FFFFFFF;
+                }
+                const Cand fb = F.split_rank ? wave_best_fp32(c, ok ? cand_q32(c) : -1.0f)
+                                             : wave_best_exact(c);
+                if (fb.nl != 0 && (best.nl == 0 || cand_better(fb, best))) best = fb;
             }
-            c.nl = nl;
-            c.nr = N - nl;
-            c.sl = sl;
-            c.sr = sr;
-            const bool ok = valid && b <= B - 2 && nl > 0 && nl < N;
-            if (!ok) {
-                c.nl = 0;
-                c.b = 0x7FFFFFFF;
-            }
-            const Cand fb =
-                F.split_rank ? wave_best_fp32(c, ok ? cand_q32(c) : -1.0f) : wave_best_exact(c);
-            if (fb.nl != 0 && (best.nl == 0 || cand_better(fb, best))) best = fb;
         }
     }
     if (F.alg_bytes && lane == 0)
         atomicAdd((unsigned long long*)&F.alg_bytes[1],
                   (unsigned long long)len * (unsigned long long)(J.mtry + 6));
     if (best.nl == 0 || !cand_positive(best, S, N)) return;  // stays the leaf it was created as
-    const uint8_t* col = J.colptr[best.f];
-    const bool left = valid && (int)col[row] <= best.b;
+    const uint8_t* col = ldg(J.colptr + best.f);
+    const bool left = valid && (int)ldg(col + row) <= best.b;
     const uint64_t lm = __ballot(left), vm = __ballot(valid);
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const uint32_t nl_rows = (uint32_t)__popcll(lm);
@@ -313,49 +327,63 @@ __device__ Cand feature_best(const uint32_t* h, int B, int q, int f, const uint3
     return wave_best_exact(lb);
 }
 
-// Large nodes: one workgroup per (node, feature tile).
+// Large nodes, phase 1: one workgroup per (node, feature tile).  FT columns
+// per tile keep the LDS histogram at FT * 256 * KMAX * 4 = 32 KB.
 template <int KMAX>
-__global__ __launch_bounds__(256) void k_split_large(ForestDev F) {
-    extern __shared__ uint32_t hist[];  // [ft][B][KMAX]
-    __shared__ const uint8_t* s_col[16];
-    __shared__ int s_feat[16];
-    __shared__ Cand s_fbest[16];
-    __shared__ Cand s_best;
-    __shared__ int s_last, s_split;
-    __shared__ uint32_t s_cl[KMAX];
-    __shared__ uint32_t s_wcnt[4];
-    __shared__ uint32_t s_run;
+__global__ __launch_bounds__(256) void k_hist_tile(ForestDev F) {
+    constexpr int FT = 32 / KMAX;
+    extern __shared__ uint32_t hist[];  // [FT][B][KMAX]
+    __shared__ const uint8_t* s_col[FT];
+    __shared__ int s_feat[FT];
+    __shared__ Cand s_fbest[FT];
     const Item it = F.items_in[blockIdx.x];
     const NodeDev nd = F.nodes[it.node];
     const TreeDev tr = F.trees[nd.tree];
-    JobDev& J = F.jobs[tr.job];
+    const JobDev& J = F.jobs[tr.job];
     const int B = J.B, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int q0 = (int)it.tile * F.ft;
-    const int nf = min(F.ft, J.mtry - q0);
+    const int q0 = (int)it.tile * FT;
+    const int nf = min(FT, J.mtry - q0);
     if (tid < nf) {
         const KeyedPerm P = make_perm(J.seed_lo, J.seed_hi, kMtry, (uint32_t)J.t,
                                       (uint32_t)tr.tau, nd.heap, 0u, (uint64_t)J.p_w);
         const int f = (int)perm_apply(P, (uint32_t)(q0 + tid));
         s_feat[tid] = f;
-        s_col[tid] = J.colptr[f];
+        s_col[tid] = ldg(J.colptr + f);
     }
-    for (int i = tid; i < nf * B * KMAX; i += 256) hist[i] = 0;
-    if (tid < KMAX) s_cl[tid] = 0;
+    for (int i = tid; i < FT * B * KMAX; i += 256) hist[i] = 0;
     __syncthreads();
+    const uint8_t* col[FT];
+#pragma unroll
+    for (int q = 0; q < FT; ++q) col[q] = q < nf ? s_col[q] : s_col[0];
     const uint64_t* recs = J.rec[F.parity] + (size_t)tr.tau * J.n + nd.seg;
-    for (uint32_t i = tid; i < nd.len; i += 256) {
-        const uint64_t r = recs[i];
-        const uint32_t row = rec_row(r), wt = rec_w(r), yv = rec_y(r);
-        for (int q = 0; q < nf; ++q) atomicAdd(&hist[(q * B + s_col[q][row]) * KMAX + yv], wt);
+    const uint32_t len = nd.len;
+    // two rows per thread per pass: up to 2 * FT bin gathers in flight
+    for (uint32_t i0 = tid; i0 < len; i0 += 512) {
+        const uint32_t i1 = i0 + 256;
+        const bool v1 = i1 < len;
+        const uint64_t r0 = ldg(recs + i0);
+        const uint64_t r1 = v1 ? ldg(recs + i1) : r0;
+        const uint32_t row0 = rec_row(r0), row1 = rec_row(r1);
+        uint32_t b0[FT], b1[FT];
+#pragma unroll
+        for (int q = 0; q < FT; ++q) {
+            b0[q] = ldg(col[q] + row0);
+            b1[q] = ldg(col[q] + row1);
+        }
+        const uint32_t w0 = rec_w(r0), y0 = rec_y(r0);
+        const uint32_t w1 = v1 ? rec_w(r1) : 0u, y1 = rec_y(r1);
+#pragma unroll
+        for (int q = 0; q < FT; ++q) {
+            if (q < nf) {
+                atomicAdd(&hist[(q * B + b0[q]) * KMAX + y0], w0);
+                if (v1) atomicAdd(&hist[(q * B + b1[q]) * KMAX + y1], w1);
+            }
+        }
     }
     __syncthreads();
     uint32_t cnode[KMAX];
-    uint64_t S = 0;
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-        cnode[k] = k < J.K ? F.cls[(size_t)it.node * F.kmax + k] : 0u;
-        S += (uint64_t)cnode[k] * cnode[k];
-    }
+    for (int k = 0; k < KMAX; ++k) cnode[k] = k < J.K ? F.cls[(size_t)it.node * F.kmax + k] : 0u;
     const uint32_t N = nd.n;
     for (int q = wave; q < nf; q += 4) {
         const Cand fb =
@@ -370,35 +398,57 @@ __global__ __launch_bounds__(256) void k_split_large(ForestDev F) {
         F.cand[(size_t)it.slot * F.max_tiles + it.tile] = tb;
         if (F.alg_bytes)
             atomicAdd((unsigned long long*)&F.alg_bytes[0],
-                      (unsigned long long)nd.len * (unsigned long long)(nf + (it.tile == 0 ? 6 : 0)));
-        __threadfence();
-        const uint32_t prev = atomicAdd(&F.done[it.slot], 1u);
-        s_last = prev == (uint32_t)J.ntiles - 1u;
+                      (unsigned long long)len * (unsigned long long)(nf + (it.tile == 0 ? 6 : 0)));
     }
-    __syncthreads();
-    if (!s_last) return;
-    // ---- last tile of the node: choose the split over all tiles
+}
+
+// Large nodes, phase 2: one workgroup per node.  The node's split is the
+// best tile candidate (tiles hold increasing draw positions, so keeping the
+// first of equal candidates keeps the earliest draw); a strictly positive
+// decrease splits the node and its rows are partitioned stably, left first.
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_split_finalize(ForestDev F, uint32_t slot_base) {
+    __shared__ Cand s_best;
+    __shared__ int s_split;
+    __shared__ uint32_t s_cl[KMAX];
+    __shared__ uint32_t s_wcnt[4];
+    __shared__ uint32_t s_run;
+    const uint32_t slot = slot_base + blockIdx.x;
+    const uint32_t id = F.slot_node_in[slot];
+    const NodeDev nd = F.nodes[id];
+    const TreeDev tr = F.trees[nd.tree];
+    JobDev& J = F.jobs[tr.job];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t cnode[KMAX];
+    uint64_t S = 0;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        cnode[k] = k < J.K ? F.cls[(size_t)id * F.kmax + k] : 0u;
+        S += (uint64_t)cnode[k] * cnode[k];
+    }
+    const uint32_t N = nd.n;
+    if (tid < KMAX) s_cl[tid] = 0;
     if (tid == 0) {
-        __threadfence();
         Cand best;
         best.nl = 0;
         for (int tl = 0; tl < J.ntiles; ++tl) {
-            const Cand c = F.cand[(size_t)it.slot * F.max_tiles + tl];
+            const Cand c = F.cand[(size_t)slot * F.max_tiles + tl];
             if (c.nl != 0 && (best.nl == 0 || cand_better(c, best))) best = c;
         }
-        F.done[it.slot] = 0;
         s_best = best;
         s_split = best.nl != 0 && cand_positive(best, S, N);
         s_run = 0;
     }
     __syncthreads();
-    if (!s_split) return;
+    if (!s_split) return;  // stays the leaf it was created as
     const Cand best = s_best;
-    const uint8_t* col = J.colptr[best.f];
+    const uint8_t* col = ldg(J.colptr + best.f);
+    const uint64_t* recs = J.rec[F.parity] + (size_t)tr.tau * J.n + nd.seg;
     uint64_t* rout = J.rec[F.parity ^ 1] + (size_t)tr.tau * J.n + nd.seg;
     // pass 1: distinct rows going left
     uint32_t cnt = 0;
-    for (uint32_t i = tid; i < nd.len; i += 256) cnt += (int)col[rec_row(recs[i])] <= best.b;
+    for (uint32_t i = tid; i < nd.len; i += 256)
+        cnt += (int)ldg(col + rec_row(ldg(recs + i))) <= best.b;
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) cnt += __shfl_xor(cnt, m);
     if (lane == 0) s_wcnt[wave] = cnt;
@@ -410,9 +460,9 @@ __global__ __launch_bounds__(256) void k_split_large(ForestDev F) {
     for (uint32_t base = 0; base < nd.len; base += 256) {
         const uint32_t i = base + tid;
         const bool valid = i < nd.len;
-        const uint64_t r = valid ? recs[i] : 0ull;
-        const bool left = valid && (int)col[rec_row(r)] <= best.b;
-        const uint64_t lm = __ballot(left), vm = __ballot(valid);
+        const uint64_t r = valid ? ldg(recs + i) : 0ull;
+        const bool left = valid && (int)ldg(col + rec_row(r)) <= best.b;
+        const uint64_t lm = __ballot(left);
         if (lane == 0) s_wcnt[wave] = (uint32_t)__popcll(lm);
         __syncthreads();
         uint32_t lpre = s_run;
@@ -427,7 +477,6 @@ __global__ __launch_bounds__(256) void k_split_large(ForestDev F) {
                 rout[nl_rows + (i - lrow)] = r;
             }
         }
-        (void)vm;
         __syncthreads();
         if (tid == 0) s_run += s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
         __syncthreads();
@@ -438,7 +487,7 @@ __global__ __launch_bounds__(256) void k_split_large(ForestDev F) {
             cl[k] = k < KMAX ? s_cl[k] : 0u;
             cr[k] = (k < KMAX ? cnode[k] : 0u) - cl[k];
         }
-        split_node(F, J, tr, it.node, nd, best, nl_rows, cl, cr, cand_gain_fix(best, S, N));
+        split_node(F, J, tr, id, nd, best, nl_rows, cl, cr, cand_gain_fix(best, S, N));
     }
 }
 
@@ -458,14 +507,27 @@ void launch_split_small(const ForestDev& F, uint32_t n_small, hipStream_t st) {
     }
 }
 
-void launch_split_large(const ForestDev& F, uint32_t n_items, int B, hipStream_t st) {
+void launch_hist_tile(const ForestDev& F, uint32_t n_items, int B, hipStream_t st) {
     if (!n_items) return;
-    const size_t lds = (size_t)F.ft * B * F.kmax * sizeof(uint32_t);
+    const size_t lds = (size_t)32 * B * sizeof(uint32_t);  // FT * B * KMAX words, FT * KMAX = 32
     const dim3 grid(n_items);
     switch (F.kmax) {
-        case 4: hipLaunchKernelGGL(k_split_large<4>, grid, dim3(256), lds, st, F); break;
-        case 8: hipLaunchKernelGGL(k_split_large<8>, grid, dim3(256), lds, st, F); break;
-        default: hipLaunchKernelGGL(k_split_large<16>, grid, dim3(256), lds, st, F); break;
+        case 4: hipLaunchKernelGGL(k_hist_tile<4>, grid, dim3(256), lds, st, F); break;
+        case 8: hipLaunchKernelGGL(k_hist_tile<8>, grid, dim3(256), lds, st, F); break;
+        default: hipLaunchKernelGGL(k_hist_tile<16>, grid, dim3(256), lds, st, F); break;
+    }
+}
+
+void launch_split_finalize(const ForestDev& F, uint32_t slot_base, uint32_t n_slots,
+                           hipStream_t st) {
+    if (!n_slots) return;
+    const dim3 grid(n_slots);
+    switch (F.kmax) {
+        case 4: hipLaunchKernelGGL(k_split_finalize<4>, grid, dim3(256), 0, st, F, slot_base); break;
+        case 8: hipLaunchKernelGGL(k_split_finalize<8>, grid, dim3(256), 0, st, F, slot_base); break;
+        default:
+            hipLaunchKernelGGL(k_split_finalize<16>, grid, dim3(256), 0, st, F, slot_base);
+            break;
     }
 }
 
