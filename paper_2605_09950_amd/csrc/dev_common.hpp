@@ -120,6 +120,18 @@ __device__ __forceinline__ T ldg(const T* p) {
     return *(const __attribute__((address_space(1))) T*)p;
 }
 
+// Wave-uniform values: the compiler cannot see that e.g. threadIdx.x / 64 is
+// the same in every lane; readfirstlane moves such values to scalar registers.
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+// Value of lane `src` (a wave-uniform index) as a scalar.
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int src) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // ---------------------------------------------------------------------------
 // Exact integer helpers.
 __device__ __forceinline__ int clz128(u128 v) {
@@ -257,7 +269,7 @@ struct Item {
 
 // Per-level append counters (reset before each level).
 struct LevelCtr {
-    uint32_t n_nodes;   // children appended to the next level
+    uint32_t unused;
     uint32_t n_items;   // (large node, feature tile) items
     uint32_t n_slots;   // large nodes
     uint32_t n_small;   // small nodes
@@ -290,9 +302,11 @@ struct ForestDev {
     Item* items_out;
     uint32_t* small_out;
     LevelCtr* ctr;
-    uint64_t* alg_bytes;  // [2] algorithmic bytes (large, small), nullable
+    uint64_t* alg_bytes;  // [2][64] algorithmic bytes (large, small), nullable; the
+                          // 64 words per kernel spread the atomics
     uint32_t node_cap, item_cap, slot_cap, small_cap;
     uint32_t next_base;   // first node index of the next level
+    uint32_t n_small_cur; // small nodes searched in this level
     int32_t kmax, ft, max_tiles, parity, split_rank, pad;
 };
 

@@ -29,7 +29,7 @@ void launch_boot_draw(JobDev*, const TreeDev*, int, int64_t, hipStream_t);
 void launch_fill_u32(uint32_t*, size_t, uint32_t, hipStream_t);
 // k_forest.hip
 void launch_boot_compact(const ForestDev&, uint32_t, hipStream_t);
-void launch_split_small(const ForestDev&, uint32_t, hipStream_t);
+void launch_split_small(const ForestDev&, uint32_t, uint32_t, hipStream_t);
 void launch_hist_tile(const ForestDev&, uint32_t, int, hipStream_t);
 void launch_split_finalize(const ForestDev&, uint32_t, uint32_t, hipStream_t);
 // k_importance.hip
@@ -192,7 +192,9 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
         pl.jp.push_back(j);
         const uint64_t per_tree_nodes =
             std::min<uint64_t>((uint64_t(1) << (s.D + 1)) - 1, 2 * (uint64_t)s.n - 1);
-        node_cap += T * per_tree_nodes;
+        // every searched node reserves a pair of child slots (a leaf leaves its
+        // pair unused), so the pool holds up to twice the nodes of the trees
+        node_cap += T + 2 * T * per_tree_nodes;
         const uint64_t large_per_tree = (uint64_t)(s.n + kSmallRows) / (kSmallRows + 1);
         slot_cap += T * large_per_tree;
         item_cap += T * large_per_tree * (uint64_t)j.ntiles_max;
@@ -226,7 +228,7 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     pl.slot0 = r.take((size_t)pl.slot_cap * 4);
     pl.slot1 = r.take((size_t)pl.slot_cap * 4);
     pl.ctr = r.take(sizeof(LevelCtr));
-    pl.alg = r.take(16);
+    pl.alg = r.take(128 * 8);
     pl.tot = r.take((size_t)pl.T_total * 8);
     pl.total = r.total + 256;
     return pl;
@@ -394,7 +396,7 @@ void Engine::setup(std::vector<int>& status) {
     }
     for (int j = 0; j < nj; ++j)
         if (status[j] != BORUTA_OK) hj[j].live = 0;
-    launch_fill_u32(at<uint32_t>(pl.alg), 4, 0u, st);
+    launch_fill_u32(at<uint32_t>(pl.alg), 256, 0u, st);
     h2d(at<JobDev>(pl.jobs), hj.data(), hj.size() * sizeof(JobDev));
     HIPC(hipStreamSynchronize(st));
 }
@@ -403,15 +405,9 @@ void Engine::grow_level_plain(ForestDev F, uint32_t n_items, uint32_t n_small) {
     // One launch (or, for a large node, one histogram launch over its tiles
     // and one finalize launch) per node: the node lists are read back and
     // each node is its own launch.
-    std::vector<uint32_t> small(n_small);
     std::vector<Item> items(n_items);
-    if (n_small) d2h(small.data(), F.small_in, n_small * 4);
     if (n_items) d2h(items.data(), F.items_in, n_items * sizeof(Item));
-    const uint32_t* small_base = F.small_in;
-    for (uint32_t i = 0; i < n_small; ++i) {
-        F.small_in = small_base + i;
-        launch_split_small(F, 1, st);
-    }
+    for (uint32_t i = 0; i < n_small; ++i) launch_split_small(F, i, 1, st);
     const Item* item_base = F.items_in;
     for (uint32_t a = 0; a < n_items;) {
         uint32_t b = a + 1;
@@ -504,14 +500,18 @@ void Engine::iteration(const std::vector<int>& live) {
         F.small_out = small[(d + 1) & 1];
         F.slot_node_out = slots[(d + 1) & 1];
         F.next_base = n_nodes;
+        F.n_small_cur = work_small;
         F.parity = d & 1;
+        // children of this level: a pair per searched node, small nodes first
+        const uint64_t level_end = (uint64_t)n_nodes + 2ull * (work_small + work_slots);
+        if (level_end > pl.node_cap) throw Error(BORUTA_E_DEVICE, "node pool too small");
         launch_fill_u32((uint32_t*)F.ctr, sizeof(LevelCtr) / 4, 0u, st);
         if (O.form == BORUTA_FORM_PLAIN) {
             grow_level_plain(F, work_items, work_small);
         } else {
             if (work_small) {
                 ts.start(st);
-                launch_split_small(F, work_small, st);
+                launch_split_small(F, 0, work_small, st);
                 if (O.stats) {
                     O.stats->hist_small.ms += ts.stop(st);
                     O.stats->hist_small.launches += 1;
@@ -534,7 +534,7 @@ void Engine::iteration(const std::vector<int>& live) {
         }
         d2h(&c, F.ctr, sizeof(c));
         if (c.overflow) throw Error(BORUTA_E_DEVICE, "internal capacity exceeded (tree level)");
-        n_nodes += c.n_nodes;
+        n_nodes = (uint32_t)level_end;
         work_items = c.n_items;
         work_small = c.n_small;
         work_slots = c.n_slots;
@@ -586,6 +586,7 @@ void Engine::emit_trace(const std::vector<int>& live, const std::vector<int>& tr
         const int g0 = tree_base[li];
         std::vector<std::vector<uint32_t>> idx(J.T);
         for (uint32_t i = 0; i < n_nodes; ++i) {
+            if (nodes[i].tree == 0xFFFFFFFFu) continue;  // unused child pair of a leaf
             const int g = (int)nodes[i].tree;
             if (g >= g0 && g < g0 + J.T) idx[g - g0].push_back(i);
         }
@@ -640,11 +641,13 @@ int Engine::step() {
 
 void Engine::flush_stats() {
     if (!O.stats) return;
-    uint64_t ab[2];
-    d2h(ab, at<uint64_t>(pl.alg), 16);
-    O.stats->hist_large.alg_bytes += (double)ab[0];
-    O.stats->hist_small.alg_bytes += (double)ab[1];
-    launch_fill_u32(at<uint32_t>(pl.alg), 4, 0u, st);
+    uint64_t ab[128];
+    d2h(ab, at<uint64_t>(pl.alg), sizeof(ab));
+    for (int i = 0; i < 64; ++i) {
+        O.stats->hist_large.alg_bytes += (double)ab[i];
+        O.stats->hist_small.alg_bytes += (double)ab[64 + i];
+    }
+    launch_fill_u32(at<uint32_t>(pl.alg), 256, 0u, st);
 }
 
 void Engine::result(int j, Out& o) {

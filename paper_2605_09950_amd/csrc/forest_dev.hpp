@@ -92,9 +92,74 @@ __device__ __forceinline__ Cand wave_best_fp32(const Cand& c, float q32) {
     return wave_best_exact(f);
 }
 
-// Fill a new node record and queue it for a split search, or finalise it
-// as a leaf.  counts[k] are its weighted class counts.
-__device__ inline void init_node(const ForestDev& F, const JobDev& J, uint32_t idx, uint32_t tree,
+// Segment-wide variants for a wave split into 64/W aligned segments of W
+// lanes (W a power of two): every segment holds the candidates of one
+// feature, so the per-feature rules above apply within a segment.
+__device__ __forceinline__ Cand seg_best_exact(Cand c, int W) {
+    for (int m = 1; m < W; m <<= 1) {
+        const Cand o = shfl_xor_cand(c, m);
+        if (cand_wins_same_feature(o, c)) c = o;
+    }
+    return c;
+}
+
+__device__ __forceinline__ Cand seg_best_fp32(const Cand& c, float q32, int W) {
+    const int lane = threadIdx.x & 63;
+    float qmax = q32;
+    for (int m = 1; m < W; m <<= 1) qmax = fmaxf(qmax, __shfl_xor(qmax, m));
+    Cand out;
+    out.nl = 0;
+    out.b = 0x7FFFFFFF;
+    out.q = c.q;
+    if (qmax < 0.0f) return out;  // no valid candidate in the segment
+    const bool fin = q32 >= fp32_floor(qmax);
+    int bmin = fin ? c.b : 0x7FFFFFFF, bmax = fin ? c.b : -1;
+    for (int m = 1; m < W; m <<= 1) {
+        bmin = min(bmin, __shfl_xor(bmin, m));
+        bmax = max(bmax, __shfl_xor(bmax, m));
+    }
+    if (bmin == bmax) {
+        // a single threshold among the finalists: the same candidate in each of their lanes
+        const int base = lane & ~(W - 1);
+        const unsigned long long seg =
+            (W == 64 ? ~0ull : ((1ull << W) - 1ull)) << base;
+        const unsigned long long mask = __ballot(fin && c.b == bmin) & seg;
+        return shfl_cand(c, (int)__ffsll(mask) - 1);
+    }
+    Cand f = c;
+    if (!fin) {
+        f.nl = 0;
+        f.b = 0x7FFFFFFF;
+    }
+    return seg_best_exact(f, W);
+}
+
+// a beats b in the total order (higher Q, then earlier draw position);
+// equal Q and q can only be the same candidate.
+__device__ __forceinline__ bool cand_wins_total(const Cand& a, const Cand& b) {
+    if (b.nl == 0) return a.nl != 0;
+    if (a.nl == 0) return false;
+    if (cand_better(a, b)) return true;
+    if (cand_better(b, a)) return false;
+    return a.q < b.q;
+}
+
+// Best over the segments of the wave (segments hold different features).
+__device__ __forceinline__ Cand cross_seg_best(Cand c, int W) {
+    for (int m = W; m < 64; m <<= 1) {
+        const Cand o = shfl_xor_cand(c, m);
+        if (cand_wins_total(o, c)) c = o;
+    }
+    return c;
+}
+
+enum : int { kLeaf = 0, kSmall = 1, kLarge = 2 };
+
+// Write a new node record -- a leaf until a split search turns it into a
+// split -- and return what it needs next: nothing (final leaf: maximum depth,
+// fewer than two distinct rows or a single class), the wave path (<= 64
+// distinct rows) or the tiled histogram path.
+__device__ inline int write_node(const ForestDev& F, const JobDev& J, uint32_t idx, uint32_t tree,
                                  uint32_t heap, uint32_t seg, uint32_t len, uint32_t n,
                                  uint32_t depth, const uint32_t* counts) {
     uint32_t arg = 0, nonzero = 0;
@@ -116,33 +181,67 @@ __device__ inline void init_node(const ForestDev& F, const JobDev& J, uint32_t i
     nd.depth = (uint8_t)depth;
     F.nodes[idx] = nd;
     F.ngain[idx] = 0;
-    if ((int)depth >= J.D || len < 2 || nonzero <= 1) return;  // leaf
-    if (len <= (uint32_t)kSmallRows && n < 65536u) {
-        const uint32_t s = atomicAdd(&F.ctr->n_small, 1u);
-        if (s < F.small_cap)
-            F.small_out[s] = idx;
-        else
-            atomicOr(&F.ctr->overflow, 1u);
-        return;
-    }
-    const uint32_t ntiles = (uint32_t)J.ntiles;
-    const uint32_t slot = atomicAdd(&F.ctr->n_slots, 1u);
-    const uint32_t it = atomicAdd(&F.ctr->n_items, ntiles);
-    if (slot >= F.slot_cap || it + ntiles > F.item_cap) {
+    if ((int)depth >= J.D || len < 2 || nonzero <= 1) return kLeaf;
+    return (len <= (uint32_t)kSmallRows && n < 65536u) ? kSmall : kLarge;
+}
+
+// Place node idx in the next level's lists at already reserved positions.
+__device__ inline void put_small(const ForestDev& F, uint32_t pos, uint32_t idx) {
+    if (pos < F.small_cap)
+        F.small_out[pos] = idx;
+    else
+        atomicOr(&F.ctr->overflow, 1u);
+}
+
+__device__ inline void put_large(const ForestDev& F, uint32_t slot, uint32_t item,
+                                 uint32_t ntiles, uint32_t idx) {
+    if (slot >= F.slot_cap || item + ntiles > F.item_cap) {
         atomicOr(&F.ctr->overflow, 2u);
         return;
     }
     F.slot_node_out[slot] = idx;
-    for (uint32_t tl = 0; tl < ntiles; ++tl) F.items_out[it + tl] = Item{idx, slot, tl, 0};
+    for (uint32_t tl = 0; tl < ntiles; ++tl) F.items_out[item + tl] = Item{idx, slot, tl, 0};
 }
 
-// Turn node `id` into a split on (best.f, best.b) with the given child row
-// counts / class counts, and create both children in the next level.
+// Reserve list positions for up to two new nodes (one atomic per list) and
+// place them.
+__device__ inline void enqueue_nodes(const ForestDev& F, const JobDev& J, uint32_t idx0,
+                                     const int* kinds, int count) {
+    uint32_t ns = 0, nl = 0;
+    for (int c = 0; c < count; ++c) {
+        ns += kinds[c] == kSmall;
+        nl += kinds[c] == kLarge;
+    }
+    const uint32_t nt = (uint32_t)J.ntiles;
+    uint32_t ps = ns ? atomicAdd(&F.ctr->n_small, ns) : 0u;
+    uint32_t pl = nl ? atomicAdd(&F.ctr->n_slots, nl) : 0u;
+    uint32_t pi = nl ? atomicAdd(&F.ctr->n_items, nl * nt) : 0u;
+    for (int c = 0; c < count; ++c) {
+        if (kinds[c] == kSmall) put_small(F, ps++, idx0 + c);
+        if (kinds[c] == kLarge) {
+            put_large(F, pl++, pi, nt, idx0 + c);
+            pi += nt;
+        }
+    }
+}
+
+// Children of the i-th searched node of a level (small nodes first, then
+// large-node slots) live at next_base + 2 i: no allocation counter.  A
+// searched node that stays a leaf marks its pair unused.
+__device__ inline void mark_unused_pair(const ForestDev& F, uint32_t child) {
+    if (child + 2 <= F.node_cap) {
+        F.nodes[child].tree = 0xFFFFFFFFu;
+        F.nodes[child + 1].tree = 0xFFFFFFFFu;
+    }
+}
+
+// Turn node `id` into a split on (best.f, best.b) and write both children
+// at child, child + 1; kinds[] receives what each child needs next.
 __device__ inline void split_node(const ForestDev& F, JobDev& J, const TreeDev& tr, uint32_t id,
                                   const NodeDev& nd, const Cand& best, uint32_t nl_rows,
-                                  const uint32_t* cl, const uint32_t* cr, uint64_t gain) {
-    const uint32_t off = atomicAdd(&F.ctr->n_nodes, 2u);
-    const uint32_t child = F.next_base + off;
+                                  const uint32_t* cl, const uint32_t* cr, uint64_t gain,
+                                  uint32_t child, int* kinds) {
+    kinds[0] = kinds[1] = kLeaf;
     if (child + 2 > F.node_cap) {
         atomicOr(&F.ctr->overflow, 4u);
         return;  // stays a leaf; the host reports the failure
@@ -154,9 +253,10 @@ __device__ inline void split_node(const ForestDev& F, JobDev& J, const TreeDev& 
     if (J.mode == 0)
         atomicAdd((unsigned long long*)&J.G[(size_t)tr.tau * J.pw_cap + best.f],
                   (unsigned long long)gain);
-    init_node(F, J, child, nd.tree, 2 * nd.heap, nd.seg, nl_rows, best.nl, nd.depth + 1u, cl);
-    init_node(F, J, child + 1, nd.tree, 2 * nd.heap + 1, nd.seg + nl_rows, nd.len - nl_rows,
-              best.nr, nd.depth + 1u, cr);
+    kinds[0] = write_node(F, J, child, nd.tree, 2 * nd.heap, nd.seg, nl_rows, best.nl,
+                          nd.depth + 1u, cl);
+    kinds[1] = write_node(F, J, child + 1, nd.tree, 2 * nd.heap + 1, nd.seg + nl_rows,
+                          nd.len - nl_rows, best.nr, nd.depth + 1u, cr);
 }
 
 }  // namespace boruta

@@ -86,19 +86,32 @@ __global__ __launch_bounds__(1024) void k_boot_compact(ForestDev F) {
             counts[k] = s_cls[k];
             tot += s_cls[k];
         }
-        init_node(F, J, g, g, 1u, 0u, s_base_in, tot, 0u, counts);
+        const int kind = write_node(F, J, g, g, 1u, 0u, s_base_in, tot, 0u, counts);
+        enqueue_nodes(F, J, g, &kind, 1);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Small nodes: one wavefront per node, one row per lane.
+// Small nodes: one wavefront per node.  With W = the node's row count rounded
+// up to a power of two, the wave is split into 64/W segments of W lanes; a
+// segment holds the node's rows (one per lane) and evaluates one drawn
+// feature, so 64/W features are scored per pass.  The left class counts of
+// the threshold at a lane's own bin come from an all-pairs sum over the
+// segment; the bins of the next pass are gathered while this one computes.
+struct SmallOut {
+    int kinds[2];
+    uint32_t child;
+    uint32_t ntiles;
+    uint64_t alg;
+};
+
 template <int KMAX>
-__global__ __launch_bounds__(256) void k_split_small(ForestDev F, uint32_t n_small) {
+__device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out) {
     constexpr int NW = (KMAX + 3) / 4;  // 16-bit class counters packed four per u64
     const int lane = threadIdx.x & 63;
-    const uint32_t idx = blockIdx.x * 4u + (threadIdx.x >> 6);
-    if (idx >= n_small) return;
-    const uint32_t id = F.small_in[idx];
+    out.kinds[0] = out.kinds[1] = kLeaf;
+    out.child = F.next_base + 2u * idx;
+    const uint32_t id = uniform(F.small_in[idx]);
     const NodeDev nd = F.nodes[id];
     const TreeDev tr = F.trees[nd.tree];
     JobDev& J = F.jobs[tr.job];
@@ -106,14 +119,18 @@ __global__ __launch_bounds__(256) void k_split_small(ForestDev F, uint32_t n_sma
     const size_t tbase = (size_t)tr.tau * J.n + nd.seg;
     const uint64_t* rin = J.rec[F.parity] + tbase;
     uint64_t* rout = J.rec[F.parity ^ 1] + tbase;
-    const int len = (int)nd.len;
-    const bool valid = lane < len;
-    const uint64_t rec = valid ? rin[lane] : 0ull;
+    const int len = (int)uniform(nd.len);
+    int W = 2;
+    while (W < len) W <<= 1;
+    const int G = 64 / W;                // features per pass
+    const int seg = lane / W, i = lane & (W - 1);
+    const bool valid = i < len;
+    const uint64_t rec = valid ? ldg(rin + i) : 0ull;
     const uint32_t row = rec_row(rec), wt = rec_w(rec), yv = rec_y(rec);
     uint64_t cv[NW];
 #pragma unroll
-    for (int i = 0; i < NW; ++i)
-        cv[i] = (valid && (int)(yv >> 2) == i) ? ((uint64_t)wt << (16 * (yv & 3))) : 0ull;
+    for (int k = 0; k < NW; ++k)
+        cv[k] = (valid && (int)(yv >> 2) == k) ? ((uint64_t)wt << (16 * (yv & 3))) : 0ull;
     uint32_t cnode[KMAX];
     uint64_t S = 0;
 #pragma unroll
@@ -126,88 +143,103 @@ __global__ __launch_bounds__(256) void k_split_small(ForestDev F, uint32_t n_sma
                                   nd.heap, 0u, (uint64_t)J.p_w);
     Cand best;
     best.nl = 0;
-    best.q = -1;
+    best.q = 0x7FFFFFFF;
     best.b = 0x7FFFFFFF;
-    constexpr int kPre = 8;  // feature bins gathered ahead, to keep loads in flight
     for (int q0 = 0; q0 < J.mtry; q0 += 64) {
         const int nq = min(64, J.mtry - q0);
         const int myf = lane < nq ? (int)perm_apply(P, (uint32_t)(q0 + lane)) : 0;
-        const uint8_t* mycol = lane < nq ? ldg(J.colptr + myf) : nullptr;
-        for (int qc = 0; qc < nq; qc += kPre) {
-            int bq[kPre];
+        const unsigned long long mycol =
+            lane < nq ? (unsigned long long)ldg(J.colptr + myf) : 0ull;
+        const int passes = (nq + G - 1) / G;
+        auto gather = [&](int pass) {
+            const int qq = pass * G + seg;
+            const bool act = qq < nq;
+            const uint8_t* col = (const uint8_t*)__shfl(mycol, act ? qq : 0);
+            return (valid && act) ? (int)ldg(col + row) : 0x7FFF;
+        };
+        int b_next = gather(0);
+        for (int pass = 0; pass < passes; ++pass) {
+            const int b = b_next;
+            if (pass + 1 < passes) b_next = gather(pass + 1);
+            const int qq = pass * G + seg;
+            const bool act = qq < nq;
+            const int f = __shfl(myf, act ? qq : 0);
+            uint64_t acc[NW];
 #pragma unroll
-            for (int u = 0; u < kPre; ++u) {
-                const int src = min(qc + u, nq - 1);
-                const uint8_t* col = (const uint8_t*)__shfl((unsigned long long)mycol, src);
-                bq[u] = (valid && qc + u < nq) ? (int)ldg(col + row) : 0x7FFF;
-            }
+            for (int k = 0; k < NW; ++k) acc[k] = 0;
+            // rows j of the segment: bins by lane permute (eight in flight),
+            // class counters of row j read from lane j as scalars
+            const int sbase = lane - i;
+            for (int j0 = 0; j0 < len; j0 += 8) {
+                int bj[8];
 #pragma unroll
-            for (int u = 0; u < kPre; ++u) {
-                if (qc + u >= nq) break;
-                const int f = __shfl(myf, qc + u);
-                const int b = bq[u];
-                uint64_t acc[NW];
+                for (int u = 0; u < 8; ++u) bj[u] = __shfl(b, sbase + min(j0 + u, len - 1));
 #pragma unroll
-                for (int i = 0; i < NW; ++i) acc[i] = 0;
-                for (int j = 0; j < len; ++j) {
-                    const bool take = __shfl(b, j) <= b;
+                for (int u = 0; u < 8; ++u) {
+                    const int j = min(j0 + u, len - 1);
+                    const bool take = j0 + u < len && bj[u] <= b;
 #pragma unroll
-                    for (int i = 0; i < NW; ++i) {
-                        const uint64_t o = __shfl(cv[i], j);
-                        acc[i] += take ? o : 0ull;
+                    for (int k = 0; k < NW; ++k) {
+                        const uint64_t o = readlane64(cv[k], j);
+                        acc[k] += take ? o : 0ull;
                     }
                 }
-                Cand c;
-                c.q = q0 + qc + u;
-                c.f = f;
-                c.b = b;
-                c.pad = 0;
-                uint32_t nl = 0;
-                uint64_t sl = 0, sr = 0;
-#pragma unroll
-                for (int k = 0; k < KMAX; ++k) {
-                    const uint32_t l = (uint32_t)(acc[k >> 2] >> (16 * (k & 3))) & 0xFFFFu;
-                    const uint32_t r = cnode[k] - l;
-                    nl += l;
-                    sl += (uint64_t)l * l;
-                    sr += (uint64_t)r * r;
-                }
-                c.nl = nl;
-                c.nr = N - nl;
-                c.sl = sl;
-                c.sr = sr;
-                const bool ok = valid && b <= B - 2 && nl > 0 && nl < N;
-                if (!ok) {
-                    c.nl = 0;
-                    c.b = 0x7FFFFFFF;
-                }
-                const Cand fb = F.split_rank ? wave_best_fp32(c, ok ? cand_q32(c) : -1.0f)
-                                             : wave_best_exact(c);
-                if (fb.nl != 0 && (best.nl == 0 || cand_better(fb, best))) best = fb;
             }
+            Cand c;
+            c.q = q0 + qq;
+            c.f = f;
+            c.b = b;
+            c.pad = 0;
+            uint32_t nl = 0;
+            uint64_t sl = 0, sr = 0;
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                const uint32_t l = (uint32_t)(acc[k >> 2] >> (16 * (k & 3))) & 0xFFFFu;
+                const uint32_t r = cnode[k] - l;
+                nl += l;
+                sl += (uint64_t)l * l;
+                sr += (uint64_t)r * r;
+            }
+            c.nl = nl;
+            c.nr = N - nl;
+            c.sl = sl;
+            c.sr = sr;
+            const bool ok = valid && act && b <= B - 2 && nl > 0 && nl < N;
+            if (!ok) {
+                c.nl = 0;
+                c.b = 0x7FFFFFFF;
+            }
+            const Cand sb = F.split_rank ? seg_best_fp32(c, ok ? cand_q32(c) : -1.0f, W)
+                                         : seg_best_exact(c, W);
+            const Cand pb = cross_seg_best(sb, W);
+            if (pb.nl != 0 && (best.nl == 0 || cand_better(pb, best))) best = pb;
         }
     }
-    if (F.alg_bytes && lane == 0)
-        atomicAdd((unsigned long long*)&F.alg_bytes[1],
-                  (unsigned long long)len * (unsigned long long)(J.mtry + 6));
-    if (best.nl == 0 || !cand_positive(best, S, N)) return;  // stays the leaf it was created as
+    out.ntiles = (uint32_t)J.ntiles;
+    out.alg = (uint64_t)len * (uint64_t)(J.mtry + 6);
+    if (best.nl == 0 || !cand_positive(best, S, N)) {  // stays the leaf it was created as
+        if (lane == 0) mark_unused_pair(F, out.child);
+        return;
+    }
+    // partition with the lanes of segment 0
+    const bool mine = seg == 0 && valid;
     const uint8_t* col = ldg(J.colptr + best.f);
-    const bool left = valid && (int)ldg(col + row) <= best.b;
-    const uint64_t lm = __ballot(left), vm = __ballot(valid);
+    const bool left = mine && (int)ldg(col + row) <= best.b;
+    const uint64_t lm = __ballot(left), vm = __ballot(mine);
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const uint32_t nl_rows = (uint32_t)__popcll(lm);
-    if (valid) {
+    if (mine) {
         const uint32_t pos = left ? (uint32_t)__popcll(lm & below)
                                   : nl_rows + (uint32_t)__popcll(vm & ~lm & below);
         rout[pos] = rec;
     }
     uint64_t lc[NW];
 #pragma unroll
-    for (int i = 0; i < NW; ++i) {
-        uint64_t v = left ? cv[i] : 0ull;
+    for (int k = 0; k < NW; ++k) {
+        uint64_t v = left ? cv[k] : 0ull;
 #pragma unroll
         for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
-        lc[i] = v;
+        lc[k] = v;
     }
     if (lane == 0) {
         uint32_t cl[16], cr[16];
@@ -215,7 +247,59 @@ __global__ __launch_bounds__(256) void k_split_small(ForestDev F, uint32_t n_sma
             cl[k] = k < KMAX ? (uint32_t)(lc[k >> 2] >> (16 * (k & 3))) & 0xFFFFu : 0u;
             cr[k] = (k < KMAX ? cnode[k] : 0u) - cl[k];
         }
-        split_node(F, J, tr, id, nd, best, nl_rows, cl, cr, cand_gain_fix(best, S, N));
+        split_node(F, J, tr, id, nd, best, nl_rows, cl, cr, cand_gain_fix(best, S, N),
+                   out.child, out.kinds);
+    }
+}
+
+// Four nodes per workgroup (one per wave); the children's list positions are
+// reserved with one atomic per list for the whole workgroup.
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_split_small(ForestDev F, uint32_t first,
+                                                     uint32_t count) {
+    __shared__ uint32_t s_ns[4], s_nl[4], s_ni[4], s_base[3];
+    __shared__ unsigned long long s_alg[4];
+    const int lane = threadIdx.x & 63, wave = (int)uniform(threadIdx.x >> 6);
+    const uint32_t li = blockIdx.x * 4u + wave;
+    SmallOut o;
+    o.kinds[0] = o.kinds[1] = kLeaf;
+    o.child = 0;
+    o.ntiles = 0;
+    o.alg = 0;
+    if (li < count) small_node<KMAX>(F, first + li, o);
+    if (lane == 0) {
+        s_ns[wave] = (o.kinds[0] == kSmall) + (o.kinds[1] == kSmall);
+        s_nl[wave] = (o.kinds[0] == kLarge) + (o.kinds[1] == kLarge);
+        s_ni[wave] = s_nl[wave] * o.ntiles;
+        s_alg[wave] = o.alg;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t ts = s_ns[0] + s_ns[1] + s_ns[2] + s_ns[3];
+        const uint32_t tl = s_nl[0] + s_nl[1] + s_nl[2] + s_nl[3];
+        const uint32_t ti = s_ni[0] + s_ni[1] + s_ni[2] + s_ni[3];
+        s_base[0] = ts ? atomicAdd(&F.ctr->n_small, ts) : 0u;
+        s_base[1] = tl ? atomicAdd(&F.ctr->n_slots, tl) : 0u;
+        s_base[2] = ti ? atomicAdd(&F.ctr->n_items, ti) : 0u;
+        if (F.alg_bytes)
+            atomicAdd((unsigned long long*)&F.alg_bytes[64 + (blockIdx.x & 63)],
+                      s_alg[0] + s_alg[1] + s_alg[2] + s_alg[3]);
+    }
+    __syncthreads();
+    if (lane == 0 && li < count) {
+        uint32_t ps = s_base[0], pl = s_base[1], pi = s_base[2];
+        for (int v = 0; v < wave; ++v) {
+            ps += s_ns[v];
+            pl += s_nl[v];
+            pi += s_ni[v];
+        }
+        for (int c = 0; c < 2; ++c) {
+            if (o.kinds[c] == kSmall) put_small(F, ps++, o.child + c);
+            if (o.kinds[c] == kLarge) {
+                put_large(F, pl++, pi, o.ntiles, o.child + c);
+                pi += o.ntiles;
+            }
+        }
     }
 }
 
@@ -340,7 +424,7 @@ __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F) {
     const NodeDev nd = F.nodes[it.node];
     const TreeDev tr = F.trees[nd.tree];
     const JobDev& J = F.jobs[tr.job];
-    const int B = J.B, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int B = J.B, tid = threadIdx.x, lane = tid & 63, wave = (int)uniform(tid >> 6);
     const int q0 = (int)it.tile * FT;
     const int nf = min(FT, J.mtry - q0);
     if (tid < nf) {
@@ -397,7 +481,7 @@ __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F) {
             if (s_fbest[q].nl != 0 && (tb.nl == 0 || cand_better(s_fbest[q], tb))) tb = s_fbest[q];
         F.cand[(size_t)it.slot * F.max_tiles + it.tile] = tb;
         if (F.alg_bytes)
-            atomicAdd((unsigned long long*)&F.alg_bytes[0],
+            atomicAdd((unsigned long long*)&F.alg_bytes[blockIdx.x & 63],
                       (unsigned long long)len * (unsigned long long)(nf + (it.tile == 0 ? 6 : 0)));
     }
 }
@@ -440,15 +524,34 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F, uint32_t sl
         s_run = 0;
     }
     __syncthreads();
-    if (!s_split) return;  // stays the leaf it was created as
+    const uint32_t child = F.next_base + 2u * (F.n_small_cur + slot);
+    if (!s_split) {  // stays the leaf it was created as
+        if (tid == 0) mark_unused_pair(F, child);
+        return;
+    }
     const Cand best = s_best;
     const uint8_t* col = ldg(J.colptr + best.f);
     const uint64_t* recs = J.rec[F.parity] + (size_t)tr.tau * J.n + nd.seg;
     uint64_t* rout = J.rec[F.parity ^ 1] + (size_t)tr.tau * J.n + nd.seg;
+    // Rows are handled in blocks of 256 x kR: thread t owns rows
+    // [blk + t*kR, blk + t*kR + kR), so the order of (thread, row) is the row
+    // order and the scatter below is stable.  All loads of a block are issued
+    // before they are used.
+    constexpr int kR = 8;
+    const uint32_t len = nd.len;
     // pass 1: distinct rows going left
     uint32_t cnt = 0;
-    for (uint32_t i = tid; i < nd.len; i += 256)
-        cnt += (int)ldg(col + rec_row(ldg(recs + i))) <= best.b;
+    for (uint32_t blk = 0; blk < len; blk += 256 * kR) {
+        const uint32_t i0 = blk + (uint32_t)tid * kR;
+        uint64_t r[kR];
+#pragma unroll
+        for (int u = 0; u < kR; ++u) r[u] = i0 + u < len ? ldg(recs + i0 + u) : 0ull;
+        int bb[kR];
+#pragma unroll
+        for (int u = 0; u < kR; ++u) bb[u] = i0 + u < len ? (int)ldg(col + rec_row(r[u])) : 0x7FFF;
+#pragma unroll
+        for (int u = 0; u < kR; ++u) cnt += bb[u] <= best.b;
+    }
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) cnt += __shfl_xor(cnt, m);
     if (lane == 0) s_wcnt[wave] = cnt;
@@ -456,29 +559,43 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F, uint32_t sl
     const uint32_t nl_rows = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
     __syncthreads();
     // pass 2: stable scatter, left rows first
-    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    for (uint32_t base = 0; base < nd.len; base += 256) {
-        const uint32_t i = base + tid;
-        const bool valid = i < nd.len;
-        const uint64_t r = valid ? ldg(recs + i) : 0ull;
-        const bool left = valid && (int)ldg(col + rec_row(r)) <= best.b;
-        const uint64_t lm = __ballot(left);
-        if (lane == 0) s_wcnt[wave] = (uint32_t)__popcll(lm);
+    for (uint32_t blk = 0; blk < len; blk += 256 * kR) {
+        const uint32_t i0 = blk + (uint32_t)tid * kR;
+        uint64_t r[kR];
+#pragma unroll
+        for (int u = 0; u < kR; ++u) r[u] = i0 + u < len ? ldg(recs + i0 + u) : 0ull;
+        int bb[kR];
+#pragma unroll
+        for (int u = 0; u < kR; ++u) bb[u] = i0 + u < len ? (int)ldg(col + rec_row(r[u])) : 0x7FFF;
+        uint32_t mine = 0;
+#pragma unroll
+        for (int u = 0; u < kR; ++u) mine += bb[u] <= best.b;
+        // exclusive prefix of the left counts over the block's threads
+        uint32_t incl = mine;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t t = __shfl_up(incl, off);
+            if (lane >= off) incl += t;
+        }
+        if (lane == 63) s_wcnt[wave] = incl;
         __syncthreads();
-        uint32_t lpre = s_run;
-        for (int v = 0; v < wave; ++v) lpre += s_wcnt[v];
-        const uint32_t lrow = lpre + (uint32_t)__popcll(lm & below);
-        if (valid) {
-            if (left) {
-                rout[lrow] = r;
-                atomicAdd(&s_cl[rec_y(r)], rec_w(r));
+        uint32_t lrow = s_run + incl - mine;
+        for (int v = 0; v < wave; ++v) lrow += s_wcnt[v];
+        const uint32_t blk_left = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
+#pragma unroll
+        for (int u = 0; u < kR; ++u) {
+            const uint32_t i = i0 + u;
+            if (i >= len) break;
+            if (bb[u] <= best.b) {
+                rout[lrow++] = r[u];
+                atomicAdd(&s_cl[rec_y(r[u])], rec_w(r[u]));
             } else {
-                // rows before i that go right = i - (left rows before i)
-                rout[nl_rows + (i - lrow)] = r;
+                // right rows before i = i - (left rows before i)
+                rout[nl_rows + (i - lrow)] = r[u];
             }
         }
         __syncthreads();
-        if (tid == 0) s_run += s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
+        if (tid == 0) s_run += blk_left;
         __syncthreads();
     }
     if (tid == 0) {
@@ -487,7 +604,10 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F, uint32_t sl
             cl[k] = k < KMAX ? s_cl[k] : 0u;
             cr[k] = (k < KMAX ? cnode[k] : 0u) - cl[k];
         }
-        split_node(F, J, tr, id, nd, best, nl_rows, cl, cr, cand_gain_fix(best, S, N));
+        int kinds[2];
+        split_node(F, J, tr, id, nd, best, nl_rows, cl, cr, cand_gain_fix(best, S, N), child,
+                   kinds);
+        enqueue_nodes(F, J, child, kinds, 2);
     }
 }
 
@@ -497,13 +617,15 @@ void launch_boot_compact(const ForestDev& F, uint32_t n_trees, hipStream_t st) {
     hipLaunchKernelGGL(k_boot_compact, dim3(n_trees), dim3(1024), 0, st, F);
 }
 
-void launch_split_small(const ForestDev& F, uint32_t n_small, hipStream_t st) {
-    if (!n_small) return;
-    const dim3 grid((n_small + 3) / 4);
+void launch_split_small(const ForestDev& F, uint32_t first, uint32_t count, hipStream_t st) {
+    if (!count) return;
+    const dim3 grid((count + 3) / 4);
     switch (F.kmax) {
-        case 4: hipLaunchKernelGGL(k_split_small<4>, grid, dim3(256), 0, st, F, n_small); break;
-        case 8: hipLaunchKernelGGL(k_split_small<8>, grid, dim3(256), 0, st, F, n_small); break;
-        default: hipLaunchKernelGGL(k_split_small<16>, grid, dim3(256), 0, st, F, n_small); break;
+        case 4: hipLaunchKernelGGL(k_split_small<4>, grid, dim3(256), 0, st, F, first, count); break;
+        case 8: hipLaunchKernelGGL(k_split_small<8>, grid, dim3(256), 0, st, F, first, count); break;
+        default:
+            hipLaunchKernelGGL(k_split_small<16>, grid, dim3(256), 0, st, F, first, count);
+            break;
     }
 }
 

@@ -41,12 +41,18 @@ __global__ __launch_bounds__(256) void k_treeimp(JobDev* jobs, const int32_t* li
     if (J.mode != 0 || f >= J.p_w) return;
     const int g0 = tree_base[blockIdx.y];
     int64_t s = 0;
-    for (int tau = 0; tau < J.T; ++tau) {
-        uint64_t* gp = J.G + (size_t)tau * J.pw_cap + f;
-        const uint64_t g = *gp;
-        if (g == 0) continue;
-        *gp = 0;
-        s += (int64_t)udiv128((u128)g << 44, (u128)tot[g0 + tau]);
+    constexpr int kU = 8;  // trees per step: independent loads in flight
+    for (int t0 = 0; t0 < J.T; t0 += kU) {
+        uint64_t g[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            g[u] = t0 + u < J.T ? ldg(J.G + (size_t)(t0 + u) * J.pw_cap + f) : 0ull;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (g[u] == 0) continue;
+            J.G[(size_t)(t0 + u) * J.pw_cap + f] = 0;
+            s += (int64_t)udiv128((u128)g[u] << 44, (u128)tot[g0 + t0 + u]);
+        }
     }
     J.imp[f] = s;
 }
