@@ -211,8 +211,13 @@ __device__ __forceinline__ uint64_t cand_gain_fix(const Cand& c, uint64_t s, uin
     return udiv128(num << 32, den);
 }
 
+// FP32 score used only to rank candidates: S_L * rcp(N_L) + S_R * rcp(N_R)
+// with the hardware reciprocal (1 ulp).  Relative error <= 5u, u = 2^-24:
+// u converting S, 2u the reciprocal, u the product, u the sum (N < 2^24 is
+// exact in FP32).
 __device__ __forceinline__ float cand_q32(const Cand& c) {
-    return (float)c.sl / (float)c.nl + (float)c.sr / (float)c.nr;
+    return (float)c.sl * __builtin_amdgcn_rcpf((float)c.nl) +
+           (float)c.sr * __builtin_amdgcn_rcpf((float)c.nr);
 }
 
 // ---------------------------------------------------------------------------
@@ -307,6 +312,7 @@ struct ForestDev {
     uint32_t node_cap, item_cap, slot_cap, small_cap;
     uint32_t next_base;   // first node index of the next level
     uint32_t n_small_cur; // small nodes searched in this level
+    uint32_t small_ncap;  // a node takes the wave path only below this weighted count
     int32_t kmax, ft, max_tiles, parity, split_rank, pad;
 };
 

@@ -155,7 +155,7 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
         maxK = std::max(maxK, s.K);
         keys_words = std::max<int64_t>(keys_words, s.p * pow2_at_least(s.n));
     }
-    pl.kmax = maxK <= 4 ? 4 : (maxK <= 8 ? 8 : 16);
+    pl.kmax = maxK <= 2 ? 2 : (maxK <= 4 ? 4 : (maxK <= 8 ? 8 : 16));
     pl.ft = 32 / pl.kmax;  // feature columns per histogram tile (32 KB of LDS at 256 bins)
     pl.keys = r.take((size_t)keys_words * 4);
     uint64_t node_cap = 0, item_cap = 0, slot_cap = 0, small_cap = 0;
@@ -472,6 +472,8 @@ void Engine::iteration(const std::vector<int>& live) {
     F.ft = pl.ft;
     F.max_tiles = pl.max_tiles;
     F.split_rank = O.split_rank;
+    // the wave path packs class counters in 16-bit fields (8-bit for 3-4 classes)
+    F.small_ncap = pl.kmax == 4 ? 256u : 65536u;
     F.pad = 0;
     F.items_in = items[1];
     F.small_in = small[1];

@@ -2,6 +2,8 @@
 // node creation / classification and wave-level candidate reductions.
 #pragma once
 
+#include <climits>
+
 #include "dev_common.hpp"
 
 namespace boruta {
@@ -62,10 +64,10 @@ __device__ __forceinline__ int wave_max_i(int v) {
     return v;
 }
 
-// Relative margin of the FP32 ranking: every lane's FP32 score is within
-// 3 ulp (2^-24 each) of its exact value, so the exact best scores at least
-// (1 - 6 * 2^-24) * FP32 max; candidates at or above (1 - 2^-20) * FP32 max
-// are re-ranked exactly.
+// Margin of the FP32 ranking: each FP32 score is within 5u (u = 2^-24) of
+// its exact value, so the exact best scores at least (1 - 10u) * FP32 max;
+// every candidate at or above (1 - 2^-20) * FP32 max (16u) is re-ranked
+// exactly, hence the FP32-ranked choice equals the exact one.
 __device__ __forceinline__ float fp32_floor(float qmax) { return qmax * (1.0f - 0x1.0p-20f); }
 
 // Best of one feature's candidates with FP32 ranking and exact recheck of the
@@ -92,38 +94,59 @@ __device__ __forceinline__ Cand wave_best_fp32(const Cand& c, float q32) {
     return wave_best_exact(f);
 }
 
-// Segment-wide variants for a wave split into 64/W aligned segments of W
-// lanes (W a power of two): every segment holds the candidates of one
-// feature, so the per-feature rules above apply within a segment.
-__device__ __forceinline__ Cand seg_best_exact(Cand c, int W) {
-    for (int m = 1; m < W; m <<= 1) {
+// Total order over candidates of different features: higher Q, then the
+// earlier draw position q, then the smaller threshold b (equal (q, b) is the
+// same candidate).  The winner over a set is the sequential rule's choice.
+__device__ __forceinline__ bool cand_wins_total(const Cand& a, const Cand& b) {
+    if (b.nl == 0) return a.nl != 0;
+    if (a.nl == 0) return false;
+    if (cand_better(a, b)) return true;
+    if (cand_better(b, a)) return false;
+    return a.q < b.q || (a.q == b.q && a.b < b.b);
+}
+
+__device__ __forceinline__ Cand wave_best_total_exact(Cand c) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
         const Cand o = shfl_xor_cand(c, m);
-        if (cand_wins_same_feature(o, c)) c = o;
+        if (cand_wins_total(o, c)) c = o;
     }
     return c;
 }
 
-__device__ __forceinline__ Cand seg_best_fp32(const Cand& c, float q32, int W) {
-    const int lane = threadIdx.x & 63;
-    float qmax = q32;
-    for (int m = 1; m < W; m <<= 1) qmax = fmaxf(qmax, __shfl_xor(qmax, m));
+__device__ __forceinline__ long long wave_min_ll(long long v) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        const long long o = __shfl_xor(v, m);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ long long wave_max_ll(long long v) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        const long long o = __shfl_xor(v, m);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// The same with FP32 ranking: exact comparisons only among the finalists,
+// and none when all finalists are one candidate (the common case).
+__device__ __forceinline__ Cand wave_best_total_fp32(const Cand& c, float q32) {
+    const float qmax = wave_max_f(q32);
     Cand out;
     out.nl = 0;
     out.b = 0x7FFFFFFF;
-    out.q = c.q;
-    if (qmax < 0.0f) return out;  // no valid candidate in the segment
+    out.q = 0x7FFFFFFF;
+    if (qmax < 0.0f) return out;
     const bool fin = q32 >= fp32_floor(qmax);
-    int bmin = fin ? c.b : 0x7FFFFFFF, bmax = fin ? c.b : -1;
-    for (int m = 1; m < W; m <<= 1) {
-        bmin = min(bmin, __shfl_xor(bmin, m));
-        bmax = max(bmax, __shfl_xor(bmax, m));
-    }
-    if (bmin == bmax) {
-        // a single threshold among the finalists: the same candidate in each of their lanes
-        const int base = lane & ~(W - 1);
-        const unsigned long long seg =
-            (W == 64 ? ~0ull : ((1ull << W) - 1ull)) << base;
-        const unsigned long long mask = __ballot(fin && c.b == bmin) & seg;
+    const long long key = ((long long)c.q << 9) | (long long)(c.b & 511);
+    const long long kmin = wave_min_ll(fin ? key : LLONG_MAX);
+    const long long kmax = wave_max_ll(fin ? key : -1ll);
+    if (kmin == kmax) {
+        const unsigned long long mask = __ballot(fin && key == kmin);
         return shfl_cand(c, (int)__ffsll(mask) - 1);
     }
     Cand f = c;
@@ -131,26 +154,7 @@ __device__ __forceinline__ Cand seg_best_fp32(const Cand& c, float q32, int W) {
         f.nl = 0;
         f.b = 0x7FFFFFFF;
     }
-    return seg_best_exact(f, W);
-}
-
-// a beats b in the total order (higher Q, then earlier draw position);
-// equal Q and q can only be the same candidate.
-__device__ __forceinline__ bool cand_wins_total(const Cand& a, const Cand& b) {
-    if (b.nl == 0) return a.nl != 0;
-    if (a.nl == 0) return false;
-    if (cand_better(a, b)) return true;
-    if (cand_better(b, a)) return false;
-    return a.q < b.q;
-}
-
-// Best over the segments of the wave (segments hold different features).
-__device__ __forceinline__ Cand cross_seg_best(Cand c, int W) {
-    for (int m = W; m < 64; m <<= 1) {
-        const Cand o = shfl_xor_cand(c, m);
-        if (cand_wins_total(o, c)) c = o;
-    }
-    return c;
+    return wave_best_total_exact(f);
 }
 
 enum : int { kLeaf = 0, kSmall = 1, kLarge = 2 };
@@ -182,7 +186,7 @@ __device__ inline int write_node(const ForestDev& F, const JobDev& J, uint32_t i
     F.nodes[idx] = nd;
     F.ngain[idx] = 0;
     if ((int)depth >= J.D || len < 2 || nonzero <= 1) return kLeaf;
-    return (len <= (uint32_t)kSmallRows && n < 65536u) ? kSmall : kLarge;
+    return (len <= (uint32_t)kSmallRows && n < F.small_ncap) ? kSmall : kLarge;
 }
 
 // Place node idx in the next level's lists at already reserved positions.

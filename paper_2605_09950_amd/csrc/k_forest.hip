@@ -17,6 +17,8 @@
 // Q = S_L/N_L + S_R/N_R over drawn features and thresholds "bin <= b",
 // exact rational comparison, ties to the earlier draw then the smaller b;
 // split only on a strictly positive decrease Q - S/N.
+#include <type_traits>
+
 #include "forest_dev.hpp"
 
 namespace boruta {
@@ -105,9 +107,31 @@ struct SmallOut {
     uint64_t alg;
 };
 
+// Packed per-class counters of the wave path: KMAX <= 4 classes fit one
+// 32-bit word (16-bit fields for 2 classes, 8-bit for 4; the node's weighted
+// count stays below the field range), more classes use 64-bit words of four
+// 16-bit fields.
+template <int KMAX>
+struct Pack {
+    static constexpr bool kU32 = KMAX <= 4;
+    typedef typename std::conditional<kU32, uint32_t, uint64_t>::type word;
+    static constexpr int kPer = kU32 ? KMAX : 4;         // fields per word
+    static constexpr int kBits = kU32 ? 32 / KMAX : 16;  // bits per field
+    static constexpr int kWords = kU32 ? 1 : KMAX / 4;
+    static __device__ __forceinline__ uint32_t field(word w, int k) {
+        return (uint32_t)(w >> (kBits * (k % kPer))) & ((1u << kBits) - 1u);
+    }
+};
+
+__device__ __forceinline__ uint32_t readlane_w(uint32_t v, int src) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, src);
+}
+__device__ __forceinline__ uint64_t readlane_w(uint64_t v, int src) { return readlane64(v, src); }
+
 template <int KMAX>
 __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out) {
-    constexpr int NW = (KMAX + 3) / 4;  // 16-bit class counters packed four per u64
+    typedef Pack<KMAX> PK;
+    typedef typename PK::word word;
     const int lane = threadIdx.x & 63;
     out.kinds[0] = out.kinds[1] = kLeaf;
     out.child = F.next_base + 2u * idx;
@@ -127,10 +151,14 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out) {
     const bool valid = i < len;
     const uint64_t rec = valid ? ldg(rin + i) : 0ull;
     const uint32_t row = rec_row(rec), wt = rec_w(rec), yv = rec_y(rec);
-    uint64_t cv[NW];
+    // class counter word of this lane's row; zero outside segment 0 so that
+    // reading lane j >= len (any segment) contributes nothing
+    word cv[PK::kWords];
 #pragma unroll
-    for (int k = 0; k < NW; ++k)
-        cv[k] = (valid && (int)(yv >> 2) == k) ? ((uint64_t)wt << (16 * (yv & 3))) : 0ull;
+    for (int w = 0; w < PK::kWords; ++w)
+        cv[w] = (seg == 0 && valid && (int)yv / PK::kPer == w)
+                    ? ((word)wt << (PK::kBits * ((int)yv % PK::kPer)))
+                    : (word)0;
     uint32_t cnode[KMAX];
     uint64_t S = 0;
 #pragma unroll
@@ -164,24 +192,24 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out) {
             const int qq = pass * G + seg;
             const bool act = qq < nq;
             const int f = __shfl(myf, act ? qq : 0);
-            uint64_t acc[NW];
+            // left counts of threshold b: the segment's rows j with bin <= b.
+            // Bins by lane permute (eight in flight), counters of row j read
+            // from lane j as scalars; rows j >= len read zero counters.
+            word acc[PK::kWords];
 #pragma unroll
-            for (int k = 0; k < NW; ++k) acc[k] = 0;
-            // rows j of the segment: bins by lane permute (eight in flight),
-            // class counters of row j read from lane j as scalars
+            for (int w = 0; w < PK::kWords; ++w) acc[w] = 0;
             const int sbase = lane - i;
             for (int j0 = 0; j0 < len; j0 += 8) {
                 int bj[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) bj[u] = __shfl(b, sbase + min(j0 + u, len - 1));
+                for (int u = 0; u < 8; ++u) bj[u] = __shfl(b, sbase + j0 + u);
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    const int j = min(j0 + u, len - 1);
-                    const bool take = j0 + u < len && bj[u] <= b;
+                    const bool take = bj[u] <= b;
 #pragma unroll
-                    for (int k = 0; k < NW; ++k) {
-                        const uint64_t o = readlane64(cv[k], j);
-                        acc[k] += take ? o : 0ull;
+                    for (int w = 0; w < PK::kWords; ++w) {
+                        const word o = readlane_w(cv[w], j0 + u);
+                        acc[w] += take ? o : (word)0;
                     }
                 }
             }
@@ -194,7 +222,7 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out) {
             uint64_t sl = 0, sr = 0;
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) {
-                const uint32_t l = (uint32_t)(acc[k >> 2] >> (16 * (k & 3))) & 0xFFFFu;
+                const uint32_t l = PK::field(acc[k / PK::kPer], k);
                 const uint32_t r = cnode[k] - l;
                 nl += l;
                 sl += (uint64_t)l * l;
@@ -208,10 +236,10 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out) {
             if (!ok) {
                 c.nl = 0;
                 c.b = 0x7FFFFFFF;
+                c.q = 0x7FFFFFFF;
             }
-            const Cand sb = F.split_rank ? seg_best_fp32(c, ok ? cand_q32(c) : -1.0f, W)
-                                         : seg_best_exact(c, W);
-            const Cand pb = cross_seg_best(sb, W);
+            const Cand pb = F.split_rank ? wave_best_total_fp32(c, ok ? cand_q32(c) : -1.0f)
+                                         : wave_best_total_exact(c);
             if (pb.nl != 0 && (best.nl == 0 || cand_better(pb, best))) best = pb;
         }
     }
@@ -233,18 +261,18 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out) {
                                   : nl_rows + (uint32_t)__popcll(vm & ~lm & below);
         rout[pos] = rec;
     }
-    uint64_t lc[NW];
+    word lc[PK::kWords];
 #pragma unroll
-    for (int k = 0; k < NW; ++k) {
-        uint64_t v = left ? cv[k] : 0ull;
+    for (int w = 0; w < PK::kWords; ++w) {
+        word v = left ? cv[w] : (word)0;
 #pragma unroll
         for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
-        lc[k] = v;
+        lc[w] = v;
     }
     if (lane == 0) {
         uint32_t cl[16], cr[16];
         for (int k = 0; k < 16; ++k) {
-            cl[k] = k < KMAX ? (uint32_t)(lc[k >> 2] >> (16 * (k & 3))) & 0xFFFFu : 0u;
+            cl[k] = k < KMAX ? PK::field(lc[k / PK::kPer], k) : 0u;
             cr[k] = (k < KMAX ? cnode[k] : 0u) - cl[k];
         }
         split_node(F, J, tr, id, nd, best, nl_rows, cl, cr, cand_gain_fix(best, S, N),
@@ -367,8 +395,16 @@ __device__ Cand feature_best(const uint32_t* h, int B, int q, int f, const uint3
         for (int u = 0; u < bpl; ++u) {
             const int b = b0 + u;
             if (b >= B - 1) break;
+            uint32_t add = 0;
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k) cl[k] += h[b * KMAX + k];
+            for (int k = 0; k < KMAX; ++k) {
+                const uint32_t v = h[b * KMAX + k];
+                cl[k] += v;
+                add += v;
+            }
+            // an empty bin repeats the previous threshold's partition, which the
+            // smaller threshold already represents
+            if (add == 0) continue;
             const Cand c = make(b, cl);
             if (c.nl == 0 || c.nl == N) continue;
             if (lb.nl == 0 || cand_better(c, lb)) lb = c;
@@ -383,8 +419,14 @@ __device__ Cand feature_best(const uint32_t* h, int B, int q, int f, const uint3
     for (int u = 0; u < bpl; ++u) {
         const int b = b0 + u;
         if (b >= B - 1) break;
+        uint32_t add = 0;
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k) cl[k] += h[b * KMAX + k];
+        for (int k = 0; k < KMAX; ++k) {
+            const uint32_t v = h[b * KMAX + k];
+            cl[k] += v;
+            add += v;
+        }
+        if (add == 0) continue;
         const Cand c = make(b, cl);
         if (c.nl == 0 || c.nl == N) continue;
         lq = fmaxf(lq, cand_q32(c));
@@ -398,8 +440,14 @@ __device__ Cand feature_best(const uint32_t* h, int B, int q, int f, const uint3
         for (int u = 0; u < bpl; ++u) {
             const int b = b0 + u;
             if (b >= B - 1) break;
+            uint32_t add = 0;
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k) cl[k] += h[b * KMAX + k];
+            for (int k = 0; k < KMAX; ++k) {
+                const uint32_t v = h[b * KMAX + k];
+                cl[k] += v;
+                add += v;
+            }
+            if (add == 0) continue;
             const Cand c = make(b, cl);
             if (c.nl == 0 || c.nl == N) continue;
             if (cand_q32(c) < floor32) continue;
@@ -621,6 +669,7 @@ void launch_split_small(const ForestDev& F, uint32_t first, uint32_t count, hipS
     if (!count) return;
     const dim3 grid((count + 3) / 4);
     switch (F.kmax) {
+        case 2: hipLaunchKernelGGL(k_split_small<2>, grid, dim3(256), 0, st, F, first, count); break;
         case 4: hipLaunchKernelGGL(k_split_small<4>, grid, dim3(256), 0, st, F, first, count); break;
         case 8: hipLaunchKernelGGL(k_split_small<8>, grid, dim3(256), 0, st, F, first, count); break;
         default:
@@ -634,6 +683,7 @@ void launch_hist_tile(const ForestDev& F, uint32_t n_items, int B, hipStream_t s
     const size_t lds = (size_t)32 * B * sizeof(uint32_t);  // FT * B * KMAX words, FT * KMAX = 32
     const dim3 grid(n_items);
     switch (F.kmax) {
+        case 2: hipLaunchKernelGGL(k_hist_tile<2>, grid, dim3(256), lds, st, F); break;
         case 4: hipLaunchKernelGGL(k_hist_tile<4>, grid, dim3(256), lds, st, F); break;
         case 8: hipLaunchKernelGGL(k_hist_tile<8>, grid, dim3(256), lds, st, F); break;
         default: hipLaunchKernelGGL(k_hist_tile<16>, grid, dim3(256), lds, st, F); break;
@@ -645,6 +695,7 @@ void launch_split_finalize(const ForestDev& F, uint32_t slot_base, uint32_t n_sl
     if (!n_slots) return;
     const dim3 grid(n_slots);
     switch (F.kmax) {
+        case 2: hipLaunchKernelGGL(k_split_finalize<2>, grid, dim3(256), 0, st, F, slot_base); break;
         case 4: hipLaunchKernelGGL(k_split_finalize<4>, grid, dim3(256), 0, st, F, slot_base); break;
         case 8: hipLaunchKernelGGL(k_split_finalize<8>, grid, dim3(256), 0, st, F, slot_base); break;
         default:
