@@ -272,7 +272,9 @@ struct Item {
     uint32_t node, slot, tile, pad;
 };
 
-// Per-level append counters (reset before each level).
+// Per-level counters: the lists of tree level d (small nodes, large-node
+// slots, (node, tile) items) are counted in ctrs[d]; they are zeroed once per
+// iteration.
 struct LevelCtr {
     uint32_t unused;
     uint32_t n_items;   // (large node, feature tile) items
@@ -306,7 +308,9 @@ struct ForestDev {
     const uint32_t* small_in;
     Item* items_out;
     uint32_t* small_out;
-    LevelCtr* ctr;
+    LevelCtr* ctr;        // counters the current launch appends to (set per kernel)
+    LevelCtr* ctrs;       // [levels + 1]: ctrs[d] counts the lists of tree level d
+    uint32_t n_roots;     // trees of the iteration (= root nodes [0, n_roots))
     uint64_t* alg_bytes;  // [2][64] algorithmic bytes (large, small), nullable; the
                           // 64 words per kernel spread the atomics
     uint32_t node_cap, item_cap, slot_cap, small_cap;

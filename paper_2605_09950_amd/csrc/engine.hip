@@ -1,8 +1,10 @@
 // engine.hip -- host orchestration of the Boruta loop and the C ABI of
 // libboruta.so.  Every step of an iteration runs in the HIP kernels of
 // k_prep.hip, k_forest.hip and k_importance.hip; this file plans device
-// memory, launches them in order on one stream and reads back the few
-// counters the host needs to size the next launch.
+// memory and launches them in order on one stream.  An iteration is a fixed
+// launch sequence sized by plan-time bounds (the kernels read their real
+// work counts on the device), followed by one read-back of the job records
+// and level counters.
 #include <algorithm>
 #include <climits>
 #include <memory>
@@ -24,18 +26,17 @@ void launch_binning(const float*, int64_t, int64_t, int, uint8_t*, int64_t, uint
                     hipStream_t);
 void launch_thresholds(int32_t, int64_t, uint64_t, int32_t, int32_t*, int32_t*, hipStream_t);
 void launch_active(JobDev*, int, int, hipStream_t);
-void launch_shadow(JobDev*, const int32_t*, int, int64_t, int, hipStream_t);
+void launch_shadow(JobDev*, int, int64_t, int, hipStream_t);
 void launch_boot_draw(JobDev*, const TreeDev*, int, int64_t, hipStream_t);
 void launch_fill_u32(uint32_t*, size_t, uint32_t, hipStream_t);
 // k_forest.hip
 void launch_boot_compact(const ForestDev&, uint32_t, hipStream_t);
-void launch_split_small(const ForestDev&, uint32_t, uint32_t, hipStream_t);
-void launch_hist_tile(const ForestDev&, uint32_t, int, hipStream_t);
-void launch_split_finalize(const ForestDev&, uint32_t, uint32_t, hipStream_t);
+void launch_split_small(const ForestDev&, int, uint32_t, uint32_t, uint32_t, hipStream_t);
+void launch_hist_tile(const ForestDev&, int, uint32_t, uint32_t, uint32_t, int, hipStream_t);
+void launch_split_finalize(const ForestDev&, int, uint32_t, uint32_t, uint32_t, hipStream_t);
 // k_importance.hip
 void launch_tree_totals(JobDev*, const TreeDev*, int, uint64_t*, hipStream_t);
-void launch_treeimp(JobDev*, const int32_t*, int, const int32_t*, const uint64_t*, int,
-                    hipStream_t);
+void launch_treeimp(JobDev*, int, const int32_t*, const uint64_t*, int, hipStream_t);
 void launch_permut(JobDev*, const TreeDev*, const NodeDev*, int, int64_t, int, hipStream_t);
 void launch_hits_decide(JobDev*, int, hipStream_t);
 void launch_copy(void*, const void*, size_t, hipStream_t);
@@ -138,8 +139,8 @@ struct JobPlan {
 
 struct Plan {
     std::vector<JobPlan> jp;
-    size_t keys, jobs, trees, live, tree_base, flags, nodes, cls, ngain, items0, items1, small0,
-        small1, cand, slot0, slot1, ctr, alg, tot;
+    size_t keys, jobs, trees, tree_base, flags, nodes, cls, ngain, items0, items1, small0,
+        small1, cand, slot0, slot1, ctrs, alg, tot;
     uint32_t node_cap = 0, item_cap = 0, slot_cap = 0, small_cap = 0;
     int kmax = 4, ft = 8, max_tiles = 1, max_sha = 1, max_pw = 1, max_D = 1, T_total = 0;
     int64_t max_n = 0;
@@ -214,7 +215,6 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     pl.small_cap = (uint32_t)small_cap;
     pl.jobs = r.take(specs.size() * sizeof(JobDev));
     pl.trees = r.take((size_t)pl.T_total * sizeof(TreeDev));
-    pl.live = r.take(specs.size() * 4);
     pl.tree_base = r.take(specs.size() * 4);
     pl.flags = r.take(64);
     pl.nodes = r.take((size_t)pl.node_cap * sizeof(NodeDev));
@@ -227,7 +227,8 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     pl.cand = r.take((size_t)pl.slot_cap * pl.max_tiles * sizeof(Cand));
     pl.slot0 = r.take((size_t)pl.slot_cap * 4);
     pl.slot1 = r.take((size_t)pl.slot_cap * 4);
-    pl.ctr = r.take(sizeof(LevelCtr));
+    // level d < max_D reads ctrs[d] and appends to ctrs[d + 1]
+    pl.ctrs = r.take((size_t)(pl.max_D + 2) * sizeof(LevelCtr));
     pl.alg = r.take(128 * 8);
     pl.tot = r.take((size_t)pl.T_total * 8);
     pl.total = r.total + 256;
@@ -242,31 +243,59 @@ struct Out {
     int32_t n_iter = 0;
 };
 
-struct EventTimer {
-    hipEvent_t a = nullptr, b = nullptr;
-    bool on = false;
-    explicit EventTimer(bool enable) : on(enable) {
-        if (on) {
-            HIPC(hipEventCreate(&a));
-            HIPC(hipEventCreate(&b));
+// HIP event pairs around launches, recorded without host waits and read
+// after the synchronisation that ends the iteration.
+class KernelClock {
+public:
+    explicit KernelClock(bool on) : on_(on) {}
+    ~KernelClock() {
+        for (hipEvent_t e : pool_) (void)hipEventDestroy(e);
+    }
+    KernelClock(const KernelClock&) = delete;
+    KernelClock& operator=(const KernelClock&) = delete;
+    // Returns the handle that end() takes.
+    size_t begin(boruta_kernel_stat* k, hipStream_t st) {
+        if (!on_) return 0;
+        Rec r;
+        r.k = k;
+        r.a = take();
+        r.b = take();
+        HIPC(hipEventRecord(r.a, st));
+        recs_.push_back(r);
+        return recs_.size() - 1;
+    }
+    void end(size_t h, hipStream_t st) {
+        if (on_) HIPC(hipEventRecord(recs_[h].b, st));
+    }
+    // Every recorded event must have completed (the stream was synchronised).
+    void collect() {
+        for (const Rec& r : recs_) {
+            float ms = 0.f;
+            HIPC(hipEventElapsedTime(&ms, r.a, r.b));
+            r.k->ms += ms;
+            r.k->launches += 1;
         }
+        recs_.clear();
+        next_ = 0;
     }
-    ~EventTimer() {
-        if (a) (void)hipEventDestroy(a);
-        if (b) (void)hipEventDestroy(b);
+
+private:
+    struct Rec {
+        boruta_kernel_stat* k;
+        hipEvent_t a, b;
+    };
+    hipEvent_t take() {
+        if (next_ == pool_.size()) {
+            hipEvent_t e = nullptr;
+            HIPC(hipEventCreate(&e));
+            pool_.push_back(e);
+        }
+        return pool_[next_++];
     }
-    void start(hipStream_t st) {
-        if (on) HIPC(hipEventRecord(a, st));
-    }
-    // stop and return elapsed ms (synchronises on the stop event)
-    double stop(hipStream_t st) {
-        if (!on) return 0.0;
-        HIPC(hipEventRecord(b, st));
-        HIPC(hipEventSynchronize(b));
-        float ms = 0.f;
-        HIPC(hipEventElapsedTime(&ms, a, b));
-        return ms;
-    }
+    bool on_;
+    std::vector<hipEvent_t> pool_;
+    size_t next_ = 0;
+    std::vector<Rec> recs_;
 };
 
 // ---------------------------------------------------------------------------
@@ -274,7 +303,7 @@ class Engine {
 public:
     Engine(const std::vector<Spec>& specs, const Opts& o, bool dev_inputs, char* base,
            hipStream_t st)
-        : S(specs), O(o), dev_in(dev_inputs), base(base), st(st) {
+        : S(specs), O(o), dev_in(dev_inputs), base(base), st(st), clock(o.stats != nullptr) {
         pl = make_plan(specs, o, dev_inputs);
     }
 
@@ -305,9 +334,9 @@ public:
 
 private:
     void iteration(const std::vector<int>& live);
-    void grow_level_plain(ForestDev F, uint32_t n_items, uint32_t n_small);
-    void emit_trace(const std::vector<int>& live, const std::vector<int>& tree_base,
-                    uint32_t n_nodes);
+    ForestDev forest() const;
+    void grow_level_plain(const ForestDev& F, int level);
+    void emit_trace(const std::vector<int>& live, uint32_t n_nodes);
 
     std::vector<Spec> S;
     Opts O;
@@ -315,7 +344,10 @@ private:
     char* base;
     hipStream_t st;
     Plan pl;
-    std::vector<JobDev> hj;  // host mirror of the job records
+    KernelClock clock;
+    std::vector<JobDev> hj;       // host mirror of the job records
+    std::vector<int> tree_base;   // first tree of each job in the static tree table
+    bool any_treeimp = false, any_permut = false;
 };
 
 void Engine::setup(std::vector<int>& status) {
@@ -392,77 +424,41 @@ void Engine::setup(std::vector<int>& status) {
         launch_fill_u32((uint32_t*)J.hits, (size_t)s.p, 0u, st);
         if (s.mode == 0)
             launch_fill_u32((uint32_t*)J.G, (size_t)s.T * jp.pw_cap * 2, 0u, st);
+        // bootstrap multiplicities: zero here, then cleared by their reader
+        launch_fill_u32(J.wbuf, (size_t)s.T * s.n, 0u, st);
         status[j] = BORUTA_OK;
     }
     for (int j = 0; j < nj; ++j)
         if (status[j] != BORUTA_OK) hj[j].live = 0;
+    // static tree table: the trees of every job in job order; the kernels
+    // skip the trees of jobs that are no longer live
+    std::vector<TreeDev> trees;
+    tree_base.assign(nj, 0);
+    for (int j = 0; j < nj; ++j) {
+        tree_base[j] = (int)trees.size();
+        for (int tau = 0; tau < S[j].T; ++tau) trees.push_back(TreeDev{j, tau});
+        any_treeimp |= S[j].mode == 0;
+        any_permut |= S[j].mode == 1;
+    }
+    h2d(at<TreeDev>(pl.trees), trees.data(), trees.size() * sizeof(TreeDev));
+    h2d(at<int32_t>(pl.tree_base), tree_base.data(), tree_base.size() * 4);
     launch_fill_u32(at<uint32_t>(pl.alg), 256, 0u, st);
     h2d(at<JobDev>(pl.jobs), hj.data(), hj.size() * sizeof(JobDev));
     HIPC(hipStreamSynchronize(st));
 }
 
-void Engine::grow_level_plain(ForestDev F, uint32_t n_items, uint32_t n_small) {
-    // One launch (or, for a large node, one histogram launch over its tiles
-    // and one finalize launch) per node: the node lists are read back and
-    // each node is its own launch.
-    std::vector<Item> items(n_items);
-    if (n_items) d2h(items.data(), F.items_in, n_items * sizeof(Item));
-    for (uint32_t i = 0; i < n_small; ++i) launch_split_small(F, i, 1, st);
-    const Item* item_base = F.items_in;
-    for (uint32_t a = 0; a < n_items;) {
-        uint32_t b = a + 1;
-        while (b < n_items && items[b].node == items[a].node) ++b;
-        F.items_in = item_base + a;
-        launch_hist_tile(F, b - a, O.B, st);
-        launch_split_finalize(F, items[a].slot, 1, st);
-        a = b;
-    }
-}
-
-void Engine::iteration(const std::vector<int>& live) {
-    const int nj = (int)S.size();
-    // trees of the live jobs, in job order
-    std::vector<TreeDev> trees;
-    std::vector<int> tree_base;
-    for (int j : live) {
-        tree_base.push_back((int)trees.size());
-        for (int tau = 0; tau < S[j].T; ++tau) trees.push_back(TreeDev{j, tau});
-    }
-    const int n_trees = (int)trees.size();
-    const int n_live = (int)live.size();
-    h2d(at<TreeDev>(pl.trees), trees.data(), trees.size() * sizeof(TreeDev));
-    h2d(at<int32_t>(pl.live), live.data(), live.size() * 4);
-    h2d(at<int32_t>(pl.tree_base), tree_base.data(), tree_base.size() * 4);
-    JobDev* djobs = at<JobDev>(pl.jobs);
-    launch_active(djobs, nj, pl.ft, st);
-    d2h(hj.data(), djobs, hj.size() * sizeof(JobDev));
-    int64_t max_n = 0;
-    int max_sha = 1, max_pw = 1, max_D = 1;
-    bool any_permut = false;
-    for (int j : live) {
-        const JobDev& J = hj[j];
-        max_n = std::max<int64_t>(max_n, J.n);
-        max_sha = std::max(max_sha, J.n_sha);
-        max_pw = std::max(max_pw, J.p_w);
-        max_D = std::max(max_D, J.D);
-        any_permut |= J.mode == 1;
-        launch_fill_u32(J.wbuf, (size_t)J.T * J.n, 0u, st);
-        if (J.mode == 1) launch_fill_u32((uint32_t*)J.imp, (size_t)J.p_w * 2, 0u, st);
-    }
-    launch_shadow(djobs, at<int32_t>(pl.live), n_live, max_n, max_sha, st);
-    launch_boot_draw(djobs, at<TreeDev>(pl.trees), n_trees, max_n, st);
-
+ForestDev Engine::forest() const {
     ForestDev F;
-    F.jobs = djobs;
+    std::memset(&F, 0, sizeof(F));
+    F.jobs = at<JobDev>(pl.jobs);
     F.trees = at<TreeDev>(pl.trees);
     F.nodes = at<NodeDev>(pl.nodes);
     F.cls = at<uint32_t>(pl.cls);
     F.ngain = at<uint64_t>(pl.ngain);
     F.cand = at<Cand>(pl.cand);
-    uint32_t* slots[2] = {at<uint32_t>(pl.slot0), at<uint32_t>(pl.slot1)};
-    Item* items[2] = {at<Item>(pl.items0), at<Item>(pl.items1)};
-    uint32_t* small[2] = {at<uint32_t>(pl.small0), at<uint32_t>(pl.small1)};
-    F.ctr = at<LevelCtr>(pl.ctr);
+    F.ctrs = at<LevelCtr>(pl.ctrs);
+    F.ctr = F.ctrs;
+    F.n_roots = (uint32_t)pl.T_total;
     F.alg_bytes = O.stats ? at<uint64_t>(pl.alg) : nullptr;
     F.node_cap = pl.node_cap;
     F.item_cap = pl.item_cap;
@@ -474,25 +470,66 @@ void Engine::iteration(const std::vector<int>& live) {
     F.split_rank = O.split_rank;
     // the wave path packs class counters in 16-bit fields (8-bit for 3-4 classes)
     F.small_ncap = pl.kmax == 4 ? 256u : 65536u;
-    F.pad = 0;
-    F.items_in = items[1];
-    F.small_in = small[1];
-    F.slot_node_in = slots[1];
+    return F;
+}
+
+void Engine::grow_level_plain(const ForestDev& F, int level) {
+    // One launch (or, for a large node, one histogram launch over its tiles
+    // and one finalize launch) per node: the level's counters and node lists
+    // are read back and each node is its own launch.
+    LevelCtr c;
+    d2h(&c, F.ctrs + level, sizeof(c));
+    if (c.overflow) return;  // reported after the iteration
+    std::vector<Item> items(c.n_items);
+    if (c.n_items) d2h(items.data(), F.items_in, c.n_items * sizeof(Item));
+    for (uint32_t i = 0; i < c.n_small; ++i) launch_split_small(F, level, i, 1, 1, st);
+    for (uint32_t a = 0; a < c.n_items;) {
+        uint32_t b = a + 1;
+        while (b < c.n_items && items[b].node == items[a].node) ++b;
+        launch_hist_tile(F, level, a, b - a, b - a, O.B, st);
+        launch_split_finalize(F, level, items[a].slot, 1, 1, st);
+        a = b;
+    }
+}
+
+namespace {
+// Grid of a grid-stride level kernel: enough workgroups to fill the 256 CUs
+// several times over, never more than the level's capacity can use.
+uint32_t level_grid(uint64_t cap_units, uint32_t per_wg, uint32_t limit) {
+    const uint64_t g = (cap_units + per_wg - 1) / per_wg;
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, limit));
+}
+constexpr uint32_t kAll = 0xFFFFFFFFu;  // level kernels: work count read on the device
+}  // namespace
+
+void Engine::iteration(const std::vector<int>& live) {
+    const int nj = (int)S.size();
+    const uint32_t n_trees = (uint32_t)pl.T_total;
+    JobDev* djobs = at<JobDev>(pl.jobs);
+    TreeDev* dtrees = at<TreeDev>(pl.trees);
+    boruta_stats* stats = O.stats;
+    boruta_kernel_stat whole{};
+    const size_t h_whole = clock.begin(&whole, st);
+    launch_active(djobs, nj, pl.ft, st);
+    launch_shadow(djobs, nj, pl.max_n, pl.max_sha, st);
+    launch_boot_draw(djobs, dtrees, (int)n_trees, pl.max_n, st);
+
+    ForestDev F = forest();
+    // levels 0 .. max_D - 1 search splits; nodes of depth max_D are leaves
+    const int n_levels = pl.max_D;
+    launch_fill_u32((uint32_t*)F.ctrs, (size_t)(n_levels + 1) * sizeof(LevelCtr) / 4, 0u, st);
+    uint32_t* slots[2] = {at<uint32_t>(pl.slot0), at<uint32_t>(pl.slot1)};
+    Item* items[2] = {at<Item>(pl.items0), at<Item>(pl.items1)};
+    uint32_t* small[2] = {at<uint32_t>(pl.small0), at<uint32_t>(pl.small1)};
+    // the roots go to the level-0 lists (parity 0)
     F.items_out = items[0];
     F.small_out = small[0];
     F.slot_node_out = slots[0];
-    F.next_base = (uint32_t)n_trees;
-    F.parity = 0;
-    if ((uint32_t)n_trees > pl.node_cap) throw Error(BORUTA_E_DEVICE, "node pool too small");
-    launch_fill_u32((uint32_t*)F.ctr, sizeof(LevelCtr) / 4, 0u, st);
-    launch_boot_compact(F, (uint32_t)n_trees, st);
-    LevelCtr c;
-    d2h(&c, F.ctr, sizeof(c));
-    uint32_t n_nodes = (uint32_t)n_trees;
-    uint32_t work_items = c.n_items, work_small = c.n_small, work_slots = c.n_slots;
-    if (c.overflow) throw Error(BORUTA_E_DEVICE, "internal capacity exceeded (roots)");
-    EventTimer tl(O.stats != nullptr), ts(O.stats != nullptr), tf(O.stats != nullptr);
-    for (int d = 0; work_items || work_small; ++d) {
+    launch_boot_compact(F, n_trees, st);
+    const uint32_t g_small = level_grid(pl.small_cap, 4, 2048);
+    const uint32_t g_tile = level_grid(pl.item_cap, 1, 2560);
+    const uint32_t g_fin = level_grid(pl.slot_cap, 1, 1024);
+    for (int d = 0; d < n_levels; ++d) {
         // lists, slots and row records of level d are read from parity d & 1
         // and the children of level d go to the other parity
         F.items_in = items[d & 1];
@@ -501,73 +538,59 @@ void Engine::iteration(const std::vector<int>& live) {
         F.items_out = items[(d + 1) & 1];
         F.small_out = small[(d + 1) & 1];
         F.slot_node_out = slots[(d + 1) & 1];
-        F.next_base = n_nodes;
-        F.n_small_cur = work_small;
         F.parity = d & 1;
-        // children of this level: a pair per searched node, small nodes first
-        const uint64_t level_end = (uint64_t)n_nodes + 2ull * (work_small + work_slots);
-        if (level_end > pl.node_cap) throw Error(BORUTA_E_DEVICE, "node pool too small");
-        launch_fill_u32((uint32_t*)F.ctr, sizeof(LevelCtr) / 4, 0u, st);
         if (O.form == BORUTA_FORM_PLAIN) {
-            grow_level_plain(F, work_items, work_small);
-        } else {
-            if (work_small) {
-                ts.start(st);
-                launch_split_small(F, 0, work_small, st);
-                if (O.stats) {
-                    O.stats->hist_small.ms += ts.stop(st);
-                    O.stats->hist_small.launches += 1;
-                }
-            }
-            if (work_items) {
-                tl.start(st);
-                launch_hist_tile(F, work_items, O.B, st);
-                if (O.stats) {
-                    O.stats->hist_large.ms += tl.stop(st);
-                    O.stats->hist_large.launches += 1;
-                }
-                tf.start(st);
-                launch_split_finalize(F, 0, work_slots, st);
-                if (O.stats) {
-                    O.stats->finalize.ms += tf.stop(st);
-                    O.stats->finalize.launches += 1;
-                }
-            }
+            grow_level_plain(F, d);
+            continue;
         }
-        d2h(&c, F.ctr, sizeof(c));
-        if (c.overflow) throw Error(BORUTA_E_DEVICE, "internal capacity exceeded (tree level)");
-        n_nodes = (uint32_t)level_end;
-        work_items = c.n_items;
-        work_small = c.n_small;
-        work_slots = c.n_slots;
+        size_t h = clock.begin(stats ? &stats->hist_small : nullptr, st);
+        launch_split_small(F, d, 0, kAll, g_small, st);
+        clock.end(h, st);
+        h = clock.begin(stats ? &stats->hist_large : nullptr, st);
+        launch_hist_tile(F, d, 0, kAll, g_tile, O.B, st);
+        clock.end(h, st);
+        h = clock.begin(stats ? &stats->finalize : nullptr, st);
+        launch_split_finalize(F, d, 0, kAll, g_fin, st);
+        clock.end(h, st);
     }
-    if (O.stats) O.stats->nodes += n_nodes;
 
     // importance
-    bool any_treeimp = false;
-    for (int j : live) any_treeimp |= hj[j].mode == 0;
     if (any_treeimp) {
-        launch_tree_totals(djobs, at<TreeDev>(pl.trees), n_trees, at<uint64_t>(pl.tot), st);
-        launch_treeimp(djobs, at<int32_t>(pl.live), n_live, at<int32_t>(pl.tree_base),
-                       at<uint64_t>(pl.tot), max_pw, st);
+        launch_tree_totals(djobs, dtrees, (int)n_trees, at<uint64_t>(pl.tot), st);
+        launch_treeimp(djobs, nj, at<int32_t>(pl.tree_base), at<uint64_t>(pl.tot), pl.max_pw,
+                       st);
     }
     if (any_permut) {
-        EventTimer tp(O.stats != nullptr);
-        tp.start(st);
-        launch_permut(djobs, at<TreeDev>(pl.trees), F.nodes, n_trees, max_n, max_D, st);
-        if (O.stats) {
-            O.stats->permut.ms += tp.stop(st);
-            O.stats->permut.launches += 1;
-        }
+        const size_t h = clock.begin(stats ? &stats->permut : nullptr, st);
+        launch_permut(djobs, dtrees, F.nodes, (int)n_trees, pl.max_n, pl.max_D, st);
+        clock.end(h, st);
     }
     launch_hits_decide(djobs, nj, st);
+    clock.end(h_whole, st);
+    std::vector<LevelCtr> c(n_levels + 1);
+    HIPC(hipMemcpyAsync(c.data(), F.ctrs, c.size() * sizeof(LevelCtr), hipMemcpyDeviceToHost,
+                        st));
     d2h(hj.data(), djobs, hj.size() * sizeof(JobDev));
-    if (O.trace) emit_trace(live, tree_base, n_nodes);
-    if (O.stats) O.stats->iterations += n_live;
+    clock.collect();
+    uint32_t overflow = 0;
+    uint64_t n_nodes = n_trees;
+    for (int d = 0; d <= n_levels; ++d) {
+        overflow |= c[d].overflow;
+        if (d < n_levels) n_nodes += 2ull * (c[d].n_small + c[d].n_slots);
+    }
+    if (overflow)
+        throw Error(BORUTA_E_DEVICE,
+                    "internal capacity exceeded (flags " + std::to_string(overflow) + ")");
+    if (n_nodes > pl.node_cap) throw Error(BORUTA_E_DEVICE, "node pool too small");
+    if (stats) {
+        stats->iter_ms += whole.ms;
+        stats->nodes += (int64_t)n_nodes;
+        stats->iterations += (int64_t)live.size();
+    }
+    if (O.trace) emit_trace(live, (uint32_t)n_nodes);
 }
 
-void Engine::emit_trace(const std::vector<int>& live, const std::vector<int>& tree_base,
-                        uint32_t n_nodes) {
+void Engine::emit_trace(const std::vector<int>& live, uint32_t n_nodes) {
     // Called after the decision kernel: importances and trees are those of
     // this iteration, hits and states already include its decision.
     std::vector<NodeDev> nodes(n_nodes);
@@ -585,7 +608,7 @@ void Engine::emit_trace(const std::vector<int>& live, const std::vector<int>& tr
         d2h(hits.data(), J.hits, (size_t)J.p * 4);
         d2h(state.data(), J.state, (size_t)J.p);
         d2h(tstat.data(), J.tstat, tstat.size() * 4);
-        const int g0 = tree_base[li];
+        const int g0 = tree_base[j];
         std::vector<std::vector<uint32_t>> idx(J.T);
         for (uint32_t i = 0; i < n_nodes; ++i) {
             if (nodes[i].tree == 0xFFFFFFFFu) continue;  // unused child pair of a leaf
@@ -632,10 +655,7 @@ int Engine::step() {
     for (int j = 0; j < (int)S.size(); ++j)
         if (hj[j].live) live.push_back(j);
     if (live.empty()) return 0;
-    EventTimer ti(O.stats != nullptr);
-    ti.start(st);
     iteration(live);
-    if (O.stats) O.stats->iter_ms += ti.stop(st);
     int n = 0;
     for (const JobDev& J : hj) n += J.live != 0;
     return n;

@@ -159,6 +159,39 @@ __device__ __forceinline__ Cand wave_best_total_fp32(const Cand& c, float q32) {
 
 enum : int { kLeaf = 0, kSmall = 1, kLarge = 2 };
 
+// Children of tree level d start at n_roots + 2 * (searched nodes of levels
+// 0..d-1): every searched node owns a pair of child slots.
+__device__ __forceinline__ uint32_t level_next_base(const ForestDev& F, int level) {
+    uint64_t b = F.n_roots;
+    for (int e = 0; e < level; ++e) b += 2ull * ((uint64_t)F.ctrs[e].n_small + F.ctrs[e].n_slots);
+    return b < F.node_cap ? (uint32_t)b : F.node_cap;  // past the pool: splits flag overflow
+}
+
+// Work lists of tree level `level` as counted on the device; empty once a
+// capacity overflow has been flagged for the level (the host reports it).
+__device__ __forceinline__ uint32_t level_small(const ForestDev& F, int level) {
+    const LevelCtr& c = F.ctrs[level];
+    return c.overflow ? 0u : min(c.n_small, F.small_cap);
+}
+__device__ __forceinline__ uint32_t level_items(const ForestDev& F, int level) {
+    const LevelCtr& c = F.ctrs[level];
+    return c.overflow ? 0u : min(c.n_items, F.item_cap);
+}
+__device__ __forceinline__ uint32_t level_slots(const ForestDev& F, int level) {
+    const LevelCtr& c = F.ctrs[level];
+    return c.overflow ? 0u : min(c.n_slots, F.slot_cap);
+}
+
+// The launch-local view of the forest for tree level `level`: appends go to
+// the next level's counters.
+__device__ __forceinline__ ForestDev level_view(const ForestDev& F, int level) {
+    ForestDev L = F;
+    L.ctr = F.ctrs + level + 1;
+    L.next_base = level_next_base(F, level);
+    L.n_small_cur = F.ctrs[level].n_small;
+    return L;
+}
+
 // Write a new node record -- a leaf until a split search turns it into a
 // split -- and return what it needs next: nothing (final leaf: maximum depth,
 // fewer than two distinct rows or a single class), the wave path (<= 64

@@ -25,16 +25,23 @@ namespace boruta {
 
 // ---------------------------------------------------------------------------
 // Per tree: compact the in-bag rows (multiplicity > 0, ascending) into row
-// records and the out-of-bag rows into a list; create the root node.
-__global__ __launch_bounds__(1024) void k_boot_compact(ForestDev F) {
+// records and the out-of-bag rows into a list; create the root node.  The
+// multiplicities are cleared behind the read.
+__global__ __launch_bounds__(1024) void k_boot_compact(ForestDev F0) {
     __shared__ uint32_t s_win[16], s_wout[16];
     __shared__ uint32_t s_cls[16];
     __shared__ uint32_t s_base_in, s_base_out;
+    ForestDev F = F0;
+    F.ctr = F0.ctrs;  // the roots form the lists of level 0
     const uint32_t g = blockIdx.x;
     const TreeDev tr = F.trees[g];
     JobDev& J = F.jobs[tr.job];
+    if (!J.live) {  // finished job: its tree slots stay empty
+        if (threadIdx.x == 0) F.nodes[g].tree = 0xFFFFFFFFu;
+        return;
+    }
     const uint32_t n = (uint32_t)J.n;
-    const uint32_t* w = J.wbuf + (size_t)tr.tau * n;
+    uint32_t* w = J.wbuf + (size_t)tr.tau * n;
     uint64_t* recs = J.rec[0] + (size_t)tr.tau * n;
     uint32_t* oob = J.oob + (size_t)tr.tau * n;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -48,6 +55,7 @@ __global__ __launch_bounds__(1024) void k_boot_compact(ForestDev F) {
     for (uint32_t base = 0; base < n; base += 1024) {
         const uint32_t i = base + tid;
         const uint32_t wi = i < n ? w[i] : 0u;
+        if (i < n) w[i] = 0;  // multiplicities start from zero next iteration
         const bool inb = i < n && wi > 0, isoob = i < n && wi == 0;
         const uint64_t mi = __ballot(inb), mo = __ballot(isoob);
         if (lane == 0) {
@@ -282,13 +290,22 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out) {
 
 // Four nodes per workgroup (one per wave); the children's list positions are
 // reserved with one atomic per list for the whole workgroup.
+// The small nodes of tree level `level`: all of them (count from the level's
+// counters, grid-stride) or, with an explicit count, list entries
+// [first, first + count).
 template <int KMAX>
-__global__ __launch_bounds__(256) void k_split_small(ForestDev F, uint32_t first,
+__global__ __launch_bounds__(256) void k_split_small(ForestDev F0, int level, uint32_t first,
                                                      uint32_t count) {
     __shared__ uint32_t s_ns[4], s_nl[4], s_ni[4], s_base[3];
     __shared__ unsigned long long s_alg[4];
+    const ForestDev F = level_view(F0, level);
+    if (count == 0xFFFFFFFFu) {
+        first = 0;
+        count = level_small(F0, level);
+    }
     const int lane = threadIdx.x & 63, wave = (int)uniform(threadIdx.x >> 6);
-    const uint32_t li = blockIdx.x * 4u + wave;
+    for (uint32_t base = blockIdx.x * 4u; base < count; base += gridDim.x * 4u) {
+    const uint32_t li = base + wave;
     SmallOut o;
     o.kinds[0] = o.kinds[1] = kLeaf;
     o.child = 0;
@@ -328,6 +345,8 @@ __global__ __launch_bounds__(256) void k_split_small(ForestDev F, uint32_t first
                 pi += o.ntiles;
             }
         }
+    }
+    __syncthreads();  // the shared counts are reused by the next batch
     }
 }
 
@@ -462,13 +481,20 @@ __device__ Cand feature_best(const uint32_t* h, int B, int q, int f, const uint3
 // Large nodes, phase 1: one workgroup per (node, feature tile).  FT columns
 // per tile keep the LDS histogram at FT * 256 * KMAX * 4 = 32 KB.
 template <int KMAX>
-__global__ __launch_bounds__(256) void k_hist_tile(ForestDev F) {
+__global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint32_t first,
+                                                   uint32_t count) {
     constexpr int FT = 32 / KMAX;
     extern __shared__ uint32_t hist[];  // [FT][B][KMAX]
     __shared__ const uint8_t* s_col[FT];
     __shared__ int s_feat[FT];
     __shared__ Cand s_fbest[FT];
-    const Item it = F.items_in[blockIdx.x];
+    if (count == 0xFFFFFFFFu) {
+        first = 0;
+        count = level_items(F, level);
+    }
+    for (uint32_t k = blockIdx.x; k < count; k += gridDim.x) {
+    const uint32_t item = first + k;
+    const Item it = F.items_in[item];
     const NodeDev nd = F.nodes[it.node];
     const TreeDev tr = F.trees[nd.tree];
     const JobDev& J = F.jobs[tr.job];
@@ -529,8 +555,10 @@ __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F) {
             if (s_fbest[q].nl != 0 && (tb.nl == 0 || cand_better(s_fbest[q], tb))) tb = s_fbest[q];
         F.cand[(size_t)it.slot * F.max_tiles + it.tile] = tb;
         if (F.alg_bytes)
-            atomicAdd((unsigned long long*)&F.alg_bytes[blockIdx.x & 63],
+            atomicAdd((unsigned long long*)&F.alg_bytes[item & 63],
                       (unsigned long long)len * (unsigned long long)(nf + (it.tile == 0 ? 6 : 0)));
+    }
+    __syncthreads();  // LDS is reused by the next item
     }
 }
 
@@ -539,13 +567,20 @@ __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F) {
 // first of equal candidates keeps the earliest draw); a strictly positive
 // decrease splits the node and its rows are partitioned stably, left first.
 template <int KMAX>
-__global__ __launch_bounds__(256) void k_split_finalize(ForestDev F, uint32_t slot_base) {
+__global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level, uint32_t first,
+                                                        uint32_t count) {
     __shared__ Cand s_best;
     __shared__ int s_split;
     __shared__ uint32_t s_cl[KMAX];
     __shared__ uint32_t s_wcnt[4];
     __shared__ uint32_t s_run;
-    const uint32_t slot = slot_base + blockIdx.x;
+    const ForestDev F = level_view(F0, level);
+    if (count == 0xFFFFFFFFu) {
+        first = 0;
+        count = level_slots(F0, level);
+    }
+    for (uint32_t k = blockIdx.x; k < count; k += gridDim.x) {
+    const uint32_t slot = first + k;
     const uint32_t id = F.slot_node_in[slot];
     const NodeDev nd = F.nodes[id];
     const TreeDev tr = F.trees[nd.tree];
@@ -575,7 +610,8 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F, uint32_t sl
     const uint32_t child = F.next_base + 2u * (F.n_small_cur + slot);
     if (!s_split) {  // stays the leaf it was created as
         if (tid == 0) mark_unused_pair(F, child);
-        return;
+        __syncthreads();
+        continue;
     }
     const Cand best = s_best;
     const uint8_t* col = ldg(J.colptr + best.f);
@@ -657,6 +693,8 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F, uint32_t sl
                    kinds);
         enqueue_nodes(F, J, child, kinds, 2);
     }
+    __syncthreads();  // shared state is reused by the next slot
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -665,42 +703,41 @@ void launch_boot_compact(const ForestDev& F, uint32_t n_trees, hipStream_t st) {
     hipLaunchKernelGGL(k_boot_compact, dim3(n_trees), dim3(1024), 0, st, F);
 }
 
-void launch_split_small(const ForestDev& F, uint32_t first, uint32_t count, hipStream_t st) {
+// count == 0xFFFFFFFF: the whole level, sized on the device (grid-stride).
+void launch_split_small(const ForestDev& F, int level, uint32_t first, uint32_t count,
+                        uint32_t grid_wg, hipStream_t st) {
     if (!count) return;
-    const dim3 grid((count + 3) / 4);
+    const dim3 grid(grid_wg);
     switch (F.kmax) {
-        case 2: hipLaunchKernelGGL(k_split_small<2>, grid, dim3(256), 0, st, F, first, count); break;
-        case 4: hipLaunchKernelGGL(k_split_small<4>, grid, dim3(256), 0, st, F, first, count); break;
-        case 8: hipLaunchKernelGGL(k_split_small<8>, grid, dim3(256), 0, st, F, first, count); break;
-        default:
-            hipLaunchKernelGGL(k_split_small<16>, grid, dim3(256), 0, st, F, first, count);
-            break;
+        case 2: hipLaunchKernelGGL(k_split_small<2>, grid, dim3(256), 0, st, F, level, first, count); break;
+        case 4: hipLaunchKernelGGL(k_split_small<4>, grid, dim3(256), 0, st, F, level, first, count); break;
+        case 8: hipLaunchKernelGGL(k_split_small<8>, grid, dim3(256), 0, st, F, level, first, count); break;
+        default: hipLaunchKernelGGL(k_split_small<16>, grid, dim3(256), 0, st, F, level, first, count); break;
     }
 }
 
-void launch_hist_tile(const ForestDev& F, uint32_t n_items, int B, hipStream_t st) {
-    if (!n_items) return;
+void launch_hist_tile(const ForestDev& F, int level, uint32_t first, uint32_t count,
+                      uint32_t grid_wg, int B, hipStream_t st) {
+    if (!count) return;
     const size_t lds = (size_t)32 * B * sizeof(uint32_t);  // FT * B * KMAX words, FT * KMAX = 32
-    const dim3 grid(n_items);
+    const dim3 grid(grid_wg);
     switch (F.kmax) {
-        case 2: hipLaunchKernelGGL(k_hist_tile<2>, grid, dim3(256), lds, st, F); break;
-        case 4: hipLaunchKernelGGL(k_hist_tile<4>, grid, dim3(256), lds, st, F); break;
-        case 8: hipLaunchKernelGGL(k_hist_tile<8>, grid, dim3(256), lds, st, F); break;
-        default: hipLaunchKernelGGL(k_hist_tile<16>, grid, dim3(256), lds, st, F); break;
+        case 2: hipLaunchKernelGGL(k_hist_tile<2>, grid, dim3(256), lds, st, F, level, first, count); break;
+        case 4: hipLaunchKernelGGL(k_hist_tile<4>, grid, dim3(256), lds, st, F, level, first, count); break;
+        case 8: hipLaunchKernelGGL(k_hist_tile<8>, grid, dim3(256), lds, st, F, level, first, count); break;
+        default: hipLaunchKernelGGL(k_hist_tile<16>, grid, dim3(256), lds, st, F, level, first, count); break;
     }
 }
 
-void launch_split_finalize(const ForestDev& F, uint32_t slot_base, uint32_t n_slots,
-                           hipStream_t st) {
-    if (!n_slots) return;
-    const dim3 grid(n_slots);
+void launch_split_finalize(const ForestDev& F, int level, uint32_t first, uint32_t count,
+                           uint32_t grid_wg, hipStream_t st) {
+    if (!count) return;
+    const dim3 grid(grid_wg);
     switch (F.kmax) {
-        case 2: hipLaunchKernelGGL(k_split_finalize<2>, grid, dim3(256), 0, st, F, slot_base); break;
-        case 4: hipLaunchKernelGGL(k_split_finalize<4>, grid, dim3(256), 0, st, F, slot_base); break;
-        case 8: hipLaunchKernelGGL(k_split_finalize<8>, grid, dim3(256), 0, st, F, slot_base); break;
-        default:
-            hipLaunchKernelGGL(k_split_finalize<16>, grid, dim3(256), 0, st, F, slot_base);
-            break;
+        case 2: hipLaunchKernelGGL(k_split_finalize<2>, grid, dim3(256), 0, st, F, level, first, count); break;
+        case 4: hipLaunchKernelGGL(k_split_finalize<4>, grid, dim3(256), 0, st, F, level, first, count); break;
+        case 8: hipLaunchKernelGGL(k_split_finalize<8>, grid, dim3(256), 0, st, F, level, first, count); break;
+        default: hipLaunchKernelGGL(k_split_finalize<16>, grid, dim3(256), 0, st, F, level, first, count); break;
     }
 }
 

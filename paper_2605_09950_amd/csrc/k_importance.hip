@@ -21,7 +21,7 @@ __global__ __launch_bounds__(256) void k_tree_totals(JobDev* jobs, const TreeDev
     __shared__ unsigned long long s[4];
     const TreeDev tr = trees[blockIdx.x];
     const JobDev& J = jobs[tr.job];
-    if (J.mode != 0) return;  // Permut job of a mixed batch: no G
+    if (!J.live || J.mode != 0) return;  // finished job, or Permut job of a mixed batch
     const uint64_t* G = J.G + (size_t)tr.tau * J.pw_cap;
     unsigned long long v = 0;
     for (int f = threadIdx.x; f < J.p_w; f += 256) v += G[f];
@@ -34,11 +34,11 @@ __global__ __launch_bounds__(256) void k_tree_totals(JobDev* jobs, const TreeDev
 
 // Per (column, job): I_f = sum over trees of floor(2^44 G[tree][f] / total).
 // G is cleared behind the read, ready for the next iteration.
-__global__ __launch_bounds__(256) void k_treeimp(JobDev* jobs, const int32_t* live,
-                                                 const int32_t* tree_base, const uint64_t* tot) {
-    JobDev& J = jobs[live[blockIdx.y]];
+__global__ __launch_bounds__(256) void k_treeimp(JobDev* jobs, const int32_t* tree_base,
+                                                 const uint64_t* tot) {
+    JobDev& J = jobs[blockIdx.y];
     const int f = blockIdx.x * 256 + threadIdx.x;
-    if (J.mode != 0 || f >= J.p_w) return;
+    if (!J.live || J.mode != 0 || f >= J.p_w) return;
     const int g0 = tree_base[blockIdx.y];
     int64_t s = 0;
     constexpr int kU = 8;  // trees per step: independent loads in flight
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
     const uint32_t g = blockIdx.y;
     const TreeDev tr = trees[g];
     JobDev& J = jobs[tr.job];
-    if (J.mode != 1) return;  // TreeImp job of a mixed batch
+    if (!J.live || J.mode != 1) return;  // finished job, or TreeImp job of a mixed batch
     const int tid = threadIdx.x;
     const uint32_t m = (uint32_t)J.tstat[tr.tau * 4 + 1];
     const uint32_t j = blockIdx.x * 256u + tid;
@@ -203,10 +203,10 @@ void launch_tree_totals(JobDev* jobs, const TreeDev* trees, int n_trees, uint64_
     hipLaunchKernelGGL(k_tree_totals, dim3(n_trees), dim3(256), 0, st, jobs, trees, tot);
 }
 
-void launch_treeimp(JobDev* jobs, const int32_t* live, int n_live, const int32_t* tree_base,
-                    const uint64_t* tot, int max_pw, hipStream_t st) {
-    hipLaunchKernelGGL(k_treeimp, dim3((unsigned)((max_pw + 255) / 256), (unsigned)n_live),
-                       dim3(256), 0, st, jobs, live, tree_base, tot);
+void launch_treeimp(JobDev* jobs, int n_jobs, const int32_t* tree_base, const uint64_t* tot,
+                    int max_pw, hipStream_t st) {
+    hipLaunchKernelGGL(k_treeimp, dim3((unsigned)((max_pw + 255) / 256), (unsigned)n_jobs),
+                       dim3(256), 0, st, jobs, tree_base, tot);
 }
 
 void launch_permut(JobDev* jobs, const TreeDev* trees, const NodeDev* nodes, int n_trees,

@@ -240,7 +240,8 @@ __global__ void k_thresholds(int32_t max_iter, int64_t p, uint64_t alpha_m, int3
 
 // ---------------------------------------------------------------------------
 // Per iteration, one workgroup per job: t += 1, active columns (state >= 0,
-// ascending), shadow count (doubled while < 5), widened column map, mtry.
+// ascending), shadow count (doubled while < 5), widened column map, mtry;
+// Permut jobs also clear their drop accumulators.
 __global__ __launch_bounds__(256) void k_active(JobDev* jobs, int ft) {
     __shared__ uint32_t s_w[4];
     __shared__ uint32_t s_base;
@@ -267,6 +268,8 @@ __global__ __launch_bounds__(256) void k_active(JobDev* jobs, int ft) {
     int n_sha = p_cur;
     while (n_sha > 0 && n_sha < 5) n_sha *= 2;
     const int p_w = p_cur + n_sha;
+    if (J.mode == 1)  // Permut sums its drops into imp with atomics
+        for (int c = tid; c < p_w; c += 256) J.imp[c] = 0;
     for (int c = tid; c < p_w; c += 256) {
         if (c < p_cur) {
             J.colptr[c] = J.orig + (size_t)J.act[c] * J.n_pad;
@@ -301,11 +304,11 @@ __global__ __launch_bounds__(256) void k_active(JobDev* jobs, int ft) {
 // the Feistel round functions are tabulated in LDS first.
 constexpr int kShadowChunk = 8192;
 
-__global__ __launch_bounds__(256) void k_shadow(JobDev* jobs, const int32_t* live) {
+__global__ __launch_bounds__(256) void k_shadow(JobDev* jobs) {
     __shared__ uint16_t tab[6 << 12];  // rounds x 2^half, largest case: half 12, 6 rounds
-    JobDev& J = jobs[live[blockIdx.z]];
+    JobDev& J = jobs[blockIdx.z];
     const int s = blockIdx.y;
-    if (s >= J.n_sha) return;
+    if (!J.live || s >= J.n_sha) return;
     const int64_t r0 = (int64_t)blockIdx.x * kShadowChunk;
     if (r0 >= J.n) return;
     const KeyedPerm P = make_perm(J.seed_lo, J.seed_hi, kShadow, (uint32_t)J.t, (uint32_t)s, 0u,
@@ -327,6 +330,7 @@ __global__ __launch_bounds__(256) void k_shadow(JobDev* jobs, const int32_t* liv
 __global__ void k_boot_draw(JobDev* jobs, const TreeDev* trees) {
     const TreeDev tr = trees[blockIdx.y];
     const JobDev& J = jobs[tr.job];
+    if (!J.live) return;
     const uint32_t pair = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t n = (uint32_t)J.n;
     if (2ull * pair >= n) return;
@@ -393,12 +397,11 @@ void launch_active(JobDev* jobs, int n_jobs, int ft, hipStream_t st) {
     hipLaunchKernelGGL(k_active, dim3(n_jobs), dim3(256), 0, st, jobs, ft);
 }
 
-void launch_shadow(JobDev* jobs, const int32_t* live, int n_live, int64_t max_n, int max_sha,
-                   hipStream_t st) {
+void launch_shadow(JobDev* jobs, int n_jobs, int64_t max_n, int max_sha, hipStream_t st) {
     hipLaunchKernelGGL(k_shadow,
                        dim3((unsigned)((max_n + kShadowChunk - 1) / kShadowChunk),
-                            (unsigned)max_sha, (unsigned)n_live),
-                       dim3(256), 0, st, jobs, live);
+                            (unsigned)max_sha, (unsigned)n_jobs),
+                       dim3(256), 0, st, jobs);
 }
 
 void launch_boot_draw(JobDev* jobs, const TreeDev* trees, int n_trees, int64_t max_n,
