@@ -34,7 +34,24 @@ def parse():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the Permut / exact / plain comparison legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe-copy", type=int, default=0, metavar="BYTES",
+                    help="only run the library's streaming copy kernel over BYTES bytes "
+                         "(calibrates the FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
+
+
+def probe_copy(nbytes):
+    """Five launches of the library's 16-byte-per-lane streaming copy."""
+    import torch
+    from paper_2605_09950_amd import binding as B
+    src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        B.boruta_probe_copy(dst, src, nbytes)
+    torch.cuda.synchronize()
+    assert bool((dst == 1).all())
+    print(json.dumps({"probe_copy_bytes": nbytes, "launches": 5}), flush=True)
 
 
 def workload(name):
@@ -77,6 +94,8 @@ def run_gpu(c, pr, mode, steps, warmup, form, rank, stats):
             k = getattr(sess.stats, f)
             k.launches, k.ms, k.alg_bytes = 0, 0.0, 0.0
         sess.stats.iter_ms, sess.stats.iterations, sess.stats.nodes = 0.0, 0, 0
+        for d in range(32):
+            sess.stats.level_small[d] = sess.stats.level_large[d] = 0
     done = 0
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -147,6 +166,9 @@ def main():
     from paper_2605_09950_amd import binding as B
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     B.lib()
+    if args.probe_copy:
+        probe_copy(args.probe_copy)
+        return
     c, pr, n, p, desc = workload(args.workload)
     mode = B.TREEIMP if args.mode == "treeimp" else B.PERMUT
     main_leg = run_gpu(c, pr, mode, args.steps, args.warmup, B.FORM_BATCHED, B.RANK_FP32,
@@ -156,6 +178,12 @@ def main():
     extra = {"kernels": kernels, "timed_iterations": f"{args.warmup + 1}.."
              f"{args.warmup + main_leg['steps']}",
              "device_iter_ms": round(main_leg["stats"].iter_ms / max(1, main_leg["steps"]), 3)}
+    st = main_leg["stats"]
+    extra["nodes_per_iteration_by_depth"] = {
+        "small": [round(st.level_small[d] / main_leg["steps"], 1)
+                  for d in range(pr["max_depth"])],
+        "large": [round(st.level_large[d] / main_leg["steps"], 1)
+                  for d in range(pr["max_depth"])]}
     if not args.no_compare:
         k = max(1, min(5, args.steps))
         other = B.PERMUT if mode == B.TREEIMP else B.TREEIMP

@@ -93,6 +93,8 @@ typedef struct {
     double iter_ms;                /* device time of all iterations               */
     int64_t iterations;            /* job-iterations run                          */
     int64_t nodes;                 /* tree nodes grown                            */
+    int64_t level_small[32];       /* nodes searched by the wave path, per depth  */
+    int64_t level_large[32];       /* nodes searched by the tiled path, per depth */
 } boruta_stats;
 
 typedef struct {

@@ -50,7 +50,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("hist_large", KernelStat), ("hist_small", KernelStat), ("finalize", KernelStat),
                 ("permut", KernelStat),
                 ("iter_ms", ctypes.c_double), ("iterations", ctypes.c_int64),
-                ("nodes", ctypes.c_int64)]
+                ("nodes", ctypes.c_int64), ("level_small", ctypes.c_int64 * 32),
+                ("level_large", ctypes.c_int64 * 32)]
 
 
 class Options(ctypes.Structure):

@@ -586,6 +586,10 @@ void Engine::iteration(const std::vector<int>& live) {
         stats->iter_ms += whole.ms;
         stats->nodes += (int64_t)n_nodes;
         stats->iterations += (int64_t)live.size();
+        for (int d = 0; d < n_levels && d < 32; ++d) {
+            stats->level_small[d] += c[d].n_small;
+            stats->level_large[d] += c[d].n_slots;
+        }
     }
     if (O.trace) emit_trace(live, (uint32_t)n_nodes);
 }
