@@ -177,40 +177,51 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out) {
     const uint32_t N = nd.n;
     const KeyedPerm P = make_perm(J.seed_lo, J.seed_hi, kMtry, (uint32_t)J.t, (uint32_t)tr.tau,
                                   nd.heap, 0u, (uint64_t)J.p_w);
-    Cand best;
-    best.nl = 0;
-    best.q = 0x7FFFFFFF;
-    best.b = 0x7FFFFFFF;
+    // Each lane keeps the best of its own candidates over the passes (they
+    // arrive in increasing draw position, so an exact tie keeps the earlier
+    // one); one wave-wide reduction per node picks the winner.  With FP32
+    // ranking, two candidates are compared exactly only when their FP32
+    // scores are within the ranking margin of each other.
+    Cand lb;
+    lb.nl = 0;
+    lb.q = 0x7FFFFFFF;
+    lb.b = 0x7FFFFFFF;
+    lb.f = 0;
+    lb.nr = 0;
+    lb.pad = 0;
+    lb.sl = lb.sr = 0;
+    float lq = -1.0f;
+    const bool fp32 = F.split_rank != 0;
+    const int abase = (lane - i) << 2;  // ds_bpermute byte address of the segment's lane 0
     for (int q0 = 0; q0 < J.mtry; q0 += 64) {
         const int nq = min(64, J.mtry - q0);
         const int myf = lane < nq ? (int)perm_apply(P, (uint32_t)(q0 + lane)) : 0;
         const unsigned long long mycol =
             lane < nq ? (unsigned long long)ldg(J.colptr + myf) : 0ull;
         const int passes = (nq + G - 1) / G;
+        // The bin load is unconditional (lanes without a row read row 0, lanes
+        // past the drawn features read the first one) so that blocks of loads
+        // issue back to back; eval() masks what does not count.
         auto gather = [&](int pass) {
             const int qq = pass * G + seg;
-            const bool act = qq < nq;
-            const uint8_t* col = (const uint8_t*)__shfl(mycol, act ? qq : 0);
-            return (valid && act) ? (int)ldg(col + row) : 0x7FFF;
+            const uint8_t* col = (const uint8_t*)__shfl(mycol, qq < nq ? qq : 0);
+            return (int)ldg(col + row);
         };
-        int b_next = gather(0);
-        for (int pass = 0; pass < passes; ++pass) {
-            const int b = b_next;
-            if (pass + 1 < passes) b_next = gather(pass + 1);
+        auto eval = [&](int pass, int raw) {
             const int qq = pass * G + seg;
             const bool act = qq < nq;
-            const int f = __shfl(myf, act ? qq : 0);
+            const int b = (valid && act) ? raw : 0x7FFF;
             // left counts of threshold b: the segment's rows j with bin <= b.
-            // Bins by lane permute (eight in flight), counters of row j read
-            // from lane j as scalars; rows j >= len read zero counters.
+            // Bins by lane permute, counters of row j read from lane j as
+            // scalars; rows j >= len read zero counters.
             word acc[PK::kWords];
 #pragma unroll
             for (int w = 0; w < PK::kWords; ++w) acc[w] = 0;
-            const int sbase = lane - i;
             for (int j0 = 0; j0 < len; j0 += 8) {
                 int bj[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) bj[u] = __shfl(b, sbase + j0 + u);
+                for (int u = 0; u < 8; ++u)
+                    bj[u] = __builtin_amdgcn_ds_bpermute(abase + ((j0 + u) << 2), b);
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const bool take = bj[u] <= b;
@@ -223,7 +234,7 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out) {
             }
             Cand c;
             c.q = q0 + qq;
-            c.f = f;
+            c.f = __shfl(myf, act ? qq : 0);
             c.b = b;
             c.pad = 0;
             uint32_t nl = 0;
@@ -241,16 +252,42 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out) {
             c.sl = sl;
             c.sr = sr;
             const bool ok = valid && act && b <= B - 2 && nl > 0 && nl < N;
-            if (!ok) {
-                c.nl = 0;
-                c.b = 0x7FFFFFFF;
-                c.q = 0x7FFFFFFF;
+            const bool has = lb.nl != 0;
+            bool better;
+            float qc = -1.0f;
+            if (fp32) {
+                qc = ok ? cand_q32(c) : -1.0f;
+                const bool near = ok && has && qc >= fp32_floor(lq) && lq >= fp32_floor(qc);
+                bool exact = false;
+                if (__ballot(near)) exact = cand_better(c, lb);
+                better = ok && (!has || (near ? exact : qc > lq));
+            } else {
+                better = ok && (!has || cand_better(c, lb));
             }
-            const Cand pb = F.split_rank ? wave_best_total_fp32(c, ok ? cand_q32(c) : -1.0f)
-                                         : wave_best_total_exact(c);
-            if (pb.nl != 0 && (best.nl == 0 || cand_better(pb, best))) best = pb;
+            if (better) {
+                lb = c;
+                lq = qc;
+            }
+        };
+        // bins of eight passes are in flight while the previous eight are scored
+        int bq[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) bq[u] = gather(u);
+        for (int pb = 0; pb < passes; pb += 8) {
+            int bn[8];
+            if (pb + 8 < passes) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) bn[u] = gather(pb + 8 + u);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (pb + u < passes) eval(pb + u, bq[u]);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) bq[u] = bn[u];
         }
     }
+    const Cand best = fp32 ? wave_best_total_fp32(lb, lb.nl != 0 ? lq : -1.0f)
+                           : wave_best_total_exact(lb);
     out.ntiles = (uint32_t)J.ntiles;
     out.alg = (uint64_t)len * (uint64_t)(J.mtry + 6);
     if (best.nl == 0 || !cand_positive(best, S, N)) {  // stays the leaf it was created as
