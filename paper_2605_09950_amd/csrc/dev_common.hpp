@@ -302,6 +302,7 @@ struct ForestDev {
     uint32_t* cls;        // [node][kmax] weighted class counts
     uint64_t* ngain;      // [node] fixed-point Gini decrease of a split node
     Cand* cand;           // [slot][max_tiles] best candidate of each feature tile
+    uint32_t* cand_cl;    // [slot][max_tiles][kmax] left class counts of that candidate
     const uint32_t* slot_node_in;  // [slot] node of each large-node slot of this level
     uint32_t* slot_node_out;       // [slot] the same for the next level
     const Item* items_in;

@@ -140,7 +140,7 @@ struct JobPlan {
 struct Plan {
     std::vector<JobPlan> jp;
     size_t keys, jobs, trees, tree_base, flags, nodes, cls, ngain, items0, items1, small0,
-        small1, cand, slot0, slot1, ctrs, alg, tot;
+        small1, cand, cand_cl, slot0, slot1, ctrs, alg, tot;
     uint32_t node_cap = 0, item_cap = 0, slot_cap = 0, small_cap = 0;
     int kmax = 4, ft = 8, max_tiles = 1, max_sha = 1, max_pw = 1, max_D = 1, T_total = 0;
     int64_t max_n = 0;
@@ -225,6 +225,7 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     pl.small0 = r.take((size_t)pl.small_cap * 4);
     pl.small1 = r.take((size_t)pl.small_cap * 4);
     pl.cand = r.take((size_t)pl.slot_cap * pl.max_tiles * sizeof(Cand));
+    pl.cand_cl = r.take((size_t)pl.slot_cap * pl.max_tiles * pl.kmax * 4);
     pl.slot0 = r.take((size_t)pl.slot_cap * 4);
     pl.slot1 = r.take((size_t)pl.slot_cap * 4);
     // level d < max_D reads ctrs[d] and appends to ctrs[d + 1]
@@ -456,6 +457,7 @@ ForestDev Engine::forest() const {
     F.cls = at<uint32_t>(pl.cls);
     F.ngain = at<uint64_t>(pl.ngain);
     F.cand = at<Cand>(pl.cand);
+    F.cand_cl = at<uint32_t>(pl.cand_cl);
     F.ctrs = at<LevelCtr>(pl.ctrs);
     F.ctr = F.ctrs;
     F.n_roots = (uint32_t)pl.T_total;

@@ -46,6 +46,32 @@ __device__ __forceinline__ Cand wave_best_exact(Cand c) {
     return c;
 }
 
+// Wave-wide scans through DPP row shifts (within rows of 16 lanes) and row
+// broadcasts (lane 15 -> next row, lane 31 -> rows 2-3); lanes whose DPP
+// source is outside the pattern take the identity.  No LDS traffic.
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
+}
+
+// Maximum over the wave (a max-scan; lane 63 ends with the total), as a
+// wave-uniform value.  The values must be >= -1 (the "no candidate" mark).
+__device__ __forceinline__ float wave_max_f_dpp(float v) {
+    const int lo = __float_as_int(-2.0f);
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(lo, __float_as_int(v), 0x111, 0xf, 0xf, false)));
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(lo, __float_as_int(v), 0x112, 0xf, 0xf, false)));
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(lo, __float_as_int(v), 0x114, 0xf, 0xf, false)));
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(lo, __float_as_int(v), 0x118, 0xf, 0xf, false)));
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(lo, __float_as_int(v), 0x142, 0xa, 0xf, false)));
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(lo, __float_as_int(v), 0x143, 0xc, 0xf, false)));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 __device__ __forceinline__ float wave_max_f(float v) {
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) v = fmaxf(v, __shfl_xor(v, m));

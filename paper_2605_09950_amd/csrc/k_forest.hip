@@ -7,7 +7,7 @@
 //                     rows sit in lanes and every threshold's left class
 //                     counts come from an in-register all-pairs sum;
 //   * k_hist_tile     one workgroup per (node, tile of drawn features):
-//                     LDS class-count histogram [feature][bin][class] built
+//                     LDS class-count histogram [feature][class][bin] built
 //                     with LDS atomics from batched global gathers, then a
 //                     wave prefix scan over the bins per feature; writes the
 //                     tile's best candidate;
@@ -388,35 +388,36 @@ __global__ __launch_bounds__(256) void k_split_small(ForestDev F0, int level, ui
 }
 
 // ---------------------------------------------------------------------------
-// Best threshold of one feature from its LDS histogram h[B][KMAX]: each lane
-// owns ceil(B/64) consecutive bins; class prefix sums come from a wave scan.
+// Best threshold of one feature from its LDS histogram h[KMAX][256] (class
+// rows of 256 bins; bins >= B stay zero).  Lane l owns bins 4l .. 4l+3, read
+// as one 16-byte word per class (consecutive lanes, consecutive words: no
+// bank conflicts); class prefix sums come from a DPP wave scan.
 template <int KMAX>
 __device__ Cand feature_best(const uint32_t* h, int B, int q, int f, const uint32_t* cnode,
                              uint32_t N, int split_rank) {
+    constexpr bool kRegs = KMAX <= 4;  // keep the lane's counts in registers
     const int lane = threadIdx.x & 63;
-    const int bpl = (B + 63) >> 6;
-    const int b0 = lane * bpl;
-    uint32_t acc[KMAX];
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) acc[k] = 0;
-    for (int u = 0; u < bpl; ++u) {
-        const int b = b0 + u;
-        if (b < B) {
-#pragma unroll
-            for (int k = 0; k < KMAX; ++k) acc[k] += h[b * KMAX + k];
-        }
-    }
+    const int b0 = lane * 4;
+    uint32_t hv[kRegs ? KMAX : 1][4];
     uint32_t excl[KMAX];
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
-        uint32_t v = acc[k];
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t t = __shfl_up(v, off);
-            if (lane >= off) v += t;
+        const uint4 v = *reinterpret_cast<const uint4*>(h + k * 256 + b0);
+        if constexpr (kRegs) {
+            hv[k][0] = v.x;
+            hv[k][1] = v.y;
+            hv[k][2] = v.z;
+            hv[k][3] = v.w;
         }
-        excl[k] = v - acc[k];
+        const uint32_t a = v.x + v.y + v.z + v.w;
+        excl[k] = wave_incl_sum(a) - a;
     }
+    auto hval = [&](int k, int u) -> uint32_t {
+        if constexpr (kRegs)
+            return hv[k][u];
+        else
+            return h[k * 256 + b0 + u];
+    };
     // candidates of this lane, in ascending threshold order
     auto make = [&](int b, const uint32_t* cl) {
         Cand c;
@@ -444,87 +445,118 @@ __device__ Cand feature_best(const uint32_t* h, int B, int q, int f, const uint3
     lb.b = 0x7FFFFFFF;
     lb.q = q;
     lb.f = f;
+    lb.nr = 0;
+    lb.pad = 0;
+    lb.sl = lb.sr = 0;
     uint32_t cl[KMAX];
     if (!split_rank) {
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) cl[k] = excl[k];
-        for (int u = 0; u < bpl; ++u) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
             const int b = b0 + u;
-            if (b >= B - 1) break;
             uint32_t add = 0;
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) {
-                const uint32_t v = h[b * KMAX + k];
+                const uint32_t v = hval(k, u);
                 cl[k] += v;
                 add += v;
             }
             // an empty bin repeats the previous threshold's partition, which the
             // smaller threshold already represents
-            if (add == 0) continue;
+            if (b > B - 2 || add == 0) continue;
             const Cand c = make(b, cl);
             if (c.nl == 0 || c.nl == N) continue;
             if (lb.nl == 0 || cand_better(c, lb)) lb = c;
         }
         return wave_best_exact(lb);
     }
-    // FP32 ranking: pass 1 finds the wave's FP32 maximum, pass 2 re-ranks the
-    // candidates within the margin exactly.
-    float lq = -1.0f;
+    // FP32 ranking: the lane's best and second-best FP32 scores; finalists
+    // are the lanes whose best is within the margin of the wave maximum.  A
+    // finalist lane whose second-best is also within it re-ranks its bins
+    // exactly; otherwise its finalist is the best bin alone.
+    float q1 = -1.0f, q2 = -1.0f;
+    int u1 = 0;
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) cl[k] = excl[k];
-    for (int u = 0; u < bpl; ++u) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
         const int b = b0 + u;
-        if (b >= B - 1) break;
         uint32_t add = 0;
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
-            const uint32_t v = h[b * KMAX + k];
+            const uint32_t v = hval(k, u);
             cl[k] += v;
             add += v;
         }
-        if (add == 0) continue;
+        if (b > B - 2 || add == 0) continue;
         const Cand c = make(b, cl);
         if (c.nl == 0 || c.nl == N) continue;
-        lq = fmaxf(lq, cand_q32(c));
-    }
-    const float qmax = wave_max_f(lq);
-    if (qmax < 0.0f) return lb;
-    const float floor32 = fp32_floor(qmax);
-    if (lq >= floor32) {
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k) cl[k] = excl[k];
-        for (int u = 0; u < bpl; ++u) {
-            const int b = b0 + u;
-            if (b >= B - 1) break;
-            uint32_t add = 0;
-#pragma unroll
-            for (int k = 0; k < KMAX; ++k) {
-                const uint32_t v = h[b * KMAX + k];
-                cl[k] += v;
-                add += v;
-            }
-            if (add == 0) continue;
-            const Cand c = make(b, cl);
-            if (c.nl == 0 || c.nl == N) continue;
-            if (cand_q32(c) < floor32) continue;
-            if (lb.nl == 0 || cand_better(c, lb)) lb = c;
+        const float qc = cand_q32(c);
+        if (qc > q1) {
+            q2 = q1;
+            q1 = qc;
+            u1 = u;
+        } else if (qc > q2) {
+            q2 = qc;
         }
     }
-    const unsigned long long fin = __ballot(lb.nl != 0);
-    if (__popcll(fin) == 1) return shfl_cand(lb, (int)__ffsll(fin) - 1);
+    const float qmax = wave_max_f_dpp(q1);
+    if (qmax < 0.0f) return lb;
+    const float floor32 = fp32_floor(qmax);
+    const bool fin = q1 >= floor32;
+    const bool multi = fin && q2 >= floor32;
+    if (__ballot(multi)) {
+        if (multi) {
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) cl[k] = excl[k];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int b = b0 + u;
+                uint32_t add = 0;
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k) {
+                    const uint32_t v = hval(k, u);
+                    cl[k] += v;
+                    add += v;
+                }
+                if (b > B - 2 || add == 0) continue;
+                const Cand c = make(b, cl);
+                if (c.nl == 0 || c.nl == N) continue;
+                if (cand_q32(c) < floor32) continue;
+                if (lb.nl == 0 || cand_better(c, lb)) lb = c;
+            }
+        }
+    }
+    if (fin && !multi) {
+        // class counts left of bin b0 + u1
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            uint32_t v = excl[k];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v += u <= u1 ? hval(k, u) : 0u;
+            cl[k] = v;
+        }
+        lb = make(b0 + u1, cl);
+    }
+    const unsigned long long finm = __ballot(lb.nl != 0);
+    if (__popcll(finm) == 1) return shfl_cand(lb, (int)__ffsll(finm) - 1);
     return wave_best_exact(lb);
 }
 
 // Large nodes, phase 1: one workgroup per (node, feature tile).  FT columns
-// per tile keep the LDS histogram at FT * 256 * KMAX * 4 = 32 KB.
+// per tile keep the LDS histogram at FT * KMAX * 256 * 4 = 32 KB; the class-
+// major rows spread a wave's atomics over the banks by bin.
 template <int KMAX>
 __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint32_t first,
                                                    uint32_t count) {
     constexpr int FT = 32 / KMAX;
-    extern __shared__ uint32_t hist[];  // [FT][B][KMAX]
+    extern __shared__ uint4 hist_raw[];  // [FT][KMAX][256] class counts (16-byte aligned)
+    uint32_t* hist = reinterpret_cast<uint32_t*>(hist_raw);
     __shared__ const uint8_t* s_col[FT];
     __shared__ int s_feat[FT];
     __shared__ Cand s_fbest[FT];
+    __shared__ int s_bi;
     if (count == 0xFFFFFFFFu) {
         first = 0;
         count = level_items(F, level);
@@ -545,7 +577,8 @@ __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint3
         s_feat[tid] = f;
         s_col[tid] = ldg(J.colptr + f);
     }
-    for (int i = tid; i < FT * B * KMAX; i += 256) hist[i] = 0;
+    for (int i = tid; i < FT * KMAX * 64; i += 256)
+        reinterpret_cast<uint4*>(hist)[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     const uint8_t* col[FT];
 #pragma unroll
@@ -570,8 +603,8 @@ __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint3
 #pragma unroll
         for (int q = 0; q < FT; ++q) {
             if (q < nf) {
-                atomicAdd(&hist[(q * B + b0[q]) * KMAX + y0], w0);
-                if (v1) atomicAdd(&hist[(q * B + b1[q]) * KMAX + y1], w1);
+                atomicAdd(&hist[(q * KMAX + y0) * 256 + b0[q]], w0);
+                if (v1) atomicAdd(&hist[(q * KMAX + y1) * 256 + b1[q]], w1);
             }
         }
     }
@@ -582,18 +615,37 @@ __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint3
     const uint32_t N = nd.n;
     for (int q = wave; q < nf; q += 4) {
         const Cand fb =
-            feature_best<KMAX>(hist + q * B * KMAX, B, q0 + q, s_feat[q], cnode, N, F.split_rank);
+            feature_best<KMAX>(hist + q * KMAX * 256, B, q0 + q, s_feat[q], cnode, N, F.split_rank);
         if (lane == 0) s_fbest[q] = fb;
     }
     __syncthreads();
     if (tid == 0) {
-        Cand tb = s_fbest[0];
+        int bi = 0;  // earliest draw among equal scores: strict comparison
         for (int q = 1; q < nf; ++q)
-            if (s_fbest[q].nl != 0 && (tb.nl == 0 || cand_better(s_fbest[q], tb))) tb = s_fbest[q];
-        F.cand[(size_t)it.slot * F.max_tiles + it.tile] = tb;
+            if (s_fbest[q].nl != 0 &&
+                (s_fbest[bi].nl == 0 || cand_better(s_fbest[q], s_fbest[bi])))
+                bi = q;
+        s_bi = bi;
+        F.cand[(size_t)it.slot * F.max_tiles + it.tile] = s_fbest[bi];
         if (F.alg_bytes)
             atomicAdd((unsigned long long*)&F.alg_bytes[item & 63],
                       (unsigned long long)len * (unsigned long long)(nf + (it.tile == 0 ? 6 : 0)));
+    }
+    __syncthreads();
+    if (wave == 0) {
+        // left class counts of the tile's candidate, for the partition step
+        const int bi = s_bi;
+        const int bt = s_fbest[bi].nl != 0 ? s_fbest[bi].b : -1;
+        uint32_t* out = F.cand_cl + ((size_t)it.slot * F.max_tiles + it.tile) * F.kmax;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const uint4 v = *reinterpret_cast<const uint4*>(hist + (bi * KMAX + k) * 256 + lane * 4);
+            const int bl = lane * 4;
+            const uint32_t a = (bl <= bt ? v.x : 0u) + (bl + 1 <= bt ? v.y : 0u) +
+                               (bl + 2 <= bt ? v.z : 0u) + (bl + 3 <= bt ? v.w : 0u);
+            const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_sum(a), 63);
+            if (lane == k) out[k] = tot;
+        }
     }
     __syncthreads();  // LDS is reused by the next item
     }
@@ -607,10 +659,10 @@ template <int KMAX>
 __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level, uint32_t first,
                                                         uint32_t count) {
     __shared__ Cand s_best;
-    __shared__ int s_split;
-    __shared__ uint32_t s_cl[KMAX];
+    __shared__ Cand s_tiles[64];
+    __shared__ int s_split, s_bt;
     __shared__ uint32_t s_wcnt[4];
-    __shared__ uint32_t s_run;
+    __shared__ uint32_t s_runl, s_runr;
     const ForestDev F = level_view(F0, level);
     if (count == 0xFFFFFFFFu) {
         first = 0;
@@ -631,17 +683,27 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
         S += (uint64_t)cnode[k] * cnode[k];
     }
     const uint32_t N = nd.n;
-    if (tid < KMAX) s_cl[tid] = 0;
+    // the tiles' candidates are loaded in parallel, then ranked in draw order
+    // (a strictly better score replaces: the earliest tile keeps a tie)
+    int bt = -1;
+    for (int t0 = 0; t0 < J.ntiles; t0 += 64) {
+        const int nt = min(64, J.ntiles - t0);
+        if (tid < nt) s_tiles[tid] = F.cand[(size_t)slot * F.max_tiles + t0 + tid];
+        __syncthreads();
+        if (tid == 0)
+            for (int t = 0; t < nt; ++t)
+                if (s_tiles[t].nl != 0 &&
+                    (bt < 0 || cand_better(s_tiles[t], s_best)) ) {
+                    s_best = s_tiles[t];
+                    bt = t0 + t;
+                }
+        __syncthreads();
+    }
     if (tid == 0) {
-        Cand best;
-        best.nl = 0;
-        for (int tl = 0; tl < J.ntiles; ++tl) {
-            const Cand c = F.cand[(size_t)slot * F.max_tiles + tl];
-            if (c.nl != 0 && (best.nl == 0 || cand_better(c, best))) best = c;
-        }
-        s_best = best;
-        s_split = best.nl != 0 && cand_positive(best, S, N);
-        s_run = 0;
+        s_split = bt >= 0 && cand_positive(s_best, S, N);
+        s_bt = bt;
+        s_runl = 0;
+        s_runr = 0;
     }
     __syncthreads();
     const uint32_t child = F.next_base + 2u * (F.n_small_cur + slot);
@@ -654,14 +716,13 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
     const uint8_t* col = ldg(J.colptr + best.f);
     const uint64_t* recs = J.rec[F.parity] + (size_t)tr.tau * J.n + nd.seg;
     uint64_t* rout = J.rec[F.parity ^ 1] + (size_t)tr.tau * J.n + nd.seg;
-    // Rows are handled in blocks of 256 x kR: thread t owns rows
-    // [blk + t*kR, blk + t*kR + kR), so the order of (thread, row) is the row
-    // order and the scatter below is stable.  All loads of a block are issued
-    // before they are used.
+    // One pass over blocks of 256 x kR rows (thread t owns rows
+    // [blk + t kR, blk + t kR + kR)): left rows are written from the front in
+    // row order, right rows from the back in reverse row order.  No result
+    // depends on the order of a node's rows; each child segment stays
+    // monotone in row index, which keeps the next level's gathers local.
     constexpr int kR = 8;
     const uint32_t len = nd.len;
-    // pass 1: distinct rows going left
-    uint32_t cnt = 0;
     for (uint32_t blk = 0; blk < len; blk += 256 * kR) {
         const uint32_t i0 = blk + (uint32_t)tid * kR;
         uint64_t r[kR];
@@ -670,63 +731,46 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
         int bb[kR];
 #pragma unroll
         for (int u = 0; u < kR; ++u) bb[u] = i0 + u < len ? (int)ldg(col + rec_row(r[u])) : 0x7FFF;
-#pragma unroll
-        for (int u = 0; u < kR; ++u) cnt += bb[u] <= best.b;
-    }
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) cnt += __shfl_xor(cnt, m);
-    if (lane == 0) s_wcnt[wave] = cnt;
-    __syncthreads();
-    const uint32_t nl_rows = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
-    __syncthreads();
-    // pass 2: stable scatter, left rows first
-    for (uint32_t blk = 0; blk < len; blk += 256 * kR) {
-        const uint32_t i0 = blk + (uint32_t)tid * kR;
-        uint64_t r[kR];
-#pragma unroll
-        for (int u = 0; u < kR; ++u) r[u] = i0 + u < len ? ldg(recs + i0 + u) : 0ull;
-        int bb[kR];
-#pragma unroll
-        for (int u = 0; u < kR; ++u) bb[u] = i0 + u < len ? (int)ldg(col + rec_row(r[u])) : 0x7FFF;
-        uint32_t mine = 0;
-#pragma unroll
-        for (int u = 0; u < kR; ++u) mine += bb[u] <= best.b;
-        // exclusive prefix of the left counts over the block's threads
-        uint32_t incl = mine;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t t = __shfl_up(incl, off);
-            if (lane >= off) incl += t;
-        }
-        if (lane == 63) s_wcnt[wave] = incl;
-        __syncthreads();
-        uint32_t lrow = s_run + incl - mine;
-        for (int v = 0; v < wave; ++v) lrow += s_wcnt[v];
-        const uint32_t blk_left = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
+        uint32_t nlm = 0, nrm = 0;
 #pragma unroll
         for (int u = 0; u < kR; ++u) {
-            const uint32_t i = i0 + u;
-            if (i >= len) break;
-            if (bb[u] <= best.b) {
+            nlm += bb[u] <= best.b;
+            nrm += i0 + u < len && bb[u] > best.b;
+        }
+        // exclusive prefix of (left, right) counts over the block's threads,
+        // both packed in one word (a block holds at most 2048 rows)
+        const uint32_t mine = nlm | (nrm << 16);
+        const uint32_t incl = wave_incl_sum(mine);
+        if (lane == 63) s_wcnt[wave] = incl;
+        __syncthreads();
+        uint32_t pre = incl - mine;
+        for (int v = 0; v < wave; ++v) pre += s_wcnt[v];
+        const uint32_t blk_tot = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
+        uint32_t lrow = s_runl + (pre & 0xFFFFu), rrow = s_runr + (pre >> 16);
+#pragma unroll
+        for (int u = 0; u < kR; ++u) {
+            if (i0 + u >= len) break;
+            if (bb[u] <= best.b)
                 rout[lrow++] = r[u];
-                atomicAdd(&s_cl[rec_y(r[u])], rec_w(r[u]));
-            } else {
-                // right rows before i = i - (left rows before i)
-                rout[nl_rows + (i - lrow)] = r[u];
-            }
+            else
+                rout[len - 1 - rrow++] = r[u];
         }
         __syncthreads();
-        if (tid == 0) s_run += blk_left;
+        if (tid == 0) {
+            s_runl += blk_tot & 0xFFFFu;
+            s_runr += blk_tot >> 16;
+        }
         __syncthreads();
     }
     if (tid == 0) {
+        const uint32_t* clt = F.cand_cl + ((size_t)slot * F.max_tiles + s_bt) * F.kmax;
         uint32_t cl[16], cr[16];
         for (int k = 0; k < 16; ++k) {
-            cl[k] = k < KMAX ? s_cl[k] : 0u;
+            cl[k] = k < KMAX ? clt[k] : 0u;
             cr[k] = (k < KMAX ? cnode[k] : 0u) - cl[k];
         }
         int kinds[2];
-        split_node(F, J, tr, id, nd, best, nl_rows, cl, cr, cand_gain_fix(best, S, N), child,
+        split_node(F, J, tr, id, nd, best, s_runl, cl, cr, cand_gain_fix(best, S, N), child,
                    kinds);
         enqueue_nodes(F, J, child, kinds, 2);
     }
@@ -756,7 +800,7 @@ void launch_split_small(const ForestDev& F, int level, uint32_t first, uint32_t 
 void launch_hist_tile(const ForestDev& F, int level, uint32_t first, uint32_t count,
                       uint32_t grid_wg, int B, hipStream_t st) {
     if (!count) return;
-    const size_t lds = (size_t)32 * B * sizeof(uint32_t);  // FT * B * KMAX words, FT * KMAX = 32
+    const size_t lds = (size_t)32 * 256 * sizeof(uint32_t);  // FT * KMAX * 256 words, FT * KMAX = 32
     const dim3 grid(grid_wg);
     switch (F.kmax) {
         case 2: hipLaunchKernelGGL(k_hist_tile<2>, grid, dim3(256), lds, st, F, level, first, count); break;
