@@ -36,7 +36,7 @@ void launch_hist_tile(const ForestDev&, int, uint32_t, uint32_t, uint32_t, int, 
 void launch_split_finalize(const ForestDev&, int, uint32_t, uint32_t, uint32_t, hipStream_t);
 // k_importance.hip
 void launch_tree_totals(JobDev*, const TreeDev*, int, uint64_t*, hipStream_t);
-void launch_treeimp(JobDev*, int, const int32_t*, const uint64_t*, int, hipStream_t);
+void launch_treeimp(JobDev*, const TreeDev*, int, const uint64_t*, int, hipStream_t);
 void launch_permut(JobDev*, const TreeDev*, const NodeDev*, int, int64_t, int, hipStream_t);
 void launch_hits_decide(JobDev*, int, hipStream_t);
 void launch_copy(void*, const void*, size_t, hipStream_t);
@@ -559,8 +559,7 @@ void Engine::iteration(const std::vector<int>& live) {
     // importance
     if (any_treeimp) {
         launch_tree_totals(djobs, dtrees, (int)n_trees, at<uint64_t>(pl.tot), st);
-        launch_treeimp(djobs, nj, at<int32_t>(pl.tree_base), at<uint64_t>(pl.tot), pl.max_pw,
-                       st);
+        launch_treeimp(djobs, dtrees, (int)n_trees, at<uint64_t>(pl.tot), pl.max_pw, st);
     }
     if (any_permut) {
         const size_t h = clock.begin(stats ? &stats->permut : nullptr, st);

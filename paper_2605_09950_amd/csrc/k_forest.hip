@@ -660,7 +660,7 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
                                                         uint32_t count) {
     __shared__ Cand s_best;
     __shared__ Cand s_tiles[64];
-    __shared__ int s_split, s_bt;
+    __shared__ int s_split, s_bt, s_part;
     __shared__ uint32_t s_wcnt[4];
     __shared__ uint32_t s_runl, s_runr;
     const ForestDev F = level_view(F0, level);
@@ -704,6 +704,20 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
         s_bt = bt;
         s_runl = 0;
         s_runr = 0;
+        // Rows are partitioned only for a child that is searched next: below
+        // the maximum depth with two or more classes (which implies two or
+        // more distinct rows); other children are final leaves.
+        s_part = 0;
+        if (s_split && (int)nd.depth + 1 < J.D) {
+            const uint32_t* clt = F.cand_cl + ((size_t)slot * F.max_tiles + bt) * F.kmax;
+            int nzl = 0, nzr = 0;
+            for (int k = 0; k < KMAX; ++k) {
+                const uint32_t l = clt[k];
+                nzl += l != 0;
+                nzr += cnode[k] != l;
+            }
+            s_part = nzl >= 2 || nzr >= 2;
+        }
     }
     __syncthreads();
     const uint32_t child = F.next_base + 2u * (F.n_small_cur + slot);
@@ -722,7 +736,7 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
     // depends on the order of a node's rows; each child segment stays
     // monotone in row index, which keeps the next level's gathers local.
     constexpr int kR = 8;
-    const uint32_t len = nd.len;
+    const uint32_t len = s_part ? nd.len : 0u;  // no partition: both children are leaves
     for (uint32_t blk = 0; blk < len; blk += 256 * kR) {
         const uint32_t i0 = blk + (uint32_t)tid * kR;
         uint64_t r[kR];

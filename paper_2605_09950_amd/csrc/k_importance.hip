@@ -32,29 +32,22 @@ __global__ __launch_bounds__(256) void k_tree_totals(JobDev* jobs, const TreeDev
     if (threadIdx.x == 0) tot[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
 }
 
-// Per (column, job): I_f = sum over trees of floor(2^44 G[tree][f] / total).
-// G is cleared behind the read, ready for the next iteration.
-__global__ __launch_bounds__(256) void k_treeimp(JobDev* jobs, const int32_t* tree_base,
+// Per (column, tree): I_f += floor(2^44 G[tree][f] / total of the tree),
+// summed with 64-bit integer atomics (exact in any order).  G is cleared
+// behind the read, ready for the next iteration.
+__global__ __launch_bounds__(256) void k_treeimp(JobDev* jobs, const TreeDev* trees,
                                                  const uint64_t* tot) {
-    JobDev& J = jobs[blockIdx.y];
+    const uint32_t g = blockIdx.y;
+    const TreeDev tr = trees[g];
+    JobDev& J = jobs[tr.job];
     const int f = blockIdx.x * 256 + threadIdx.x;
     if (!J.live || J.mode != 0 || f >= J.p_w) return;
-    const int g0 = tree_base[blockIdx.y];
-    int64_t s = 0;
-    constexpr int kU = 8;  // trees per step: independent loads in flight
-    for (int t0 = 0; t0 < J.T; t0 += kU) {
-        uint64_t g[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u)
-            g[u] = t0 + u < J.T ? ldg(J.G + (size_t)(t0 + u) * J.pw_cap + f) : 0ull;
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            if (g[u] == 0) continue;
-            J.G[(size_t)(t0 + u) * J.pw_cap + f] = 0;
-            s += (int64_t)udiv128((u128)g[u] << 44, (u128)tot[g0 + t0 + u]);
-        }
-    }
-    J.imp[f] = s;
+    uint64_t* Gp = J.G + (size_t)tr.tau * J.pw_cap + f;
+    const uint64_t gv = ldg(Gp);
+    if (gv == 0) return;
+    *Gp = 0;
+    atomicAdd((unsigned long long*)&J.imp[f],
+              (unsigned long long)udiv128((u128)gv << 44, (u128)tot[g]));
 }
 
 // Permut: one thread per (tree, OOB row).
@@ -203,10 +196,10 @@ void launch_tree_totals(JobDev* jobs, const TreeDev* trees, int n_trees, uint64_
     hipLaunchKernelGGL(k_tree_totals, dim3(n_trees), dim3(256), 0, st, jobs, trees, tot);
 }
 
-void launch_treeimp(JobDev* jobs, int n_jobs, const int32_t* tree_base, const uint64_t* tot,
+void launch_treeimp(JobDev* jobs, const TreeDev* trees, int n_trees, const uint64_t* tot,
                     int max_pw, hipStream_t st) {
-    hipLaunchKernelGGL(k_treeimp, dim3((unsigned)((max_pw + 255) / 256), (unsigned)n_jobs),
-                       dim3(256), 0, st, jobs, tree_base, tot);
+    hipLaunchKernelGGL(k_treeimp, dim3((unsigned)((max_pw + 255) / 256), (unsigned)n_trees),
+                       dim3(256), 0, st, jobs, trees, tot);
 }
 
 void launch_permut(JobDev* jobs, const TreeDev* trees, const NodeDev* nodes, int n_trees,

@@ -2,6 +2,8 @@
 // input validation, quantile binning (per-column bitonic sort + cut table),
 // exact binomial decision thresholds, the active/widened column map,
 // shadow columns and bootstrap draws.
+#include <algorithm>
+
 #include "dev_common.hpp"
 
 namespace boruta {
@@ -241,7 +243,7 @@ __global__ void k_thresholds(int32_t max_iter, int64_t p, uint64_t alpha_m, int3
 // ---------------------------------------------------------------------------
 // Per iteration, one workgroup per job: t += 1, active columns (state >= 0,
 // ascending), shadow count (doubled while < 5), widened column map, mtry;
-// Permut jobs also clear their drop accumulators.
+// the importance accumulators are cleared.
 __global__ __launch_bounds__(256) void k_active(JobDev* jobs, int ft) {
     __shared__ uint32_t s_w[4];
     __shared__ uint32_t s_base;
@@ -268,8 +270,8 @@ __global__ __launch_bounds__(256) void k_active(JobDev* jobs, int ft) {
     int n_sha = p_cur;
     while (n_sha > 0 && n_sha < 5) n_sha *= 2;
     const int p_w = p_cur + n_sha;
-    if (J.mode == 1)  // Permut sums its drops into imp with atomics
-        for (int c = tid; c < p_w; c += 256) J.imp[c] = 0;
+    // both importances are summed into imp with integer atomics
+    for (int c = tid; c < p_w; c += 256) J.imp[c] = 0;
     for (int c = tid; c < p_w; c += 256) {
         if (c < p_cur) {
             J.colptr[c] = J.orig + (size_t)J.act[c] * J.n_pad;
@@ -302,10 +304,10 @@ __global__ __launch_bounds__(256) void k_active(JobDev* jobs, int ft) {
 // column s mod p_cur through its own keyed permutation of the n rows:
 // sha[s][i] = orig[src][pi_s(i)].  One workgroup per (chunk, shadow, job);
 // the Feistel round functions are tabulated in LDS first.
-constexpr int kShadowChunk = 8192;
+constexpr int kShadowChunk = 2048;  // rows per workgroup: 256 threads x 4 rows x 2
 
 __global__ __launch_bounds__(256) void k_shadow(JobDev* jobs) {
-    __shared__ uint16_t tab[6 << 12];  // rounds x 2^half, largest case: half 12, 6 rounds
+    extern __shared__ uint16_t tab[];  // rounds x 2^half round-function values
     JobDev& J = jobs[blockIdx.z];
     const int s = blockIdx.y;
     if (!J.live || s >= J.n_sha) return;
@@ -319,9 +321,16 @@ __global__ __launch_bounds__(256) void k_shadow(JobDev* jobs) {
     __syncthreads();
     const uint8_t* src = J.orig + (size_t)J.act[s % J.p_cur] * J.n_pad;
     uint8_t* dst = J.sha + (size_t)s * J.n_pad;
-    const int64_t r1 = min(r0 + (int64_t)kShadowChunk, (int64_t)J.n);
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += 256)
-        dst[i] = src[perm_apply_tab(P, tab, (uint32_t)i)];
+    // four consecutive rows per thread, one 32-bit store (rows are padded to
+    // a multiple of 256; pad rows get 0)
+    for (int64_t i = r0 + 4 * (int64_t)threadIdx.x; i < r0 + kShadowChunk && i < J.n; i += 1024) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i + u < J.n)
+                v |= (uint32_t)src[perm_apply_tab(P, tab, (uint32_t)(i + u))] << (8 * u);
+        *reinterpret_cast<uint32_t*>(dst + i) = v;
+    }
 }
 
 // Bootstrap draws: draw j of tree tau is floor(u * n / 2^64) with u the
@@ -398,10 +407,19 @@ void launch_active(JobDev* jobs, int n_jobs, int ft, hipStream_t st) {
 }
 
 void launch_shadow(JobDev* jobs, int n_jobs, int64_t max_n, int max_sha, hipStream_t st) {
+    // round-function table of the largest job: the keyed bijection of [0, n)
+    // works on 2 * half bits (smallest even >= 2 with 2^bits >= n) with
+    // max(6, ceil(24 / half)) rounds
+    uint32_t k = 0;
+    while ((int64_t(1) << k) < max_n) ++k;
+    if (k < 2) k = 2;
+    k += k & 1u;
+    const uint32_t half = k >> 1, rounds = std::max(6u, (24u + half - 1u) / half);
+    const size_t lds = (size_t)(rounds << half) * sizeof(uint16_t);
     hipLaunchKernelGGL(k_shadow,
                        dim3((unsigned)((max_n + kShadowChunk - 1) / kShadowChunk),
                             (unsigned)max_sha, (unsigned)n_jobs),
-                       dim3(256), 0, st, jobs);
+                       dim3(256), lds, st, jobs);
 }
 
 void launch_boot_draw(JobDev* jobs, const TreeDev* trees, int n_trees, int64_t max_n,
