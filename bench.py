@@ -70,7 +70,7 @@ def workload(name):
     return c, pr, n, p, desc
 
 
-def run_gpu(c, pr, mode, steps, warmup, form, rank, stats):
+def run_gpu(c, pr, mode, steps, warmup, form, rank, stats, graph=True):
     import torch
     from paper_2605_09950_amd import binding as B
     dX = torch.from_numpy(c["X"]).cuda()
@@ -85,7 +85,7 @@ def run_gpu(c, pr, mode, steps, warmup, form, rank, stats):
     stream = torch.cuda.current_stream()
     sess = B.Session([job], n_bins=pr["n_bins"], n_perm=pr["n_perm"], split_rank=rank,
                      form=form, stats=stats, inputs_on_device=True, workspace=ws,
-                     stream=stream)
+                     stream=stream, graph=graph)
     for _ in range(warmup):
         sess.step()
     torch.cuda.synchronize()
@@ -171,14 +171,22 @@ def main():
         return
     c, pr, n, p, desc = workload(args.workload)
     mode = B.TREEIMP if args.mode == "treeimp" else B.PERMUT
+    # timed region: iterations replayed from the captured HIP graph
     main_leg = run_gpu(c, pr, mode, args.steps, args.warmup, B.FORM_BATCHED, B.RANK_FP32,
-                       stats=True)
+                       stats=False, graph=True)
     value = main_leg["steps"] / main_leg["seconds"]
-    roof, kernels = roofline(main_leg["stats"])
+    # the same iterations launched eagerly with HIP events around every
+    # forest kernel: per-kernel durations and algorithmic bytes
+    ev_leg = run_gpu(c, pr, mode, args.steps, args.warmup, B.FORM_BATCHED, B.RANK_FP32,
+                     stats=True, graph=False)
+    assert ev_leg["steps"] == main_leg["steps"]
+    assert (ev_leg["decision"] == main_leg["decision"]).all()
+    roof, kernels = roofline(ev_leg["stats"])
     extra = {"kernels": kernels, "timed_iterations": f"{args.warmup + 1}.."
              f"{args.warmup + main_leg['steps']}",
-             "device_iter_ms": round(main_leg["stats"].iter_ms / max(1, main_leg["steps"]), 3)}
-    st = main_leg["stats"]
+             "device_iter_ms": round(ev_leg["stats"].iter_ms / max(1, ev_leg["steps"]), 3),
+             "eager_iters_per_s": round(ev_leg["steps"] / ev_leg["seconds"], 3)}
+    st = ev_leg["stats"]
     extra["nodes_per_iteration_by_depth"] = {
         "small": [round(st.level_small[d] / main_leg["steps"], 1)
                   for d in range(pr["max_depth"])],

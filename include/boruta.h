@@ -105,6 +105,12 @@ typedef struct {
     int32_t form;         /* BORUTA_FORM_PLAIN (one launch per tree node) or
                              BORUTA_FORM_BATCHED (all nodes of a tree level of all
                              trees and jobs per launch); default BATCHED           */
+    int32_t graph;        /* batched form: 1 = capture one iteration's launch
+                             sequence as a HIP graph on the first step and replay
+                             it on every later step, 0 = launch eagerly; default 1.
+                             Ignored (eager) when stats is set: kernel timing
+                             needs events around every launch.  Results are
+                             identical either way.                                 */
     boruta_trace_fn trace;/* nullable                                              */
     void* trace_user;
     boruta_stats* stats;  /* nullable                                              */

@@ -57,6 +57,7 @@ class Stats(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("n_bins", ctypes.c_int32), ("n_perm", ctypes.c_int32),
                 ("split_rank", ctypes.c_int32), ("form", ctypes.c_int32),
+                ("graph", ctypes.c_int32),
                 ("trace", TRACE_FN), ("trace_user", ctypes.c_void_p),
                 ("stats", ctypes.POINTER(Stats))]
 
@@ -180,11 +181,12 @@ def _trace_collector(store, p, keep_iters=None):
 
 
 def make_options(n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED, trace=False,
-                 stats=False, p=0):
+                 stats=False, p=0, graph=True):
     """Options plus the Python objects that must stay alive during the call.
     trace: False, True (every iteration) or a set of iterations to keep."""
     o = boruta_default_options()
     o.n_bins, o.n_perm, o.split_rank, o.form = n_bins, n_perm, split_rank, form
+    o.graph = int(bool(graph))
     keep = {"iters": []}
     if trace is not False:
         keep["cb"] = _trace_collector(keep, p, None if trace is True else set(trace))
@@ -197,7 +199,7 @@ def make_options(n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED, 
 
 def boruta_fit_ex(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=TREEIMP,
                   max_iter=20, alpha=0.05, seed=0, n_bins=256, n_perm=1, split_rank=RANK_FP32,
-                  form=FORM_BATCHED, trace=False, stats=False):
+                  form=FORM_BATCHED, trace=False, stats=False, graph=True):
     """Host arrays in, host arrays out (see boruta_fit in include/boruta.h)."""
     X = np.ascontiguousarray(X, dtype=np.float32)
     y = np.ascontiguousarray(y, dtype=np.int32)
@@ -207,7 +209,7 @@ def boruta_fit_ex(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=T
     hits = np.zeros(p, np.int32)
     smax = np.full(max_iter, np.nan)
     n_iter = np.zeros(1, np.int32)
-    o, keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p)
+    o, keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p, graph)
     rc = lib().boruta_fit_ex(_ptr(X), _ptr(y), n, p, n_classes, n_trees, max_depth, mtry,
                              importance_mode, max_iter, alpha, seed, ctypes.byref(o), _ptr(dec),
                              _ptr(hist), _ptr(hits), _ptr(smax), _ptr(n_iter))
@@ -338,7 +340,8 @@ class Session:
     inputs_on_device, X/y are torch CUDA tensors (float32 [n][p], int32 [n])."""
 
     def __init__(self, jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED,
-                 trace=False, stats=False, inputs_on_device=False, workspace=None, stream=None):
+                 trace=False, stats=False, inputs_on_device=False, workspace=None, stream=None,
+                 graph=True):
         self._arrays, cj = [], (Job * len(jobs))()
         self._shapes = []
         for i, jd in enumerate(jobs):
@@ -361,7 +364,8 @@ class Session:
             cj[i] = j
             self._shapes.append((p, j.max_iter))
         p0 = self._shapes[0][0]
-        self.opt, self.keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p0)
+        self.opt, self.keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p0,
+                                           graph)
         self._jobs = cj
         self._ws = workspace
         ws_ptr = workspace.data_ptr() if workspace is not None else None

@@ -67,7 +67,7 @@ struct Spec {
 };
 
 struct Opts {
-    int B = 256, R = 1, split_rank = 1, form = 1;
+    int B = 256, R = 1, split_rank = 1, form = 1, graph = 1;
     boruta_trace_fn trace = nullptr;
     void* trace_user = nullptr;
     boruta_stats* stats = nullptr;
@@ -80,6 +80,7 @@ Opts read_opts(const boruta_options* o) {
         r.R = o->n_perm;
         r.split_rank = o->split_rank;
         r.form = o->form;
+        r.graph = o->graph;
         r.trace = o->trace;
         r.trace_user = o->trace_user;
         r.stats = o->stats;
@@ -89,6 +90,7 @@ Opts read_opts(const boruta_options* o) {
     if (r.split_rank != 0 && r.split_rank != 1)
         throw Error(BORUTA_E_INVALID_ARG, "split_rank must be 0 or 1");
     if (r.form != 0 && r.form != 1) throw Error(BORUTA_E_INVALID_ARG, "form must be 0 or 1");
+    if (r.graph != 0 && r.graph != 1) throw Error(BORUTA_E_INVALID_ARG, "graph must be 0 or 1");
     return r;
 }
 
@@ -269,15 +271,19 @@ public:
         if (on_) HIPC(hipEventRecord(recs_[h].b, st));
     }
     // Every recorded event must have completed (the stream was synchronised).
-    void collect() {
+    // keep: the records belong to a captured graph and are recorded again by
+    // every replay.
+    void collect(bool keep) {
         for (const Rec& r : recs_) {
             float ms = 0.f;
             HIPC(hipEventElapsedTime(&ms, r.a, r.b));
             r.k->ms += ms;
             r.k->launches += 1;
         }
-        recs_.clear();
-        next_ = 0;
+        if (!keep) {
+            recs_.clear();
+            next_ = 0;
+        }
     }
 
 private:
@@ -307,6 +313,12 @@ public:
         : S(specs), O(o), dev_in(dev_inputs), base(base), st(st), clock(o.stats != nullptr) {
         pl = make_plan(specs, o, dev_inputs);
     }
+    ~Engine() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+    Engine(const Engine&) = delete;
+    Engine& operator=(const Engine&) = delete;
 
     template <class T>
     T* at(size_t off) const {
@@ -335,6 +347,7 @@ public:
 
 private:
     void iteration(const std::vector<int>& live);
+    void enqueue_iteration();
     ForestDev forest() const;
     void grow_level_plain(const ForestDev& F, int level);
     void emit_trace(const std::vector<int>& live, uint32_t n_nodes);
@@ -346,6 +359,9 @@ private:
     hipStream_t st;
     Plan pl;
     KernelClock clock;
+    boruta_kernel_stat iter_stat{};  // event time of whole iterations
+    hipGraph_t graph = nullptr;      // captured iteration (batched form)
+    hipGraphExec_t gexec = nullptr;
     std::vector<JobDev> hj;       // host mirror of the job records
     std::vector<int> tree_base;   // first tree of each job in the static tree table
     bool any_treeimp = false, any_permut = false;
@@ -504,14 +520,17 @@ uint32_t level_grid(uint64_t cap_units, uint32_t per_wg, uint32_t limit) {
 constexpr uint32_t kAll = 0xFFFFFFFFu;  // level kernels: work count read on the device
 }  // namespace
 
-void Engine::iteration(const std::vector<int>& live) {
+// The launch sequence of one iteration of every live job.  Work sizes come
+// from plan-time bounds; every kernel reads its real work count on the device,
+// so the sequence is the same for every iteration (and capturable), except in
+// the plain form, which reads each level's node list back.
+void Engine::enqueue_iteration() {
     const int nj = (int)S.size();
     const uint32_t n_trees = (uint32_t)pl.T_total;
     JobDev* djobs = at<JobDev>(pl.jobs);
     TreeDev* dtrees = at<TreeDev>(pl.trees);
     boruta_stats* stats = O.stats;
-    boruta_kernel_stat whole{};
-    const size_t h_whole = clock.begin(&whole, st);
+    const size_t h_whole = clock.begin(&iter_stat, st);
     launch_active(djobs, nj, pl.ft, st);
     launch_shadow(djobs, nj, pl.max_n, pl.max_sha, st);
     launch_boot_draw(djobs, dtrees, (int)n_trees, pl.max_n, st);
@@ -568,13 +587,52 @@ void Engine::iteration(const std::vector<int>& live) {
     }
     launch_hits_decide(djobs, nj, st);
     clock.end(h_whole, st);
+}
+
+void Engine::iteration(const std::vector<int>& live) {
+    // Kernel timing needs events around each launch, which a replayed graph
+    // cannot report: with stats the sequence is launched eagerly.
+    const bool use_graph = O.graph && O.form == BORUTA_FORM_BATCHED && !O.stats;
+    if (use_graph) {
+        if (!gexec) {
+            // Captured on a private stream (the caller's stream may be the
+            // null stream, which cannot be captured); replays go to the
+            // caller's stream.
+            hipStream_t user = st, cs = nullptr;
+            HIPC(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            st = cs;
+            try {
+                HIPC(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+                try {
+                    enqueue_iteration();
+                } catch (...) {
+                    hipGraph_t g = nullptr;
+                    (void)hipStreamEndCapture(cs, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    throw;
+                }
+                HIPC(hipStreamEndCapture(cs, &graph));
+                HIPC(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+            } catch (...) {
+                st = user;
+                (void)hipStreamDestroy(cs);
+                throw;
+            }
+            st = user;
+            (void)hipStreamDestroy(cs);
+        }
+        HIPC(hipGraphLaunch(gexec, st));
+    } else {
+        enqueue_iteration();
+    }
+    const int n_levels = pl.max_D;
     std::vector<LevelCtr> c(n_levels + 1);
-    HIPC(hipMemcpyAsync(c.data(), F.ctrs, c.size() * sizeof(LevelCtr), hipMemcpyDeviceToHost,
-                        st));
-    d2h(hj.data(), djobs, hj.size() * sizeof(JobDev));
-    clock.collect();
+    HIPC(hipMemcpyAsync(c.data(), at<LevelCtr>(pl.ctrs), c.size() * sizeof(LevelCtr),
+                        hipMemcpyDeviceToHost, st));
+    d2h(hj.data(), at<JobDev>(pl.jobs), hj.size() * sizeof(JobDev));
+    clock.collect(use_graph);
     uint32_t overflow = 0;
-    uint64_t n_nodes = n_trees;
+    uint64_t n_nodes = (uint32_t)pl.T_total;
     for (int d = 0; d <= n_levels; ++d) {
         overflow |= c[d].overflow;
         if (d < n_levels) n_nodes += 2ull * (c[d].n_small + c[d].n_slots);
@@ -583,8 +641,9 @@ void Engine::iteration(const std::vector<int>& live) {
         throw Error(BORUTA_E_DEVICE,
                     "internal capacity exceeded (flags " + std::to_string(overflow) + ")");
     if (n_nodes > pl.node_cap) throw Error(BORUTA_E_DEVICE, "node pool too small");
+    boruta_stats* stats = O.stats;
     if (stats) {
-        stats->iter_ms += whole.ms;
+        stats->iter_ms += iter_stat.ms;
         stats->nodes += (int64_t)n_nodes;
         stats->iterations += (int64_t)live.size();
         for (int d = 0; d < n_levels && d < 32; ++d) {
@@ -592,6 +651,7 @@ void Engine::iteration(const std::vector<int>& live) {
             stats->level_large[d] += c[d].n_slots;
         }
     }
+    iter_stat.ms = 0.0;
     if (O.trace) emit_trace(live, (uint32_t)n_nodes);
 }
 
@@ -831,6 +891,7 @@ void boruta_default_options(boruta_options* opt) {
     opt->n_perm = 1;
     opt->split_rank = BORUTA_RANK_FP32;
     opt->form = BORUTA_FORM_BATCHED;
+    opt->graph = 1;
     opt->trace = nullptr;
     opt->trace_user = nullptr;
     opt->stats = nullptr;

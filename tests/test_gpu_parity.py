@@ -173,3 +173,39 @@ def test_session_steps_and_resume_reproduce_a_run():
     assert np.array_equal(res["hits"], full["hits"])
     assert res["n_iter"] == full["n_iter"]
     np.testing.assert_array_equal(res["imp_history"][5:k], full["imp_history"][5:k])
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_graph_replays_match_eager_launches(mode):
+    """The batched iteration captured once as a HIP graph and replayed every
+    step (with the host's read-back and checks between replays) gives the
+    eager launch sequence's run, iteration by iteration."""
+    X, y = problem(26, 1800, 24, 3)
+    kw = dict(importance_mode=mode, max_iter=7, seed=12, trace=True)
+    eager = B.boruta_fit_ex(X, y, 3, 8, 9, graph=False, **kw)
+    graph = B.boruta_fit_ex(X, y, 3, 8, 9, graph=True, **kw)
+    assert len(graph["traces"]) >= 3
+    assert_same_run(graph, eager)
+
+
+def test_graph_session_with_stats_and_resume():
+    X, y = problem(27, 900, 16, 2)
+    kw = dict(n_classes=2, n_trees=7, max_depth=8, max_iter=10, seed=13)
+    full = B.boruta_fit_ex(X, y, 2, 7, 8, max_iter=10, seed=13, graph=False)
+    with B.Session([dict(X=X, y=y, **kw)], stats=True, graph=True) as s:
+        for _ in range(4):
+            s.step()
+        mid = s.result(0)
+        st = s.stats
+        assert st.iterations == 4 and st.hist_small.launches == 4 * 8
+        assert st.iter_ms > 0 and st.hist_large.ms > 0
+    with B.Session([dict(X=X, y=y, **kw)], graph=True) as s:
+        s.resume(0, 4, mid["decision"], mid["hits"])
+        while s.step():
+            pass
+        res = s.result(0)
+    assert np.array_equal(res["decision"], full["decision"])
+    assert np.array_equal(res["hits"], full["hits"])
+    k = full["n_iter"]
+    assert res["n_iter"] == k
+    np.testing.assert_array_equal(res["imp_history"][4:k], full["imp_history"][4:k])
