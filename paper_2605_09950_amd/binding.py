@@ -160,9 +160,12 @@ def boruta_default_options():
 
 def _trace_collector(store, p, keep_iters=None):
     """Copies each iteration record into store["iters"] (only iterations in
-    keep_iters when given)."""
+    keep_iters when given).  p: the feature count, or one per job."""
+    ps = list(p) if isinstance(p, (list, tuple)) else None
+
     def cb(_user, trp):
         tr = trp.contents
+        p = ps[tr.job] if ps is not None else p0
         p_w, nt, nn = tr.p_w, tr.n_trees, tr.n_nodes
         if keep_iters is not None and tr.t not in keep_iters:
             return
@@ -177,6 +180,7 @@ def _trace_collector(store, p, keep_iters=None):
             "nodes": np.ctypeslib.as_array(tr.nodes, (nn, 6)).copy() if nn else
             np.zeros((0, 6), np.int64),
         })
+    p0 = p
     return TRACE_FN(cb)
 
 
@@ -269,10 +273,8 @@ def boruta_fit_batch(jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM
         res[i].shadow_max = o["shadow_max"].ctypes.data
         arrs.append((X, y))
         outs.append(o)
-    p_max = max(np.shape(jd["X"])[1] for jd in jobs)
-    if trace is not False and len({np.shape(jd["X"])[1] for jd in jobs}) > 1:
-        raise ValueError("batch traces need jobs of equal p")
-    opt, keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p_max)
+    p_all = [int(np.shape(jd["X"])[1]) for jd in jobs]
+    opt, keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p_all)
     rc = lib().boruta_fit_batch(cj, len(jobs), ctypes.byref(opt), res)
     for i, o in enumerate(outs):
         o["n_iter"], o["status"] = res[i].n_iter, res[i].status
@@ -363,8 +365,8 @@ class Session:
                 jd.get("seed", 0)
             cj[i] = j
             self._shapes.append((p, j.max_iter))
-        p0 = self._shapes[0][0]
-        self.opt, self.keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p0,
+        p_all = [int(sh[0]) for sh in self._shapes]
+        self.opt, self.keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p_all,
                                            graph)
         self._jobs = cj
         self._ws = workspace
