@@ -2,13 +2,15 @@
 algorithmic bandwidth against the HBM roofline and the CPU oracle beside it.
 
 A step is one Boruta iteration (shadow widening, bootstrap, random forest,
-importance, hits, decision) of the MADELON-like workload: n=10,000 rows,
-p=500 float32 features (20 informative, 80 noisy mixes, 400 noise), 3
-classes, 256 quantile bins, 200 trees of depth 12, mtry = floor(sqrt(p_w)).
-Inputs are resident in device memory (torch tensors) before the timed
-region; binning happens once per job, at session creation, outside it.
+importance, hits, decision) of every live job of the workload.  The default
+workload is the MADELON-like one: n=10,000 rows, p=500 float32 features (20
+informative, 80 noisy mixes, 400 noise), 3 classes, 256 quantile bins, 200
+trees of depth 12, mtry = floor(sqrt(p_w)).  Inputs are resident in device
+memory (torch tensors) before the timed region; binning happens once per
+job, at session creation, outside it.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload madelon|planted|omics|manyjob|scale]
 """
 import argparse
 import json
@@ -28,11 +30,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["treeimp", "permut"], default="treeimp")
-    ap.add_argument("--workload", choices=["madelon", "planted", "omics", "scale"],
+    ap.add_argument("--mode", choices=["treeimp", "permut", "workload"], default="workload",
+                    help="importance mode (default: the workload's own)")
+    ap.add_argument("--workload", choices=["madelon", "planted", "omics", "manyjob", "scale"],
                     default="madelon")
     ap.add_argument("--no-compare", action="store_true",
-                    help="skip the Permut / exact / plain comparison legs")
+                    help="skip the other-mode / exact / plain comparison legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe-copy", type=int, default=0, metavar="BYTES",
                     help="only run the library's streaming copy kernel over BYTES bytes "
@@ -55,39 +58,62 @@ def probe_copy(nbytes):
 
 
 def workload(name):
+    """(jobs, run parameters, description, config keys) of a named workload."""
     from paper_2605_09950_amd import synth
-    idx = {"planted": 0, "madelon": 1, "omics": 2, "scale": 4}[name]
-    c = synth.config(idx)
-    pr = c["params"]
-    n, p = c["X"].shape
-    desc = {
-        "planted": "planted n=500 p=20 K=2, 64 bins, 50 trees depth 8",
-        "madelon": "MADELON-like n=10000 p=500 K=3 (20 informative, 80 mixes), 256 bins, "
-                   "200 trees depth 12",
-        "omics": "omics-shaped n=2000 p=20000 K=2 log-normal, 256 bins, 500 trees depth 12",
-        "scale": "mixed-type n=100000 p=2000 K=4, 256 bins, 300 trees depth 16",
-    }[name]
-    return c, pr, n, p, desc
+    if name == "manyjob":
+        cs = synth.many_jobs()
+        pr = cs[0]["params"]
+        desc = ("64 independent jobs, n in [200, 5000], p in [50, 2000], 2-5 classes, 256 "
+                "bins, 100 trees depth 10 each, Permut R=1, each job's own seed")
+        keys = {"jobs": 64, "n_trees": 100, "max_depth": 10, "n_bins": 256,
+                "seeds": "8000+j"}
+    else:
+        idx = {"planted": 0, "madelon": 1, "omics": 2, "scale": 4}[name]
+        cs = [synth.config(idx)]
+        pr = cs[0]["params"]
+        n, p = cs[0]["X"].shape
+        desc = {
+            "planted": "planted n=500 p=20 K=2, 64 bins, 50 trees depth 8",
+            "madelon": "MADELON-like n=10000 p=500 K=3 (20 informative, 80 mixes), 256 bins, "
+                       "200 trees depth 12",
+            "omics": "omics-shaped n=2000 p=20000 K=2 log-normal, 256 bins, 500 trees depth 12",
+            "scale": "mixed-type n=100000 p=2000 K=4, 256 bins, 300 trees depth 16",
+        }[name]
+        keys = {"n": n, "p": p, "n_trees": pr["n_trees"], "max_depth": pr["max_depth"],
+                "n_bins": pr["n_bins"], "seed": cs[0]["seed"]}
+    jobs = [dict(X=c["X"], y=c["y"], n_classes=c["n_classes"],
+                 n_trees=c["params"]["n_trees"], max_depth=c["params"]["max_depth"],
+                 mtry=c["params"]["mtry"], importance_mode=c["params"]["importance_mode"],
+                 max_iter=c["params"]["max_iter"], alpha=c["params"]["alpha"], seed=c["seed"])
+            for c in cs]
+    return jobs, pr, desc, keys
 
 
-def run_gpu(c, pr, mode, steps, warmup, form, rank, stats, graph=True):
+def run_gpu(jobs, pr, steps, warmup, form, rank, stats, graph=True):
+    """A session over device-resident inputs and a torch workspace: `warmup`
+    untimed steps, then up to `steps` timed ones.  Returns the timed
+    job-iterations, seconds, stats and the final decisions."""
     import torch
     from paper_2605_09950_amd import binding as B
-    dX = torch.from_numpy(c["X"]).cuda()
-    dy = torch.from_numpy(c["y"]).cuda()
-    job = dict(X=dX, y=dy, n_classes=c["n_classes"], n_trees=pr["n_trees"],
-               max_depth=pr["max_depth"], mtry=pr["mtry"], importance_mode=mode,
-               max_iter=min(1000, warmup + steps), alpha=pr["alpha"], seed=c["seed"])
-    shape = dict(n=dX.shape[0], p=dX.shape[1], **{k: v for k, v in job.items()
-                                                   if k not in ("X", "y")})
-    ws_bytes = B.boruta_workspace_size([shape], n_bins=pr["n_bins"], n_perm=pr["n_perm"])
+    dev, shapes = [], []
+    for jd in jobs:
+        d = dict(jd)
+        d["X"] = torch.from_numpy(jd["X"]).cuda()
+        d["y"] = torch.from_numpy(jd["y"]).cuda()
+        d["max_iter"] = min(jd["max_iter"], 1000, warmup + steps)
+        dev.append(d)
+        shapes.append(dict(n=d["X"].shape[0], p=d["X"].shape[1],
+                           **{k: v for k, v in d.items() if k not in ("X", "y")}))
+    ws_bytes = B.boruta_workspace_size(shapes, n_bins=pr["n_bins"], n_perm=pr["n_perm"])
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
-    sess = B.Session([job], n_bins=pr["n_bins"], n_perm=pr["n_perm"], split_rank=rank,
+    sess = B.Session(dev, n_bins=pr["n_bins"], n_perm=pr["n_perm"], split_rank=rank,
                      form=form, stats=stats, inputs_on_device=True, workspace=ws,
                      stream=stream, graph=graph)
+    live = len(jobs)
     for _ in range(warmup):
-        sess.step()
+        if live:
+            live = sess.step()
     torch.cuda.synchronize()
     if sess.stats is not None:  # count only the timed iterations
         for f in ("hist_large", "hist_small", "finalize", "permut"):
@@ -96,18 +122,19 @@ def run_gpu(c, pr, mode, steps, warmup, form, rank, stats, graph=True):
         sess.stats.iter_ms, sess.stats.iterations, sess.stats.nodes = 0.0, 0, 0
         for d in range(32):
             sess.stats.level_small[d] = sess.stats.level_large[d] = 0
-    done = 0
+    done, job_iters = 0, 0
     t0 = time.perf_counter()
     for _ in range(steps):
-        live = sess.step()
-        done += 1
         if live == 0:
             break
+        job_iters += live
+        live = sess.step()
+        done += 1
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    res = sess.result(0)
-    out = dict(steps=done, seconds=el, n_iter=res["n_iter"], stats=sess.stats,
-               decision=res["decision"])
+    decisions = [sess.result(j)["decision"] for j in range(len(jobs))]
+    out = dict(steps=done, job_iters=job_iters, seconds=el, stats=sess.stats,
+               decisions=decisions)
     sess.close()
     return out
 
@@ -130,30 +157,74 @@ def roofline(stats):
         for f in ("hist_large", "hist_small", "finalize", "permut")}
 
 
-def cpu_baseline(c, pr, mode):
-    """The CPU oracle, unchanged, on one whole iteration (iteration 1, every
-    tree) of the same workload, on all host threads.  Binning happens once
-    per job; it is timed separately and left out, as on the GPU side."""
+def cpu_baseline(name, jobs, pr):
+    """The CPU oracle, unchanged, on a bounded sample of the same workload on
+    all host threads: whole iterations in sequence (MADELON-like, planted)
+    until about 10 s have passed, a subset of the trees of iteration 1 scaled
+    to the whole forest (omics-shaped, mixed-type), or whole first iterations
+    of a subset of the jobs (many-job).  Binning happens once per job; it is
+    timed separately and left out, as on the GPU side."""
     import numpy as np
     from oracle import oracle as O
     cores = os.cpu_count() or 1
-    X, y = c["X"], c["y"]
-    p = X.shape[1]
-    st = np.zeros(p, np.int8)
-    ht = np.zeros(p, np.int32)
-    t0 = time.perf_counter()
-    O.bin_matrix(X, pr["n_bins"])
-    t_bin = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    O.boruta_step(X, y, c["n_classes"], pr["n_trees"], pr["max_depth"], 1, st, ht,
-                  mtry=pr["mtry"], importance_mode=mode, alpha=pr["alpha"], seed=c["seed"],
-                  n_bins=pr["n_bins"], n_perm=pr["n_perm"], n_threads=cores, trace=False)
-    t_iter = time.perf_counter() - t0 - t_bin
-    return {"value": round(1.0 / t_iter, 5), "unit": "iters/s", "cores": cores,
+
+    def step(jd, t, st, ht, trees=None):
+        return O.boruta_step(jd["X"], jd["y"], jd["n_classes"], jd["n_trees"],
+                             jd["max_depth"], t, st, ht, mtry=jd["mtry"],
+                             importance_mode=jd["importance_mode"], alpha=jd["alpha"],
+                             seed=jd["seed"], n_bins=pr["n_bins"], n_perm=pr["n_perm"],
+                             tree_subset=trees, n_threads=cores, trace=False)
+
+    def bin_time(jd):
+        t0 = time.perf_counter()
+        O.bin_matrix(jd["X"], pr["n_bins"])
+        return time.perf_counter() - t0
+
+    if name in ("madelon", "planted"):
+        jd = jobs[0]
+        p = jd["X"].shape[1]
+        st, ht = np.zeros(p, np.int8), np.zeros(p, np.int32)
+        t_bin, spent, it = bin_time(jd), 0.0, 0
+        while spent < 10.0 and it < jd["max_iter"]:
+            t0 = time.perf_counter()
+            r = step(jd, it + 1, st, ht)
+            spent += time.perf_counter() - t0 - t_bin
+            st, ht, it = r["state"], r["hits"], it + 1
+        return {"value": round(it / spent, 5), "unit": "iters/s", "cores": cores,
+                "kind": "oracle",
+                "sample": f"iterations 1..{it} in sequence (all {jd['n_trees']} trees each) on "
+                          f"{cores} threads: {spent:.2f}s; the once-per-job binning "
+                          f"({t_bin:.2f}s per call) is left out"}
+    if name in ("omics", "scale"):
+        jd = jobs[0]
+        p = jd["X"].shape[1]
+        k = min(jd["n_trees"], cores)
+        trees = list(range(k))
+        t_bin = bin_time(jd)
+        t0 = time.perf_counter()
+        step(jd, 1, np.zeros(p, np.int8), np.zeros(p, np.int32), trees)
+        spent = time.perf_counter() - t0 - t_bin
+        it_time = spent * jd["n_trees"] / k
+        return {"value": round(1.0 / it_time, 6), "unit": "iters/s", "cores": cores,
+                "kind": "oracle",
+                "sample": f"trees 0..{k - 1} of iteration 1 (one per thread, {cores} threads) "
+                          f"in {spent:.2f}s, scaled by {jd['n_trees']}/{k} to the whole forest; "
+                          f"binning ({t_bin:.2f}s) left out"}
+    # many-job: first iterations of the first jobs until about 10 s have passed
+    spent, done = 0.0, 0
+    for jd in jobs:
+        if spent >= 10.0:
+            break
+        p = jd["X"].shape[1]
+        t_bin = bin_time(jd)
+        t0 = time.perf_counter()
+        step(jd, 1, np.zeros(p, np.int8), np.zeros(p, np.int32))
+        spent += time.perf_counter() - t0 - t_bin
+        done += 1
+    return {"value": round(done / spent, 5), "unit": "job-iters/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"one whole iteration (t=1, all {pr['n_trees']} trees, shadows, "
-                      f"importance, decision) on {cores} threads: {t_iter:.2f}s; the once-per-"
-                      f"job binning ({t_bin:.2f}s) is left out"}
+            "sample": f"iteration 1 of jobs 0..{done - 1} (all 100 trees each, {cores} threads "
+                      f"per job) in {spent:.2f}s; binning left out"}
 
 
 def main():
@@ -169,53 +240,61 @@ def main():
     if args.probe_copy:
         probe_copy(args.probe_copy)
         return
-    c, pr, n, p, desc = workload(args.workload)
-    mode = B.TREEIMP if args.mode == "treeimp" else B.PERMUT
+    jobs, pr, desc, keys = workload(args.workload)
+    if args.mode != "workload":
+        for jd in jobs:
+            jd["importance_mode"] = B.TREEIMP if args.mode == "treeimp" else B.PERMUT
+    mode = jobs[0]["importance_mode"]
+    unit = "job-iters/s" if len(jobs) > 1 else "iters/s"
     # timed region: iterations replayed from the captured HIP graph
-    main_leg = run_gpu(c, pr, mode, args.steps, args.warmup, B.FORM_BATCHED, B.RANK_FP32,
+    main_leg = run_gpu(jobs, pr, args.steps, args.warmup, B.FORM_BATCHED, B.RANK_FP32,
                        stats=False, graph=True)
-    value = main_leg["steps"] / main_leg["seconds"]
+    value = main_leg["job_iters"] / main_leg["seconds"]
     # the same iterations launched eagerly with HIP events around every
     # forest kernel: per-kernel durations and algorithmic bytes
-    ev_leg = run_gpu(c, pr, mode, args.steps, args.warmup, B.FORM_BATCHED, B.RANK_FP32,
+    ev_leg = run_gpu(jobs, pr, args.steps, args.warmup, B.FORM_BATCHED, B.RANK_FP32,
                      stats=True, graph=False)
-    assert ev_leg["steps"] == main_leg["steps"]
-    assert (ev_leg["decision"] == main_leg["decision"]).all()
+    assert ev_leg["job_iters"] == main_leg["job_iters"]
+    assert all((a == b).all() for a, b in zip(ev_leg["decisions"], main_leg["decisions"]))
     roof, kernels = roofline(ev_leg["stats"])
-    extra = {"kernels": kernels, "timed_iterations": f"{args.warmup + 1}.."
-             f"{args.warmup + main_leg['steps']}",
-             "device_iter_ms": round(ev_leg["stats"].iter_ms / max(1, ev_leg["steps"]), 3),
-             "eager_iters_per_s": round(ev_leg["steps"] / ev_leg["seconds"], 3)}
     st = ev_leg["stats"]
-    extra["nodes_per_iteration_by_depth"] = {
-        "small": [round(st.level_small[d] / main_leg["steps"], 1)
-                  for d in range(pr["max_depth"])],
-        "large": [round(st.level_large[d] / main_leg["steps"], 1)
-                  for d in range(pr["max_depth"])]}
+    n_steps = max(1, ev_leg["steps"])
+    extra = {"kernels": kernels, "timed_iterations": f"{args.warmup + 1}.."
+             f"{args.warmup + main_leg['steps']}", "job_iterations": main_leg["job_iters"],
+             "device_iter_ms": round(st.iter_ms / n_steps, 3),
+             "eager_" + unit.replace("/", "_per_"): round(ev_leg["job_iters"] /
+                                                         ev_leg["seconds"], 3),
+             "nodes_per_step_by_depth": {
+                 "small": [round(st.level_small[d] / n_steps, 1)
+                           for d in range(max(j["max_depth"] for j in jobs))],
+                 "large": [round(st.level_large[d] / n_steps, 1)
+                           for d in range(max(j["max_depth"] for j in jobs))]}}
     if not args.no_compare:
         k = max(1, min(5, args.steps))
-        other = B.PERMUT if mode == B.TREEIMP else B.TREEIMP
-        leg = run_gpu(c, pr, other, k, args.warmup, B.FORM_BATCHED, B.RANK_FP32, stats=False)
-        extra["other_mode_iters_per_s"] = round(leg["steps"] / leg["seconds"], 3)
-        leg = run_gpu(c, pr, mode, k, args.warmup, B.FORM_BATCHED, B.RANK_EXACT, stats=False)
-        extra["exact_rank_iters_per_s"] = round(leg["steps"] / leg["seconds"], 3)
-        leg = run_gpu(c, pr, mode, 1, 1, B.FORM_PLAIN, B.RANK_FP32, stats=False)
-        extra["plain_form_iters_per_s"] = round(leg["steps"] / leg["seconds"], 4)
+        other = [dict(jd, importance_mode=1 - jd["importance_mode"]) for jd in jobs]
+        leg = run_gpu(other, pr, k, args.warmup, B.FORM_BATCHED, B.RANK_FP32, stats=False)
+        extra["other_mode_" + unit.replace("/", "_per_")] = round(
+            leg["job_iters"] / leg["seconds"], 3)
+        leg = run_gpu(jobs, pr, k, args.warmup, B.FORM_BATCHED, B.RANK_EXACT, stats=False)
+        extra["exact_rank_" + unit.replace("/", "_per_")] = round(
+            leg["job_iters"] / leg["seconds"], 3)
+        leg = run_gpu(jobs, pr, 1, 1, B.FORM_PLAIN, B.RANK_FP32, stats=False)
+        extra["plain_form_" + unit.replace("/", "_per_")] = round(
+            leg["job_iters"] / leg["seconds"], 4)
     line = {
-        "metric": METRIC, "value": round(value, 3), "unit": "iters/s", "n_gpus": 1,
+        "metric": METRIC, "value": round(value, 3), "unit": unit, "n_gpus": 1,
         "steps": main_leg["steps"], "warmup": args.warmup,
-        "ms_per_step": round(1e3 * main_leg["seconds"] / main_leg["steps"], 3),
+        "ms_per_step": round(1e3 * main_leg["seconds"] / max(1, main_leg["steps"]), 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": desc + (", TreeImp" if mode == B.TREEIMP else ", Permut R=1") +
-                   ", batched form, FP32 ranking + exact recheck", "n": n, "p": p,
-                   "n_trees": pr["n_trees"], "max_depth": pr["max_depth"],
-                   "n_bins": pr["n_bins"], "seed": c["seed"]},
+        "config": dict({"workload": desc + (", TreeImp" if mode == B.TREEIMP else
+                                            f", Permut R={pr['n_perm']}") +
+                        ", batched form, FP32 ranking + exact recheck"}, **keys),
         "roofline": roof,
         "extra": extra,
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(c, pr, mode)
+        line["cpu_baseline"] = cpu_baseline(args.workload, jobs, pr)
     print(json.dumps(line), flush=True)
 
 

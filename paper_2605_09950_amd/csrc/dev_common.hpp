@@ -247,7 +247,7 @@ struct JobDev {
     uint32_t* oob;         // [T][n] out-of-bag rows, ascending
     int32_t* tstat;        // [T][4] distinct in-bag, OOB rows, OOB correct, spare
     // per iteration, written on the device
-    int32_t t, p_cur, n_sha, p_w, mtry, ntiles, n_undecided, live;
+    int32_t t, p_cur, n_sha, p_w, mtry, pad_i, n_undecided, live;
 };
 
 struct TreeDev {
@@ -268,16 +268,10 @@ struct NodeDev {
     uint8_t depth;
 };
 
-struct Item {
-    uint32_t node, slot, tile, pad;
-};
-
 // Per-level counters: the lists of tree level d (small nodes, large-node
-// slots, (node, tile) items) are counted in ctrs[d]; they are zeroed once per
-// iteration.
+// slots) are counted in ctrs[d]; they are zeroed once per iteration.
 struct LevelCtr {
-    uint32_t unused;
-    uint32_t n_items;   // (large node, feature tile) items
+    uint32_t unused[2];
     uint32_t n_slots;   // large nodes
     uint32_t n_small;   // small nodes
     uint32_t overflow;  // a capacity check failed
@@ -301,24 +295,25 @@ struct ForestDev {
     NodeDev* nodes;
     uint32_t* cls;        // [node][kmax] weighted class counts
     uint64_t* ngain;      // [node] fixed-point Gini decrease of a split node
-    Cand* cand;           // [slot][max_tiles] best candidate of each feature tile
-    uint32_t* cand_cl;    // [slot][max_tiles][kmax] left class counts of that candidate
+    Cand* cand;           // [slot][npi] best candidate of each histogram item
+    uint32_t* cand_cl;    // [slot][npi][kmax] left class counts of that candidate
+    uint32_t* feat;       // [slot][mtry_cap] the node's drawn features, draw order
     const uint32_t* slot_node_in;  // [slot] node of each large-node slot of this level
     uint32_t* slot_node_out;       // [slot] the same for the next level
-    const Item* items_in;
     const uint32_t* small_in;
-    Item* items_out;
     uint32_t* small_out;
     LevelCtr* ctr;        // counters the current launch appends to (set per kernel)
     LevelCtr* ctrs;       // [levels + 1]: ctrs[d] counts the lists of tree level d
     uint32_t n_roots;     // trees of the iteration (= root nodes [0, n_roots))
     uint64_t* alg_bytes;  // [2][64] algorithmic bytes (large, small), nullable; the
                           // 64 words per kernel spread the atomics
-    uint32_t node_cap, item_cap, slot_cap, small_cap;
+    uint32_t node_cap, slot_cap, small_cap;
     uint32_t next_base;   // first node index of the next level
     uint32_t n_small_cur; // small nodes searched in this level
     uint32_t small_ncap;  // a node takes the wave path only below this weighted count
-    int32_t kmax, ft, max_tiles, parity, split_rank, pad;
+    int32_t kmax, ft, parity, split_rank;
+    int32_t npi;          // histogram items per large node (draw positions / FW)
+    int32_t mtry_cap;     // row stride of feat
 };
 
 }  // namespace boruta

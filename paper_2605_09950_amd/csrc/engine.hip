@@ -25,7 +25,7 @@ void launch_labels(const int32_t*, size_t, uint8_t*, hipStream_t);
 void launch_binning(const float*, int64_t, int64_t, int, uint8_t*, int64_t, uint32_t*, int64_t,
                     hipStream_t);
 void launch_thresholds(int32_t, int64_t, uint64_t, int32_t, int32_t*, int32_t*, hipStream_t);
-void launch_active(JobDev*, int, int, hipStream_t);
+void launch_active(JobDev*, int, hipStream_t);
 void launch_shadow(JobDev*, int, int64_t, int, hipStream_t);
 void launch_boot_draw(JobDev*, const TreeDev*, int, int64_t, hipStream_t);
 void launch_fill_u32(uint32_t*, size_t, uint32_t, hipStream_t);
@@ -34,6 +34,7 @@ void launch_boot_compact(const ForestDev&, uint32_t, hipStream_t);
 void launch_split_small(const ForestDev&, int, uint32_t, uint32_t, uint32_t, hipStream_t);
 void launch_hist_tile(const ForestDev&, int, uint32_t, uint32_t, uint32_t, int, hipStream_t);
 void launch_split_finalize(const ForestDev&, int, uint32_t, uint32_t, uint32_t, hipStream_t);
+void launch_draws(const ForestDev&, int, uint32_t, hipStream_t);
 // k_importance.hip
 void launch_tree_totals(JobDev*, const TreeDev*, int, uint64_t*, hipStream_t);
 void launch_treeimp(JobDev*, const TreeDev*, int, const uint64_t*, int, hipStream_t);
@@ -134,17 +135,18 @@ struct Region {
 
 struct JobPlan {
     int64_t n_pad, P;
-    int max_sha, pw_cap, mtry_max, ntiles_max;
+    int max_sha, pw_cap, mtry_max;
     size_t X, y32, y8, orig, sha, colptr, colsrc, act, state, hits, hist, smax, hconf, hrej, G,
         imp, wbuf, rec0, rec1, oob, tstat;
 };
 
 struct Plan {
     std::vector<JobPlan> jp;
-    size_t keys, jobs, trees, tree_base, flags, nodes, cls, ngain, items0, items1, small0,
-        small1, cand, cand_cl, slot0, slot1, ctrs, alg, tot;
-    uint32_t node_cap = 0, item_cap = 0, slot_cap = 0, small_cap = 0;
-    int kmax = 4, ft = 8, max_tiles = 1, max_sha = 1, max_pw = 1, max_D = 1, T_total = 0;
+    size_t keys, jobs, trees, tree_base, flags, nodes, cls, ngain, small0, small1, cand, cand_cl,
+        feat, slot0, slot1, ctrs, alg, tot;
+    uint32_t node_cap = 0, slot_cap = 0, small_cap = 0;
+    int kmax = 4, ft = 8, max_sha = 1, max_pw = 1, max_D = 1, T_total = 0, mtry_cap = 1,
+        npi = 1;
     int64_t max_n = 0;
     size_t total = 0;
 };
@@ -161,7 +163,7 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     pl.kmax = maxK <= 2 ? 2 : (maxK <= 4 ? 4 : (maxK <= 8 ? 8 : 16));
     pl.ft = 32 / pl.kmax;  // feature columns per histogram tile (32 KB of LDS at 256 bins)
     pl.keys = r.take((size_t)keys_words * 4);
-    uint64_t node_cap = 0, item_cap = 0, slot_cap = 0, small_cap = 0;
+    uint64_t node_cap = 0, slot_cap = 0, small_cap = 0;
     for (const Spec& s : specs) {
         JobPlan j;
         j.n_pad = round_up(s.n, 256);
@@ -169,7 +171,6 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
         j.max_sha = (int)std::max<int64_t>(s.p, 8);
         j.pw_cap = (int)(s.p + j.max_sha);
         j.mtry_max = s.mtry > 0 ? std::min(s.mtry, j.pw_cap) : isqrt_i(j.pw_cap);
-        j.ntiles_max = (j.mtry_max + pl.ft - 1) / pl.ft;
         const size_t n = (size_t)s.n, p = (size_t)s.p, T = (size_t)s.T;
         j.X = inputs_on_device ? 0 : r.take(n * p * 4);
         j.y32 = inputs_on_device ? 0 : r.take(n * 4);
@@ -200,19 +201,20 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
         node_cap += T + 2 * T * per_tree_nodes;
         const uint64_t large_per_tree = (uint64_t)(s.n + kSmallRows) / (kSmallRows + 1);
         slot_cap += T * large_per_tree;
-        item_cap += T * large_per_tree * (uint64_t)j.ntiles_max;
         small_cap += T * (uint64_t)((s.n + 1) / 2);
-        pl.max_tiles = std::max(pl.max_tiles, j.ntiles_max);
         pl.max_sha = std::max(pl.max_sha, j.max_sha);
         pl.max_pw = std::max(pl.max_pw, j.pw_cap);
+        pl.mtry_cap = std::max(pl.mtry_cap, j.mtry_max);
         pl.max_D = std::max(pl.max_D, s.D);
         pl.max_n = std::max(pl.max_n, s.n);
         pl.T_total += s.T;
     }
-    if (node_cap >= 0xFFFFFFF0ull || item_cap >= 0xFFFFFFF0ull || small_cap >= 0xFFFFFFF0ull)
+    // histogram items per large node: FW = 8 / kmax draws each (1 for 16 classes)
+    pl.npi = (pl.mtry_cap + (pl.kmax <= 8 ? 8 / pl.kmax : 1) - 1) / (pl.kmax <= 8 ? 8 / pl.kmax : 1);
+    if (node_cap >= 0xFFFFFFF0ull || slot_cap * (uint64_t)pl.npi >= 0xFFFFFFF0ull ||
+        small_cap >= 0xFFFFFFF0ull)
         throw Error(BORUTA_E_INVALID_ARG, "problem too large: more than 2^32 tree nodes");
     pl.node_cap = (uint32_t)node_cap;
-    pl.item_cap = (uint32_t)item_cap;
     pl.slot_cap = (uint32_t)slot_cap;
     pl.small_cap = (uint32_t)small_cap;
     pl.jobs = r.take(specs.size() * sizeof(JobDev));
@@ -222,12 +224,11 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     pl.nodes = r.take((size_t)pl.node_cap * sizeof(NodeDev));
     pl.cls = r.take((size_t)pl.node_cap * pl.kmax * 4);
     pl.ngain = r.take((size_t)pl.node_cap * 8);
-    pl.items0 = r.take((size_t)pl.item_cap * sizeof(Item));
-    pl.items1 = r.take((size_t)pl.item_cap * sizeof(Item));
     pl.small0 = r.take((size_t)pl.small_cap * 4);
     pl.small1 = r.take((size_t)pl.small_cap * 4);
-    pl.cand = r.take((size_t)pl.slot_cap * pl.max_tiles * sizeof(Cand));
-    pl.cand_cl = r.take((size_t)pl.slot_cap * pl.max_tiles * pl.kmax * 4);
+    pl.cand = r.take((size_t)pl.slot_cap * pl.npi * sizeof(Cand));
+    pl.cand_cl = r.take((size_t)pl.slot_cap * pl.npi * pl.kmax * 4);
+    pl.feat = r.take((size_t)pl.slot_cap * pl.mtry_cap * 4);
     pl.slot0 = r.take((size_t)pl.slot_cap * 4);
     pl.slot1 = r.take((size_t)pl.slot_cap * 4);
     // level d < max_D reads ctrs[d] and appends to ctrs[d + 1]
@@ -474,17 +475,18 @@ ForestDev Engine::forest() const {
     F.ngain = at<uint64_t>(pl.ngain);
     F.cand = at<Cand>(pl.cand);
     F.cand_cl = at<uint32_t>(pl.cand_cl);
+    F.feat = at<uint32_t>(pl.feat);
+    F.npi = pl.npi;
+    F.mtry_cap = pl.mtry_cap;
     F.ctrs = at<LevelCtr>(pl.ctrs);
     F.ctr = F.ctrs;
     F.n_roots = (uint32_t)pl.T_total;
     F.alg_bytes = O.stats ? at<uint64_t>(pl.alg) : nullptr;
     F.node_cap = pl.node_cap;
-    F.item_cap = pl.item_cap;
     F.slot_cap = pl.slot_cap;
     F.small_cap = pl.small_cap;
     F.kmax = pl.kmax;
     F.ft = pl.ft;
-    F.max_tiles = pl.max_tiles;
     F.split_rank = O.split_rank;
     // the wave path packs class counters in 16-bit fields (8-bit for 3-4 classes)
     F.small_ncap = pl.kmax == 4 ? 256u : 65536u;
@@ -492,21 +494,17 @@ ForestDev Engine::forest() const {
 }
 
 void Engine::grow_level_plain(const ForestDev& F, int level) {
-    // One launch (or, for a large node, one histogram launch over its tiles
-    // and one finalize launch) per node: the level's counters and node lists
-    // are read back and each node is its own launch.
+    // One launch (or, for a large node, one histogram launch over its column
+    // groups and one finalize launch) per node: the level's counters are read
+    // back and each node is its own launch.
     LevelCtr c;
     d2h(&c, F.ctrs + level, sizeof(c));
     if (c.overflow) return;  // reported after the iteration
-    std::vector<Item> items(c.n_items);
-    if (c.n_items) d2h(items.data(), F.items_in, c.n_items * sizeof(Item));
     for (uint32_t i = 0; i < c.n_small; ++i) launch_split_small(F, level, i, 1, 1, st);
-    for (uint32_t a = 0; a < c.n_items;) {
-        uint32_t b = a + 1;
-        while (b < c.n_items && items[b].node == items[a].node) ++b;
-        launch_hist_tile(F, level, a, b - a, b - a, O.B, st);
-        launch_split_finalize(F, level, items[a].slot, 1, 1, st);
-        a = b;
+    if (c.n_slots) launch_draws(F, level, 1, st);
+    for (uint32_t sl = 0; sl < c.n_slots; ++sl) {
+        launch_hist_tile(F, level, sl * pl.npi, pl.npi, (pl.npi + 3) / 4, O.B, st);
+        launch_split_finalize(F, level, sl, 1, 1, st);
     }
 }
 
@@ -531,7 +529,7 @@ void Engine::enqueue_iteration() {
     TreeDev* dtrees = at<TreeDev>(pl.trees);
     boruta_stats* stats = O.stats;
     const size_t h_whole = clock.begin(&iter_stat, st);
-    launch_active(djobs, nj, pl.ft, st);
+    launch_active(djobs, nj, st);
     launch_shadow(djobs, nj, pl.max_n, pl.max_sha, st);
     launch_boot_draw(djobs, dtrees, (int)n_trees, pl.max_n, st);
 
@@ -540,23 +538,21 @@ void Engine::enqueue_iteration() {
     const int n_levels = pl.max_D;
     launch_fill_u32((uint32_t*)F.ctrs, (size_t)(n_levels + 1) * sizeof(LevelCtr) / 4, 0u, st);
     uint32_t* slots[2] = {at<uint32_t>(pl.slot0), at<uint32_t>(pl.slot1)};
-    Item* items[2] = {at<Item>(pl.items0), at<Item>(pl.items1)};
     uint32_t* small[2] = {at<uint32_t>(pl.small0), at<uint32_t>(pl.small1)};
     // the roots go to the level-0 lists (parity 0)
-    F.items_out = items[0];
     F.small_out = small[0];
     F.slot_node_out = slots[0];
     launch_boot_compact(F, n_trees, st);
     const uint32_t g_small = level_grid(pl.small_cap, 4, 2048);
-    const uint32_t g_tile = level_grid(pl.item_cap, 1, 2560);
+    // a multiple of 8: workgroup b serves the node slots congruent to b mod 8
+    const uint32_t g_tile = (level_grid((uint64_t)pl.slot_cap * pl.npi, 4, 2560) + 7) / 8 * 8;
+    const uint32_t g_draw = level_grid(pl.slot_cap, 4, 1024);
     const uint32_t g_fin = level_grid(pl.slot_cap, 1, 1024);
     for (int d = 0; d < n_levels; ++d) {
         // lists, slots and row records of level d are read from parity d & 1
         // and the children of level d go to the other parity
-        F.items_in = items[d & 1];
         F.small_in = small[d & 1];
         F.slot_node_in = slots[d & 1];
-        F.items_out = items[(d + 1) & 1];
         F.small_out = small[(d + 1) & 1];
         F.slot_node_out = slots[(d + 1) & 1];
         F.parity = d & 1;
@@ -567,6 +563,7 @@ void Engine::enqueue_iteration() {
         size_t h = clock.begin(stats ? &stats->hist_small : nullptr, st);
         launch_split_small(F, d, 0, kAll, g_small, st);
         clock.end(h, st);
+        launch_draws(F, d, g_draw, st);
         h = clock.begin(stats ? &stats->hist_large : nullptr, st);
         launch_hist_tile(F, d, 0, kAll, g_tile, O.B, st);
         clock.end(h, st);

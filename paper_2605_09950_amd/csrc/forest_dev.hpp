@@ -199,10 +199,6 @@ __device__ __forceinline__ uint32_t level_small(const ForestDev& F, int level) {
     const LevelCtr& c = F.ctrs[level];
     return c.overflow ? 0u : min(c.n_small, F.small_cap);
 }
-__device__ __forceinline__ uint32_t level_items(const ForestDev& F, int level) {
-    const LevelCtr& c = F.ctrs[level];
-    return c.overflow ? 0u : min(c.n_items, F.item_cap);
-}
 __device__ __forceinline__ uint32_t level_slots(const ForestDev& F, int level) {
     const LevelCtr& c = F.ctrs[level];
     return c.overflow ? 0u : min(c.n_slots, F.slot_cap);
@@ -256,14 +252,12 @@ __device__ inline void put_small(const ForestDev& F, uint32_t pos, uint32_t idx)
         atomicOr(&F.ctr->overflow, 1u);
 }
 
-__device__ inline void put_large(const ForestDev& F, uint32_t slot, uint32_t item,
-                                 uint32_t ntiles, uint32_t idx) {
-    if (slot >= F.slot_cap || item + ntiles > F.item_cap) {
+__device__ inline void put_large(const ForestDev& F, uint32_t slot, uint32_t idx) {
+    if (slot >= F.slot_cap) {
         atomicOr(&F.ctr->overflow, 2u);
         return;
     }
     F.slot_node_out[slot] = idx;
-    for (uint32_t tl = 0; tl < ntiles; ++tl) F.items_out[item + tl] = Item{idx, slot, tl, 0};
 }
 
 // Reserve list positions for up to two new nodes (one atomic per list) and
@@ -275,16 +269,11 @@ __device__ inline void enqueue_nodes(const ForestDev& F, const JobDev& J, uint32
         ns += kinds[c] == kSmall;
         nl += kinds[c] == kLarge;
     }
-    const uint32_t nt = (uint32_t)J.ntiles;
     uint32_t ps = ns ? atomicAdd(&F.ctr->n_small, ns) : 0u;
     uint32_t pl = nl ? atomicAdd(&F.ctr->n_slots, nl) : 0u;
-    uint32_t pi = nl ? atomicAdd(&F.ctr->n_items, nl * nt) : 0u;
     for (int c = 0; c < count; ++c) {
         if (kinds[c] == kSmall) put_small(F, ps++, idx0 + c);
-        if (kinds[c] == kLarge) {
-            put_large(F, pl++, pi, nt, idx0 + c);
-            pi += nt;
-        }
+        if (kinds[c] == kLarge) put_large(F, pl++, idx0 + c);
     }
 }
 

@@ -111,7 +111,6 @@ __global__ __launch_bounds__(1024) void k_boot_compact(ForestDev F0) {
 struct SmallOut {
     int kinds[2];
     uint32_t child;
-    uint32_t ntiles;
     uint64_t alg;
 };
 
@@ -288,7 +287,6 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out) {
     }
     const Cand best = fp32 ? wave_best_total_fp32(lb, lb.nl != 0 ? lq : -1.0f)
                            : wave_best_total_exact(lb);
-    out.ntiles = (uint32_t)J.ntiles;
     out.alg = (uint64_t)len * (uint64_t)(J.mtry + 6);
     if (best.nl == 0 || !cand_positive(best, S, N)) {  // stays the leaf it was created as
         if (lane == 0) mark_unused_pair(F, out.child);
@@ -333,7 +331,7 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out) {
 template <int KMAX>
 __global__ __launch_bounds__(256) void k_split_small(ForestDev F0, int level, uint32_t first,
                                                      uint32_t count) {
-    __shared__ uint32_t s_ns[4], s_nl[4], s_ni[4], s_base[3];
+    __shared__ uint32_t s_ns[4], s_nl[4], s_base[2];
     __shared__ unsigned long long s_alg[4];
     const ForestDev F = level_view(F0, level);
     if (count == 0xFFFFFFFFu) {
@@ -346,41 +344,34 @@ __global__ __launch_bounds__(256) void k_split_small(ForestDev F0, int level, ui
     SmallOut o;
     o.kinds[0] = o.kinds[1] = kLeaf;
     o.child = 0;
-    o.ntiles = 0;
     o.alg = 0;
     if (li < count) small_node<KMAX>(F, first + li, o);
     if (lane == 0) {
         s_ns[wave] = (o.kinds[0] == kSmall) + (o.kinds[1] == kSmall);
         s_nl[wave] = (o.kinds[0] == kLarge) + (o.kinds[1] == kLarge);
-        s_ni[wave] = s_nl[wave] * o.ntiles;
+
         s_alg[wave] = o.alg;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         const uint32_t ts = s_ns[0] + s_ns[1] + s_ns[2] + s_ns[3];
         const uint32_t tl = s_nl[0] + s_nl[1] + s_nl[2] + s_nl[3];
-        const uint32_t ti = s_ni[0] + s_ni[1] + s_ni[2] + s_ni[3];
         s_base[0] = ts ? atomicAdd(&F.ctr->n_small, ts) : 0u;
         s_base[1] = tl ? atomicAdd(&F.ctr->n_slots, tl) : 0u;
-        s_base[2] = ti ? atomicAdd(&F.ctr->n_items, ti) : 0u;
         if (F.alg_bytes)
             atomicAdd((unsigned long long*)&F.alg_bytes[64 + (blockIdx.x & 63)],
                       s_alg[0] + s_alg[1] + s_alg[2] + s_alg[3]);
     }
     __syncthreads();
     if (lane == 0 && li < count) {
-        uint32_t ps = s_base[0], pl = s_base[1], pi = s_base[2];
+        uint32_t ps = s_base[0], pl = s_base[1];
         for (int v = 0; v < wave; ++v) {
             ps += s_ns[v];
             pl += s_nl[v];
-            pi += s_ni[v];
         }
         for (int c = 0; c < 2; ++c) {
             if (o.kinds[c] == kSmall) put_small(F, ps++, o.child + c);
-            if (o.kinds[c] == kLarge) {
-                put_large(F, pl++, pi, o.ntiles, o.child + c);
-                pi += o.ntiles;
-            }
+            if (o.kinds[c] == kLarge) put_large(F, pl++, o.child + c);
         }
     }
     __syncthreads();  // the shared counts are reused by the next batch
@@ -544,110 +535,142 @@ __device__ Cand feature_best(const uint32_t* h, int B, int q, int f, const uint3
     return wave_best_exact(lb);
 }
 
-// Large nodes, phase 1: one workgroup per (node, feature tile).  FT columns
-// per tile keep the LDS histogram at FT * KMAX * 256 * 4 = 32 KB; the class-
-// major rows spread a wave's atomics over the banks by bin.
+// Large nodes, phase 0: one wavefront per node draws its mtry features
+// (the keyed permutation of the node's heap id, in draw order).
+__global__ __launch_bounds__(256) void k_draws(ForestDev F, int level) {
+    const uint32_t count = level_slots(F, level);
+    const int lane = threadIdx.x & 63;
+    const uint32_t w0 = blockIdx.x * 4u + uniform(threadIdx.x >> 6);
+    for (uint32_t slot = w0; slot < count; slot += gridDim.x * 4u) {
+        const NodeDev nd = F.nodes[F.slot_node_in[slot]];
+        const TreeDev tr = F.trees[nd.tree];
+        const JobDev& J = F.jobs[tr.job];
+        const KeyedPerm P = make_perm(J.seed_lo, J.seed_hi, kMtry, (uint32_t)J.t,
+                                      (uint32_t)tr.tau, nd.heap, 0u, (uint64_t)J.p_w);
+        uint32_t* out = F.feat + (size_t)slot * F.mtry_cap;
+        for (int q = lane; q < J.mtry; q += 64) out[q] = perm_apply(P, (uint32_t)q);
+    }
+}
+
+// Large nodes, phase 1: one wavefront per (node, FW consecutive draws)
+// item, with its own LDS histogram [FW][KMAX][256] (8 KB; 16 KB for 9-16
+// classes).  The wave gathers the bins of its features at the node's rows,
+// accumulates the weighted class counts with LDS atomics (class-major rows
+// spread a wave's atomics over the banks by bin), scans each feature and
+// writes the item's best candidate and its left class counts.  No barriers:
+// the four waves of a workgroup are independent.
 template <int KMAX>
 __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint32_t first,
                                                    uint32_t count) {
-    constexpr int FT = 32 / KMAX;
-    extern __shared__ uint4 hist_raw[];  // [FT][KMAX][256] class counts (16-byte aligned)
-    uint32_t* hist = reinterpret_cast<uint32_t*>(hist_raw);
-    __shared__ const uint8_t* s_col[FT];
-    __shared__ int s_feat[FT];
-    __shared__ Cand s_fbest[FT];
-    __shared__ int s_bi;
+    constexpr int FW = KMAX <= 8 ? 8 / KMAX : 1;
+    constexpr int WORDS = FW * KMAX * 256;
+    constexpr int RB = 4;  // rows per lane per batch: RB record loads, RB * FW gathers in flight
+    extern __shared__ uint4 lds_raw[];
+    const int lane = threadIdx.x & 63, wave = (int)uniform(threadIdx.x >> 6);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(lds_raw) + wave * WORDS;
+    const uint32_t npi = (uint32_t)F.npi;
+    // Work of a level: node slots [0, n) with npi items each.  Workgroup b
+    // takes the slots congruent to b mod 8 (the grid is a multiple of 8), and
+    // its waves walk those slots' items in order, so a node's items run side
+    // by side in one XCD and share its records through that XCD's L2 when the
+    // hardware deals workgroups round-robin to the 8 XCDs (any mapping gives
+    // the same results: every item is visited once).  With an explicit count,
+    // items [first, first + count) are walked directly (plain form).
+    uint32_t n_slots, x = 0, r, R, m_end;
     if (count == 0xFFFFFFFFu) {
-        first = 0;
-        count = level_items(F, level);
+        n_slots = level_slots(F, level);
+        x = blockIdx.x % 8u;
+        r = (blockIdx.x / 8u) * 4u + (uint32_t)wave;
+        R = (gridDim.x / 8u) * 4u;
+        m_end = n_slots > x ? (n_slots - x + 7u) / 8u * npi : 0u;
+    } else {
+        r = blockIdx.x * 4u + (uint32_t)wave;
+        R = gridDim.x * 4u;
+        m_end = count;
     }
-    for (uint32_t k = blockIdx.x; k < count; k += gridDim.x) {
-    const uint32_t item = first + k;
-    const Item it = F.items_in[item];
-    const NodeDev nd = F.nodes[it.node];
-    const TreeDev tr = F.trees[nd.tree];
-    const JobDev& J = F.jobs[tr.job];
-    const int B = J.B, tid = threadIdx.x, lane = tid & 63, wave = (int)uniform(tid >> 6);
-    const int q0 = (int)it.tile * FT;
-    const int nf = min(FT, J.mtry - q0);
-    if (tid < nf) {
-        const KeyedPerm P = make_perm(J.seed_lo, J.seed_hi, kMtry, (uint32_t)J.t,
-                                      (uint32_t)tr.tau, nd.heap, 0u, (uint64_t)J.p_w);
-        const int f = (int)perm_apply(P, (uint32_t)(q0 + tid));
-        s_feat[tid] = f;
-        s_col[tid] = ldg(J.colptr + f);
-    }
-    for (int i = tid; i < FT * KMAX * 64; i += 256)
-        reinterpret_cast<uint4*>(hist)[i] = make_uint4(0u, 0u, 0u, 0u);
-    __syncthreads();
-    const uint8_t* col[FT];
+    for (uint32_t m = r; m < m_end; m += R) {
+        const uint32_t item = count == 0xFFFFFFFFu ? (8u * (m / npi) + x) * npi + m % npi
+                                                   : first + m;
+        const uint32_t slot = item / npi, j = item % npi;
+        const uint32_t id = uniform(F.slot_node_in[slot]);
+        const NodeDev nd = F.nodes[id];
+        const TreeDev tr = F.trees[nd.tree];
+        const JobDev& J = F.jobs[tr.job];
+        const int q0 = (int)j * FW;
+        if (q0 >= J.mtry) continue;  // the job draws fewer features this iteration
+        const int nf = min(FW, J.mtry - q0);
+        const uint32_t* drawn = F.feat + (size_t)slot * F.mtry_cap + q0;
+        int fq[FW];
+        const uint8_t* col[FW];
 #pragma unroll
-    for (int q = 0; q < FT; ++q) col[q] = q < nf ? s_col[q] : s_col[0];
-    const uint64_t* recs = J.rec[F.parity] + (size_t)tr.tau * J.n + nd.seg;
-    const uint32_t len = nd.len;
-    // two rows per thread per pass: up to 2 * FT bin gathers in flight
-    for (uint32_t i0 = tid; i0 < len; i0 += 512) {
-        const uint32_t i1 = i0 + 256;
-        const bool v1 = i1 < len;
-        const uint64_t r0 = ldg(recs + i0);
-        const uint64_t r1 = v1 ? ldg(recs + i1) : r0;
-        const uint32_t row0 = rec_row(r0), row1 = rec_row(r1);
-        uint32_t b0[FT], b1[FT];
-#pragma unroll
-        for (int q = 0; q < FT; ++q) {
-            b0[q] = ldg(col[q] + row0);
-            b1[q] = ldg(col[q] + row1);
+        for (int u = 0; u < FW; ++u) {
+            fq[u] = (int)uniform(ldg(drawn + (u < nf ? u : 0)));
+            col[u] = ldg(J.colptr + fq[u]);
         }
-        const uint32_t w0 = rec_w(r0), y0 = rec_y(r0);
-        const uint32_t w1 = v1 ? rec_w(r1) : 0u, y1 = rec_y(r1);
 #pragma unroll
-        for (int q = 0; q < FT; ++q) {
-            if (q < nf) {
-                atomicAdd(&hist[(q * KMAX + y0) * 256 + b0[q]], w0);
-                if (v1) atomicAdd(&hist[(q * KMAX + y1) * 256 + b1[q]], w1);
+        for (int i = 0; i < WORDS / 256; ++i)
+            reinterpret_cast<uint4*>(hist)[i * 64 + lane] = make_uint4(0u, 0u, 0u, 0u);
+        const uint64_t* recs = J.rec[F.parity] + (size_t)tr.tau * J.n + nd.seg;
+        const uint32_t len = uniform(nd.len);
+        for (uint32_t i0 = 0; i0 < len; i0 += 64 * RB) {
+            uint64_t r[RB];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const uint32_t i = i0 + u * 64 + lane;
+                r[u] = i < len ? ldg(recs + i) : 0ull;
+            }
+            uint32_t b[RB][FW];
+#pragma unroll
+            for (int u = 0; u < RB; ++u)
+#pragma unroll
+                for (int v = 0; v < FW; ++v) b[u][v] = ldg(col[v] + rec_row(r[u]));
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const uint32_t w = rec_w(r[u]), y = rec_y(r[u]);  // padding rows: w = 0
+#pragma unroll
+                for (int v = 0; v < FW; ++v)
+                    if (v < nf && w) atomicAdd(&hist[(v * KMAX + y) * 256 + b[u][v]], w);
             }
         }
-    }
-    __syncthreads();
-    uint32_t cnode[KMAX];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        uint32_t cnode[KMAX];
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) cnode[k] = k < J.K ? F.cls[(size_t)it.node * F.kmax + k] : 0u;
-    const uint32_t N = nd.n;
-    for (int q = wave; q < nf; q += 4) {
-        const Cand fb =
-            feature_best<KMAX>(hist + q * KMAX * 256, B, q0 + q, s_feat[q], cnode, N, F.split_rank);
-        if (lane == 0) s_fbest[q] = fb;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        int bi = 0;  // earliest draw among equal scores: strict comparison
-        for (int q = 1; q < nf; ++q)
-            if (s_fbest[q].nl != 0 &&
-                (s_fbest[bi].nl == 0 || cand_better(s_fbest[q], s_fbest[bi])))
-                bi = q;
-        s_bi = bi;
-        F.cand[(size_t)it.slot * F.max_tiles + it.tile] = s_fbest[bi];
-        if (F.alg_bytes)
-            atomicAdd((unsigned long long*)&F.alg_bytes[item & 63],
-                      (unsigned long long)len * (unsigned long long)(nf + (it.tile == 0 ? 6 : 0)));
-    }
-    __syncthreads();
-    if (wave == 0) {
-        // left class counts of the tile's candidate, for the partition step
-        const int bi = s_bi;
-        const int bt = s_fbest[bi].nl != 0 ? s_fbest[bi].b : -1;
-        uint32_t* out = F.cand_cl + ((size_t)it.slot * F.max_tiles + it.tile) * F.kmax;
+        for (int c = 0; c < KMAX; ++c) cnode[c] = c < J.K ? F.cls[(size_t)id * F.kmax + c] : 0u;
+        const uint32_t N = nd.n;
+        Cand best;
+        best.nl = 0;
+        int bi = 0;
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            const uint4 v = *reinterpret_cast<const uint4*>(hist + (bi * KMAX + k) * 256 + lane * 4);
-            const int bl = lane * 4;
-            const uint32_t a = (bl <= bt ? v.x : 0u) + (bl + 1 <= bt ? v.y : 0u) +
-                               (bl + 2 <= bt ? v.z : 0u) + (bl + 3 <= bt ? v.w : 0u);
-            const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_sum(a), 63);
-            if (lane == k) out[k] = tot;
+        for (int v = 0; v < FW; ++v) {
+            if (v >= nf) break;
+            const Cand fb = feature_best<KMAX>(hist + v * KMAX * 256, J.B, q0 + v, fq[v], cnode,
+                                               N, F.split_rank);
+            // draws in order: a strictly better score replaces
+            if (fb.nl != 0 && (best.nl == 0 || cand_better(fb, best))) {
+                best = fb;
+                bi = v;
+            }
         }
-    }
-    __syncthreads();  // LDS is reused by the next item
+        // left class counts of the item's best, for the partition step
+        uint32_t* out = F.cand_cl + (size_t)item * F.kmax;
+        const int bt = best.nl != 0 ? best.b : -1;
+#pragma unroll
+        for (int c = 0; c < KMAX; ++c) {
+            const uint4 v4 = *reinterpret_cast<const uint4*>(hist + (bi * KMAX + c) * 256 + lane * 4);
+            const int bl = lane * 4;
+            const uint32_t a = (bl <= bt ? v4.x : 0u) + (bl + 1 <= bt ? v4.y : 0u) +
+                               (bl + 2 <= bt ? v4.z : 0u) + (bl + 3 <= bt ? v4.w : 0u);
+            const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_sum(a), 63);
+            if (lane == c) out[c] = tot;
+        }
+        if (lane == 0) {
+            F.cand[item] = best;
+            if (F.alg_bytes)
+                atomicAdd((unsigned long long*)&F.alg_bytes[item & 63],
+                          (unsigned long long)len * (unsigned long long)(nf + (j == 0 ? 6 : 0)));
+        }
+        // the histogram is rewritten by the wave's next item
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
 }
 
@@ -659,7 +682,6 @@ template <int KMAX>
 __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level, uint32_t first,
                                                         uint32_t count) {
     __shared__ Cand s_best;
-    __shared__ Cand s_tiles[64];
     __shared__ int s_split, s_bt, s_part;
     __shared__ uint32_t s_wcnt[4];
     __shared__ uint32_t s_runl, s_runr;
@@ -683,25 +705,40 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
         S += (uint64_t)cnode[k] * cnode[k];
     }
     const uint32_t N = nd.n;
-    // the tiles' candidates are loaded in parallel, then ranked in draw order
-    // (a strictly better score replaces: the earliest tile keeps a tie)
-    int bt = -1;
-    for (int t0 = 0; t0 < J.ntiles; t0 += 64) {
-        const int nt = min(64, J.ntiles - t0);
-        if (tid < nt) s_tiles[tid] = F.cand[(size_t)slot * F.max_tiles + t0 + tid];
-        __syncthreads();
-        if (tid == 0)
-            for (int t = 0; t < nt; ++t)
-                if (s_tiles[t].nl != 0 &&
-                    (bt < 0 || cand_better(s_tiles[t], s_best)) ) {
-                    s_best = s_tiles[t];
-                    bt = t0 + t;
-                }
-        __syncthreads();
+    // the node's item candidates, ranked by score, then draw position, then
+    // threshold: each lane of wave 0 keeps the best of its items, then one
+    // wave reduction
+    if (tid < 64) {
+        const int fw = F.kmax <= 8 ? 8 / F.kmax : 1;
+        const int ni = (J.mtry + fw - 1) / fw;
+        Cand c;
+        c.nl = 0;
+        c.q = 0x7FFFFFFF;
+        c.b = 0x7FFFFFFF;
+        c.f = 0;
+        c.nr = 0;
+        c.pad = 0;
+        c.sl = c.sr = 0;
+        int ci = -1;
+        for (int t = tid; t < ni; t += 64) {
+            const Cand d = F.cand[(size_t)slot * F.npi + t];
+            if (d.nl != 0 && (c.nl == 0 || cand_wins_total(d, c))) {
+                c = d;
+                ci = t;
+            }
+        }
+        const Cand w = wave_best_total_exact(c);
+        const unsigned long long hit =
+            __ballot(w.nl != 0 && c.nl != 0 && c.q == w.q && c.b == w.b);
+        if (tid == (int)(hit ? __ffsll(hit) - 1 : 0)) {
+            s_best = w;
+            s_bt = hit ? ci : -1;
+        }
     }
+    __syncthreads();
+    const int bt = s_bt;
     if (tid == 0) {
         s_split = bt >= 0 && cand_positive(s_best, S, N);
-        s_bt = bt;
         s_runl = 0;
         s_runr = 0;
         // Rows are partitioned only for a child that is searched next: below
@@ -709,7 +746,7 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
         // more distinct rows); other children are final leaves.
         s_part = 0;
         if (s_split && (int)nd.depth + 1 < J.D) {
-            const uint32_t* clt = F.cand_cl + ((size_t)slot * F.max_tiles + bt) * F.kmax;
+            const uint32_t* clt = F.cand_cl + ((size_t)slot * F.npi + bt) * F.kmax;
             int nzl = 0, nzr = 0;
             for (int k = 0; k < KMAX; ++k) {
                 const uint32_t l = clt[k];
@@ -777,7 +814,7 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
         __syncthreads();
     }
     if (tid == 0) {
-        const uint32_t* clt = F.cand_cl + ((size_t)slot * F.max_tiles + s_bt) * F.kmax;
+        const uint32_t* clt = F.cand_cl + ((size_t)slot * F.npi + s_bt) * F.kmax;
         uint32_t cl[16], cr[16];
         for (int k = 0; k < 16; ++k) {
             cl[k] = k < KMAX ? clt[k] : 0u;
@@ -811,10 +848,15 @@ void launch_split_small(const ForestDev& F, int level, uint32_t first, uint32_t 
     }
 }
 
+void launch_draws(const ForestDev& F, int level, uint32_t grid_wg, hipStream_t st) {
+    hipLaunchKernelGGL(k_draws, dim3(grid_wg), dim3(256), 0, st, F, level);
+}
+
 void launch_hist_tile(const ForestDev& F, int level, uint32_t first, uint32_t count,
                       uint32_t grid_wg, int B, hipStream_t st) {
     if (!count) return;
-    const size_t lds = (size_t)32 * 256 * sizeof(uint32_t);  // FT * KMAX * 256 words, FT * KMAX = 32
+    // four waves of FW * KMAX * 256 words (FW * KMAX = 8, or 16 for 16 classes)
+    const size_t lds = (size_t)4 * (F.kmax <= 8 ? 8 : 16) * 256 * sizeof(uint32_t);
     const dim3 grid(grid_wg);
     switch (F.kmax) {
         case 2: hipLaunchKernelGGL(k_hist_tile<2>, grid, dim3(256), lds, st, F, level, first, count); break;

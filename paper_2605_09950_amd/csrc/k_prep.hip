@@ -244,7 +244,7 @@ __global__ void k_thresholds(int32_t max_iter, int64_t p, uint64_t alpha_m, int3
 // Per iteration, one workgroup per job: t += 1, active columns (state >= 0,
 // ascending), shadow count (doubled while < 5), widened column map, mtry;
 // the importance accumulators are cleared.
-__global__ __launch_bounds__(256) void k_active(JobDev* jobs, int ft) {
+__global__ __launch_bounds__(256) void k_active(JobDev* jobs) {
     __shared__ uint32_t s_w[4];
     __shared__ uint32_t s_base;
     JobDev& J = jobs[blockIdx.x];
@@ -296,7 +296,6 @@ __global__ __launch_bounds__(256) void k_active(JobDev* jobs, int ft) {
             if (m < 1) m = 1;
         }
         J.mtry = m;
-        J.ntiles = (m + ft - 1) / ft;
     }
 }
 
@@ -402,8 +401,8 @@ void launch_thresholds(int32_t max_iter, int64_t p, uint64_t alpha_m, int32_t al
                        max_iter, p, alpha_m, alpha_e, h_conf, h_rej);
 }
 
-void launch_active(JobDev* jobs, int n_jobs, int ft, hipStream_t st) {
-    hipLaunchKernelGGL(k_active, dim3(n_jobs), dim3(256), 0, st, jobs, ft);
+void launch_active(JobDev* jobs, int n_jobs, hipStream_t st) {
+    hipLaunchKernelGGL(k_active, dim3(n_jobs), dim3(256), 0, st, jobs);
 }
 
 void launch_shadow(JobDev* jobs, int n_jobs, int64_t max_n, int max_sha, hipStream_t st) {

@@ -139,7 +139,7 @@ def config(i):
     if i == 4:
         X, y, inf = mixed_scale()
         return dict(X=X, y=y, informative=inf, n_classes=4, seed=7004,
-                    params=_params(n_trees=300, max_depth=16, max_iter=100))
+                    params=_params(n_trees=300, max_depth=16, max_iter=100, n_perm=5))
     raise ValueError("workload 3 is a batch: use many_jobs()")
 
 
