@@ -90,11 +90,34 @@ __device__ __forceinline__ int wave_max_i(int v) {
     return v;
 }
 
-// Margin of the FP32 ranking: each FP32 score is within 5u (u = 2^-24) of
-// its exact value, so the exact best scores at least (1 - 10u) * FP32 max;
-// every candidate at or above (1 - 2^-20) * FP32 max (16u) is re-ranked
-// exactly, hence the FP32-ranked choice equals the exact one.
-__device__ __forceinline__ float fp32_floor(float qmax) { return qmax * (1.0f - 0x1.0p-20f); }
+// Margin of the FP32 ranking.  An FP32 score is within eps of its exact value
+// Q: eps = 5u (u = 2^-24) for cand_q32 and (K + 4)u <= 20u for hist_q32
+// below.  The exact best then scores at least (1 - 2 eps) * FP32 max, so
+// every candidate at or above (1 - 2^-18) * FP32 max (64u > 2 * 20u plus the
+// rounding of this product) is re-ranked exactly, and the FP32-ranked choice
+// equals the exact one.  Two scores farther apart than this margin are in
+// exact order.
+__device__ __forceinline__ float fp32_floor(float qmax) { return qmax * (1.0f - 0x1.0p-18f); }
+
+// FP32 score straight from the left class counts of a threshold:
+// S_L = sum cl_k^2 and S_R = sum (c_k - cl_k)^2 by FMA chains (K roundings
+// each; the counts are exact in FP32 below 2^24), then S_L rcp(N_L) +
+// S_R rcp(N_R).  Relative error <= (K + 4)u.  Returns -1 when one side is
+// empty.
+template <int KMAX>
+__device__ __forceinline__ float hist_q32(const uint32_t* cl, const uint32_t* cnode, uint32_t N) {
+    float nl = 0.0f, sl = 0.0f, sr = 0.0f;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const float l = (float)cl[k], r = (float)(cnode[k] - cl[k]);
+        nl += l;
+        sl = fmaf(l, l, sl);
+        sr = fmaf(r, r, sr);
+    }
+    const float nr = (float)N - nl;
+    if (nl == 0.0f || nr == 0.0f) return -1.0f;
+    return sl * __builtin_amdgcn_rcpf(nl) + sr * __builtin_amdgcn_rcpf(nr);
+}
 
 // Best of one feature's candidates with FP32 ranking and exact recheck of the
 // finalists.  q32 < 0 marks an invalid candidate.

@@ -481,9 +481,8 @@ __device__ Cand feature_best(const uint32_t* h, int B, int q, int f, const uint3
             add += v;
         }
         if (b > B - 2 || add == 0) continue;
-        const Cand c = make(b, cl);
-        if (c.nl == 0 || c.nl == N) continue;
-        const float qc = cand_q32(c);
+        const float qc = hist_q32<KMAX>(cl, cnode, N);
+        if (qc < 0.0f) continue;
         if (qc > q1) {
             q2 = q1;
             q1 = qc;
@@ -512,9 +511,9 @@ __device__ Cand feature_best(const uint32_t* h, int B, int q, int f, const uint3
                     add += v;
                 }
                 if (b > B - 2 || add == 0) continue;
+                const float qc = hist_q32<KMAX>(cl, cnode, N);
+                if (qc < floor32) continue;  // includes the empty-side -1
                 const Cand c = make(b, cl);
-                if (c.nl == 0 || c.nl == N) continue;
-                if (cand_q32(c) < floor32) continue;
                 if (lb.nl == 0 || cand_better(c, lb)) lb = c;
             }
         }
