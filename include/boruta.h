@@ -111,6 +111,18 @@ typedef struct {
                              Ignored (eager) when stats is set: kernel timing
                              needs events around every launch.  Results are
                              identical either way.                                 */
+    /* Launch tuning (batched form; every choice gives identical results;
+     * 0 = the library's default).                                                 */
+    int32_t small_rows;   /* nodes with at most this many distinct rows (and a
+                             weighted count below the packed-counter limit) take
+                             the wavefront path, [2, 64]; default 32              */
+    int32_t grid_small;   /* workgroups of the wavefront-path launch (4 nodes
+                             each, grid-stride); default min(4096, needed)       */
+    int32_t grid_hist;    /* workgroups of the histogram launch (4 items each),
+                             rounded up to a multiple of 8; default
+                             min(8192, needed)                                   */
+    int32_t grid_finalize;/* workgroups of the split/partition launch; default
+                             min(4096, needed)                                   */
     boruta_trace_fn trace;/* nullable                                              */
     void* trace_user;
     boruta_stats* stats;  /* nullable                                              */

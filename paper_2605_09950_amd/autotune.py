@@ -1,0 +1,106 @@
+"""Device-timed search over the launch parameters of the batched form.
+
+The tunable parameters (boruta_options.small_rows, grid_small, grid_hist,
+grid_finalize) change only how the work of a tree level is spread over
+workgroups and which of the two split-search paths a node takes; every
+choice gives identical results.  The search is a coordinate descent: each
+parameter in turn is set to each of its candidate values, a session over the
+workload is stepped a few times (graph replays, inputs resident on the
+device), and the fastest value is kept.  The outcome can be cached as JSON,
+keyed by a signature of the workload's shapes.
+
+    tune = autotune(jobs, n_bins=256)             # dict for Session(tune=...)
+"""
+import json
+import os
+import time
+
+from paper_2605_09950_amd import binding as B
+
+# candidate values per parameter, in search order (0 = library default)
+CANDIDATES = (
+    ("small_rows", (32, 64, 48, 16)),
+    ("grid_hist", (0, 2048, 4096, 16384)),
+    ("grid_small", (0, 1024, 2048, 8192)),
+    ("grid_finalize", (0, 1024, 2048, 8192)),
+)
+
+
+def signature(jobs, n_bins=256, n_perm=1):
+    """Shape signature of a workload: what the launch parameters depend on."""
+    parts = [f"B{n_bins}", f"R{n_perm}"]
+    for jd in jobs:
+        n, p = jd["X"].shape
+        parts.append(f"{n}x{p}K{jd['n_classes']}T{jd['n_trees']}D{jd['max_depth']}"
+                     f"m{jd.get('mtry', 0)}i{jd.get('importance_mode', 0)}")
+    return "|".join(parts)
+
+
+def _time_session(dev_jobs, shapes, n_bins, n_perm, tune, steps, warmup):
+    import torch
+    ws_bytes = B.boruta_workspace_size(shapes, n_bins=n_bins, n_perm=n_perm, tune=tune)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    with B.Session(dev_jobs, n_bins=n_bins, n_perm=n_perm, inputs_on_device=True,
+                   workspace=ws, stream=stream, graph=True, tune=tune) as s:
+        live = len(dev_jobs)
+        for _ in range(warmup):
+            if live:
+                live = s.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        for _ in range(steps):
+            if not live:
+                break
+            live = s.step()
+            done += 1
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    return el / max(1, done) * 1e3
+
+
+def autotune(jobs, n_bins=256, n_perm=1, steps=3, warmup=2, cache=None, log=None):
+    """Returns the fastest tuning dict for `jobs` (host arrays, as for
+    boruta_fit_batch).  With `cache` (a JSON file path) a stored result for
+    the same signature is reused and a new one is stored."""
+    import torch
+    sig = signature(jobs, n_bins, n_perm)
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            stored = json.load(f)
+        if sig in stored:
+            return dict(stored[sig]["tune"])
+    dev, shapes = [], []
+    for jd in jobs:
+        d = dict(jd)
+        d["X"] = torch.from_numpy(jd["X"]).cuda()
+        d["y"] = torch.from_numpy(jd["y"]).cuda()
+        d["max_iter"] = min(jd.get("max_iter", 20), warmup + steps)
+        dev.append(d)
+        shapes.append(dict(n=d["X"].shape[0], p=d["X"].shape[1],
+                           **{k: v for k, v in d.items() if k not in ("X", "y")}))
+    best = {}
+    best_ms = _time_session(dev, shapes, n_bins, n_perm, best, steps, warmup)
+    trials = [({}, best_ms)]
+    for key, values in CANDIDATES:
+        for v in values:
+            if best.get(key, 0 if key != "small_rows" else 32) == v:
+                continue
+            cand = dict(best, **{key: v})
+            ms = _time_session(dev, shapes, n_bins, n_perm, cand, steps, warmup)
+            trials.append((cand, ms))
+            if log:
+                log(f"autotune {cand}: {ms:.3f} ms/step")
+            if ms < best_ms:
+                best, best_ms = cand, ms
+    if cache:
+        stored = {}
+        if os.path.exists(cache):
+            with open(cache) as f:
+                stored = json.load(f)
+        stored[sig] = {"tune": best, "ms_per_step": best_ms,
+                       "trials": [{"tune": t, "ms_per_step": m} for t, m in trials]}
+        with open(cache, "w") as f:
+            json.dump(stored, f, indent=1)
+    return best

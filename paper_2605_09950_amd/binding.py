@@ -57,7 +57,9 @@ class Stats(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("n_bins", ctypes.c_int32), ("n_perm", ctypes.c_int32),
                 ("split_rank", ctypes.c_int32), ("form", ctypes.c_int32),
-                ("graph", ctypes.c_int32),
+                ("graph", ctypes.c_int32), ("small_rows", ctypes.c_int32),
+                ("grid_small", ctypes.c_int32), ("grid_hist", ctypes.c_int32),
+                ("grid_finalize", ctypes.c_int32),
                 ("trace", TRACE_FN), ("trace_user", ctypes.c_void_p),
                 ("stats", ctypes.POINTER(Stats))]
 
@@ -184,13 +186,20 @@ def _trace_collector(store, p, keep_iters=None):
     return TRACE_FN(cb)
 
 
+TUNE_KEYS = ("small_rows", "grid_small", "grid_hist", "grid_finalize")
+
+
 def make_options(n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED, trace=False,
-                 stats=False, p=0, graph=True):
+                 stats=False, p=0, graph=True, tune=None):
     """Options plus the Python objects that must stay alive during the call.
     trace: False, True (every iteration) or a set of iterations to keep."""
     o = boruta_default_options()
     o.n_bins, o.n_perm, o.split_rank, o.form = n_bins, n_perm, split_rank, form
     o.graph = int(bool(graph))
+    for k, v in (tune or {}).items():
+        if k not in TUNE_KEYS:
+            raise ValueError(f"unknown tuning key {k}")
+        setattr(o, k, int(v))
     keep = {"iters": []}
     if trace is not False:
         keep["cb"] = _trace_collector(keep, p, None if trace is True else set(trace))
@@ -203,7 +212,7 @@ def make_options(n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED, 
 
 def boruta_fit_ex(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=TREEIMP,
                   max_iter=20, alpha=0.05, seed=0, n_bins=256, n_perm=1, split_rank=RANK_FP32,
-                  form=FORM_BATCHED, trace=False, stats=False, graph=True):
+                  form=FORM_BATCHED, trace=False, stats=False, graph=True, tune=None):
     """Host arrays in, host arrays out (see boruta_fit in include/boruta.h)."""
     X = np.ascontiguousarray(X, dtype=np.float32)
     y = np.ascontiguousarray(y, dtype=np.int32)
@@ -213,7 +222,7 @@ def boruta_fit_ex(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=T
     hits = np.zeros(p, np.int32)
     smax = np.full(max_iter, np.nan)
     n_iter = np.zeros(1, np.int32)
-    o, keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p, graph)
+    o, keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p, graph, tune)
     rc = lib().boruta_fit_ex(_ptr(X), _ptr(y), n, p, n_classes, n_trees, max_depth, mtry,
                              importance_mode, max_iter, alpha, seed, ctypes.byref(o), _ptr(dec),
                              _ptr(hist), _ptr(hits), _ptr(smax), _ptr(n_iter))
@@ -283,7 +292,7 @@ def boruta_fit_batch(jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM
 
 
 def boruta_workspace_size(jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32,
-                          form=FORM_BATCHED):
+                          form=FORM_BATCHED, tune=None):
     """jobs: list of dicts with shapes (X may be any array with .shape)."""
     cj = (Job * len(jobs))()
     for i, jd in enumerate(jobs):
@@ -294,7 +303,7 @@ def boruta_workspace_size(jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32,
         j.mtry, j.importance_mode = jd.get("mtry", 0), jd.get("importance_mode", TREEIMP)
         j.max_iter, j.alpha, j.seed = jd.get("max_iter", 20), jd.get("alpha", 0.05), 0
         cj[i] = j
-    opt, _ = make_options(n_bins, n_perm, split_rank, form)
+    opt, _ = make_options(n_bins, n_perm, split_rank, form, tune=tune)
     out = ctypes.c_size_t(0)
     _check(lib().boruta_workspace_size(cj, len(jobs), ctypes.byref(opt), ctypes.byref(out)))
     return int(out.value)
@@ -343,7 +352,7 @@ class Session:
 
     def __init__(self, jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED,
                  trace=False, stats=False, inputs_on_device=False, workspace=None, stream=None,
-                 graph=True):
+                 graph=True, tune=None):
         self._arrays, cj = [], (Job * len(jobs))()
         self._shapes = []
         for i, jd in enumerate(jobs):
@@ -367,7 +376,7 @@ class Session:
             self._shapes.append((p, j.max_iter))
         p_all = [int(sh[0]) for sh in self._shapes]
         self.opt, self.keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p_all,
-                                           graph)
+                                           graph, tune)
         self._jobs = cj
         self._ws = workspace
         ws_ptr = workspace.data_ptr() if workspace is not None else None

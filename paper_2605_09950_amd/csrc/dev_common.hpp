@@ -313,6 +313,7 @@ struct ForestDev {
     uint32_t small_ncap;  // a node takes the wave path only below this weighted count
     int32_t kmax, ft, parity, split_rank;
     int32_t npi;          // histogram items per large node (draw positions / FW)
+    uint32_t small_rows;  // a node takes the wave path only up to this many distinct rows
     int32_t mtry_cap;     // row stride of feat
 };
 

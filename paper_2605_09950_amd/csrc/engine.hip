@@ -69,6 +69,7 @@ struct Spec {
 
 struct Opts {
     int B = 256, R = 1, split_rank = 1, form = 1, graph = 1;
+    int small_rows = 32, grid_small = 0, grid_hist = 0, grid_finalize = 0;
     boruta_trace_fn trace = nullptr;
     void* trace_user = nullptr;
     boruta_stats* stats = nullptr;
@@ -82,6 +83,10 @@ Opts read_opts(const boruta_options* o) {
         r.split_rank = o->split_rank;
         r.form = o->form;
         r.graph = o->graph;
+        if (o->small_rows) r.small_rows = o->small_rows;
+        r.grid_small = o->grid_small;
+        r.grid_hist = o->grid_hist;
+        r.grid_finalize = o->grid_finalize;
         r.trace = o->trace;
         r.trace_user = o->trace_user;
         r.stats = o->stats;
@@ -92,6 +97,11 @@ Opts read_opts(const boruta_options* o) {
         throw Error(BORUTA_E_INVALID_ARG, "split_rank must be 0 or 1");
     if (r.form != 0 && r.form != 1) throw Error(BORUTA_E_INVALID_ARG, "form must be 0 or 1");
     if (r.graph != 0 && r.graph != 1) throw Error(BORUTA_E_INVALID_ARG, "graph must be 0 or 1");
+    if (r.small_rows < 2 || r.small_rows > kSmallRows)
+        throw Error(BORUTA_E_INVALID_ARG, "small_rows outside [2, 64]");
+    if (r.grid_small < 0 || r.grid_hist < 0 || r.grid_finalize < 0 || r.grid_small > 65536 ||
+        r.grid_hist > 65536 || r.grid_finalize > 65536)
+        throw Error(BORUTA_E_INVALID_ARG, "grid sizes outside [0, 65536]");
     return r;
 }
 
@@ -199,7 +209,7 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
         // every searched node reserves a pair of child slots (a leaf leaves its
         // pair unused), so the pool holds up to twice the nodes of the trees
         node_cap += T + 2 * T * per_tree_nodes;
-        const uint64_t large_per_tree = (uint64_t)(s.n + kSmallRows) / (kSmallRows + 1);
+        const uint64_t large_per_tree = (uint64_t)(s.n + o.small_rows) / (o.small_rows + 1);
         slot_cap += T * large_per_tree;
         small_cap += T * (uint64_t)((s.n + 1) / 2);
         pl.max_sha = std::max(pl.max_sha, j.max_sha);
@@ -477,6 +487,7 @@ ForestDev Engine::forest() const {
     F.cand_cl = at<uint32_t>(pl.cand_cl);
     F.feat = at<uint32_t>(pl.feat);
     F.npi = pl.npi;
+    F.small_rows = (uint32_t)O.small_rows;
     F.mtry_cap = pl.mtry_cap;
     F.ctrs = at<LevelCtr>(pl.ctrs);
     F.ctr = F.ctrs;
@@ -543,11 +554,15 @@ void Engine::enqueue_iteration() {
     F.small_out = small[0];
     F.slot_node_out = slots[0];
     launch_boot_compact(F, n_trees, st);
-    const uint32_t g_small = level_grid(pl.small_cap, 4, 2048);
+    const uint32_t g_small =
+        O.grid_small ? (uint32_t)O.grid_small : level_grid(pl.small_cap, 4, 4096);
     // a multiple of 8: workgroup b serves the node slots congruent to b mod 8
-    const uint32_t g_tile = (level_grid((uint64_t)pl.slot_cap * pl.npi, 4, 2560) + 7) / 8 * 8;
+    const uint32_t g_tile =
+        ((O.grid_hist ? (uint32_t)O.grid_hist : level_grid((uint64_t)pl.slot_cap * pl.npi, 4, 8192)) +
+         7) / 8 * 8;
     const uint32_t g_draw = level_grid(pl.slot_cap, 4, 1024);
-    const uint32_t g_fin = level_grid(pl.slot_cap, 1, 1024);
+    const uint32_t g_fin =
+        O.grid_finalize ? (uint32_t)O.grid_finalize : level_grid(pl.slot_cap, 1, 4096);
     for (int d = 0; d < n_levels; ++d) {
         // lists, slots and row records of level d are read from parity d & 1
         // and the children of level d go to the other parity
@@ -889,6 +904,10 @@ void boruta_default_options(boruta_options* opt) {
     opt->split_rank = BORUTA_RANK_FP32;
     opt->form = BORUTA_FORM_BATCHED;
     opt->graph = 1;
+    opt->small_rows = 32;
+    opt->grid_small = 0;
+    opt->grid_hist = 0;
+    opt->grid_finalize = 0;
     opt->trace = nullptr;
     opt->trace_user = nullptr;
     opt->stats = nullptr;

@@ -264,7 +264,7 @@ __device__ inline int write_node(const ForestDev& F, const JobDev& J, uint32_t i
     F.nodes[idx] = nd;
     F.ngain[idx] = 0;
     if ((int)depth >= J.D || len < 2 || nonzero <= 1) return kLeaf;
-    return (len <= (uint32_t)kSmallRows && n < F.small_ncap) ? kSmall : kLarge;
+    return (len <= F.small_rows && n < F.small_ncap) ? kSmall : kLarge;
 }
 
 // Place node idx in the next level's lists at already reserved positions.

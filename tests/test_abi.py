@@ -35,6 +35,25 @@ def test_library_exports_every_declared_symbol():
 def test_default_options():
     o = B.boruta_default_options()
     assert (o.n_bins, o.n_perm, o.split_rank, o.form) == (256, 1, B.RANK_FP32, B.FORM_BATCHED)
+    assert (o.graph, o.small_rows, o.grid_small, o.grid_hist, o.grid_finalize) == (1, 32, 0, 0, 0)
+    assert not o.trace and not o.stats
+
+
+def test_tuning_options_validated_on_the_host():
+    for tune in (dict(small_rows=1), dict(small_rows=65), dict(grid_hist=-1),
+                 dict(grid_small=70000)):
+        with pytest.raises(B.BorutaError) as e:
+            B.boruta_workspace_size([dict(n=100, p=5, n_classes=2, n_trees=2, max_depth=3)],
+                                    tune=tune)
+        assert e.value.code == B.BORUTA_E_INVALID_ARG
+    with pytest.raises(ValueError):
+        B.make_options(tune=dict(bogus=1))
+
+
+def test_small_rows_sizes_the_large_node_lists():
+    job = [dict(n=5000, p=50, n_classes=3, n_trees=10, max_depth=10)]
+    assert B.boruta_workspace_size(job, tune=dict(small_rows=16)) > B.boruta_workspace_size(job)
+    assert B.boruta_workspace_size(job, tune=dict(small_rows=64)) < B.boruta_workspace_size(job)
 
 
 def _call(**kw):

@@ -209,3 +209,32 @@ def test_graph_session_with_stats_and_resume():
     k = full["n_iter"]
     assert res["n_iter"] == k
     np.testing.assert_array_equal(res["imp_history"][4:k], full["imp_history"][4:k])
+
+
+@pytest.mark.parametrize("tune", [dict(small_rows=16),
+                                  dict(small_rows=32, grid_hist=64, grid_small=8,
+                                       grid_finalize=3)],
+                         ids=["small_rows16", "tiny_grids"])
+def test_launch_tuning_leaves_results_unchanged(tune):
+    X, y = problem(28, 2200, 30, 4)
+    kw = dict(max_iter=4, seed=14, trace=True)
+    a = B.boruta_fit_ex(X, y, 4, 8, 10, **kw)
+    b = B.boruta_fit_ex(X, y, 4, 8, 10, tune=tune, **kw)
+    assert_same_run(a, b)
+
+
+def test_autotuner_returns_a_valid_choice(tmp_path):
+    from paper_2605_09950_amd import autotune as A
+    c = synth.config(0)
+    pr = c["params"]
+    jobs = [dict(X=c["X"], y=c["y"], n_classes=2, n_trees=pr["n_trees"],
+                 max_depth=pr["max_depth"], max_iter=pr["max_iter"], seed=c["seed"])]
+    cache = str(tmp_path / "tune.json")
+    t = A.autotune(jobs, n_bins=pr["n_bins"], steps=1, warmup=1, cache=cache)
+    assert set(t) <= set(B.TUNE_KEYS)
+    assert A.autotune(jobs, n_bins=pr["n_bins"], cache=cache) == t  # served from the cache
+    g = B.boruta_fit_ex(c["X"], c["y"], 2, pr["n_trees"], pr["max_depth"], max_iter=4,
+                        seed=c["seed"], n_bins=pr["n_bins"], tune=t)
+    d = B.boruta_fit_ex(c["X"], c["y"], 2, pr["n_trees"], pr["max_depth"], max_iter=4,
+                        seed=c["seed"], n_bins=pr["n_bins"])
+    assert_same_run(g, d)
