@@ -268,6 +268,17 @@ struct NodeDev {
     uint8_t depth;
 };
 
+// What a histogram item needs of its large node, gathered once per node and
+// level so that an item's first loads do not depend on each other.
+struct SlotRec {
+    const uint64_t* recs;  // the node's row records (this level's parity)
+    uint32_t id;           // node index
+    uint32_t len, n;       // distinct rows, weighted rows
+    uint32_t mtry;         // features drawn this iteration
+    uint32_t B, pad;
+    uint32_t cnode[16];    // weighted class counts (zero past K)
+};
+
 // Per-level counters: the lists of tree level d (small nodes, large-node
 // slots) are counted in ctrs[d]; they are zeroed once per iteration.
 struct LevelCtr {
@@ -298,6 +309,8 @@ struct ForestDev {
     Cand* cand;           // [slot][npi] best candidate of each histogram item
     uint32_t* cand_cl;    // [slot][npi][kmax] left class counts of that candidate
     uint32_t* feat;       // [slot][mtry_cap] the node's drawn features, draw order
+    const uint8_t** fcol; // [slot][mtry_cap] their bin columns
+    SlotRec* srec;        // [slot] the large nodes of the level
     const uint32_t* slot_node_in;  // [slot] node of each large-node slot of this level
     uint32_t* slot_node_out;       // [slot] the same for the next level
     const uint32_t* small_in;

@@ -153,7 +153,7 @@ struct JobPlan {
 struct Plan {
     std::vector<JobPlan> jp;
     size_t keys, jobs, trees, tree_base, flags, nodes, cls, ngain, small0, small1, cand, cand_cl,
-        feat, slot0, slot1, ctrs, alg, tot;
+        feat, fcol, srec, slot0, slot1, ctrs, alg, tot;
     uint32_t node_cap = 0, slot_cap = 0, small_cap = 0;
     int kmax = 4, ft = 8, max_sha = 1, max_pw = 1, max_D = 1, T_total = 0, mtry_cap = 1,
         npi = 1;
@@ -239,6 +239,8 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     pl.cand = r.take((size_t)pl.slot_cap * pl.npi * sizeof(Cand));
     pl.cand_cl = r.take((size_t)pl.slot_cap * pl.npi * pl.kmax * 4);
     pl.feat = r.take((size_t)pl.slot_cap * pl.mtry_cap * 4);
+    pl.fcol = r.take((size_t)pl.slot_cap * pl.mtry_cap * 8);
+    pl.srec = r.take((size_t)pl.slot_cap * sizeof(SlotRec));
     pl.slot0 = r.take((size_t)pl.slot_cap * 4);
     pl.slot1 = r.take((size_t)pl.slot_cap * 4);
     // level d < max_D reads ctrs[d] and appends to ctrs[d + 1]
@@ -486,6 +488,8 @@ ForestDev Engine::forest() const {
     F.cand = at<Cand>(pl.cand);
     F.cand_cl = at<uint32_t>(pl.cand_cl);
     F.feat = at<uint32_t>(pl.feat);
+    F.fcol = at<const uint8_t*>(pl.fcol);
+    F.srec = at<SlotRec>(pl.srec);
     F.npi = pl.npi;
     F.small_rows = (uint32_t)O.small_rows;
     F.mtry_cap = pl.mtry_cap;

@@ -339,6 +339,7 @@ __global__ __launch_bounds__(256) void k_split_small(ForestDev F0, int level, ui
         count = level_small(F0, level);
     }
     const int lane = threadIdx.x & 63, wave = (int)uniform(threadIdx.x >> 6);
+    unsigned long long alg = 0;  // statistics, thread 0
     for (uint32_t base = blockIdx.x * 4u; base < count; base += gridDim.x * 4u) {
     const uint32_t li = base + wave;
     SmallOut o;
@@ -358,9 +359,7 @@ __global__ __launch_bounds__(256) void k_split_small(ForestDev F0, int level, ui
         const uint32_t tl = s_nl[0] + s_nl[1] + s_nl[2] + s_nl[3];
         s_base[0] = ts ? atomicAdd(&F.ctr->n_small, ts) : 0u;
         s_base[1] = tl ? atomicAdd(&F.ctr->n_slots, tl) : 0u;
-        if (F.alg_bytes)
-            atomicAdd((unsigned long long*)&F.alg_bytes[64 + (blockIdx.x & 63)],
-                      s_alg[0] + s_alg[1] + s_alg[2] + s_alg[3]);
+        alg += s_alg[0] + s_alg[1] + s_alg[2] + s_alg[3];
     }
     __syncthreads();
     if (lane == 0 && li < count) {
@@ -376,6 +375,9 @@ __global__ __launch_bounds__(256) void k_split_small(ForestDev F0, int level, ui
     }
     __syncthreads();  // the shared counts are reused by the next batch
     }
+    // one atomic per workgroup for the statistics
+    if (F.alg_bytes && threadIdx.x == 0 && alg)
+        atomicAdd((unsigned long long*)&F.alg_bytes[64 + (blockIdx.x & 63)], alg);
 }
 
 // ---------------------------------------------------------------------------
@@ -534,20 +536,205 @@ __device__ Cand feature_best(const uint32_t* h, int B, int q, int f, const uint3
     return wave_best_exact(lb);
 }
 
+// Best threshold of one feature, compacted form (up to 4 classes): as
+// feature_best, but the thresholds worth scoring (a non-empty bin below
+// B - 1 with rows on both sides) are first packed into a dense list, so a
+// node with few distinct bins costs one scoring round instead of four.  The
+// list overwrites the feature's histogram h (read first); each entry is
+// KMAX words, the bin in the top byte of the first (counts stay below 2^24).
+// cl_out receives the winner's left class counts.
+template <int KMAX>
+__device__ Cand feature_best_compact(uint32_t* h, int B, int q, int f, const uint32_t* cnode,
+                                     uint32_t N, int split_rank, uint32_t* cl_out) {
+    static_assert(KMAX <= 4, "compact scan keeps four bins per class in registers");
+    const int lane = threadIdx.x & 63;
+    const int b0 = lane * 4;
+    uint32_t hv[KMAX][4], excl[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const uint4 v = *reinterpret_cast<const uint4*>(h + k * 256 + b0);
+        hv[k][0] = v.x;
+        hv[k][1] = v.y;
+        hv[k][2] = v.z;
+        hv[k][3] = v.w;
+        const uint32_t a = v.x + v.y + v.z + v.w;
+        excl[k] = wave_incl_sum(a) - a;
+    }
+    // the lane's thresholds worth scoring, their prefix counts
+    uint32_t cl[4][KMAX];
+    bool ok[4];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        uint32_t add = 0, nl = 0;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            cl[u][k] = (u == 0 ? excl[k] : cl[u - 1][k]) + hv[k][u];
+            add += hv[k][u];
+            nl += cl[u][k];
+        }
+        ok[u] = b0 + u <= B - 2 && add != 0 && nl != 0 && nl != N;
+        cnt += ok[u];
+    }
+    const uint32_t incl = wave_incl_sum(cnt);
+    const int total = __builtin_amdgcn_readlane((int)incl, 63);
+    uint32_t pos = incl - cnt;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // h has been read
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (ok[u]) {
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                h[pos * KMAX + k] = cl[u][k] | (k == 0 ? (uint32_t)(b0 + u) << 24 : 0u);
+            ++pos;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    auto entry = [&](int e, uint32_t* c) {
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) c[k] = h[e * KMAX + k];
+        const int b = (int)(c[0] >> 24);
+        c[0] &= 0xFFFFFFu;
+        return b;
+    };
+    auto make = [&](int b, const uint32_t* c) {
+        Cand x;
+        x.q = q;
+        x.f = f;
+        x.b = b;
+        x.pad = 0;
+        uint32_t nl = 0;
+        uint64_t sl = 0, sr = 0;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const uint32_t r = cnode[k] - c[k];
+            nl += c[k];
+            sl += (uint64_t)c[k] * c[k];
+            sr += (uint64_t)r * r;
+        }
+        x.nl = nl;
+        x.nr = N - nl;
+        x.sl = sl;
+        x.sr = sr;
+        return x;
+    };
+    Cand lb;
+    lb.nl = 0;
+    lb.b = 0x7FFFFFFF;
+    lb.q = q;
+    lb.f = f;
+    lb.nr = 0;
+    lb.pad = 0;
+    lb.sl = lb.sr = 0;
+    uint32_t lcl[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) lcl[k] = 0;
+    if (!split_rank) {
+        // exact: each lane ranks its entries (ascending thresholds: a strictly
+        // better score replaces, so ties keep the smaller threshold)
+        for (int e = lane; e < total; e += 64) {
+            uint32_t c[KMAX];
+            const int b = entry(e, c);
+            const Cand x = make(b, c);
+            if (lb.nl == 0 || cand_better(x, lb)) {
+                lb = x;
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k) lcl[k] = c[k];
+            }
+        }
+    } else {
+        float q1 = -1.0f, q2 = -1.0f;
+        int e1 = 0;
+        for (int e = lane; e < total; e += 64) {
+            uint32_t c[KMAX];
+            (void)entry(e, c);
+            const float qc = hist_q32<KMAX>(c, cnode, N);
+            if (qc > q1) {
+                q2 = q1;
+                q1 = qc;
+                e1 = e;
+            } else if (qc > q2) {
+                q2 = qc;
+            }
+        }
+        const float qmax = wave_max_f_dpp(q1);
+        if (qmax < 0.0f) return lb;
+        const float floor32 = fp32_floor(qmax);
+        const bool fin = q1 >= floor32;
+        const bool multi = fin && q2 >= floor32;
+        if (__ballot(multi)) {
+            if (multi) {
+                for (int e = lane; e < total; e += 64) {
+                    uint32_t c[KMAX];
+                    const int b = entry(e, c);
+                    if (hist_q32<KMAX>(c, cnode, N) < floor32) continue;
+                    const Cand x = make(b, c);
+                    if (lb.nl == 0 || cand_better(x, lb)) {
+                        lb = x;
+#pragma unroll
+                        for (int k = 0; k < KMAX; ++k) lcl[k] = c[k];
+                    }
+                }
+            }
+        }
+        if (fin && !multi) {
+            uint32_t c[KMAX];
+            const int b = entry(e1, c);
+            lb = make(b, c);
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) lcl[k] = c[k];
+        }
+    }
+    const unsigned long long finm = __ballot(lb.nl != 0);
+    if (!finm) return lb;
+    int src;
+    Cand w;
+    if (__popcll(finm) == 1) {
+        src = (int)__ffsll(finm) - 1;
+        w = shfl_cand(lb, src);
+    } else {
+        w = wave_best_exact(lb);
+        const unsigned long long m = __ballot(lb.nl != 0 && lb.b == w.b);
+        src = (int)__ffsll(m) - 1;
+    }
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+        cl_out[k] = (uint32_t)__builtin_amdgcn_readlane((int)lcl[k], src);
+    return w;
+}
+
 // Large nodes, phase 0: one wavefront per node draws its mtry features
-// (the keyed permutation of the node's heap id, in draw order).
+// (the keyed permutation of the node's heap id, in draw order), resolves
+// their bin columns and writes the node's SlotRec.
 __global__ __launch_bounds__(256) void k_draws(ForestDev F, int level) {
     const uint32_t count = level_slots(F, level);
     const int lane = threadIdx.x & 63;
     const uint32_t w0 = blockIdx.x * 4u + uniform(threadIdx.x >> 6);
     for (uint32_t slot = w0; slot < count; slot += gridDim.x * 4u) {
-        const NodeDev nd = F.nodes[F.slot_node_in[slot]];
+        const uint32_t id = uniform(F.slot_node_in[slot]);
+        const NodeDev nd = F.nodes[id];
         const TreeDev tr = F.trees[nd.tree];
         const JobDev& J = F.jobs[tr.job];
         const KeyedPerm P = make_perm(J.seed_lo, J.seed_hi, kMtry, (uint32_t)J.t,
                                       (uint32_t)tr.tau, nd.heap, 0u, (uint64_t)J.p_w);
         uint32_t* out = F.feat + (size_t)slot * F.mtry_cap;
-        for (int q = lane; q < J.mtry; q += 64) out[q] = perm_apply(P, (uint32_t)q);
+        const uint8_t** oc = F.fcol + (size_t)slot * F.mtry_cap;
+        for (int q = lane; q < J.mtry; q += 64) {
+            const uint32_t f = perm_apply(P, (uint32_t)q);
+            out[q] = f;
+            oc[q] = ldg(J.colptr + f);
+        }
+        SlotRec* sr = F.srec + slot;
+        if (lane < 16) sr->cnode[lane] = lane < J.K ? F.cls[(size_t)id * F.kmax + lane] : 0u;
+        if (lane == 0) {
+            sr->recs = J.rec[F.parity] + (size_t)tr.tau * J.n + nd.seg;
+            sr->id = id;
+            sr->len = nd.len;
+            sr->n = nd.n;
+            sr->mtry = (uint32_t)J.mtry;
+            sr->B = (uint32_t)J.B;
+            sr->pad = 0;
+        }
     }
 }
 
@@ -575,42 +762,38 @@ __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint3
     // hardware deals workgroups round-robin to the 8 XCDs (any mapping gives
     // the same results: every item is visited once).  With an explicit count,
     // items [first, first + count) are walked directly (plain form).
-    uint32_t n_slots, x = 0, r, R, m_end;
-    if (count == 0xFFFFFFFFu) {
-        n_slots = level_slots(F, level);
+    const bool dyn = count == 0xFFFFFFFFu;
+    uint32_t x = 0, r = blockIdx.x * 4u + (uint32_t)wave, R = gridDim.x * 4u, m_end = count;
+    if (dyn) {
+        const uint32_t n_slots = level_slots(F, level);
         x = blockIdx.x % 8u;
         r = (blockIdx.x / 8u) * 4u + (uint32_t)wave;
         R = (gridDim.x / 8u) * 4u;
         m_end = n_slots > x ? (n_slots - x + 7u) / 8u * npi : 0u;
-    } else {
-        r = blockIdx.x * 4u + (uint32_t)wave;
-        R = gridDim.x * 4u;
-        m_end = count;
     }
-    for (uint32_t m = r; m < m_end; m += R) {
-        const uint32_t item = count == 0xFFFFFFFFu ? (8u * (m / npi) + x) * npi + m % npi
-                                                   : first + m;
+    unsigned long long alg = 0;
+    for (uint32_t cur = r; cur < m_end; cur += R) {
+        const uint32_t item = dyn ? (8u * (cur / npi) + x) * npi + cur % npi : first + cur;
         const uint32_t slot = item / npi, j = item % npi;
-        const uint32_t id = uniform(F.slot_node_in[slot]);
-        const NodeDev nd = F.nodes[id];
-        const TreeDev tr = F.trees[nd.tree];
-        const JobDev& J = F.jobs[tr.job];
+        const SlotRec& sr = F.srec[slot];
         const int q0 = (int)j * FW;
-        if (q0 >= J.mtry) continue;  // the job draws fewer features this iteration
-        const int nf = min(FW, J.mtry - q0);
+        const int mtry = (int)sr.mtry;
+        if (q0 >= mtry) continue;  // the job draws fewer features this iteration
+        const int nf = min(FW, mtry - q0);
         const uint32_t* drawn = F.feat + (size_t)slot * F.mtry_cap + q0;
+        const uint8_t* const* dcol = F.fcol + (size_t)slot * F.mtry_cap + q0;
         int fq[FW];
         const uint8_t* col[FW];
 #pragma unroll
         for (int u = 0; u < FW; ++u) {
-            fq[u] = (int)uniform(ldg(drawn + (u < nf ? u : 0)));
-            col[u] = ldg(J.colptr + fq[u]);
+            fq[u] = (int)drawn[u < nf ? u : 0];
+            col[u] = dcol[u < nf ? u : 0];
         }
 #pragma unroll
         for (int i = 0; i < WORDS / 256; ++i)
             reinterpret_cast<uint4*>(hist)[i * 64 + lane] = make_uint4(0u, 0u, 0u, 0u);
-        const uint64_t* recs = J.rec[F.parity] + (size_t)tr.tau * J.n + nd.seg;
-        const uint32_t len = uniform(nd.len);
+        const uint64_t* recs = sr.recs;
+        const uint32_t len = sr.len;
         for (uint32_t i0 = 0; i0 < len; i0 += 64 * RB) {
             uint64_t r[RB];
 #pragma unroll
@@ -634,43 +817,66 @@ __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint3
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         uint32_t cnode[KMAX];
 #pragma unroll
-        for (int c = 0; c < KMAX; ++c) cnode[c] = c < J.K ? F.cls[(size_t)id * F.kmax + c] : 0u;
-        const uint32_t N = nd.n;
+        for (int c = 0; c < KMAX; ++c) cnode[c] = sr.cnode[c];
+        const uint32_t N = sr.n;
+        const int B = (int)sr.B;
         Cand best;
         best.nl = 0;
         int bi = 0;
+        uint32_t best_cl[KMAX];
+#pragma unroll
+        for (int c = 0; c < KMAX; ++c) best_cl[c] = 0;
 #pragma unroll
         for (int v = 0; v < FW; ++v) {
             if (v >= nf) break;
-            const Cand fb = feature_best<KMAX>(hist + v * KMAX * 256, J.B, q0 + v, fq[v], cnode,
-                                               N, F.split_rank);
+            Cand fb;
+            uint32_t fcl[KMAX];
+            if constexpr (KMAX <= 4)
+                fb = feature_best_compact<KMAX>(hist + v * KMAX * 256, B, q0 + v, fq[v], cnode,
+                                                N, F.split_rank, fcl);
+            else
+                fb = feature_best<KMAX>(hist + v * KMAX * 256, B, q0 + v, fq[v], cnode, N,
+                                        F.split_rank);
             // draws in order: a strictly better score replaces
             if (fb.nl != 0 && (best.nl == 0 || cand_better(fb, best))) {
                 best = fb;
                 bi = v;
+                if constexpr (KMAX <= 4) {
+#pragma unroll
+                    for (int c = 0; c < KMAX; ++c) best_cl[c] = fcl[c];
+                }
             }
         }
         // left class counts of the item's best, for the partition step
         uint32_t* out = F.cand_cl + (size_t)item * F.kmax;
-        const int bt = best.nl != 0 ? best.b : -1;
+        if constexpr (KMAX <= 4) {
+            if (lane < KMAX) {
 #pragma unroll
-        for (int c = 0; c < KMAX; ++c) {
-            const uint4 v4 = *reinterpret_cast<const uint4*>(hist + (bi * KMAX + c) * 256 + lane * 4);
-            const int bl = lane * 4;
-            const uint32_t a = (bl <= bt ? v4.x : 0u) + (bl + 1 <= bt ? v4.y : 0u) +
-                               (bl + 2 <= bt ? v4.z : 0u) + (bl + 3 <= bt ? v4.w : 0u);
-            const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_sum(a), 63);
-            if (lane == c) out[c] = tot;
+                for (int c = 0; c < KMAX; ++c)
+                    if (lane == c) out[c] = best.nl != 0 ? best_cl[c] : 0u;
+            }
+        } else {
+            const int bt = best.nl != 0 ? best.b : -1;
+#pragma unroll
+            for (int c = 0; c < KMAX; ++c) {
+                const uint4 v4 =
+                    *reinterpret_cast<const uint4*>(hist + (bi * KMAX + c) * 256 + lane * 4);
+                const int bl = lane * 4;
+                const uint32_t a = (bl <= bt ? v4.x : 0u) + (bl + 1 <= bt ? v4.y : 0u) +
+                                   (bl + 2 <= bt ? v4.z : 0u) + (bl + 3 <= bt ? v4.w : 0u);
+                const uint32_t tot =
+                    (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_sum(a), 63);
+                if (lane == c) out[c] = tot;
+            }
         }
-        if (lane == 0) {
-            F.cand[item] = best;
-            if (F.alg_bytes)
-                atomicAdd((unsigned long long*)&F.alg_bytes[item & 63],
-                          (unsigned long long)len * (unsigned long long)(nf + (j == 0 ? 6 : 0)));
-        }
+        if (lane == 0) F.cand[item] = best;
+        alg += (unsigned long long)len * (unsigned long long)(nf + (j == 0 ? 6 : 0));
         // the histogram is rewritten by the wave's next item
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
+    // one atomic per wave for the statistics
+    if (F.alg_bytes && lane == 0 && alg)
+        atomicAdd((unsigned long long*)&F.alg_bytes[(blockIdx.x * 4u + wave) & 63], alg);
 }
 
 // Large nodes, phase 2: one workgroup per node.  The node's split is the
