@@ -311,6 +311,9 @@ struct ForestDev {
     uint32_t* feat;       // [slot][mtry_cap] the node's drawn features, draw order
     const uint8_t** fcol; // [slot][mtry_cap] their bin columns
     SlotRec* srec;        // [slot] the large nodes of the level
+    uint8_t* kinds;       // [searched node of the level] what its two children need
+                          // next (2 bits each: leaf, wave path, histogram path)
+    unsigned long long* chunk_sums;  // [chunk] (wave-path, histogram-path) children
     const uint32_t* slot_node_in;  // [slot] node of each large-node slot of this level
     uint32_t* slot_node_out;       // [slot] the same for the next level
     const uint32_t* small_in;

@@ -35,6 +35,7 @@ void launch_split_small(const ForestDev&, int, uint32_t, uint32_t, uint32_t, hip
 void launch_hist_tile(const ForestDev&, int, uint32_t, uint32_t, uint32_t, int, hipStream_t);
 void launch_split_finalize(const ForestDev&, int, uint32_t, uint32_t, uint32_t, hipStream_t);
 void launch_draws(const ForestDev&, int, uint32_t, hipStream_t);
+void launch_lists(const ForestDev&, int, uint32_t, hipStream_t);
 // k_importance.hip
 void launch_tree_totals(JobDev*, const TreeDev*, int, uint64_t*, hipStream_t);
 void launch_treeimp(JobDev*, const TreeDev*, int, const uint64_t*, int, hipStream_t);
@@ -153,7 +154,7 @@ struct JobPlan {
 struct Plan {
     std::vector<JobPlan> jp;
     size_t keys, jobs, trees, tree_base, flags, nodes, cls, ngain, small0, small1, cand, cand_cl,
-        feat, fcol, srec, slot0, slot1, ctrs, alg, tot;
+        feat, fcol, srec, kinds, chunk_sums, slot0, slot1, ctrs, alg, tot;
     uint32_t node_cap = 0, slot_cap = 0, small_cap = 0;
     int kmax = 4, ft = 8, max_sha = 1, max_pw = 1, max_D = 1, T_total = 0, mtry_cap = 1,
         npi = 1;
@@ -241,6 +242,8 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     pl.feat = r.take((size_t)pl.slot_cap * pl.mtry_cap * 4);
     pl.fcol = r.take((size_t)pl.slot_cap * pl.mtry_cap * 8);
     pl.srec = r.take((size_t)pl.slot_cap * sizeof(SlotRec));
+    pl.kinds = r.take((size_t)pl.small_cap + pl.slot_cap);
+    pl.chunk_sums = r.take(((size_t)pl.small_cap + pl.slot_cap + 4095) / 4096 * 8);
     pl.slot0 = r.take((size_t)pl.slot_cap * 4);
     pl.slot1 = r.take((size_t)pl.slot_cap * 4);
     // level d < max_D reads ctrs[d] and appends to ctrs[d + 1]
@@ -490,6 +493,8 @@ ForestDev Engine::forest() const {
     F.feat = at<uint32_t>(pl.feat);
     F.fcol = at<const uint8_t*>(pl.fcol);
     F.srec = at<SlotRec>(pl.srec);
+    F.kinds = at<uint8_t>(pl.kinds);
+    F.chunk_sums = at<unsigned long long>(pl.chunk_sums);
     F.npi = pl.npi;
     F.small_rows = (uint32_t)O.small_rows;
     F.mtry_cap = pl.mtry_cap;
@@ -521,6 +526,8 @@ void Engine::grow_level_plain(const ForestDev& F, int level) {
         launch_hist_tile(F, level, sl * pl.npi, pl.npi, (pl.npi + 3) / 4, O.B, st);
         launch_split_finalize(F, level, sl, 1, 1, st);
     }
+    const uint32_t chunks = (c.n_small + c.n_slots + 4095) / 4096;
+    if (chunks && level + 1 < pl.max_D) launch_lists(F, level, chunks, st);
 }
 
 namespace {
@@ -565,6 +572,7 @@ void Engine::enqueue_iteration() {
         ((O.grid_hist ? (uint32_t)O.grid_hist : level_grid((uint64_t)pl.slot_cap * pl.npi, 4, 8192)) +
          7) / 8 * 8;
     const uint32_t g_draw = level_grid(pl.slot_cap, 4, 1024);
+    const uint32_t g_list = level_grid((uint64_t)pl.small_cap + pl.slot_cap, 4096, 1024);
     const uint32_t g_fin =
         O.grid_finalize ? (uint32_t)O.grid_finalize : level_grid(pl.slot_cap, 1, 4096);
     for (int d = 0; d < n_levels; ++d) {
@@ -589,6 +597,8 @@ void Engine::enqueue_iteration() {
         h = clock.begin(stats ? &stats->finalize : nullptr, st);
         launch_split_finalize(F, d, 0, kAll, g_fin, st);
         clock.end(h, st);
+        // the children of the last level are all leaves (maximum depth)
+        if (d + 1 < n_levels) launch_lists(F, d, g_list, st);
     }
 
     // importance

@@ -323,61 +323,33 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out) {
     }
 }
 
-// Four nodes per workgroup (one per wave); the children's list positions are
-// reserved with one atomic per list for the whole workgroup.
+// One wavefront per node (grid-stride over the level's small-node list).
 // The small nodes of tree level `level`: all of them (count from the level's
 // counters, grid-stride) or, with an explicit count, list entries
 // [first, first + count).
 template <int KMAX>
 __global__ __launch_bounds__(256) void k_split_small(ForestDev F0, int level, uint32_t first,
                                                      uint32_t count) {
-    __shared__ uint32_t s_ns[4], s_nl[4], s_base[2];
-    __shared__ unsigned long long s_alg[4];
     const ForestDev F = level_view(F0, level);
     if (count == 0xFFFFFFFFu) {
         first = 0;
         count = level_small(F0, level);
     }
     const int lane = threadIdx.x & 63, wave = (int)uniform(threadIdx.x >> 6);
-    unsigned long long alg = 0;  // statistics, thread 0
-    for (uint32_t base = blockIdx.x * 4u; base < count; base += gridDim.x * 4u) {
-    const uint32_t li = base + wave;
-    SmallOut o;
-    o.kinds[0] = o.kinds[1] = kLeaf;
-    o.child = 0;
-    o.alg = 0;
-    if (li < count) small_node<KMAX>(F, first + li, o);
-    if (lane == 0) {
-        s_ns[wave] = (o.kinds[0] == kSmall) + (o.kinds[1] == kSmall);
-        s_nl[wave] = (o.kinds[0] == kLarge) + (o.kinds[1] == kLarge);
-
-        s_alg[wave] = o.alg;
+    unsigned long long alg = 0;  // statistics
+    for (uint32_t li = blockIdx.x * 4u + (uint32_t)wave; li < count; li += gridDim.x * 4u) {
+        SmallOut o;
+        o.kinds[0] = o.kinds[1] = kLeaf;
+        o.child = 0;
+        o.alg = 0;
+        small_node<KMAX>(F, first + li, o);
+        // what the children need next; the next level's lists are built from these
+        if (lane == 0) F.kinds[first + li] = (uint8_t)(o.kinds[0] | o.kinds[1] << 2);
+        alg += o.alg;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t ts = s_ns[0] + s_ns[1] + s_ns[2] + s_ns[3];
-        const uint32_t tl = s_nl[0] + s_nl[1] + s_nl[2] + s_nl[3];
-        s_base[0] = ts ? atomicAdd(&F.ctr->n_small, ts) : 0u;
-        s_base[1] = tl ? atomicAdd(&F.ctr->n_slots, tl) : 0u;
-        alg += s_alg[0] + s_alg[1] + s_alg[2] + s_alg[3];
-    }
-    __syncthreads();
-    if (lane == 0 && li < count) {
-        uint32_t ps = s_base[0], pl = s_base[1];
-        for (int v = 0; v < wave; ++v) {
-            ps += s_ns[v];
-            pl += s_nl[v];
-        }
-        for (int c = 0; c < 2; ++c) {
-            if (o.kinds[c] == kSmall) put_small(F, ps++, o.child + c);
-            if (o.kinds[c] == kLarge) put_large(F, pl++, o.child + c);
-        }
-    }
-    __syncthreads();  // the shared counts are reused by the next batch
-    }
-    // one atomic per workgroup for the statistics
-    if (F.alg_bytes && threadIdx.x == 0 && alg)
-        atomicAdd((unsigned long long*)&F.alg_bytes[64 + (blockIdx.x & 63)], alg);
+    // one atomic per wave for the statistics
+    if (F.alg_bytes && lane == 0 && alg)
+        atomicAdd((unsigned long long*)&F.alg_bytes[64 + ((blockIdx.x * 4u + wave) & 63)], alg);
 }
 
 // ---------------------------------------------------------------------------
@@ -964,7 +936,10 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
     __syncthreads();
     const uint32_t child = F.next_base + 2u * (F.n_small_cur + slot);
     if (!s_split) {  // stays the leaf it was created as
-        if (tid == 0) mark_unused_pair(F, child);
+        if (tid == 0) {
+            mark_unused_pair(F, child);
+            F.kinds[F.n_small_cur + slot] = 0;
+        }
         __syncthreads();
         continue;
     }
@@ -1028,9 +1003,114 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
         int kinds[2];
         split_node(F, J, tr, id, nd, best, s_runl, cl, cr, cand_gain_fix(best, S, N), child,
                    kinds);
-        enqueue_nodes(F, J, child, kinds, 2);
+        F.kinds[F.n_small_cur + slot] = (uint8_t)(kinds[0] | kinds[1] << 2);
     }
     __syncthreads();  // shared state is reused by the next slot
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Next-level lists, without atomics: searched node i of level d (the small
+// nodes first, then the large-node slots) owns the child pair at
+// next_base + 2i, and its children's kinds were recorded in kinds[i].  Two
+// passes over chunks of kListChunk nodes: count the wave-path and the
+// histogram-path children per chunk, then let every chunk add up the counts
+// of the chunks before it and write its children to the lists in node order.
+constexpr uint32_t kListChunk = 4096;  // 1024 threads x 4 nodes
+
+__device__ __forceinline__ uint32_t level_searched(const ForestDev& F, int level) {
+    return level_small(F, level) + level_slots(F, level);
+}
+
+// Packed (wave path | histogram path << 16) children of 4 nodes from i0.
+__device__ __forceinline__ uint32_t kinds4(const ForestDev& F, uint32_t i0, uint32_t n,
+                                           uint32_t* kd) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        kd[u] = i0 + u < n ? F.kinds[i0 + u] : 0u;
+        const uint32_t a = kd[u] & 3u, b = kd[u] >> 2;
+        c += (a == (uint32_t)kSmall) + (b == (uint32_t)kSmall) +
+             (((a == (uint32_t)kLarge) + (b == (uint32_t)kLarge)) << 16);
+    }
+    return c;
+}
+
+// Sum over the workgroup of 1024 threads (16 waves); all threads get it.
+__device__ __forceinline__ unsigned long long block_sum64(unsigned long long v,
+                                                          unsigned long long* s_w) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
+    if (lane == 0) s_w[wave] = v;
+    __syncthreads();
+    unsigned long long t = 0;
+    for (int w = 0; w < 16; ++w) t += s_w[w];
+    __syncthreads();
+    return t;
+}
+
+__global__ __launch_bounds__(1024) void k_lists_count(ForestDev F, int level) {
+    __shared__ unsigned long long s_w[16];
+    const uint32_t n = level_searched(F, level);
+    const uint32_t nchunks = (n + kListChunk - 1) / kListChunk;
+    for (uint32_t b = blockIdx.x; b < nchunks; b += gridDim.x) {
+        uint32_t kd[4];
+        const uint32_t c = kinds4(F, b * kListChunk + threadIdx.x * 4u, n, kd);
+        const unsigned long long t =
+            block_sum64((unsigned long long)(c & 0xFFFFu) | ((unsigned long long)(c >> 16) << 32),
+                        s_w);
+        if (threadIdx.x == 0) F.chunk_sums[b] = t;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_lists_write(ForestDev F0, int level) {
+    __shared__ unsigned long long s_w[16];
+    __shared__ uint32_t s_wc[16];
+    const ForestDev F = level_view(F0, level);  // appends describe level + 1
+    const uint32_t n = level_searched(F0, level);
+    const uint32_t nchunks = (n + kListChunk - 1) / kListChunk;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (uint32_t b = blockIdx.x; b < nchunks; b += gridDim.x) {
+        // children of the chunks before this one
+        unsigned long long pre = 0;
+        for (uint32_t e = threadIdx.x; e < b; e += 1024) pre += F.chunk_sums[e];
+        pre = block_sum64(pre, s_w);
+        uint32_t kd[4];
+        const uint32_t i0 = b * kListChunk + threadIdx.x * 4u;
+        const uint32_t c = kinds4(F0, i0, n, kd);
+        const uint32_t incl = wave_incl_sum(c);  // per field < 2^16: 4096 nodes, 2 children
+        if (lane == 63) s_wc[wave] = incl;
+        __syncthreads();
+        uint32_t off = incl - c;
+        for (int w = 0; w < wave; ++w) off += s_wc[w];
+        uint32_t ps = (uint32_t)pre + (off & 0xFFFFu), pl = (uint32_t)(pre >> 32) + (off >> 16);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int ch = 0; ch < 2; ++ch) {
+                const uint32_t k = (kd[u] >> (2 * ch)) & 3u;
+                const uint32_t node = F.next_base + 2u * (i0 + u) + ch;
+                if (k == (uint32_t)kSmall) {
+                    if (ps < F.small_cap)
+                        F.small_out[ps] = node;
+                    else
+                        atomicOr(&F.ctr->overflow, 1u);
+                    ++ps;
+                } else if (k == (uint32_t)kLarge) {
+                    if (pl < F.slot_cap)
+                        F.slot_node_out[pl] = node;
+                    else
+                        atomicOr(&F.ctr->overflow, 2u);
+                    ++pl;
+                }
+            }
+        }
+        if (b == nchunks - 1 && threadIdx.x == 1023) {  // the last node's totals
+            F.ctr->n_small = min(ps, F.small_cap);
+            F.ctr->n_slots = min(pl, F.slot_cap);
+        }
+        __syncthreads();  // shared sums are reused by the next chunk
     }
 }
 
@@ -1051,6 +1131,11 @@ void launch_split_small(const ForestDev& F, int level, uint32_t first, uint32_t 
         case 8: hipLaunchKernelGGL(k_split_small<8>, grid, dim3(256), 0, st, F, level, first, count); break;
         default: hipLaunchKernelGGL(k_split_small<16>, grid, dim3(256), 0, st, F, level, first, count); break;
     }
+}
+
+void launch_lists(const ForestDev& F, int level, uint32_t grid_wg, hipStream_t st) {
+    hipLaunchKernelGGL(k_lists_count, dim3(grid_wg), dim3(1024), 0, st, F, level);
+    hipLaunchKernelGGL(k_lists_write, dim3(grid_wg), dim3(1024), 0, st, F, level);
 }
 
 void launch_draws(const ForestDev& F, int level, uint32_t grid_wg, hipStream_t st) {
