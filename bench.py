@@ -160,6 +160,32 @@ def roofline(stats):
         for f in ("hist_large", "hist_small", "finalize", "permut")}
 
 
+def measured_traffic(workload_name, kernel):
+    """HBM-side traffic per launch of the histogram kernel (bytes), from the
+    calibrated FETCH_SIZE + WRITE_SIZE counter summary committed under
+    profiles/, or None when there is none for this workload or the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    if kernel != "hist_large":
+        return None
+    path = os.path.join(ROOT, "profiles", f"k_hist_tile_{workload_name}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.strip().startswith(("traffic_bytes_per_launch",
+                                                        "kernel_source_sha256")):
+                k, v = line.strip().split(":", 1)
+                fields[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2605_09950_amd", "csrc", "k_forest.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(name, jobs, pr):
     """The CPU oracle, unchanged, on a bounded sample of the same workload on
     all host threads: whole iterations in sequence (MADELON-like, planted)
@@ -253,7 +279,8 @@ def main():
     if not args.no_tune:  # results are identical for every choice; timed outside the region
         from paper_2605_09950_amd.autotune import autotune
         t0 = time.perf_counter()
-        tune = autotune(jobs, n_bins=pr["n_bins"], n_perm=pr["n_perm"])
+        tune_report = {}
+        tune = autotune(jobs, n_bins=pr["n_bins"], n_perm=pr["n_perm"], report=tune_report)
         tune_s = time.perf_counter() - t0
     # timed region: iterations replayed from the captured HIP graph
     main_leg = run_gpu(jobs, pr, args.steps, args.warmup, B.FORM_BATCHED, B.RANK_FP32,
@@ -266,13 +293,16 @@ def main():
     assert ev_leg["job_iters"] == main_leg["job_iters"]
     assert all((a == b).all() for a, b in zip(ev_leg["decisions"], main_leg["decisions"]))
     roof, kernels = roofline(ev_leg["stats"])
+    if roof is not None:
+        roof["traffic"] = measured_traffic(args.workload, roof["kernel"])
     st = ev_leg["stats"]
     n_steps = max(1, ev_leg["steps"])
     extra = {"kernels": kernels, "timed_iterations": f"{args.warmup + 1}.."
              f"{args.warmup + main_leg['steps']}", "job_iterations": main_leg["job_iters"],
              "device_iter_ms": round(st.iter_ms / n_steps, 3),
-             "tune": dict(tune or {}, **({"search_s": round(tune_s, 2)} if tune is not None
-                                         else {})),
+             "tune": dict(tune or {}, **({"search_s": round(tune_s, 2),
+                                          "sessions": tune_report.get("sessions", 0)}
+                                         if tune is not None else {})),
              "eager_" + unit.replace("/", "_per_"): round(ev_leg["job_iters"] /
                                                          ev_leg["seconds"], 3),
              "nodes_per_step_by_depth": {

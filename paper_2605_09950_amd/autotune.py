@@ -60,10 +60,11 @@ def _time_session(dev_jobs, shapes, n_bins, n_perm, tune, steps, warmup):
     return el / max(1, done) * 1e3
 
 
-def autotune(jobs, n_bins=256, n_perm=1, steps=3, warmup=2, cache=None, log=None):
+def autotune(jobs, n_bins=256, n_perm=1, steps=3, warmup=2, cache=None, log=None, report=None):
     """Returns the fastest tuning dict for `jobs` (host arrays, as for
     boruta_fit_batch).  With `cache` (a JSON file path) a stored result for
-    the same signature is reused and a new one is stored."""
+    the same signature is reused and a new one is stored.  `report` (a dict)
+    receives the number of timed sessions and their times."""
     import torch
     sig = signature(jobs, n_bins, n_perm)
     if cache and os.path.exists(cache):
@@ -94,6 +95,9 @@ def autotune(jobs, n_bins=256, n_perm=1, steps=3, warmup=2, cache=None, log=None
                 log(f"autotune {cand}: {ms:.3f} ms/step")
             if ms < best_ms:
                 best, best_ms = cand, ms
+    if report is not None:
+        report["sessions"] = len(trials)
+        report["trials"] = [{"tune": t, "ms_per_step": round(m, 4)} for t, m in trials]
     if cache:
         stored = {}
         if os.path.exists(cache):

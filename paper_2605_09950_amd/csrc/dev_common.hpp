@@ -299,6 +299,11 @@ __device__ __forceinline__ uint32_t rec_y(uint64_t r) { return (uint32_t)(r >> 4
 
 constexpr int kSmallRows = 64;  // nodes with at most this many distinct rows take the wave path
 constexpr int kWave = 64;
+constexpr uint32_t kAlgWords = 1024;  // statistics words per kernel
+
+// Draws per histogram work item (one wavefront, LDS histogram of
+// hist_fw * kmax rows of 256 bins): 4 KB per wave up to 4 classes.
+__host__ __device__ constexpr int hist_fw(int kmax) { return kmax <= 4 ? 4 / kmax : 1; }
 
 struct ForestDev {
     JobDev* jobs;
@@ -321,8 +326,8 @@ struct ForestDev {
     LevelCtr* ctr;        // counters the current launch appends to (set per kernel)
     LevelCtr* ctrs;       // [levels + 1]: ctrs[d] counts the lists of tree level d
     uint32_t n_roots;     // trees of the iteration (= root nodes [0, n_roots))
-    uint64_t* alg_bytes;  // [2][64] algorithmic bytes (large, small), nullable; the
-                          // 64 words per kernel spread the atomics
+    uint64_t* alg_bytes;  // [2][kAlgWords] algorithmic bytes (large, small), nullable;
+                          // the words per kernel spread the atomics
     uint32_t node_cap, slot_cap, small_cap;
     uint32_t next_base;   // first node index of the next level
     uint32_t n_small_cur; // small nodes searched in this level

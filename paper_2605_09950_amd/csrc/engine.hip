@@ -221,7 +221,7 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
         pl.T_total += s.T;
     }
     // histogram items per large node: FW = 8 / kmax draws each (1 for 16 classes)
-    pl.npi = (pl.mtry_cap + (pl.kmax <= 8 ? 8 / pl.kmax : 1) - 1) / (pl.kmax <= 8 ? 8 / pl.kmax : 1);
+    pl.npi = (pl.mtry_cap + hist_fw(pl.kmax) - 1) / hist_fw(pl.kmax);
     if (node_cap >= 0xFFFFFFF0ull || slot_cap * (uint64_t)pl.npi >= 0xFFFFFFF0ull ||
         small_cap >= 0xFFFFFFF0ull)
         throw Error(BORUTA_E_INVALID_ARG, "problem too large: more than 2^32 tree nodes");
@@ -248,7 +248,7 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     pl.slot1 = r.take((size_t)pl.slot_cap * 4);
     // level d < max_D reads ctrs[d] and appends to ctrs[d + 1]
     pl.ctrs = r.take((size_t)(pl.max_D + 2) * sizeof(LevelCtr));
-    pl.alg = r.take(128 * 8);
+    pl.alg = r.take(2 * kAlgWords * 8);
     pl.tot = r.take((size_t)pl.T_total * 8);
     pl.total = r.total + 256;
     return pl;
@@ -475,7 +475,7 @@ void Engine::setup(std::vector<int>& status) {
     }
     h2d(at<TreeDev>(pl.trees), trees.data(), trees.size() * sizeof(TreeDev));
     h2d(at<int32_t>(pl.tree_base), tree_base.data(), tree_base.size() * 4);
-    launch_fill_u32(at<uint32_t>(pl.alg), 256, 0u, st);
+    launch_fill_u32(at<uint32_t>(pl.alg), 4 * kAlgWords, 0u, st);
     h2d(at<JobDev>(pl.jobs), hj.data(), hj.size() * sizeof(JobDev));
     HIPC(hipStreamSynchronize(st));
 }
@@ -754,13 +754,13 @@ int Engine::step() {
 
 void Engine::flush_stats() {
     if (!O.stats) return;
-    uint64_t ab[128];
-    d2h(ab, at<uint64_t>(pl.alg), sizeof(ab));
-    for (int i = 0; i < 64; ++i) {
+    std::vector<uint64_t> ab(2 * kAlgWords);
+    d2h(ab.data(), at<uint64_t>(pl.alg), ab.size() * 8);
+    for (uint32_t i = 0; i < kAlgWords; ++i) {
         O.stats->hist_large.alg_bytes += (double)ab[i];
-        O.stats->hist_small.alg_bytes += (double)ab[64 + i];
+        O.stats->hist_small.alg_bytes += (double)ab[kAlgWords + i];
     }
-    launch_fill_u32(at<uint32_t>(pl.alg), 256, 0u, st);
+    launch_fill_u32(at<uint32_t>(pl.alg), 4 * kAlgWords, 0u, st);
 }
 
 void Engine::result(int j, Out& o) {

@@ -349,7 +349,8 @@ __global__ __launch_bounds__(256) void k_split_small(ForestDev F0, int level, ui
     }
     // one atomic per wave for the statistics
     if (F.alg_bytes && lane == 0 && alg)
-        atomicAdd((unsigned long long*)&F.alg_bytes[64 + ((blockIdx.x * 4u + wave) & 63)], alg);
+        atomicAdd((unsigned long long*)&F.alg_bytes[kAlgWords + ((blockIdx.x * 4u + wave) &
+                                                                 (kAlgWords - 1))], alg);
 }
 
 // ---------------------------------------------------------------------------
@@ -711,8 +712,8 @@ __global__ __launch_bounds__(256) void k_draws(ForestDev F, int level) {
 }
 
 // Large nodes, phase 1: one wavefront per (node, FW consecutive draws)
-// item, with its own LDS histogram [FW][KMAX][256] (8 KB; 16 KB for 9-16
-// classes).  The wave gathers the bins of its features at the node's rows,
+// item, with its own LDS histogram [FW][KMAX][256] (4 KB up to 4 classes,
+// 8 KB / 16 KB for 5-8 / 9-16 classes).  The wave gathers the bins of its features at the node's rows,
 // accumulates the weighted class counts with LDS atomics (class-major rows
 // spread a wave's atomics over the banks by bin), scans each feature and
 // writes the item's best candidate and its left class counts.  No barriers:
@@ -720,7 +721,7 @@ __global__ __launch_bounds__(256) void k_draws(ForestDev F, int level) {
 template <int KMAX>
 __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint32_t first,
                                                    uint32_t count) {
-    constexpr int FW = KMAX <= 8 ? 8 / KMAX : 1;
+    constexpr int FW = hist_fw(KMAX);
     constexpr int WORDS = FW * KMAX * 256;
     constexpr int RB = 4;  // rows per lane per batch: RB record loads, RB * FW gathers in flight
     extern __shared__ uint4 lds_raw[];
@@ -848,7 +849,8 @@ __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint3
     }
     // one atomic per wave for the statistics
     if (F.alg_bytes && lane == 0 && alg)
-        atomicAdd((unsigned long long*)&F.alg_bytes[(blockIdx.x * 4u + wave) & 63], alg);
+        atomicAdd((unsigned long long*)&F.alg_bytes[(blockIdx.x * 4u + wave) & (kAlgWords - 1)],
+                  alg);
 }
 
 // Large nodes, phase 2: one workgroup per node.  The node's split is the
@@ -886,7 +888,7 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
     // threshold: each lane of wave 0 keeps the best of its items, then one
     // wave reduction
     if (tid < 64) {
-        const int fw = F.kmax <= 8 ? 8 / F.kmax : 1;
+        const int fw = hist_fw(F.kmax);
         const int ni = (J.mtry + fw - 1) / fw;
         Cand c;
         c.nl = 0;
@@ -1145,8 +1147,8 @@ void launch_draws(const ForestDev& F, int level, uint32_t grid_wg, hipStream_t s
 void launch_hist_tile(const ForestDev& F, int level, uint32_t first, uint32_t count,
                       uint32_t grid_wg, int B, hipStream_t st) {
     if (!count) return;
-    // four waves of FW * KMAX * 256 words (FW * KMAX = 8, or 16 for 16 classes)
-    const size_t lds = (size_t)4 * (F.kmax <= 8 ? 8 : 16) * 256 * sizeof(uint32_t);
+    // four waves of FW * KMAX * 256 words
+    const size_t lds = (size_t)4 * hist_fw(F.kmax) * F.kmax * 256 * sizeof(uint32_t);
     const dim3 grid(grid_wg);
     switch (F.kmax) {
         case 2: hipLaunchKernelGGL(k_hist_tile<2>, grid, dim3(256), lds, st, F, level, first, count); break;
