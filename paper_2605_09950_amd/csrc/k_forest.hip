@@ -268,21 +268,22 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out) {
                 lq = qc;
             }
         };
-        // bins of eight passes are in flight while the previous eight are scored
-        int bq[8];
+        // bins of kPF passes are in flight while the previous kPF are scored
+        constexpr int kPF = 4;
+        int bq[kPF];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) bq[u] = gather(u);
-        for (int pb = 0; pb < passes; pb += 8) {
-            int bn[8];
-            if (pb + 8 < passes) {
+        for (int u = 0; u < kPF; ++u) bq[u] = gather(u);
+        for (int pb = 0; pb < passes; pb += kPF) {
+            int bn[kPF];
+            if (pb + kPF < passes) {
 #pragma unroll
-                for (int u = 0; u < 8; ++u) bn[u] = gather(pb + 8 + u);
+                for (int u = 0; u < kPF; ++u) bn[u] = gather(pb + kPF + u);
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
+            for (int u = 0; u < kPF; ++u)
                 if (pb + u < passes) eval(pb + u, bq[u]);
 #pragma unroll
-            for (int u = 0; u < 8; ++u) bq[u] = bn[u];
+            for (int u = 0; u < kPF; ++u) bq[u] = bn[u];
         }
     }
     const Cand best = fp32 ? wave_best_total_fp32(lb, lb.nl != 0 ? lq : -1.0f)
