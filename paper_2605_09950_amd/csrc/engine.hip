@@ -574,7 +574,7 @@ void Engine::enqueue_iteration() {
     const uint32_t g_draw = level_grid(pl.slot_cap, 4, 1024);
     const uint32_t g_list = level_grid((uint64_t)pl.small_cap + pl.slot_cap, 4096, 1024);
     const uint32_t g_fin =
-        O.grid_finalize ? (uint32_t)O.grid_finalize : level_grid(pl.slot_cap, 1, 4096);
+        O.grid_finalize ? (uint32_t)O.grid_finalize : level_grid(pl.slot_cap, 4, 4096);
     for (int d = 0; d < n_levels; ++d) {
         // lists, slots and row records of level d are read from parity d & 1
         // and the children of level d go to the other parity

@@ -854,43 +854,40 @@ __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint3
                   alg);
 }
 
-// Large nodes, phase 2: one workgroup per node.  The node's split is the
-// best tile candidate (tiles hold increasing draw positions, so keeping the
-// first of equal candidates keeps the earliest draw); a strictly positive
-// decrease splits the node and its rows are partitioned stably, left first.
+// Large nodes, phase 2: one wavefront per node (four per workgroup, no
+// barriers).  The node's split is the best of its histogram items' candidates
+// (exact score, then draw position, then threshold); a strictly positive
+// decrease splits the node and its rows are partitioned in one pass: left
+// rows from the front in row order, right rows from the back in reverse row
+// order.  No result depends on the order of a node's rows, and each child
+// segment stays monotone in row index for the next level's gathers.
 template <int KMAX>
 __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level, uint32_t first,
                                                         uint32_t count) {
-    __shared__ Cand s_best;
-    __shared__ int s_split, s_bt, s_part;
-    __shared__ uint32_t s_wcnt[4];
-    __shared__ uint32_t s_runl, s_runr;
     const ForestDev F = level_view(F0, level);
     if (count == 0xFFFFFFFFu) {
         first = 0;
         count = level_slots(F0, level);
     }
-    for (uint32_t k = blockIdx.x; k < count; k += gridDim.x) {
-    const uint32_t slot = first + k;
-    const uint32_t id = F.slot_node_in[slot];
-    const NodeDev nd = F.nodes[id];
-    const TreeDev tr = F.trees[nd.tree];
-    JobDev& J = F.jobs[tr.job];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    uint32_t cnode[KMAX];
-    uint64_t S = 0;
+    const int lane = threadIdx.x & 63, wave = (int)uniform(threadIdx.x >> 6);
+    for (uint32_t k = blockIdx.x * 4u + (uint32_t)wave; k < count; k += gridDim.x * 4u) {
+        const uint32_t slot = first + k;
+        const SlotRec& sr = F.srec[slot];
+        const uint32_t id = sr.id;
+        const NodeDev nd = F.nodes[id];
+        const TreeDev tr = F.trees[nd.tree];
+        JobDev& J = F.jobs[tr.job];
+        uint32_t cnode[KMAX];
+        uint64_t S = 0;
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-        cnode[k] = k < J.K ? F.cls[(size_t)id * F.kmax + k] : 0u;
-        S += (uint64_t)cnode[k] * cnode[k];
-    }
-    const uint32_t N = nd.n;
-    // the node's item candidates, ranked by score, then draw position, then
-    // threshold: each lane of wave 0 keeps the best of its items, then one
-    // wave reduction
-    if (tid < 64) {
+        for (int c = 0; c < KMAX; ++c) {
+            cnode[c] = sr.cnode[c];
+            S += (uint64_t)cnode[c] * cnode[c];
+        }
+        const uint32_t N = sr.n;
+        // rank the items' candidates: each lane keeps the best of its items
         const int fw = hist_fw(F.kmax);
-        const int ni = (J.mtry + fw - 1) / fw;
+        const int ni = ((int)sr.mtry + fw - 1) / fw;
         Cand c;
         c.nl = 0;
         c.q = 0x7FFFFFFF;
@@ -900,115 +897,85 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
         c.pad = 0;
         c.sl = c.sr = 0;
         int ci = -1;
-        for (int t = tid; t < ni; t += 64) {
+        for (int t = lane; t < ni; t += 64) {
             const Cand d = F.cand[(size_t)slot * F.npi + t];
             if (d.nl != 0 && (c.nl == 0 || cand_wins_total(d, c))) {
                 c = d;
                 ci = t;
             }
         }
-        const Cand w = wave_best_total_exact(c);
+        const Cand best = wave_best_total_exact(c);
         const unsigned long long hit =
-            __ballot(w.nl != 0 && c.nl != 0 && c.q == w.q && c.b == w.b);
-        if (tid == (int)(hit ? __ffsll(hit) - 1 : 0)) {
-            s_best = w;
-            s_bt = hit ? ci : -1;
+            __ballot(best.nl != 0 && c.nl != 0 && c.q == best.q && c.b == best.b);
+        const int bt = hit ? __shfl(ci, (int)__ffsll(hit) - 1) : -1;
+        const uint32_t child = F.next_base + 2u * (F.n_small_cur + slot);
+        const bool split = bt >= 0 && cand_positive(best, S, N);
+        if (!split) {  // stays the leaf it was created as
+            if (lane == 0) {
+                mark_unused_pair(F, child);
+                F.kinds[F.n_small_cur + slot] = 0;
+            }
+            continue;
         }
-    }
-    __syncthreads();
-    const int bt = s_bt;
-    if (tid == 0) {
-        s_split = bt >= 0 && cand_positive(s_best, S, N);
-        s_runl = 0;
-        s_runr = 0;
+        const uint32_t* clt = F.cand_cl + ((size_t)slot * F.npi + bt) * F.kmax;
+        uint32_t cl[16], cr[16];
+        int nzl = 0, nzr = 0;
+#pragma unroll
+        for (int c2 = 0; c2 < 16; ++c2) {
+            cl[c2] = c2 < KMAX ? clt[c2] : 0u;
+            cr[c2] = (c2 < KMAX ? cnode[c2] : 0u) - cl[c2];
+            nzl += cl[c2] != 0;
+            nzr += cr[c2] != 0;
+        }
         // Rows are partitioned only for a child that is searched next: below
         // the maximum depth with two or more classes (which implies two or
         // more distinct rows); other children are final leaves.
-        s_part = 0;
-        if (s_split && (int)nd.depth + 1 < J.D) {
-            const uint32_t* clt = F.cand_cl + ((size_t)slot * F.npi + bt) * F.kmax;
-            int nzl = 0, nzr = 0;
-            for (int k = 0; k < KMAX; ++k) {
-                const uint32_t l = clt[k];
-                nzl += l != 0;
-                nzr += cnode[k] != l;
+        const bool part = (int)nd.depth + 1 < J.D && (nzl >= 2 || nzr >= 2);
+        const uint8_t* col = ldg(J.colptr + best.f);
+        const uint64_t* recs = sr.recs;
+        uint64_t* rout = J.rec[F.parity ^ 1] + (size_t)tr.tau * J.n + nd.seg;
+        constexpr int kR = 8;  // rows per lane per block: lane l owns rows [l kR, l kR + kR)
+        const uint32_t len = part ? sr.len : 0u;
+        uint32_t runl = 0, runr = 0;
+        for (uint32_t blk = 0; blk < len; blk += 64 * kR) {
+            const uint32_t i0 = blk + (uint32_t)lane * kR;
+            uint64_t r[kR];
+#pragma unroll
+            for (int u = 0; u < kR; ++u) r[u] = i0 + u < len ? ldg(recs + i0 + u) : 0ull;
+            int bb[kR];
+#pragma unroll
+            for (int u = 0; u < kR; ++u)
+                bb[u] = i0 + u < len ? (int)ldg(col + rec_row(r[u])) : 0x7FFF;
+            uint32_t nlm = 0, nrm = 0;
+#pragma unroll
+            for (int u = 0; u < kR; ++u) {
+                nlm += bb[u] <= best.b;
+                nrm += i0 + u < len && bb[u] > best.b;
             }
-            s_part = nzl >= 2 || nzr >= 2;
-        }
-    }
-    __syncthreads();
-    const uint32_t child = F.next_base + 2u * (F.n_small_cur + slot);
-    if (!s_split) {  // stays the leaf it was created as
-        if (tid == 0) {
-            mark_unused_pair(F, child);
-            F.kinds[F.n_small_cur + slot] = 0;
-        }
-        __syncthreads();
-        continue;
-    }
-    const Cand best = s_best;
-    const uint8_t* col = ldg(J.colptr + best.f);
-    const uint64_t* recs = J.rec[F.parity] + (size_t)tr.tau * J.n + nd.seg;
-    uint64_t* rout = J.rec[F.parity ^ 1] + (size_t)tr.tau * J.n + nd.seg;
-    // One pass over blocks of 256 x kR rows (thread t owns rows
-    // [blk + t kR, blk + t kR + kR)): left rows are written from the front in
-    // row order, right rows from the back in reverse row order.  No result
-    // depends on the order of a node's rows; each child segment stays
-    // monotone in row index, which keeps the next level's gathers local.
-    constexpr int kR = 8;
-    const uint32_t len = s_part ? nd.len : 0u;  // no partition: both children are leaves
-    for (uint32_t blk = 0; blk < len; blk += 256 * kR) {
-        const uint32_t i0 = blk + (uint32_t)tid * kR;
-        uint64_t r[kR];
+            // exclusive prefix of (left, right) over the lanes, both packed in
+            // one word (a block holds 512 rows)
+            const uint32_t mine = nlm | (nrm << 16);
+            const uint32_t incl = wave_incl_sum(mine);
+            const uint32_t pre = incl - mine;
+            const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+            uint32_t lrow = runl + (pre & 0xFFFFu), rrow = runr + (pre >> 16);
 #pragma unroll
-        for (int u = 0; u < kR; ++u) r[u] = i0 + u < len ? ldg(recs + i0 + u) : 0ull;
-        int bb[kR];
-#pragma unroll
-        for (int u = 0; u < kR; ++u) bb[u] = i0 + u < len ? (int)ldg(col + rec_row(r[u])) : 0x7FFF;
-        uint32_t nlm = 0, nrm = 0;
-#pragma unroll
-        for (int u = 0; u < kR; ++u) {
-            nlm += bb[u] <= best.b;
-            nrm += i0 + u < len && bb[u] > best.b;
+            for (int u = 0; u < kR; ++u) {
+                if (i0 + u >= len) break;
+                if (bb[u] <= best.b)
+                    rout[lrow++] = r[u];
+                else
+                    rout[len - 1 - rrow++] = r[u];
+            }
+            runl += tot & 0xFFFFu;
+            runr += tot >> 16;
         }
-        // exclusive prefix of (left, right) counts over the block's threads,
-        // both packed in one word (a block holds at most 2048 rows)
-        const uint32_t mine = nlm | (nrm << 16);
-        const uint32_t incl = wave_incl_sum(mine);
-        if (lane == 63) s_wcnt[wave] = incl;
-        __syncthreads();
-        uint32_t pre = incl - mine;
-        for (int v = 0; v < wave; ++v) pre += s_wcnt[v];
-        const uint32_t blk_tot = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
-        uint32_t lrow = s_runl + (pre & 0xFFFFu), rrow = s_runr + (pre >> 16);
-#pragma unroll
-        for (int u = 0; u < kR; ++u) {
-            if (i0 + u >= len) break;
-            if (bb[u] <= best.b)
-                rout[lrow++] = r[u];
-            else
-                rout[len - 1 - rrow++] = r[u];
+        if (lane == 0) {
+            int kinds[2];
+            split_node(F, J, tr, id, nd, best, runl, cl, cr, cand_gain_fix(best, S, N), child,
+                       kinds);
+            F.kinds[F.n_small_cur + slot] = (uint8_t)(kinds[0] | kinds[1] << 2);
         }
-        __syncthreads();
-        if (tid == 0) {
-            s_runl += blk_tot & 0xFFFFu;
-            s_runr += blk_tot >> 16;
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        const uint32_t* clt = F.cand_cl + ((size_t)slot * F.npi + s_bt) * F.kmax;
-        uint32_t cl[16], cr[16];
-        for (int k = 0; k < 16; ++k) {
-            cl[k] = k < KMAX ? clt[k] : 0u;
-            cr[k] = (k < KMAX ? cnode[k] : 0u) - cl[k];
-        }
-        int kinds[2];
-        split_node(F, J, tr, id, nd, best, s_runl, cl, cr, cand_gain_fix(best, S, N), child,
-                   kinds);
-        F.kinds[F.n_small_cur + slot] = (uint8_t)(kinds[0] | kinds[1] << 2);
-    }
-    __syncthreads();  // shared state is reused by the next slot
     }
 }
 
