@@ -332,6 +332,9 @@ public:
     ~Engine() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (side) (void)hipStreamDestroy(side);
     }
     Engine(const Engine&) = delete;
     Engine& operator=(const Engine&) = delete;
@@ -378,6 +381,8 @@ private:
     boruta_kernel_stat iter_stat{};  // event time of whole iterations
     hipGraph_t graph = nullptr;      // captured iteration (batched form)
     hipGraphExec_t gexec = nullptr;
+    hipStream_t side = nullptr;      // second stream of the batched form
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<JobDev> hj;       // host mirror of the job records
     std::vector<int> tree_base;   // first tree of each job in the static tree table
     bool any_treeimp = false, any_permut = false;
@@ -385,6 +390,11 @@ private:
 
 void Engine::setup(std::vector<int>& status) {
     const int nj = (int)S.size();
+    if (O.form == BORUTA_FORM_BATCHED) {
+        HIPC(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+        HIPC(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+        HIPC(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+    }
     hj.assign(nj, JobDev{});
     uint32_t* flags = at<uint32_t>(pl.flags);
     for (int j = 0; j < nj; ++j) {
@@ -587,9 +597,21 @@ void Engine::enqueue_iteration() {
             grow_level_plain(F, d);
             continue;
         }
-        size_t h = clock.begin(stats ? &stats->hist_small : nullptr, st);
-        launch_split_small(F, d, 0, kAll, g_small, st);
-        clock.end(h, st);
+        // The small nodes and the large nodes of a level touch disjoint
+        // nodes, child pairs, row segments and kinds entries: without kernel
+        // statistics the small-node launch runs on a second stream, beside
+        // the large-node kernels, and rejoins before the lists are built.
+        const bool fork = !stats && side != nullptr;
+        hipStream_t ss = st;
+        if (fork) {
+            HIPC(hipEventRecord(ev_fork, st));
+            HIPC(hipStreamWaitEvent(side, ev_fork, 0));
+            ss = side;
+        }
+        size_t h = clock.begin(stats ? &stats->hist_small : nullptr, ss);
+        launch_split_small(F, d, 0, kAll, g_small, ss);
+        clock.end(h, ss);
+        if (fork) HIPC(hipEventRecord(ev_join, side));
         launch_draws(F, d, g_draw, st);
         h = clock.begin(stats ? &stats->hist_large : nullptr, st);
         launch_hist_tile(F, d, 0, kAll, g_tile, O.B, st);
@@ -597,6 +619,7 @@ void Engine::enqueue_iteration() {
         h = clock.begin(stats ? &stats->finalize : nullptr, st);
         launch_split_finalize(F, d, 0, kAll, g_fin, st);
         clock.end(h, st);
+        if (fork) HIPC(hipStreamWaitEvent(st, ev_join, 0));
         // the children of the last level are all leaves (maximum depth)
         if (d + 1 < n_levels) launch_lists(F, d, g_list, st);
     }
