@@ -120,7 +120,7 @@ typedef struct {
                              each, grid-stride); default min(4096, needed)       */
     int32_t grid_hist;    /* workgroups of the histogram launch (4 items each),
                              rounded up to a multiple of 8; default
-                             min(8192, needed)                                   */
+                             min(16384, needed)                                  */
     int32_t grid_finalize;/* workgroups of the split/partition launch (4 nodes
                              each, grid-stride); default min(4096, needed)       */
     boruta_trace_fn trace;/* nullable                                              */

@@ -20,8 +20,8 @@ from paper_2605_09950_amd import binding as B
 # candidate values per parameter, in search order (0 = library default)
 CANDIDATES = (
     ("small_rows", (32, 64, 48, 16)),
-    ("grid_hist", (0, 2048, 4096, 16384)),
-    ("grid_small", (0, 1024, 2048, 8192)),
+    ("grid_hist", (0, 4096, 32768, 65536)),
+    ("grid_small", (0, 1024, 2048, 8192, 16384)),
     ("grid_finalize", (0, 1024, 2048, 8192)),
 )
 

@@ -579,7 +579,7 @@ void Engine::enqueue_iteration() {
         O.grid_small ? (uint32_t)O.grid_small : level_grid(pl.small_cap, 4, 4096);
     // a multiple of 8: workgroup b serves the node slots congruent to b mod 8
     const uint32_t g_tile =
-        ((O.grid_hist ? (uint32_t)O.grid_hist : level_grid((uint64_t)pl.slot_cap * pl.npi, 4, 8192)) +
+        ((O.grid_hist ? (uint32_t)O.grid_hist : level_grid((uint64_t)pl.slot_cap * pl.npi, 4, 16384)) +
          7) / 8 * 8;
     const uint32_t g_draw = level_grid(pl.slot_cap, 4, 1024);
     const uint32_t g_list = level_grid((uint64_t)pl.small_cap + pl.slot_cap, 4096, 1024);

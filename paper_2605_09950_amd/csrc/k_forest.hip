@@ -534,33 +534,42 @@ __device__ Cand feature_best_compact(uint32_t* h, int B, int q, int f, const uin
         const uint32_t a = v.x + v.y + v.z + v.w;
         excl[k] = wave_incl_sum(a) - a;
     }
-    // the lane's thresholds worth scoring, their prefix counts
-    uint32_t cl[4][KMAX];
-    bool ok[4];
-    uint32_t cnt = 0;
+    // the lane's thresholds worth scoring: a non-empty bin below B - 1 with
+    // rows on both sides (prefix counts are rebuilt in the writing pass)
+    uint32_t okm = 0, cnt = 0;
+    {
+        uint32_t nl = 0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        uint32_t add = 0, nl = 0;
+        for (int k = 0; k < KMAX; ++k) nl += excl[k];
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            cl[u][k] = (u == 0 ? excl[k] : cl[u - 1][k]) + hv[k][u];
-            add += hv[k][u];
-            nl += cl[u][k];
+        for (int u = 0; u < 4; ++u) {
+            uint32_t add = 0;
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) add += hv[k][u];
+            nl += add;
+            const bool ok = b0 + u <= B - 2 && add != 0 && nl != 0 && nl != N;
+            okm |= (uint32_t)ok << u;
+            cnt += ok;
         }
-        ok[u] = b0 + u <= B - 2 && add != 0 && nl != 0 && nl != N;
-        cnt += ok[u];
     }
     const uint32_t incl = wave_incl_sum(cnt);
     const int total = __builtin_amdgcn_readlane((int)incl, 63);
     uint32_t pos = incl - cnt;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // h has been read
+    {
+        uint32_t cl[KMAX];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        if (ok[u]) {
+        for (int k = 0; k < KMAX; ++k) cl[k] = excl[k];
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k)
-                h[pos * KMAX + k] = cl[u][k] | (k == 0 ? (uint32_t)(b0 + u) << 24 : 0u);
-            ++pos;
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) cl[k] += hv[k][u];
+            if (okm >> u & 1u) {
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k)
+                    h[pos * KMAX + k] = cl[k] | (k == 0 ? (uint32_t)(b0 + u) << 24 : 0u);
+                ++pos;
+            }
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -724,7 +733,7 @@ __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint3
                                                    uint32_t count) {
     constexpr int FW = hist_fw(KMAX);
     constexpr int WORDS = FW * KMAX * 256;
-    constexpr int RB = 4;  // rows per lane per batch: RB record loads, RB * FW gathers in flight
+    constexpr int RB = 8;  // rows per lane per batch: RB record loads, RB * FW gathers in flight
     extern __shared__ uint4 lds_raw[];
     const int lane = threadIdx.x & 63, wave = (int)uniform(threadIdx.x >> 6);
     uint32_t* hist = reinterpret_cast<uint32_t*>(lds_raw) + wave * WORDS;
