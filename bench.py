@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the other-mode / exact / plain comparison legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--set", default="", metavar="KEY=V,...",
+                    help="launch tuning values (boruta_options fields), instead of the autotuner")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the device-timed autotuner (library default launch parameters)")
     ap.add_argument("--probe-copy", type=int, default=0, metavar="BYTES",
@@ -275,11 +277,12 @@ def main():
             jd["importance_mode"] = B.TREEIMP if args.mode == "treeimp" else B.PERMUT
     mode = jobs[0]["importance_mode"]
     unit = "job-iters/s" if len(jobs) > 1 else "iters/s"
-    tune = None
-    if not args.no_tune:  # results are identical for every choice; timed outside the region
+    tune, tune_s, tune_report = None, 0.0, {}
+    if args.set:
+        tune = {k: int(v) for k, v in (kv.split("=") for kv in args.set.split(","))}
+    elif not args.no_tune:  # results are identical for every choice; timed outside the region
         from paper_2605_09950_amd.autotune import autotune
         t0 = time.perf_counter()
-        tune_report = {}
         tune = autotune(jobs, n_bins=pr["n_bins"], n_perm=pr["n_perm"], report=tune_report)
         tune_s = time.perf_counter() - t0
     # timed region: iterations replayed from the captured HIP graph

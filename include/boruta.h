@@ -123,6 +123,19 @@ typedef struct {
                              min(16384, needed)                                  */
     int32_t grid_finalize;/* workgroups of the split/partition launch (4 nodes
                              each, grid-stride); default min(4096, needed)       */
+    int32_t col_level;    /* large nodes of tree levels >= col_level take the
+                             column-major histogram path (items bucketed by bin
+                             column, each column staged once per unit in LDS);
+                             [1, 64], 64 = never; 0 (default) = automatic: level
+                             5 when some job's widened bin matrix (2p columns of
+                             n rounded up to 256 bytes) exceeds 128 MiB, else
+                             never.  The path needs a whole bin column plus two
+                             histograms in one workgroup's LDS; where it does
+                             not fit, every level stays node-major.              */
+    int32_t col_unit;     /* items (node, draw) per unit of that path, [1, 65536];
+                             default 512                                          */
+    int32_t grid_col;     /* workgroups of its histogram launch (one unit at a
+                             time, grid-stride); default min(2048, needed)      */
     boruta_trace_fn trace;/* nullable                                              */
     void* trace_user;
     boruta_stats* stats;  /* nullable                                              */

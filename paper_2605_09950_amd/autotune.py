@@ -1,9 +1,10 @@
 """Device-timed search over the launch parameters of the batched form.
 
 The tunable parameters (boruta_options.small_rows, grid_small, grid_hist,
-grid_finalize) change only how the work of a tree level is spread over
-workgroups and which of the two split-search paths a node takes; every
-choice gives identical results.  The search is a coordinate descent: each
+grid_finalize, col_level, col_unit, grid_col) change only how the work of a
+tree level is spread over workgroups, which of the two split-search paths a
+node takes and which of the two histogram layouts a level uses; every choice
+gives identical results.  The search is a coordinate descent: each
 parameter in turn is set to each of its candidate values, a session over the
 workload is stepped a few times (graph replays, inputs resident on the
 device), and the fastest value is kept.  The outcome can be cached as JSON,
@@ -22,6 +23,9 @@ from paper_2605_09950_amd import binding as B
 # the library default (32) unless the caller asks for it, so that per-kernel
 # measurements stay comparable between tuned runs.
 CANDIDATES = (
+    ("col_level", (64, 5, 3, 7)),
+    ("col_unit", (256, 1024)),
+    ("grid_col", (1024, 4096)),
     ("grid_hist", (0, 4096, 32768, 65536)),
     ("grid_small", (0, 1024, 2048, 8192, 16384)),
     ("grid_finalize", (0, 1024, 2048, 8192)),

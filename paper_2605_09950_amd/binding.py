@@ -60,6 +60,9 @@ class Options(ctypes.Structure):
                 ("graph", ctypes.c_int32), ("small_rows", ctypes.c_int32),
                 ("grid_small", ctypes.c_int32), ("grid_hist", ctypes.c_int32),
                 ("grid_finalize", ctypes.c_int32),
+                ("col_level", ctypes.c_int32),
+                ("col_unit", ctypes.c_int32),
+                ("grid_col", ctypes.c_int32),
                 ("trace", TRACE_FN), ("trace_user", ctypes.c_void_p),
                 ("stats", ctypes.POINTER(Stats))]
 
@@ -186,7 +189,8 @@ def _trace_collector(store, p, keep_iters=None):
     return TRACE_FN(cb)
 
 
-TUNE_KEYS = ("small_rows", "grid_small", "grid_hist", "grid_finalize")
+TUNE_KEYS = ("small_rows", "grid_small", "grid_hist", "grid_finalize", "col_level", "col_unit",
+             "grid_col")
 
 
 def make_options(n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED, trace=False,

@@ -228,6 +228,8 @@ struct JobDev {
     uint32_t seed_lo, seed_hi;
     int32_t max_sha;       // shadow column capacity
     int32_t pw_cap;        // p + max_sha
+    uint32_t gbase;        // first global column id of the job (column-major histogram path)
+    uint32_t gq;           // 16-byte words of one bin column (n_pad / 16)
     const uint8_t* y;      // [n]
     uint8_t* orig;         // [p][n_pad] binned originals
     uint8_t* sha;          // [max_sha][n_pad] shadows of the current iteration
@@ -286,7 +288,8 @@ struct LevelCtr {
     uint32_t n_slots;   // large nodes
     uint32_t n_small;   // small nodes
     uint32_t overflow;  // a capacity check failed
-    uint32_t pad[3];
+    uint32_t n_units;   // column units of the column-major histogram path
+    uint32_t pad[2];
 };
 
 // Row record: row | weight << 32 | label << 48.
@@ -304,6 +307,15 @@ constexpr uint32_t kAlgWords = 1024;  // statistics words per kernel
 // Draws per histogram work item (one wavefront, LDS histogram of
 // hist_fw * kmax rows of 256 bins): 4 KB per wave up to 4 classes.
 __host__ __device__ constexpr int hist_fw(int kmax) { return kmax <= 4 ? 4 / kmax : 1; }
+
+// Column-major histogram path: a unit is a run of items (node, draw) of one
+// bin column; the column is staged once per unit in LDS.
+struct ColUnit {
+    uint32_t begin, end;  // items [begin, end) of the feature-sorted item list
+    uint32_t gq;          // 16-byte words of the column
+    uint32_t pad;
+};
+constexpr uint32_t kColWavesMax = 16;  // waves per workgroup of the column path
 
 struct ForestDev {
     JobDev* jobs;
@@ -333,9 +345,19 @@ struct ForestDev {
     uint32_t n_small_cur; // small nodes searched in this level
     uint32_t small_ncap;  // a node takes the wave path only below this weighted count
     int32_t kmax, ft, parity, split_rank;
-    int32_t npi;          // histogram items per large node (draw positions / FW)
+    int32_t npi;          // histogram items per large node (draw positions / fw)
+    int32_t fw;           // draws per histogram item
     uint32_t small_rows;  // a node takes the wave path only up to this many distinct rows
     int32_t mtry_cap;     // row stride of feat
+    // column-major histogram path (null when the plan has none)
+    uint32_t* fcnt;       // [n_gcol] items per global column, zero between levels
+    uint32_t* fpos;       // [slot][mtry_cap] an item's place within its column's items,
+                          // then [n_gcol] the columns' offsets in fitems
+    const uint32_t* gcol_q;  // [n_gcol] 16-byte words of each column
+    uint32_t* fitems;     // [slot * mtry_cap] items sorted by column
+    ColUnit* units;       // [unit_cap]
+    uint32_t n_gcol, unit_cap, col_unit;  // columns, unit capacity, items per unit
+    int32_t col_count;    // this level takes the column path: k_draws counts items
 };
 
 }  // namespace boruta

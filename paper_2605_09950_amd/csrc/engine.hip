@@ -36,6 +36,10 @@ void launch_hist_tile(const ForestDev&, int, uint32_t, uint32_t, uint32_t, int, 
 void launch_split_finalize(const ForestDev&, int, uint32_t, uint32_t, uint32_t, hipStream_t);
 void launch_draws(const ForestDev&, int, uint32_t, hipStream_t);
 void launch_lists(const ForestDev&, int, uint32_t, hipStream_t);
+void launch_col_sort(const ForestDev&, int, uint32_t, hipStream_t);
+size_t hist_col_lds(int, int, uint32_t);
+hipError_t prepare_hist_col(int, size_t);
+void launch_hist_col(const ForestDev&, int, uint32_t, int, uint32_t, hipStream_t);
 // k_importance.hip
 void launch_tree_totals(JobDev*, const TreeDev*, int, uint64_t*, hipStream_t);
 void launch_treeimp(JobDev*, const TreeDev*, int, const uint64_t*, int, hipStream_t);
@@ -46,6 +50,17 @@ void launch_copy(void*, const void*, size_t, hipStream_t);
 namespace {
 
 thread_local std::string g_err;
+
+// LDS a gfx950 workgroup may allocate (checked against the device at set-up).
+constexpr size_t kLdsPerWorkgroup = 160 * 1024;
+// Column-major histogram path: the first tree level it serves when chosen
+// automatically, the widened bin matrix of one job above which it is chosen
+// (such a matrix no longer stays in the 256 MB last-level cache beside the
+// row records, so node-major gathers pull whole lines from HBM), and the
+// value that disables it.
+constexpr int kColLevelAuto = 5;
+constexpr size_t kColAutoBytes = size_t(128) << 20;
+constexpr int kColNever = 64;
 
 struct Error : std::runtime_error {
     int code;
@@ -71,6 +86,7 @@ struct Spec {
 struct Opts {
     int B = 256, R = 1, split_rank = 1, form = 1, graph = 1;
     int small_rows = 32, grid_small = 0, grid_hist = 0, grid_finalize = 0;
+    int col_level = 0, col_unit = 512, grid_col = 0;
     boruta_trace_fn trace = nullptr;
     void* trace_user = nullptr;
     boruta_stats* stats = nullptr;
@@ -88,6 +104,9 @@ Opts read_opts(const boruta_options* o) {
         r.grid_small = o->grid_small;
         r.grid_hist = o->grid_hist;
         r.grid_finalize = o->grid_finalize;
+        if (o->col_level) r.col_level = o->col_level;
+        if (o->col_unit) r.col_unit = o->col_unit;
+        r.grid_col = o->grid_col;
         r.trace = o->trace;
         r.trace_user = o->trace_user;
         r.stats = o->stats;
@@ -103,6 +122,12 @@ Opts read_opts(const boruta_options* o) {
     if (r.grid_small < 0 || r.grid_hist < 0 || r.grid_finalize < 0 || r.grid_small > 65536 ||
         r.grid_hist > 65536 || r.grid_finalize > 65536)
         throw Error(BORUTA_E_INVALID_ARG, "grid sizes outside [0, 65536]");
+    if (r.col_level < 0 || r.col_level > kColNever)
+        throw Error(BORUTA_E_INVALID_ARG, "col_level outside [0, 64]");
+    if (r.col_unit < 1 || r.col_unit > 65536)
+        throw Error(BORUTA_E_INVALID_ARG, "col_unit outside [1, 65536]");
+    if (r.grid_col < 0 || r.grid_col > 65536)
+        throw Error(BORUTA_E_INVALID_ARG, "grid_col outside [0, 65536]");
     return r;
 }
 
@@ -146,6 +171,7 @@ struct Region {
 
 struct JobPlan {
     int64_t n_pad, P;
+    uint32_t gbase;
     int max_sha, pw_cap, mtry_max;
     size_t X, y32, y8, orig, sha, colptr, colsrc, act, state, hits, hist, smax, hconf, hrej, G,
         imp, wbuf, rec0, rec1, oob, tstat;
@@ -155,9 +181,13 @@ struct Plan {
     std::vector<JobPlan> jp;
     size_t keys, jobs, trees, tree_base, flags, nodes, cls, ngain, small0, small1, cand, cand_cl,
         feat, fcol, srec, kinds, chunk_sums, slot0, slot1, ctrs, alg, tot;
+    size_t fcnt = 0, fpos = 0, fitems = 0, units = 0, gcolq = 0;
     uint32_t node_cap = 0, slot_cap = 0, small_cap = 0;
     int kmax = 4, ft = 8, max_sha = 1, max_pw = 1, max_D = 1, T_total = 0, mtry_cap = 1,
-        npi = 1;
+        npi = 1, fw = 1;
+    // column-major histogram path: levels >= col_level (col_level >= max_D: none)
+    int col_level = kColNever, col_waves = 0;
+    uint32_t n_gcol = 0, unit_cap = 0, gq_max = 0;
     int64_t max_n = 0;
     size_t total = 0;
 };
@@ -174,13 +204,16 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     pl.kmax = maxK <= 2 ? 2 : (maxK <= 4 ? 4 : (maxK <= 8 ? 8 : 16));
     pl.ft = 32 / pl.kmax;  // feature columns per histogram tile (32 KB of LDS at 256 bins)
     pl.keys = r.take((size_t)keys_words * 4);
-    uint64_t node_cap = 0, slot_cap = 0, small_cap = 0;
+    uint64_t node_cap = 0, slot_cap = 0, small_cap = 0, n_gcol = 0;
     for (const Spec& s : specs) {
         JobPlan j;
         j.n_pad = round_up(s.n, 256);
         j.P = pow2_at_least(s.n);
         j.max_sha = (int)std::max<int64_t>(s.p, 8);
         j.pw_cap = (int)(s.p + j.max_sha);
+        j.gbase = (uint32_t)n_gcol;
+        n_gcol += (uint64_t)j.pw_cap;
+        pl.gq_max = std::max<uint32_t>(pl.gq_max, (uint32_t)(j.n_pad / 16));
         j.mtry_max = s.mtry > 0 ? std::min(s.mtry, j.pw_cap) : isqrt_i(j.pw_cap);
         const size_t n = (size_t)s.n, p = (size_t)s.p, T = (size_t)s.T;
         j.X = inputs_on_device ? 0 : r.take(n * p * 4);
@@ -220,9 +253,27 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
         pl.max_n = std::max(pl.max_n, s.n);
         pl.T_total += s.T;
     }
-    // histogram items per large node: FW = 8 / kmax draws each (1 for 16 classes)
-    pl.npi = (pl.mtry_cap + hist_fw(pl.kmax) - 1) / hist_fw(pl.kmax);
-    if (node_cap >= 0xFFFFFFF0ull || slot_cap * (uint64_t)pl.npi >= 0xFFFFFFF0ull ||
+    // The column-major path (batched form) stages a whole bin column in LDS
+    // beside its waves' histograms: it is planned when a column and two
+    // waves fit the workgroup's LDS, with up to kColWavesMax waves.
+    int col_level = o.col_level;
+    if (col_level == 0) {
+        size_t widest = 0;
+        for (const JobPlan& j : pl.jp) widest = std::max(widest, (size_t)j.pw_cap * j.n_pad);
+        col_level = widest > kColAutoBytes ? kColLevelAuto : kColNever;
+    }
+    if (o.form == BORUTA_FORM_BATCHED && col_level < pl.max_D) {
+        const size_t per_wave = (size_t)pl.kmax * 256 * 4, col = (size_t)pl.gq_max * 16;
+        if (col + 2 * per_wave <= kLdsPerWorkgroup) {
+            pl.col_level = col_level;
+            pl.col_waves = (int)std::min<size_t>(kColWavesMax, (kLdsPerWorkgroup - col) / per_wave);
+        }
+    }
+    // histogram items per large node: fw draws each (the column-major path
+    // takes one draw per item, and both paths then share that layout)
+    pl.fw = pl.col_level < pl.max_D ? 1 : hist_fw(pl.kmax);
+    pl.npi = (pl.mtry_cap + pl.fw - 1) / pl.fw;
+    if (node_cap >= 0xFFFFFFF0ull || slot_cap * (uint64_t)pl.mtry_cap + n_gcol >= 0xFFFFFFF0ull ||
         small_cap >= 0xFFFFFFF0ull)
         throw Error(BORUTA_E_INVALID_ARG, "problem too large: more than 2^32 tree nodes");
     pl.node_cap = (uint32_t)node_cap;
@@ -250,6 +301,18 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     pl.ctrs = r.take((size_t)(pl.max_D + 2) * sizeof(LevelCtr));
     pl.alg = r.take(2 * kAlgWords * 8);
     pl.tot = r.take((size_t)pl.T_total * 8);
+    if (pl.col_level < pl.max_D) {
+        const uint64_t items = slot_cap * (uint64_t)pl.mtry_cap;
+        pl.n_gcol = (uint32_t)n_gcol;
+        // units: at most one partial run per column plus the full runs
+        pl.unit_cap = (uint32_t)std::min<uint64_t>(items / (uint64_t)o.col_unit + n_gcol + 1,
+                                                   0xFFFFFFF0ull);
+        pl.fcnt = r.take(n_gcol * 4);
+        pl.fpos = r.take((items + n_gcol) * 4);
+        pl.fitems = r.take(items * 4);
+        pl.units = r.take((size_t)pl.unit_cap * sizeof(ColUnit));
+        pl.gcolq = r.take(n_gcol * 4);
+    }
     pl.total = r.total + 256;
     return pl;
 }
@@ -442,6 +505,8 @@ void Engine::setup(std::vector<int>& status) {
         J.seed_hi = (uint32_t)(s.seed >> 32);
         J.max_sha = jp.max_sha;
         J.pw_cap = jp.pw_cap;
+        J.gbase = jp.gbase;
+        J.gq = (uint32_t)(jp.n_pad / 16);
         J.y = at<uint8_t>(jp.y8);
         J.orig = at<uint8_t>(jp.orig);
         J.sha = at<uint8_t>(jp.sha);
@@ -486,6 +551,24 @@ void Engine::setup(std::vector<int>& status) {
     h2d(at<TreeDev>(pl.trees), trees.data(), trees.size() * sizeof(TreeDev));
     h2d(at<int32_t>(pl.tree_base), tree_base.data(), tree_base.size() * 4);
     launch_fill_u32(at<uint32_t>(pl.alg), 4 * kAlgWords, 0u, st);
+    if (pl.col_level < pl.max_D) {
+        int dev = 0, lds_max = 0;
+        HIPC(hipGetDevice(&dev));
+        HIPC(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        const size_t lds = hist_col_lds(pl.kmax, pl.col_waves, pl.gq_max);
+        if ((size_t)lds_max < lds || prepare_hist_col(pl.kmax, lds) != hipSuccess) {
+            (void)hipGetLastError();
+            pl.col_level = kColNever;  // node-major at every level (same item layout)
+        } else {
+            std::vector<uint32_t> gq(pl.n_gcol, 0u);
+            for (int j = 0; j < nj; ++j)
+                for (int f = 0; f < pl.jp[j].pw_cap; ++f)
+                    gq[pl.jp[j].gbase + f] = (uint32_t)(pl.jp[j].n_pad / 16);
+            h2d(at<uint32_t>(pl.gcolq), gq.data(), gq.size() * 4);
+            // per-column counts start at zero; each level's scan clears them
+            launch_fill_u32(at<uint32_t>(pl.fcnt), pl.n_gcol, 0u, st);
+        }
+    }
     h2d(at<JobDev>(pl.jobs), hj.data(), hj.size() * sizeof(JobDev));
     HIPC(hipStreamSynchronize(st));
 }
@@ -506,6 +589,17 @@ ForestDev Engine::forest() const {
     F.kinds = at<uint8_t>(pl.kinds);
     F.chunk_sums = at<unsigned long long>(pl.chunk_sums);
     F.npi = pl.npi;
+    F.fw = pl.fw;
+    if (pl.col_level < pl.max_D) {
+        F.fcnt = at<uint32_t>(pl.fcnt);
+        F.fpos = at<uint32_t>(pl.fpos);
+        F.fitems = at<uint32_t>(pl.fitems);
+        F.units = at<ColUnit>(pl.units);
+        F.gcol_q = at<uint32_t>(pl.gcolq);
+        F.n_gcol = pl.n_gcol;
+        F.unit_cap = pl.unit_cap;
+        F.col_unit = (uint32_t)O.col_unit;
+    }
     F.small_rows = (uint32_t)O.small_rows;
     F.mtry_cap = pl.mtry_cap;
     F.ctrs = at<LevelCtr>(pl.ctrs);
@@ -581,10 +675,11 @@ void Engine::enqueue_iteration() {
     const uint32_t g_tile =
         ((O.grid_hist ? (uint32_t)O.grid_hist : level_grid((uint64_t)pl.slot_cap * pl.npi, 4, 16384)) +
          7) / 8 * 8;
-    const uint32_t g_draw = level_grid(pl.slot_cap, 4, 1024);
+    const uint32_t g_draw = level_grid(pl.slot_cap, 4, 16384);
     const uint32_t g_list = level_grid((uint64_t)pl.small_cap + pl.slot_cap, 4096, 1024);
     const uint32_t g_fin =
         O.grid_finalize ? (uint32_t)O.grid_finalize : level_grid(pl.slot_cap, 4, 4096);
+    const uint32_t g_col = O.grid_col ? (uint32_t)O.grid_col : level_grid(pl.unit_cap, 1, 2048);
     for (int d = 0; d < n_levels; ++d) {
         // lists, slots and row records of level d are read from parity d & 1
         // and the children of level d go to the other parity
@@ -612,10 +707,23 @@ void Engine::enqueue_iteration() {
         launch_split_small(F, d, 0, kAll, g_small, ss);
         clock.end(h, ss);
         if (fork) HIPC(hipEventRecord(ev_join, side));
-        launch_draws(F, d, g_draw, st);
-        h = clock.begin(stats ? &stats->hist_large : nullptr, st);
-        launch_hist_tile(F, d, 0, kAll, g_tile, O.B, st);
-        clock.end(h, st);
+        const bool col = d >= pl.col_level;
+        if (col) {
+            // items bucketed by column, one LDS-staged column per unit
+            ForestDev Fc = F;
+            Fc.col_count = 1;
+            launch_draws(Fc, d, g_draw, st);
+            launch_col_sort(F, d, g_draw, st);
+            h = clock.begin(stats ? &stats->hist_large : nullptr, st);
+            launch_hist_col(F, d, g_col, pl.col_waves, pl.gq_max, st);
+            HIPC(hipGetLastError());  // a refused launch would leave stale candidates
+            clock.end(h, st);
+        } else {
+            launch_draws(F, d, g_draw, st);
+            h = clock.begin(stats ? &stats->hist_large : nullptr, st);
+            launch_hist_tile(F, d, 0, kAll, g_tile, O.B, st);
+            clock.end(h, st);
+        }
         h = clock.begin(stats ? &stats->finalize : nullptr, st);
         launch_split_finalize(F, d, 0, kAll, g_fin, st);
         clock.end(h, st);
@@ -945,6 +1053,9 @@ void boruta_default_options(boruta_options* opt) {
     opt->grid_small = 0;
     opt->grid_hist = 0;
     opt->grid_finalize = 0;
+    opt->col_level = 0;
+    opt->col_unit = 512;
+    opt->grid_col = 0;
     opt->trace = nullptr;
     opt->trace_user = nullptr;
     opt->stats = nullptr;

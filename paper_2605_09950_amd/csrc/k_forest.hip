@@ -702,10 +702,13 @@ __global__ __launch_bounds__(256) void k_draws(ForestDev F, int level) {
                                       (uint32_t)tr.tau, nd.heap, 0u, (uint64_t)J.p_w);
         uint32_t* out = F.feat + (size_t)slot * F.mtry_cap;
         const uint8_t** oc = F.fcol + (size_t)slot * F.mtry_cap;
+        uint32_t* pos = F.fpos + (size_t)slot * F.mtry_cap;
         for (int q = lane; q < J.mtry; q += 64) {
             const uint32_t f = perm_apply(P, (uint32_t)q);
             out[q] = f;
             oc[q] = ldg(J.colptr + f);
+            // column-major path: the item's place among its column's items
+            if (F.col_count) pos[q] = atomicAdd(F.fcnt + J.gbase + f, 1u);
         }
         SlotRec* sr = F.srec + slot;
         if (lane < 16) sr->cnode[lane] = lane < J.K ? F.cls[(size_t)id * F.kmax + lane] : 0u;
@@ -728,10 +731,9 @@ __global__ __launch_bounds__(256) void k_draws(ForestDev F, int level) {
 // spread a wave's atomics over the banks by bin), scans each feature and
 // writes the item's best candidate and its left class counts.  No barriers:
 // the four waves of a workgroup are independent.
-template <int KMAX>
+template <int KMAX, int FW>
 __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint32_t first,
                                                    uint32_t count) {
-    constexpr int FW = hist_fw(KMAX);
     constexpr int WORDS = FW * KMAX * 256;
     constexpr int RB = 8;  // rows per lane per batch: RB record loads, RB * FW gathers in flight
     extern __shared__ uint4 lds_raw[];
@@ -863,6 +865,215 @@ __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint3
                   alg);
 }
 
+// ---------------------------------------------------------------------------
+// Column-major histogram path.  At deep levels the nodes are small and a
+// node-major gather pulls one cache line per row and drawn feature from a
+// column far larger than the node; here the items (node, draw) of a level are
+// bucketed by bin column instead, and each workgroup stages one column in LDS
+// once and serves the histograms of a run of that column's items from it.
+//
+// k_col_scan (one workgroup): exclusive offsets of the per-column item counts
+// that k_draws accumulated, the units (runs of at most col_unit items of one
+// column), and zero counts for the next level.
+__global__ __launch_bounds__(256) void k_col_scan(ForestDev F, int level) {
+    __shared__ uint32_t s_i[4], s_u[4];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const uint32_t G = F.n_gcol, U = F.col_unit;
+    const uint32_t C = (G + 255u) / 256u;
+    const uint32_t a = min(G, tid * C), b = min(G, a + C);
+    uint32_t si = 0, su = 0;
+    for (uint32_t g = a; g < b; ++g) {
+        const uint32_t c = F.fcnt[g];
+        si += c;
+        su += (c + U - 1u) / U;
+    }
+    const uint32_t ii = wave_incl_sum(si), iu = wave_incl_sum(su);
+    if (lane == 63) {
+        s_i[wave] = ii;
+        s_u[wave] = iu;
+    }
+    __syncthreads();
+    uint32_t oi = ii - si, ou = iu - su, tu = 0;
+    for (uint32_t v = 0; v < 4; ++v) {
+        if (v < wave) {
+            oi += s_i[v];
+            ou += s_u[v];
+        }
+        tu += s_u[v];
+    }
+    for (uint32_t g = a; g < b; ++g) {
+        const uint32_t c = F.fcnt[g];
+        F.fcnt[g] = 0;
+        F.fpos[(size_t)F.slot_cap * F.mtry_cap + g] = oi;  // column offsets follow the places
+        const uint32_t gq = F.gcol_q[g];
+        for (uint32_t k = 0; k * U < c; ++k) {
+            if (ou < F.unit_cap) {
+                ColUnit cu;
+                cu.begin = oi + k * U;
+                cu.end = oi + min(c, (k + 1u) * U);
+                cu.gq = gq;
+                cu.pad = 0;
+                F.units[ou] = cu;
+            }
+            ++ou;
+        }
+        oi += c;
+    }
+    if (tid == 0) {
+        if (tu > F.unit_cap) atomicOr(&F.ctrs[level].overflow, 16u);
+        F.ctrs[level].n_units = min(tu, F.unit_cap);
+    }
+}
+
+// k_col_scatter: one wavefront per large node; each drawn item goes to its
+// column's run of the sorted list (order within a run is immaterial: every
+// item writes only its own candidate).
+__global__ __launch_bounds__(256) void k_col_scatter(ForestDev F, int level) {
+    const uint32_t count = level_slots(F, level);
+    const int lane = threadIdx.x & 63;
+    const uint32_t* off = F.fpos + (size_t)F.slot_cap * F.mtry_cap;
+    for (uint32_t slot = blockIdx.x * 4u + uniform(threadIdx.x >> 6); slot < count;
+         slot += gridDim.x * 4u) {
+        const SlotRec& sr = F.srec[slot];
+        const NodeDev nd = F.nodes[uniform(sr.id)];
+        const uint32_t gb = F.jobs[F.trees[nd.tree].job].gbase;
+        const size_t row = (size_t)slot * F.mtry_cap;
+        for (uint32_t q = lane; q < sr.mtry; q += 64) {
+            const uint32_t dst = off[gb + F.feat[row + q]] + F.fpos[row + q];
+            F.fitems[dst] = (uint32_t)(row + q);
+        }
+    }
+}
+
+// k_hist_col: grid-stride over units.  The workgroup copies the unit's bin
+// column into LDS (16-byte loads, the whole column once), then each wave
+// takes the unit's items in turn: an LDS class-count histogram [KMAX][256]
+// from the node's row records and the staged bins, the prefix scan, and the
+// item's candidate and left class counts (item = slot * mtry_cap + draw).
+template <int KMAX>
+__global__ __launch_bounds__(1024) void k_hist_col(ForestDev F, int level) {
+    constexpr int WORDS = KMAX * 256;
+    constexpr int RB = 8;
+    extern __shared__ uint4 lds_raw[];
+    const int lane = threadIdx.x & 63, wave = (int)uniform(threadIdx.x >> 6);
+    const uint32_t nw = blockDim.x >> 6;
+    uint32_t* hist = reinterpret_cast<uint32_t*>(lds_raw) + wave * WORDS;
+    uint4* colq = lds_raw + nw * (WORDS / 4);
+    const uint8_t* colb = reinterpret_cast<const uint8_t*>(colq);
+    const LevelCtr& lc = F.ctrs[level];
+    const uint32_t n_units = lc.overflow ? 0u : min(lc.n_units, F.unit_cap);
+    const uint32_t mc = (uint32_t)F.mtry_cap;
+    unsigned long long alg = 0;
+    for (uint32_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+        const ColUnit cu = F.units[u];
+        const uint4* src = reinterpret_cast<const uint4*>(F.fcol[F.fitems[cu.begin]]);
+        for (uint32_t i = threadIdx.x; i < cu.gq; i += blockDim.x) colq[i] = src[i];
+        __syncthreads();
+        // The wave's items are k0 + t * nw; their node records are loaded
+        // one per lane, 64 at a time, and read back with readlane.
+        for (uint32_t k0 = cu.begin + (uint32_t)wave; k0 < cu.end; k0 += 64u * nw) {
+            const uint32_t kk = k0 + (uint32_t)lane * nw;
+            const bool have = kk < cu.end;
+            const uint32_t my_item = have ? F.fitems[kk] : 0u;
+            const SlotRec* msr = F.srec + my_item / mc;
+            const uint64_t my_recs = have ? reinterpret_cast<uint64_t>(msr->recs) : 0ull;
+            const uint32_t my_len = have ? msr->len : 0u, my_n = have ? msr->n : 0u;
+            const uint32_t my_B = have ? msr->B : 0u, my_f = have ? F.feat[my_item] : 0u;
+            uint32_t my_cn[KMAX];
+#pragma unroll
+            for (int c = 0; c < KMAX; ++c) my_cn[c] = have ? msr->cnode[c] : 0u;
+            const uint32_t n_here = min(64u, (cu.end - k0 + nw - 1u) / nw);
+            // the first record batch of the next item is loaded while this
+            // item is counted and scanned
+            uint64_t rn[RB];
+            {
+                const uint64_t* recs = reinterpret_cast<const uint64_t*>(readlane64(my_recs, 0));
+                const uint32_t len = readlane_w(my_len, 0);
+#pragma unroll
+                for (int v = 0; v < RB; ++v) {
+                    const uint32_t i = v * 64 + lane;
+                    rn[v] = i < len ? ldg(recs + i) : 0ull;
+                }
+            }
+            for (uint32_t t = 0; t < n_here; ++t) {
+                const uint32_t item = readlane_w(my_item, (int)t);
+                const uint32_t q = item - (item / mc) * mc;
+                const uint64_t* recs = reinterpret_cast<const uint64_t*>(readlane64(my_recs, (int)t));
+                const uint32_t len = readlane_w(my_len, (int)t);
+                uint64_t r[RB];
+#pragma unroll
+                for (int v = 0; v < RB; ++v) r[v] = rn[v];
+                if (t + 1 < n_here) {
+                    const uint64_t* nrecs =
+                        reinterpret_cast<const uint64_t*>(readlane64(my_recs, (int)t + 1));
+                    const uint32_t nlen = readlane_w(my_len, (int)t + 1);
+#pragma unroll
+                    for (int v = 0; v < RB; ++v) {
+                        const uint32_t i = v * 64 + lane;
+                        rn[v] = i < nlen ? ldg(nrecs + i) : 0ull;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < WORDS / 256; ++i)
+                    reinterpret_cast<uint4*>(hist)[i * 64 + lane] = make_uint4(0u, 0u, 0u, 0u);
+                for (uint32_t i0 = 0;;) {
+#pragma unroll
+                    for (int v = 0; v < RB; ++v) {
+                        const uint32_t w = rec_w(r[v]);  // padding rows: w = 0
+                        if (w) atomicAdd(&hist[rec_y(r[v]) * 256 + colb[rec_row(r[v])]], w);
+                    }
+                    i0 += 64 * RB;
+                    if (i0 >= len) break;
+#pragma unroll
+                    for (int v = 0; v < RB; ++v) {
+                        const uint32_t i = i0 + v * 64 + lane;
+                        r[v] = i < len ? ldg(recs + i) : 0ull;
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                uint32_t cnode[KMAX];
+#pragma unroll
+                for (int c = 0; c < KMAX; ++c) cnode[c] = readlane_w(my_cn[c], (int)t);
+                const int B = (int)readlane_w(my_B, (int)t), fq = (int)readlane_w(my_f, (int)t);
+                const uint32_t N = readlane_w(my_n, (int)t);
+                Cand best;
+                uint32_t* out = F.cand_cl + (size_t)item * F.kmax;
+                if constexpr (KMAX <= 4) {
+                    uint32_t cl[KMAX];
+                    best = feature_best_compact<KMAX>(hist, B, (int)q, fq, cnode, N, F.split_rank,
+                                                      cl);
+                    if (lane < KMAX) {
+#pragma unroll
+                        for (int c = 0; c < KMAX; ++c)
+                            if (lane == c) out[c] = best.nl != 0 ? cl[c] : 0u;
+                    }
+                } else {
+                    best = feature_best<KMAX>(hist, B, (int)q, fq, cnode, N, F.split_rank);
+                    const int bt = best.nl != 0 ? best.b : -1;
+#pragma unroll
+                    for (int c = 0; c < KMAX; ++c) {
+                        const uint4 v4 =
+                            *reinterpret_cast<const uint4*>(hist + c * 256 + lane * 4);
+                        const int bl = lane * 4;
+                        const uint32_t a = (bl <= bt ? v4.x : 0u) + (bl + 1 <= bt ? v4.y : 0u) +
+                                           (bl + 2 <= bt ? v4.z : 0u) + (bl + 3 <= bt ? v4.w : 0u);
+                        const uint32_t tot =
+                            (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_sum(a), 63);
+                        if (lane == c) out[c] = tot;
+                    }
+                }
+                if (lane == 0) F.cand[item] = best;
+                alg += (unsigned long long)len * (unsigned long long)(1u + (q == 0 ? 6u : 0u));
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            }
+        }
+        __syncthreads();  // the column is replaced by the next unit's
+    }
+    if (F.alg_bytes && lane == 0 && alg)
+        atomicAdd((unsigned long long*)&F.alg_bytes[(blockIdx.x * nw + wave) & (kAlgWords - 1)],
+                  alg);
+}
+
 // Large nodes, phase 2: one wavefront per node (four per workgroup, no
 // barriers).  The node's split is the best of its histogram items' candidates
 // (exact score, then draw position, then threshold); a strictly positive
@@ -895,8 +1106,7 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
         }
         const uint32_t N = sr.n;
         // rank the items' candidates: each lane keeps the best of its items
-        const int fw = hist_fw(F.kmax);
-        const int ni = ((int)sr.mtry + fw - 1) / fw;
+        const int ni = ((int)sr.mtry + F.fw - 1) / F.fw;
         Cand c;
         c.nl = 0;
         c.q = 0x7FFFFFFF;
@@ -1124,14 +1334,49 @@ void launch_draws(const ForestDev& F, int level, uint32_t grid_wg, hipStream_t s
 void launch_hist_tile(const ForestDev& F, int level, uint32_t first, uint32_t count,
                       uint32_t grid_wg, int B, hipStream_t st) {
     if (!count) return;
-    // four waves of FW * KMAX * 256 words
-    const size_t lds = (size_t)4 * hist_fw(F.kmax) * F.kmax * 256 * sizeof(uint32_t);
+    // four waves of fw * KMAX * 256 words
+    const size_t lds = (size_t)4 * F.fw * F.kmax * 256 * sizeof(uint32_t);
     const dim3 grid(grid_wg);
+    switch (F.kmax * 4 + F.fw) {
+        case 2 * 4 + 2: hipLaunchKernelGGL((k_hist_tile<2, 2>), grid, dim3(256), lds, st, F, level, first, count); break;
+        case 2 * 4 + 1: hipLaunchKernelGGL((k_hist_tile<2, 1>), grid, dim3(256), lds, st, F, level, first, count); break;
+        case 4 * 4 + 1: hipLaunchKernelGGL((k_hist_tile<4, 1>), grid, dim3(256), lds, st, F, level, first, count); break;
+        case 8 * 4 + 1: hipLaunchKernelGGL((k_hist_tile<8, 1>), grid, dim3(256), lds, st, F, level, first, count); break;
+        default: hipLaunchKernelGGL((k_hist_tile<16, 1>), grid, dim3(256), lds, st, F, level, first, count); break;
+    }
+}
+
+size_t hist_col_lds(int kmax, int waves, uint32_t gq_max) {
+    return (size_t)waves * kmax * 256 * sizeof(uint32_t) + (size_t)gq_max * 16;
+}
+
+void launch_col_sort(const ForestDev& F, int level, uint32_t grid_wg, hipStream_t st) {
+    hipLaunchKernelGGL(k_col_scan, dim3(1), dim3(256), 0, st, F, level);
+    hipLaunchKernelGGL(k_col_scatter, dim3(grid_wg), dim3(256), 0, st, F, level);
+}
+
+// Allows the column path's dynamic LDS (above the default per-launch limit)
+// for the instantiation of kmax classes.
+hipError_t prepare_hist_col(int kmax, size_t lds) {
+    const void* fn;
+    switch (kmax) {
+        case 2: fn = reinterpret_cast<const void*>(&k_hist_col<2>); break;
+        case 4: fn = reinterpret_cast<const void*>(&k_hist_col<4>); break;
+        case 8: fn = reinterpret_cast<const void*>(&k_hist_col<8>); break;
+        default: fn = reinterpret_cast<const void*>(&k_hist_col<16>); break;
+    }
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+void launch_hist_col(const ForestDev& F, int level, uint32_t grid_wg, int waves, uint32_t gq_max,
+                     hipStream_t st) {
+    const size_t lds = hist_col_lds(F.kmax, waves, gq_max);
+    const dim3 grid(grid_wg), block(64 * waves);
     switch (F.kmax) {
-        case 2: hipLaunchKernelGGL(k_hist_tile<2>, grid, dim3(256), lds, st, F, level, first, count); break;
-        case 4: hipLaunchKernelGGL(k_hist_tile<4>, grid, dim3(256), lds, st, F, level, first, count); break;
-        case 8: hipLaunchKernelGGL(k_hist_tile<8>, grid, dim3(256), lds, st, F, level, first, count); break;
-        default: hipLaunchKernelGGL(k_hist_tile<16>, grid, dim3(256), lds, st, F, level, first, count); break;
+        case 2: hipLaunchKernelGGL(k_hist_col<2>, grid, block, lds, st, F, level); break;
+        case 4: hipLaunchKernelGGL(k_hist_col<4>, grid, block, lds, st, F, level); break;
+        case 8: hipLaunchKernelGGL(k_hist_col<8>, grid, block, lds, st, F, level); break;
+        default: hipLaunchKernelGGL(k_hist_col<16>, grid, block, lds, st, F, level); break;
     }
 }
 

@@ -36,12 +36,14 @@ def test_default_options():
     o = B.boruta_default_options()
     assert (o.n_bins, o.n_perm, o.split_rank, o.form) == (256, 1, B.RANK_FP32, B.FORM_BATCHED)
     assert (o.graph, o.small_rows, o.grid_small, o.grid_hist, o.grid_finalize) == (1, 32, 0, 0, 0)
+    assert (o.col_level, o.col_unit, o.grid_col) == (0, 512, 0)
     assert not o.trace and not o.stats
 
 
 def test_tuning_options_validated_on_the_host():
     for tune in (dict(small_rows=1), dict(small_rows=65), dict(grid_hist=-1),
-                 dict(grid_small=70000)):
+                 dict(grid_small=70000), dict(col_level=-1), dict(col_level=65),
+                 dict(col_unit=-2), dict(col_unit=65537), dict(grid_col=70000)):
         with pytest.raises(B.BorutaError) as e:
             B.boruta_workspace_size([dict(n=100, p=5, n_classes=2, n_trees=2, max_depth=3)],
                                     tune=tune)
@@ -54,6 +56,31 @@ def test_small_rows_sizes_the_large_node_lists():
     job = [dict(n=5000, p=50, n_classes=3, n_trees=10, max_depth=10)]
     assert B.boruta_workspace_size(job, tune=dict(small_rows=16)) > B.boruta_workspace_size(job)
     assert B.boruta_workspace_size(job, tune=dict(small_rows=64)) < B.boruta_workspace_size(job)
+
+
+def test_column_path_buffers_only_when_a_level_uses_it():
+    # depth 8: col_level 5 puts levels 5..7 on the column-major path; col_level
+    # 64 (never) or a tree too shallow to reach col_level plans no column buffers
+    job = [dict(n=5000, p=50, n_classes=3, n_trees=10, max_depth=8)]
+    never = B.boruta_workspace_size(job, tune=dict(col_level=64))
+    assert B.boruta_workspace_size(job, tune=dict(col_level=5)) > never
+    assert B.boruta_workspace_size(job, tune=dict(col_level=8)) == never
+    assert B.boruta_workspace_size(job, tune=dict(col_level=7)) > never
+    # automatic choice: a 100 KB-column, 4000-column matrix (about 400 MB)
+    # takes it, a small one does not
+    assert B.boruta_workspace_size(job) == never
+    big = [dict(n=100000, p=2000, n_classes=4, n_trees=2, max_depth=8)]
+    assert (B.boruta_workspace_size(big) ==
+            B.boruta_workspace_size(big, tune=dict(col_level=5)) >
+            B.boruta_workspace_size(big, tune=dict(col_level=64)))
+    # the plain form never takes it
+    assert (B.boruta_workspace_size(job, form=B.FORM_PLAIN) ==
+            B.boruta_workspace_size(job, form=B.FORM_PLAIN, tune=dict(col_level=64)))
+    # a column wider than a workgroup's LDS (n = 200,000 rows) keeps every level
+    # node-major
+    wide = [dict(n=200000, p=4, n_classes=2, n_trees=1, max_depth=8)]
+    assert (B.boruta_workspace_size(wide) ==
+            B.boruta_workspace_size(wide, tune=dict(col_level=64)))
 
 
 def _call(**kw):

@@ -29,7 +29,7 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
                       "fullsize_trees.json")
 
 
-def gpu_first_iteration(jobs, n_bins, n_perm=1):
+def gpu_first_iteration(jobs, n_bins, n_perm=1, tune=None):
     """One step of a session shaped like the bench's; returns the traces."""
     import torch
     dev = []
@@ -40,11 +40,11 @@ def gpu_first_iteration(jobs, n_bins, n_perm=1):
         dev.append(d)
     shapes = [dict(n=d["X"].shape[0], p=d["X"].shape[1],
                    **{k: v for k, v in d.items() if k not in ("X", "y")}) for d in dev]
-    ws_bytes = B.boruta_workspace_size(shapes, n_bins=n_bins, n_perm=n_perm)
+    ws_bytes = B.boruta_workspace_size(shapes, n_bins=n_bins, n_perm=n_perm, tune=tune)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     with B.Session(dev, n_bins=n_bins, n_perm=n_perm, trace={1}, inputs_on_device=True,
-                   workspace=ws, stream=stream, graph=True) as s:
+                   workspace=ws, stream=stream, graph=True, tune=tune) as s:
         s.step()
         traces = list(s.traces)
     torch.cuda.synchronize()
@@ -68,13 +68,16 @@ def oracle_first_iteration(jd, n_bins, n_perm=1, trees=None):
                          n_threads=min(16, os.cpu_count() or 1), trace=True)
 
 
+# the automatic choice keeps these workloads node-major; the column-major path
+# (col_level 5) is checked on them as well
+@pytest.mark.parametrize("tune", [None, dict(col_level=5)], ids=["auto", "column"])
 @pytest.mark.parametrize("mode", [B.TREEIMP, B.PERMUT])
-def test_madelon_like_first_iteration_all_trees(mode):
+def test_madelon_like_first_iteration_all_trees(mode, tune):
     c = synth.config(1)
     pr = c["params"]
     jd = job_of(c, mode)
-    print(f"MADELON-like n=10000 p=500 T=200 D=12 mode={mode}", flush=True)
-    g = gpu_first_iteration([jd], pr["n_bins"], pr["n_perm"])
+    print(f"MADELON-like n=10000 p=500 T=200 D=12 mode={mode} tune={tune}", flush=True)
+    g = gpu_first_iteration([jd], pr["n_bins"], pr["n_perm"], tune=tune)
     assert len(g) == 1 and g[0]["t"] == 1
     o = oracle_first_iteration(jd, pr["n_bins"], pr["n_perm"])
     assert_same_trace(g[0], o["trace"])
@@ -82,14 +85,15 @@ def test_madelon_like_first_iteration_all_trees(mode):
     assert np.array_equal(g[0]["state"], o["state"])
 
 
-def test_many_job_batch_sampled_jobs():
+@pytest.mark.parametrize("tune", [None, dict(col_level=5)], ids=["auto", "column"])
+def test_many_job_batch_sampled_jobs(tune):
     jobs = [dict(X=j["X"], y=j["y"], n_classes=j["n_classes"],
                  n_trees=j["params"]["n_trees"], max_depth=j["params"]["max_depth"],
                  mtry=j["params"]["mtry"], importance_mode=j["params"]["importance_mode"],
                  max_iter=j["params"]["max_iter"], alpha=j["params"]["alpha"], seed=j["seed"])
             for j in synth.many_jobs()]
-    print("many-job batch: 64 jobs, sampled 0, 17, 40, 63", flush=True)
-    g = gpu_first_iteration(jobs, 256)
+    print(f"many-job batch: 64 jobs, sampled 0, 17, 40, 63, tune={tune}", flush=True)
+    g = gpu_first_iteration(jobs, 256, tune=tune)
     by_job = {t["job"]: t for t in g}
     assert sorted(by_job) == list(range(64))
     for j in (0, 17, 40, 63):
@@ -103,8 +107,14 @@ def digest(nodes):
     return hashlib.sha256(np.ascontiguousarray(nodes, dtype=np.int64).tobytes()).hexdigest()
 
 
+# omics: node-major by the automatic choice, also run on the column-major path;
+# mixed (a 400 MB widened matrix): column-major from level 5 automatically,
+# also run node-major
+@pytest.mark.parametrize("tune", [None, "other"], ids=["auto", "other_path"])
 @pytest.mark.parametrize("idx", [2, 4], ids=["omics_n2000_p20000", "mixed_n100000_p2000"])
-def test_sampled_trees_match_oracle_digests(idx):
+def test_sampled_trees_match_oracle_digests(idx, tune):
+    if tune == "other":
+        tune = dict(col_level=5) if idx == 2 else dict(col_level=64)
     with open(GOLDEN) as f:
         ref = json.load(f)[str(idx)]
     c = synth.config(idx)
@@ -112,7 +122,7 @@ def test_sampled_trees_match_oracle_digests(idx):
     jd = job_of(c, B.TREEIMP)
     print(f"workload {idx}: n={c['X'].shape[0]} p={c['X'].shape[1]} T={pr['n_trees']} "
           f"D={pr['max_depth']}, trees {ref['trees']}", flush=True)
-    g = gpu_first_iteration([jd], pr["n_bins"])[0]
+    g = gpu_first_iteration([jd], pr["n_bins"], tune=tune)[0]
     assert (g["t"], g["p_w"], g["mtry"]) == (ref["t"], ref["p_w"], ref["mtry"])
     nodes = g["nodes"][np.isin(g["nodes"][:, 0], ref["trees"])]
     assert nodes.shape[0] == ref["n_nodes"]

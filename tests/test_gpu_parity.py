@@ -18,9 +18,11 @@ def both(X, y, K, T, D, **kw):
     kw = dict(kw)
     split_rank = kw.pop("split_rank", B.RANK_FP32)
     form = kw.pop("form", B.FORM_BATCHED)
+    tune = kw.pop("tune", None)
     print(f"case n={X.shape[0]} p={X.shape[1]} K={K} T={T} D={D} {kw} rank={split_rank} "
-          f"form={form}", flush=True)
-    g = B.boruta_fit_ex(X, y, K, T, D, split_rank=split_rank, form=form, trace=True, **kw)
+          f"form={form} tune={tune}", flush=True)
+    g = B.boruta_fit_ex(X, y, K, T, D, split_rank=split_rank, form=form, trace=True, tune=tune,
+                        **kw)
     o = O.boruta_fit(X, y, K, T, D, trace=True, **kw)
     return g, o
 
@@ -60,21 +62,29 @@ CASES = [
 ]
 
 
+# histogram layouts: node-major at every level, or the column-major path from
+# level 1 with runs of three items (many units per column)
+PATHS = {"node": dict(col_level=64), "column": dict(col_level=1, col_unit=3)}
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
 @pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("case", CASES, ids=[str(c[0]) for c in CASES])
-def test_parity_cases(case, mode):
+def test_parity_cases(case, mode, path):
     seed, n, p, K, T, D, kw = case
     kw = dict(kw)
     X, y = problem(seed, n, p, K, kw.pop("kind", "normal"))
     extra = dict(n_perm=2) if mode == 1 else {}
-    g, o = both(X, y, K, T, D, importance_mode=mode, seed=100 + seed, **extra, **kw)
+    g, o = both(X, y, K, T, D, importance_mode=mode, seed=100 + seed, tune=PATHS[path],
+                **extra, **kw)
     assert_same_run(g, o)
 
 
 def test_many_classes_and_tiny_n():
     X, y = problem(12, 3000, 20, 16)
-    g, o = both(X, y, 16, 4, 10, max_iter=3, seed=3)
-    assert_same_run(g, o)
+    for tune in PATHS.values():
+        g, o = both(X, y, 16, 4, 10, max_iter=3, seed=3, tune=tune)
+        assert_same_run(g, o)
     rng = np.random.default_rng(0)
     for n in (2, 3, 5):
         X = rng.standard_normal((n, 4)).astype(np.float32)
@@ -211,15 +221,20 @@ def test_graph_session_with_stats_and_resume():
     np.testing.assert_array_equal(res["imp_history"][4:k], full["imp_history"][4:k])
 
 
+@pytest.mark.parametrize("K", [2, 4])
 @pytest.mark.parametrize("tune", [dict(small_rows=16),
                                   dict(small_rows=32, grid_hist=64, grid_small=8,
-                                       grid_finalize=3)],
-                         ids=["small_rows16", "tiny_grids"])
-def test_launch_tuning_leaves_results_unchanged(tune):
-    X, y = problem(28, 2200, 30, 4)
+                                       grid_finalize=3),
+                                  dict(col_level=64),
+                                  dict(col_level=1, col_unit=1, grid_col=5),
+                                  dict(col_level=3, col_unit=7, grid_col=64)],
+                         ids=["small_rows16", "tiny_grids", "node_major_only", "column_all_tiny",
+                              "column_from3"])
+def test_launch_tuning_leaves_results_unchanged(tune, K):
+    X, y = problem(28, 2200, 30, K)
     kw = dict(max_iter=4, seed=14, trace=True)
-    a = B.boruta_fit_ex(X, y, 4, 8, 10, **kw)
-    b = B.boruta_fit_ex(X, y, 4, 8, 10, tune=tune, **kw)
+    a = B.boruta_fit_ex(X, y, K, 8, 10, **kw)
+    b = B.boruta_fit_ex(X, y, K, 8, 10, tune=tune, **kw)
     assert_same_run(a, b)
 
 
