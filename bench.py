@@ -121,7 +121,7 @@ def run_gpu(jobs, pr, steps, warmup, form, rank, stats, graph=True, tune=None):
             live = sess.step()
     torch.cuda.synchronize()
     if sess.stats is not None:  # count only the timed iterations
-        for f in ("hist_large", "hist_small", "finalize", "permut"):
+        for f in KERNELS:
             k = getattr(sess.stats, f)
             k.launches, k.ms, k.alg_bytes = 0, 0.0, 0.0
         sess.stats.iter_ms, sess.stats.iterations, sess.stats.nodes = 0.0, 0, 0
@@ -144,8 +144,16 @@ def run_gpu(jobs, pr, steps, warmup, form, rank, stats, graph=True, tune=None):
     return out
 
 
+# kernel statistics of the library: node-major histogram (large nodes),
+# wave path (small nodes), split/partition, OOB traversal, column-major histogram
+KERNELS = ("hist_large", "hist_small", "finalize", "permut", "hist_col")
+# the kernel behind each histogram statistic (for the counter summaries)
+KERNEL_NAMES = {"hist_large": "k_hist_tile", "hist_small": "k_split_small",
+                "hist_col": "k_hist_col"}
+
+
 def roofline(stats):
-    legs = {"hist_large": stats.hist_large, "hist_small": stats.hist_small}
+    legs = {f: getattr(stats, f) for f in ("hist_large", "hist_small", "hist_col")}
     name, k = max(legs.items(), key=lambda kv: kv[1].ms)
     if k.launches == 0 or k.ms <= 0:
         return None, None
@@ -159,7 +167,7 @@ def roofline(stats):
             "launches": int(k.launches)}, {
         f: {"launches": int(getattr(stats, f).launches), "ms": round(getattr(stats, f).ms, 3),
             "alg_GB": round(getattr(stats, f).alg_bytes / 1e9, 4)}
-        for f in ("hist_large", "hist_small", "finalize", "permut")}
+        for f in KERNELS}
 
 
 def measured_traffic(workload_name, kernel):
@@ -168,9 +176,9 @@ def measured_traffic(workload_name, kernel):
     profiles/, or None when there is none for this workload or the kernel
     source has changed since the counters were taken."""
     import hashlib
-    if kernel != "hist_large":
+    if kernel not in ("hist_large", "hist_col"):
         return None
-    path = os.path.join(ROOT, "profiles", f"k_hist_tile_{workload_name}_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"{KERNEL_NAMES[kernel]}_{workload_name}_traffic.md")
     if not os.path.exists(path):
         return None
     fields = {}

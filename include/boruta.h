@@ -95,6 +95,8 @@ typedef struct {
     int64_t nodes;                 /* tree nodes grown                            */
     int64_t level_small[32];       /* nodes searched by the wave path, per depth  */
     int64_t level_large[32];       /* nodes searched by the tiled path, per depth */
+    boruta_kernel_stat hist_col;   /* column-major histogram + split scan (levels
+                                      >= col_level; hist_large covers the others) */
 } boruta_stats;
 
 typedef struct {

@@ -51,7 +51,7 @@ class Stats(ctypes.Structure):
                 ("permut", KernelStat),
                 ("iter_ms", ctypes.c_double), ("iterations", ctypes.c_int64),
                 ("nodes", ctypes.c_int64), ("level_small", ctypes.c_int64 * 32),
-                ("level_large", ctypes.c_int64 * 32)]
+                ("level_large", ctypes.c_int64 * 32), ("hist_col", KernelStat)]
 
 
 class Options(ctypes.Structure):

@@ -338,7 +338,8 @@ struct ForestDev {
     LevelCtr* ctr;        // counters the current launch appends to (set per kernel)
     LevelCtr* ctrs;       // [levels + 1]: ctrs[d] counts the lists of tree level d
     uint32_t n_roots;     // trees of the iteration (= root nodes [0, n_roots))
-    uint64_t* alg_bytes;  // [2][kAlgWords] algorithmic bytes (large, small), nullable;
+    uint64_t* alg_bytes;  // [3][kAlgWords] algorithmic bytes (node-major large, small,
+                          // column-major large), nullable;
                           // the words per kernel spread the atomics
     uint32_t node_cap, slot_cap, small_cap;
     uint32_t next_base;   // first node index of the next level

@@ -299,7 +299,7 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     pl.slot1 = r.take((size_t)pl.slot_cap * 4);
     // level d < max_D reads ctrs[d] and appends to ctrs[d + 1]
     pl.ctrs = r.take((size_t)(pl.max_D + 2) * sizeof(LevelCtr));
-    pl.alg = r.take(2 * kAlgWords * 8);
+    pl.alg = r.take(3 * kAlgWords * 8);
     pl.tot = r.take((size_t)pl.T_total * 8);
     if (pl.col_level < pl.max_D) {
         const uint64_t items = slot_cap * (uint64_t)pl.mtry_cap;
@@ -550,7 +550,7 @@ void Engine::setup(std::vector<int>& status) {
     }
     h2d(at<TreeDev>(pl.trees), trees.data(), trees.size() * sizeof(TreeDev));
     h2d(at<int32_t>(pl.tree_base), tree_base.data(), tree_base.size() * 4);
-    launch_fill_u32(at<uint32_t>(pl.alg), 4 * kAlgWords, 0u, st);
+    launch_fill_u32(at<uint32_t>(pl.alg), 6 * kAlgWords, 0u, st);
     if (pl.col_level < pl.max_D) {
         int dev = 0, lds_max = 0;
         HIPC(hipGetDevice(&dev));
@@ -714,7 +714,7 @@ void Engine::enqueue_iteration() {
             Fc.col_count = 1;
             launch_draws(Fc, d, g_draw, st);
             launch_col_sort(F, d, g_draw, st);
-            h = clock.begin(stats ? &stats->hist_large : nullptr, st);
+            h = clock.begin(stats ? &stats->hist_col : nullptr, st);
             launch_hist_col(F, d, g_col, pl.col_waves, pl.gq_max, st);
             HIPC(hipGetLastError());  // a refused launch would leave stale candidates
             clock.end(h, st);
@@ -885,13 +885,14 @@ int Engine::step() {
 
 void Engine::flush_stats() {
     if (!O.stats) return;
-    std::vector<uint64_t> ab(2 * kAlgWords);
+    std::vector<uint64_t> ab(3 * kAlgWords);
     d2h(ab.data(), at<uint64_t>(pl.alg), ab.size() * 8);
     for (uint32_t i = 0; i < kAlgWords; ++i) {
         O.stats->hist_large.alg_bytes += (double)ab[i];
         O.stats->hist_small.alg_bytes += (double)ab[kAlgWords + i];
+        O.stats->hist_col.alg_bytes += (double)ab[2 * kAlgWords + i];
     }
-    launch_fill_u32(at<uint32_t>(pl.alg), 4 * kAlgWords, 0u, st);
+    launch_fill_u32(at<uint32_t>(pl.alg), 6 * kAlgWords, 0u, st);
 }
 
 void Engine::result(int j, Out& o) {

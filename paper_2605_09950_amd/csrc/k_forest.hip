@@ -1070,7 +1070,8 @@ __global__ __launch_bounds__(1024) void k_hist_col(ForestDev F, int level) {
         __syncthreads();  // the column is replaced by the next unit's
     }
     if (F.alg_bytes && lane == 0 && alg)
-        atomicAdd((unsigned long long*)&F.alg_bytes[(blockIdx.x * nw + wave) & (kAlgWords - 1)],
+        atomicAdd((unsigned long long*)&F.alg_bytes[2 * kAlgWords +
+                                                    ((blockIdx.x * nw + wave) & (kAlgWords - 1))],
                   alg);
 }
 
