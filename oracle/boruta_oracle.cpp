@@ -10,6 +10,10 @@
 //   * permutation importance (Permut) ............. Sec. 2 (Kursa's accuracy
 //     drop) and Sec. 2.2; the out-of-bag accuracy-drop reading is listed
 //     with the other readings of the paper in the design notes.
+//   * prediction-divergence permutation importance  Algorithm 3 (Sec. 2.2):
+//     one shared row permutation, the forest's class probabilities on the
+//     full training matrix, KL divergence between unpermuted and permuted
+//     predictions (importance mode 2).
 // Where the paper leaves a choice open (binning, split rule, randomness,
 // the significance test), the reading implemented here is stated in the
 // comment of the function that implements it.
@@ -35,6 +39,7 @@ const uint32_t kStreamBoot = 1;     // bootstrap draws, keyed by (t, tree, draw)
 const uint32_t kStreamMtry = 2;     // per-node feature draws, keyed by (t, tree, heap id)
 const uint32_t kStreamShadow = 3;   // shadow-column shuffles, keyed by (t, shadow)
 const uint32_t kStreamOobPerm = 4;  // OOB permutations, keyed by (t, tree, column, replica)
+const uint32_t kStreamFlush = 5;    // Algorithm 3's shared row permutation, keyed by t
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 as published by Salmon, Moraes, Dror and Shaw (SC'11,
@@ -223,6 +228,7 @@ struct TNode {
     uint64_t n = 0;
     uint64_t gain = 0;  // floor(2^32 * Gini decrease), split nodes only
     int32_t left = -1, right = -1;
+    std::vector<uint64_t> counts;  // weighted in-bag class counts
 };
 
 struct TreeCtx {
@@ -253,6 +259,7 @@ int32_t grow(TreeCtx& c, const std::vector<uint32_t>& rows, int depth, int64_t h
     c.nodes[idx].heap = heap;
     c.nodes[idx].depth = depth;
     c.nodes[idx].n = n;
+    c.nodes[idx].counts = counts;
 
     Cand best;
     std::vector<int32_t> feats;
@@ -325,6 +332,7 @@ void run_tree(const Data& d, const IterParams& ip, uint32_t tree, TreeResult& ou
             if (nd.feat >= 0) out.gain_sum[nd.feat] += nd.gain;
         return;
     }
+    if (ip.mode == 2) return;  // scored over the whole forest (forest_divergence)
     // Out-of-bag accuracy drop under permutation of one column among the
     // tree's OOB rows (Kursa's importance): rows o_0 < o_1 < ... of the OOB
     // set; replica r of column f moves the bin of o_pi(j) into row o_j, with
@@ -361,6 +369,109 @@ void run_tree(const Data& d, const IterParams& ip, uint32_t tree, TreeResult& ou
         for (int32_t f : path)
             for (int r = 0; r < ip.R; ++r) out.drop[f] += base[j] - permuted_correct(f, r, j);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 3 (importance mode 2), with these readings:
+//   * the forest's predicted class distribution for a row is the mean over
+//     trees of the class frequencies of the leaf the row reaches (weighted
+//     in-bag counts), each frequency held as floor(2^32 c_k / N) and summed
+//     over the trees exactly;
+//   * one row permutation pi per iteration (keyed by t) serves every column:
+//     the permuted matrix gives row r the bin of row pi(r) in the column;
+//   * the loss is the KL divergence KL(P || Q) of the unpermuted prediction
+//     P from the permuted one Q, in bits, with 32 fractional bits, summed
+//     over all n rows; a class that P gives positive probability and Q none
+//     is given one fixed-point unit in Q (so identical predictions give 0).
+
+// floor-ish 2^32 * log2(x), x in [1, 2^62): the integer part from the bit
+// length, then 32 fraction digits by repeated squaring of the mantissa
+// (held in [1, 2) with 62 fractional bits, truncated after each squaring).
+uint64_t log2_fix32(uint64_t x) {
+    int e = 63;
+    while (!(x >> e)) --e;
+    uint64_t m = x << (62 - e);
+    uint64_t frac = 0;
+    for (int i = 0; i < 32; ++i) {
+        m = (uint64_t)(((u128)m * m) >> 62);
+        frac <<= 1;
+        if (m >> 63) {
+            frac |= 1;
+            m >>= 1;
+        }
+    }
+    return ((uint64_t)e << 32) | frac;
+}
+
+// KL(P || Q) in bits with 32 fractional bits, P = S / sum S and
+// Q = S~ / sum S~ with S~_k = Sq_k, raised to 1 where Sq_k = 0 < S_k:
+//   sum over S_k > 0 of (S_k / sum S) (log2 S_k - log2 S~_k) + log2 sum S~ - log2 sum S,
+// the first term floored as a whole.
+int64_t kl_fix32(const uint64_t* S, const uint64_t* Sq, int K) {
+    uint64_t sp = 0, sq = 0;
+    __int128 v = 0;
+    for (int k = 0; k < K; ++k) {
+        const uint64_t q = (Sq[k] == 0 && S[k] != 0) ? 1 : Sq[k];
+        sp += S[k];
+        sq += q;
+        if (S[k])
+            v += (__int128)S[k] * ((__int128)log2_fix32(S[k]) - (__int128)log2_fix32(q));
+    }
+    __int128 first = v / (__int128)sp;
+    if (v < 0 && first * (__int128)sp != v) first -= 1;  // floor
+    return (int64_t)first + (int64_t)log2_fix32(sq) - (int64_t)log2_fix32(sp);
+}
+
+// Leaf reached by a row, with column sub_f's bin replaced by sub_b.
+int32_t leaf_of_row(const std::vector<TNode>& nodes, const Data& d, uint32_t row, int32_t sub_f,
+                    int sub_b) {
+    int32_t i = 0;
+    while (nodes[i].feat >= 0) {
+        const int32_t f = nodes[i].feat;
+        const int b = (f == sub_f) ? sub_b : d.col[f][row];
+        i = (b <= nodes[i].thr) ? nodes[i].left : nodes[i].right;
+    }
+    return i;
+}
+
+// Summed fixed-point class frequencies of the leaves row `row` reaches.
+void forest_predict(const std::vector<std::vector<TNode>*>& forest, const Data& d, uint32_t row,
+                    int32_t sub_f, int sub_b, uint64_t* S) {
+    for (int k = 0; k < d.K; ++k) S[k] = 0;
+    for (const std::vector<TNode>* tree : forest) {
+        const TNode& leaf = (*tree)[leaf_of_row(*tree, d, row, sub_f, sub_b)];
+        for (int k = 0; k < d.K; ++k) S[k] += (uint64_t)(((u128)leaf.counts[k] << 32) / leaf.n);
+    }
+}
+
+// imp[f] = sum over rows of the fixed-point divergence for column f: for
+// each column, the predictions of the matrix with that column permuted
+// against those of the unpermuted matrix (Algorithm 3, one predict call
+// per column).
+void forest_divergence(const std::vector<std::vector<TNode>*>& forest, const Data& d,
+                       uint64_t seed, uint32_t t, int n_threads, int64_t* imp) {
+    const int K = d.K;
+    std::vector<uint64_t> base((size_t)d.n * K);
+    std::vector<uint32_t> pi((size_t)d.n);
+    for (int64_t r = 0; r < d.n; ++r) {
+        forest_predict(forest, d, (uint32_t)r, -1, 0, &base[(size_t)r * K]);
+        pi[r] = (uint32_t)keyed_perm(seed, kStreamFlush, t, 0u, 0u, 0u, (uint64_t)d.n, (uint64_t)r);
+    }
+    if (n_threads <= 0) n_threads = (int)std::max(1u, std::thread::hardware_concurrency());
+    std::vector<std::thread> pool;
+    for (int w = 0; w < std::min<int64_t>(n_threads, d.p_w); ++w)
+        pool.emplace_back([&, w] {
+            std::vector<uint64_t> q(K);
+            for (int64_t f = w; f < d.p_w; f += n_threads) {
+                int64_t acc = 0;
+                for (int64_t r = 0; r < d.n; ++r) {
+                    forest_predict(forest, d, (uint32_t)r, (int32_t)f, d.col[f][pi[r]], q.data());
+                    acc += kl_fix32(&base[(size_t)r * K], q.data(), K);
+                }
+                imp[f] = acc;
+            }
+        });
+    for (auto& th : pool) th.join();
 }
 
 // ---------------------------------------------------------------------------
@@ -485,7 +596,7 @@ int validate(const float* X, const int32_t* y, int64_t n, int64_t p, int K, int 
     if (!X || !y) return -1;
     if (n < 2 || n > (int64_t(1) << 24) || p < 1 || p > (int64_t(1) << 30)) return -1;
     if (K < 2 || K > 16 || T < 1 || T > 65535 || D < 1 || D > 30 || mtry < 0) return -1;
-    if (mode != 0 && mode != 1) return -1;
+    if (mode < 0 || mode > 2) return -1;
     if (max_iter < 1 || max_iter > 1000) return -1;
     if (!(alpha > 0.0 && alpha < 0.5)) return -1;
     if (B < 2 || B > 256 || R < 1 || R > 65535) return -1;
@@ -589,6 +700,13 @@ void iteration(const Run& run, int t, int8_t* state, int32_t* hits,
             int64_t s = 0;
             for (int64_t v : imp) s += v;
             denom = (double)s;
+        } else if (run.mode == 2) {
+            // Algorithm 3 over the whole forest of the iteration; reported as
+            // the mean divergence per row in bits
+            std::vector<std::vector<TNode>*> forest;
+            for (TreeResult& r : res) forest.push_back(&r.nodes);
+            forest_divergence(forest, d, run.seed, (uint32_t)t, run.n_threads, imp.data());
+            denom = (double)d.n * 4294967296.0;
         } else {
             int64_t oob_total = 0;
             for (const TreeResult& r : res) {
@@ -690,6 +808,12 @@ int oracle_bin(const float* X, int64_t n, int64_t p, int32_t n_bins, uint8_t* bi
         if (!std::isfinite(X[i])) return -2;
     bin_columns(X, n, p, n_bins, bins_out, cuts_out, ncuts_out);
     return 0;
+}
+
+uint64_t oracle_log2_fix32(uint64_t x) { return x ? log2_fix32(x) : 0; }
+
+int64_t oracle_kl_fix32(const uint64_t* S, const uint64_t* Sq, int32_t K) {
+    return kl_fix32(S, Sq, K);
 }
 
 void oracle_bootstrap(uint64_t seed, uint32_t t, uint32_t tree, int64_t n, uint32_t* w_out) {

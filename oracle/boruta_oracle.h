@@ -32,7 +32,9 @@ typedef struct {
     int32_t n_trees;        /* trees grown (all, or the requested subset)          */
     const int32_t* col_src; /* [p_w] original feature index behind widened column  */
     const int64_t* imp_int; /* [p_w] integer importance: TreeImp sum of per-tree
-                               fixed-point shares, or Permut accuracy-drop count   */
+                               fixed-point shares, Permut accuracy-drop count, or
+                               (mode 2) the sum over rows of the KL divergence in
+                               bits with 32 fractional bits                        */
     const int32_t* hits;    /* [p] hit counts after this iteration                 */
     const int8_t* state;    /* [p] decisions after this iteration                  */
     const int64_t* tree_stats; /* [n_trees][5]: tree id, distinct in-bag rows,
@@ -87,7 +89,14 @@ int64_t oracle_grow_tree(const uint8_t* bins, int64_t n, int64_t p_w, const int3
  * -1 (reject) or 0, for `hits` hits in t trials, p features, level alpha. */
 int oracle_binom_decide(int32_t hits, int32_t t, int64_t p, double alpha);
 
-/* Full run.  mode 0 = TreeImp, 1 = Permut.  n_threads 0 = all cores.
+/* 2^32 log2(x) by the squaring digit method (x >= 1; 0 for x = 0), and the
+ * fixed-point KL divergence of mode 2 for K-class summed probabilities. */
+uint64_t oracle_log2_fix32(uint64_t x);
+int64_t oracle_kl_fix32(const uint64_t* S, const uint64_t* Sq, int32_t K);
+
+/* Full run.  mode 0 = TreeImp, 1 = Permut (OOB accuracy drop), 2 = Algorithm
+ * 3's prediction divergence (KL, full training matrix, one shared row
+ * permutation per iteration).  n_threads 0 = all cores.
  * permut_naive = 1 re-traverses every (tree, column, replica, OOB row) in
  * full instead of only the columns on the row's path (same integers).
  * imp_history_out is [max_iter][p]; rows past n_iter are left untouched. */

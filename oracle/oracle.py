@@ -2,7 +2,8 @@
 
 The oracle (``boruta_oracle.cpp``) is a plain, slow CPU reference of one
 Boruta run (Algorithm 1; impurity importance of Algorithm 2, Sec. 2.1;
-out-of-bag permutation importance, Sec. 2 and 2.2).  Only the tests, the
+out-of-bag permutation importance, Sec. 2 and 2.2; the prediction-divergence
+permutation importance of Algorithm 3, Sec. 2.2).  Only the tests, the
 smoke check and the CPU-baseline leg of the benchmark may import this module.
 It shares no code with the HIP library.
 """
@@ -16,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "boruta_oracle.cpp")
 LIB = os.path.join(HERE, "liboracle_boruta.so")
 
-STREAM_BOOT, STREAM_MTRY, STREAM_SHADOW, STREAM_OOBPERM = 1, 2, 3, 4
+STREAM_BOOT, STREAM_MTRY, STREAM_SHADOW, STREAM_OOBPERM, STREAM_FLUSH = 1, 2, 3, 4, 5
 
 
 def build():
@@ -61,6 +62,10 @@ def lib():
         L.oracle_keyed_perm.restype = u64
         L.oracle_bin.argtypes = [P, i64, i64, i32, P, P, P]
         L.oracle_bin.restype = i32
+        L.oracle_log2_fix32.argtypes = [u64]
+        L.oracle_log2_fix32.restype = u64
+        L.oracle_kl_fix32.argtypes = [P, P, i32]
+        L.oracle_kl_fix32.restype = i64
         L.oracle_bootstrap.argtypes = [u64, u32, u32, i64, P]
         L.oracle_bootstrap.restype = None
         L.oracle_best_split.argtypes = [P, i64, P, P, P, i64, P, i32, i32, i32, P]
@@ -106,6 +111,16 @@ def bin_matrix(X, n_bins):
     if rc:
         raise ValueError(f"oracle_bin failed: {rc}")
     return bins, cuts, ncuts
+
+
+def log2_fix32(x):
+    return int(lib().oracle_log2_fix32(int(x)))
+
+
+def kl_fix32(S, Sq):
+    S = np.ascontiguousarray(S, dtype=np.uint64)
+    Sq = np.ascontiguousarray(Sq, dtype=np.uint64)
+    return int(lib().oracle_kl_fix32(_ptr(S), _ptr(Sq), len(S)))
 
 
 def bootstrap(seed, t, tree, n):

@@ -27,6 +27,19 @@ def test_planted_recovery(run0):
     assert np.sum(r["decision"] == -1) >= 12
 
 
+@pytest.mark.parametrize("mode", [1, 2], ids=["permut_oob", "permut_kl"])
+def test_planted_recovery_with_permutation_importances(mode):
+    # both permutation importances (OOB accuracy drop, and Algorithm 3's
+    # prediction divergence) confirm exactly the planted columns
+    c = synth.config(0)
+    pr = c["params"]
+    r = O.boruta_fit(c["X"], c["y"], c["n_classes"], pr["n_trees"], pr["max_depth"],
+                     importance_mode=mode, max_iter=pr["max_iter"], seed=c["seed"],
+                     n_bins=pr["n_bins"])
+    assert set(np.flatnonzero(r["decision"] == 1).tolist()) == set(c["informative"].tolist())
+    assert np.sum(r["decision"] == -1) >= 8
+
+
 def test_decisions_final_and_history(run0):
     c, r = run0
     p = c["X"].shape[1]

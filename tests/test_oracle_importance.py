@@ -4,7 +4,11 @@ TreeImp is checked against a literal double-precision transcription of
 Algorithm 2 (per-node decrease x count summed per feature, per-tree
 normalisation, mean over trees, renormalisation) computed from the traced
 trees by routing the rows again; Permut against a direct recount of the
-out-of-bag accuracy drop and against its own naive full re-traversal."""
+out-of-bag accuracy drop and against its own naive full re-traversal.  The
+prediction-divergence importance of Algorithm 3 (mode 2) is checked through
+its parts: the fixed-point log2 against 60-digit decimal logarithms, the
+fixed-point KL against scipy's entropy, the whole score against a recount
+from leaf class counts routed afresh, and a pure stump's closed form."""
 import numpy as np
 import pytest
 
@@ -131,3 +135,138 @@ def test_permut_identity_when_oob_tiny():
     out = O.boruta_step(X, y, 2, 8, 2, t=1, state=np.zeros(2, np.int8),
                         hits=np.zeros(2, np.int32), importance_mode=1, seed=1, n_bins=4)
     assert np.all(out["trace"]["imp_int"] == 0)
+
+
+# ---------------------------------------------------------------------------
+# Importance mode 2: Algorithm 3 (shared row permutation, forest class
+# probabilities on the full training matrix, KL divergence in bits with 32
+# fractional bits, summed over rows).
+
+def _log2_exact_units(x):
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    return Decimal(x).ln() / Decimal(2).ln() * Decimal(2**32)
+
+
+def test_log2_fix32_digit_method():
+    # exact at powers of two; otherwise at most two units below 2^32 log2 x
+    # (each of the 32 squarings truncates the 62-bit mantissa)
+    for e in range(0, 62):
+        assert O.log2_fix32(2**e) == e << 32
+    rng = np.random.default_rng(9)
+    xs = [3, 5, 7, 10, 1000, 2**32 - 1, 2**32 + 1, 3 * 2**40 + 17]
+    xs += [int(v) for v in rng.integers(1, 2**48, 300)]
+    for x in xs:
+        ref = _log2_exact_units(x)
+        got = O.log2_fix32(x)
+        assert ref - 2 <= got <= ref, (x, got, ref)
+
+
+def test_kl_fix32_matches_library_divergence():
+    from scipy.stats import entropy
+    rng = np.random.default_rng(10)
+    for K in (2, 3, 4, 7):
+        for _ in range(60):
+            S = rng.integers(0, 2**36, K).astype(np.uint64)
+            S[rng.integers(0, K)] = 0 if K > 2 and rng.random() < 0.3 else S[0]
+            if S.sum() == 0:
+                S[0] = 1
+            Sq = rng.integers(0, 2**36, K).astype(np.uint64)
+            if rng.random() < 0.2:
+                Sq[rng.integers(0, K)] = 0
+            if rng.random() < 0.2:
+                Sq = S.copy()  # identical predictions: exactly zero
+            got = O.kl_fix32(S, Sq)
+            q = np.where((Sq == 0) & (S > 0), 1, Sq).astype(np.float64)
+            ref = entropy(S.astype(np.float64), q, base=2)  # normalises both
+            assert abs(got / 2**32 - ref) <= 4 * 2**-32 * max(1.0, ref), (S, Sq, got, ref)
+            if np.array_equal(S, Sq):
+                assert got == 0
+    # a class the permuted prediction misses gets one unit: p = (1, 0), q = (0, 1)
+    assert abs(O.kl_fix32([2**32, 0], [0, 2**32]) / 2**32 - 32.0) < 1e-9
+
+
+def _forest_probs(tr, W, y, K, seed, t, T, n):
+    """Per tree: leaf class counts of the in-bag rows, routed afresh."""
+    out = []
+    for tree in range(T):
+        w = O.bootstrap(seed, t, tree, n)
+        td = tree_dict(tr["nodes"], tree)
+        cnt = route_counts(td, W, np.flatnonzero(w), w, y, K)
+        out.append((td, cnt))
+    return out
+
+
+def _predict_fix(forest, W, row, K, sub_f=-1, sub_b=0):
+    S = np.zeros(K, dtype=np.uint64)
+    for td, cnt in forest:
+        c = cnt[leaf_of(td, W, row, sub_f, sub_b)]
+        N = int(c.sum())
+        S += np.array([(int(v) << 32) // N for v in c], dtype=np.uint64)
+    return S
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_kl_importance_matches_direct_recount(seed):
+    X, y = _problem(seed, n=80, p=4)
+    K, T, D, B, t = 3, 4, 4, 16, 2
+    state = np.zeros(4, np.int8)
+    out = O.boruta_step(X, y, K, T, D, t=t, state=state, hits=np.zeros(4, np.int32),
+                        importance_mode=2, seed=seed, n_bins=B)
+    tr = out["trace"]
+    W, active, n_sha = widened(X, state, t, seed, B)
+    n, p_w = X.shape[0], W.shape[0]
+    forest = _forest_probs(tr, W, y, K, seed, t, T, n)
+    pi = [O.keyed_perm(seed, O.STREAM_FLUSH, t, 0, 0, 0, n, r) for r in range(n)]
+    assert sorted(pi) == list(range(n))
+    base = [_predict_fix(forest, W, r, K) for r in range(n)]
+    imp = np.zeros(p_w, np.int64)
+    imp_float = np.zeros(p_w)
+    from scipy.stats import entropy
+    for f in range(p_w):
+        for r in range(n):
+            q = _predict_fix(forest, W, r, K, f, int(W[f][pi[r]]))
+            imp[f] += O.kl_fix32(base[r], q)
+            qq = np.where((q == 0) & (base[r] > 0), 1, q).astype(float)
+            imp_float[f] += entropy(base[r].astype(float), qq, base=2)
+    assert np.array_equal(imp, tr["imp_int"])
+    assert np.all(np.abs(imp / 2**32 - imp_float) <= n * 4 * 2**-32 * np.maximum(1, imp_float))
+    used = {int(r[2]) for r in tr["nodes"] if r[2] >= 0}
+    for f in range(p_w):
+        if f not in used:
+            assert tr["imp_int"][f] == 0
+    for c, j in enumerate(active):
+        assert out["imp_row"][j] == imp[c] / (n * 2**32)
+    best = max(imp[len(active):])
+    assert np.array_equal(out["hits"], np.array([1 if imp[c] > best else 0
+                                                  for c in range(len(active))], np.int32))
+
+
+def test_kl_importance_of_a_pure_stump():
+    # one tree of depth 1 splitting column 0, whose bins separate the two
+    # classes: every leaf is pure, so a row whose permuted bin falls on the
+    # other side of the threshold moves from p = (1, 0) to q = (0, 1) and adds
+    # KL = 32 + log2(1 + 2^-32) bits (the missing class gets one unit); rows
+    # that stay add nothing.  Other columns are never tested.
+    n = 64
+    X = np.zeros((n, 2), np.float32)
+    X[:, 0] = np.arange(n)
+    X[:, 1] = np.random.default_rng(1).standard_normal(n)
+    y = (X[:, 0] >= n / 2).astype(np.int32)
+    seed, t = 3, 1
+    out = O.boruta_step(X, y, 2, 1, 1, t=t, state=np.zeros(2, np.int8),
+                        hits=np.zeros(2, np.int32), mtry=100, importance_mode=2, seed=seed,
+                        n_bins=64)
+    tr = out["trace"]
+    root = [r for r in tr["nodes"] if r[1] == 1][0]
+    assert root[2] == 0
+    bins, _, _ = O.bin_matrix(X, 64)
+    thr = int(root[3])
+    side = bins[0] <= thr
+    pi = [O.keyed_perm(seed, O.STREAM_FLUSH, t, 0, 0, 0, n, r) for r in range(n)]
+    moved = sum(1 for r in range(n) if side[r] != side[pi[r]])
+    assert moved > 0
+    per_row = O.kl_fix32([2**32, 0], [0, 2**32])
+    assert per_row == (32 << 32) + O.log2_fix32(2**32 + 1) - (32 << 32)
+    assert tr["imp_int"][0] == moved * per_row
+    assert np.all(tr["imp_int"][1:] == 0)
