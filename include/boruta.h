@@ -45,7 +45,7 @@ extern "C" {
 #define BORUTA_E_DEVICE -4      /* HIP runtime error or internal capacity check failed */
 #define BORUTA_E_UNSUPPORTED -5 /* no usable gfx950 device                              */
 
-enum { BORUTA_TREEIMP = 0, BORUTA_PERMUT = 1 };
+enum { BORUTA_TREEIMP = 0, BORUTA_PERMUT = 1, BORUTA_PERMUT_KL = 2 };
 enum { BORUTA_REJECTED = -1, BORUTA_TENTATIVE = 0, BORUTA_CONFIRMED = 1 };
 enum { BORUTA_FORM_PLAIN = 0, BORUTA_FORM_BATCHED = 1 };
 enum { BORUTA_RANK_EXACT = 0, BORUTA_RANK_FP32 = 1 };
@@ -89,7 +89,7 @@ typedef struct {
     boruta_kernel_stat hist_large; /* node histogram + split scan, > 64 rows      */
     boruta_kernel_stat hist_small; /* wave-per-node split search, <= 64 rows      */
     boruta_kernel_stat finalize;   /* split choice + row partition, > 64 rows     */
-    boruta_kernel_stat permut;     /* OOB traversal for permutation importance    */
+    boruta_kernel_stat permut;     /* re-routing for the permutation importances  */
     double iter_ms;                /* device time of all iterations               */
     int64_t iterations;            /* job-iterations run                          */
     int64_t nodes;                 /* tree nodes grown                            */
@@ -138,6 +138,10 @@ typedef struct {
                              default 512                                          */
     int32_t grid_col;     /* workgroups of its histogram launch (one unit at a
                              time, grid-stride); default min(2048, needed)      */
+    int32_t kl_rows;      /* BORUTA_PERMUT_KL: rows per block of the divergence
+                             step (its per-(column, row, class) buffer is sized
+                             for one block), >= 0; default (0): as many rows as
+                             keep that buffer within 256 MiB                     */
     boruta_trace_fn trace;/* nullable                                              */
     void* trace_user;
     boruta_stats* stats;  /* nullable                                              */
@@ -152,7 +156,13 @@ void boruta_default_options(boruta_options* opt);
  *   n_trees    [1, 65535]; max_depth in [1, 30] (root = depth 0).
  *   mtry       features drawn per node; 0 = floor(sqrt(p_w)) recomputed each
  *              iteration, otherwise min(mtry, p_w).
- *   importance_mode  BORUTA_TREEIMP or BORUTA_PERMUT.
+ *   importance_mode  BORUTA_TREEIMP (impurity decrease, Algorithm 2),
+ *              BORUTA_PERMUT (out-of-bag accuracy drop under a column
+ *              permutation per tree, Kursa's importance, Sec. 2) or
+ *              BORUTA_PERMUT_KL (Algorithm 3: one row permutation per
+ *              iteration shared by all columns, the forest's class
+ *              probabilities on the full training matrix, KL divergence of
+ *              the unpermuted from the permuted prediction).
  *   max_iter   [1, 1000]; alpha in (0, 0.5); seed keys every random draw.
  * Outputs (caller-allocated):
  *   decision_out    [p]  -1 rejected / 0 tentative / 1 confirmed.
@@ -160,7 +170,8 @@ void boruta_default_options(boruta_options* opt);
  *                   feature at iteration t (TreeImp: its share of the
  *                   renormalised impurity importance over all widened
  *                   columns; Permut: accuracy drop / (n_perm x OOB rows of
- *                   all trees)), NaN for features rejected before t; rows
+ *                   all trees); Permut-KL: mean divergence per row in bits),
+ *                   NaN for features rejected before t; rows
  *                   at and past n_iter are left untouched.
  *   hits_out [p], shadow_max_out [max_iter]: nullable.
  *   n_iter_out      iterations run. */

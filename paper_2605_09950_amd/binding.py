@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(PKG, "libboruta.so")
 
 BORUTA_OK, BORUTA_E_INVALID_ARG, BORUTA_E_NONFINITE, BORUTA_E_OOM, BORUTA_E_DEVICE, \
     BORUTA_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-TREEIMP, PERMUT = 0, 1
+TREEIMP, PERMUT, PERMUT_KL = 0, 1, 2
 FORM_PLAIN, FORM_BATCHED = 0, 1
 RANK_EXACT, RANK_FP32 = 0, 1
 
@@ -63,6 +63,7 @@ class Options(ctypes.Structure):
                 ("col_level", ctypes.c_int32),
                 ("col_unit", ctypes.c_int32),
                 ("grid_col", ctypes.c_int32),
+                ("kl_rows", ctypes.c_int32),
                 ("trace", TRACE_FN), ("trace_user", ctypes.c_void_p),
                 ("stats", ctypes.POINTER(Stats))]
 
@@ -190,7 +191,7 @@ def _trace_collector(store, p, keep_iters=None):
 
 
 TUNE_KEYS = ("small_rows", "grid_small", "grid_hist", "grid_finalize", "col_level", "col_unit",
-             "grid_col")
+             "grid_col", "kl_rows")
 
 
 def make_options(n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED, trace=False,

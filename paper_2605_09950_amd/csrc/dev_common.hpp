@@ -13,7 +13,7 @@ typedef unsigned __int128 u128;
 // Random streams.  Every random draw of a run is Philox4x32-10 (Salmon et al.,
 // SC'11) keyed by the job's 64-bit seed, at a counter that names what is
 // drawn: word0 = stream<<28 | feistel_round<<24 | iteration, then (a, b, c).
-enum : uint32_t { kBoot = 1, kMtry = 2, kShadow = 3, kOobPerm = 4 };
+enum : uint32_t { kBoot = 1, kMtry = 2, kShadow = 3, kOobPerm = 4, kFlush = 5 };
 
 struct Philox4 {
     uint32_t x, y, z, w;

@@ -45,6 +45,9 @@ void launch_tree_totals(JobDev*, const TreeDev*, int, uint64_t*, hipStream_t);
 void launch_treeimp(JobDev*, const TreeDev*, int, const uint64_t*, int, hipStream_t);
 void launch_permut(JobDev*, const TreeDev*, const NodeDev*, int, int64_t, int, hipStream_t);
 void launch_hits_decide(JobDev*, int, hipStream_t);
+void launch_kl_block(JobDev*, int, const NodeDev*, const uint32_t*, int, uint32_t, int, int,
+                     uint32_t, uint32_t, uint64_t*, uint32_t*, unsigned long long*, int,
+                     hipStream_t);
 void launch_copy(void*, const void*, size_t, hipStream_t);
 
 namespace {
@@ -61,6 +64,8 @@ constexpr size_t kLdsPerWorkgroup = 160 * 1024;
 constexpr int kColLevelAuto = 5;
 constexpr size_t kColAutoBytes = size_t(128) << 20;
 constexpr int kColNever = 64;
+// KL importance: bound of its per-block difference buffer.
+constexpr uint64_t kKlDeltaBytes = uint64_t(256) << 20;
 
 struct Error : std::runtime_error {
     int code;
@@ -86,7 +91,7 @@ struct Spec {
 struct Opts {
     int B = 256, R = 1, split_rank = 1, form = 1, graph = 1;
     int small_rows = 32, grid_small = 0, grid_hist = 0, grid_finalize = 0;
-    int col_level = 0, col_unit = 512, grid_col = 0;
+    int col_level = 0, col_unit = 512, grid_col = 0, kl_rows = 0;
     boruta_trace_fn trace = nullptr;
     void* trace_user = nullptr;
     boruta_stats* stats = nullptr;
@@ -107,6 +112,7 @@ Opts read_opts(const boruta_options* o) {
         if (o->col_level) r.col_level = o->col_level;
         if (o->col_unit) r.col_unit = o->col_unit;
         r.grid_col = o->grid_col;
+        r.kl_rows = o->kl_rows;
         r.trace = o->trace;
         r.trace_user = o->trace_user;
         r.stats = o->stats;
@@ -128,6 +134,7 @@ Opts read_opts(const boruta_options* o) {
         throw Error(BORUTA_E_INVALID_ARG, "col_unit outside [1, 65536]");
     if (r.grid_col < 0 || r.grid_col > 65536)
         throw Error(BORUTA_E_INVALID_ARG, "grid_col outside [0, 65536]");
+    if (r.kl_rows < 0) throw Error(BORUTA_E_INVALID_ARG, "kl_rows must be >= 0");
     return r;
 }
 
@@ -140,7 +147,7 @@ void check_spec(const Spec& s) {
     if (s.T < 1 || s.T > 65535) bad("n_trees outside [1, 65535]");
     if (s.D < 1 || s.D > 30) bad("max_depth outside [1, 30]");
     if (s.mtry < 0) bad("mtry < 0");
-    if (s.mode != 0 && s.mode != 1) bad("importance_mode must be 0 or 1");
+    if (s.mode < 0 || s.mode > 2) bad("importance_mode must be 0, 1 or 2");
     if (s.max_iter < 1 || s.max_iter > 1000) bad("max_iter outside [1, 1000]");
     if (!(s.alpha > 0.0 && s.alpha < 0.5)) bad("alpha outside (0, 0.5)");
 }
@@ -172,6 +179,7 @@ struct Region {
 struct JobPlan {
     int64_t n_pad, P;
     uint32_t gbase;
+    uint32_t kl_rb;  // KL importance: rows per block (0: the job does not use it)
     int max_sha, pw_cap, mtry_max;
     size_t X, y32, y8, orig, sha, colptr, colsrc, act, state, hits, hist, smax, hconf, hrej, G,
         imp, wbuf, rec0, rec1, oob, tstat;
@@ -182,6 +190,7 @@ struct Plan {
     size_t keys, jobs, trees, tree_base, flags, nodes, cls, ngain, small0, small1, cand, cand_cl,
         feat, fcol, srec, kinds, chunk_sums, slot0, slot1, ctrs, alg, tot;
     size_t fcnt = 0, fpos = 0, fitems = 0, units = 0, gcolq = 0;
+    size_t kl_S = 0, kl_pi = 0, kl_delta = 0;  // KL importance buffers (shared by its jobs)
     uint32_t node_cap = 0, slot_cap = 0, small_cap = 0;
     int kmax = 4, ft = 8, max_sha = 1, max_pw = 1, max_D = 1, T_total = 0, mtry_cap = 1,
         npi = 1, fw = 1;
@@ -205,6 +214,7 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     pl.ft = 32 / pl.kmax;  // feature columns per histogram tile (32 KB of LDS at 256 bins)
     pl.keys = r.take((size_t)keys_words * 4);
     uint64_t node_cap = 0, slot_cap = 0, small_cap = 0, n_gcol = 0;
+    uint64_t kl_S = 0, kl_pi = 0, kl_delta = 0;
     for (const Spec& s : specs) {
         JobPlan j;
         j.n_pad = round_up(s.n, 256);
@@ -237,6 +247,18 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
         j.rec1 = r.take(T * n * 8);
         j.oob = r.take(T * n * 4);
         j.tstat = r.take(T * 16);
+        // KL importance: the per-(column, row, class) leaf differences of a
+        // block of rows are bounded by kKlDeltaBytes
+        j.kl_rb = 0;
+        if (s.mode == 2) {
+            const uint64_t per_row = (uint64_t)j.pw_cap * s.K * 8;
+            j.kl_rb = (uint32_t)std::max<uint64_t>(
+                1, std::min<uint64_t>((uint64_t)s.n, kKlDeltaBytes / per_row));
+            if (o.kl_rows) j.kl_rb = (uint32_t)std::min<int64_t>(s.n, o.kl_rows);
+            kl_S = std::max<uint64_t>(kl_S, (uint64_t)j.kl_rb * s.K * 8);
+            kl_pi = std::max<uint64_t>(kl_pi, (uint64_t)j.kl_rb * 4);
+            kl_delta = std::max<uint64_t>(kl_delta, (uint64_t)j.kl_rb * per_row);
+        }
         pl.jp.push_back(j);
         const uint64_t per_tree_nodes =
             std::min<uint64_t>((uint64_t(1) << (s.D + 1)) - 1, 2 * (uint64_t)s.n - 1);
@@ -301,6 +323,11 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     pl.ctrs = r.take((size_t)(pl.max_D + 2) * sizeof(LevelCtr));
     pl.alg = r.take(3 * kAlgWords * 8);
     pl.tot = r.take((size_t)pl.T_total * 8);
+    if (kl_delta) {
+        pl.kl_S = r.take(kl_S);
+        pl.kl_pi = r.take(kl_pi);
+        pl.kl_delta = r.take(kl_delta);
+    }
     if (pl.col_level < pl.max_D) {
         const uint64_t items = slot_cap * (uint64_t)pl.mtry_cap;
         pl.n_gcol = (uint32_t)n_gcol;
@@ -448,7 +475,7 @@ private:
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<JobDev> hj;       // host mirror of the job records
     std::vector<int> tree_base;   // first tree of each job in the static tree table
-    bool any_treeimp = false, any_permut = false;
+    bool any_treeimp = false, any_permut = false, any_kl = false;
 };
 
 void Engine::setup(std::vector<int>& status) {
@@ -547,10 +574,19 @@ void Engine::setup(std::vector<int>& status) {
         for (int tau = 0; tau < S[j].T; ++tau) trees.push_back(TreeDev{j, tau});
         any_treeimp |= S[j].mode == 0;
         any_permut |= S[j].mode == 1;
+        any_kl |= S[j].mode == 2;
     }
     h2d(at<TreeDev>(pl.trees), trees.data(), trees.size() * sizeof(TreeDev));
     h2d(at<int32_t>(pl.tree_base), tree_base.data(), tree_base.size() * 4);
     launch_fill_u32(at<uint32_t>(pl.alg), 6 * kAlgWords, 0u, st);
+    // KL importance differences start at zero; each block's reader clears them
+    if (any_kl) {
+        size_t words = 0;
+        for (int j = 0; j < nj; ++j)
+            if (pl.jp[j].kl_rb)
+                words = std::max(words, (size_t)pl.jp[j].kl_rb * pl.jp[j].pw_cap * S[j].K * 2);
+        launch_fill_u32(at<uint32_t>(pl.kl_delta), words, 0u, st);
+    }
     if (pl.col_level < pl.max_D) {
         int dev = 0, lds_max = 0;
         HIPC(hipGetDevice(&dev));
@@ -740,6 +776,20 @@ void Engine::enqueue_iteration() {
     if (any_permut) {
         const size_t h = clock.begin(stats ? &stats->permut : nullptr, st);
         launch_permut(djobs, dtrees, F.nodes, (int)n_trees, pl.max_n, pl.max_D, st);
+        clock.end(h, st);
+    }
+    if (any_kl) {
+        // per job of mode 2, blocks of rows (the kernels skip finished jobs)
+        const size_t h = clock.begin(stats ? &stats->permut : nullptr, st);
+        for (int j = 0; j < (int)S.size(); ++j) {
+            const uint32_t rb = pl.jp[j].kl_rb;
+            if (!rb) continue;
+            for (int64_t r0 = 0; r0 < S[j].n; r0 += rb)
+                launch_kl_block(djobs, j, F.nodes, F.cls, pl.kmax, (uint32_t)tree_base[j], S[j].T,
+                                pl.jp[j].pw_cap, (uint32_t)r0, rb, at<uint64_t>(pl.kl_S),
+                                at<uint32_t>(pl.kl_pi), at<unsigned long long>(pl.kl_delta),
+                                pl.max_D, st);
+        }
         clock.end(h, st);
     }
     launch_hits_decide(djobs, nj, st);
@@ -1057,6 +1107,7 @@ void boruta_default_options(boruta_options* opt) {
     opt->col_level = 0;
     opt->col_unit = 512;
     opt->grid_col = 0;
+    opt->kl_rows = 0;
     opt->trace = nullptr;
     opt->trace_user = nullptr;
     opt->stats = nullptr;
@@ -1144,7 +1195,7 @@ int boruta_workspace_size(const boruta_job* jobs, int32_t n_jobs, const boruta_o
         for (const Spec& s : specs) {
             if (s.n < 2 || s.n > (int64_t(1) << 24) || s.p < 1 || s.p > (int64_t(1) << 24) ||
                 s.T < 1 || s.D < 1 || s.D > 30 || s.max_iter < 1 || s.max_iter > 1000 ||
-                s.K < 2 || s.K > 16 || s.mode < 0 || s.mode > 1 || s.mtry < 0)
+                s.K < 2 || s.K > 16 || s.mode < 0 || s.mode > 2 || s.mtry < 0)
                 throw Error(BORUTA_E_INVALID_ARG, "job arguments out of range");
         }
         *bytes = make_plan(specs, o, true).total;

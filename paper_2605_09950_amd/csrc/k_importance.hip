@@ -10,6 +10,16 @@
 //     tree's OOB rows for (t, tree, f, r); the drop in correct predictions is
 //     summed per column.  Columns off the path cannot change the prediction,
 //     so only path columns are re-routed, from their first node on the path.
+//   * KL permutation importance (Algorithm 3, Sec. 2.2; importance mode 2):
+//     the forest's class distribution for row r is the sum over trees of
+//     floor(2^32 c_k / N) at the leaf r reaches; one keyed row permutation
+//     pi per iteration serves every column, whose bin at row r is replaced
+//     by the bin at row pi(r); the column scores the sum over rows of
+//     KL(P || Q) in bits with 32 fractional bits (a class Q misses while P
+//     has it counts one unit).  Again only the columns on a row's path in a
+//     tree can move it to another leaf of that tree: per (row, tree) those
+//     columns are re-routed and the leaf differences accumulated per
+//     (column, row); rows are taken in blocks that bound that buffer.
 //   * hits (strictly above the best shadow) and the binomial decision.
 #include "dev_common.hpp"
 
@@ -110,6 +120,211 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
     }
 }
 
+// ---------------------------------------------------------------------------
+// KL permutation importance.
+
+// Fixed-point class frequency of a leaf: floor(2^32 c_k / N).
+__device__ __forceinline__ uint64_t leaf_freq(const uint32_t* cls, int kmax, uint32_t node,
+                                              int k, uint32_t N) {
+    return ((uint64_t)cls[(size_t)node * kmax + k] << 32) / N;
+}
+
+__device__ __forceinline__ uint32_t leaf_weight(const uint32_t* cls, int kmax, uint32_t node,
+                                                int K) {
+    uint32_t N = 0;
+    for (int k = 0; k < K; ++k) N += cls[(size_t)node * kmax + k];
+    return N;
+}
+
+// 2^32 log2(x), 1 <= x < 2^62: bit length, then 32 digits of the fraction
+// from successive squares of the mantissa (62 fractional bits, truncated).
+__device__ __forceinline__ uint64_t lg2_q32(uint64_t x) {
+    const int e = 63 - __builtin_clzll(x);
+    uint64_t m = x << (62 - e);
+    uint64_t frac = 0;
+    for (int i = 0; i < 32; ++i) {
+        const uint64_t hi = __umul64hi(m, m), lo = m * m;
+        m = (hi << 2) | (lo >> 62);
+        const uint64_t top = m >> 63;
+        frac = (frac << 1) | top;
+        m >>= top;
+    }
+    return ((uint64_t)e << 32) | frac;
+}
+
+// KL(P || Q) in 2^-32 bits for summed fixed-point frequencies S (P) and
+// Sq (Q), Q's missing classes raised to one unit where P has them:
+// floor(sum_k S_k (lg S_k - lg Q_k) / sum S) + lg sum Q - lg sum S.
+template <int KMAX>
+__device__ int64_t kl_q32(const uint64_t* S, const uint64_t* Sq, int K) {
+    u128 pos = 0, neg = 0;
+    uint64_t sp = 0, sq = 0;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        if (k >= K) break;
+        const uint64_t q = (Sq[k] == 0 && S[k] != 0) ? 1 : Sq[k];
+        sp += S[k];
+        sq += q;
+        if (S[k]) {
+            const uint64_t a = lg2_q32(S[k]), b = lg2_q32(q);
+            if (a >= b)
+                pos += (u128)S[k] * (a - b);
+            else
+                neg += (u128)S[k] * (b - a);
+        }
+    }
+    int64_t first;
+    if (pos >= neg) {
+        first = (int64_t)udiv128(pos - neg, (u128)sp);
+    } else {  // floor of a negative quotient
+        const u128 m = neg - pos;
+        const uint64_t qt = udiv128(m, (u128)sp);
+        first = -(int64_t)qt - (((u128)qt * sp != m) ? 1 : 0);
+    }
+    return first + (int64_t)lg2_q32(sq) - (int64_t)lg2_q32(sp);
+}
+
+// Rows [r0, r0 + rb) of job J: one wavefront per row, lanes over the job's
+// trees; writes the summed leaf frequencies S[row][k] and pi(row).
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_kl_base(JobDev* jobs, int j, const NodeDev* nodes,
+                                                 const uint32_t* cls, int kmax, uint32_t tree0,
+                                                 uint32_t r0, uint32_t rb, uint64_t* S,
+                                                 uint32_t* pi) {
+    const JobDev& J = jobs[j];
+    if (!J.live) return;
+    const int lane = threadIdx.x & 63;
+    const uint32_t rr = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (rr >= rb || r0 + rr >= (uint32_t)J.n) return;
+    const uint32_t row = r0 + rr;
+    const int K = J.K;
+    uint64_t acc[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) acc[k] = 0;
+    for (int tau = lane; tau < J.T; tau += 64) {
+        uint32_t node = tree0 + (uint32_t)tau;
+        NodeDev nd = nodes[node];
+        while (nd.feat >= 0) {
+            node = (int)J.colptr[nd.feat][row] <= (int)nd.thr ? nd.left : nd.left + 1;
+            nd = nodes[node];
+        }
+        const uint32_t N = leaf_weight(cls, kmax, node, K);
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+            if (k < K) acc[k] += leaf_freq(cls, kmax, node, k, N);
+    }
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        uint64_t v = acc[k];
+        for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
+        if (lane == 0 && k < K) S[(size_t)rr * K + k] = v;
+    }
+    if (lane == 0) {
+        const KeyedPerm P = make_perm(J.seed_lo, J.seed_hi, kFlush, (uint32_t)J.t, 0u, 0u, 0u,
+                                      (uint64_t)J.n);
+        pi[rr] = perm_apply(P, row);
+    }
+}
+
+// One thread per (row of the block, tree): the row's path; for each column
+// on it (first occurrence), the row is re-routed from that node with the
+// column's bin taken from row pi(row), and a different leaf adds its
+// frequency difference to delta[column][row][k] (64-bit two's complement).
+__global__ __launch_bounds__(256) void k_kl_delta(JobDev* jobs, int j, const NodeDev* nodes,
+                                                  const uint32_t* cls, int kmax, uint32_t tree0,
+                                                  uint32_t r0, uint32_t rb, const uint32_t* pi,
+                                                  unsigned long long* delta, int max_depth) {
+    extern __shared__ uint32_t s_path[];  // [2][max_depth][256]: node, column
+    const JobDev& J = jobs[j];
+    if (!J.live) return;
+    const int tid = threadIdx.x;
+    const uint64_t gi = (uint64_t)blockIdx.x * 256u + (uint64_t)tid;
+    const uint32_t T = (uint32_t)J.T;
+    const uint32_t rr = (uint32_t)(gi / T), tau = (uint32_t)(gi % T);
+    if (rr >= rb || r0 + rr >= (uint32_t)J.n) return;
+    const uint32_t row = r0 + rr, src = pi[rr];
+    const int K = J.K;
+    uint32_t* pn = s_path;
+    uint32_t* pf = s_path + max_depth * 256;
+    int len = 0;
+    uint32_t node = tree0 + tau;
+    NodeDev nd = nodes[node];
+    while (nd.feat >= 0) {
+        pn[len * 256 + tid] = node;
+        pf[len * 256 + tid] = (uint32_t)nd.feat;
+        ++len;
+        node = (int)J.colptr[nd.feat][row] <= (int)nd.thr ? nd.left : nd.left + 1;
+        nd = nodes[node];
+    }
+    const uint32_t leaf0 = node;
+    const uint32_t N0 = leaf_weight(cls, kmax, leaf0, K);
+    for (int a = 0; a < len; ++a) {
+        const uint32_t f = pf[a * 256 + tid];
+        bool dup = false;
+        for (int b = 0; b < a; ++b) dup |= pf[b * 256 + tid] == f;
+        if (dup) continue;
+        const int sb = J.colptr[f][src];
+        uint32_t ni = pn[a * 256 + tid];
+        NodeDev x = nodes[ni];
+        while (x.feat >= 0) {
+            const int bin = (uint32_t)x.feat == f ? sb : (int)J.colptr[x.feat][row];
+            ni = bin <= (int)x.thr ? x.left : x.left + 1;
+            x = nodes[ni];
+        }
+        if (ni == leaf0) continue;
+        const uint32_t N1 = leaf_weight(cls, kmax, ni, K);
+        unsigned long long* d = delta + ((size_t)f * rb + rr) * K;
+        for (int k = 0; k < K; ++k) {
+            const uint64_t dv = leaf_freq(cls, kmax, ni, k, N1) - leaf_freq(cls, kmax, leaf0, k, N0);
+            if (dv) atomicAdd(d + k, (unsigned long long)dv);
+        }
+    }
+}
+
+// One thread per (column, row of the block): the row's divergence for the
+// column from S and S + delta (zero when delta is), delta cleared behind the
+// read; one 64-bit atomic per workgroup into the column's importance.
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_kl_reduce(JobDev* jobs, int j, uint32_t r0, uint32_t rb,
+                                                   uint32_t row_groups, const uint64_t* S,
+                                                   unsigned long long* delta) {
+    __shared__ long long s_sum[4];
+    JobDev& J = jobs[j];
+    if (!J.live) return;
+    const uint32_t f = blockIdx.x / row_groups;
+    const uint32_t rr = (blockIdx.x % row_groups) * 256u + threadIdx.x;
+    const int K = J.K;
+    long long kl = 0;
+    if (f < (uint32_t)J.p_w && rr < rb && r0 + rr < (uint32_t)J.n) {
+        unsigned long long* d = delta + ((size_t)f * rb + rr) * K;
+        uint64_t base[KMAX], q[KMAX];
+        bool moved = false;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            base[k] = q[k] = 0;
+            if (k < K) {
+                const uint64_t dv = d[k];
+                moved |= dv != 0;
+                base[k] = S[(size_t)rr * K + k];
+                q[k] = base[k] + dv;
+            }
+        }
+        if (moved) {
+            kl = kl_q32<KMAX>(base, q, K);
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k < K) d[k] = 0;
+        }
+    }
+    for (int m = 1; m < 64; m <<= 1) kl += __shfl_xor(kl, m);
+    if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = kl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const long long v = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
+        if (v) atomicAdd((unsigned long long*)&J.imp[f], (unsigned long long)v);
+    }
+}
+
 // Per job: hits, history row, shadow maximum, decisions, liveness.
 __global__ __launch_bounds__(256) void k_hits_decide(JobDev* jobs) {
     __shared__ long long s_max[4], s_sum[4];
@@ -143,6 +358,8 @@ __global__ __launch_bounds__(256) void k_hits_decide(JobDev* jobs) {
     double denom;
     if (J.mode == 0) {
         denom = (double)total;
+    } else if (J.mode == 2) {  // mean divergence per row, in bits
+        denom = (double)J.n * 4294967296.0;
     } else {
         long long oob = 0;
         for (int tau = 0; tau < J.T; ++tau) oob += J.tstat[tau * 4 + 1];
@@ -207,6 +424,32 @@ void launch_permut(JobDev* jobs, const TreeDev* trees, const NodeDev* nodes, int
     const size_t lds = (size_t)2 * max_depth * 256 * sizeof(uint32_t);
     hipLaunchKernelGGL(k_permut, dim3((unsigned)((max_n + 255) / 256), (unsigned)n_trees),
                        dim3(256), lds, st, jobs, trees, nodes, max_depth);
+}
+
+// The KL importance of job j over rows [r0, r0 + rb): base, deltas, reduce.
+void launch_kl_block(JobDev* jobs, int j, const NodeDev* nodes, const uint32_t* cls, int kmax,
+                     uint32_t tree0, int T, int p_w_cap, uint32_t r0, uint32_t rb, uint64_t* S,
+                     uint32_t* pi, unsigned long long* delta, int max_depth, hipStream_t st) {
+    const dim3 b256(256);
+    const unsigned g_base = (rb + 3) / 4;
+    switch (kmax) {
+        case 2: hipLaunchKernelGGL(k_kl_base<2>, dim3(g_base), b256, 0, st, jobs, j, nodes, cls, kmax, tree0, r0, rb, S, pi); break;
+        case 4: hipLaunchKernelGGL(k_kl_base<4>, dim3(g_base), b256, 0, st, jobs, j, nodes, cls, kmax, tree0, r0, rb, S, pi); break;
+        case 8: hipLaunchKernelGGL(k_kl_base<8>, dim3(g_base), b256, 0, st, jobs, j, nodes, cls, kmax, tree0, r0, rb, S, pi); break;
+        default: hipLaunchKernelGGL(k_kl_base<16>, dim3(g_base), b256, 0, st, jobs, j, nodes, cls, kmax, tree0, r0, rb, S, pi); break;
+    }
+    const size_t lds = (size_t)2 * max_depth * 256 * sizeof(uint32_t);
+    const unsigned g_delta = (unsigned)(((uint64_t)rb * T + 255) / 256);
+    hipLaunchKernelGGL(k_kl_delta, dim3(g_delta), b256, lds, st, jobs, j, nodes, cls, kmax, tree0,
+                       r0, rb, pi, delta, max_depth);
+    const uint32_t groups = (rb + 255) / 256;
+    const unsigned g_red = (unsigned)(groups * (uint64_t)p_w_cap);
+    switch (kmax) {
+        case 2: hipLaunchKernelGGL(k_kl_reduce<2>, dim3(g_red), b256, 0, st, jobs, j, r0, rb, groups, S, delta); break;
+        case 4: hipLaunchKernelGGL(k_kl_reduce<4>, dim3(g_red), b256, 0, st, jobs, j, r0, rb, groups, S, delta); break;
+        case 8: hipLaunchKernelGGL(k_kl_reduce<8>, dim3(g_red), b256, 0, st, jobs, j, r0, rb, groups, S, delta); break;
+        default: hipLaunchKernelGGL(k_kl_reduce<16>, dim3(g_red), b256, 0, st, jobs, j, r0, rb, groups, S, delta); break;
+    }
 }
 
 void launch_hits_decide(JobDev* jobs, int n_jobs, hipStream_t st) {

@@ -36,14 +36,15 @@ def test_default_options():
     o = B.boruta_default_options()
     assert (o.n_bins, o.n_perm, o.split_rank, o.form) == (256, 1, B.RANK_FP32, B.FORM_BATCHED)
     assert (o.graph, o.small_rows, o.grid_small, o.grid_hist, o.grid_finalize) == (1, 32, 0, 0, 0)
-    assert (o.col_level, o.col_unit, o.grid_col) == (0, 512, 0)
+    assert (o.col_level, o.col_unit, o.grid_col, o.kl_rows) == (0, 512, 0, 0)
     assert not o.trace and not o.stats
 
 
 def test_tuning_options_validated_on_the_host():
     for tune in (dict(small_rows=1), dict(small_rows=65), dict(grid_hist=-1),
                  dict(grid_small=70000), dict(col_level=-1), dict(col_level=65),
-                 dict(col_unit=-2), dict(col_unit=65537), dict(grid_col=70000)):
+                 dict(col_unit=-2), dict(col_unit=65537), dict(grid_col=70000),
+                 dict(kl_rows=-1)):
         with pytest.raises(B.BorutaError) as e:
             B.boruta_workspace_size([dict(n=100, p=5, n_classes=2, n_trees=2, max_depth=3)],
                                     tune=tune)
@@ -83,6 +84,16 @@ def test_column_path_buffers_only_when_a_level_uses_it():
             B.boruta_workspace_size(wide, tune=dict(col_level=64)))
 
 
+def test_kl_buffers_sized_by_row_block():
+    job = [dict(n=5000, p=50, n_classes=3, n_trees=10, max_depth=8, importance_mode=2)]
+    other = [dict(job[0], importance_mode=1)]
+    full = B.boruta_workspace_size(job)
+    # one block of all rows: differences [p_w][n][K] u64 plus the row sums
+    assert full >= B.boruta_workspace_size(other) + 100 * 5000 * 3 * 8
+    assert B.boruta_workspace_size(job, tune=dict(kl_rows=100)) < full
+    assert B.boruta_workspace_size(job, tune=dict(kl_rows=100000)) == full
+
+
 def _call(**kw):
     args = dict(X=np.zeros((10, 3), np.float32), y=np.zeros(10, np.int32), n_classes=2,
                 n_trees=2, max_depth=2, max_iter=3)
@@ -93,7 +104,7 @@ def _call(**kw):
 @pytest.mark.parametrize("kw", [dict(n_classes=1), dict(n_classes=17), dict(n_trees=0),
                                 dict(max_depth=0), dict(max_depth=31), dict(max_iter=0),
                                 dict(max_iter=1001), dict(alpha=0.5), dict(alpha=0.0),
-                                dict(mtry=-1), dict(importance_mode=2), dict(n_bins=1),
+                                dict(mtry=-1), dict(importance_mode=3), dict(importance_mode=-1), dict(n_bins=1),
                                 dict(n_bins=257), dict(n_perm=0), dict(split_rank=2),
                                 dict(form=3), dict(X=np.zeros((1, 3), np.float32),
                                                    y=np.zeros(1, np.int32))])

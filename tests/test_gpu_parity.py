@@ -68,7 +68,7 @@ PATHS = {"node": dict(col_level=64), "column": dict(col_level=1, col_unit=3)}
 
 
 @pytest.mark.parametrize("path", sorted(PATHS))
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 @pytest.mark.parametrize("case", CASES, ids=[str(c[0]) for c in CASES])
 def test_parity_cases(case, mode, path):
     seed, n, p, K, T, D, kw = case
@@ -113,10 +113,10 @@ def test_plain_and_batched_forms_identical():
 
 def test_batch_equals_single_jobs():
     jobs = []
-    for j in range(5):
+    for j in range(6):
         X, y = problem(30 + j, 200 + 300 * j, 15, 2 + j % 3)
         jobs.append(dict(X=X, y=y, n_classes=2 + j % 3, n_trees=4 + j, max_depth=6 + j,
-                         importance_mode=j % 2, max_iter=3 + j, seed=40 + j))
+                         importance_mode=j % 3, max_iter=3 + j, seed=40 + j))
     batch = B.boruta_fit_batch(jobs, trace=True)
     for j, jd in enumerate(jobs):
         single = B.boruta_fit_ex(jd["X"], jd["y"], jd["n_classes"], jd["n_trees"],
@@ -185,7 +185,7 @@ def test_session_steps_and_resume_reproduce_a_run():
     np.testing.assert_array_equal(res["imp_history"][5:k], full["imp_history"][5:k])
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_graph_replays_match_eager_launches(mode):
     """The batched iteration captured once as a HIP graph and replayed every
     step (with the host's read-back and checks between replays) gives the
@@ -236,6 +236,24 @@ def test_launch_tuning_leaves_results_unchanged(tune, K):
     a = B.boruta_fit_ex(X, y, K, 8, 10, **kw)
     b = B.boruta_fit_ex(X, y, K, 8, 10, tune=tune, **kw)
     assert_same_run(a, b)
+
+
+@pytest.mark.parametrize("kl_rows", [7, 256])
+def test_kl_importance_in_row_blocks(kl_rows):
+    # the divergence step in blocks of 7 rows (ragged last block) or 256,
+    # against the oracle, and against the default single block
+    X, y = problem(41, 1500, 12, 3)
+    kw = dict(importance_mode=2, max_iter=4, seed=17)
+    g, o = both(X, y, 3, 9, 9, tune=dict(kl_rows=kl_rows), **kw)
+    assert_same_run(g, o)
+    d = B.boruta_fit_ex(X, y, 3, 9, 9, trace=True, **kw)
+    assert_same_run(g, d)
+
+
+def test_kl_importance_medium_problem():
+    X, y = problem(42, 4000, 40, 4, "mixed")
+    g, o = both(X, y, 4, 24, 12, importance_mode=2, max_iter=3, seed=18)
+    assert_same_run(g, o)
 
 
 def test_autotuner_returns_a_valid_choice(tmp_path):
