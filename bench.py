@@ -30,8 +30,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["treeimp", "permut", "workload"], default="workload",
-                    help="importance mode (default: the workload's own)")
+    ap.add_argument("--mode", choices=["treeimp", "permut", "kl", "workload"], default="workload",
+                    help="importance mode (default: the workload's own); kl = Algorithm 3's "
+                         "prediction divergence")
     ap.add_argument("--workload", choices=["madelon", "planted", "omics", "manyjob", "scale"],
                     default="madelon")
     ap.add_argument("--no-compare", action="store_true",
@@ -282,7 +283,8 @@ def main():
     jobs, pr, desc, keys = workload(args.workload)
     if args.mode != "workload":
         for jd in jobs:
-            jd["importance_mode"] = B.TREEIMP if args.mode == "treeimp" else B.PERMUT
+            jd["importance_mode"] = {"treeimp": B.TREEIMP, "permut": B.PERMUT,
+                                     "kl": B.PERMUT_KL}[args.mode]
     mode = jobs[0]["importance_mode"]
     unit = "job-iters/s" if len(jobs) > 1 else "iters/s"
     tune, tune_s, tune_report = None, 0.0, {}
@@ -323,11 +325,18 @@ def main():
                            for d in range(max(j["max_depth"] for j in jobs))]}}
     if not args.no_compare:
         k = max(1, min(5, args.steps))
-        other = [dict(jd, importance_mode=1 - jd["importance_mode"]) for jd in jobs]
+        other = [dict(jd, importance_mode=B.PERMUT if jd["importance_mode"] == B.TREEIMP
+                      else B.TREEIMP) for jd in jobs]
         leg = run_gpu(other, pr, k, args.warmup, B.FORM_BATCHED, B.RANK_FP32, stats=False,
                       tune=tune)
         extra["other_mode_" + unit.replace("/", "_per_")] = round(
             leg["job_iters"] / leg["seconds"], 3)
+        if mode != B.PERMUT_KL:
+            kl = [dict(jd, importance_mode=B.PERMUT_KL) for jd in jobs]
+            leg = run_gpu(kl, pr, k, args.warmup, B.FORM_BATCHED, B.RANK_FP32, stats=False,
+                          tune=tune)
+            extra["permut_kl_" + unit.replace("/", "_per_")] = round(
+                leg["job_iters"] / leg["seconds"], 3)
         leg = run_gpu(jobs, pr, k, args.warmup, B.FORM_BATCHED, B.RANK_EXACT, stats=False,
                       tune=tune)
         extra["exact_rank_" + unit.replace("/", "_per_")] = round(
@@ -341,13 +350,18 @@ def main():
         "ms_per_step": round(1e3 * main_leg["seconds"] / max(1, main_leg["steps"]), 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
         "data": "synthetic",
-        "config": dict({"workload": desc + (", TreeImp" if mode == B.TREEIMP else
-                                            f", Permut R={pr['n_perm']}") +
+        "config": dict({"workload": desc + {B.TREEIMP: ", TreeImp",
+                                            B.PERMUT: f", Permut R={pr['n_perm']}",
+                                            B.PERMUT_KL: ", Permut-KL (Algorithm 3)"}[mode] +
                         ", batched form, FP32 ranking + exact recheck"}, **keys),
         "roofline": roof,
         "extra": extra,
     }
-    if not args.no_cpu_baseline:
+    if mode == B.PERMUT_KL:
+        # the oracle's divergence step re-routes every (column, row, tree): no
+        # sample of it stays within the CPU leg's time budget
+        extra["cpu_baseline_note"] = "not run for the divergence mode"
+    elif not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, jobs, pr)
     print(json.dumps(line), flush=True)
 
