@@ -938,6 +938,41 @@ int oracle_boruta_fit(const float* X, const int32_t* y, int64_t n, int64_t p, in
     return 0;
 }
 
+// Final ranking of Algorithm 1: confirmed features rank 1, undecided ones 2,
+// rejected ones by descending historical importance from 3 on.  Reading: a
+// rejected feature's historical importance is the mean of its finite history
+// entries (the iterations in which it was active), summed in iteration order;
+// its rank is 3 plus the number of rejected features with a strictly larger
+// mean (equal means share a rank).
+void oracle_rank(const int8_t* decision, const double* imp_history, int64_t p, int32_t n_iter,
+                 int32_t* rank_out) {
+    std::vector<double> mean(p, 0.0);
+    for (int64_t j = 0; j < p; ++j) {
+        if (decision[j] != -1) continue;
+        double s = 0.0;
+        int c = 0;
+        for (int32_t t = 0; t < n_iter; ++t) {
+            const double v = imp_history[(size_t)t * p + j];
+            if (std::isnan(v)) continue;
+            s += v;
+            ++c;
+        }
+        mean[j] = c ? s / c : 0.0;
+    }
+    for (int64_t j = 0; j < p; ++j) {
+        if (decision[j] == 1) {
+            rank_out[j] = 1;
+        } else if (decision[j] == 0) {
+            rank_out[j] = 2;
+        } else {
+            int32_t above = 0;
+            for (int64_t g = 0; g < p; ++g)
+                if (decision[g] == -1 && mean[g] > mean[j]) ++above;
+            rank_out[j] = 3 + above;
+        }
+    }
+}
+
 int oracle_boruta_step(const float* X, const int32_t* y, int64_t n, int64_t p, int32_t n_classes,
                        int32_t n_trees, int32_t max_depth, int32_t mtry, int32_t importance_mode,
                        double alpha, uint64_t seed, int32_t n_bins, int32_t n_perm, int32_t t,

@@ -109,6 +109,12 @@ int oracle_boruta_fit(const float* X, const int32_t* y, int64_t n, int64_t p,
                       int32_t* hits_out, double* shadow_max_out, int32_t* n_iter_out,
                       oracle_trace_fn trace, void* trace_user);
 
+/* Algorithm 1's final ranking from a run's decision and history: 1
+ * confirmed, 2 undecided, rejected from 3 by descending mean historical
+ * importance (ties share a rank). */
+void oracle_rank(const int8_t* decision, const double* imp_history, int64_t p, int32_t n_iter,
+                 int32_t* rank_out);
+
 /* One iteration t from a given (state, hits): the state machine of Algorithm
  * 1 is memoryless apart from these two vectors, so any iteration of a run
  * can be recomputed alone.  state/hits are updated in place.  tree_subset

@@ -66,6 +66,8 @@ def lib():
         L.oracle_log2_fix32.restype = u64
         L.oracle_kl_fix32.argtypes = [P, P, i32]
         L.oracle_kl_fix32.restype = i64
+        L.oracle_rank.argtypes = [P, P, i64, i32, P]
+        L.oracle_rank.restype = None
         L.oracle_bootstrap.argtypes = [u64, u32, u32, i64, P]
         L.oracle_bootstrap.restype = None
         L.oracle_best_split.argtypes = [P, i64, P, P, P, i64, P, i32, i32, i32, P]
@@ -200,8 +202,19 @@ def boruta_fit(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=0, m
                                  cb, None)
     if rc:
         raise ValueError(f"oracle_boruta_fit failed: {rc}")
+    rank = np.zeros(p, dtype=np.int32)
+    hist_c = np.ascontiguousarray(hist)
+    lib().oracle_rank(_ptr(dec), _ptr(hist_c), p, n_iter.value, _ptr(rank))
     return {"decision": dec, "imp_history": hist, "hits": hits, "shadow_max": smax,
-            "n_iter": n_iter.value, "traces": traces, "rc": rc}
+            "n_iter": n_iter.value, "traces": traces, "rc": rc, "rank": rank}
+
+
+def rank(decision, imp_history, n_iter):
+    dec = np.ascontiguousarray(decision, dtype=np.int8)
+    hist = np.ascontiguousarray(imp_history, dtype=np.float64)
+    out = np.zeros(dec.shape[0], dtype=np.int32)
+    lib().oracle_rank(_ptr(dec), _ptr(hist), dec.shape[0], n_iter, _ptr(out))
+    return out
 
 
 def boruta_step(X, y, n_classes, n_trees, max_depth, t, state, hits, mtry=0,

@@ -64,3 +64,34 @@ def test_monotone_thresholds():
         d = [O.binom_decide(h, t, 100, 0.05) for h in range(t + 1)]
         # -1 ... -1, 0 ... 0, 1 ... 1
         assert d == sorted(d)
+
+
+def test_final_ranking_of_algorithm1():
+    # hand-computed: features 0 and 3 confirmed, 4 undecided, 1, 2, 5 rejected
+    # with mean history (over their finite entries) 0.2, 0.35, 0.35 -> ranks
+    # 5, 3, 3 (equal means share the smaller rank)
+    nan = np.nan
+    hist = np.array([[0.5, 0.1, 0.4, 0.6, 0.2, 0.3],
+                     [0.6, 0.3, 0.3, 0.7, 0.1, 0.4],
+                     [0.7, nan, nan, 0.8, 0.3, nan],
+                     [9.0, 9.0, 9.0, 9.0, 9.0, 9.0]])  # past n_iter: ignored
+    dec = np.array([1, -1, -1, 1, 0, -1], np.int8)
+    r = O.rank(dec, hist, 3)
+    assert list(r) == [1, 5, 3, 1, 2, 3]
+
+
+def test_final_ranking_properties_on_a_run():
+    from paper_2605_09950_amd import synth
+    c = synth.config(0)
+    pr = c["params"]
+    out = O.boruta_fit(c["X"], c["y"], 2, pr["n_trees"], pr["max_depth"], max_iter=pr["max_iter"],
+                       seed=c["seed"], n_bins=pr["n_bins"])
+    r, d, h = out["rank"], out["decision"], out["imp_history"][: out["n_iter"]]
+    assert np.all(r[d == 1] == 1) and np.all(r[d == 0] == 2) and np.all(r[d == -1] >= 3)
+    rej = np.flatnonzero(d == -1)
+    m = {j: np.nanmean(h[:, j]) for j in rej}
+    for a in rej:
+        for b in rej:
+            if m[a] > m[b] + 1e-12:
+                assert r[a] < r[b]
+    assert r[rej].min() == 3
