@@ -204,6 +204,11 @@ typedef struct {
     double* imp_history;
     int32_t* hits;       /* nullable */
     double* shadow_max;  /* nullable */
+    int32_t* rank;       /* nullable: [p] Algorithm 1's final ranking -- 1 confirmed,
+                            2 undecided, rejected features from 3 by descending
+                            historical importance (mean of their history entries;
+                            equal means share a rank).  After boruta_session_resume
+                            the history counted starts at the resume point. */
     int32_t n_iter;      /* out */
     int32_t status;      /* out: BORUTA_OK or the job's own error code */
 } boruta_result;

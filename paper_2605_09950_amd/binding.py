@@ -80,6 +80,7 @@ class Job(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("decision", ctypes.c_void_p), ("imp_history", ctypes.c_void_p),
                 ("hits", ctypes.c_void_p), ("shadow_max", ctypes.c_void_p),
+                ("rank", ctypes.c_void_p),
                 ("n_iter", ctypes.c_int32), ("status", ctypes.c_int32)]
 
 
@@ -280,11 +281,13 @@ def boruta_fit_batch(jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM
                      jd.get("importance_mode", TREEIMP), max_iter, jd.get("alpha", 0.05),
                      jd.get("seed", 0))
         o = {"decision": np.zeros(p, np.int8), "imp_history": np.full((max_iter, p), np.nan),
-             "hits": np.zeros(p, np.int32), "shadow_max": np.full(max_iter, np.nan)}
+             "hits": np.zeros(p, np.int32), "shadow_max": np.full(max_iter, np.nan),
+             "rank": np.zeros(p, np.int32)}
         res[i].decision = o["decision"].ctypes.data
         res[i].imp_history = o["imp_history"].ctypes.data
         res[i].hits = o["hits"].ctypes.data
         res[i].shadow_max = o["shadow_max"].ctypes.data
+        res[i].rank = o["rank"].ctypes.data
         arrs.append((X, y))
         outs.append(o)
     p_all = [int(np.shape(jd["X"])[1]) for jd in jobs]
@@ -411,12 +414,14 @@ class Session:
     def result(self, job=0):
         p, max_iter = self._shapes[job]
         o = {"decision": np.zeros(p, np.int8), "imp_history": np.full((max_iter, p), np.nan),
-             "hits": np.zeros(p, np.int32), "shadow_max": np.full(max_iter, np.nan)}
+             "hits": np.zeros(p, np.int32), "shadow_max": np.full(max_iter, np.nan),
+             "rank": np.zeros(p, np.int32)}
         r = Result()
         r.decision = o["decision"].ctypes.data
         r.imp_history = o["imp_history"].ctypes.data
         r.hits = o["hits"].ctypes.data
         r.shadow_max = o["shadow_max"].ctypes.data
+        r.rank = o["rank"].ctypes.data
         _check(lib().boruta_session_result(self.h, job, ctypes.byref(r)))
         o["n_iter"] = r.n_iter
         return o

@@ -49,6 +49,7 @@ void launch_kl_block(JobDev*, int, const NodeDev*, const uint32_t*, int, uint32_
                      uint32_t, uint32_t, uint64_t*, uint32_t*, unsigned long long*, int,
                      hipStream_t);
 void launch_copy(void*, const void*, size_t, hipStream_t);
+void launch_rank(const int8_t*, const double*, int64_t, int, int, double*, int32_t*, hipStream_t);
 
 namespace {
 
@@ -180,6 +181,7 @@ struct JobPlan {
     int64_t n_pad, P;
     uint32_t gbase;
     uint32_t kl_rb;  // KL importance: rows per block (0: the job does not use it)
+    size_t rmean, rank;  // final ranking: per-feature mean history, rank
     int max_sha, pw_cap, mtry_max;
     size_t X, y32, y8, orig, sha, colptr, colsrc, act, state, hits, hist, smax, hconf, hrej, G,
         imp, wbuf, rec0, rec1, oob, tstat;
@@ -247,6 +249,8 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
         j.rec1 = r.take(T * n * 8);
         j.oob = r.take(T * n * 4);
         j.tstat = r.take(T * 16);
+        j.rmean = r.take(p * 8);
+        j.rank = r.take(p * 4);
         // KL importance: the per-(column, row, class) leaf differences of a
         // block of rows are bounded by kKlDeltaBytes
         j.kl_rb = 0;
@@ -349,6 +353,7 @@ struct Out {
     double* hist;
     int32_t* hits;
     double* smax;
+    int32_t* rank = nullptr;
     int32_t n_iter = 0;
 };
 
@@ -475,6 +480,7 @@ private:
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<JobDev> hj;       // host mirror of the job records
     std::vector<int> tree_base;   // first tree of each job in the static tree table
+    std::vector<int> hist_t0;     // first history row computed here (after a resume: t)
     bool any_treeimp = false, any_permut = false, any_kl = false;
 };
 
@@ -486,6 +492,7 @@ void Engine::setup(std::vector<int>& status) {
         HIPC(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
     }
     hj.assign(nj, JobDev{});
+    hist_t0.assign(nj, 0);
     uint32_t* flags = at<uint32_t>(pl.flags);
     for (int j = 0; j < nj; ++j) {
         const Spec& s = S[j];
@@ -953,6 +960,12 @@ void Engine::result(int j, Out& o) {
     if (J.t > 0 && o.hist) d2h(o.hist, J.hist, (size_t)J.t * s.p * 8);
     if (o.hits) d2h(o.hits, J.hits, (size_t)s.p * 4);
     if (o.smax && J.t > 0) d2h(o.smax, J.shadow_max, (size_t)J.t * 8);
+    if (o.rank) {
+        const JobPlan& jp = pl.jp[j];
+        launch_rank(J.state, J.hist, s.p, hist_t0[j], J.t, at<double>(jp.rmean),
+                    at<int32_t>(jp.rank), st);
+        d2h(o.rank, at<int32_t>(jp.rank), (size_t)s.p * 4);
+    }
     o.n_iter = J.t;
 }
 
@@ -970,6 +983,7 @@ void Engine::resume(int j, int t, const int8_t* state, const int32_t* hits) {
     for (int64_t i = 0; i < s.p; ++i) und |= state[i] == 0;
     J.t = t;
     J.live = und ? 1 : 0;
+    hist_t0[j] = t;  // history rows before t are the caller's
     h2d(at<JobDev>(pl.jobs) + j, &J, sizeof(JobDev));
     HIPC(hipStreamSynchronize(st));
 }
@@ -1172,6 +1186,7 @@ int boruta_fit_batch(const boruta_job* jobs, int32_t n_jobs, const boruta_option
         outs[i].hist = results[i].imp_history;
         outs[i].hits = results[i].hits;
         outs[i].smax = results[i].shadow_max;
+        outs[i].rank = results[i].rank;
     }
     std::vector<int> status(n_jobs, BORUTA_OK);
     const int rc = run_jobs(specs, opt, outs, status, false, nullptr, 0, nullptr);
@@ -1314,6 +1329,7 @@ int boruta_session_result(boruta_session* s, int32_t job, boruta_result* out) {
         o.hist = out->imp_history;
         o.hits = out->hits;
         o.smax = out->shadow_max;
+        o.rank = out->rank;
         s->ctx->eng->result(job, o);
         out->n_iter = o.n_iter;
         out->status = BORUTA_OK;

@@ -20,7 +20,10 @@
 //     tree can move it to another leaf of that tree: per (row, tree) those
 //     columns are re-routed and the leaf differences accumulated per
 //     (column, row); rows are taken in blocks that bound that buffer.
-//   * hits (strictly above the best shadow) and the binomial decision.
+//   * hits (strictly above the best shadow) and the binomial decision;
+//   * Algorithm 1's final ranking: confirmed 1, undecided 2, rejected from 3
+//     by descending historical importance (the mean of the feature's finite
+//     history entries, summed in iteration order; equal means share a rank).
 #include "dev_common.hpp"
 
 namespace boruta {
@@ -401,6 +404,48 @@ __global__ __launch_bounds__(256) void k_hits_decide(JobDev* jobs) {
     }
 }
 
+// Final ranking, step 1: one thread per feature; a rejected feature's mean
+// over its finite history entries of iterations [t0, t1).
+__global__ __launch_bounds__(256) void k_rank_mean(const int8_t* state, const double* hist,
+                                                   int64_t p, int t0, int t1, double* mean) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= p) return;
+    double s = 0.0, m = 0.0;
+    int c = 0;
+    if (state[j] == -1) {
+        for (int t = t0; t < t1; ++t) {
+            const double v = hist[(size_t)t * p + j];
+            if (v != v) continue;  // NaN: not active in iteration t
+            s += v;
+            ++c;
+        }
+        m = c ? s / c : 0.0;
+    }
+    mean[j] = m;
+}
+
+// Step 2: one thread per feature; a rejected feature ranks 3 plus the number
+// of rejected features with a strictly larger mean.
+__global__ __launch_bounds__(256) void k_rank_count(const int8_t* state, const double* mean,
+                                                    int64_t p, int32_t* rank) {
+    __shared__ double s_m[256];
+    __shared__ int8_t s_s[256];
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int8_t sj = j < p ? state[j] : (int8_t)0;
+    const double mj = j < p ? mean[j] : 0.0;
+    int above = 0;
+    for (int64_t g0 = 0; g0 < p; g0 += 256) {
+        __syncthreads();
+        const int64_t g = g0 + threadIdx.x;
+        s_m[threadIdx.x] = g < p ? mean[g] : 0.0;
+        s_s[threadIdx.x] = g < p ? state[g] : (int8_t)0;
+        __syncthreads();
+        const int lim = (int)(p - g0 < 256 ? p - g0 : 256);
+        for (int i = 0; i < lim; ++i) above += (s_s[i] == -1 && s_m[i] > mj) ? 1 : 0;
+    }
+    if (j < p) rank[j] = sj == 1 ? 1 : (sj == 0 ? 2 : 3 + above);
+}
+
 // Streaming copy used to calibrate hardware byte counters.
 __global__ void k_copy(uint4* dst, const uint4* src, size_t n16) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -454,6 +499,13 @@ void launch_kl_block(JobDev* jobs, int j, const NodeDev* nodes, const uint32_t* 
 
 void launch_hits_decide(JobDev* jobs, int n_jobs, hipStream_t st) {
     hipLaunchKernelGGL(k_hits_decide, dim3(n_jobs), dim3(256), 0, st, jobs);
+}
+
+void launch_rank(const int8_t* state, const double* hist, int64_t p, int t0, int t1,
+                 double* mean, int32_t* rank, hipStream_t st) {
+    const unsigned g = (unsigned)((p + 255) / 256);
+    hipLaunchKernelGGL(k_rank_mean, dim3(g), dim3(256), 0, st, state, hist, p, t0, t1, mean);
+    hipLaunchKernelGGL(k_rank_count, dim3(g), dim3(256), 0, st, state, mean, p, rank);
 }
 
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {

@@ -31,6 +31,8 @@ def assert_same_run(g, o):
     assert np.array_equal(np.isnan(gh), np.isnan(oh))
     assert np.array_equal(gh[~np.isnan(gh)], oh[~np.isnan(oh)])
     assert np.array_equal(g["shadow_max"][:k], o["shadow_max"][:k])
+    if "rank" in g and "rank" in o:
+        assert np.array_equal(g["rank"], o["rank"])
     if g.get("traces") and o.get("traces"):
         assert len(g["traces"]) == len(o["traces"])
         for gt, ot in zip(g["traces"], o["traces"]):

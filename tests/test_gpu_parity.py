@@ -238,6 +238,28 @@ def test_launch_tuning_leaves_results_unchanged(tune, K):
     assert_same_run(a, b)
 
 
+def test_final_ranking_matches_oracle():
+    # Algorithm 1's ranking through the batch API (all three importance
+    # modes) and through a session's result
+    jobs = []
+    for j in range(3):
+        X, y = problem(50 + j, 600, 14, 3)
+        jobs.append(dict(X=X, y=y, n_classes=3, n_trees=8, max_depth=7, importance_mode=j,
+                         max_iter=12, seed=60 + j))
+    batch = B.boruta_fit_batch(jobs)
+    for j, jd in enumerate(jobs):
+        o = O.boruta_fit(jd["X"], jd["y"], 3, 8, 7, importance_mode=j, max_iter=12, seed=60 + j)
+        r = batch["results"][j]
+        assert r["n_iter"] == o["n_iter"]
+        assert np.array_equal(r["decision"], o["decision"])
+        assert np.array_equal(r["rank"], o["rank"])
+        assert (r["rank"] == 3).any() or not (r["decision"] == -1).any()
+    with B.Session(jobs[:1]) as s:
+        while s.step():
+            pass
+        assert np.array_equal(s.result(0)["rank"], batch["results"][0]["rank"])
+
+
 @pytest.mark.parametrize("kl_rows", [7, 256])
 def test_kl_importance_in_row_blocks(kl_rows):
     # the divergence step in blocks of 7 rows (ragged last block) or 256,
