@@ -3,16 +3,24 @@
 // Trees grow level by level, all trees of all live jobs in the same launch:
 //   * k_boot_compact  per tree: in-bag row records and OOB rows from the
 //                     bootstrap multiplicities, root node;
-//   * k_split_small   one wavefront per node with <= 64 distinct rows: the
-//                     rows sit in lanes and every threshold's left class
-//                     counts come from an in-register all-pairs sum;
-//   * k_hist_tile     one workgroup per (node, tile of drawn features):
-//                     LDS class-count histogram [feature][class][bin] built
-//                     with LDS atomics from batched global gathers, then a
-//                     wave prefix scan over the bins per feature; writes the
-//                     tile's best candidate;
-//   * k_split_finalize one workgroup per large node: best over the node's
-//                     tiles, then a stable partition of its rows.
+//   * k_split_small   one wavefront per node with <= small_rows distinct
+//                     rows: the rows sit in lanes and every threshold's left
+//                     class counts come from an in-register all-pairs sum;
+//   * k_draws         one wavefront per large node: its drawn features and
+//                     their columns, and the node's slot record;
+//   * k_hist_tile     node-major: one wavefront per (large node, fw drawn
+//                     features): LDS class-count histogram [feature][class]
+//                     [bin] built with LDS atomics from batched global bin
+//                     gathers, then a wave prefix scan per feature; writes
+//                     the item's best candidate;
+//   * k_col_scan, k_col_scatter, k_hist_col  column-major (deep levels of
+//                     large matrices): the level's items bucketed by bin
+//                     column, each column staged once per unit in LDS, the
+//                     same histogram and scan per item from the staged bins;
+//   * k_split_finalize one wavefront per large node: best over the node's
+//                     items, then a partition of its rows;
+//   * k_lists_count, k_lists_write  the next level's node lists, in parent
+//                     order, without atomics.
 // The split rule (reading of the Gini forest of Sec. 2.1): maximise
 // Q = S_L/N_L + S_R/N_R over drawn features and thresholds "bin <= b",
 // exact rational comparison, ties to the earlier draw then the smaller b;
