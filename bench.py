@@ -176,7 +176,6 @@ def measured_traffic(workload_name, kernel):
     calibrated FETCH_SIZE + WRITE_SIZE counter summary committed under
     profiles/, or None when there is none for this workload or the kernel
     source has changed since the counters were taken."""
-    import hashlib
     if kernel not in ("hist_large", "hist_col"):
         return None
     path = os.path.join(ROOT, "profiles", f"{KERNEL_NAMES[kernel]}_{workload_name}_traffic.md")
@@ -189,12 +188,25 @@ def measured_traffic(workload_name, kernel):
                                                         "kernel_source_sha256")):
                 k, v = line.strip().split(":", 1)
                 fields[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_2605_09950_amd", "csrc", "k_forest.hip")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    if fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+    if fields.get("kernel_code_sha256") != kernel_code_digest() or \
+            "traffic_bytes_per_launch" not in fields:
         return None
     return float(fields["traffic_bytes_per_launch"])
+
+
+def kernel_code_digest():
+    """SHA-256 of the code lines (line comments and blank lines dropped) of
+    the forest kernels and their headers: the key under which a counter
+    summary in profiles/ stays valid."""
+    import hashlib
+    lines = []
+    for name in ("k_forest.hip", "forest_dev.hpp", "dev_common.hpp"):
+        with open(os.path.join(ROOT, "paper_2605_09950_amd", "csrc", name)) as f:
+            for line in f:
+                code = line.split("//", 1)[0].rstrip()
+                if code.strip():
+                    lines.append(code)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()
 
 
 def cpu_baseline(name, jobs, pr):
