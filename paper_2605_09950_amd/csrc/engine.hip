@@ -259,7 +259,7 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
             j.kl_rb = (uint32_t)std::max<uint64_t>(
                 1, std::min<uint64_t>((uint64_t)s.n, kKlDeltaBytes / per_row));
             if (o.kl_rows) j.kl_rb = (uint32_t)std::min<int64_t>(s.n, o.kl_rows);
-            kl_S = std::max<uint64_t>(kl_S, (uint64_t)j.kl_rb * s.K * 8);
+            kl_S = std::max<uint64_t>(kl_S, (uint64_t)j.kl_rb * (2 * s.K + 1) * 8);
             kl_pi = std::max<uint64_t>(kl_pi, (uint64_t)j.kl_rb * 4);
             kl_delta = std::max<uint64_t>(kl_delta, (uint64_t)j.kl_rb * per_row);
         }

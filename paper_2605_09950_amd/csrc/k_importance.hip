@@ -158,8 +158,11 @@ __device__ __forceinline__ uint64_t lg2_q32(uint64_t x) {
 // KL(P || Q) in 2^-32 bits for summed fixed-point frequencies S (P) and
 // Sq (Q), Q's missing classes raised to one unit where P has them:
 // floor(sum_k S_k (lg S_k - lg Q_k) / sum S) + lg sum Q - lg sum S.
+// lgS[k] = lg S_k (where S_k > 0) and lgsum = lg sum S come with P: a row's
+// P is shared by every column.
 template <int KMAX>
-__device__ int64_t kl_q32(const uint64_t* S, const uint64_t* Sq, int K) {
+__device__ int64_t kl_q32(const uint64_t* S, const uint64_t* lgS, uint64_t lgsum,
+                          const uint64_t* Sq, int K) {
     u128 pos = 0, neg = 0;
     uint64_t sp = 0, sq = 0;
 #pragma unroll
@@ -169,7 +172,7 @@ __device__ int64_t kl_q32(const uint64_t* S, const uint64_t* Sq, int K) {
         sp += S[k];
         sq += q;
         if (S[k]) {
-            const uint64_t a = lg2_q32(S[k]), b = lg2_q32(q);
+            const uint64_t a = lgS[k], b = q == S[k] ? a : lg2_q32(q);
             if (a >= b)
                 pos += (u128)S[k] * (a - b);
             else
@@ -184,11 +187,12 @@ __device__ int64_t kl_q32(const uint64_t* S, const uint64_t* Sq, int K) {
         const uint64_t qt = udiv128(m, (u128)sp);
         first = -(int64_t)qt - (((u128)qt * sp != m) ? 1 : 0);
     }
-    return first + (int64_t)lg2_q32(sq) - (int64_t)lg2_q32(sp);
+    return first + (int64_t)(sq == sp ? lgsum : lg2_q32(sq)) - (int64_t)lgsum;
 }
 
 // Rows [r0, r0 + rb) of job J: one wavefront per row, lanes over the job's
-// trees; writes the summed leaf frequencies S[row][k] and pi(row).
+// trees; writes the row's summed leaf frequencies S_k, their lg S_k and
+// lg sum S (S[row][2K + 1]), and pi(row).
 template <int KMAX>
 __global__ __launch_bounds__(256) void k_kl_base(JobDev* jobs, int j, const NodeDev* nodes,
                                                  const uint32_t* cls, int kmax, uint32_t tree0,
@@ -216,12 +220,20 @@ __global__ __launch_bounds__(256) void k_kl_base(JobDev* jobs, int j, const Node
         for (int k = 0; k < KMAX; ++k)
             if (k < K) acc[k] += leaf_freq(cls, kmax, node, k, N);
     }
+    uint64_t mine = 0, sum = 0;  // lane k < K keeps S_k
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
         uint64_t v = acc[k];
         for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
-        if (lane == 0 && k < K) S[(size_t)rr * K + k] = v;
+        if (lane == k) mine = v;
+        if (k < K) sum += v;
     }
+    uint64_t* row_out = S + (size_t)rr * (2 * K + 1);
+    if (lane < K) {
+        row_out[lane] = mine;
+        row_out[K + lane] = mine ? lg2_q32(mine) : 0ull;
+    }
+    if (lane == K) row_out[2 * K] = lg2_q32(sum);
     if (lane == 0) {
         const KeyedPerm P = make_perm(J.seed_lo, J.seed_hi, kFlush, (uint32_t)J.t, 0u, 0u, 0u,
                                       (uint64_t)J.n);
@@ -229,10 +241,13 @@ __global__ __launch_bounds__(256) void k_kl_base(JobDev* jobs, int j, const Node
     }
 }
 
-// One thread per (row of the block, tree): the row's path; for each column
-// on it (first occurrence), the row is re-routed from that node with the
-// column's bin taken from row pi(row), and a different leaf adds its
-// frequency difference to delta[column][row][k] (64-bit two's complement).
+// One thread per (tree, row of the block), rows fastest so that a wave
+// walks one tree for 64 rows (its node and bin loads and its atomics then
+// spread over rows, not over trees meeting at one column): the row's path;
+// for each column on it (first occurrence), the row is re-routed from that
+// node with the column's bin taken from row pi(row), and a different leaf
+// adds its frequency difference to delta[column][row][k] (64-bit two's
+// complement).
 __global__ __launch_bounds__(256) void k_kl_delta(JobDev* jobs, int j, const NodeDev* nodes,
                                                   const uint32_t* cls, int kmax, uint32_t tree0,
                                                   uint32_t r0, uint32_t rb, const uint32_t* pi,
@@ -243,8 +258,8 @@ __global__ __launch_bounds__(256) void k_kl_delta(JobDev* jobs, int j, const Nod
     const int tid = threadIdx.x;
     const uint64_t gi = (uint64_t)blockIdx.x * 256u + (uint64_t)tid;
     const uint32_t T = (uint32_t)J.T;
-    const uint32_t rr = (uint32_t)(gi / T), tau = (uint32_t)(gi % T);
-    if (rr >= rb || r0 + rr >= (uint32_t)J.n) return;
+    const uint32_t tau = (uint32_t)(gi / rb), rr = (uint32_t)(gi % rb);
+    if (tau >= T || r0 + rr >= (uint32_t)J.n) return;
     const uint32_t row = r0 + rr, src = pi[rr];
     const int K = J.K;
     uint32_t* pn = s_path;
@@ -300,20 +315,24 @@ __global__ __launch_bounds__(256) void k_kl_reduce(JobDev* jobs, int j, uint32_t
     long long kl = 0;
     if (f < (uint32_t)J.p_w && rr < rb && r0 + rr < (uint32_t)J.n) {
         unsigned long long* d = delta + ((size_t)f * rb + rr) * K;
-        uint64_t base[KMAX], q[KMAX];
+        uint64_t base[KMAX], lg[KMAX], q[KMAX];
+        const uint64_t* row_in = S + (size_t)rr * (2 * K + 1);
         bool moved = false;
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
-            base[k] = q[k] = 0;
+            base[k] = q[k] = lg[k] = 0;
             if (k < K) {
                 const uint64_t dv = d[k];
                 moved |= dv != 0;
-                base[k] = S[(size_t)rr * K + k];
+                base[k] = row_in[k];
                 q[k] = base[k] + dv;
             }
         }
         if (moved) {
-            kl = kl_q32<KMAX>(base, q, K);
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k < K) lg[k] = row_in[K + k];
+            kl = kl_q32<KMAX>(base, lg, row_in[2 * K], q, K);
 #pragma unroll
             for (int k = 0; k < KMAX; ++k)
                 if (k < K) d[k] = 0;
