@@ -345,7 +345,7 @@ struct ForestDev {
     uint32_t next_base;   // first node index of the next level
     uint32_t n_small_cur; // small nodes searched in this level
     uint32_t small_ncap;  // a node takes the wave path only below this weighted count
-    int32_t kmax, ft, parity, split_rank;
+    int32_t kmax, parity, split_rank;
     int32_t npi;          // histogram items per large node (draw positions / fw)
     int32_t fw;           // draws per histogram item
     uint32_t small_rows;  // a node takes the wave path only up to this many distinct rows

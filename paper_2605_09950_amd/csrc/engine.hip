@@ -194,7 +194,7 @@ struct Plan {
     size_t fcnt = 0, fpos = 0, fitems = 0, units = 0, gcolq = 0;
     size_t kl_S = 0, kl_pi = 0, kl_delta = 0;  // KL importance buffers (shared by its jobs)
     uint32_t node_cap = 0, slot_cap = 0, small_cap = 0;
-    int kmax = 4, ft = 8, max_sha = 1, max_pw = 1, max_D = 1, T_total = 0, mtry_cap = 1,
+    int kmax = 4, max_sha = 1, max_pw = 1, max_D = 1, T_total = 0, mtry_cap = 1,
         npi = 1, fw = 1;
     // column-major histogram path: levels >= col_level (col_level >= max_D: none)
     int col_level = kColNever, col_waves = 0;
@@ -213,7 +213,6 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
         keys_words = std::max<int64_t>(keys_words, s.p * pow2_at_least(s.n));
     }
     pl.kmax = maxK <= 2 ? 2 : (maxK <= 4 ? 4 : (maxK <= 8 ? 8 : 16));
-    pl.ft = 32 / pl.kmax;  // feature columns per histogram tile (32 KB of LDS at 256 bins)
     pl.keys = r.take((size_t)keys_words * 4);
     uint64_t node_cap = 0, slot_cap = 0, small_cap = 0, n_gcol = 0;
     uint64_t kl_S = 0, kl_pi = 0, kl_delta = 0;
@@ -653,7 +652,6 @@ ForestDev Engine::forest() const {
     F.slot_cap = pl.slot_cap;
     F.small_cap = pl.small_cap;
     F.kmax = pl.kmax;
-    F.ft = pl.ft;
     F.split_rank = O.split_rank;
     // the wave path packs class counters in 16-bit fields (8-bit for 3-4 classes)
     F.small_ncap = pl.kmax == 4 ? 256u : 65536u;
