@@ -212,7 +212,8 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
         maxK = std::max(maxK, s.K);
         keys_words = std::max<int64_t>(keys_words, s.p * pow2_at_least(s.n));
     }
-    pl.kmax = maxK <= 2 ? 2 : (maxK <= 4 ? 4 : (maxK <= 8 ? 8 : 16));
+    // class planes of the kernels: exactly 2, 3 or 4, else 8 or 16
+    pl.kmax = maxK <= 4 ? maxK : (maxK <= 8 ? 8 : 16);
     pl.keys = r.take((size_t)keys_words * 4);
     uint64_t node_cap = 0, slot_cap = 0, small_cap = 0, n_gcol = 0;
     uint64_t kl_S = 0, kl_pi = 0, kl_delta = 0;
@@ -653,8 +654,9 @@ ForestDev Engine::forest() const {
     F.small_cap = pl.small_cap;
     F.kmax = pl.kmax;
     F.split_rank = O.split_rank;
-    // the wave path packs class counters in 16-bit fields (8-bit for 3-4 classes)
-    F.small_ncap = pl.kmax == 4 ? 256u : 65536u;
+    // the wave path packs class counters in 32/kmax-bit fields up to 4 classes
+    // (16-bit for 2, 10-bit for 3, 8-bit for 4), 16-bit fields beyond
+    F.small_ncap = pl.kmax == 4 ? 256u : (pl.kmax == 3 ? 1024u : 65536u);
     return F;
 }
 

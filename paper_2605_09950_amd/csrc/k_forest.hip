@@ -1325,6 +1325,7 @@ void launch_split_small(const ForestDev& F, int level, uint32_t first, uint32_t 
     const dim3 grid(grid_wg);
     switch (F.kmax) {
         case 2: hipLaunchKernelGGL(k_split_small<2>, grid, dim3(256), 0, st, F, level, first, count); break;
+        case 3: hipLaunchKernelGGL(k_split_small<3>, grid, dim3(256), 0, st, F, level, first, count); break;
         case 4: hipLaunchKernelGGL(k_split_small<4>, grid, dim3(256), 0, st, F, level, first, count); break;
         case 8: hipLaunchKernelGGL(k_split_small<8>, grid, dim3(256), 0, st, F, level, first, count); break;
         default: hipLaunchKernelGGL(k_split_small<16>, grid, dim3(256), 0, st, F, level, first, count); break;
@@ -1349,6 +1350,7 @@ void launch_hist_tile(const ForestDev& F, int level, uint32_t first, uint32_t co
     switch (F.kmax * 4 + F.fw) {
         case 2 * 4 + 2: hipLaunchKernelGGL((k_hist_tile<2, 2>), grid, dim3(256), lds, st, F, level, first, count); break;
         case 2 * 4 + 1: hipLaunchKernelGGL((k_hist_tile<2, 1>), grid, dim3(256), lds, st, F, level, first, count); break;
+        case 3 * 4 + 1: hipLaunchKernelGGL((k_hist_tile<3, 1>), grid, dim3(256), lds, st, F, level, first, count); break;
         case 4 * 4 + 1: hipLaunchKernelGGL((k_hist_tile<4, 1>), grid, dim3(256), lds, st, F, level, first, count); break;
         case 8 * 4 + 1: hipLaunchKernelGGL((k_hist_tile<8, 1>), grid, dim3(256), lds, st, F, level, first, count); break;
         default: hipLaunchKernelGGL((k_hist_tile<16, 1>), grid, dim3(256), lds, st, F, level, first, count); break;
@@ -1370,6 +1372,7 @@ hipError_t prepare_hist_col(int kmax, size_t lds) {
     const void* fn;
     switch (kmax) {
         case 2: fn = reinterpret_cast<const void*>(&k_hist_col<2>); break;
+        case 3: fn = reinterpret_cast<const void*>(&k_hist_col<3>); break;
         case 4: fn = reinterpret_cast<const void*>(&k_hist_col<4>); break;
         case 8: fn = reinterpret_cast<const void*>(&k_hist_col<8>); break;
         default: fn = reinterpret_cast<const void*>(&k_hist_col<16>); break;
@@ -1383,6 +1386,7 @@ void launch_hist_col(const ForestDev& F, int level, uint32_t grid_wg, int waves,
     const dim3 grid(grid_wg), block(64 * waves);
     switch (F.kmax) {
         case 2: hipLaunchKernelGGL(k_hist_col<2>, grid, block, lds, st, F, level); break;
+        case 3: hipLaunchKernelGGL(k_hist_col<3>, grid, block, lds, st, F, level); break;
         case 4: hipLaunchKernelGGL(k_hist_col<4>, grid, block, lds, st, F, level); break;
         case 8: hipLaunchKernelGGL(k_hist_col<8>, grid, block, lds, st, F, level); break;
         default: hipLaunchKernelGGL(k_hist_col<16>, grid, block, lds, st, F, level); break;
@@ -1395,6 +1399,7 @@ void launch_split_finalize(const ForestDev& F, int level, uint32_t first, uint32
     const dim3 grid(grid_wg);
     switch (F.kmax) {
         case 2: hipLaunchKernelGGL(k_split_finalize<2>, grid, dim3(256), 0, st, F, level, first, count); break;
+        case 3: hipLaunchKernelGGL(k_split_finalize<3>, grid, dim3(256), 0, st, F, level, first, count); break;
         case 4: hipLaunchKernelGGL(k_split_finalize<4>, grid, dim3(256), 0, st, F, level, first, count); break;
         case 8: hipLaunchKernelGGL(k_split_finalize<8>, grid, dim3(256), 0, st, F, level, first, count); break;
         default: hipLaunchKernelGGL(k_split_finalize<16>, grid, dim3(256), 0, st, F, level, first, count); break;

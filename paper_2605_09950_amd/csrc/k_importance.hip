@@ -498,6 +498,7 @@ void launch_kl_block(JobDev* jobs, int j, const NodeDev* nodes, const uint32_t* 
     const unsigned g_base = (rb + 3) / 4;
     switch (kmax) {
         case 2: hipLaunchKernelGGL(k_kl_base<2>, dim3(g_base), b256, 0, st, jobs, j, nodes, cls, kmax, tree0, r0, rb, S, pi); break;
+        case 3: hipLaunchKernelGGL(k_kl_base<3>, dim3(g_base), b256, 0, st, jobs, j, nodes, cls, kmax, tree0, r0, rb, S, pi); break;
         case 4: hipLaunchKernelGGL(k_kl_base<4>, dim3(g_base), b256, 0, st, jobs, j, nodes, cls, kmax, tree0, r0, rb, S, pi); break;
         case 8: hipLaunchKernelGGL(k_kl_base<8>, dim3(g_base), b256, 0, st, jobs, j, nodes, cls, kmax, tree0, r0, rb, S, pi); break;
         default: hipLaunchKernelGGL(k_kl_base<16>, dim3(g_base), b256, 0, st, jobs, j, nodes, cls, kmax, tree0, r0, rb, S, pi); break;
@@ -510,6 +511,7 @@ void launch_kl_block(JobDev* jobs, int j, const NodeDev* nodes, const uint32_t* 
     const unsigned g_red = (unsigned)(groups * (uint64_t)p_w_cap);
     switch (kmax) {
         case 2: hipLaunchKernelGGL(k_kl_reduce<2>, dim3(g_red), b256, 0, st, jobs, j, r0, rb, groups, S, delta); break;
+        case 3: hipLaunchKernelGGL(k_kl_reduce<3>, dim3(g_red), b256, 0, st, jobs, j, r0, rb, groups, S, delta); break;
         case 4: hipLaunchKernelGGL(k_kl_reduce<4>, dim3(g_red), b256, 0, st, jobs, j, r0, rb, groups, S, delta); break;
         case 8: hipLaunchKernelGGL(k_kl_reduce<8>, dim3(g_red), b256, 0, st, jobs, j, r0, rb, groups, S, delta); break;
         default: hipLaunchKernelGGL(k_kl_reduce<16>, dim3(g_red), b256, 0, st, jobs, j, r0, rb, groups, S, delta); break;
