@@ -43,7 +43,7 @@ void launch_hist_col(const ForestDev&, int, uint32_t, int, uint32_t, hipStream_t
 // k_importance.hip
 void launch_tree_totals(JobDev*, const TreeDev*, int, uint64_t*, hipStream_t);
 void launch_treeimp(JobDev*, const TreeDev*, int, const uint64_t*, int, hipStream_t);
-void launch_permut(JobDev*, const TreeDev*, const NodeDev*, int, int64_t, int, hipStream_t);
+void launch_permut(JobDev*, const TreeDev*, const NodeDev*, int, int64_t, int, int, hipStream_t);
 void launch_hits_decide(JobDev*, int, hipStream_t);
 void launch_kl_block(JobDev*, int, const NodeDev*, const uint32_t*, int, uint32_t, int, int,
                      uint32_t, uint32_t, uint64_t*, uint32_t*, unsigned long long*, int,
@@ -782,7 +782,7 @@ void Engine::enqueue_iteration() {
     }
     if (any_permut) {
         const size_t h = clock.begin(stats ? &stats->permut : nullptr, st);
-        launch_permut(djobs, dtrees, F.nodes, (int)n_trees, pl.max_n, pl.max_D, st);
+        launch_permut(djobs, dtrees, F.nodes, (int)n_trees, pl.max_n, pl.max_D, pl.max_pw, st);
         clock.end(h, st);
     }
     if (any_kl) {

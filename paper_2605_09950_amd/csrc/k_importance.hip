@@ -63,10 +63,14 @@ __global__ __launch_bounds__(256) void k_treeimp(JobDev* jobs, const TreeDev* tr
               (unsigned long long)udiv128((u128)gv << 44, (u128)tot[g]));
 }
 
-// Permut: one thread per (tree, OOB row).
+// Permut: one thread per (tree, OOB row).  With lds_cols > 0 (at least the
+// widened width of every job) the drops are summed per column in LDS and
+// each workgroup adds its nonzero sums to the importances: once most columns
+// are decided, few remain and per-row atomics would all meet on them.
 __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* trees,
-                                                const NodeDev* nodes, int max_depth) {
-    extern __shared__ uint32_t s_path[];  // [2][max_depth][256]: node, feature
+                                                const NodeDev* nodes, int max_depth,
+                                                int lds_cols) {
+    extern __shared__ uint32_t s_path[];  // [2][max_depth][256]: node, feature; [lds_cols] drops
     const uint32_t g = blockIdx.y;
     const TreeDev tr = trees[g];
     JobDev& J = jobs[tr.job];
@@ -75,6 +79,11 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
     const uint32_t m = (uint32_t)J.tstat[tr.tau * 4 + 1];
     const uint32_t j = blockIdx.x * 256u + tid;
     if (blockIdx.x * 256u >= m) return;
+    int* s_drop = reinterpret_cast<int*>(s_path + 2 * max_depth * 256);
+    if (lds_cols) {
+        for (int c = tid; c < J.p_w; c += 256) s_drop[c] = 0;
+        __syncthreads();
+    }
     const bool active = j < m;
     const uint32_t* oob = J.oob + (size_t)tr.tau * J.n;
     const uint32_t row = active ? oob[j] : 0u;
@@ -97,8 +106,7 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
     }
     const unsigned long long okm = __ballot(active && base_ok);
     if ((tid & 63) == 0 && okm) atomicAdd(&J.tstat[tr.tau * 4 + 2], (int)__popcll(okm));
-    if (!active) return;
-    for (int pi = 0; pi < len; ++pi) {
+    for (int pi = 0; active && pi < len; ++pi) {
         const uint32_t f = pf[pi * 256 + tid];
         bool dup = false;
         for (int pj = 0; pj < pi; ++pj) dup |= pf[pj * 256 + tid] == f;
@@ -119,7 +127,18 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
             }
             drop += (int)base_ok - (int)(nd.leaf_class == yv);
         }
-        if (drop) atomicAdd((unsigned long long*)&J.imp[f], (unsigned long long)(int64_t)drop);
+        if (drop) {
+            if (lds_cols)
+                atomicAdd(&s_drop[f], drop);
+            else
+                atomicAdd((unsigned long long*)&J.imp[f], (unsigned long long)(int64_t)drop);
+        }
+    }
+    if (lds_cols) {
+        __syncthreads();
+        for (int c = tid; c < J.p_w; c += 256)
+            if (s_drop[c])
+                atomicAdd((unsigned long long*)&J.imp[c], (unsigned long long)(int64_t)s_drop[c]);
     }
 }
 
@@ -484,10 +503,12 @@ void launch_treeimp(JobDev* jobs, const TreeDev* trees, int n_trees, const uint6
 }
 
 void launch_permut(JobDev* jobs, const TreeDev* trees, const NodeDev* nodes, int n_trees,
-                   int64_t max_n, int max_depth, hipStream_t st) {
-    const size_t lds = (size_t)2 * max_depth * 256 * sizeof(uint32_t);
+                   int64_t max_n, int max_depth, int max_pw, hipStream_t st) {
+    // per-column drop sums in LDS up to 8192 widened columns (32 KB)
+    const int lds_cols = max_pw <= 8192 ? max_pw : 0;
+    const size_t lds = (size_t)2 * max_depth * 256 * sizeof(uint32_t) + (size_t)lds_cols * 4;
     hipLaunchKernelGGL(k_permut, dim3((unsigned)((max_n + 255) / 256), (unsigned)n_trees),
-                       dim3(256), lds, st, jobs, trees, nodes, max_depth);
+                       dim3(256), lds, st, jobs, trees, nodes, max_depth, lds_cols);
 }
 
 // The KL importance of job j over rows [r0, r0 + rb): base, deltas, reduce.
