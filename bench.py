@@ -353,9 +353,13 @@ def main():
                       tune=tune)
         extra["exact_rank_" + unit.replace("/", "_per_")] = round(
             leg["job_iters"] / leg["seconds"], 3)
-        leg = run_gpu(jobs, pr, 1, 1, B.FORM_PLAIN, B.RANK_FP32, stats=False)
-        extra["plain_form_" + unit.replace("/", "_per_")] = round(
-            leg["job_iters"] / leg["seconds"], 4)
+        if args.workload == "scale":
+            # one launch per node: about a million launches per iteration here
+            extra["plain_form_note"] = "not run on this workload (one launch per tree node)"
+        else:
+            leg = run_gpu(jobs, pr, 1, 1, B.FORM_PLAIN, B.RANK_FP32, stats=False)
+            extra["plain_form_" + unit.replace("/", "_per_")] = round(
+                leg["job_iters"] / leg["seconds"], 4)
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": unit, "n_gpus": 1,
         "steps": main_leg["steps"], "warmup": args.warmup,
