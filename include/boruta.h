@@ -17,12 +17,19 @@
  *        Permut  -- out-of-bag accuracy drop when the column is permuted among
  *                   each tree's out-of-bag rows (Kursa's importance, Sec. 2;
  *                   permutation importance, Sec. 2.2);
+ *        Permut-KL -- Algorithm 3: divergence (KL, bits) of the forest's
+ *                   class probabilities on the full training matrix when the
+ *                   column is permuted by one row permutation shared by all
+ *                   columns, summed over the rows;
  *   4. adds a hit to each feature scoring strictly above the best shadow;
  *   5. confirms / rejects undecided features with a Bonferroni-corrected
- *      exact binomial test at level alpha.
+ *      exact binomial test at level alpha;
+ * and at the end ranks the features (Algorithm 1's final ranking; see
+ * boruta_result.rank).
  * Results are a deterministic function of (inputs, seed, n_bins, n_perm):
- * identical across the plain and batched forms, the two split-ranking modes
- * and batch composition.
+ * identical across the plain and batched forms, the two split-ranking modes,
+ * the launch tuning and batch composition (all scores are integers; hits
+ * compare integers).
  *
  * Conventions: the caller owns every buffer; the library never frees caller
  * memory.  Host pointers unless stated otherwise.  All entry points are
