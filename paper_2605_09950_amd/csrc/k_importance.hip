@@ -63,10 +63,12 @@ __global__ __launch_bounds__(256) void k_treeimp(JobDev* jobs, const TreeDev* tr
               (unsigned long long)udiv128((u128)gv << 44, (u128)tot[g]));
 }
 
-// Permut: one thread per (tree, OOB row).  With lds_cols > 0 (at least the
-// widened width of every job) the drops are summed per column in LDS and
-// each workgroup adds its nonzero sums to the importances: once most columns
-// are decided, few remain and per-row atomics would all meet on them.
+// Permut: one thread per (tree, OOB row).  When the job's widened width is
+// at most lds_cols, the drops are summed per column in LDS and each
+// workgroup adds its nonzero sums to the importances: once most columns are
+// decided, few remain and per-row atomics would all meet on them (with many
+// columns the per-row atomics are spread out and cheaper than a flush per
+// workgroup).
 __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* trees,
                                                 const NodeDev* nodes, int max_depth,
                                                 int lds_cols) {
@@ -80,7 +82,8 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
     const uint32_t j = blockIdx.x * 256u + tid;
     if (blockIdx.x * 256u >= m) return;
     int* s_drop = reinterpret_cast<int*>(s_path + 2 * max_depth * 256);
-    if (lds_cols) {
+    const bool lds = J.p_w <= lds_cols;  // uniform: one tree per workgroup
+    if (lds) {
         for (int c = tid; c < J.p_w; c += 256) s_drop[c] = 0;
         __syncthreads();
     }
@@ -128,13 +131,13 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
             drop += (int)base_ok - (int)(nd.leaf_class == yv);
         }
         if (drop) {
-            if (lds_cols)
+            if (lds)
                 atomicAdd(&s_drop[f], drop);
             else
                 atomicAdd((unsigned long long*)&J.imp[f], (unsigned long long)(int64_t)drop);
         }
     }
-    if (lds_cols) {
+    if (lds) {
         __syncthreads();
         for (int c = tid; c < J.p_w; c += 256)
             if (s_drop[c])
@@ -504,8 +507,8 @@ void launch_treeimp(JobDev* jobs, const TreeDev* trees, int n_trees, const uint6
 
 void launch_permut(JobDev* jobs, const TreeDev* trees, const NodeDev* nodes, int n_trees,
                    int64_t max_n, int max_depth, int max_pw, hipStream_t st) {
-    // per-column drop sums in LDS up to 8192 widened columns (32 KB)
-    const int lds_cols = max_pw <= 8192 ? max_pw : 0;
+    // per-column drop sums in LDS for jobs of at most 1024 widened columns
+    const int lds_cols = max_pw < 1024 ? max_pw : 1024;
     const size_t lds = (size_t)2 * max_depth * 256 * sizeof(uint32_t) + (size_t)lds_cols * 4;
     hipLaunchKernelGGL(k_permut, dim3((unsigned)((max_n + 255) / 256), (unsigned)n_trees),
                        dim3(256), lds, st, jobs, trees, nodes, max_depth, lds_cols);
