@@ -220,12 +220,12 @@ def cpu_baseline(name, jobs, pr):
     from oracle import oracle as O
     cores = os.cpu_count() or 1
 
-    def step(jd, t, st, ht, trees=None):
+    def step(jd, t, st, ht, trees=None, threads=cores):
         return O.boruta_step(jd["X"], jd["y"], jd["n_classes"], jd["n_trees"],
                              jd["max_depth"], t, st, ht, mtry=jd["mtry"],
                              importance_mode=jd["importance_mode"], alpha=jd["alpha"],
                              seed=jd["seed"], n_bins=pr["n_bins"], n_perm=pr["n_perm"],
-                             tree_subset=trees, n_threads=cores, trace=False)
+                             tree_subset=trees, n_threads=threads, trace=False)
 
     def bin_time(jd):
         t0 = time.perf_counter()
@@ -242,11 +242,19 @@ def cpu_baseline(name, jobs, pr):
             r = step(jd, it + 1, st, ht)
             spent += time.perf_counter() - t0 - t_bin
             st, ht, it = r["state"], r["hits"], it + 1
+        # one core: the first trees of iteration 1 on one thread, scaled to the forest
+        k = min(jd["n_trees"], 8)
+        t0 = time.perf_counter()
+        step(jd, 1, np.zeros(p, np.int8), np.zeros(p, np.int32), list(range(k)), threads=1)
+        one = time.perf_counter() - t0 - t_bin
         return {"value": round(it / spent, 5), "unit": "iters/s", "cores": cores,
                 "kind": "oracle",
                 "sample": f"iterations 1..{it} in sequence (all {jd['n_trees']} trees each) on "
                           f"{cores} threads: {spent:.2f}s; the once-per-job binning "
-                          f"({t_bin:.2f}s per call) is left out"}
+                          f"({t_bin:.2f}s per call) is left out",
+                "one_core": {"value": round(k / (one * jd["n_trees"]), 5), "unit": "iters/s",
+                             "sample": f"trees 0..{k - 1} of iteration 1 on one thread in "
+                                       f"{one:.2f}s, scaled by {jd['n_trees']}/{k}"}}
     if name in ("omics", "scale"):
         jd = jobs[0]
         p = jd["X"].shape[1]
