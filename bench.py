@@ -185,7 +185,7 @@ def measured_traffic(workload_name, kernel):
     with open(path) as f:
         for line in f:
             if ":" in line and line.strip().startswith(("traffic_bytes_per_launch",
-                                                        "kernel_source_sha256")):
+                                                        "kernel_code_sha256")):
                 k, v = line.strip().split(":", 1)
                 fields[k.strip()] = v.strip()
     if fields.get("kernel_code_sha256") != kernel_code_digest() or \
