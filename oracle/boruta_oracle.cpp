@@ -449,7 +449,8 @@ void forest_predict(const std::vector<std::vector<TNode>*>& forest, const Data& 
 // against those of the unpermuted matrix (Algorithm 3, one predict call
 // per column).
 void forest_divergence(const std::vector<std::vector<TNode>*>& forest, const Data& d,
-                       uint64_t seed, uint32_t t, int n_threads, int64_t* imp) {
+                       uint64_t seed, uint32_t t, int n_threads, int64_t* imp,
+                       const std::vector<int32_t>& only) {
     const int K = d.K;
     std::vector<uint64_t> base((size_t)d.n * K);
     std::vector<uint32_t> pi((size_t)d.n);
@@ -457,12 +458,18 @@ void forest_divergence(const std::vector<std::vector<TNode>*>& forest, const Dat
         forest_predict(forest, d, (uint32_t)r, -1, 0, &base[(size_t)r * K]);
         pi[r] = (uint32_t)keyed_perm(seed, kStreamFlush, t, 0u, 0u, 0u, (uint64_t)d.n, (uint64_t)r);
     }
+    // the columns to score: all, or (checks at full size) the listed ones
+    std::vector<int32_t> cols;
+    for (int32_t f = 0; f < d.p_w; ++f)
+        if (only.empty() || std::find(only.begin(), only.end(), f) != only.end()) cols.push_back(f);
     if (n_threads <= 0) n_threads = (int)std::max(1u, std::thread::hardware_concurrency());
+    const int64_t nc = (int64_t)cols.size();
     std::vector<std::thread> pool;
-    for (int w = 0; w < std::min<int64_t>(n_threads, d.p_w); ++w)
+    for (int w = 0; w < std::min<int64_t>(n_threads, nc); ++w)
         pool.emplace_back([&, w] {
             std::vector<uint64_t> q(K);
-            for (int64_t f = w; f < d.p_w; f += n_threads) {
+            for (int64_t ci = w; ci < nc; ci += n_threads) {
+                const int32_t f = cols[ci];
                 int64_t acc = 0;
                 for (int64_t r = 0; r < d.n; ++r) {
                     forest_predict(forest, d, (uint32_t)r, (int32_t)f, d.col[f][pi[r]], q.data());
@@ -589,6 +596,7 @@ struct Run {
     std::vector<uint8_t> orig;  // [p][n]
     int n_threads;
     bool naive;
+    std::vector<int32_t> kl_cols;  // mode 2: score only these columns (empty: all)
 };
 
 int validate(const float* X, const int32_t* y, int64_t n, int64_t p, int K, int T, int D,
@@ -705,7 +713,8 @@ void iteration(const Run& run, int t, int8_t* state, int32_t* hits,
             // the mean divergence per row in bits
             std::vector<std::vector<TNode>*> forest;
             for (TreeResult& r : res) forest.push_back(&r.nodes);
-            forest_divergence(forest, d, run.seed, (uint32_t)t, run.n_threads, imp.data());
+            forest_divergence(forest, d, run.seed, (uint32_t)t, run.n_threads, imp.data(),
+                              run.kl_cols);
             denom = (double)d.n * 4294967296.0;
         } else {
             int64_t oob_total = 0;
@@ -979,11 +988,26 @@ int oracle_boruta_step(const float* X, const int32_t* y, int64_t n, int64_t p, i
                        int8_t* state, int32_t* hits, const int32_t* tree_subset, int32_t n_subset,
                        int32_t n_threads, int32_t permut_naive, double* imp_row_out,
                        double* shadow_max_out, oracle_trace_fn trace, void* trace_user) {
+    return oracle_boruta_step_cols(X, y, n, p, n_classes, n_trees, max_depth, mtry,
+                                   importance_mode, alpha, seed, n_bins, n_perm, t, state, hits,
+                                   tree_subset, n_subset, nullptr, 0, n_threads, permut_naive,
+                                   imp_row_out, shadow_max_out, trace, trace_user);
+}
+
+int oracle_boruta_step_cols(const float* X, const int32_t* y, int64_t n, int64_t p,
+                            int32_t n_classes, int32_t n_trees, int32_t max_depth, int32_t mtry,
+                            int32_t importance_mode, double alpha, uint64_t seed, int32_t n_bins,
+                            int32_t n_perm, int32_t t, int8_t* state, int32_t* hits,
+                            const int32_t* tree_subset, int32_t n_subset, const int32_t* kl_cols,
+                            int32_t n_kl_cols, int32_t n_threads, int32_t permut_naive,
+                            double* imp_row_out, double* shadow_max_out, oracle_trace_fn trace,
+                            void* trace_user) {
     if (!state || !hits || t < 1 || t > 1000) return -1;
     Run run;
     const int rc = setup(run, X, y, n, p, n_classes, n_trees, max_depth, mtry, importance_mode,
                          1000, alpha, seed, n_bins, n_perm, n_threads, permut_naive);
     if (rc) return rc;
+    if (kl_cols) run.kl_cols.assign(kl_cols, kl_cols + n_kl_cols);
     std::vector<int32_t> trees;
     if (tree_subset) {
         for (int i = 0; i < n_subset; ++i) {

@@ -130,6 +130,18 @@ int oracle_boruta_step(const float* X, const int32_t* y, int64_t n, int64_t p,
                        double* imp_row_out, double* shadow_max_out,
                        oracle_trace_fn trace, void* trace_user);
 
+/* oracle_boruta_step with, for importance mode 2, only the listed widened
+ * columns scored (the others read 0; hits and decisions are then
+ * meaningless): checks of sampled columns at full size. */
+int oracle_boruta_step_cols(const float* X, const int32_t* y, int64_t n, int64_t p,
+                            int32_t n_classes, int32_t n_trees, int32_t max_depth, int32_t mtry,
+                            int32_t importance_mode, double alpha, uint64_t seed, int32_t n_bins,
+                            int32_t n_perm, int32_t t, int8_t* state, int32_t* hits,
+                            const int32_t* tree_subset, int32_t n_subset, const int32_t* kl_cols,
+                            int32_t n_kl_cols, int32_t n_threads, int32_t permut_naive,
+                            double* imp_row_out, double* shadow_max_out, oracle_trace_fn trace,
+                            void* trace_user);
+
 #ifdef __cplusplus
 }
 #endif

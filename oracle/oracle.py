@@ -83,6 +83,10 @@ def lib():
         L.oracle_boruta_step.argtypes = [P, P, i64, i64, i32, i32, i32, i32, i32, f64, u64, i32,
                                          i32, i32, P, P, P, i32, i32, i32, P, P, TRACE_FN, P]
         L.oracle_boruta_step.restype = i32
+        L.oracle_boruta_step_cols.argtypes = [P, P, i64, i64, i32, i32, i32, i32, i32, f64, u64,
+                                              i32, i32, i32, P, P, P, i32, P, i32, i32, i32, P, P,
+                                              TRACE_FN, P]
+        L.oracle_boruta_step_cols.restype = i32
         _lib = L
     return _lib
 
@@ -219,9 +223,10 @@ def rank(decision, imp_history, n_iter):
 
 def boruta_step(X, y, n_classes, n_trees, max_depth, t, state, hits, mtry=0,
                 importance_mode=0, alpha=0.05, seed=0, n_bins=256, n_perm=1, tree_subset=None,
-                n_threads=0, permut_naive=False, trace=True):
+                n_threads=0, permut_naive=False, trace=True, kl_cols=None):
     """Iteration t of Algorithm 1 from the given (state, hits); returns the
-    updated vectors, the importance row and the trace record."""
+    updated vectors, the importance row and the trace record.  kl_cols (mode
+    2): score only these widened columns (the others read 0)."""
     X = np.ascontiguousarray(X, dtype=np.float32)
     y = np.ascontiguousarray(y, dtype=np.int32)
     n, p = X.shape
@@ -235,10 +240,12 @@ def boruta_step(X, y, n_classes, n_trees, max_depth, t, state, hits, mtry=0,
         sub = np.zeros(1, np.int32)  # non-null pointer, zero trees: widening only
     traces = []
     cb = _trace_collector(traces) if trace else TRACE_FN()
-    rc = lib().oracle_boruta_step(_ptr(X), _ptr(y), n, p, n_classes, n_trees, max_depth, mtry,
-                                  importance_mode, alpha, seed, n_bins, n_perm, t, _ptr(st),
-                                  _ptr(ht), _ptr(sub), n_sub, n_threads,
-                                  int(permut_naive), _ptr(row), _ptr(smax), cb, None)
+    kc = None if kl_cols is None else np.ascontiguousarray(kl_cols, dtype=np.int32)
+    rc = lib().oracle_boruta_step_cols(_ptr(X), _ptr(y), n, p, n_classes, n_trees, max_depth,
+                                       mtry, importance_mode, alpha, seed, n_bins, n_perm, t,
+                                       _ptr(st), _ptr(ht), _ptr(sub), n_sub, _ptr(kc),
+                                       0 if kc is None else len(kc), n_threads,
+                                       int(permut_naive), _ptr(row), _ptr(smax), cb, None)
     if rc:
         raise ValueError(f"oracle_boruta_step failed: {rc}")
     return {"state": st, "hits": ht, "imp_row": row, "shadow_max": float(smax[0]),

@@ -3,7 +3,9 @@ configuration bench.py times (a session over device-resident inputs, a
 caller-provided workspace, iterations replayed from the captured graph).
 
   * MADELON-like (n=10,000, p=500, 200 trees of depth 12): the whole first
-    iteration, every tree, both importance modes, against the oracle run live.
+    iteration, every tree, both out-of-bag importance modes, against the
+    oracle run live; with the divergence importance (Algorithm 3), every tree
+    and 24 sampled columns' scores.
   * Many-job batch (64 jobs of uneven n, p and class count): the first
     iteration of sampled jobs, every tree, against the oracle run live.
   * Omics-shaped (n=2,000, p=20,000) and mixed-type (n=100,000, p=2,000):
@@ -59,13 +61,13 @@ def job_of(c, mode=None):
                 max_iter=pr["max_iter"], alpha=pr["alpha"], seed=c["seed"])
 
 
-def oracle_first_iteration(jd, n_bins, n_perm=1, trees=None):
+def oracle_first_iteration(jd, n_bins, n_perm=1, trees=None, kl_cols=None):
     p = jd["X"].shape[1]
     return O.boruta_step(jd["X"], jd["y"], jd["n_classes"], jd["n_trees"], jd["max_depth"], 1,
                          np.zeros(p, np.int8), np.zeros(p, np.int32), mtry=jd["mtry"],
                          importance_mode=jd["importance_mode"], alpha=jd["alpha"],
                          seed=jd["seed"], n_bins=n_bins, n_perm=n_perm, tree_subset=trees,
-                         n_threads=min(16, os.cpu_count() or 1), trace=True)
+                         n_threads=min(16, os.cpu_count() or 1), trace=True, kl_cols=kl_cols)
 
 
 # the automatic choice keeps these workloads node-major; the column-major path
@@ -83,6 +85,22 @@ def test_madelon_like_first_iteration_all_trees(mode, tune):
     assert_same_trace(g[0], o["trace"])
     assert np.array_equal(g[0]["hits"], o["hits"])
     assert np.array_equal(g[0]["state"], o["state"])
+
+
+def test_madelon_like_kl_sampled_columns():
+    # Algorithm 3 at full size: every tree of the first iteration, and the
+    # divergence scores of 24 sampled widened columns (originals and shadows)
+    c = synth.config(1)
+    pr = c["params"]
+    jd = job_of(c, B.PERMUT_KL)
+    print("MADELON-like n=10000 p=500 T=200 D=12 mode=KL, 24 sampled columns", flush=True)
+    g = gpu_first_iteration([jd], pr["n_bins"])[0]
+    cols = sorted(set(np.linspace(0, g["p_w"] - 1, 24).astype(int).tolist()))
+    o = oracle_first_iteration(jd, pr["n_bins"], kl_cols=cols)["trace"]
+    assert np.array_equal(g["nodes"], o["nodes"])
+    assert np.array_equal(g["tree_stats"], o["tree_stats"])
+    assert np.array_equal(g["imp_int"][cols], o["imp_int"][cols])
+    assert (g["imp_int"][cols] > 0).sum() >= 4  # used columns carry nonzero scores
 
 
 @pytest.mark.parametrize("tune", [None, dict(col_level=5)], ids=["auto", "column"])
