@@ -982,6 +982,39 @@ void oracle_rank(const int8_t* decision, const double* imp_history, int64_t p, i
     }
 }
 
+// The paper's multi-seed protocol (Sec. 3: runs with different seeds, the
+// median importance as the basis of the selection).  Reading: per run, a
+// feature's importance is the mean of its finite history entries (summed in
+// iteration order); the median over runs (the mean of the two middle values
+// for an even count); the selection is the lower median of the runs'
+// decisions (confirmed in more than half of the runs -> confirmed; rejected
+// in at least half -> rejected; else tentative).
+void oracle_seed_median(const int8_t* decisions, const double* histories, const int32_t* n_iters,
+                        int64_t p, int32_t max_iter, int32_t n_runs, double* median_out,
+                        int8_t* decision_out) {
+    std::vector<double> v(n_runs);
+    std::vector<int8_t> dv(n_runs);
+    for (int64_t j = 0; j < p; ++j) {
+        for (int32_t r = 0; r < n_runs; ++r) {
+            const double* h = histories + (size_t)r * max_iter * p;
+            double sum = 0.0;
+            int c = 0;
+            for (int32_t t = 0; t < n_iters[r]; ++t) {
+                const double x = h[(size_t)t * p + j];
+                if (std::isnan(x)) continue;
+                sum += x;
+                ++c;
+            }
+            v[r] = c ? sum / c : 0.0;
+            dv[r] = decisions[(size_t)r * p + j];
+        }
+        std::sort(v.begin(), v.end());
+        std::sort(dv.begin(), dv.end());
+        median_out[j] = n_runs % 2 ? v[n_runs / 2] : (v[n_runs / 2 - 1] + v[n_runs / 2]) / 2.0;
+        decision_out[j] = dv[(n_runs - 1) / 2];
+    }
+}
+
 int oracle_boruta_step(const float* X, const int32_t* y, int64_t n, int64_t p, int32_t n_classes,
                        int32_t n_trees, int32_t max_depth, int32_t mtry, int32_t importance_mode,
                        double alpha, uint64_t seed, int32_t n_bins, int32_t n_perm, int32_t t,

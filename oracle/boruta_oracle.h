@@ -130,6 +130,14 @@ int oracle_boruta_step(const float* X, const int32_t* y, int64_t n, int64_t p,
                        double* imp_row_out, double* shadow_max_out,
                        oracle_trace_fn trace, void* trace_user);
 
+/* Multi-seed aggregate of n_runs finished runs of one problem: decisions
+ * [n_runs][p], histories [n_runs][max_iter][p], n_iters [n_runs]; per
+ * feature the median over runs of its mean history importance and the lower
+ * median of its decisions. */
+void oracle_seed_median(const int8_t* decisions, const double* histories, const int32_t* n_iters,
+                        int64_t p, int32_t max_iter, int32_t n_runs, double* median_out,
+                        int8_t* decision_out);
+
 /* oracle_boruta_step with, for importance mode 2, only the listed widened
  * columns scored (the others read 0; hits and decisions are then
  * meaningless): checks of sampled columns at full size. */

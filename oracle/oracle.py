@@ -66,6 +66,8 @@ def lib():
         L.oracle_log2_fix32.restype = u64
         L.oracle_kl_fix32.argtypes = [P, P, i32]
         L.oracle_kl_fix32.restype = i64
+        L.oracle_seed_median.argtypes = [P, P, P, i64, i32, i32, P, P]
+        L.oracle_seed_median.restype = None
         L.oracle_rank.argtypes = [P, P, i64, i32, P]
         L.oracle_rank.restype = None
         L.oracle_bootstrap.argtypes = [u64, u32, u32, i64, P]
@@ -211,6 +213,21 @@ def boruta_fit(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=0, m
     lib().oracle_rank(_ptr(dec), _ptr(hist_c), p, n_iter.value, _ptr(rank))
     return {"decision": dec, "imp_history": hist, "hits": hits, "shadow_max": smax,
             "n_iter": n_iter.value, "traces": traces, "rc": rc, "rank": rank}
+
+
+def seed_median(runs):
+    """Multi-seed aggregate of finished runs (dicts of boruta_fit): per feature
+    the median of the runs' mean history importances and the lower median of
+    their decisions."""
+    dec = np.ascontiguousarray(np.stack([r["decision"] for r in runs]), dtype=np.int8)
+    hist = np.ascontiguousarray(np.stack([r["imp_history"] for r in runs]), dtype=np.float64)
+    n_it = np.ascontiguousarray([r["n_iter"] for r in runs], dtype=np.int32)
+    n_runs, max_iter, p = hist.shape
+    med = np.zeros(p, np.float64)
+    out = np.zeros(p, np.int8)
+    lib().oracle_seed_median(_ptr(dec), _ptr(hist), _ptr(n_it), p, max_iter, n_runs, _ptr(med),
+                             _ptr(out))
+    return med, out
 
 
 def rank(decision, imp_history, n_iter):

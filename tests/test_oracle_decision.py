@@ -95,3 +95,36 @@ def test_final_ranking_properties_on_a_run():
             if m[a] > m[b] + 1e-12:
                 assert r[a] < r[b]
     assert r[rej].min() == 3
+
+
+def test_seed_median_hand_computed_and_library_median():
+    import statistics
+    nan = np.nan
+    # two features, three runs of up to three iterations
+    runs = [dict(decision=np.array([1, -1], np.int8), n_iter=3,
+                 imp_history=np.array([[0.5, 0.1], [0.7, nan], [0.6, nan]])),
+            dict(decision=np.array([1, 0], np.int8), n_iter=2,
+                 imp_history=np.array([[0.2, 0.3], [0.4, 0.1], [9.0, 9.0]])),
+            dict(decision=np.array([0, -1], np.int8), n_iter=1,
+                 imp_history=np.array([[0.9, 0.05], [9.0, 9.0], [9.0, 9.0]]))]
+    med, dec = O.seed_median(runs)
+    # feature 0: means 0.6, 0.3, 0.9 -> 0.6; feature 1: 0.1, 0.2, 0.05 -> 0.1
+    assert med[0] == (0.5 + 0.7 + 0.6) / 3 and med[1] == 0.1
+    assert list(dec) == [1, -1]
+    # even count: mean of the middle pair; decisions: lower median
+    med2, dec2 = O.seed_median(runs[:2])
+    assert med2[0] == ((0.5 + 0.7 + 0.6) / 3 + (0.2 + 0.4) / 2) / 2
+    assert list(dec2) == [1, -1]
+    rng = np.random.default_rng(3)
+    runs = []
+    for r in range(7):
+        h = rng.random((5, 4))
+        n_it = int(rng.integers(1, 6))
+        runs.append(dict(decision=rng.integers(-1, 2, 4).astype(np.int8), n_iter=n_it,
+                         imp_history=h))
+    med, dec = O.seed_median(runs)
+    for j in range(4):
+        means = [sum(float(r["imp_history"][t][j]) for t in range(r["n_iter"])) / r["n_iter"]
+                 for r in runs]
+        assert med[j] == statistics.median(means)
+        assert dec[j] == statistics.median_low([int(r["decision"][j]) for r in runs])
