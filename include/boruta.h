@@ -226,6 +226,29 @@ typedef struct {
 int boruta_fit_batch(const boruta_job* jobs, int32_t n_jobs, const boruta_options* opt,
                      boruta_result* results);
 
+/* The repeated-seed protocol of the experiments (Results and Discussion,
+ * Synthetic experiments and Experiments on Public Datasets: every method is
+ * run with several random seeds and the median importance decides): one
+ * problem run once per entry of seeds[n_seeds] (1..64 seeds), all runs
+ * advanced together as one batch, each equal to a boruta_fit with that seed.
+ * On the device, per feature j:
+ *   median_importance_out[j] = median over the runs of the mean of the run's
+ *     non-NaN history entries for j (0 if it has none); with an even count,
+ *     the mean of the two middle values;
+ *   decision_out[j] = the lower median of the runs' decisions (-1 < 0 < 1),
+ *     i.e. confirmed only if more than half of the runs confirm it, rejected
+ *     if at least half reject it.
+ * Both are host arrays of p entries.  results (nullable) is an array of
+ * n_seeds per-run outputs as for boruta_fit_batch; where its decision and
+ * imp_history are set they receive the runs' own results.  Returns
+ * BORUTA_E_INVALID_ARG for a missing output or a seed count out of range, or
+ * the first run's error. */
+int boruta_fit_seeds(const float* X, const int32_t* y, int64_t n, int64_t p, int32_t n_classes,
+                     int32_t n_trees, int32_t max_depth, int32_t mtry, int32_t importance_mode,
+                     int32_t max_iter, double alpha, const uint64_t* seeds, int32_t n_seeds,
+                     const boruta_options* opt, double* median_importance_out,
+                     int8_t* decision_out, boruta_result* results);
+
 /* Device bytes a call with these jobs needs (for boruta_fit_device). */
 int boruta_workspace_size(const boruta_job* jobs, int32_t n_jobs, const boruta_options* opt,
                           size_t* bytes);

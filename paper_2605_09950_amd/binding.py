@@ -85,6 +85,7 @@ class Result(ctypes.Structure):
 
 
 EXPORTS = ["boruta_default_options", "boruta_fit", "boruta_fit_ex", "boruta_fit_batch",
+           "boruta_fit_seeds",
            "boruta_workspace_size", "boruta_fit_device", "boruta_session_create",
            "boruta_session_step", "boruta_session_result", "boruta_session_resume",
            "boruta_session_destroy", "boruta_probe_copy", "boruta_last_error"]
@@ -120,6 +121,10 @@ def lib():
         L.boruta_fit_batch.argtypes = [ctypes.POINTER(Job), i32, ctypes.POINTER(Options),
                                        ctypes.POINTER(Result)]
         L.boruta_fit_batch.restype = ctypes.c_int
+        L.boruta_fit_seeds.argtypes = [P, P, i64, i64, i32, i32, i32, i32, i32, i32, f64, P,
+                                       i32, ctypes.POINTER(Options), P, P,
+                                       ctypes.POINTER(Result)]
+        L.boruta_fit_seeds.restype = ctypes.c_int
         L.boruta_workspace_size.argtypes = [ctypes.POINTER(Job), i32, ctypes.POINTER(Options),
                                             ctypes.POINTER(ctypes.c_size_t)]
         L.boruta_workspace_size.restype = ctypes.c_int
@@ -297,6 +302,42 @@ def boruta_fit_batch(jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM
         o["n_iter"], o["status"] = res[i].n_iter, res[i].status
     _check(rc)
     return {"results": outs, "traces": keep["iters"], "stats": keep.get("stats")}
+
+
+def boruta_fit_seeds(X, y, n_classes, n_trees, max_depth, seeds, mtry=0,
+                     importance_mode=TREEIMP, max_iter=20, alpha=0.05, n_bins=256, n_perm=1,
+                     split_rank=RANK_FP32, form=FORM_BATCHED, tune=None, runs=True):
+    """One problem run once per seed (as one batch) and the multi-seed aggregate:
+    returns {"median_importance", "decision", "runs"} where runs (if asked for)
+    holds each seed's own results as boruta_fit_batch does."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    n, p = X.shape
+    sd = np.ascontiguousarray(seeds, dtype=np.uint64)
+    med = np.zeros(p, np.float64)
+    dec = np.zeros(p, np.int8)
+    res, outs = None, []
+    if runs:
+        res = (Result * len(sd))()
+        for i in range(len(sd)):
+            o = {"decision": np.zeros(p, np.int8),
+                 "imp_history": np.full((max_iter, p), np.nan),
+                 "hits": np.zeros(p, np.int32), "shadow_max": np.full(max_iter, np.nan),
+                 "rank": np.zeros(p, np.int32)}
+            res[i].decision = o["decision"].ctypes.data
+            res[i].imp_history = o["imp_history"].ctypes.data
+            res[i].hits = o["hits"].ctypes.data
+            res[i].shadow_max = o["shadow_max"].ctypes.data
+            res[i].rank = o["rank"].ctypes.data
+            outs.append(o)
+    opt, _ = make_options(n_bins, n_perm, split_rank, form, tune=tune)
+    rc = lib().boruta_fit_seeds(_ptr(X), _ptr(y), n, p, n_classes, n_trees, max_depth, mtry,
+                                importance_mode, max_iter, alpha, _ptr(sd), len(sd),
+                                ctypes.byref(opt), _ptr(med), _ptr(dec), res)
+    for i, o in enumerate(outs):
+        o["n_iter"], o["status"] = res[i].n_iter, res[i].status
+    _check(rc)
+    return {"median_importance": med, "decision": dec, "runs": outs}
 
 
 def boruta_workspace_size(jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32,

@@ -49,6 +49,7 @@ void launch_kl_block(JobDev*, int, const NodeDev*, const uint32_t*, int, uint32_
                      uint32_t, uint32_t, uint64_t*, uint32_t*, unsigned long long*, int,
                      hipStream_t);
 void launch_copy(void*, const void*, size_t, hipStream_t);
+void launch_seed_median(const JobDev*, int, int64_t, double*, int8_t*, hipStream_t);
 void launch_rank(const int8_t*, const double*, int64_t, int, int, double*, int32_t*, hipStream_t);
 
 namespace {
@@ -192,6 +193,7 @@ struct Plan {
     size_t keys, jobs, trees, tree_base, flags, nodes, cls, ngain, small0, small1, cand, cand_cl,
         feat, fcol, srec, kinds, chunk_sums, slot0, slot1, ctrs, alg, tot;
     size_t fcnt = 0, fpos = 0, fitems = 0, units = 0, gcolq = 0;
+    size_t seed_med = 0, seed_dec = 0;  // multi-seed aggregate [p]
     size_t kl_S = 0, kl_pi = 0, kl_delta = 0;  // KL importance buffers (shared by its jobs)
     uint32_t node_cap = 0, slot_cap = 0, small_cap = 0;
     int kmax = 4, max_sha = 1, max_pw = 1, max_D = 1, T_total = 0, mtry_cap = 1,
@@ -327,6 +329,12 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     pl.ctrs = r.take((size_t)(pl.max_D + 2) * sizeof(LevelCtr));
     pl.alg = r.take(3 * kAlgWords * 8);
     pl.tot = r.take((size_t)pl.T_total * 8);
+    {
+        int64_t pmax = 1;
+        for (const Spec& sp : specs) pmax = std::max<int64_t>(pmax, sp.p);
+        pl.seed_med = r.take((size_t)pmax * 8);
+        pl.seed_dec = r.take((size_t)pmax);
+    }
     if (kl_delta) {
         pl.kl_S = r.take(kl_S);
         pl.kl_pi = r.take(kl_pi);
@@ -458,6 +466,13 @@ public:
     void resume(int j, int t, const int8_t* state, const int32_t* hits);
     void flush_stats();
     const JobDev& job(int j) const { return hj[j]; }
+    // Multi-seed aggregate over all jobs (runs of one problem with p features).
+    void seed_median(int64_t p, double* med, int8_t* dec) {
+        launch_seed_median(at<JobDev>(pl.jobs), (int)S.size(), p, at<double>(pl.seed_med),
+                           at<int8_t>(pl.seed_dec), st);
+        d2h(med, at<double>(pl.seed_med), (size_t)p * 8);
+        d2h(dec, at<int8_t>(pl.seed_dec), (size_t)p);
+    }
 
 private:
     void iteration(const std::vector<int>& live);
@@ -1146,6 +1161,67 @@ int boruta_fit_ex(const float* X, const int32_t* y, int64_t n, int64_t p, int32_
     std::vector<int> status(1, BORUTA_OK);
     const int rc = run_jobs(specs, opt, outs, status, false, nullptr, 0, nullptr);
     return finish_single(rc, outs, n_iter_out);
+}
+
+int boruta_fit_seeds(const float* X, const int32_t* y, int64_t n, int64_t p, int32_t n_classes,
+                     int32_t n_trees, int32_t max_depth, int32_t mtry, int32_t importance_mode,
+                     int32_t max_iter, double alpha, const uint64_t* seeds, int32_t n_seeds,
+                     const boruta_options* opt, double* median_importance_out,
+                     int8_t* decision_out, boruta_result* results) {
+    g_err.clear();
+    if (!seeds || n_seeds < 1 || n_seeds > 64 || !median_importance_out || !decision_out) {
+        g_err = "seeds (1..64 of them), median_importance_out and decision_out are required";
+        return BORUTA_E_INVALID_ARG;
+    }
+    if (p < 1) {
+        g_err = "p must be positive";
+        return BORUTA_E_INVALID_ARG;
+    }
+    std::vector<Spec> specs;
+    for (int i = 0; i < n_seeds; ++i)
+        specs.push_back(spec_from(X, y, n, p, n_classes, n_trees, max_depth, mtry,
+                                  importance_mode, max_iter, alpha, seeds[i]));
+    // per-run outputs: the caller's, or a decision scratch (the aggregate reads
+    // the histories on the device)
+    std::vector<std::vector<int8_t>> dec_s((size_t)n_seeds);
+    std::vector<Out> outs(n_seeds);
+    for (int i = 0; i < n_seeds; ++i) {
+        if (results && results[i].decision && results[i].imp_history) {
+            outs[i].decision = results[i].decision;
+            outs[i].hist = results[i].imp_history;
+            outs[i].hits = results[i].hits;
+            outs[i].smax = results[i].shadow_max;
+            outs[i].rank = results[i].rank;
+        } else {
+            dec_s[i].resize((size_t)p);
+            outs[i].decision = dec_s[i].data();
+            outs[i].hist = nullptr;
+        }
+    }
+    std::vector<int> status(n_seeds, BORUTA_OK);
+    try {
+        std::unique_ptr<Context> c = prepare(specs, opt, false, nullptr, 0, nullptr);
+        c->eng->run(outs, status);
+        for (int s2 : status)
+            if (s2 != BORUTA_OK) {
+                g_err = "the problem failed validation";
+                return s2;
+            }
+        c->eng->seed_median(p, median_importance_out, decision_out);
+        HIPC(hipStreamSynchronize(c->st));
+        if (results)
+            for (int i = 0; i < n_seeds; ++i) {
+                results[i].n_iter = outs[i].n_iter;
+                results[i].status = BORUTA_OK;
+            }
+        return BORUTA_OK;
+    } catch (const Error& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return BORUTA_E_DEVICE;
+    }
 }
 
 int boruta_fit(const float* X, const int32_t* y, int64_t n, int64_t p, int32_t n_classes,

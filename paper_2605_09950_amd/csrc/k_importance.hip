@@ -487,6 +487,45 @@ __global__ __launch_bounds__(256) void k_rank_count(const int8_t* state, const d
     if (j < p) rank[j] = sj == 1 ? 1 : (sj == 0 ? 2 : 3 + above);
 }
 
+// Multi-seed aggregate over the n_jobs runs of one problem (same p): one
+// thread per feature; per run the mean of the feature's finite history
+// entries (summed in iteration order), then the median over runs (mean of
+// the middle pair for an even count) and the lower median of the decisions.
+__global__ __launch_bounds__(256) void k_seed_median(const JobDev* jobs, int n_jobs, int64_t p,
+                                                     double* med, int8_t* dec) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= p) return;
+    double v[64];
+    int dv[64];
+    for (int r = 0; r < n_jobs; ++r) {
+        const JobDev& J = jobs[r];
+        double s = 0.0;
+        int c = 0;
+        for (int t = 0; t < J.t; ++t) {
+            const double x = J.hist[(size_t)t * p + j];
+            if (x != x) continue;  // NaN: rejected before iteration t + 1
+            s += x;
+            ++c;
+        }
+        const double m = c ? s / c : 0.0;
+        const int d = J.state[j];
+        int i = r;  // insertion into the sorted prefixes
+        while (i > 0 && v[i - 1] > m) {
+            v[i] = v[i - 1];
+            --i;
+        }
+        v[i] = m;
+        i = r;
+        while (i > 0 && dv[i - 1] > d) {
+            dv[i] = dv[i - 1];
+            --i;
+        }
+        dv[i] = d;
+    }
+    med[j] = n_jobs % 2 ? v[n_jobs / 2] : (v[n_jobs / 2 - 1] + v[n_jobs / 2]) / 2.0;
+    dec[j] = (int8_t)dv[(n_jobs - 1) / 2];
+}
+
 // Streaming copy used to calibrate hardware byte counters.
 __global__ void k_copy(uint4* dst, const uint4* src, size_t n16) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -551,6 +590,12 @@ void launch_rank(const int8_t* state, const double* hist, int64_t p, int t0, int
     const unsigned g = (unsigned)((p + 255) / 256);
     hipLaunchKernelGGL(k_rank_mean, dim3(g), dim3(256), 0, st, state, hist, p, t0, t1, mean);
     hipLaunchKernelGGL(k_rank_count, dim3(g), dim3(256), 0, st, state, mean, p, rank);
+}
+
+void launch_seed_median(const JobDev* jobs, int n_jobs, int64_t p, double* med, int8_t* dec,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_seed_median, dim3((unsigned)((p + 255) / 256)), dim3(256), 0, st, jobs,
+                       n_jobs, p, med, dec);
 }
 
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {

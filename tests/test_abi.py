@@ -115,6 +115,14 @@ def test_invalid_arguments_rejected_on_host(kw):
     assert B.boruta_last_error()
 
 
+@pytest.mark.parametrize("seeds", [[], list(range(65))], ids=["none", "65"])
+def test_seed_count_rejected_on_host(seeds):
+    with pytest.raises(B.BorutaError) as e:
+        B.boruta_fit_seeds(np.zeros((10, 3), np.float32), np.zeros(10, np.int32), 2, 2, 2,
+                           seeds, max_iter=3)
+    assert e.value.code == B.BORUTA_E_INVALID_ARG
+
+
 def test_workspace_size_is_host_only():
     small = B.boruta_workspace_size([dict(n=500, p=20, n_classes=2, n_trees=50, max_depth=8)])
     big = B.boruta_workspace_size([dict(n=10000, p=500, n_classes=3, n_trees=200,
@@ -132,4 +140,8 @@ def test_no_cpu_fallback_without_gpu():
         pytest.skip("a GPU is present")
     with pytest.raises(B.BorutaError) as e:
         _call()
+    assert e.value.code == B.BORUTA_E_UNSUPPORTED
+    with pytest.raises(B.BorutaError) as e:
+        B.boruta_fit_seeds(np.zeros((10, 3), np.float32), np.zeros(10, np.int32), 2, 2, 2,
+                           [1, 2], max_iter=3)
     assert e.value.code == B.BORUTA_E_UNSUPPORTED

@@ -260,6 +260,33 @@ def test_final_ranking_matches_oracle():
         assert np.array_equal(s.result(0)["rank"], batch["results"][0]["rank"])
 
 
+@pytest.mark.parametrize("seeds", [[3, 11, 29, 47, 90], [5, 6, 7, 8]], ids=["odd", "even"])
+def test_multi_seed_median_matches_oracle(seeds):
+    # the repeated-seed protocol: every run against the oracle's run of its
+    # seed, and the device aggregate against the oracle's aggregate of those
+    # runs (an odd count takes the middle value, an even one the mean of two)
+    X, y = problem(77, 700, 16, 2)
+    kw = dict(mtry=0, importance_mode=B.PERMUT, max_iter=10, alpha=0.05)
+    print(f"multi-seed n=700 p=16 seeds={seeds}", flush=True)
+    g = B.boruta_fit_seeds(X, y, 2, 8, 8, seeds, **kw)
+    runs = []
+    for i, sd in enumerate(seeds):
+        o = O.boruta_fit(X, y, 2, 8, 8, seed=sd, **kw)
+        r = g["runs"][i]
+        assert r["n_iter"] == o["n_iter"]
+        assert np.array_equal(r["decision"], o["decision"])
+        assert np.array_equal(r["imp_history"], o["imp_history"], equal_nan=True)
+        runs.append(o)
+    med, dec = O.seed_median(runs)
+    assert np.array_equal(g["median_importance"], med)
+    assert np.array_equal(g["decision"], dec)
+    # without per-run outputs the aggregate is the same
+    h = B.boruta_fit_seeds(X, y, 2, 8, 8, seeds, runs=False, **kw)
+    assert np.array_equal(h["median_importance"], med)
+    assert np.array_equal(h["decision"], dec)
+    assert (dec == 1).any()
+
+
 @pytest.mark.parametrize("kl_rows", [7, 256])
 def test_kl_importance_in_row_blocks(kl_rows):
     # the divergence step in blocks of 7 rows (ragged last block) or 256,
