@@ -88,7 +88,26 @@ struct Spec {
     int K, T, D, mtry, mode, max_iter;
     double alpha;
     uint64_t seed;
+    // an earlier job of the same batch with the same inputs (X, y, n, p, K):
+    // its input copy, labels and binned matrix serve this job too (-1: none)
+    int share = -1;
 };
+
+// Jobs of one batch that pass the same input arrays (several seeds of one
+// problem) are binned once.
+void mark_shared_inputs(std::vector<Spec>& specs) {
+    for (size_t j = 0; j < specs.size(); ++j) {
+        specs[j].share = -1;
+        for (size_t i = 0; i < j; ++i) {
+            const Spec &a = specs[i], &b = specs[j];
+            if (a.share < 0 && a.X == b.X && a.y == b.y && a.n == b.n && a.p == b.p &&
+                a.K == b.K) {
+                specs[j].share = (int)i;
+                break;
+            }
+        }
+    }
+}
 
 struct Opts {
     int B = 256, R = 1, split_rank = 1, form = 1, graph = 1;
@@ -221,6 +240,7 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     uint64_t kl_S = 0, kl_pi = 0, kl_delta = 0;
     for (const Spec& s : specs) {
         JobPlan j;
+        const JobPlan* sh = s.share >= 0 ? &pl.jp[(size_t)s.share] : nullptr;
         j.n_pad = round_up(s.n, 256);
         j.P = pow2_at_least(s.n);
         j.max_sha = (int)std::max<int64_t>(s.p, 8);
@@ -230,10 +250,10 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
         pl.gq_max = std::max<uint32_t>(pl.gq_max, (uint32_t)(j.n_pad / 16));
         j.mtry_max = s.mtry > 0 ? std::min(s.mtry, j.pw_cap) : isqrt_i(j.pw_cap);
         const size_t n = (size_t)s.n, p = (size_t)s.p, T = (size_t)s.T;
-        j.X = inputs_on_device ? 0 : r.take(n * p * 4);
-        j.y32 = inputs_on_device ? 0 : r.take(n * 4);
-        j.y8 = r.take(n);
-        j.orig = r.take(p * j.n_pad);
+        j.X = inputs_on_device || sh ? 0 : r.take(n * p * 4);
+        j.y32 = inputs_on_device || sh ? 0 : r.take(n * 4);
+        j.y8 = sh ? sh->y8 : r.take(n);
+        j.orig = sh ? sh->orig : r.take(p * j.n_pad);
         j.sha = r.take((size_t)j.max_sha * j.n_pad);
         j.colptr = r.take((size_t)j.pw_cap * 8);
         j.colsrc = r.take((size_t)j.pw_cap * 4);
@@ -512,27 +532,33 @@ void Engine::setup(std::vector<int>& status) {
     for (int j = 0; j < nj; ++j) {
         const Spec& s = S[j];
         const JobPlan& jp = pl.jp[j];
-        const float* X = dev_in ? s.X : at<float>(jp.X);
-        const int32_t* y = dev_in ? s.y : at<int32_t>(jp.y32);
-        if (!dev_in) {
-            h2d((void*)X, s.X, (size_t)s.n * s.p * 4);
-            h2d((void*)y, s.y, (size_t)s.n * 4);
+        if (s.share >= 0) {
+            // inputs validated, labelled and binned with job s.share
+            status[j] = status[(size_t)s.share];
+            if (status[j] != BORUTA_OK) continue;
+        } else {
+            const float* X = dev_in ? s.X : at<float>(jp.X);
+            const int32_t* y = dev_in ? s.y : at<int32_t>(jp.y32);
+            if (!dev_in) {
+                h2d((void*)X, s.X, (size_t)s.n * s.p * 4);
+                h2d((void*)y, s.y, (size_t)s.n * 4);
+            }
+            launch_fill_u32(flags, 1, 0u, st);
+            launch_validate(X, (size_t)s.n * s.p, y, (size_t)s.n, s.K, flags, st);
+            uint32_t f = 0;
+            d2h(&f, flags, 4);
+            if (f & 1u) {
+                status[j] = BORUTA_E_NONFINITE;
+                continue;
+            }
+            if (f & 2u) {
+                status[j] = BORUTA_E_INVALID_ARG;
+                continue;
+            }
+            launch_labels(y, (size_t)s.n, at<uint8_t>(jp.y8), st);
+            launch_binning(X, s.n, s.p, O.B, at<uint8_t>(jp.orig), jp.n_pad,
+                           at<uint32_t>(pl.keys), jp.P, st);
         }
-        launch_fill_u32(flags, 1, 0u, st);
-        launch_validate(X, (size_t)s.n * s.p, y, (size_t)s.n, s.K, flags, st);
-        uint32_t f = 0;
-        d2h(&f, flags, 4);
-        if (f & 1u) {
-            status[j] = BORUTA_E_NONFINITE;
-            continue;
-        }
-        if (f & 2u) {
-            status[j] = BORUTA_E_INVALID_ARG;
-            continue;
-        }
-        launch_labels(y, (size_t)s.n, at<uint8_t>(jp.y8), st);
-        launch_binning(X, s.n, s.p, O.B, at<uint8_t>(jp.orig), jp.n_pad, at<uint32_t>(pl.keys),
-                       jp.P, st);
         int ex = 0;
         const double fr = std::frexp(s.alpha, &ex);
         const uint64_t am = (uint64_t)std::ldexp(fr, 53);
@@ -1058,12 +1084,13 @@ std::unique_ptr<Context> prepare(const std::vector<Spec>& specs, const boruta_op
     require_device();
     std::unique_ptr<Context> c(new Context);
     c->specs = specs;
+    mark_shared_inputs(c->specs);
     c->st = user_stream;
     if (!ws && !c->st) {
         HIPC(hipStreamCreate(&c->st));
         c->own_stream = true;
     }
-    const size_t need = make_plan(specs, o, dev_inputs).total;
+    const size_t need = make_plan(c->specs, o, dev_inputs).total;
     char* base = nullptr;
     if (ws) {
         if (ws_bytes < need) throw Error(BORUTA_E_OOM, "workspace smaller than boruta_workspace_size");

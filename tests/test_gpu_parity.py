@@ -128,6 +128,35 @@ def test_batch_equals_single_jobs():
         assert_same_run(r, single)
 
 
+def test_batch_jobs_sharing_inputs_equal_single_jobs():
+    # jobs passing the same X and y arrays are binned once and share the binned
+    # matrix; each still equals its own single run (mixed with an unshared job,
+    # and with a job of the same arrays but another importance mode)
+    X, y = problem(33, 900, 13, 3)
+    X2, y2 = problem(34, 700, 9, 2)
+    jobs = [dict(X=X, y=y, n_classes=3, n_trees=6, max_depth=8, max_iter=5, seed=s)
+            for s in (1, 2)]
+    jobs.insert(1, dict(X=X2, y=y2, n_classes=2, n_trees=5, max_depth=7, max_iter=4, seed=3))
+    jobs.append(dict(X=X, y=y, n_classes=3, n_trees=7, max_depth=9, importance_mode=B.PERMUT,
+                     max_iter=4, seed=4))
+    batch = B.boruta_fit_batch(jobs, trace=True)
+    for j, jd in enumerate(jobs):
+        single = B.boruta_fit_ex(jd["X"], jd["y"], jd["n_classes"], jd["n_trees"],
+                                 jd["max_depth"], importance_mode=jd.get("importance_mode", 0),
+                                 max_iter=jd["max_iter"], seed=jd["seed"], trace=True)
+        r = dict(batch["results"][j])
+        r["traces"] = [t for t in batch["traces"] if t["job"] == j]
+        assert r["status"] == 0
+        assert_same_run(r, single)
+    # a shared input that fails validation fails every job that shares it
+    Xbad = X.copy()
+    Xbad[5, 2] = np.nan
+    bad = [dict(jobs[0], X=Xbad), dict(jobs[2], X=Xbad)]
+    with pytest.raises(B.BorutaError) as e:
+        B.boruta_fit_batch(bad)
+    assert e.value.code == B.BORUTA_E_NONFINITE
+
+
 def test_device_entry_point_matches_host_entry_point():
     import torch
     X, y = problem(23, 1000, 12, 2)
@@ -222,13 +251,13 @@ def test_graph_session_with_stats_and_resume():
 
 
 @pytest.mark.parametrize("K", [2, 4])
-@pytest.mark.parametrize("tune", [dict(small_rows=16),
+@pytest.mark.parametrize("tune", [dict(small_rows=16), dict(small_rows=64),
                                   dict(small_rows=32, grid_hist=64, grid_small=8,
                                        grid_finalize=3),
                                   dict(col_level=64),
                                   dict(col_level=1, col_unit=1, grid_col=5),
                                   dict(col_level=3, col_unit=7, grid_col=64)],
-                         ids=["small_rows16", "tiny_grids", "node_major_only", "column_all_tiny",
+                         ids=["small_rows16", "small_rows64", "tiny_grids", "node_major_only", "column_all_tiny",
                               "column_from3"])
 def test_launch_tuning_leaves_results_unchanged(tune, K):
     X, y = problem(28, 2200, 30, K)
@@ -236,6 +265,17 @@ def test_launch_tuning_leaves_results_unchanged(tune, K):
     a = B.boruta_fit_ex(X, y, K, 8, 10, **kw)
     b = B.boruta_fit_ex(X, y, K, 8, 10, tune=tune, **kw)
     assert_same_run(a, b)
+
+
+@pytest.mark.parametrize("split_rank", [B.RANK_FP32, B.RANK_EXACT], ids=["fp32", "exact"])
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_wide_small_node_segments_match_oracle(K, split_rank):
+    # nodes of up to 64 rows on the wave path: segments of 32 and 64 lanes
+    # score their thresholds in the sorted form
+    X, y = problem(91 + K, 1800, 24, K, kind="mixed")
+    g, o = both(X, y, K, 10, 11, max_iter=5, seed=23, split_rank=split_rank,
+                tune=dict(small_rows=64))
+    assert_same_run(g, o)
 
 
 def test_final_ranking_matches_oracle():
