@@ -14,6 +14,9 @@
 //     one shared row permutation, the forest's class probabilities on the
 //     full training matrix, KL divergence between unpermuted and permuted
 //     predictions (importance mode 2).
+//   * options outside Algorithm 1, off by default: a percentile of the
+//     shadow importances as the hit threshold, and the rough fix of the
+//     features still tentative at the end (both from Kursa's Boruta).
 // Where the paper leaves a choice open (binning, split rule, randomness,
 // the significance test), the reading implemented here is stated in the
 // comment of the function that implements it.
@@ -597,7 +600,42 @@ struct Run {
     int n_threads;
     bool naive;
     std::vector<int32_t> kl_cols;  // mode 2: score only these columns (empty: all)
+    int perc = 100;                // hit threshold: percentile of the shadow importances
 };
+
+// Hit threshold of an iteration: the perc-th percentile of the m shadow
+// importances by the nearest-rank rule, i.e. the ceil(perc m / 100)-th
+// smallest.  perc = 100 gives the maximum that Algorithm 1 compares against.
+int64_t shadow_threshold(const int64_t* sha, int m, int perc) {
+    std::vector<int64_t> v(sha, sha + m);
+    std::sort(v.begin(), v.end());
+    const int64_t rank = ((int64_t)perc * m + 99) / 100;  // 1-based, >= 1 for perc >= 1
+    return v[(size_t)(rank - 1)];
+}
+
+// Median of a list of doubles; an even count takes the mean of the two middle
+// values.
+double median_of(std::vector<double> v) {
+    std::sort(v.begin(), v.end());
+    const size_t k = v.size();
+    return k % 2 ? v[k / 2] : (v[k / 2 - 1] + v[k / 2]) / 2.0;
+}
+
+// Rough fix of the features still tentative after the last iteration (an
+// extension of Kursa's Boruta, not part of Algorithm 1): a tentative feature
+// is confirmed when the median of its history importances exceeds the median
+// of the per-iteration shadow thresholds, and rejected otherwise.  A
+// tentative feature was active in every iteration, so its history has no NaN.
+void rough_fix(int8_t* state, const double* hist, const double* smax, int64_t p, int n_iter) {
+    if (n_iter < 1) return;
+    const double ms = median_of(std::vector<double>(smax, smax + n_iter));
+    for (int64_t j = 0; j < p; ++j) {
+        if (state[j] != 0) continue;
+        std::vector<double> col((size_t)n_iter);
+        for (int t = 0; t < n_iter; ++t) col[(size_t)t] = hist[(size_t)t * p + j];
+        state[j] = median_of(col) > ms ? 1 : -1;
+    }
+}
 
 int validate(const float* X, const int32_t* y, int64_t n, int64_t p, int K, int T, int D,
              int mtry, int mode, int max_iter, double alpha, int B, int R) {
@@ -725,9 +763,9 @@ void iteration(const Run& run, int t, int8_t* state, int32_t* hits,
             denom = (double)((int64_t)run.R * oob_total);
         }
         auto report = [&](int64_t v) { return denom > 0.0 ? (double)v / denom : 0.0; };
-        // Hit: strictly above the best shadow (Algorithm 1).
-        int64_t best_shadow = imp[p_cur];
-        for (int s = 1; s < n_sha; ++s) best_shadow = std::max(best_shadow, imp[p_cur + s]);
+        // Hit: strictly above the best shadow (Algorithm 1), or above the
+        // shadows' perc-th percentile when that option is set.
+        const int64_t best_shadow = shadow_threshold(&imp[p_cur], n_sha, run.perc);
         if (imp_row) {
             for (int64_t j = 0; j < p; ++j) imp_row[j] = std::nan("");
             for (int c = 0; c < p_cur; ++c) imp_row[active[c]] = report(imp[c]);
@@ -919,11 +957,28 @@ int oracle_boruta_fit(const float* X, const int32_t* y, int64_t n, int64_t p, in
                       int8_t* decision_out, double* imp_history_out, int32_t* hits_out,
                       double* shadow_max_out, int32_t* n_iter_out, oracle_trace_fn trace,
                       void* trace_user) {
+    return oracle_boruta_fit_ext(X, y, n, p, n_classes, n_trees, max_depth, mtry,
+                                 importance_mode, max_iter, alpha, seed, n_bins, n_perm,
+                                 n_threads, permut_naive, 100, 0, decision_out, imp_history_out,
+                                 hits_out, shadow_max_out, n_iter_out, trace, trace_user);
+}
+
+int oracle_boruta_fit_ext(const float* X, const int32_t* y, int64_t n, int64_t p,
+                          int32_t n_classes, int32_t n_trees, int32_t max_depth, int32_t mtry,
+                          int32_t importance_mode, int32_t max_iter, double alpha, uint64_t seed,
+                          int32_t n_bins, int32_t n_perm, int32_t n_threads,
+                          int32_t permut_naive, int32_t perc, int32_t rough,
+                          int8_t* decision_out, double* imp_history_out, int32_t* hits_out,
+                          double* shadow_max_out, int32_t* n_iter_out, oracle_trace_fn trace,
+                          void* trace_user) {
     if (!decision_out || !imp_history_out || !n_iter_out) return -1;
+    if (perc < 1 || perc > 100 || (rough != 0 && rough != 1)) return -1;
     Run run;
     const int rc = setup(run, X, y, n, p, n_classes, n_trees, max_depth, mtry, importance_mode,
                          max_iter, alpha, seed, n_bins, n_perm, n_threads, permut_naive);
     if (rc) return rc;
+    run.perc = perc;
+    std::vector<double> smax_all((size_t)max_iter, 0.0);
     std::vector<int8_t> state(p, 0);
     std::vector<int32_t> hits(p, 0);
     std::vector<int32_t> all_trees(n_trees);
@@ -940,7 +995,9 @@ int oracle_boruta_fit(const float* X, const int32_t* y, int64_t n, int64_t p, in
         iteration(run, t, state.data(), hits.data(), all_trees, true,
                   imp_history_out + (size_t)(t - 1) * p, &smax, trace, trace_user);
         if (shadow_max_out) shadow_max_out[t - 1] = smax;
+        smax_all[(size_t)(t - 1)] = smax;
     }
+    if (rough) rough_fix(state.data(), imp_history_out, smax_all.data(), p, t);
     std::copy(state.begin(), state.end(), decision_out);
     if (hits_out) std::copy(hits.begin(), hits.end(), hits_out);
     *n_iter_out = t;
@@ -989,6 +1046,15 @@ void oracle_rank(const int8_t* decision, const double* imp_history, int64_t p, i
 // for an even count); the selection is the lower median of the runs'
 // decisions (confirmed in more than half of the runs -> confirmed; rejected
 // in at least half -> rejected; else tentative).
+int64_t oracle_shadow_threshold(const int64_t* sha, int32_t m, int32_t perc) {
+    return shadow_threshold(sha, m, perc);
+}
+
+void oracle_rough_fix(int8_t* decision, const double* imp_history, const double* shadow_max,
+                      int64_t p, int32_t n_iter) {
+    rough_fix(decision, imp_history, shadow_max, p, n_iter);
+}
+
 void oracle_seed_median(const int8_t* decisions, const double* histories, const int32_t* n_iters,
                         int64_t p, int32_t max_iter, int32_t n_runs, double* median_out,
                         int8_t* decision_out) {

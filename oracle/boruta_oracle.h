@@ -130,6 +130,31 @@ int oracle_boruta_step(const float* X, const int32_t* y, int64_t n, int64_t p,
                        double* imp_row_out, double* shadow_max_out,
                        oracle_trace_fn trace, void* trace_user);
 
+/* oracle_boruta_fit with the two options outside Algorithm 1 (from Kursa's
+ * Boruta): perc in [1, 100] makes the hit threshold the perc-th percentile of
+ * the shadow importances (nearest rank: the ceil(perc m / 100)-th smallest of
+ * m; 100 = the maximum), and rough = 1 resolves the features still tentative
+ * after the last iteration by oracle_rough_fix.  Returns -1 for perc or rough
+ * out of range. */
+int oracle_boruta_fit_ext(const float* X, const int32_t* y, int64_t n, int64_t p,
+                          int32_t n_classes, int32_t n_trees, int32_t max_depth, int32_t mtry,
+                          int32_t importance_mode, int32_t max_iter, double alpha, uint64_t seed,
+                          int32_t n_bins, int32_t n_perm, int32_t n_threads,
+                          int32_t permut_naive, int32_t perc, int32_t rough,
+                          int8_t* decision_out, double* imp_history_out, int32_t* hits_out,
+                          double* shadow_max_out, int32_t* n_iter_out, oracle_trace_fn trace,
+                          void* trace_user);
+
+/* Hit threshold over m >= 1 shadow importances at percentile perc (above). */
+int64_t oracle_shadow_threshold(const int64_t* sha, int32_t m, int32_t perc);
+
+/* Rough fix in place: each decision[j] == 0 becomes 1 when the median of
+ * imp_history[t][j] over t < n_iter exceeds the median of shadow_max[t] over
+ * t < n_iter, else -1 (medians of an even count: mean of the two middle
+ * values).  n_iter == 0 changes nothing. */
+void oracle_rough_fix(int8_t* decision, const double* imp_history, const double* shadow_max,
+                      int64_t p, int32_t n_iter);
+
 /* Multi-seed aggregate of n_runs finished runs of one problem: decisions
  * [n_runs][p], histories [n_runs][max_iter][p], n_iters [n_runs]; per
  * feature the median over runs of its mean history importance and the lower

@@ -82,6 +82,14 @@ def lib():
         L.oracle_boruta_fit.argtypes = [P, P, i64, i64, i32, i32, i32, i32, i32, i32, f64, u64,
                                         i32, i32, i32, i32, P, P, P, P, P, TRACE_FN, P]
         L.oracle_boruta_fit.restype = i32
+        L.oracle_boruta_fit_ext.argtypes = [P, P, i64, i64, i32, i32, i32, i32, i32, i32, f64,
+                                            u64, i32, i32, i32, i32, i32, i32, P, P, P, P, P,
+                                            TRACE_FN, P]
+        L.oracle_boruta_fit_ext.restype = i32
+        L.oracle_shadow_threshold.argtypes = [P, i32, i32]
+        L.oracle_shadow_threshold.restype = i64
+        L.oracle_rough_fix.argtypes = [P, P, P, i64, i32]
+        L.oracle_rough_fix.restype = None
         L.oracle_boruta_step.argtypes = [P, P, i64, i64, i32, i32, i32, i32, i32, f64, u64, i32,
                                          i32, i32, P, P, P, i32, i32, i32, P, P, TRACE_FN, P]
         L.oracle_boruta_step.restype = i32
@@ -190,7 +198,7 @@ def _trace_collector(store):
 
 def boruta_fit(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=0, max_iter=20,
                alpha=0.05, seed=0, n_bins=256, n_perm=1, n_threads=0, permut_naive=False,
-               trace=False):
+               trace=False, perc=100, rough_fix=False):
     X = np.ascontiguousarray(X, dtype=np.float32)
     y = np.ascontiguousarray(y, dtype=np.int32)
     n, p = X.shape
@@ -201,11 +209,13 @@ def boruta_fit(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=0, m
     n_iter = ctypes.c_int32(0)
     traces = []
     cb = _trace_collector(traces) if trace else TRACE_FN()
-    rc = lib().oracle_boruta_fit(_ptr(X), _ptr(y), n, p, n_classes, n_trees, max_depth, mtry,
-                                 importance_mode, max_iter, alpha, seed, n_bins, n_perm,
-                                 n_threads, int(permut_naive), _ptr(dec), _ptr(hist), _ptr(hits),
-                                 _ptr(smax), ctypes.cast(ctypes.byref(n_iter), ctypes.c_void_p),
-                                 cb, None)
+    rc = lib().oracle_boruta_fit_ext(_ptr(X), _ptr(y), n, p, n_classes, n_trees, max_depth,
+                                     mtry, importance_mode, max_iter, alpha, seed, n_bins,
+                                     n_perm, n_threads, int(permut_naive), perc,
+                                     int(bool(rough_fix)), _ptr(dec), _ptr(hist), _ptr(hits),
+                                     _ptr(smax),
+                                     ctypes.cast(ctypes.byref(n_iter), ctypes.c_void_p), cb,
+                                     None)
     if rc:
         raise ValueError(f"oracle_boruta_fit failed: {rc}")
     rank = np.zeros(p, dtype=np.int32)
@@ -213,6 +223,21 @@ def boruta_fit(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=0, m
     lib().oracle_rank(_ptr(dec), _ptr(hist_c), p, n_iter.value, _ptr(rank))
     return {"decision": dec, "imp_history": hist, "hits": hits, "shadow_max": smax,
             "n_iter": n_iter.value, "traces": traces, "rc": rc, "rank": rank}
+
+
+def shadow_threshold(sha, perc):
+    """Hit threshold over shadow importances (integers) at percentile perc."""
+    a = np.ascontiguousarray(sha, dtype=np.int64)
+    return int(lib().oracle_shadow_threshold(_ptr(a), a.shape[0], perc))
+
+
+def rough_fix(decision, imp_history, shadow_max, n_iter):
+    """Rough fix of the tentative features of a finished run (a new array)."""
+    dec = np.array(decision, dtype=np.int8)
+    hist = np.ascontiguousarray(imp_history, dtype=np.float64)
+    smax = np.ascontiguousarray(shadow_max, dtype=np.float64)
+    lib().oracle_rough_fix(_ptr(dec), _ptr(hist), _ptr(smax), dec.shape[0], n_iter)
+    return dec
 
 
 def seed_median(runs):

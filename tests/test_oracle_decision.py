@@ -128,3 +128,69 @@ def test_seed_median_hand_computed_and_library_median():
                  for r in runs]
         assert med[j] == statistics.median(means)
         assert dec[j] == statistics.median_low([int(r["decision"][j]) for r in runs])
+
+
+def test_shadow_threshold_is_numpys_inverted_cdf_percentile():
+    # nearest-rank percentile = numpy's "inverted_cdf" method; 100 = maximum
+    rng = np.random.default_rng(8)
+    for m in (1, 2, 5, 7, 40, 333):
+        for _ in range(3):
+            a = rng.integers(-50, 50, m) * int(rng.integers(1, 2**40))
+            assert O.shadow_threshold(a, 100) == a.max()
+            for q in (1, 10, 25, 33, 50, 67, 75, 90, 99):
+                want = np.percentile(a, q, method="inverted_cdf")
+                assert O.shadow_threshold(a, q) == int(want)
+    # hand-computed: sorted [1, 3, 5, 9]; ranks ceil(q * 4 / 100)
+    assert [O.shadow_threshold([5, 1, 9, 3], q) for q in (1, 25, 26, 50, 51, 75, 76, 100)] == \
+        [1, 1, 3, 3, 5, 5, 9, 9]
+
+
+def test_rough_fix_hand_computed_and_library_median():
+    nan = np.nan
+    dec = np.array([0, 1, 0, -1, 0], np.int8)
+    hist = np.array([[0.30, 0.9, 0.10, 0.5, 0.20],
+                     [0.10, 0.8, 0.05, nan, 0.25],
+                     [0.40, 0.7, 0.20, nan, 0.15],
+                     [9.00, 9.0, 9.00, 9.0, 9.00]])
+    smax = np.array([0.2, 0.2, 0.25, 7.0])
+    # three iterations: shadow median 0.2; tentative medians 0.30, 0.10, 0.20
+    out = O.rough_fix(dec, hist, smax, 3)
+    assert list(out) == [1, 1, -1, -1, -1]  # equal to the shadow median is not above it
+    assert list(O.rough_fix(dec, hist, smax, 0)) == list(dec)
+    # two iterations (even count): shadow median 0.2; medians 0.2, 0.075, 0.225
+    assert list(O.rough_fix(dec, hist, smax, 2)) == [-1, 1, -1, -1, 1]
+    rng = np.random.default_rng(12)
+    for _ in range(20):
+        p, t = int(rng.integers(1, 9)), int(rng.integers(1, 8))
+        dec = rng.integers(-1, 2, p).astype(np.int8)
+        hist = rng.random((t + 2, p))
+        smax = rng.random(t + 2)
+        out = O.rough_fix(dec, hist, smax, t)
+        ms = np.median(smax[:t])
+        for j in range(p):
+            want = dec[j] if dec[j] != 0 else (1 if np.median(hist[:t, j]) > ms else -1)
+            assert out[j] == want
+
+
+def test_percentile_and_rough_fix_on_runs():
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((300, 10)).astype(np.float32)
+    y = (X[:, 0] + 0.5 * X[:, 1] + 0.7 * rng.standard_normal(300) > 0).astype(np.int32)
+    kw = dict(n_bins=32, seed=3)
+    base = O.boruta_fit(X, y, 2, 10, 6, max_iter=12, **kw)
+    same = O.boruta_fit(X, y, 2, 10, 6, max_iter=12, perc=100, **kw)
+    assert np.array_equal(base["decision"], same["decision"])
+    assert np.array_equal(base["imp_history"], same["imp_history"], equal_nan=True)
+    # the first iteration's forest does not depend on the threshold: a lower
+    # percentile gives every feature at least its hits against the maximum
+    h100 = O.boruta_fit(X, y, 2, 10, 6, max_iter=1, **kw)["hits"]
+    for q in (90, 50, 10):
+        hq = O.boruta_fit(X, y, 2, 10, 6, max_iter=1, perc=q, **kw)["hits"]
+        assert (hq >= h100).all()
+    # the rough fix only post-processes the finished run
+    fixed = O.boruta_fit(X, y, 2, 10, 6, max_iter=12, rough_fix=True, **kw)
+    assert np.array_equal(fixed["imp_history"], base["imp_history"], equal_nan=True)
+    want = O.rough_fix(base["decision"], base["imp_history"], base["shadow_max"], base["n_iter"])
+    assert np.array_equal(fixed["decision"], want)
+    assert (base["decision"] == 0).any() and not (fixed["decision"] == 0).any()
+    assert not (fixed["rank"] == 2).any()
