@@ -149,6 +149,20 @@ typedef struct {
                              step (its per-(column, row, class) buffer is sized
                              for one block), >= 0; default (0): as many rows as
                              keep that buffer within 256 MiB                     */
+    /* Two options outside Algorithm 1, from Kursa's Boruta; the defaults keep
+     * Algorithm 1 as written.                                                     */
+    int32_t perc;         /* hit threshold: the perc-th percentile of the
+                             iteration's shadow importances by the nearest-rank
+                             rule (the ceil(perc n_sha / 100)-th smallest of the
+                             n_sha shadows), [1, 100]; 0 or 100 (default) = the
+                             maximum.  shadow_max reports this threshold.       */
+    int32_t rough_fix;    /* 1: a feature still tentative when the results are
+                             read is reported confirmed if the median of its
+                             history entries exceeds the median of the shadow
+                             thresholds of the same iterations, else rejected
+                             (medians of an even count: mean of the middle two).
+                             Only the reported decision and rank change; a
+                             session's own state does not.  Default 0.          */
     boruta_trace_fn trace;/* nullable                                              */
     void* trace_user;
     boruta_stats* stats;  /* nullable                                              */

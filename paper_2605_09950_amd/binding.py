@@ -64,6 +64,7 @@ class Options(ctypes.Structure):
                 ("col_unit", ctypes.c_int32),
                 ("grid_col", ctypes.c_int32),
                 ("kl_rows", ctypes.c_int32),
+                ("perc", ctypes.c_int32), ("rough_fix", ctypes.c_int32),
                 ("trace", TRACE_FN), ("trace_user", ctypes.c_void_p),
                 ("stats", ctypes.POINTER(Stats))]
 
@@ -201,12 +202,14 @@ TUNE_KEYS = ("small_rows", "grid_small", "grid_hist", "grid_finalize", "col_leve
 
 
 def make_options(n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED, trace=False,
-                 stats=False, p=0, graph=True, tune=None):
+                 stats=False, p=0, graph=True, tune=None, perc=100, rough_fix=False):
     """Options plus the Python objects that must stay alive during the call.
-    trace: False, True (every iteration) or a set of iterations to keep."""
+    trace: False, True (every iteration) or a set of iterations to keep.
+    perc / rough_fix: the two options outside Algorithm 1 (boruta_options)."""
     o = boruta_default_options()
     o.n_bins, o.n_perm, o.split_rank, o.form = n_bins, n_perm, split_rank, form
     o.graph = int(bool(graph))
+    o.perc, o.rough_fix = int(perc), int(bool(rough_fix))
     for k, v in (tune or {}).items():
         if k not in TUNE_KEYS:
             raise ValueError(f"unknown tuning key {k}")
@@ -223,7 +226,8 @@ def make_options(n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED, 
 
 def boruta_fit_ex(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=TREEIMP,
                   max_iter=20, alpha=0.05, seed=0, n_bins=256, n_perm=1, split_rank=RANK_FP32,
-                  form=FORM_BATCHED, trace=False, stats=False, graph=True, tune=None):
+                  form=FORM_BATCHED, trace=False, stats=False, graph=True, tune=None, perc=100,
+                  rough_fix=False):
     """Host arrays in, host arrays out (see boruta_fit in include/boruta.h)."""
     X = np.ascontiguousarray(X, dtype=np.float32)
     y = np.ascontiguousarray(y, dtype=np.int32)
@@ -233,7 +237,8 @@ def boruta_fit_ex(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=T
     hits = np.zeros(p, np.int32)
     smax = np.full(max_iter, np.nan)
     n_iter = np.zeros(1, np.int32)
-    o, keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p, graph, tune)
+    o, keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p, graph, tune, perc,
+                           rough_fix)
     rc = lib().boruta_fit_ex(_ptr(X), _ptr(y), n, p, n_classes, n_trees, max_depth, mtry,
                              importance_mode, max_iter, alpha, seed, ctypes.byref(o), _ptr(dec),
                              _ptr(hist), _ptr(hits), _ptr(smax), _ptr(n_iter))
@@ -273,7 +278,7 @@ def _job(X, y, n_classes, n_trees, max_depth, mtry, importance_mode, max_iter, a
 
 
 def boruta_fit_batch(jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED,
-                     trace=False, stats=False):
+                     trace=False, stats=False, perc=100, rough_fix=False):
     """jobs: list of dicts with X, y, n_classes, n_trees, max_depth and optional mtry,
     importance_mode, max_iter, alpha, seed."""
     arrs, cj, res, outs = [], (Job * len(jobs))(), (Result * len(jobs))(), []
@@ -296,7 +301,8 @@ def boruta_fit_batch(jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM
         arrs.append((X, y))
         outs.append(o)
     p_all = [int(np.shape(jd["X"])[1]) for jd in jobs]
-    opt, keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p_all)
+    opt, keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p_all,
+                             perc=perc, rough_fix=rough_fix)
     rc = lib().boruta_fit_batch(cj, len(jobs), ctypes.byref(opt), res)
     for i, o in enumerate(outs):
         o["n_iter"], o["status"] = res[i].n_iter, res[i].status
@@ -306,7 +312,8 @@ def boruta_fit_batch(jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM
 
 def boruta_fit_seeds(X, y, n_classes, n_trees, max_depth, seeds, mtry=0,
                      importance_mode=TREEIMP, max_iter=20, alpha=0.05, n_bins=256, n_perm=1,
-                     split_rank=RANK_FP32, form=FORM_BATCHED, tune=None, runs=True):
+                     split_rank=RANK_FP32, form=FORM_BATCHED, tune=None, runs=True, perc=100,
+                     rough_fix=False):
     """One problem run once per seed (as one batch) and the multi-seed aggregate:
     returns {"median_importance", "decision", "runs"} where runs (if asked for)
     holds each seed's own results as boruta_fit_batch does."""
@@ -330,7 +337,8 @@ def boruta_fit_seeds(X, y, n_classes, n_trees, max_depth, seeds, mtry=0,
             res[i].shadow_max = o["shadow_max"].ctypes.data
             res[i].rank = o["rank"].ctypes.data
             outs.append(o)
-    opt, _ = make_options(n_bins, n_perm, split_rank, form, tune=tune)
+    opt, _ = make_options(n_bins, n_perm, split_rank, form, tune=tune, perc=perc,
+                          rough_fix=rough_fix)
     rc = lib().boruta_fit_seeds(_ptr(X), _ptr(y), n, p, n_classes, n_trees, max_depth, mtry,
                                 importance_mode, max_iter, alpha, _ptr(sd), len(sd),
                                 ctypes.byref(opt), _ptr(med), _ptr(dec), res)
@@ -361,7 +369,7 @@ def boruta_workspace_size(jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32,
 def boruta_fit_device(dX, dy, n_classes, n_trees, max_depth, workspace, stream=None, mtry=0,
                       importance_mode=TREEIMP, max_iter=20, alpha=0.05, seed=0, n_bins=256,
                       n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED, trace=False,
-                      stats=False):
+                      stats=False, perc=100, rough_fix=False):
     """dX [n][p] float32, dy [n] int32 and workspace (uint8) are torch CUDA tensors; stream a
     torch.cuda.Stream (default: the current stream)."""
     import torch
@@ -374,7 +382,8 @@ def boruta_fit_device(dX, dy, n_classes, n_trees, max_depth, workspace, stream=N
     hits = np.zeros(p, np.int32)
     smax = np.full(max_iter, np.nan)
     n_iter = np.zeros(1, np.int32)
-    opt, keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p)
+    opt, keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p, perc=perc,
+                             rough_fix=rough_fix)
     rc = lib().boruta_fit_device(dX.data_ptr(), dy.data_ptr(), n, p, n_classes, n_trees,
                                  max_depth, mtry, importance_mode, max_iter, alpha, seed,
                                  ctypes.byref(opt), workspace.data_ptr(), workspace.numel(),
@@ -401,7 +410,7 @@ class Session:
 
     def __init__(self, jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED,
                  trace=False, stats=False, inputs_on_device=False, workspace=None, stream=None,
-                 graph=True, tune=None):
+                 graph=True, tune=None, perc=100, rough_fix=False):
         self._arrays, cj = [], (Job * len(jobs))()
         self._shapes = []
         for i, jd in enumerate(jobs):
@@ -425,7 +434,7 @@ class Session:
             self._shapes.append((p, j.max_iter))
         p_all = [int(sh[0]) for sh in self._shapes]
         self.opt, self.keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p_all,
-                                           graph, tune)
+                                           graph, tune, perc, rough_fix)
         self._jobs = cj
         self._ws = workspace
         ws_ptr = workspace.data_ptr() if workspace is not None else None

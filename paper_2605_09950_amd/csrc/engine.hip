@@ -44,12 +44,15 @@ void launch_hist_col(const ForestDev&, int, uint32_t, int, uint32_t, hipStream_t
 void launch_tree_totals(JobDev*, const TreeDev*, int, uint64_t*, hipStream_t);
 void launch_treeimp(JobDev*, const TreeDev*, int, const uint64_t*, int, hipStream_t);
 void launch_permut(JobDev*, const TreeDev*, const NodeDev*, int, int64_t, int, int, hipStream_t);
-void launch_hits_decide(JobDev*, int, hipStream_t);
+void launch_hits_decide(JobDev*, int, int, hipStream_t);
+void launch_rough_fix(const int8_t*, const double*, const double*, int64_t, int, int, int8_t*,
+                      hipStream_t);
 void launch_kl_block(JobDev*, int, const NodeDev*, const uint32_t*, int, uint32_t, int, int,
                      uint32_t, uint32_t, uint64_t*, uint32_t*, unsigned long long*, int,
                      hipStream_t);
 void launch_copy(void*, const void*, size_t, hipStream_t);
-void launch_seed_median(const JobDev*, int, int64_t, double*, int8_t*, hipStream_t);
+void launch_seed_median(const JobDev*, const int8_t* const*, int, int64_t, double*, int8_t*,
+                        hipStream_t);
 void launch_rank(const int8_t*, const double*, int64_t, int, int, double*, int32_t*, hipStream_t);
 
 namespace {
@@ -113,6 +116,7 @@ struct Opts {
     int B = 256, R = 1, split_rank = 1, form = 1, graph = 1;
     int small_rows = 32, grid_small = 0, grid_hist = 0, grid_finalize = 0;
     int col_level = 0, col_unit = 512, grid_col = 0, kl_rows = 0;
+    int perc = 100, rough_fix = 0;
     boruta_trace_fn trace = nullptr;
     void* trace_user = nullptr;
     boruta_stats* stats = nullptr;
@@ -134,6 +138,8 @@ Opts read_opts(const boruta_options* o) {
         if (o->col_unit) r.col_unit = o->col_unit;
         r.grid_col = o->grid_col;
         r.kl_rows = o->kl_rows;
+        if (o->perc) r.perc = o->perc;
+        r.rough_fix = o->rough_fix;
         r.trace = o->trace;
         r.trace_user = o->trace_user;
         r.stats = o->stats;
@@ -156,6 +162,9 @@ Opts read_opts(const boruta_options* o) {
     if (r.grid_col < 0 || r.grid_col > 65536)
         throw Error(BORUTA_E_INVALID_ARG, "grid_col outside [0, 65536]");
     if (r.kl_rows < 0) throw Error(BORUTA_E_INVALID_ARG, "kl_rows must be >= 0");
+    if (r.perc < 1 || r.perc > 100) throw Error(BORUTA_E_INVALID_ARG, "perc outside [1, 100]");
+    if (r.rough_fix != 0 && r.rough_fix != 1)
+        throw Error(BORUTA_E_INVALID_ARG, "rough_fix must be 0 or 1");
     return r;
 }
 
@@ -202,6 +211,7 @@ struct JobPlan {
     uint32_t gbase;
     uint32_t kl_rb;  // KL importance: rows per block (0: the job does not use it)
     size_t rmean, rank;  // final ranking: per-feature mean history, rank
+    size_t fixdec;       // decisions after the rough fix (when that option is set)
     int max_sha, pw_cap, mtry_max;
     size_t X, y32, y8, orig, sha, colptr, colsrc, act, state, hits, hist, smax, hconf, hrej, G,
         imp, wbuf, rec0, rec1, oob, tstat;
@@ -213,6 +223,7 @@ struct Plan {
         feat, fcol, srec, kinds, chunk_sums, slot0, slot1, ctrs, alg, tot;
     size_t fcnt = 0, fpos = 0, fitems = 0, units = 0, gcolq = 0;
     size_t seed_med = 0, seed_dec = 0;  // multi-seed aggregate [p]
+    size_t dec_ptrs = 0;                // per job: the decisions the aggregate reads
     size_t kl_S = 0, kl_pi = 0, kl_delta = 0;  // KL importance buffers (shared by its jobs)
     uint32_t node_cap = 0, slot_cap = 0, small_cap = 0;
     int kmax = 4, max_sha = 1, max_pw = 1, max_D = 1, T_total = 0, mtry_cap = 1,
@@ -273,6 +284,7 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
         j.tstat = r.take(T * 16);
         j.rmean = r.take(p * 8);
         j.rank = r.take(p * 4);
+        j.fixdec = o.rough_fix ? r.take(p) : 0;
         // KL importance: the per-(column, row, class) leaf differences of a
         // block of rows are bounded by kKlDeltaBytes
         j.kl_rb = 0;
@@ -354,6 +366,7 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
         for (const Spec& sp : specs) pmax = std::max<int64_t>(pmax, sp.p);
         pl.seed_med = r.take((size_t)pmax * 8);
         pl.seed_dec = r.take((size_t)pmax);
+        pl.dec_ptrs = r.take(specs.size() * sizeof(void*));
     }
     if (kl_delta) {
         pl.kl_S = r.take(kl_S);
@@ -482,14 +495,18 @@ public:
     // One iteration of every live job; returns the number still live.
     int step();
     void result(int j, Out& o);
+    const int8_t* decisions(int j);
     // Continue job j from a checkpoint: the next iteration is t + 1.
     void resume(int j, int t, const int8_t* state, const int32_t* hits);
     void flush_stats();
     const JobDev& job(int j) const { return hj[j]; }
     // Multi-seed aggregate over all jobs (runs of one problem with p features).
     void seed_median(int64_t p, double* med, int8_t* dec) {
-        launch_seed_median(at<JobDev>(pl.jobs), (int)S.size(), p, at<double>(pl.seed_med),
-                           at<int8_t>(pl.seed_dec), st);
+        std::vector<const int8_t*> ptrs(S.size());
+        for (size_t j = 0; j < S.size(); ++j) ptrs[j] = decisions((int)j);
+        h2d(at<void>(pl.dec_ptrs), ptrs.data(), ptrs.size() * sizeof(void*));
+        launch_seed_median(at<JobDev>(pl.jobs), at<const int8_t*>(pl.dec_ptrs), (int)S.size(), p,
+                           at<double>(pl.seed_med), at<int8_t>(pl.seed_dec), st);
         d2h(med, at<double>(pl.seed_med), (size_t)p * 8);
         d2h(dec, at<int8_t>(pl.seed_dec), (size_t)p);
     }
@@ -840,7 +857,7 @@ void Engine::enqueue_iteration() {
         }
         clock.end(h, st);
     }
-    launch_hits_decide(djobs, nj, st);
+    launch_hits_decide(djobs, nj, O.perc, st);
     clock.end(h_whole, st);
 }
 
@@ -993,17 +1010,28 @@ void Engine::flush_stats() {
     launch_fill_u32(at<uint32_t>(pl.alg), 6 * kAlgWords, 0u, st);
 }
 
+// Decisions of job j as reported: the live state, or after the rough fix of
+// the tentative features over the iterations run here.
+const int8_t* Engine::decisions(int j) {
+    const JobDev& J = hj[j];
+    if (!O.rough_fix || J.t <= hist_t0[j]) return J.state;
+    int8_t* out = at<int8_t>(pl.jp[j].fixdec);
+    launch_rough_fix(J.state, J.hist, J.shadow_max, S[j].p, hist_t0[j], J.t, out, st);
+    return out;
+}
+
 void Engine::result(int j, Out& o) {
     const Spec& s = S[j];
     const JobDev& J = hj[j];
     HIPC(hipStreamSynchronize(st));
-    d2h(o.decision, J.state, (size_t)s.p);
+    const int8_t* dec = decisions(j);
+    d2h(o.decision, dec, (size_t)s.p);
     if (J.t > 0 && o.hist) d2h(o.hist, J.hist, (size_t)J.t * s.p * 8);
     if (o.hits) d2h(o.hits, J.hits, (size_t)s.p * 4);
     if (o.smax && J.t > 0) d2h(o.smax, J.shadow_max, (size_t)J.t * 8);
     if (o.rank) {
         const JobPlan& jp = pl.jp[j];
-        launch_rank(J.state, J.hist, s.p, hist_t0[j], J.t, at<double>(jp.rmean),
+        launch_rank(dec, J.hist, s.p, hist_t0[j], J.t, at<double>(jp.rmean),
                     at<int32_t>(jp.rank), st);
         d2h(o.rank, at<int32_t>(jp.rank), (size_t)s.p * 4);
     }
@@ -1164,6 +1192,8 @@ void boruta_default_options(boruta_options* opt) {
     opt->col_unit = 512;
     opt->grid_col = 0;
     opt->kl_rows = 0;
+    opt->perc = 100;
+    opt->rough_fix = 0;
     opt->trace = nullptr;
     opt->trace_user = nullptr;
     opt->stats = nullptr;

@@ -369,10 +369,46 @@ __global__ __launch_bounds__(256) void k_kl_reduce(JobDev* jobs, int j, uint32_t
     }
 }
 
-// Per job: hits, history row, shadow maximum, decisions, liveness.
-__global__ __launch_bounds__(256) void k_hits_decide(JobDev* jobs) {
+// Selection of the k-th smallest (0-based) of the job's n_sha shadow
+// importances by a most-significant-digit radix select over the order-
+// preserving unsigned keys (sign bit flipped): eight passes of an 8-bit
+// digit histogram in LDS.  All 256 threads call it.
+__device__ long long shadow_select(const JobDev& J, int k, unsigned* s_hist, int* s_sel) {
+    const int tid = threadIdx.x;
+    const int p_cur = J.p_cur, p_w = J.p_w;
+    unsigned long long prefix = 0, mask = 0;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        s_hist[tid] = 0u;
+        __syncthreads();
+        for (int c = p_cur + tid; c < p_w; c += 256) {
+            const unsigned long long u = (unsigned long long)J.imp[c] ^ (1ull << 63);
+            if ((u & mask) == prefix) atomicAdd(&s_hist[(u >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int d = 0;
+            unsigned below = 0;
+            while (d < 255 && below + s_hist[d] <= (unsigned)k) below += s_hist[d++];
+            s_sel[0] = d;
+            s_sel[1] = k - (int)below;
+        }
+        __syncthreads();
+        prefix |= (unsigned long long)s_sel[0] << shift;
+        mask |= 0xFFull << shift;
+        k = s_sel[1];
+        __syncthreads();  // s_sel and s_hist are rewritten by the next pass
+    }
+    return (long long)(prefix ^ (1ull << 63));
+}
+
+// Per job: hits, history row, shadow threshold, decisions, liveness.  The
+// hit threshold is the maximum shadow importance (perc = 100) or the
+// ceil(perc n_sha / 100)-th smallest one.
+__global__ __launch_bounds__(256) void k_hits_decide(JobDev* jobs, int perc) {
     __shared__ long long s_max[4], s_sum[4];
     __shared__ int s_und[4];
+    __shared__ unsigned s_hist[256];
+    __shared__ int s_sel[2];
     JobDev& J = jobs[blockIdx.x];
     if (!J.live) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -398,6 +434,10 @@ __global__ __launch_bounds__(256) void k_hits_decide(JobDev* jobs) {
     for (int v = 1; v < 4; ++v) {
         best = s_max[v] > best ? s_max[v] : best;
         total += s_sum[v];
+    }
+    if (perc < 100) {
+        const int rank = (int)(((long long)perc * J.n_sha + 99) / 100);  // 1-based
+        best = shadow_select(J, rank - 1, s_hist, s_sel);
     }
     double denom;
     if (J.mode == 0) {
@@ -491,8 +531,9 @@ __global__ __launch_bounds__(256) void k_rank_count(const int8_t* state, const d
 // thread per feature; per run the mean of the feature's finite history
 // entries (summed in iteration order), then the median over runs (mean of
 // the middle pair for an even count) and the lower median of the decisions.
-__global__ __launch_bounds__(256) void k_seed_median(const JobDev* jobs, int n_jobs, int64_t p,
-                                                     double* med, int8_t* dec) {
+__global__ __launch_bounds__(256) void k_seed_median(const JobDev* jobs,
+                                                     const int8_t* const* decisions, int n_jobs,
+                                                     int64_t p, double* med, int8_t* dec) {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= p) return;
     double v[64];
@@ -508,7 +549,7 @@ __global__ __launch_bounds__(256) void k_seed_median(const JobDev* jobs, int n_j
             ++c;
         }
         const double m = c ? s / c : 0.0;
-        const int d = J.state[j];
+        const int d = decisions[r][j];
         int i = r;  // insertion into the sorted prefixes
         while (i > 0 && v[i - 1] > m) {
             v[i] = v[i - 1];
@@ -524,6 +565,53 @@ __global__ __launch_bounds__(256) void k_seed_median(const JobDev* jobs, int n_j
     }
     med[j] = n_jobs % 2 ? v[n_jobs / 2] : (v[n_jobs / 2 - 1] + v[n_jobs / 2]) / 2.0;
     dec[j] = (int8_t)dv[(n_jobs - 1) / 2];
+}
+
+// Rough fix of the features still tentative (an option outside Algorithm 1,
+// from Kursa's Boruta): one workgroup per feature.  A tentative feature is
+// confirmed when the median of its history entries of iterations [t0, t1)
+// exceeds the median of the shadow thresholds of those iterations, else
+// rejected; other decisions are copied.  Medians by rank counting in LDS
+// (t1 - t0 <= 1000 values); an even count takes the mean of the middle two.
+__device__ double lds_median(const double* v, int m, double* s_mid) {
+    // the element of rank r (0-based) is v[i] with #{v < v[i]} + #{v[j] ==
+    // v[i], j < i} == r: one writer per rank
+    const int r0 = (m - 1) / 2, r1 = m / 2;
+    for (int i = threadIdx.x; i < m; i += 256) {
+        int less = 0, eq_before = 0;
+        for (int j = 0; j < m; ++j) {
+            less += v[j] < v[i];
+            eq_before += j < i && v[j] == v[i];
+        }
+        const int r = less + eq_before;
+        if (r == r0) s_mid[0] = v[i];
+        if (r == r1) s_mid[1] = v[i];
+    }
+    __syncthreads();
+    const double med = m % 2 ? s_mid[0] : (s_mid[0] + s_mid[1]) / 2.0;
+    __syncthreads();  // s_mid is rewritten by the next call
+    return med;
+}
+
+__global__ __launch_bounds__(256) void k_rough_fix(const int8_t* state, const double* hist,
+                                                   const double* smax, int64_t p, int t0, int t1,
+                                                   int8_t* out) {
+    __shared__ double s_v[1000];
+    __shared__ double s_mid[2];
+    const int64_t j = blockIdx.x;
+    const int8_t st = state[j];
+    if (st != 0) {
+        if (threadIdx.x == 0) out[j] = st;
+        return;
+    }
+    const int m = t1 - t0;
+    for (int i = threadIdx.x; i < m; i += 256) s_v[i] = smax[t0 + i];
+    __syncthreads();
+    const double ms = lds_median(s_v, m, s_mid);
+    for (int i = threadIdx.x; i < m; i += 256) s_v[i] = hist[(size_t)(t0 + i) * p + j];
+    __syncthreads();
+    const double mf = lds_median(s_v, m, s_mid);
+    if (threadIdx.x == 0) out[j] = mf > ms ? (int8_t)1 : (int8_t)-1;
 }
 
 // Streaming copy used to calibrate hardware byte counters.
@@ -581,8 +669,14 @@ void launch_kl_block(JobDev* jobs, int j, const NodeDev* nodes, const uint32_t* 
     }
 }
 
-void launch_hits_decide(JobDev* jobs, int n_jobs, hipStream_t st) {
-    hipLaunchKernelGGL(k_hits_decide, dim3(n_jobs), dim3(256), 0, st, jobs);
+void launch_hits_decide(JobDev* jobs, int n_jobs, int perc, hipStream_t st) {
+    hipLaunchKernelGGL(k_hits_decide, dim3(n_jobs), dim3(256), 0, st, jobs, perc);
+}
+
+void launch_rough_fix(const int8_t* state, const double* hist, const double* smax, int64_t p,
+                      int t0, int t1, int8_t* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_rough_fix, dim3((unsigned)p), dim3(256), 0, st, state, hist, smax, p, t0,
+                       t1, out);
 }
 
 void launch_rank(const int8_t* state, const double* hist, int64_t p, int t0, int t1,
@@ -592,10 +686,10 @@ void launch_rank(const int8_t* state, const double* hist, int64_t p, int t0, int
     hipLaunchKernelGGL(k_rank_count, dim3(g), dim3(256), 0, st, state, mean, p, rank);
 }
 
-void launch_seed_median(const JobDev* jobs, int n_jobs, int64_t p, double* med, int8_t* dec,
-                        hipStream_t st) {
+void launch_seed_median(const JobDev* jobs, const int8_t* const* decisions, int n_jobs, int64_t p,
+                        double* med, int8_t* dec, hipStream_t st) {
     hipLaunchKernelGGL(k_seed_median, dim3((unsigned)((p + 255) / 256)), dim3(256), 0, st, jobs,
-                       n_jobs, p, med, dec);
+                       decisions, n_jobs, p, med, dec);
 }
 
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {

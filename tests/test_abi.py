@@ -37,7 +37,23 @@ def test_default_options():
     assert (o.n_bins, o.n_perm, o.split_rank, o.form) == (256, 1, B.RANK_FP32, B.FORM_BATCHED)
     assert (o.graph, o.small_rows, o.grid_small, o.grid_hist, o.grid_finalize) == (1, 32, 0, 0, 0)
     assert (o.col_level, o.col_unit, o.grid_col, o.kl_rows) == (0, 512, 0, 0)
+    assert (o.perc, o.rough_fix) == (100, 0)
     assert not o.trace and not o.stats
+
+
+@pytest.mark.parametrize("field,value", [("perc", 101), ("perc", -1), ("rough_fix", 2)])
+def test_percentile_and_rough_fix_validated_on_the_host(field, value):
+    import ctypes
+    o, _ = B.make_options()
+    setattr(o, field, value)
+    job = (B.Job * 1)()
+    job[0].X = job[0].y = 1
+    job[0].n, job[0].p, job[0].n_classes, job[0].n_trees = 100, 5, 2, 2
+    job[0].max_depth, job[0].max_iter, job[0].alpha = 3, 3, 0.05
+    out = ctypes.c_size_t(0)
+    rc = B.lib().boruta_workspace_size(job, 1, ctypes.byref(o), ctypes.byref(out))
+    assert rc == B.BORUTA_E_INVALID_ARG
+    assert "perc" in B.boruta_last_error() or "rough_fix" in B.boruta_last_error()
 
 
 def test_tuning_options_validated_on_the_host():

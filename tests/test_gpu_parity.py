@@ -327,6 +327,52 @@ def test_multi_seed_median_matches_oracle(seeds):
     assert (dec == 1).any()
 
 
+@pytest.mark.parametrize("perc", [90, 50])
+@pytest.mark.parametrize("mode", [B.TREEIMP, B.PERMUT, B.PERMUT_KL])
+def test_percentile_shadow_threshold_matches_oracle(mode, perc):
+    # the hit threshold as the perc-th percentile of the shadow importances
+    # (radix select on the device)
+    X, y = problem(61, 900, 14, 3)
+    kw = dict(importance_mode=mode, max_iter=8, seed=31, perc=perc)
+    g, o = both(X, y, 3, 8, 8, **kw)
+    assert_same_run(g, o)
+    assert (g["hits"] > 0).any()
+
+
+def test_rough_fix_matches_oracle_and_leaves_the_session_state():
+    # tentative features resolved by the rough fix in the reported decision
+    # and rank (batch of two modes; multi-seed aggregate); a session read
+    # mid-run with the fix continues exactly like one read without it
+    X, y = problem(63, 800, 12, 2)
+    jobs = [dict(X=X, y=y, n_classes=2, n_trees=8, max_depth=8, importance_mode=m, max_iter=9,
+                 seed=70 + m) for m in (0, 1)]
+    batch = B.boruta_fit_batch(jobs, rough_fix=True)
+    for j, jd in enumerate(jobs):
+        o = O.boruta_fit(X, y, 2, 8, 8, importance_mode=jd["importance_mode"], max_iter=9,
+                         seed=jd["seed"], rough_fix=True)
+        r = batch["results"][j]
+        assert np.array_equal(r["decision"], o["decision"])
+        assert np.array_equal(r["rank"], o["rank"])
+        assert not (r["decision"] == 0).any()
+    plain = B.boruta_fit_batch(jobs)
+    assert any((r["decision"] == 0).any() for r in plain["results"])
+    seeds = [5, 6, 7]
+    g = B.boruta_fit_seeds(X, y, 2, 8, 8, seeds, max_iter=9, rough_fix=True)
+    runs = [O.boruta_fit(X, y, 2, 8, 8, max_iter=9, seed=s, rough_fix=True) for s in seeds]
+    med, dec = O.seed_median(runs)
+    assert np.array_equal(g["median_importance"], med)
+    assert np.array_equal(g["decision"], dec)
+    with B.Session(jobs[:1], rough_fix=True) as s:
+        for _ in range(4):
+            s.step()
+        mid = s.result(0)
+        o4 = O.boruta_fit(X, y, 2, 8, 8, max_iter=4, seed=70, rough_fix=True)
+        assert np.array_equal(mid["decision"], o4["decision"])
+        while s.step():
+            pass
+        assert np.array_equal(s.result(0)["decision"], batch["results"][0]["decision"])
+
+
 @pytest.mark.parametrize("kl_rows", [7, 256])
 def test_kl_importance_in_row_blocks(kl_rows):
     # the divergence step in blocks of 7 rows (ragged last block) or 256,
