@@ -181,14 +181,83 @@ uint64_t gain_fixed(const Cand& c, uint64_t s, uint64_t n) {
     return (uint64_t)((num << 32) / den);
 }
 
+// Regression forest (the paper's regression experiments; reading): targets
+// quantised to integer levels y in [0, Q], Q = 255.  A node with bootstrap
+// weights w has W = sum w and T = sum w y; the split minimising the weighted
+// squared error of the children maximises  T_L^2/W_L + T_R^2/W_R,  which is
+// the same exact comparison as the Gini rule with (n, s) = (W, T^2).  Its
+// decrease  D = T_L^2/W_L + T_R^2/W_R - T^2/W  (the weighted squared-error
+// decrease in level units) is held in fixed point as floor(2^33 D / Q).
+constexpr int kLevels = 255;
+constexpr int64_t kRegMaxRows = 65536;  // keeps Q * (weighted rows) below 2^24
+
+uint64_t gain_fixed_reg(const Cand& c, uint64_t s, uint64_t n) {
+    const u128 num = ((u128)c.sl * c.nr + (u128)c.sr * c.nl) * n - (u128)s * c.nl * c.nr;
+    const u128 den = (u128)c.nl * c.nr * n * (u128)kLevels;
+    return (uint64_t)((num << 33) / den);
+}
+
+// Target quantisation: y -> floor((y - min) Q / (max - min) + 1/2) in double,
+// 0 for a constant target.
+void quantize_target(const float* y, int64_t n, int32_t* out) {
+    double lo = y[0], hi = y[0];
+    for (int64_t i = 1; i < n; ++i) {
+        lo = std::min(lo, (double)y[i]);
+        hi = std::max(hi, (double)y[i]);
+    }
+    const double range = hi - lo;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(range > 0.0)) {
+            out[i] = 0;
+            continue;
+        }
+        const double v = ((double)y[i] - lo) * (double)kLevels / range;
+        out[i] = (int32_t)std::floor(v + 0.5);
+    }
+}
+
 struct Data {
     int64_t n = 0;
     int64_t p_w = 0;
     std::vector<const uint8_t*> col;  // [p_w] column base pointers, each [n]
-    const int32_t* y = nullptr;
+    const int32_t* y = nullptr;  // class labels, or quantised targets (reg)
     int K = 2;
     int B = 256;
+    bool reg = false;
 };
+
+// Regression form of best_split: per bin the weight W and the weighted target
+// sum T; candidates carry (nl, sl, nr, sr) = (W_L, T_L^2, W_R, T_R^2).
+Cand best_split_reg(const Data& d, const std::vector<uint32_t>& rows, const uint32_t* w,
+                    const std::vector<int32_t>& feats, uint64_t W, uint64_t T) {
+    std::vector<uint64_t> hw((size_t)d.B), ht((size_t)d.B);
+    Cand best;
+    for (size_t q = 0; q < feats.size(); ++q) {
+        const uint8_t* col = d.col[feats[q]];
+        std::fill(hw.begin(), hw.end(), 0);
+        std::fill(ht.begin(), ht.end(), 0);
+        for (uint32_t i : rows) {
+            hw[col[i]] += w[i];
+            ht[col[i]] += (uint64_t)w[i] * (uint64_t)d.y[i];
+        }
+        uint64_t lw = 0, lt = 0;
+        for (int b = 0; b + 1 < d.B; ++b) {
+            lw += hw[(size_t)b];
+            lt += ht[(size_t)b];
+            Cand c;
+            c.valid = true;
+            c.q = (int)q;
+            c.b = b;
+            c.nl = lw;
+            c.sl = lt * lt;
+            c.nr = W - lw;
+            c.sr = (T - lt) * (T - lt);
+            if (c.nl == 0 || c.nr == 0) continue;
+            if (!best.valid || better(c, best)) best = c;
+        }
+    }
+    return best;
+}
 
 // Exhaustive search over the node's drawn features and every threshold
 // b = 0..B-2, keeping the first best in (draw position, threshold) order.
@@ -253,15 +322,30 @@ int32_t grow(TreeCtx& c, const std::vector<uint32_t>& rows, int depth, int64_t h
     const int32_t idx = (int32_t)c.nodes.size();
     c.nodes.emplace_back();
     std::vector<uint64_t> counts(d.K, 0);
-    for (uint32_t i : rows) counts[d.y[i]] += c.w[i];
     uint64_t n = 0, s = 0;
-    for (uint64_t v : counts) {
-        n += v;
-        s += v * v;
+    if (d.reg) {
+        // (n, s) = (W, T^2); the node's reported weighted count is Q W and its
+        // "class" counts (Q W - T, T)
+        uint64_t W = 0, T = 0;
+        for (uint32_t i : rows) {
+            W += c.w[i];
+            T += (uint64_t)c.w[i] * (uint64_t)d.y[i];
+        }
+        counts[0] = (uint64_t)kLevels * W - T;
+        counts[1] = T;
+        n = W;
+        s = T * T;
+        c.nodes[idx].n = (uint64_t)kLevels * W;
+    } else {
+        for (uint32_t i : rows) counts[d.y[i]] += c.w[i];
+        for (uint64_t v : counts) {
+            n += v;
+            s += v * v;
+        }
+        c.nodes[idx].n = n;
     }
     c.nodes[idx].heap = heap;
     c.nodes[idx].depth = depth;
-    c.nodes[idx].n = n;
     c.nodes[idx].counts = counts;
 
     Cand best;
@@ -270,7 +354,8 @@ int32_t grow(TreeCtx& c, const std::vector<uint32_t>& rows, int depth, int64_t h
         for (int q = 0; q < c.mtry; ++q)
             feats.push_back((int32_t)keyed_perm(c.seed, kStreamMtry, c.t, c.tree, (uint32_t)heap,
                                                 0u, (uint64_t)d.p_w, (uint64_t)q));
-        best = best_split(d, rows, c.w, feats, counts);
+        best = d.reg ? best_split_reg(d, rows, c.w, feats, n, counts[1])
+                     : best_split(d, rows, c.w, feats, counts);
     }
     if (best.valid && positive_gain(best, s, n)) {
         const int32_t f = feats[best.q];
@@ -278,7 +363,7 @@ int32_t grow(TreeCtx& c, const std::vector<uint32_t>& rows, int depth, int64_t h
         for (uint32_t i : rows) (d.col[f][i] <= best.b ? lrows : rrows).push_back(i);
         c.nodes[idx].feat = f;
         c.nodes[idx].thr = best.b;
-        c.nodes[idx].gain = gain_fixed(best, s, n);
+        c.nodes[idx].gain = d.reg ? gain_fixed_reg(best, s, n) : gain_fixed(best, s, n);
         const int32_t l = grow(c, lrows, depth + 1, 2 * heap);
         const int32_t r = grow(c, rrows, depth + 1, 2 * heap + 1);
         c.nodes[idx].left = l;
@@ -601,6 +686,8 @@ struct Run {
     bool naive;
     std::vector<int32_t> kl_cols;  // mode 2: score only these columns (empty: all)
     int perc = 100;                // hit threshold: percentile of the shadow importances
+    bool reg = false;              // regression forest (y holds quantised targets)
+    std::vector<int32_t> yq;       // regression: quantised targets
 };
 
 // Hit threshold of an iteration: the perc-th percentile of the m shadow
@@ -637,8 +724,10 @@ void rough_fix(int8_t* state, const double* hist, const double* smax, int64_t p,
     }
 }
 
+// Labels must lie in [0, y_hi): the classes, or the quantised levels of a
+// regression target.
 int validate(const float* X, const int32_t* y, int64_t n, int64_t p, int K, int T, int D,
-             int mtry, int mode, int max_iter, double alpha, int B, int R) {
+             int mtry, int mode, int max_iter, double alpha, int B, int R, int y_hi) {
     if (!X || !y) return -1;
     if (n < 2 || n > (int64_t(1) << 24) || p < 1 || p > (int64_t(1) << 30)) return -1;
     if (K < 2 || K > 16 || T < 1 || T > 65535 || D < 1 || D > 30 || mtry < 0) return -1;
@@ -647,7 +736,7 @@ int validate(const float* X, const int32_t* y, int64_t n, int64_t p, int K, int 
     if (!(alpha > 0.0 && alpha < 0.5)) return -1;
     if (B < 2 || B > 256 || R < 1 || R > 65535) return -1;
     for (int64_t i = 0; i < n; ++i)
-        if (y[i] < 0 || y[i] >= K) return -1;
+        if (y[i] < 0 || y[i] >= y_hi) return -1;
     for (int64_t i = 0; i < n * p; ++i)
         if (!std::isfinite(X[i])) return -2;
     return 0;
@@ -698,6 +787,7 @@ void iteration(const Run& run, int t, int8_t* state, int32_t* hits,
     d.y = run.y;
     d.K = run.K;
     d.B = run.B;
+    d.reg = run.reg;
     std::vector<int32_t> col_src(d.p_w);
     for (int c = 0; c < p_cur; ++c) {
         d.col.push_back(run.orig.data() + (size_t)active[c] * n);
@@ -813,8 +903,9 @@ void iteration(const Run& run, int t, int8_t* state, int32_t* hits,
 
 int setup(Run& run, const float* X, const int32_t* y, int64_t n, int64_t p, int K, int T, int D,
           int mtry, int mode, int max_iter, double alpha, uint64_t seed, int B, int R,
-          int n_threads, int naive) {
-    const int rc = validate(X, y, n, p, K, T, D, mtry, mode, max_iter, alpha, B, R);
+          int n_threads, int naive, int y_hi = 0) {
+    const int rc =
+        validate(X, y, n, p, K, T, D, mtry, mode, max_iter, alpha, B, R, y_hi ? y_hi : K);
     if (rc) return rc;
     run.n = n;
     run.p = p;
@@ -834,6 +925,11 @@ int setup(Run& run, const float* X, const int32_t* y, int64_t n, int64_t p, int 
     bin_columns(X, n, p, B, run.orig.data(), nullptr, nullptr);
     return 0;
 }
+
+// The Boruta loop over a prepared run (defined below the exported functions).
+int fit_run(Run& run, int n_trees, int max_iter, int rough, int8_t* decision_out,
+            double* imp_history_out, int32_t* hits_out, double* shadow_max_out,
+            int32_t* n_iter_out, oracle_trace_fn trace, void* trace_user);
 
 }  // namespace
 
@@ -978,6 +1074,76 @@ int oracle_boruta_fit_ext(const float* X, const int32_t* y, int64_t n, int64_t p
                          max_iter, alpha, seed, n_bins, n_perm, n_threads, permut_naive);
     if (rc) return rc;
     run.perc = perc;
+    return fit_run(run, n_trees, max_iter, rough, decision_out, imp_history_out, hits_out,
+                   shadow_max_out, n_iter_out, trace, trace_user);
+}
+
+int oracle_boruta_fit_reg(const float* X, const float* y, int64_t n, int64_t p,
+                          int32_t n_trees, int32_t max_depth, int32_t mtry,
+                          int32_t importance_mode, int32_t max_iter, double alpha, uint64_t seed,
+                          int32_t n_bins, int32_t n_threads, int8_t* decision_out,
+                          double* imp_history_out, int32_t* hits_out, double* shadow_max_out,
+                          int32_t* n_iter_out, oracle_trace_fn trace, void* trace_user) {
+    if (!decision_out || !imp_history_out || !n_iter_out || !y) return -1;
+    if (n < 2 || n > kRegMaxRows || importance_mode != 0) return -1;
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(y[i])) return -2;
+    Run run;
+    run.reg = true;
+    run.yq.resize((size_t)n);
+    quantize_target(y, n, run.yq.data());
+    const int rc = setup(run, X, run.yq.data(), n, p, 2, n_trees, max_depth, mtry,
+                         importance_mode, max_iter, alpha, seed, n_bins, 1, n_threads, 0,
+                         kLevels + 1);
+    if (rc) return rc;
+    return fit_run(run, n_trees, max_iter, 0, decision_out, imp_history_out, hits_out,
+                   shadow_max_out, n_iter_out, trace, trace_user);
+}
+
+void oracle_quantize_target(const float* y, int64_t n, int32_t* out) { quantize_target(y, n, out); }
+
+int oracle_best_split_reg(const uint8_t* bins, int64_t n, const int32_t* yq, const uint32_t* w,
+                          const uint32_t* rows, int64_t n_rows, const int32_t* feats,
+                          int32_t n_feats, int32_t n_bins, uint64_t out[8]) {
+    if (!bins || !yq || !w || !rows || !feats || n_feats < 1 || n_bins < 2) return -1;
+    Data d;
+    d.n = n;
+    d.y = yq;
+    d.K = 2;
+    d.B = n_bins;
+    d.reg = true;
+    int32_t maxf = 0;
+    for (int q = 0; q < n_feats; ++q) maxf = std::max(maxf, feats[q]);
+    d.p_w = maxf + 1;
+    for (int64_t f = 0; f < d.p_w; ++f) d.col.push_back(bins + f * n);
+    std::vector<uint32_t> rv(rows, rows + n_rows);
+    std::vector<int32_t> fv(feats, feats + n_feats);
+    uint64_t W = 0, T = 0;
+    for (uint32_t i : rv) {
+        W += w[i];
+        T += (uint64_t)w[i] * (uint64_t)yq[i];
+    }
+    const Cand c = best_split_reg(d, rv, w, fv, W, T);
+    const bool found = c.valid && positive_gain(c, T * T, W);
+    out[0] = found;
+    out[1] = (uint64_t)c.q;
+    out[2] = (uint64_t)c.b;
+    out[3] = c.nl;
+    out[4] = c.sl;
+    out[5] = c.nr;
+    out[6] = c.sr;
+    out[7] = found ? gain_fixed_reg(c, T * T, W) : 0;
+    return 0;
+}
+
+}  // extern "C"
+
+namespace {
+
+int fit_run(Run& run, int n_trees, int max_iter, int rough, int8_t* decision_out,
+            double* imp_history_out, int32_t* hits_out, double* shadow_max_out,
+            int32_t* n_iter_out, oracle_trace_fn trace, void* trace_user) {
+    const int64_t p = run.p;
     std::vector<double> smax_all((size_t)max_iter, 0.0);
     std::vector<int8_t> state(p, 0);
     std::vector<int32_t> hits(p, 0);
@@ -1003,6 +1169,10 @@ int oracle_boruta_fit_ext(const float* X, const int32_t* y, int64_t n, int64_t p
     *n_iter_out = t;
     return 0;
 }
+
+}  // namespace
+
+extern "C" {
 
 // Final ranking of Algorithm 1: confirmed features rank 1, undecided ones 2,
 // rejected ones by descending historical importance from 3 on.  Reading: a

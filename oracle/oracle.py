@@ -86,6 +86,13 @@ def lib():
                                             u64, i32, i32, i32, i32, i32, i32, P, P, P, P, P,
                                             TRACE_FN, P]
         L.oracle_boruta_fit_ext.restype = i32
+        L.oracle_boruta_fit_reg.argtypes = [P, P, i64, i64, i32, i32, i32, i32, i32, f64, u64,
+                                            i32, i32, P, P, P, P, P, TRACE_FN, P]
+        L.oracle_boruta_fit_reg.restype = i32
+        L.oracle_quantize_target.argtypes = [P, i64, P]
+        L.oracle_quantize_target.restype = None
+        L.oracle_best_split_reg.argtypes = [P, i64, P, P, P, i64, P, i32, i32, P]
+        L.oracle_best_split_reg.restype = i32
         L.oracle_shadow_threshold.argtypes = [P, i32, i32]
         L.oracle_shadow_threshold.restype = i64
         L.oracle_rough_fix.argtypes = [P, P, P, i64, i32]
@@ -160,6 +167,28 @@ def best_split(bins, y, w, rows, feats, n_classes, n_bins):
     return {k: int(v) for k, v in zip(keys, out)}
 
 
+def best_split_reg(bins, yq, w, rows, feats, n_bins):
+    bins = np.ascontiguousarray(bins, dtype=np.uint8)
+    yq = np.ascontiguousarray(yq, dtype=np.int32)
+    w = np.ascontiguousarray(w, dtype=np.uint32)
+    rows = np.ascontiguousarray(rows, dtype=np.uint32)
+    feats = np.ascontiguousarray(feats, dtype=np.int32)
+    out = np.zeros(8, dtype=np.uint64)
+    rc = lib().oracle_best_split_reg(_ptr(bins), bins.shape[1], _ptr(yq), _ptr(w), _ptr(rows),
+                                     len(rows), _ptr(feats), len(feats), n_bins, _ptr(out))
+    if rc:
+        raise ValueError("oracle_best_split_reg failed")
+    keys = ["found", "q", "b", "nl", "sl", "nr", "sr", "gain_fix"]
+    return {k: int(v) for k, v in zip(keys, out)}
+
+
+def quantize_target(y):
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    out = np.zeros(y.shape[0], dtype=np.int32)
+    lib().oracle_quantize_target(_ptr(y), y.shape[0], _ptr(out))
+    return out
+
+
 def grow_tree(bins, y, w, n_classes, n_bins, max_depth, mtry, seed, t, tree):
     bins = np.ascontiguousarray(bins, dtype=np.uint8)
     p_w, n = bins.shape
@@ -221,6 +250,32 @@ def boruta_fit(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=0, m
     rank = np.zeros(p, dtype=np.int32)
     hist_c = np.ascontiguousarray(hist)
     lib().oracle_rank(_ptr(dec), _ptr(hist_c), p, n_iter.value, _ptr(rank))
+    return {"decision": dec, "imp_history": hist, "hits": hits, "shadow_max": smax,
+            "n_iter": n_iter.value, "traces": traces, "rc": rc, "rank": rank}
+
+
+def boruta_fit_reg(X, y, n_trees, max_depth, mtry=0, importance_mode=0, max_iter=20,
+                   alpha=0.05, seed=0, n_bins=256, n_threads=0, trace=False):
+    """Regression Boruta (TreeImp): y float targets."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    n, p = X.shape
+    dec = np.zeros(p, dtype=np.int8)
+    hist = np.full((max_iter, p), np.nan)
+    hits = np.zeros(p, dtype=np.int32)
+    smax = np.full(max_iter, np.nan)
+    n_iter = ctypes.c_int32(0)
+    traces = []
+    cb = _trace_collector(traces) if trace else TRACE_FN()
+    rc = lib().oracle_boruta_fit_reg(_ptr(X), _ptr(y), n, p, n_trees, max_depth, mtry,
+                                     importance_mode, max_iter, alpha, seed, n_bins, n_threads,
+                                     _ptr(dec), _ptr(hist), _ptr(hits), _ptr(smax),
+                                     ctypes.cast(ctypes.byref(n_iter), ctypes.c_void_p), cb,
+                                     None)
+    if rc:
+        raise ValueError(f"oracle_boruta_fit_reg failed: {rc}")
+    rank = np.zeros(p, dtype=np.int32)
+    lib().oracle_rank(_ptr(dec), _ptr(np.ascontiguousarray(hist)), p, n_iter.value, _ptr(rank))
     return {"decision": dec, "imp_history": hist, "hits": hits, "shadow_max": smax,
             "n_iter": n_iter.value, "traces": traces, "rc": rc, "rank": rank}
 
