@@ -10,7 +10,7 @@ memory (torch tensors) before the timed region; binning happens once per
 job, at session creation, outside it.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload madelon|planted|omics|manyjob|scale]
+                    [--workload madelon|planted|omics|manyjob|scale|regression]
 """
 import argparse
 import json
@@ -33,7 +33,8 @@ def parse():
     ap.add_argument("--mode", choices=["treeimp", "permut", "kl", "workload"], default="workload",
                     help="importance mode (default: the workload's own); kl = Algorithm 3's "
                          "prediction divergence")
-    ap.add_argument("--workload", choices=["madelon", "planted", "omics", "manyjob", "scale"],
+    ap.add_argument("--workload", choices=["madelon", "planted", "omics", "manyjob", "scale",
+                                           "regression"],
                     default="madelon")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the other-mode / exact / plain comparison legs")
@@ -73,7 +74,7 @@ def workload(name):
         keys = {"jobs": 64, "n_trees": 100, "max_depth": 10, "n_bins": 256,
                 "seeds": "8000+j"}
     else:
-        idx = {"planted": 0, "madelon": 1, "omics": 2, "scale": 4}[name]
+        idx = {"planted": 0, "madelon": 1, "omics": 2, "scale": 4, "regression": 5}[name]
         cs = [synth.config(idx)]
         pr = cs[0]["params"]
         n, p = cs[0]["X"].shape
@@ -83,11 +84,14 @@ def workload(name):
                        "200 trees depth 12",
             "omics": "omics-shaped n=2000 p=20000 K=2 log-normal, 256 bins, 500 trees depth 12",
             "scale": "mixed-type n=100000 p=2000 K=4, 256 bins, 300 trees depth 16",
+            "regression": "regression n=10000 p=50 U(0,1) (10 informative), float target, "
+                          "256 bins, 200 trees depth 12",
         }[name]
         keys = {"n": n, "p": p, "n_trees": pr["n_trees"], "max_depth": pr["max_depth"],
                 "n_bins": pr["n_bins"], "seed": cs[0]["seed"]}
-    jobs = [dict(X=c["X"], y=c["y"], n_classes=c["n_classes"],
-                 n_trees=c["params"]["n_trees"], max_depth=c["params"]["max_depth"],
+    jobs = [dict({"y_reg": c["y_reg"]} if "y_reg" in c else
+                 {"y": c["y"], "n_classes": c["n_classes"]},
+                 X=c["X"], n_trees=c["params"]["n_trees"], max_depth=c["params"]["max_depth"],
                  mtry=c["params"]["mtry"], importance_mode=c["params"]["importance_mode"],
                  max_iter=c["params"]["max_iter"], alpha=c["params"]["alpha"], seed=c["seed"])
             for c in cs]
@@ -104,11 +108,13 @@ def run_gpu(jobs, pr, steps, warmup, form, rank, stats, graph=True, tune=None):
     for jd in jobs:
         d = dict(jd)
         d["X"] = torch.from_numpy(jd["X"]).cuda()
-        d["y"] = torch.from_numpy(jd["y"]).cuda()
+        for key in ("y", "y_reg"):
+            if key in jd:
+                d[key] = torch.from_numpy(jd[key]).cuda()
         d["max_iter"] = min(jd["max_iter"], 1000, warmup + steps)
         dev.append(d)
-        shapes.append(dict(n=d["X"].shape[0], p=d["X"].shape[1],
-                           **{k: v for k, v in d.items() if k not in ("X", "y")}))
+        shapes.append(dict(n=d["X"].shape[0], p=d["X"].shape[1], regression="y_reg" in jd,
+                           **{k: v for k, v in d.items() if k not in ("X", "y", "y_reg")}))
     ws_bytes = B.boruta_workspace_size(shapes, n_bins=pr["n_bins"], n_perm=pr["n_perm"],
                                        tune=tune)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
@@ -255,6 +261,23 @@ def cpu_baseline(name, jobs, pr):
                 "one_core": {"value": round(k / (one * jd["n_trees"]), 5), "unit": "iters/s",
                              "sample": f"trees 0..{k - 1} of iteration 1 on one thread in "
                                        f"{one:.2f}s, scaled by {jd['n_trees']}/{k}"}}
+    if name == "regression":
+        jd = jobs[0]
+        t_bin = bin_time(jd)
+        t0 = time.perf_counter()
+        O.boruta_fit_reg(jd["X"], jd["y_reg"], jd["n_trees"], jd["max_depth"], max_iter=1,
+                         seed=jd["seed"], n_bins=pr["n_bins"], n_threads=cores)
+        one_it = max(1e-3, time.perf_counter() - t0 - t_bin)
+        it = int(max(1, min(jd["max_iter"], 10.0 // one_it)))
+        t0 = time.perf_counter()
+        r = O.boruta_fit_reg(jd["X"], jd["y_reg"], jd["n_trees"], jd["max_depth"], max_iter=it,
+                             seed=jd["seed"], n_bins=pr["n_bins"], n_threads=cores)
+        spent = time.perf_counter() - t0 - t_bin
+        return {"value": round(r["n_iter"] / spent, 5), "unit": "iters/s", "cores": cores,
+                "kind": "oracle",
+                "sample": f"iterations 1..{r['n_iter']} in sequence (all {jd['n_trees']} "
+                          f"trees each) on {cores} threads: {spent:.2f}s; the binning "
+                          f"({t_bin:.2f}s) is left out"}
     if name in ("omics", "scale"):
         jd = jobs[0]
         p = jd["X"].shape[1]
@@ -343,15 +366,17 @@ def main():
                            for d in range(max(j["max_depth"] for j in jobs))],
                  "large": [round(st.level_large[d] / n_steps, 1)
                            for d in range(max(j["max_depth"] for j in jobs))]}}
+    regression = any("y_reg" in jd for jd in jobs)
     if not args.no_compare:
         k = max(1, min(5, args.steps))
-        other = [dict(jd, importance_mode=B.PERMUT if jd["importance_mode"] == B.TREEIMP
-                      else B.TREEIMP) for jd in jobs]
-        leg = run_gpu(other, pr, k, args.warmup, B.FORM_BATCHED, B.RANK_FP32, stats=False,
-                      tune=tune)
-        extra["other_mode_" + unit.replace("/", "_per_")] = round(
-            leg["job_iters"] / leg["seconds"], 3)
-        if mode != B.PERMUT_KL:
+        if not regression:  # the regression forest has TreeImp only
+            other = [dict(jd, importance_mode=B.PERMUT if jd["importance_mode"] == B.TREEIMP
+                          else B.TREEIMP) for jd in jobs]
+            leg = run_gpu(other, pr, k, args.warmup, B.FORM_BATCHED, B.RANK_FP32,
+                          stats=False, tune=tune)
+            extra["other_mode_" + unit.replace("/", "_per_")] = round(
+                leg["job_iters"] / leg["seconds"], 3)
+        if mode != B.PERMUT_KL and not regression:
             kl = [dict(jd, importance_mode=B.PERMUT_KL) for jd in jobs]
             leg = run_gpu(kl, pr, k, args.warmup, B.FORM_BATCHED, B.RANK_FP32, stats=False,
                           tune=tune)

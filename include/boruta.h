@@ -209,7 +209,30 @@ int boruta_fit_ex(const float* X, const int32_t* y, int64_t n, int64_t p, int32_
                   int8_t* decision_out, double* imp_history_out, int32_t* hits_out,
                   double* shadow_max_out, int32_t* n_iter_out);
 
-/* One job of a batch: the problem arguments of boruta_fit. */
+/* Regression Boruta (the paper's regression experiments run Boruta on a
+ * random-forest regressor), TreeImp importance (importance_mode 0; others
+ * return BORUTA_E_UNSUPPORTED).  y: [n] float32 targets, finite, n <= 65536
+ * (else BORUTA_E_INVALID_ARG; non-finite X or y: BORUTA_E_NONFINITE).  The
+ * targets are quantised to levels 0..255, floor((y - min) 255 / (max - min) +
+ * 1/2) in double (all 0 for a constant target); a split maximises
+ * T_L^2/W_L + T_R^2/W_R (W: bootstrap weight, T: weighted level sum of a
+ * child), i.e. minimises the children's weighted squared error, with the
+ * exact comparison and tie-break of the classification rule, and Algorithm 2
+ * accumulates floor(2^33 D / 255) per split, D the squared-error decrease.
+ * Each in-bag row is held as two records, class 0 with weight w (255 - y) and
+ * class 1 with weight w y, whose Gini decrease equals 2 D / 255, so the
+ * classification kernels grow the forest unchanged.  Arguments and outputs
+ * otherwise as boruta_fit_ex; in a trace a node's weighted count is 255 W and
+ * a leaf's class is 1 when T > 255 W - T, else 0. */
+int boruta_fit_regression(const float* X, const float* y, int64_t n, int64_t p, int32_t n_trees,
+                          int32_t max_depth, int32_t mtry, int32_t importance_mode,
+                          int32_t max_iter, double alpha, uint64_t seed, const boruta_options* opt,
+                          int8_t* decision_out, double* imp_history_out, int32_t* hits_out,
+                          double* shadow_max_out, int32_t* n_iter_out);
+
+/* One job of a batch: the problem arguments of boruta_fit.  With y_reg set
+ * the job is a regression job as in boruta_fit_regression: y_reg holds its
+ * [n] float targets (host or device like X), y and n_classes are ignored. */
 typedef struct {
     const float* X;
     const int32_t* y;
@@ -217,6 +240,7 @@ typedef struct {
     int32_t n_classes, n_trees, max_depth, mtry, importance_mode, max_iter;
     double alpha;
     uint64_t seed;
+    const float* y_reg;  /* nullable */
 } boruta_job;
 
 /* Caller-allocated outputs of one job (same meaning as boruta_fit). */

@@ -37,7 +37,7 @@ def signature(jobs, n_bins=256, n_perm=1):
     parts = [f"B{n_bins}", f"R{n_perm}"]
     for jd in jobs:
         n, p = jd["X"].shape
-        parts.append(f"{n}x{p}K{jd['n_classes']}T{jd['n_trees']}D{jd['max_depth']}"
+        parts.append(f"{n}x{p}K{jd.get('n_classes', 'reg')}T{jd['n_trees']}D{jd['max_depth']}"
                      f"m{jd.get('mtry', 0)}i{jd.get('importance_mode', 0)}")
     return "|".join(parts)
 
@@ -86,11 +86,13 @@ def autotune(jobs, n_bins=256, n_perm=1, steps=3, warmup=2, cache=None, log=None
     for jd in jobs:
         d = dict(jd)
         d["X"] = torch.from_numpy(jd["X"]).cuda()
-        d["y"] = torch.from_numpy(jd["y"]).cuda()
+        for key in ("y", "y_reg"):
+            if key in jd:
+                d[key] = torch.from_numpy(jd[key]).cuda()
         d["max_iter"] = min(jd.get("max_iter", 20), warmup + steps)
         dev.append(d)
-        shapes.append(dict(n=d["X"].shape[0], p=d["X"].shape[1],
-                           **{k: v for k, v in d.items() if k not in ("X", "y")}))
+        shapes.append(dict(n=d["X"].shape[0], p=d["X"].shape[1], regression="y_reg" in jd,
+                           **{k: v for k, v in d.items() if k not in ("X", "y", "y_reg")}))
     best = {}
     best_ms = _time_session(dev, shapes, n_bins, n_perm, best, steps, warmup)
     trials = [({}, best_ms)]

@@ -75,7 +75,7 @@ class Job(ctypes.Structure):
                 ("n_trees", ctypes.c_int32), ("max_depth", ctypes.c_int32),
                 ("mtry", ctypes.c_int32), ("importance_mode", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("alpha", ctypes.c_double),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("y_reg", ctypes.c_void_p)]
 
 
 class Result(ctypes.Structure):
@@ -86,7 +86,7 @@ class Result(ctypes.Structure):
 
 
 EXPORTS = ["boruta_default_options", "boruta_fit", "boruta_fit_ex", "boruta_fit_batch",
-           "boruta_fit_seeds",
+           "boruta_fit_seeds", "boruta_fit_regression",
            "boruta_workspace_size", "boruta_fit_device", "boruta_session_create",
            "boruta_session_step", "boruta_session_result", "boruta_session_resume",
            "boruta_session_destroy", "boruta_probe_copy", "boruta_last_error"]
@@ -122,6 +122,9 @@ def lib():
         L.boruta_fit_batch.argtypes = [ctypes.POINTER(Job), i32, ctypes.POINTER(Options),
                                        ctypes.POINTER(Result)]
         L.boruta_fit_batch.restype = ctypes.c_int
+        L.boruta_fit_regression.argtypes = [P, P, i64, i64, i32, i32, i32, i32, i32, f64, u64,
+                                            ctypes.POINTER(Options), P, P, P, P, P]
+        L.boruta_fit_regression.restype = ctypes.c_int
         L.boruta_fit_seeds.argtypes = [P, P, i64, i64, i32, i32, i32, i32, i32, i32, f64, P,
                                        i32, ctypes.POINTER(Options), P, P,
                                        ctypes.POINTER(Result)]
@@ -250,6 +253,33 @@ def boruta_fit_ex(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=T
     return out
 
 
+def boruta_fit_regression(X, y, n_trees, max_depth, mtry=0, importance_mode=TREEIMP,
+                          max_iter=20, alpha=0.05, seed=0, n_bins=256, split_rank=RANK_FP32,
+                          form=FORM_BATCHED, trace=False, stats=False, graph=True, tune=None,
+                          perc=100, rough_fix=False):
+    """Regression Boruta: y float targets (see boruta_fit_regression in
+    include/boruta.h)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    n, p = X.shape
+    dec = np.zeros(p, np.int8)
+    hist = np.full((max_iter, p), np.nan)
+    hits = np.zeros(p, np.int32)
+    smax = np.full(max_iter, np.nan)
+    n_iter = np.zeros(1, np.int32)
+    o, keep = make_options(n_bins, 1, split_rank, form, trace, stats, p, graph, tune, perc,
+                           rough_fix)
+    rc = lib().boruta_fit_regression(_ptr(X), _ptr(y), n, p, n_trees, max_depth, mtry,
+                                     importance_mode, max_iter, alpha, seed, ctypes.byref(o),
+                                     _ptr(dec), _ptr(hist), _ptr(hits), _ptr(smax), _ptr(n_iter))
+    _check(rc)
+    out = {"decision": dec, "imp_history": hist, "hits": hits, "shadow_max": smax,
+           "n_iter": int(n_iter[0]), "traces": keep["iters"]}
+    if stats:
+        out["stats"] = keep["stats"]
+    return out
+
+
 def boruta_fit(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=TREEIMP,
                max_iter=20, alpha=0.05, seed=0):
     X = np.ascontiguousarray(X, dtype=np.float32)
@@ -280,16 +310,24 @@ def _job(X, y, n_classes, n_trees, max_depth, mtry, importance_mode, max_iter, a
 def boruta_fit_batch(jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED,
                      trace=False, stats=False, perc=100, rough_fix=False):
     """jobs: list of dicts with X, y, n_classes, n_trees, max_depth and optional mtry,
-    importance_mode, max_iter, alpha, seed."""
+    importance_mode, max_iter, alpha, seed; a regression job has y_reg (float
+    targets) instead of y and n_classes."""
     arrs, cj, res, outs = [], (Job * len(jobs))(), (Result * len(jobs))(), []
     for i, jd in enumerate(jobs):
         X = np.ascontiguousarray(jd["X"], dtype=np.float32)
-        y = np.ascontiguousarray(jd["y"], dtype=np.int32)
+        yr = None
+        if jd.get("y_reg") is not None:
+            yr = np.ascontiguousarray(jd["y_reg"], dtype=np.float32)
+            y = np.zeros(1, np.int32)
+        else:
+            y = np.ascontiguousarray(jd["y"], dtype=np.int32)
         max_iter = jd.get("max_iter", 20)
         p = X.shape[1]
-        cj[i] = _job(X, y, jd["n_classes"], jd["n_trees"], jd["max_depth"], jd.get("mtry", 0),
-                     jd.get("importance_mode", TREEIMP), max_iter, jd.get("alpha", 0.05),
-                     jd.get("seed", 0))
+        cj[i] = _job(X, y, jd.get("n_classes", 2), jd["n_trees"], jd["max_depth"],
+                     jd.get("mtry", 0), jd.get("importance_mode", TREEIMP), max_iter,
+                     jd.get("alpha", 0.05), jd.get("seed", 0))
+        if yr is not None:
+            cj[i].y_reg = yr.ctypes.data
         o = {"decision": np.zeros(p, np.int8), "imp_history": np.full((max_iter, p), np.nan),
              "hits": np.zeros(p, np.int32), "shadow_max": np.full(max_iter, np.nan),
              "rank": np.zeros(p, np.int32)}
@@ -298,7 +336,7 @@ def boruta_fit_batch(jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM
         res[i].hits = o["hits"].ctypes.data
         res[i].shadow_max = o["shadow_max"].ctypes.data
         res[i].rank = o["rank"].ctypes.data
-        arrs.append((X, y))
+        arrs.append((X, y, yr))
         outs.append(o)
     p_all = [int(np.shape(jd["X"])[1]) for jd in jobs]
     opt, keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p_all,
@@ -356,9 +394,12 @@ def boruta_workspace_size(jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32,
         j = Job()
         j.X, j.y = 1, 1
         j.n, j.p = jd["n"], jd["p"]
-        j.n_classes, j.n_trees, j.max_depth = jd["n_classes"], jd["n_trees"], jd["max_depth"]
+        j.n_classes, j.n_trees, j.max_depth = jd.get("n_classes", 2), jd["n_trees"], \
+            jd["max_depth"]
         j.mtry, j.importance_mode = jd.get("mtry", 0), jd.get("importance_mode", TREEIMP)
         j.max_iter, j.alpha, j.seed = jd.get("max_iter", 20), jd.get("alpha", 0.05), 0
+        if jd.get("regression"):
+            j.y_reg = 1
         cj[i] = j
     opt, _ = make_options(n_bins, n_perm, split_rank, form, tune=tune)
     out = ctypes.c_size_t(0)
@@ -414,19 +455,27 @@ class Session:
         self._arrays, cj = [], (Job * len(jobs))()
         self._shapes = []
         for i, jd in enumerate(jobs):
+            yr, rp = jd.get("y_reg"), None
             if inputs_on_device:
-                X, y = jd["X"], jd["y"]
-                xp, yp = X.data_ptr(), y.data_ptr()
+                X, y = jd["X"], jd.get("y")
+                xp = X.data_ptr()
+                yp = y.data_ptr() if y is not None else None
+                rp = yr.data_ptr() if yr is not None else None
                 n, p = X.shape
             else:
                 X = np.ascontiguousarray(jd["X"], dtype=np.float32)
-                y = np.ascontiguousarray(jd["y"], dtype=np.int32)
-                xp, yp = X.ctypes.data, y.ctypes.data
+                y = np.ascontiguousarray(jd["y"], dtype=np.int32) if yr is None else None
+                if yr is not None:
+                    yr = np.ascontiguousarray(yr, dtype=np.float32)
+                    rp = yr.ctypes.data
+                xp, yp = X.ctypes.data, (y.ctypes.data if y is not None else None)
                 n, p = X.shape
-            self._arrays.append((X, y))
+            self._arrays.append((X, y, yr))
             j = Job()
             j.X, j.y, j.n, j.p = xp, yp, n, p
-            j.n_classes, j.n_trees, j.max_depth = jd["n_classes"], jd["n_trees"], jd["max_depth"]
+            j.y_reg = rp
+            j.n_classes = jd.get("n_classes", 2)
+            j.n_trees, j.max_depth = jd["n_trees"], jd["max_depth"]
             j.mtry, j.importance_mode = jd.get("mtry", 0), jd.get("importance_mode", TREEIMP)
             j.max_iter, j.alpha, j.seed = jd.get("max_iter", 20), jd.get("alpha", 0.05), \
                 jd.get("seed", 0)

@@ -230,6 +230,9 @@ struct JobDev {
     int32_t pw_cap;        // p + max_sha
     uint32_t gbase;        // first global column id of the job (column-major histogram path)
     uint32_t gq;           // 16-byte words of one bin column (n_pad / 16)
+    uint32_t rstride;      // row records per tree: n, or 2n for a regression job
+    int32_t reg;           // regression: y holds target levels 0..255, and each in-bag
+                           // row is two records (class 0 weight w(255 - y), class 1 w y)
     const uint8_t* y;      // [n]
     uint8_t* orig;         // [p][n_pad] binned originals
     uint8_t* sha;          // [max_sha][n_pad] shadows of the current iteration
@@ -245,7 +248,7 @@ struct JobDev {
     uint64_t* G;           // [T][pw_cap] per-tree fixed-point Gini decreases
     int64_t* imp;          // [pw_cap] integer importance of the iteration
     uint32_t* wbuf;        // [T][n] bootstrap multiplicities
-    uint64_t* rec[2];      // [T][n] row records, ping-pong by level parity
+    uint64_t* rec[2];      // [T][rstride] row records, ping-pong by level parity
     uint32_t* oob;         // [T][n] out-of-bag rows, ascending
     int32_t* tstat;        // [T][4] distinct in-bag, OOB rows, OOB correct, spare
     // per iteration, written on the device

@@ -21,6 +21,8 @@ namespace boruta {
 
 // launchers (k_prep.hip)
 void launch_validate(const float*, size_t, const int32_t*, size_t, int, uint32_t*, hipStream_t);
+void launch_validate_reg(const float*, size_t, const float*, size_t, uint32_t*, hipStream_t);
+void launch_target_levels(const float*, size_t, uint8_t*, hipStream_t);
 void launch_labels(const int32_t*, size_t, uint8_t*, hipStream_t);
 void launch_binning(const float*, int64_t, int64_t, int, uint8_t*, int64_t, uint32_t*, int64_t,
                     hipStream_t);
@@ -71,6 +73,9 @@ constexpr size_t kColAutoBytes = size_t(128) << 20;
 constexpr int kColNever = 64;
 // KL importance: bound of its per-block difference buffer.
 constexpr uint64_t kKlDeltaBytes = uint64_t(256) << 20;
+// Regression jobs: at most this many rows, so that the channel counts of a
+// node (255 times its bootstrap weight) stay below 2^24.
+constexpr int64_t kRegMaxRows = 65536;
 
 struct Error : std::runtime_error {
     int code;
@@ -91,6 +96,9 @@ struct Spec {
     int K, T, D, mtry, mode, max_iter;
     double alpha;
     uint64_t seed;
+    // regression: float targets [n] (y is null and K = 2, the two channels of
+    // the target levels); null for classification
+    const float* yr = nullptr;
     // an earlier job of the same batch with the same inputs (X, y, n, p, K):
     // its input copy, labels and binned matrix serve this job too (-1: none)
     int share = -1;
@@ -103,8 +111,8 @@ void mark_shared_inputs(std::vector<Spec>& specs) {
         specs[j].share = -1;
         for (size_t i = 0; i < j; ++i) {
             const Spec &a = specs[i], &b = specs[j];
-            if (a.share < 0 && a.X == b.X && a.y == b.y && a.n == b.n && a.p == b.p &&
-                a.K == b.K) {
+            if (a.share < 0 && a.X == b.X && a.y == b.y && a.yr == b.yr && a.n == b.n &&
+                a.p == b.p && a.K == b.K) {
                 specs[j].share = (int)i;
                 break;
             }
@@ -170,7 +178,12 @@ Opts read_opts(const boruta_options* o) {
 
 void check_spec(const Spec& s) {
     auto bad = [](const char* m) { throw Error(BORUTA_E_INVALID_ARG, m); };
-    if (!s.X || !s.y) bad("X and y must be non-null");
+    if (!s.X || (!s.y && !s.yr)) bad("X and y must be non-null");
+    if (s.yr) {
+        if (s.n > kRegMaxRows) bad("regression: n outside [2, 65536]");
+        if (s.mode != 0)
+            throw Error(BORUTA_E_UNSUPPORTED, "regression supports importance_mode 0 (TreeImp)");
+    }
     if (s.n < 2 || s.n > (int64_t(1) << 24)) bad("n outside [2, 2^24]");
     if (s.p < 1 || s.p > (int64_t(1) << 24)) bad("p outside [1, 2^24]");
     if (s.K < 2 || s.K > 16) bad("n_classes outside [2, 16]");
@@ -278,8 +291,10 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
         j.G = s.mode == 0 ? r.take(T * j.pw_cap * 8) : 0;
         j.imp = r.take((size_t)j.pw_cap * 8);
         j.wbuf = r.take(T * n * 4);
-        j.rec0 = r.take(T * n * 8);
-        j.rec1 = r.take(T * n * 8);
+        // regression rows are two records each
+        const size_t rs = s.yr ? 2 * n : n;
+        j.rec0 = r.take(T * rs * 8);
+        j.rec1 = r.take(T * rs * 8);
         j.oob = r.take(T * n * 4);
         j.tstat = r.take(T * 16);
         j.rmean = r.take(p * 8);
@@ -555,13 +570,21 @@ void Engine::setup(std::vector<int>& status) {
             if (status[j] != BORUTA_OK) continue;
         } else {
             const float* X = dev_in ? s.X : at<float>(jp.X);
+            // classification labels, or the regression targets (same buffer size)
             const int32_t* y = dev_in ? s.y : at<int32_t>(jp.y32);
+            const float* yr = dev_in ? s.yr : at<float>(jp.y32);
             if (!dev_in) {
                 h2d((void*)X, s.X, (size_t)s.n * s.p * 4);
-                h2d((void*)y, s.y, (size_t)s.n * 4);
+                if (s.yr)
+                    h2d((void*)yr, s.yr, (size_t)s.n * 4);
+                else
+                    h2d((void*)y, s.y, (size_t)s.n * 4);
             }
             launch_fill_u32(flags, 1, 0u, st);
-            launch_validate(X, (size_t)s.n * s.p, y, (size_t)s.n, s.K, flags, st);
+            if (s.yr)
+                launch_validate_reg(X, (size_t)s.n * s.p, yr, (size_t)s.n, flags, st);
+            else
+                launch_validate(X, (size_t)s.n * s.p, y, (size_t)s.n, s.K, flags, st);
             uint32_t f = 0;
             d2h(&f, flags, 4);
             if (f & 1u) {
@@ -572,7 +595,10 @@ void Engine::setup(std::vector<int>& status) {
                 status[j] = BORUTA_E_INVALID_ARG;
                 continue;
             }
-            launch_labels(y, (size_t)s.n, at<uint8_t>(jp.y8), st);
+            if (s.yr)
+                launch_target_levels(yr, (size_t)s.n, at<uint8_t>(jp.y8), st);
+            else
+                launch_labels(y, (size_t)s.n, at<uint8_t>(jp.y8), st);
             launch_binning(X, s.n, s.p, O.B, at<uint8_t>(jp.orig), jp.n_pad,
                            at<uint32_t>(pl.keys), jp.P, st);
         }
@@ -599,6 +625,8 @@ void Engine::setup(std::vector<int>& status) {
         J.pw_cap = jp.pw_cap;
         J.gbase = jp.gbase;
         J.gq = (uint32_t)(jp.n_pad / 16);
+        J.reg = s.yr ? 1 : 0;
+        J.rstride = (uint32_t)(s.yr ? 2 * s.n : s.n);
         J.y = at<uint8_t>(jp.y8);
         J.orig = at<uint8_t>(jp.orig);
         J.sha = at<uint8_t>(jp.sha);
@@ -1220,6 +1248,29 @@ int boruta_fit_ex(const float* X, const int32_t* y, int64_t n, int64_t p, int32_
     return finish_single(rc, outs, n_iter_out);
 }
 
+int boruta_fit_regression(const float* X, const float* y, int64_t n, int64_t p, int32_t n_trees,
+                          int32_t max_depth, int32_t mtry, int32_t importance_mode,
+                          int32_t max_iter, double alpha, uint64_t seed, const boruta_options* opt,
+                          int8_t* decision_out, double* imp_history_out, int32_t* hits_out,
+                          double* shadow_max_out, int32_t* n_iter_out) {
+    if (!decision_out || !imp_history_out || !n_iter_out) {
+        g_err = "decision_out, imp_history_out and n_iter_out must be non-null";
+        return BORUTA_E_INVALID_ARG;
+    }
+    Spec sp = spec_from(X, nullptr, n, p, 2, n_trees, max_depth, mtry, importance_mode, max_iter,
+                        alpha, seed);
+    sp.yr = y;
+    std::vector<Spec> specs{sp};
+    std::vector<Out> outs(1);
+    outs[0].decision = decision_out;
+    outs[0].hist = imp_history_out;
+    outs[0].hits = hits_out;
+    outs[0].smax = shadow_max_out;
+    std::vector<int> status(1, BORUTA_OK);
+    const int rc = run_jobs(specs, opt, outs, status, false, nullptr, 0, nullptr);
+    return finish_single(rc, outs, n_iter_out);
+}
+
 int boruta_fit_seeds(const float* X, const int32_t* y, int64_t n, int64_t p, int32_t n_classes,
                      int32_t n_trees, int32_t max_depth, int32_t mtry, int32_t importance_mode,
                      int32_t max_iter, double alpha, const uint64_t* seeds, int32_t n_seeds,
@@ -1295,8 +1346,11 @@ static std::vector<Spec> specs_of(const boruta_job* jobs, int32_t n_jobs) {
     std::vector<Spec> specs;
     for (int i = 0; i < n_jobs; ++i) {
         const boruta_job& b = jobs[i];
-        specs.push_back(spec_from(b.X, b.y, b.n, b.p, b.n_classes, b.n_trees, b.max_depth,
-                                  b.mtry, b.importance_mode, b.max_iter, b.alpha, b.seed));
+        Spec sp = spec_from(b.X, b.y_reg ? nullptr : b.y, b.n, b.p, b.y_reg ? 2 : b.n_classes,
+                            b.n_trees, b.max_depth, b.mtry, b.importance_mode, b.max_iter,
+                            b.alpha, b.seed);
+        sp.yr = b.y_reg;
+        specs.push_back(sp);
     }
     return specs;
 }

@@ -34,11 +34,14 @@ namespace boruta {
 // ---------------------------------------------------------------------------
 // Per tree: compact the in-bag rows (multiplicity > 0, ascending) into row
 // records and the out-of-bag rows into a list; create the root node.  The
-// multiplicities are cleared behind the read.
+// multiplicities are cleared behind the read.  A regression row of level y
+// and multiplicity w becomes two records, class 0 with weight w (255 - y) and
+// class 1 with weight w y (a zero-weight one is left out): the Gini rule on
+// these two classes orders splits exactly as the weighted squared error does.
 __global__ __launch_bounds__(1024) void k_boot_compact(ForestDev F0) {
-    __shared__ uint32_t s_win[16], s_wout[16];
+    __shared__ uint32_t s_win[16], s_wout[16], s_rin[16];
     __shared__ uint32_t s_cls[16];
-    __shared__ uint32_t s_base_in, s_base_out;
+    __shared__ uint32_t s_base_in, s_base_out, s_base_rows;
     ForestDev F = F0;
     F.ctr = F0.ctrs;  // the roots form the lists of level 0
     const uint32_t g = blockIdx.x;
@@ -49,14 +52,16 @@ __global__ __launch_bounds__(1024) void k_boot_compact(ForestDev F0) {
         return;
     }
     const uint32_t n = (uint32_t)J.n;
+    const bool reg = J.reg != 0;
     uint32_t* w = J.wbuf + (size_t)tr.tau * n;
-    uint64_t* recs = J.rec[0] + (size_t)tr.tau * n;
+    uint64_t* recs = J.rec[0] + (size_t)tr.tau * J.rstride;
     uint32_t* oob = J.oob + (size_t)tr.tau * n;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid < 16) s_cls[tid] = 0;
     if (tid == 0) {
         s_base_in = 0;
         s_base_out = 0;
+        s_base_rows = 0;
     }
     __syncthreads();
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -65,10 +70,17 @@ __global__ __launch_bounds__(1024) void k_boot_compact(ForestDev F0) {
         const uint32_t wi = i < n ? w[i] : 0u;
         if (i < n) w[i] = 0;  // multiplicities start from zero next iteration
         const bool inb = i < n && wi > 0, isoob = i < n && wi == 0;
-        const uint64_t mi = __ballot(inb), mo = __ballot(isoob);
+        const uint32_t yi = inb ? (uint32_t)J.y[i] : 0u;
+        // the row's records: one (class yi, weight wi), or for regression up
+        // to two (class 0, weight w0) and (class 1, weight w1)
+        const uint32_t w0 = reg ? wi * (255u - yi) : wi, w1 = reg ? wi * yi : 0u;
+        const bool h0 = inb && w0 != 0, h1 = inb && w1 != 0;
+        const uint64_t m0 = __ballot(h0), m1 = __ballot(h1), mo = __ballot(isoob);
+        const uint64_t mi = __ballot(inb);
         if (lane == 0) {
-            s_win[wave] = __popcll(mi);
+            s_win[wave] = __popcll(m0) + __popcll(m1);
             s_wout[wave] = __popcll(mo);
+            s_rin[wave] = __popcll(mi);
         }
         __syncthreads();
         uint32_t pin = s_base_in, pout = s_base_out;
@@ -77,26 +89,30 @@ __global__ __launch_bounds__(1024) void k_boot_compact(ForestDev F0) {
             pout += s_wout[v];
         }
         if (inb) {
-            const uint32_t yi = J.y[i];
-            if (wi > 0xFFFFu) atomicOr(&F.ctr->overflow, 8u);
-            recs[pin + __popcll(mi & below)] = rec_pack(i, wi, yi);
-            atomicAdd(&s_cls[yi], wi);
+            if (w0 > 0xFFFFu || w1 > 0xFFFFu) atomicOr(&F.ctr->overflow, 8u);
+            const uint32_t at = pin + __popcll(m0 & below) + __popcll(m1 & below);
+            if (h0) recs[at] = rec_pack(i, w0, reg ? 0u : yi);
+            if (h1) recs[at + (h0 ? 1u : 0u)] = rec_pack(i, w1, 1u);
+            if (h0) atomicAdd(&s_cls[reg ? 0u : yi], w0);
+            if (h1) atomicAdd(&s_cls[1], w1);
         }
         if (isoob) oob[pout + __popcll(mo & below)] = i;
         __syncthreads();
         if (tid == 0) {
-            uint32_t ti = 0, to = 0;
+            uint32_t ti = 0, to = 0, tr_ = 0;
             for (int v = 0; v < 16; ++v) {
                 ti += s_win[v];
                 to += s_wout[v];
+                tr_ += s_rin[v];
             }
             s_base_in += ti;
             s_base_out += to;
+            s_base_rows += tr_;
         }
         __syncthreads();
     }
     if (tid == 0) {
-        J.tstat[tr.tau * 4 + 0] = (int32_t)s_base_in;
+        J.tstat[tr.tau * 4 + 0] = (int32_t)s_base_rows;
         J.tstat[tr.tau * 4 + 1] = (int32_t)s_base_out;
         J.tstat[tr.tau * 4 + 2] = 0;
         uint32_t counts[16], tot = 0;
@@ -155,7 +171,7 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out) {
     const TreeDev tr = F.trees[nd.tree];
     JobDev& J = F.jobs[tr.job];
     const int B = J.B;
-    const size_t tbase = (size_t)tr.tau * J.n + nd.seg;
+    const size_t tbase = (size_t)tr.tau * J.rstride + nd.seg;
     const uint64_t* rin = J.rec[F.parity] + tbase;
     uint64_t* rout = J.rec[F.parity ^ 1] + tbase;
     const int len = (int)uniform(nd.len);
@@ -721,7 +737,7 @@ __global__ __launch_bounds__(256) void k_draws(ForestDev F, int level) {
         SlotRec* sr = F.srec + slot;
         if (lane < 16) sr->cnode[lane] = lane < J.K ? F.cls[(size_t)id * F.kmax + lane] : 0u;
         if (lane == 0) {
-            sr->recs = J.rec[F.parity] + (size_t)tr.tau * J.n + nd.seg;
+            sr->recs = J.rec[F.parity] + (size_t)tr.tau * J.rstride + nd.seg;
             sr->id = id;
             sr->len = nd.len;
             sr->n = nd.n;
@@ -1161,7 +1177,7 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
         const bool part = (int)nd.depth + 1 < J.D && (nzl >= 2 || nzr >= 2);
         const uint8_t* col = ldg(J.colptr + best.f);
         const uint64_t* recs = sr.recs;
-        uint64_t* rout = J.rec[F.parity ^ 1] + (size_t)tr.tau * J.n + nd.seg;
+        uint64_t* rout = J.rec[F.parity ^ 1] + (size_t)tr.tau * J.rstride + nd.seg;
         constexpr int kR = 8;  // rows per lane per block: lane l owns rows [l kR, l kR + kR)
         const uint32_t len = part ? sr.len : 0u;
         uint32_t runl = 0, runr = 0;

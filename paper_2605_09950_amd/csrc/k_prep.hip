@@ -21,6 +21,57 @@ __global__ void k_validate(const float* X, size_t nx, const int32_t* y, size_t n
     if (bad) atomicOr(flags, bad);
 }
 
+// Regression inputs: X and the float targets must be finite (flag 1).
+__global__ void k_validate_reg(const float* X, size_t nx, const float* y, size_t n,
+                               uint32_t* flags) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    uint32_t bad = 0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nx; i += stride)
+        if (!isfinite(X[i])) bad |= 1u;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        if (!isfinite(y[i])) bad |= 1u;
+    if (bad) atomicOr(flags, bad);
+}
+
+// Regression targets to levels 0..255 (reading of the paper's regression
+// forest): floor((y - min) 255 / (max - min) + 1/2) in double, 0 for a
+// constant target.  One workgroup (n <= 65536): the exact minimum and
+// maximum, then the levels.
+__global__ __launch_bounds__(1024) void k_target_levels(const float* y, size_t n, uint8_t* out) {
+    __shared__ float s_lo[16], s_hi[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    float lo = y[0], hi = y[0];
+    for (size_t i = (size_t)tid; i < n; i += 1024) {
+        lo = fminf(lo, y[i]);
+        hi = fmaxf(hi, y[i]);
+    }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        lo = fminf(lo, __shfl_xor(lo, m));
+        hi = fmaxf(hi, __shfl_xor(hi, m));
+    }
+    if (lane == 0) {
+        s_lo[wave] = lo;
+        s_hi[wave] = hi;
+    }
+    __syncthreads();
+    lo = s_lo[0];
+    hi = s_hi[0];
+    for (int v = 1; v < 16; ++v) {
+        lo = fminf(lo, s_lo[v]);
+        hi = fmaxf(hi, s_hi[v]);
+    }
+    const double dlo = (double)lo, range = (double)hi - dlo;
+    for (size_t i = (size_t)tid; i < n; i += 1024) {
+        uint8_t q = 0;
+        if (range > 0.0) {
+            const double v = ((double)y[i] - dlo) * 255.0 / range;
+            q = (uint8_t)floor(v + 0.5);
+        }
+        out[i] = q;
+    }
+}
+
 __global__ void k_labels_u8(const int32_t* y, size_t n, uint8_t* out) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = (uint8_t)y[i];
@@ -367,6 +418,18 @@ void launch_validate(const float* X, size_t nx, const int32_t* y, size_t n, int 
     const size_t blocks = (nx + 255) / 256;
     hipLaunchKernelGGL(k_validate, dim3((unsigned)(blocks < 4096 ? (blocks ? blocks : 1) : 4096)),
                        dim3(256), 0, st, X, nx, y, n, K, flags);
+}
+
+void launch_validate_reg(const float* X, size_t nx, const float* y, size_t n, uint32_t* flags,
+                         hipStream_t st) {
+    const size_t blocks = (nx + 255) / 256;
+    hipLaunchKernelGGL(k_validate_reg,
+                       dim3((unsigned)(blocks < 4096 ? (blocks ? blocks : 1) : 4096)), dim3(256),
+                       0, st, X, nx, y, n, flags);
+}
+
+void launch_target_levels(const float* y, size_t n, uint8_t* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_target_levels, dim3(1), dim3(1024), 0, st, y, n, out);
 }
 
 void launch_labels(const int32_t* y, size_t n, uint8_t* out, hipStream_t st) {

@@ -12,6 +12,9 @@ Workloads (data seed / Boruta seed):
   2  omics-shaped           n=2000,   p=20000,  K=2, 500 trees depth 12, 100 iterations
   3  many small jobs        64 jobs, n in [200,5000], p in [50,2000], K in [2,5]
   4  precision + scale      n=100000, p=2000,   K=4, 300 trees depth 16, 100 iterations
+  5  regression             n=10000,  p=50 U(0,1), 10 informative, float target,
+                            200 trees depth 12, 100 iterations (the shape of the
+                            paper's synthetic regression set; our own function)
 """
 import numpy as np
 
@@ -122,6 +125,19 @@ def mixed_scale(seed=1004, n=100000, p=2000, n_inf=40, n_classes=4, depth=6):
     return X, y, inf
 
 
+def regression_like(seed=1005, n=10000, p=50, n_inf=10):
+    """Float target over 10 of 50 U(0,1) columns: linear, sine, product,
+    threshold and quadratic terms, plus N(0, sd 0.5) noise."""
+    rng = np.random.default_rng(seed)
+    X = rng.random((n, p)).astype(np.float32)
+    inf = np.sort(rng.choice(p, n_inf, replace=False))
+    Z = X[:, inf].astype(np.float64)
+    y = (5.0 * Z[:, 0] + 3.0 * np.sin(np.pi * Z[:, 1] * Z[:, 2]) + 4.0 * (Z[:, 3] - 0.5) ** 2
+         + 2.0 * (Z[:, 4] > 0.5) + 1.5 * Z[:, 5] * Z[:, 6] + Z[:, 7] - Z[:, 8]
+         + 0.5 * np.cos(2 * np.pi * Z[:, 9]) + rng.normal(0.0, 0.5, n))
+    return X, y.astype(np.float32), inf
+
+
 def config(i):
     """Workload i as a dict: X, y, informative columns and the run parameters."""
     if i == 0:
@@ -140,6 +156,10 @@ def config(i):
         X, y, inf = mixed_scale()
         return dict(X=X, y=y, informative=inf, n_classes=4, seed=7004,
                     params=_params(n_trees=300, max_depth=16, max_iter=100, n_perm=5))
+    if i == 5:
+        X, y, inf = regression_like()
+        return dict(X=X, y_reg=y, informative=inf, seed=7005,
+                    params=_params(n_trees=200, max_depth=12, max_iter=100))
     raise ValueError("workload 3 is a batch: use many_jobs()")
 
 

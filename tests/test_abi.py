@@ -139,6 +139,17 @@ def test_seed_count_rejected_on_host(seeds):
     assert e.value.code == B.BORUTA_E_INVALID_ARG
 
 
+def test_regression_arguments_checked_on_the_host():
+    X = np.zeros((70000, 2), np.float32)
+    with pytest.raises(B.BorutaError) as e:
+        B.boruta_fit_regression(X, np.zeros(70000, np.float32), 2, 2, max_iter=2)
+    assert e.value.code == B.BORUTA_E_INVALID_ARG
+    with pytest.raises(B.BorutaError) as e:
+        B.boruta_fit_regression(X[:50], np.zeros(50, np.float32), 2, 2, importance_mode=B.PERMUT)
+    assert e.value.code == B.BORUTA_E_UNSUPPORTED
+    assert "TreeImp" in B.boruta_last_error()
+
+
 def test_workspace_size_is_host_only():
     small = B.boruta_workspace_size([dict(n=500, p=20, n_classes=2, n_trees=50, max_depth=8)])
     big = B.boruta_workspace_size([dict(n=10000, p=500, n_classes=3, n_trees=200,
