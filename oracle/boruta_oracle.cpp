@@ -389,6 +389,31 @@ int predict(const std::vector<TNode>& nodes, const Data& d, uint32_t row, int32_
     return nodes[i].leaf_class;
 }
 
+// Leaf reached by a row, optionally with column sub_f's bin replaced by sub_b.
+int32_t predict_leaf(const std::vector<TNode>& nodes, const Data& d, uint32_t row, int32_t sub_f,
+                     int sub_b) {
+    int32_t i = 0;
+    while (nodes[i].feat >= 0) {
+        const int32_t f = nodes[i].feat;
+        const int b = (f == sub_f) ? sub_b : d.col[f][row];
+        i = (b <= nodes[i].thr) ? nodes[i].left : nodes[i].right;
+    }
+    return i;
+}
+
+// Regression prediction of a leaf: its mean target level T/W in 1/256 level
+// units, floor(256 T / W) (with the node's counts (255 W - T, T)), and the
+// squared error of a row of level y against it, in 1/65536 level^2 units.
+int64_t leaf_level_fix(const TNode& nd) {
+    const uint64_t N = nd.counts[0] + nd.counts[1];  // 255 W
+    return (int64_t)((256ull * (uint64_t)kLevels * nd.counts[1]) / N);
+}
+
+int64_t sq_error_fix(const TNode& nd, int32_t y) {
+    const int64_t e = leaf_level_fix(nd) - 256 * (int64_t)y;
+    return e * e;
+}
+
 struct TreeResult {
     std::vector<TNode> nodes;
     int64_t n_inbag = 0, n_oob = 0, oob_correct = 0;
@@ -425,18 +450,29 @@ void run_tree(const Data& d, const IterParams& ip, uint32_t tree, TreeResult& ou
     // tree's OOB rows (Kursa's importance): rows o_0 < o_1 < ... of the OOB
     // set; replica r of column f moves the bin of o_pi(j) into row o_j, with
     // pi the keyed bijection of [0, m) for (t, tree, f, r).
+    // For a regression forest the score of a row is the negated squared error
+    // of its leaf's mean level (sq_error_fix), so the drop is the increase of
+    // the squared error.
     const uint64_t m = oob.size();
-    std::vector<int> base(m);
+    std::vector<int64_t> base(m);
     for (uint64_t j = 0; j < m; ++j) {
-        base[j] = predict(out.nodes, d, oob[j], -1, 0) == d.y[oob[j]];
-        out.oob_correct += base[j];
+        if (d.reg) {
+            base[j] = -sq_error_fix(out.nodes[predict_leaf(out.nodes, d, oob[j], -1, 0)],
+                                    d.y[oob[j]]);
+        } else {
+            base[j] = predict(out.nodes, d, oob[j], -1, 0) == d.y[oob[j]];
+            out.oob_correct += base[j];
+        }
     }
     out.drop.assign(d.p_w, 0);
-    auto permuted_correct = [&](int32_t f, int r, uint64_t j) {
+    auto permuted_correct = [&](int32_t f, int r, uint64_t j) -> int64_t {
         const uint64_t src = keyed_perm(ip.seed, kStreamOobPerm, ip.t, tree, (uint32_t)f,
                                         (uint32_t)r << 16, m, j);
         const int sb = d.col[f][oob[src]];
-        return (int)(predict(out.nodes, d, oob[j], f, sb) == d.y[oob[j]]);
+        if (d.reg)
+            return -sq_error_fix(out.nodes[predict_leaf(out.nodes, d, oob[j], f, sb)],
+                                 d.y[oob[j]]);
+        return (int64_t)(predict(out.nodes, d, oob[j], f, sb) == d.y[oob[j]]);
     };
     if (ip.naive) {
         for (int32_t f = 0; f < d.p_w; ++f)
@@ -851,6 +887,7 @@ void iteration(const Run& run, int t, int8_t* state, int32_t* hits,
                 for (int64_t f = 0; f < d.p_w; ++f) imp[f] += r.drop[f];
             }
             denom = (double)((int64_t)run.R * oob_total);
+            if (run.reg) denom *= 65536.0;  // squared errors in 1/65536 level^2 units
         }
         auto report = [&](int64_t v) { return denom > 0.0 ? (double)v / denom : 0.0; };
         // Hit: strictly above the best shadow (Algorithm 1), or above the
@@ -1081,11 +1118,14 @@ int oracle_boruta_fit_ext(const float* X, const int32_t* y, int64_t n, int64_t p
 int oracle_boruta_fit_reg(const float* X, const float* y, int64_t n, int64_t p,
                           int32_t n_trees, int32_t max_depth, int32_t mtry,
                           int32_t importance_mode, int32_t max_iter, double alpha, uint64_t seed,
-                          int32_t n_bins, int32_t n_threads, int8_t* decision_out,
-                          double* imp_history_out, int32_t* hits_out, double* shadow_max_out,
-                          int32_t* n_iter_out, oracle_trace_fn trace, void* trace_user) {
+                          int32_t n_bins, int32_t n_perm, int32_t n_threads,
+                          int32_t permut_naive, int8_t* decision_out, double* imp_history_out,
+                          int32_t* hits_out, double* shadow_max_out, int32_t* n_iter_out,
+                          oracle_trace_fn trace, void* trace_user) {
     if (!decision_out || !imp_history_out || !n_iter_out || !y) return -1;
-    if (n < 2 || n > kRegMaxRows || importance_mode != 0) return -1;
+    if (n < 2 || n > kRegMaxRows || importance_mode < 0 || importance_mode > 1) return -1;
+    // the summed squared-error drops stay below 2^63
+    if (importance_mode == 1 && (int64_t)n_trees * n * n_perm > (int64_t(1) << 31)) return -1;
     for (int64_t i = 0; i < n; ++i)
         if (!std::isfinite(y[i])) return -2;
     Run run;
@@ -1093,8 +1133,8 @@ int oracle_boruta_fit_reg(const float* X, const float* y, int64_t n, int64_t p,
     run.yq.resize((size_t)n);
     quantize_target(y, n, run.yq.data());
     const int rc = setup(run, X, run.yq.data(), n, p, 2, n_trees, max_depth, mtry,
-                         importance_mode, max_iter, alpha, seed, n_bins, 1, n_threads, 0,
-                         kLevels + 1);
+                         importance_mode, max_iter, alpha, seed, n_bins, n_perm, n_threads,
+                         permut_naive, kLevels + 1);
     if (rc) return rc;
     return fit_run(run, n_trees, max_iter, 0, decision_out, imp_history_out, hits_out,
                    shadow_max_out, n_iter_out, trace, trace_user);

@@ -145,19 +145,24 @@ int oracle_boruta_fit_ext(const float* X, const int32_t* y, int64_t n, int64_t p
                           double* shadow_max_out, int32_t* n_iter_out, oracle_trace_fn trace,
                           void* trace_user);
 
-/* Regression Boruta (the paper's regression experiments), TreeImp only
- * (importance_mode 0): y [n] float targets, quantised to levels 0..255 by
- * oracle_quantize_target; the split maximises T_L^2/W_L + T_R^2/W_R (W the
- * bootstrap weight, T the weighted level sum of a child) and the fixed-point
- * decrease is floor(2^33 D / 255), D the weighted squared-error decrease.
- * n <= 65536.  The trace's node columns hold 255 W as the weighted count and,
- * for a leaf, 1 if T > 255 W - T else 0.  Other outputs as oracle_boruta_fit. */
+/* Regression Boruta (the paper's regression experiments): y [n] float
+ * targets, quantised to levels 0..255 by oracle_quantize_target; the split
+ * maximises T_L^2/W_L + T_R^2/W_R (W the bootstrap weight, T the weighted
+ * level sum of a child) and the fixed-point decrease is floor(2^33 D / 255),
+ * D the weighted squared-error decrease.  importance_mode 0 (TreeImp) or 1
+ * (Permut: a leaf predicts floor(256 T / W), its mean level in 1/256 units;
+ * a column's drop is the increase of the OOB rows' squared error under the
+ * permutation, reported per row and replica in level^2 units; needs
+ * n_trees * n * n_perm <= 2^31).  n <= 65536.  The trace's node columns hold
+ * 255 W as the weighted count and, for a leaf, 1 if T > 255 W - T else 0; its
+ * OOB-correct count is 0.  Other outputs as oracle_boruta_fit. */
 int oracle_boruta_fit_reg(const float* X, const float* y, int64_t n, int64_t p,
                           int32_t n_trees, int32_t max_depth, int32_t mtry,
                           int32_t importance_mode, int32_t max_iter, double alpha, uint64_t seed,
-                          int32_t n_bins, int32_t n_threads, int8_t* decision_out,
-                          double* imp_history_out, int32_t* hits_out, double* shadow_max_out,
-                          int32_t* n_iter_out, oracle_trace_fn trace, void* trace_user);
+                          int32_t n_bins, int32_t n_perm, int32_t n_threads,
+                          int32_t permut_naive, int8_t* decision_out, double* imp_history_out,
+                          int32_t* hits_out, double* shadow_max_out, int32_t* n_iter_out,
+                          oracle_trace_fn trace, void* trace_user);
 
 /* Target quantisation: floor((y - min) 255 / (max - min) + 1/2) in double (0
  * for a constant target). */

@@ -87,7 +87,7 @@ def lib():
                                             TRACE_FN, P]
         L.oracle_boruta_fit_ext.restype = i32
         L.oracle_boruta_fit_reg.argtypes = [P, P, i64, i64, i32, i32, i32, i32, i32, f64, u64,
-                                            i32, i32, P, P, P, P, P, TRACE_FN, P]
+                                            i32, i32, i32, i32, P, P, P, P, P, TRACE_FN, P]
         L.oracle_boruta_fit_reg.restype = i32
         L.oracle_quantize_target.argtypes = [P, i64, P]
         L.oracle_quantize_target.restype = None
@@ -255,8 +255,9 @@ def boruta_fit(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=0, m
 
 
 def boruta_fit_reg(X, y, n_trees, max_depth, mtry=0, importance_mode=0, max_iter=20,
-                   alpha=0.05, seed=0, n_bins=256, n_threads=0, trace=False):
-    """Regression Boruta (TreeImp): y float targets."""
+                   alpha=0.05, seed=0, n_bins=256, n_perm=1, n_threads=0, permut_naive=False,
+                   trace=False):
+    """Regression Boruta (TreeImp or Permut): y float targets."""
     X = np.ascontiguousarray(X, dtype=np.float32)
     y = np.ascontiguousarray(y, dtype=np.float32)
     n, p = X.shape
@@ -268,7 +269,8 @@ def boruta_fit_reg(X, y, n_trees, max_depth, mtry=0, importance_mode=0, max_iter
     traces = []
     cb = _trace_collector(traces) if trace else TRACE_FN()
     rc = lib().oracle_boruta_fit_reg(_ptr(X), _ptr(y), n, p, n_trees, max_depth, mtry,
-                                     importance_mode, max_iter, alpha, seed, n_bins, n_threads,
+                                     importance_mode, max_iter, alpha, seed, n_bins, n_perm,
+                                     n_threads, int(permut_naive),
                                      _ptr(dec), _ptr(hist), _ptr(hits), _ptr(smax),
                                      ctypes.cast(ctypes.byref(n_iter), ctypes.c_void_p), cb,
                                      None)

@@ -116,8 +116,86 @@ def test_planted_regression_features_recovered():
 def test_regression_arguments_checked():
     X = np.zeros((10, 3), np.float32)
     with pytest.raises(ValueError):
-        O.boruta_fit_reg(X, np.arange(10, dtype=np.float32), 2, 2, importance_mode=1)
+        O.boruta_fit_reg(X, np.arange(10, dtype=np.float32), 2, 2, importance_mode=2)
     y = np.arange(10, dtype=np.float32)
     y[3] = np.inf
     with pytest.raises(ValueError):
         O.boruta_fit_reg(X, y, 2, 2)
+
+
+def test_permutation_importance_of_stumps_recomputed_in_python():
+    # Permut for regression on depth-1 trees, recomputed here from the
+    # definition: leaf mean level floor(256 T / W) of the in-bag rows on each
+    # side of the root split, squared errors in 1/65536 level^2 units, and the
+    # OOB rows' error increase when the root column's bins are moved by the
+    # keyed permutation of the OOB set (shadow columns rebuilt by their own
+    # keyed row permutation)
+    rng = np.random.default_rng(25)
+    n, p, B, T, R, seed = 400, 6, 16, 7, 2, 9
+    X = rng.random((n, p)).astype(np.float32)
+    y = (3 * X[:, 0] + np.sin(5 * X[:, 1]) + 0.3 * rng.standard_normal(n)).astype(np.float32)
+    r = O.boruta_fit_reg(X, y, T, 1, importance_mode=1, max_iter=1, seed=seed, n_bins=B,
+                         n_perm=R, trace=True)
+    tr = r["traces"][0]
+    bins, _, _ = O.bin_matrix(X, B)
+    yq = O.quantize_target(y).astype(np.int64)
+    p_cur = tr["p_cur"]
+
+    def column(fw):
+        src = tr["col_src"][fw]
+        if fw < p_cur:
+            return bins[src]
+        s = fw - p_cur
+        return np.array([bins[src][O.keyed_perm(seed, 3, 1, s, 0, 0, n, i)] for i in range(n)])
+
+    want = np.zeros(tr["p_w"], np.int64)
+    for tau in range(T):
+        w = O.bootstrap(seed, 1, tau, n).astype(np.int64)
+        root = tr["nodes"][(tr["nodes"][:, 0] == tau) & (tr["nodes"][:, 1] == 1)][0]
+        f, b = int(root[2]), int(root[3])
+        if f < 0:
+            continue
+        col = column(f).astype(np.int64)
+        left = col <= b
+        v = {}
+        for side in (True, False):
+            m_in = (w > 0) & (left == side)
+            v[side] = (256 * int((w[m_in] * yq[m_in]).sum())) // int(w[m_in].sum())
+        oob = np.flatnonzero(w == 0)
+        m = len(oob)
+        for rep in range(R):
+            for j in range(m):
+                src = O.keyed_perm(seed, 4, 1, tau, f, rep << 16, m, j)
+                e1 = v[bool(col[oob[src]] <= b)] - 256 * yq[oob[j]]
+                e0 = v[bool(col[oob[j]] <= b)] - 256 * yq[oob[j]]
+                want[f] += e1 * e1 - e0 * e0
+    assert np.array_equal(tr["imp_int"], want)
+    assert want[0] > 0
+
+
+def test_permutation_importance_path_restricted_equals_naive():
+    X, y = _problem(26)
+    kw = dict(importance_mode=1, max_iter=4, seed=2, n_bins=32, n_perm=2, trace=True)
+    a = O.boruta_fit_reg(X, y, 6, 7, **kw)
+    b = O.boruta_fit_reg(X, y, 6, 7, permut_naive=True, **kw)
+    assert np.array_equal(a["decision"], b["decision"])
+    for ta, tb in zip(a["traces"], b["traces"]):
+        assert np.array_equal(ta["imp_int"], tb["imp_int"])
+        # a column no tree splits on has exactly zero importance
+        used = np.unique(ta["nodes"][ta["nodes"][:, 2] >= 0, 2])
+        assert not ta["imp_int"][np.setdiff1d(np.arange(ta["p_w"]), used)].any()
+
+
+def test_planted_regression_features_recovered_by_permutation():
+    X, y = _problem(27)
+    r = O.boruta_fit_reg(X, y, 40, 8, importance_mode=1, max_iter=30, seed=5, n_bins=64)
+    assert list(r["decision"][:3]) == [1, 1, 1]
+    assert (r["decision"][3:] == -1).sum() >= 6
+
+
+def _problem(seed, n=600, p=12):
+    rng = np.random.default_rng(seed)
+    X = rng.random((n, p)).astype(np.float32)
+    y = (4 * X[:, 0] + 3 * np.sin(3 * X[:, 1]) + 2 * (X[:, 2] > 0.5)
+         + 0.3 * rng.standard_normal(n)).astype(np.float32)
+    return X, y
