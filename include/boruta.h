@@ -210,8 +210,8 @@ int boruta_fit_ex(const float* X, const int32_t* y, int64_t n, int64_t p, int32_
                   double* shadow_max_out, int32_t* n_iter_out);
 
 /* Regression Boruta (the paper's regression experiments run Boruta on a
- * random-forest regressor), TreeImp importance (importance_mode 0; others
- * return BORUTA_E_UNSUPPORTED).  y: [n] float32 targets, finite, n <= 65536
+ * random-forest regressor): importance_mode 0 (TreeImp) or 1 (Permut); 2
+ * returns BORUTA_E_UNSUPPORTED.  y: [n] float32 targets, finite, n <= 65536
  * (else BORUTA_E_INVALID_ARG; non-finite X or y: BORUTA_E_NONFINITE).  The
  * targets are quantised to levels 0..255, floor((y - min) 255 / (max - min) +
  * 1/2) in double (all 0 for a constant target); a split maximises
@@ -223,7 +223,12 @@ int boruta_fit_ex(const float* X, const int32_t* y, int64_t n, int64_t p, int32_
  * class 1 with weight w y, whose Gini decrease equals 2 D / 255, so the
  * classification kernels grow the forest unchanged.  Arguments and outputs
  * otherwise as boruta_fit_ex; in a trace a node's weighted count is 255 W and
- * a leaf's class is 1 when T > 255 W - T, else 0. */
+ * a leaf's class is 1 when T > 255 W - T, else 0.  Permut: a leaf predicts
+ * its mean level floor(256 T / W) (in 1/256 level units); a column's drop is
+ * the increase of the out-of-bag rows' squared error under the column's
+ * permutation (1/65536 level^2 units), reported per OOB row and replica in
+ * level^2 units; n_trees * n * n_perm must not exceed 2^31
+ * (BORUTA_E_INVALID_ARG); the trace's OOB-correct count is 0. */
 int boruta_fit_regression(const float* X, const float* y, int64_t n, int64_t p, int32_t n_trees,
                           int32_t max_depth, int32_t mtry, int32_t importance_mode,
                           int32_t max_iter, double alpha, uint64_t seed, const boruta_options* opt,

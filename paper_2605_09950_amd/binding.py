@@ -254,7 +254,8 @@ def boruta_fit_ex(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=T
 
 
 def boruta_fit_regression(X, y, n_trees, max_depth, mtry=0, importance_mode=TREEIMP,
-                          max_iter=20, alpha=0.05, seed=0, n_bins=256, split_rank=RANK_FP32,
+                          max_iter=20, alpha=0.05, seed=0, n_bins=256, n_perm=1,
+                          split_rank=RANK_FP32,
                           form=FORM_BATCHED, trace=False, stats=False, graph=True, tune=None,
                           perc=100, rough_fix=False):
     """Regression Boruta: y float targets (see boruta_fit_regression in
@@ -267,7 +268,7 @@ def boruta_fit_regression(X, y, n_trees, max_depth, mtry=0, importance_mode=TREE
     hits = np.zeros(p, np.int32)
     smax = np.full(max_iter, np.nan)
     n_iter = np.zeros(1, np.int32)
-    o, keep = make_options(n_bins, 1, split_rank, form, trace, stats, p, graph, tune, perc,
+    o, keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p, graph, tune, perc,
                            rough_fix)
     rc = lib().boruta_fit_regression(_ptr(X), _ptr(y), n, p, n_trees, max_depth, mtry,
                                      importance_mode, max_iter, alpha, seed, ctypes.byref(o),

@@ -45,7 +45,8 @@ void launch_hist_col(const ForestDev&, int, uint32_t, int, uint32_t, hipStream_t
 // k_importance.hip
 void launch_tree_totals(JobDev*, const TreeDev*, int, uint64_t*, hipStream_t);
 void launch_treeimp(JobDev*, const TreeDev*, int, const uint64_t*, int, hipStream_t);
-void launch_permut(JobDev*, const TreeDev*, const NodeDev*, int, int64_t, int, int, hipStream_t);
+void launch_permut(JobDev*, const TreeDev*, const NodeDev*, const uint32_t*, int, int, int64_t,
+                   int, int, bool, hipStream_t);
 void launch_hits_decide(JobDev*, int, int, hipStream_t);
 void launch_rough_fix(const int8_t*, const double*, const double*, int64_t, int, int, int8_t*,
                       hipStream_t);
@@ -181,8 +182,9 @@ void check_spec(const Spec& s) {
     if (!s.X || (!s.y && !s.yr)) bad("X and y must be non-null");
     if (s.yr) {
         if (s.n > kRegMaxRows) bad("regression: n outside [2, 65536]");
-        if (s.mode != 0)
-            throw Error(BORUTA_E_UNSUPPORTED, "regression supports importance_mode 0 (TreeImp)");
+        if (s.mode == 2)
+            throw Error(BORUTA_E_UNSUPPORTED,
+                        "regression supports importance_mode 0 (TreeImp) and 1 (Permut)");
     }
     if (s.n < 2 || s.n > (int64_t(1) << 24)) bad("n outside [2, 2^24]");
     if (s.p < 1 || s.p > (int64_t(1) << 24)) bad("p outside [1, 2^24]");
@@ -868,7 +870,10 @@ void Engine::enqueue_iteration() {
     }
     if (any_permut) {
         const size_t h = clock.begin(stats ? &stats->permut : nullptr, st);
-        launch_permut(djobs, dtrees, F.nodes, (int)n_trees, pl.max_n, pl.max_D, pl.max_pw, st);
+        bool any_reg = false;
+        for (const Spec& sp : S) any_reg |= sp.yr != nullptr;
+        launch_permut(djobs, dtrees, F.nodes, F.cls, pl.kmax, (int)n_trees, pl.max_n, pl.max_D,
+                      pl.max_pw, any_reg, st);
         clock.end(h, st);
     }
     if (any_kl) {
@@ -1136,7 +1141,12 @@ std::unique_ptr<Context> prepare(const std::vector<Spec>& specs, const boruta_op
                                  bool dev_inputs, void* ws, size_t ws_bytes,
                                  hipStream_t user_stream) {
     const Opts o = read_opts(opt);
-    for (const Spec& s : specs) check_spec(s);
+    for (const Spec& s : specs) {
+        check_spec(s);
+        // regression Permut: the summed squared-error drops stay below 2^63
+        if (s.yr && s.mode == 1 && (int64_t)s.T * s.n * o.R > (int64_t(1) << 31))
+            throw Error(BORUTA_E_INVALID_ARG, "regression Permut needs n_trees * n * n_perm <= 2^31");
+    }
     require_device();
     std::unique_ptr<Context> c(new Context);
     c->specs = specs;

@@ -68,10 +68,21 @@ __global__ __launch_bounds__(256) void k_treeimp(JobDev* jobs, const TreeDev* tr
 // workgroup adds its nonzero sums to the importances: once most columns are
 // decided, few remain and per-row atomics would all meet on them (with many
 // columns the per-row atomics are spread out and cheaper than a flush per
-// workgroup).
+// workgroup).  For a regression job a row's score is the negated squared
+// error of its leaf's mean level, sq_error_fix below, and the per-column sums
+// in LDS are 64-bit (a row's drop reaches 2^32).
+__device__ __forceinline__ long long sq_error_fix(const uint32_t* cls, int kmax, uint32_t node,
+                                                  uint32_t level) {
+    // the leaf's counts are (255 W - T, T): mean level floor(256 T / W)
+    const uint64_t c0 = cls[(size_t)node * kmax], c1 = cls[(size_t)node * kmax + 1];
+    const long long v = (long long)((65280ull * c1) / (c0 + c1));
+    const long long e = v - 256ll * (long long)level;
+    return e * e;
+}
+
 __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* trees,
-                                                const NodeDev* nodes, int max_depth,
-                                                int lds_cols) {
+                                                const NodeDev* nodes, const uint32_t* cls,
+                                                int kmax, int max_depth, int lds_cols) {
     extern __shared__ uint32_t s_path[];  // [2][max_depth][256]: node, feature; [lds_cols] drops
     const uint32_t g = blockIdx.y;
     const TreeDev tr = trees[g];
@@ -82,9 +93,16 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
     const uint32_t j = blockIdx.x * 256u + tid;
     if (blockIdx.x * 256u >= m) return;
     int* s_drop = reinterpret_cast<int*>(s_path + 2 * max_depth * 256);
+    long long* s_drop64 = reinterpret_cast<long long*>(s_drop);  // regression jobs
+    const bool reg = J.reg != 0;
     const bool lds = J.p_w <= lds_cols;  // uniform: one tree per workgroup
     if (lds) {
-        for (int c = tid; c < J.p_w; c += 256) s_drop[c] = 0;
+        for (int c = tid; c < J.p_w; c += 256) {
+            if (reg)
+                s_drop64[c] = 0;
+            else
+                s_drop[c] = 0;
+        }
         __syncthreads();
     }
     const bool active = j < m;
@@ -96,6 +114,7 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
     int len = 0;
     uint32_t node = g;
     bool base_ok = false;
+    long long base_err = 0;
     if (active) {
         NodeDev nd = nodes[node];
         while (nd.feat >= 0) {
@@ -105,7 +124,10 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
             node = (int)J.colptr[nd.feat][row] <= (int)nd.thr ? nd.left : nd.left + 1;
             nd = nodes[node];
         }
-        base_ok = nd.leaf_class == yv;
+        if (reg)
+            base_err = sq_error_fix(cls, kmax, node, yv);
+        else
+            base_ok = nd.leaf_class == yv;
     }
     const unsigned long long okm = __ballot(active && base_ok);
     if ((tid & 63) == 0 && okm) atomicAdd(&J.tstat[tr.tau * 4 + 2], (int)__popcll(okm));
@@ -117,6 +139,7 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
         const uint8_t* fcol = J.colptr[f];
         const uint32_t start = pn[pi * 256 + tid];
         int drop = 0;
+        long long drop_sq = 0;  // regression: increase of the squared error
         for (int r = 0; r < J.R; ++r) {
             const KeyedPerm P = make_perm(J.seed_lo, J.seed_hi, kOobPerm, (uint32_t)J.t,
                                           (uint32_t)tr.tau, f, (uint32_t)r << 16, (uint64_t)m);
@@ -128,7 +151,16 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
                 nd_i = b <= (int)nd.thr ? nd.left : nd.left + 1;
                 nd = nodes[nd_i];
             }
-            drop += (int)base_ok - (int)(nd.leaf_class == yv);
+            if (reg)
+                drop_sq += sq_error_fix(cls, kmax, nd_i, yv) - base_err;
+            else
+                drop += (int)base_ok - (int)(nd.leaf_class == yv);
+        }
+        if (drop_sq) {
+            if (lds)
+                atomicAdd((unsigned long long*)&s_drop64[f], (unsigned long long)drop_sq);
+            else
+                atomicAdd((unsigned long long*)&J.imp[f], (unsigned long long)drop_sq);
         }
         if (drop) {
             if (lds)
@@ -139,9 +171,10 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
     }
     if (lds) {
         __syncthreads();
-        for (int c = tid; c < J.p_w; c += 256)
-            if (s_drop[c])
-                atomicAdd((unsigned long long*)&J.imp[c], (unsigned long long)(int64_t)s_drop[c]);
+        for (int c = tid; c < J.p_w; c += 256) {
+            const long long v = reg ? s_drop64[c] : (long long)s_drop[c];
+            if (v) atomicAdd((unsigned long long*)&J.imp[c], (unsigned long long)v);
+        }
     }
 }
 
@@ -448,6 +481,7 @@ __global__ __launch_bounds__(256) void k_hits_decide(JobDev* jobs, int perc) {
         long long oob = 0;
         for (int tau = 0; tau < J.T; ++tau) oob += J.tstat[tau * 4 + 1];
         denom = (double)((long long)J.R * oob);
+        if (J.reg) denom *= 65536.0;  // squared errors in 1/65536 level^2 units
     }
     double* hrow = J.hist + (size_t)(t - 1) * J.p;
     for (int j = tid; j < J.p; j += 256)
@@ -632,13 +666,16 @@ void launch_treeimp(JobDev* jobs, const TreeDev* trees, int n_trees, const uint6
                        dim3(256), 0, st, jobs, trees, tot);
 }
 
-void launch_permut(JobDev* jobs, const TreeDev* trees, const NodeDev* nodes, int n_trees,
-                   int64_t max_n, int max_depth, int max_pw, hipStream_t st) {
+void launch_permut(JobDev* jobs, const TreeDev* trees, const NodeDev* nodes, const uint32_t* cls,
+                   int kmax, int n_trees, int64_t max_n, int max_depth, int max_pw,
+                   bool any_reg, hipStream_t st) {
     // per-column drop sums in LDS for jobs of at most 1024 widened columns
+    // (64-bit when the batch has a regression job)
     const int lds_cols = max_pw < 1024 ? max_pw : 1024;
-    const size_t lds = (size_t)2 * max_depth * 256 * sizeof(uint32_t) + (size_t)lds_cols * 4;
+    const size_t lds = (size_t)2 * max_depth * 256 * sizeof(uint32_t) +
+                       (size_t)lds_cols * (any_reg ? 8 : 4);
     hipLaunchKernelGGL(k_permut, dim3((unsigned)((max_n + 255) / 256), (unsigned)n_trees),
-                       dim3(256), lds, st, jobs, trees, nodes, max_depth, lds_cols);
+                       dim3(256), lds, st, jobs, trees, nodes, cls, kmax, max_depth, lds_cols);
 }
 
 // The KL importance of job j over rows [r0, r0 + rb): base, deltas, reduce.

@@ -44,6 +44,24 @@ def test_regression_run_matches_oracle(kind, split_rank):
     assert len(g["traces"]) == g["n_iter"]
 
 
+@pytest.mark.parametrize("n_perm", [1, 3])
+@pytest.mark.parametrize("kind", ["smooth", "ties"])
+def test_regression_permutation_importance_matches_oracle(kind, n_perm):
+    # out-of-bag squared-error increase under column permutation
+    X, y = problem(47, 1000, 10, kind)
+    g, o = both(X, y, 8, 9, importance_mode=B.PERMUT, max_iter=6, seed=16, n_perm=n_perm)
+    assert_same_run(g, o)
+    assert (g["hits"] > 0).any()
+
+
+def test_regression_permutation_importance_many_columns():
+    # more columns than the per-workgroup drop sums hold: the path that adds
+    # every row's drop to the importances directly, as regression always does
+    X, y = problem(48, 700, 600)
+    g, o = both(X, y, 4, 8, importance_mode=B.PERMUT, max_iter=2, seed=17, n_bins=32)
+    assert_same_run(g, o)
+
+
 @pytest.mark.parametrize("tune", [dict(small_rows=16), dict(small_rows=64),
                                   dict(col_level=1, col_unit=3), dict(col_level=64)],
                          ids=["small16", "small64", "column", "node_major"])
