@@ -572,6 +572,19 @@ void forest_predict(const std::vector<std::vector<TNode>*>& forest, const Data& 
 // each column, the predictions of the matrix with that column permuted
 // against those of the unpermuted matrix (Algorithm 3, one predict call
 // per column).
+// Regression form (reading): the forest's prediction of a row is the mean
+// over trees of its leaves' mean levels; with S the sum over trees of the
+// leaves' floor(256 T / W) and D = S(permuted) - S(unpermuted), a row's loss
+// is floor(D^2 / n_trees^2), the squared difference of the two mean
+// predictions in 1/65536 level^2 units.
+int64_t forest_level_sum(const std::vector<std::vector<TNode>*>& forest, const Data& d,
+                         uint32_t row, int32_t sub_f, int sub_b) {
+    int64_t s = 0;
+    for (const std::vector<TNode>* tree : forest)
+        s += leaf_level_fix((*tree)[leaf_of_row(*tree, d, row, sub_f, sub_b)]);
+    return s;
+}
+
 void forest_divergence(const std::vector<std::vector<TNode>*>& forest, const Data& d,
                        uint64_t seed, uint32_t t, int n_threads, int64_t* imp,
                        const std::vector<int32_t>& only) {
@@ -596,6 +609,15 @@ void forest_divergence(const std::vector<std::vector<TNode>*>& forest, const Dat
                 const int32_t f = cols[ci];
                 int64_t acc = 0;
                 for (int64_t r = 0; r < d.n; ++r) {
+                    if (d.reg) {
+                        const int64_t diff =
+                            forest_level_sum(forest, d, (uint32_t)r, (int32_t)f, d.col[f][pi[r]]) -
+                            forest_level_sum(forest, d, (uint32_t)r, -1, 0);
+                        const uint64_t a = (uint64_t)(diff < 0 ? -diff : diff);
+                        const uint64_t T = forest.size();
+                        acc += (int64_t)((a * a) / (T * T));
+                        continue;
+                    }
                     forest_predict(forest, d, (uint32_t)r, (int32_t)f, d.col[f][pi[r]], q.data());
                     acc += kl_fix32(&base[(size_t)r * K], q.data(), K);
                 }
@@ -879,7 +901,9 @@ void iteration(const Run& run, int t, int8_t* state, int32_t* hits,
             for (TreeResult& r : res) forest.push_back(&r.nodes);
             forest_divergence(forest, d, run.seed, (uint32_t)t, run.n_threads, imp.data(),
                               run.kl_cols);
-            denom = (double)d.n * 4294967296.0;
+            // mean divergence per row in bits (regression: mean squared
+            // difference in level^2 units)
+            denom = (double)d.n * (run.reg ? 65536.0 : 4294967296.0);
         } else {
             int64_t oob_total = 0;
             for (const TreeResult& r : res) {
@@ -1123,7 +1147,7 @@ int oracle_boruta_fit_reg(const float* X, const float* y, int64_t n, int64_t p,
                           int32_t* hits_out, double* shadow_max_out, int32_t* n_iter_out,
                           oracle_trace_fn trace, void* trace_user) {
     if (!decision_out || !imp_history_out || !n_iter_out || !y) return -1;
-    if (n < 2 || n > kRegMaxRows || importance_mode < 0 || importance_mode > 1) return -1;
+    if (n < 2 || n > kRegMaxRows || importance_mode < 0 || importance_mode > 2) return -1;
     // the summed squared-error drops stay below 2^63
     if (importance_mode == 1 && (int64_t)n_trees * n * n_perm > (int64_t(1) << 31)) return -1;
     for (int64_t i = 0; i < n; ++i)

@@ -149,11 +149,14 @@ int oracle_boruta_fit_ext(const float* X, const int32_t* y, int64_t n, int64_t p
  * targets, quantised to levels 0..255 by oracle_quantize_target; the split
  * maximises T_L^2/W_L + T_R^2/W_R (W the bootstrap weight, T the weighted
  * level sum of a child) and the fixed-point decrease is floor(2^33 D / 255),
- * D the weighted squared-error decrease.  importance_mode 0 (TreeImp) or 1
+ * D the weighted squared-error decrease.  importance_mode 0 (TreeImp), 1
  * (Permut: a leaf predicts floor(256 T / W), its mean level in 1/256 units;
  * a column's drop is the increase of the OOB rows' squared error under the
  * permutation, reported per row and replica in level^2 units; needs
- * n_trees * n * n_perm <= 2^31).  n <= 65536.  The trace's node columns hold
+ * n_trees * n * n_perm <= 2^31) or 2 (Algorithm 3: per row
+ * floor(D^2 / n_trees^2), D the change of the summed leaf levels under the
+ * shared row permutation, summed over rows and reported per row in level^2
+ * units).  n <= 65536.  The trace's node columns hold
  * 255 W as the weighted count and, for a leaf, 1 if T > 255 W - T else 0; its
  * OOB-correct count is 0.  Other outputs as oracle_boruta_fit. */
 int oracle_boruta_fit_reg(const float* X, const float* y, int64_t n, int64_t p,

@@ -116,7 +116,7 @@ def test_planted_regression_features_recovered():
 def test_regression_arguments_checked():
     X = np.zeros((10, 3), np.float32)
     with pytest.raises(ValueError):
-        O.boruta_fit_reg(X, np.arange(10, dtype=np.float32), 2, 2, importance_mode=2)
+        O.boruta_fit_reg(X, np.arange(10, dtype=np.float32), 2, 2, importance_mode=3)
     y = np.arange(10, dtype=np.float32)
     y[3] = np.inf
     with pytest.raises(ValueError):
@@ -199,3 +199,53 @@ def _problem(seed, n=600, p=12):
     y = (4 * X[:, 0] + 3 * np.sin(3 * X[:, 1]) + 2 * (X[:, 2] > 0.5)
          + 0.3 * rng.standard_normal(n)).astype(np.float32)
     return X, y
+
+
+def test_divergence_importance_of_stumps_recomputed_in_python():
+    # Algorithm 3 for regression on depth-1 trees, recomputed here: the shared
+    # row permutation of the iteration, per row the change D of the summed
+    # leaf levels floor(256 T / W) when the column is permuted, and the sum
+    # over rows of floor(D^2 / T^2)
+    rng = np.random.default_rng(28)
+    n, p, B, T, seed = 300, 5, 16, 6, 4
+    X = rng.random((n, p)).astype(np.float32)
+    y = (3 * X[:, 0] + np.sin(5 * X[:, 1]) + 0.3 * rng.standard_normal(n)).astype(np.float32)
+    r = O.boruta_fit_reg(X, y, T, 1, importance_mode=2, max_iter=1, seed=seed, n_bins=B,
+                         trace=True)
+    tr = r["traces"][0]
+    bins, _, _ = O.bin_matrix(X, B)
+    yq = O.quantize_target(y).astype(np.int64)
+    p_cur = tr["p_cur"]
+
+    def column(fw):
+        src = tr["col_src"][fw]
+        if fw < p_cur:
+            return bins[src].astype(np.int64)
+        s = fw - p_cur
+        return np.array([bins[src][O.keyed_perm(seed, 3, 1, s, 0, 0, n, i)] for i in range(n)],
+                        np.int64)
+
+    pi = np.array([O.keyed_perm(seed, 5, 1, 0, 0, 0, n, i) for i in range(n)])
+    stumps = []
+    for tau in range(T):
+        w = O.bootstrap(seed, 1, tau, n).astype(np.int64)
+        root = tr["nodes"][(tr["nodes"][:, 0] == tau) & (tr["nodes"][:, 1] == 1)][0]
+        f, b = int(root[2]), int(root[3])
+        if f < 0:
+            continue
+        col = column(f)
+        v = {}
+        for side in (True, False):
+            m_in = (w > 0) & ((col <= b) == side)
+            v[side] = (256 * int((w[m_in] * yq[m_in]).sum())) // int(w[m_in].sum())
+        stumps.append((f, b, col, v))
+    want = np.zeros(tr["p_w"], np.int64)
+    for f in range(tr["p_w"]):
+        for row in range(n):
+            d = 0
+            for (g, b, col, v) in stumps:
+                if g == f:
+                    d += v[bool(col[pi[row]] <= b)] - v[bool(col[row] <= b)]
+            want[f] += (d * d) // (T * T)
+    assert np.array_equal(tr["imp_int"], want)
+    assert want[0] > 0
