@@ -210,8 +210,8 @@ int boruta_fit_ex(const float* X, const int32_t* y, int64_t n, int64_t p, int32_
                   double* shadow_max_out, int32_t* n_iter_out);
 
 /* Regression Boruta (the paper's regression experiments run Boruta on a
- * random-forest regressor): importance_mode 0 (TreeImp) or 1 (Permut); 2
- * returns BORUTA_E_UNSUPPORTED.  y: [n] float32 targets, finite, n <= 65536
+ * random-forest regressor): importance_mode 0 (TreeImp), 1 (Permut) or 2
+ * (Algorithm 3).  y: [n] float32 targets, finite, n <= 65536
  * (else BORUTA_E_INVALID_ARG; non-finite X or y: BORUTA_E_NONFINITE).  The
  * targets are quantised to levels 0..255, floor((y - min) 255 / (max - min) +
  * 1/2) in double (all 0 for a constant target); a split maximises
@@ -228,7 +228,12 @@ int boruta_fit_ex(const float* X, const int32_t* y, int64_t n, int64_t p, int32_
  * the increase of the out-of-bag rows' squared error under the column's
  * permutation (1/65536 level^2 units), reported per OOB row and replica in
  * level^2 units; n_trees * n * n_perm must not exceed 2^31
- * (BORUTA_E_INVALID_ARG); the trace's OOB-correct count is 0. */
+ * (BORUTA_E_INVALID_ARG); the trace's OOB-correct count is 0.  Algorithm 3
+ * (importance_mode 2): with S a row's sum over trees of its leaves' mean
+ * levels and D the change of S when the column is permuted by the
+ * iteration's shared row permutation, the row's loss is floor(D^2 /
+ * n_trees^2), the squared difference of the mean predictions in 1/65536
+ * level^2 units; reported per row in level^2 units. */
 int boruta_fit_regression(const float* X, const float* y, int64_t n, int64_t p, int32_t n_trees,
                           int32_t max_depth, int32_t mtry, int32_t importance_mode,
                           int32_t max_iter, double alpha, uint64_t seed, const boruta_options* opt,

@@ -182,9 +182,6 @@ void check_spec(const Spec& s) {
     if (!s.X || (!s.y && !s.yr)) bad("X and y must be non-null");
     if (s.yr) {
         if (s.n > kRegMaxRows) bad("regression: n outside [2, 65536]");
-        if (s.mode == 2)
-            throw Error(BORUTA_E_UNSUPPORTED,
-                        "regression supports importance_mode 0 (TreeImp) and 1 (Permut)");
     }
     if (s.n < 2 || s.n > (int64_t(1) << 24)) bad("n outside [2, 2^24]");
     if (s.p < 1 || s.p > (int64_t(1) << 24)) bad("p outside [1, 2^24]");

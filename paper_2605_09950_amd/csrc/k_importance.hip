@@ -71,12 +71,16 @@ __global__ __launch_bounds__(256) void k_treeimp(JobDev* jobs, const TreeDev* tr
 // workgroup).  For a regression job a row's score is the negated squared
 // error of its leaf's mean level, sq_error_fix below, and the per-column sums
 // in LDS are 64-bit (a row's drop reaches 2^32).
+// Mean target level of a regression leaf in 1/256 level units: its counts
+// are (255 W - T, T), so floor(256 T / W) = floor(65280 c1 / (c0 + c1)).
+__device__ __forceinline__ long long leaf_level_fix(const uint32_t* cls, int kmax, uint32_t node) {
+    const uint64_t c0 = cls[(size_t)node * kmax], c1 = cls[(size_t)node * kmax + 1];
+    return (long long)((65280ull * c1) / (c0 + c1));
+}
+
 __device__ __forceinline__ long long sq_error_fix(const uint32_t* cls, int kmax, uint32_t node,
                                                   uint32_t level) {
-    // the leaf's counts are (255 W - T, T): mean level floor(256 T / W)
-    const uint64_t c0 = cls[(size_t)node * kmax], c1 = cls[(size_t)node * kmax + 1];
-    const long long v = (long long)((65280ull * c1) / (c0 + c1));
-    const long long e = v - 256ll * (long long)level;
+    const long long e = leaf_level_fix(cls, kmax, node) - 256ll * (long long)level;
     return e * e;
 }
 
@@ -260,6 +264,14 @@ __global__ __launch_bounds__(256) void k_kl_base(JobDev* jobs, int j, const Node
     if (rr >= rb || r0 + rr >= (uint32_t)J.n) return;
     const uint32_t row = r0 + rr;
     const int K = J.K;
+    if (J.reg) {  // regression: the loss depends on the change of the prediction only
+        if (lane == 0) {
+            const KeyedPerm P = make_perm(J.seed_lo, J.seed_hi, kFlush, (uint32_t)J.t, 0u, 0u,
+                                          0u, (uint64_t)J.n);
+            pi[rr] = perm_apply(P, row);
+        }
+        return;
+    }
     uint64_t acc[KMAX];
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) acc[k] = 0;
@@ -345,8 +357,13 @@ __global__ __launch_bounds__(256) void k_kl_delta(JobDev* jobs, int j, const Nod
             x = nodes[ni];
         }
         if (ni == leaf0) continue;
-        const uint32_t N1 = leaf_weight(cls, kmax, ni, K);
         unsigned long long* d = delta + ((size_t)f * rb + rr) * K;
+        if (J.reg) {  // change of the leaf's mean level, in the first slot
+            const long long dv = leaf_level_fix(cls, kmax, ni) - leaf_level_fix(cls, kmax, leaf0);
+            if (dv) atomicAdd(d, (unsigned long long)dv);
+            continue;
+        }
+        const uint32_t N1 = leaf_weight(cls, kmax, ni, K);
         for (int k = 0; k < K; ++k) {
             const uint64_t dv = leaf_freq(cls, kmax, ni, k, N1) - leaf_freq(cls, kmax, leaf0, k, N0);
             if (dv) atomicAdd(d + k, (unsigned long long)dv);
@@ -368,7 +385,16 @@ __global__ __launch_bounds__(256) void k_kl_reduce(JobDev* jobs, int j, uint32_t
     const uint32_t rr = (blockIdx.x % row_groups) * 256u + threadIdx.x;
     const int K = J.K;
     long long kl = 0;
-    if (f < (uint32_t)J.p_w && rr < rb && r0 + rr < (uint32_t)J.n) {
+    if (J.reg && f < (uint32_t)J.p_w && rr < rb && r0 + rr < (uint32_t)J.n) {
+        // regression: floor(D^2 / T^2), D the change of the summed leaf levels
+        unsigned long long* d = delta + ((size_t)f * rb + rr) * K;
+        const long long D = (long long)d[0];
+        if (D) {
+            const uint64_t a = (uint64_t)(D < 0 ? -D : D), T = (uint64_t)J.T;
+            kl = (long long)((a * a) / (T * T));
+            d[0] = 0;
+        }
+    } else if (f < (uint32_t)J.p_w && rr < rb && r0 + rr < (uint32_t)J.n) {
         unsigned long long* d = delta + ((size_t)f * rb + rr) * K;
         uint64_t base[KMAX], lg[KMAX], q[KMAX];
         const uint64_t* row_in = S + (size_t)rr * (2 * K + 1);
@@ -475,8 +501,8 @@ __global__ __launch_bounds__(256) void k_hits_decide(JobDev* jobs, int perc) {
     double denom;
     if (J.mode == 0) {
         denom = (double)total;
-    } else if (J.mode == 2) {  // mean divergence per row, in bits
-        denom = (double)J.n * 4294967296.0;
+    } else if (J.mode == 2) {  // mean divergence per row, in bits (regression: level^2)
+        denom = (double)J.n * (J.reg ? 65536.0 : 4294967296.0);
     } else {
         long long oob = 0;
         for (int tau = 0; tau < J.T; ++tau) oob += J.tstat[tau * 4 + 1];

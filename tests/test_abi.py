@@ -145,10 +145,8 @@ def test_regression_arguments_checked_on_the_host():
         B.boruta_fit_regression(X, np.zeros(70000, np.float32), 2, 2, max_iter=2)
     assert e.value.code == B.BORUTA_E_INVALID_ARG
     with pytest.raises(B.BorutaError) as e:
-        B.boruta_fit_regression(X[:50], np.zeros(50, np.float32), 2, 2,
-                                importance_mode=B.PERMUT_KL)
-    assert e.value.code == B.BORUTA_E_UNSUPPORTED
-    assert "Permut" in B.boruta_last_error()
+        B.boruta_fit_regression(X[:50], np.zeros(50, np.float32), 2, 2, importance_mode=3)
+    assert e.value.code == B.BORUTA_E_INVALID_ARG
     with pytest.raises(B.BorutaError) as e:  # summed squared-error drops could overflow
         B.boruta_fit_regression(X[:60000], np.zeros(60000, np.float32), 40000, 2,
                                 importance_mode=B.PERMUT, max_iter=2)

@@ -54,6 +54,17 @@ def test_regression_permutation_importance_matches_oracle(kind, n_perm):
     assert (g["hits"] > 0).any()
 
 
+@pytest.mark.parametrize("kl_rows", [0, 7])
+def test_regression_divergence_importance_matches_oracle(kl_rows):
+    # Algorithm 3 for regression: squared difference of the mean predictions
+    # under the shared row permutation (one row block, or blocks of 7 rows)
+    X, y = problem(49, 900, 10)
+    g, o = both(X, y, 8, 9, importance_mode=B.PERMUT_KL, max_iter=5, seed=18,
+                tune=dict(kl_rows=kl_rows) if kl_rows else None)
+    assert_same_run(g, o)
+    assert (g["hits"] > 0).any()
+
+
 def test_regression_permutation_importance_many_columns():
     # more columns than the per-workgroup drop sums hold: the path that adds
     # every row's drop to the importances directly, as regression always does
