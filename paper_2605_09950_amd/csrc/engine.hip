@@ -516,6 +516,8 @@ public:
     const JobDev& job(int j) const { return hj[j]; }
     // Multi-seed aggregate over all jobs (runs of one problem with p features).
     void seed_median(int64_t p, double* med, int8_t* dec) {
+        // the kernel sorts each feature's values of at most 64 runs in registers
+        if (S.size() > 64) throw Error(BORUTA_E_INVALID_ARG, "multi-seed aggregate: > 64 runs");
         std::vector<const int8_t*> ptrs(S.size());
         for (size_t j = 0; j < S.size(); ++j) ptrs[j] = decisions((int)j);
         h2d(at<void>(pl.dec_ptrs), ptrs.data(), ptrs.size() * sizeof(void*));
@@ -1317,6 +1319,11 @@ int boruta_fit_seeds(const float* X, const int32_t* y, int64_t n, int64_t p, int
     try {
         std::unique_ptr<Context> c = prepare(specs, opt, false, nullptr, 0, nullptr);
         c->eng->run(outs, status);
+        if (results)
+            for (int i = 0; i < n_seeds; ++i) {
+                results[i].n_iter = outs[i].n_iter;
+                results[i].status = status[i];
+            }
         for (int s2 : status)
             if (s2 != BORUTA_OK) {
                 g_err = "the problem failed validation";
@@ -1324,11 +1331,6 @@ int boruta_fit_seeds(const float* X, const int32_t* y, int64_t n, int64_t p, int
             }
         c->eng->seed_median(p, median_importance_out, decision_out);
         HIPC(hipStreamSynchronize(c->st));
-        if (results)
-            for (int i = 0; i < n_seeds; ++i) {
-                results[i].n_iter = outs[i].n_iter;
-                results[i].status = BORUTA_OK;
-            }
         return BORUTA_OK;
     } catch (const Error& e) {
         g_err = e.what();

@@ -325,6 +325,11 @@ def test_multi_seed_median_matches_oracle(seeds):
     assert np.array_equal(h["median_importance"], med)
     assert np.array_equal(h["decision"], dec)
     assert (dec == 1).any()
+    Xbad = X.copy()
+    Xbad[3, 1] = np.inf
+    with pytest.raises(B.BorutaError) as e:
+        B.boruta_fit_seeds(Xbad, y, 2, 8, 8, seeds[:2], **kw)
+    assert e.value.code == B.BORUTA_E_NONFINITE
 
 
 @pytest.mark.parametrize("perc", [90, 50])
