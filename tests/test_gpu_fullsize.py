@@ -8,6 +8,9 @@ caller-provided workspace, iterations replayed from the captured graph).
     and 24 sampled columns' scores.
   * Many-job batch (64 jobs of uneven n, p and class count): the first
     iteration of sampled jobs, every tree, against the oracle run live.
+  * Regression (n=10,000, p=50, 200 trees of depth 12): every tree of the
+    first iteration in all three importance modes, against the oracle run
+    live.
   * Omics-shaped (n=2,000, p=20,000) and mixed-type (n=100,000, p=2,000):
     sampled trees of the first iteration against the node-table digests in
     tests/golden/fullsize_trees.json (written by make_fullsize_golden.py,
@@ -38,10 +41,13 @@ def gpu_first_iteration(jobs, n_bins, n_perm=1, tune=None):
     for jd in jobs:
         d = dict(jd)
         d["X"] = torch.from_numpy(np.ascontiguousarray(jd["X"])).cuda()
-        d["y"] = torch.from_numpy(np.ascontiguousarray(jd["y"])).cuda()
+        for key in ("y", "y_reg"):
+            if key in jd:
+                d[key] = torch.from_numpy(np.ascontiguousarray(jd[key])).cuda()
         dev.append(d)
-    shapes = [dict(n=d["X"].shape[0], p=d["X"].shape[1],
-                   **{k: v for k, v in d.items() if k not in ("X", "y")}) for d in dev]
+    shapes = [dict(n=d["X"].shape[0], p=d["X"].shape[1], regression="y_reg" in d,
+                   **{k: v for k, v in d.items() if k not in ("X", "y", "y_reg")})
+              for d in dev]
     ws_bytes = B.boruta_workspace_size(shapes, n_bins=n_bins, n_perm=n_perm, tune=tune)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
@@ -119,6 +125,25 @@ def test_many_job_batch_sampled_jobs(tune):
         assert_same_trace(by_job[j], o["trace"])
         assert np.array_equal(by_job[j]["hits"], o["hits"])
         assert np.array_equal(by_job[j]["state"], o["state"])
+
+
+@pytest.mark.parametrize("mode", [B.TREEIMP, B.PERMUT, B.PERMUT_KL])
+def test_regression_first_iteration_all_trees(mode):
+    c = synth.config(5)
+    pr = c["params"]
+    jd = dict(X=c["X"], y_reg=c["y_reg"], n_trees=pr["n_trees"], max_depth=pr["max_depth"],
+              mtry=pr["mtry"], importance_mode=mode, max_iter=pr["max_iter"], alpha=pr["alpha"],
+              seed=c["seed"])
+    print(f"regression n=10000 p=50 T=200 D=12 mode={mode}", flush=True)
+    g = gpu_first_iteration([jd], pr["n_bins"])
+    assert len(g) == 1 and g[0]["t"] == 1
+    o = O.boruta_fit_reg(c["X"], c["y_reg"], pr["n_trees"], pr["max_depth"], mtry=pr["mtry"],
+                         importance_mode=mode, max_iter=1, alpha=pr["alpha"], seed=c["seed"],
+                         n_bins=pr["n_bins"], n_threads=min(16, os.cpu_count() or 1),
+                         trace=True)
+    assert_same_trace(g[0], o["traces"][0])
+    assert np.array_equal(g[0]["hits"], o["hits"])
+    assert np.array_equal(g[0]["state"], o["decision"])
 
 
 def digest(nodes):
