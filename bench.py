@@ -182,7 +182,7 @@ def measured_traffic(workload_name, kernel):
     calibrated FETCH_SIZE + WRITE_SIZE counter summary committed under
     profiles/, or None when there is none for this workload or the kernel
     source has changed since the counters were taken."""
-    if kernel not in ("hist_large", "hist_col"):
+    if kernel not in KERNEL_NAMES:
         return None
     path = os.path.join(ROOT, "profiles", f"{KERNEL_NAMES[kernel]}_{workload_name}_traffic.md")
     if not os.path.exists(path):
