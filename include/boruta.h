@@ -332,6 +332,14 @@ int boruta_session_create(const boruta_job* jobs, int32_t n_jobs, const boruta_o
                           void* hip_stream, boruta_session** out);
 /* One iteration of every live job; *n_live_out (nullable) = jobs still live. */
 int boruta_session_step(boruta_session* s, int32_t* n_live_out);
+/* Up to max_steps iterations of every live job, as many boruta_session_step
+ * calls would run them, with the same results; with graph replay (and no
+ * trace or statistics) the iterations are enqueued back to back, without a
+ * host wait between them, and a job that finishes on the way is skipped by
+ * the later ones.  *n_live_out and *job_iterations_out (nullable) = jobs
+ * still live and the job-iterations run. */
+int boruta_session_run(boruta_session* s, int32_t max_steps, int32_t* n_live_out,
+                       int64_t* job_iterations_out);
 /* Current decision/history/hits/shadow maximum of one job (caller buffers as
  * in boruta_result; n_iter = iterations done so far). */
 int boruta_session_result(boruta_session* s, int32_t job, boruta_result* out);

@@ -88,7 +88,8 @@ class Result(ctypes.Structure):
 EXPORTS = ["boruta_default_options", "boruta_fit", "boruta_fit_ex", "boruta_fit_batch",
            "boruta_fit_seeds", "boruta_fit_regression",
            "boruta_workspace_size", "boruta_fit_device", "boruta_session_create",
-           "boruta_session_step", "boruta_session_result", "boruta_session_resume",
+           "boruta_session_step", "boruta_session_run", "boruta_session_result",
+           "boruta_session_resume",
            "boruta_session_destroy", "boruta_probe_copy", "boruta_last_error"]
 
 _lib = None
@@ -141,6 +142,9 @@ def lib():
         L.boruta_session_create.restype = ctypes.c_int
         L.boruta_session_step.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
         L.boruta_session_step.restype = ctypes.c_int
+        L.boruta_session_run.argtypes = [P, i32, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int64)]
+        L.boruta_session_run.restype = ctypes.c_int
         L.boruta_session_result.argtypes = [P, i32, ctypes.POINTER(Result)]
         L.boruta_session_result.restype = ctypes.c_int
         L.boruta_session_resume.argtypes = [P, i32, i32, P, P]
@@ -510,6 +514,13 @@ class Session:
         n = ctypes.c_int32(0)
         _check(lib().boruta_session_step(self.h, ctypes.byref(n)))
         return n.value
+
+    def run(self, max_steps):
+        """Up to max_steps iterations enqueued back to back; returns (jobs
+        still live, job-iterations run)."""
+        n, done = ctypes.c_int32(0), ctypes.c_int64(0)
+        _check(lib().boruta_session_run(self.h, max_steps, ctypes.byref(n), ctypes.byref(done)))
+        return n.value, done.value
 
     def result(self, job=0):
         p, max_iter = self._shapes[job]

@@ -54,6 +54,7 @@ void launch_kl_block(JobDev*, int, const NodeDev*, const uint32_t*, int, uint32_
                      uint32_t, uint32_t, uint64_t*, uint32_t*, unsigned long long*, int,
                      hipStream_t);
 void launch_copy(void*, const void*, size_t, hipStream_t);
+void launch_ctr_sticky(LevelCtr*, int, hipStream_t);
 void launch_seed_median(const JobDev*, const int8_t* const*, int, int64_t, double*, int8_t*,
                         hipStream_t);
 void launch_rank(const int8_t*, const double*, int64_t, int, int, double*, int32_t*, hipStream_t);
@@ -508,6 +509,9 @@ public:
     void setup(std::vector<int>& status);
     // One iteration of every live job; returns the number still live.
     int step();
+    // Up to k iterations enqueued back to back (graph replays, no host wait
+    // between them); returns the job-iterations run and the jobs still live.
+    int64_t run_steps(int k, int* n_live);
     void result(int j, Out& o);
     const int8_t* decisions(int j);
     // Continue job j from a checkpoint: the next iteration is t + 1.
@@ -700,6 +704,8 @@ void Engine::setup(std::vector<int>& status) {
         }
     }
     h2d(at<JobDev>(pl.jobs), hj.data(), hj.size() * sizeof(JobDev));
+    // level counters, and the accumulated capacity flags after them
+    launch_fill_u32(at<uint32_t>(pl.ctrs), (size_t)(pl.max_D + 2) * sizeof(LevelCtr) / 4, 0u, st);
     HIPC(hipStreamSynchronize(st));
 }
 
@@ -890,6 +896,7 @@ void Engine::enqueue_iteration() {
         clock.end(h, st);
     }
     launch_hits_decide(djobs, nj, O.perc, st);
+    launch_ctr_sticky(at<LevelCtr>(pl.ctrs), pl.max_D, st);
     clock.end(h_whole, st);
 }
 
@@ -930,14 +937,14 @@ void Engine::iteration(const std::vector<int>& live) {
         enqueue_iteration();
     }
     const int n_levels = pl.max_D;
-    std::vector<LevelCtr> c(n_levels + 1);
+    std::vector<LevelCtr> c(n_levels + 2);  // levels, then the accumulated flags
     HIPC(hipMemcpyAsync(c.data(), at<LevelCtr>(pl.ctrs), c.size() * sizeof(LevelCtr),
                         hipMemcpyDeviceToHost, st));
     d2h(hj.data(), at<JobDev>(pl.jobs), hj.size() * sizeof(JobDev));
     clock.collect(use_graph);
     uint32_t overflow = 0;
     uint64_t n_nodes = (uint32_t)pl.T_total;
-    for (int d = 0; d <= n_levels; ++d) {
+    for (int d = 0; d <= n_levels + 1; ++d) {
         overflow |= c[d].overflow;
         if (d < n_levels) n_nodes += 2ull * (c[d].n_small + c[d].n_slots);
     }
@@ -1028,6 +1035,42 @@ int Engine::step() {
     int n = 0;
     for (const JobDev& J : hj) n += J.live != 0;
     return n;
+}
+
+int64_t Engine::run_steps(int k, int* n_live) {
+    std::vector<int32_t> t0(hj.size());
+    for (size_t j = 0; j < hj.size(); ++j) t0[j] = hj[j].t;
+    const bool replay = O.graph && O.form == BORUTA_FORM_BATCHED && !O.stats && !O.trace;
+    for (int i = 0; i < k; ++i) {
+        std::vector<int> live;
+        for (int j = 0; j < (int)S.size(); ++j)
+            if (hj[j].live) live.push_back(j);
+        if (live.empty()) break;
+        if (!replay || !gexec) {
+            iteration(live);  // with a host read-back (and the graph's capture)
+            continue;
+        }
+        // The host's view of liveness stays as it was: a job that finishes
+        // on the device is skipped by every kernel of the later replays.
+        HIPC(hipGraphLaunch(gexec, st));
+    }
+    if (replay) {
+        std::vector<LevelCtr> c(pl.max_D + 2);
+        HIPC(hipMemcpyAsync(c.data(), at<LevelCtr>(pl.ctrs), c.size() * sizeof(LevelCtr),
+                            hipMemcpyDeviceToHost, st));
+        d2h(hj.data(), at<JobDev>(pl.jobs), hj.size() * sizeof(JobDev));
+        if (c[pl.max_D + 1].overflow)
+            throw Error(BORUTA_E_DEVICE, "internal capacity exceeded (flags " +
+                                             std::to_string(c[pl.max_D + 1].overflow) + ")");
+    }
+    int64_t done = 0;
+    int n = 0;
+    for (size_t j = 0; j < hj.size(); ++j) {
+        done += hj[j].t - t0[j];
+        n += hj[j].live != 0;
+    }
+    if (n_live) *n_live = n;
+    return done;
 }
 
 void Engine::flush_stats() {
@@ -1503,6 +1546,29 @@ int boruta_session_step(boruta_session* s, int32_t* n_live_out) {
         const int n = s->ctx->eng->step();
         s->ctx->eng->flush_stats();
         if (n_live_out) *n_live_out = n;
+        return BORUTA_OK;
+    } catch (const Error& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return BORUTA_E_DEVICE;
+    }
+}
+
+int boruta_session_run(boruta_session* s, int32_t max_steps, int32_t* n_live_out,
+                       int64_t* job_iterations_out) {
+    g_err.clear();
+    if (!s || max_steps < 0) {
+        g_err = "null session or max_steps < 0";
+        return BORUTA_E_INVALID_ARG;
+    }
+    try {
+        int n = 0;
+        const int64_t done = s->ctx->eng->run_steps(max_steps, &n);
+        s->ctx->eng->flush_stats();
+        if (n_live_out) *n_live_out = n;
+        if (job_iterations_out) *job_iterations_out = done;
         return BORUTA_OK;
     } catch (const Error& e) {
         g_err = e.what();

@@ -674,6 +674,20 @@ __global__ __launch_bounds__(256) void k_rough_fix(const int8_t* state, const do
     if (threadIdx.x == 0) out[j] = mf > ms ? (int8_t)1 : (int8_t)-1;
 }
 
+// Capacity flags of an iteration's tree levels, accumulated into the word
+// after them, which only the session set-up clears: iterations enqueued back
+// to back then report a failure of any one of them.
+__global__ void k_ctr_sticky(LevelCtr* c, int n_levels) {
+    if (threadIdx.x != 0) return;
+    uint32_t o = 0;
+    for (int d = 0; d <= n_levels; ++d) o |= c[d].overflow;
+    c[n_levels + 1].overflow |= o;
+}
+
+void launch_ctr_sticky(LevelCtr* c, int n_levels, hipStream_t st) {
+    hipLaunchKernelGGL(k_ctr_sticky, dim3(1), dim3(64), 0, st, c, n_levels);
+}
+
 // Streaming copy used to calibrate hardware byte counters.
 __global__ void k_copy(uint4* dst, const uint4* src, size_t n16) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;

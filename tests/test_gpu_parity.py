@@ -227,6 +227,38 @@ def test_graph_replays_match_eager_launches(mode):
     assert_same_run(graph, eager)
 
 
+@pytest.mark.parametrize("chunk", [100, 3])
+def test_session_run_back_to_back_equals_stepping(chunk):
+    # iterations enqueued back to back (graph replays without host waits), for
+    # a batch whose jobs finish at different iterations: the same results as
+    # one step at a time, and the job-iterations counted on the device
+    jobs = []
+    for j in range(4):
+        X, y = problem(80 + j, 500 + 200 * j, 9 + j, 2 + j % 2)
+        jobs.append(dict(X=X, y=y, n_classes=2 + j % 2, n_trees=6, max_depth=7,
+                         importance_mode=j % 3, max_iter=3 + 3 * j, seed=90 + j))
+    with B.Session(jobs) as a:
+        while a.step():
+            pass
+        want = [a.result(j) for j in range(len(jobs))]
+    total = 0
+    with B.Session(jobs) as b:
+        live = len(jobs)
+        while live:
+            live, done = b.run(chunk)
+            total += done
+        got = [b.result(j) for j in range(len(jobs))]
+        assert b.run(5) == (0, 0)  # nothing left to run
+    assert total == sum(w["n_iter"] for w in want)
+    for g, w in zip(got, want):
+        assert g["n_iter"] == w["n_iter"]
+        assert np.array_equal(g["decision"], w["decision"])
+        assert np.array_equal(g["hits"], w["hits"])
+        assert np.array_equal(g["rank"], w["rank"])
+        k = w["n_iter"]
+        assert np.array_equal(g["imp_history"][:k], w["imp_history"][:k], equal_nan=True)
+
+
 def test_graph_session_with_stats_and_resume():
     X, y = problem(27, 900, 16, 2)
     kw = dict(n_classes=2, n_trees=7, max_depth=8, max_iter=10, seed=13)
