@@ -132,6 +132,7 @@ def run_gpu(jobs, pr, steps, warmup, form, rank, stats, graph=True, tune=None):
             k = getattr(sess.stats, f)
             k.launches, k.ms, k.alg_bytes = 0, 0.0, 0.0
         sess.stats.iter_ms, sess.stats.iterations, sess.stats.nodes = 0.0, 0, 0
+        sess.stats.permut_visits = 0.0
         for d in range(32):
             sess.stats.level_small[d] = sess.stats.level_large[d] = 0
     done, job_iters = 0, 0
@@ -373,6 +374,9 @@ def main():
                                          if tune is not None else {})),
              "eager_" + unit.replace("/", "_per_"): round(ev_leg["job_iters"] /
                                                          ev_leg["seconds"], 3),
+             # Permut's out-of-bag walks: tree nodes visited per second of its kernel
+             "permut_node_visits_per_s": (round(st.permut_visits / (st.permut.ms * 1e-3), 1)
+                                          if st.permut.ms > 0 else None),
              "nodes_per_step_by_depth": {
                  "small": [round(st.level_small[d] / n_steps, 1)
                            for d in range(max(j["max_depth"] for j in jobs))],

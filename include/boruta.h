@@ -104,6 +104,8 @@ typedef struct {
     int64_t level_large[32];       /* nodes searched by the tiled path, per depth */
     boruta_kernel_stat hist_col;   /* column-major histogram + split scan (levels
                                       >= col_level; hist_large covers the others) */
+    double permut_visits;          /* tree nodes visited by the out-of-bag walks of
+                                      Permut (base paths and re-routings)          */
 } boruta_stats;
 
 typedef struct {

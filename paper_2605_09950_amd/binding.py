@@ -51,7 +51,8 @@ class Stats(ctypes.Structure):
                 ("permut", KernelStat),
                 ("iter_ms", ctypes.c_double), ("iterations", ctypes.c_int64),
                 ("nodes", ctypes.c_int64), ("level_small", ctypes.c_int64 * 32),
-                ("level_large", ctypes.c_int64 * 32), ("hist_col", KernelStat)]
+                ("level_large", ctypes.c_int64 * 32), ("hist_col", KernelStat),
+                ("permut_visits", ctypes.c_double)]
 
 
 class Options(ctypes.Structure):

@@ -46,7 +46,7 @@ void launch_hist_col(const ForestDev&, int, uint32_t, int, uint32_t, hipStream_t
 void launch_tree_totals(JobDev*, const TreeDev*, int, uint64_t*, hipStream_t);
 void launch_treeimp(JobDev*, const TreeDev*, int, const uint64_t*, int, hipStream_t);
 void launch_permut(JobDev*, const TreeDev*, const NodeDev*, const uint32_t*, int, int, int64_t,
-                   int, int, bool, hipStream_t);
+                   int, int, bool, unsigned long long*, hipStream_t);
 void launch_hits_decide(JobDev*, int, int, hipStream_t);
 void launch_rough_fix(const int8_t*, const double*, const double*, int64_t, int, int, int8_t*,
                       hipStream_t);
@@ -374,7 +374,7 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     pl.slot1 = r.take((size_t)pl.slot_cap * 4);
     // level d < max_D reads ctrs[d] and appends to ctrs[d + 1]
     pl.ctrs = r.take((size_t)(pl.max_D + 2) * sizeof(LevelCtr));
-    pl.alg = r.take(3 * kAlgWords * 8);
+    pl.alg = r.take(4 * kAlgWords * 8);  // algorithmic bytes [3][..], Permut node visits
     pl.tot = r.take((size_t)pl.T_total * 8);
     {
         int64_t pmax = 1;
@@ -676,7 +676,7 @@ void Engine::setup(std::vector<int>& status) {
     }
     h2d(at<TreeDev>(pl.trees), trees.data(), trees.size() * sizeof(TreeDev));
     h2d(at<int32_t>(pl.tree_base), tree_base.data(), tree_base.size() * 4);
-    launch_fill_u32(at<uint32_t>(pl.alg), 6 * kAlgWords, 0u, st);
+    launch_fill_u32(at<uint32_t>(pl.alg), 8 * kAlgWords, 0u, st);
     // KL importance differences start at zero; each block's reader clears them
     if (any_kl) {
         size_t words = 0;
@@ -878,7 +878,9 @@ void Engine::enqueue_iteration() {
         bool any_reg = false;
         for (const Spec& sp : S) any_reg |= sp.yr != nullptr;
         launch_permut(djobs, dtrees, F.nodes, F.cls, pl.kmax, (int)n_trees, pl.max_n, pl.max_D,
-                      pl.max_pw, any_reg, st);
+                      pl.max_pw, any_reg,
+                      stats ? (unsigned long long*)at<uint64_t>(pl.alg) + 3 * kAlgWords : nullptr,
+                      st);
         clock.end(h, st);
     }
     if (any_kl) {
@@ -1075,14 +1077,15 @@ int64_t Engine::run_steps(int k, int* n_live) {
 
 void Engine::flush_stats() {
     if (!O.stats) return;
-    std::vector<uint64_t> ab(3 * kAlgWords);
+    std::vector<uint64_t> ab(4 * kAlgWords);
     d2h(ab.data(), at<uint64_t>(pl.alg), ab.size() * 8);
     for (uint32_t i = 0; i < kAlgWords; ++i) {
         O.stats->hist_large.alg_bytes += (double)ab[i];
         O.stats->hist_small.alg_bytes += (double)ab[kAlgWords + i];
         O.stats->hist_col.alg_bytes += (double)ab[2 * kAlgWords + i];
+        O.stats->permut_visits += (double)ab[3 * kAlgWords + i];
     }
-    launch_fill_u32(at<uint32_t>(pl.alg), 6 * kAlgWords, 0u, st);
+    launch_fill_u32(at<uint32_t>(pl.alg), 8 * kAlgWords, 0u, st);
 }
 
 // Decisions of job j as reported: the live state, or after the rough fix of

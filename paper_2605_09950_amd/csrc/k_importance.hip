@@ -86,7 +86,8 @@ __device__ __forceinline__ long long sq_error_fix(const uint32_t* cls, int kmax,
 
 __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* trees,
                                                 const NodeDev* nodes, const uint32_t* cls,
-                                                int kmax, int max_depth, int lds_cols) {
+                                                int kmax, int max_depth, int lds_cols,
+                                                unsigned long long* visits) {
     extern __shared__ uint32_t s_path[];  // [2][max_depth][256]: node, feature; [lds_cols] drops
     const uint32_t g = blockIdx.y;
     const TreeDev tr = trees[g];
@@ -119,6 +120,7 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
     uint32_t node = g;
     bool base_ok = false;
     long long base_err = 0;
+    unsigned long long nv = 0;  // node visits (statistics)
     if (active) {
         NodeDev nd = nodes[node];
         while (nd.feat >= 0) {
@@ -128,6 +130,7 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
             node = (int)J.colptr[nd.feat][row] <= (int)nd.thr ? nd.left : nd.left + 1;
             nd = nodes[node];
         }
+        nv += (unsigned long long)len + 1u;
         if (reg)
             base_err = sq_error_fix(cls, kmax, node, yv);
         else
@@ -150,10 +153,12 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
             const int sb = fcol[oob[perm_apply(P, j)]];
             uint32_t nd_i = start;
             NodeDev nd = nodes[nd_i];
+            ++nv;
             while (nd.feat >= 0) {
                 const int b = (uint32_t)nd.feat == f ? sb : (int)J.colptr[nd.feat][row];
                 nd_i = b <= (int)nd.thr ? nd.left : nd.left + 1;
                 nd = nodes[nd_i];
+                ++nv;
             }
             if (reg)
                 drop_sq += sq_error_fix(cls, kmax, nd_i, yv) - base_err;
@@ -179,6 +184,11 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
             const long long v = reg ? s_drop64[c] : (long long)s_drop[c];
             if (v) atomicAdd((unsigned long long*)&J.imp[c], (unsigned long long)v);
         }
+    }
+    if (visits) {
+        for (int m = 1; m < 64; m <<= 1) nv += __shfl_xor(nv, m);
+        if ((tid & 63) == 0 && nv)
+            atomicAdd(visits + ((blockIdx.x * 4u + (uint32_t)(tid >> 6)) & (kAlgWords - 1)), nv);
     }
 }
 
@@ -708,14 +718,15 @@ void launch_treeimp(JobDev* jobs, const TreeDev* trees, int n_trees, const uint6
 
 void launch_permut(JobDev* jobs, const TreeDev* trees, const NodeDev* nodes, const uint32_t* cls,
                    int kmax, int n_trees, int64_t max_n, int max_depth, int max_pw,
-                   bool any_reg, hipStream_t st) {
+                   bool any_reg, unsigned long long* visits, hipStream_t st) {
     // per-column drop sums in LDS for jobs of at most 1024 widened columns
     // (64-bit when the batch has a regression job)
     const int lds_cols = max_pw < 1024 ? max_pw : 1024;
     const size_t lds = (size_t)2 * max_depth * 256 * sizeof(uint32_t) +
                        (size_t)lds_cols * (any_reg ? 8 : 4);
     hipLaunchKernelGGL(k_permut, dim3((unsigned)((max_n + 255) / 256), (unsigned)n_trees),
-                       dim3(256), lds, st, jobs, trees, nodes, cls, kmax, max_depth, lds_cols);
+                       dim3(256), lds, st, jobs, trees, nodes, cls, kmax, max_depth, lds_cols,
+                       visits);
 }
 
 // The KL importance of job j over rows [r0, r0 + rb): base, deltas, reduce.

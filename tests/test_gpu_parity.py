@@ -259,6 +259,25 @@ def test_session_run_back_to_back_equals_stepping(chunk):
         assert np.array_equal(g["imp_history"][:k], w["imp_history"][:k], equal_nan=True)
 
 
+def test_permutation_node_visits_counted_under_statistics():
+    # every OOB row walks at least its root; a walk of depth <= D visits at
+    # most D + 1 nodes, and each of at most D path columns is re-routed R times
+    X, y = problem(29, 800, 12, 2)
+    R, D = 2, 7
+    jd = dict(X=X, y=y, n_classes=2, n_trees=5, max_depth=D, max_iter=3, seed=21)
+    with B.Session([dict(jd, importance_mode=B.PERMUT)], n_perm=R, stats=True,
+                   trace=True) as s:
+        while s.step():
+            pass
+        v = s.stats.permut_visits
+        m = sum(int(t["tree_stats"][:, 2].sum()) for t in s.traces)
+    assert m > 0 and m <= v <= m * (D + 1) * (1 + R * D)
+    with B.Session([dict(jd, importance_mode=B.TREEIMP)], stats=True) as s:
+        while s.step():
+            pass
+        assert s.stats.permut_visits == 0
+
+
 def test_graph_session_with_stats_and_resume():
     X, y = problem(27, 900, 16, 2)
     kw = dict(n_classes=2, n_trees=7, max_depth=8, max_iter=10, seed=13)
