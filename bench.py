@@ -105,6 +105,8 @@ def run_gpu(jobs, pr, steps, warmup, form, rank, stats, graph=True, tune=None):
     import torch
     from paper_2605_09950_amd import binding as B
     dev, shapes = [], []
+    torch.cuda.synchronize()
+    t_up = time.perf_counter()  # host-to-device upload of the inputs (PCIe)
     for jd in jobs:
         d = dict(jd)
         d["X"] = torch.from_numpy(jd["X"]).cuda()
@@ -115,13 +117,21 @@ def run_gpu(jobs, pr, steps, warmup, form, rank, stats, graph=True, tune=None):
         dev.append(d)
         shapes.append(dict(n=d["X"].shape[0], p=d["X"].shape[1], regression="y_reg" in jd,
                            **{k: v for k, v in d.items() if k not in ("X", "y", "y_reg")}))
+    torch.cuda.synchronize()
+    t_up = time.perf_counter() - t_up
     ws_bytes = B.boruta_workspace_size(shapes, n_bins=pr["n_bins"], n_perm=pr["n_perm"],
                                        tune=tune)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter()
+    # session set-up: validation, labels, binning and the decision thresholds
+    # of every job (inputs already on the device), outside the timed region
     sess = B.Session(dev, n_bins=pr["n_bins"], n_perm=pr["n_perm"], split_rank=rank,
                      form=form, stats=stats, inputs_on_device=True, workspace=ws,
                      stream=stream, graph=graph, tune=tune)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
     live = len(jobs)
     for _ in range(warmup):
         if live:
@@ -159,7 +169,7 @@ def run_gpu(jobs, pr, steps, warmup, form, rank, stats, graph=True, tune=None):
         el = time.perf_counter() - t0
     decisions = [sess.result(j)["decision"] for j in range(len(jobs))]
     out = dict(steps=done, job_iters=job_iters, seconds=el, stats=sess.stats,
-               decisions=decisions)
+               decisions=decisions, setup_s=t_setup, upload_s=t_up)
     sess.close()
     return out
 
@@ -369,6 +379,9 @@ def main():
     extra = {"kernels": kernels, "timed_iterations": f"{args.warmup + 1}.."
              f"{args.warmup + main_leg['steps']}", "job_iterations": main_leg["job_iters"],
              "device_iter_ms": round(st.iter_ms / n_steps, 3),
+             # per run, before the iterations: validation, labels, binning
+             "setup_ms_binning": round(main_leg["setup_s"] * 1e3, 2),
+             "upload_ms_pcie": round(main_leg["upload_s"] * 1e3, 2),
              "tune": dict(tune or {}, **({"search_s": round(tune_s, 2),
                                           "sessions": tune_report.get("sessions", 0)}
                                          if tune is not None else {})),
