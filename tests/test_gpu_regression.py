@@ -131,3 +131,27 @@ def test_regression_jobs_in_a_batch_and_a_device_session():
     assert np.array_equal(res["decision"], reg["decision"])
     k = reg["n_iter"]
     assert np.array_equal(res["imp_history"][:k], reg["imp_history"][:k])
+
+
+@pytest.mark.parametrize("n,p,D", [(2, 1, 1), (3, 2, 3), (5, 1, 30)], ids=["n2p1", "n3p2", "n5p1D30"])
+def test_regression_degenerate_shapes(n, p, D):
+    # two to five rows, one or two features (shadow doubling), depth 1 and 30
+    rng = np.random.default_rng(50 + n)
+    X = rng.random((n, p)).astype(np.float32)
+    y = rng.random(n).astype(np.float32)
+    for mode in (B.TREEIMP, B.PERMUT, B.PERMUT_KL):
+        g, o = both(X, y, 3, D, importance_mode=mode, max_iter=3, seed=19)
+        assert_same_run(g, o)
+
+
+def test_regression_at_the_row_limit():
+    # n = 65536, where 255 times a node's bootstrap weight comes closest to
+    # the 2^24 bound of the exact arithmetic
+    rng = np.random.default_rng(51)
+    n, p = 65536, 4
+    X = rng.random((n, p)).astype(np.float32)
+    y = (X[:, 0] + 0.1 * rng.standard_normal(n)).astype(np.float32)
+    g, o = both(X, y, 3, 6, max_iter=2, seed=20, n_bins=64)
+    assert_same_run(g, o)
+    root_n = max(int(t["nodes"][t["nodes"][:, 1] == 1, 4].max()) for t in g["traces"])
+    assert root_n == 255 * n  # the root's weighted count: 255 x (the n bootstrap draws)
