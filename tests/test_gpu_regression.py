@@ -155,3 +155,11 @@ def test_regression_at_the_row_limit():
     assert_same_run(g, o)
     root_n = max(int(t["nodes"][t["nodes"][:, 1] == 1, 4].max()) for t in g["traces"])
     assert root_n == 255 * n  # the root's weighted count: 255 x (the n bootstrap draws)
+
+
+def test_regression_plain_per_node_form_matches_oracle():
+    # the plain form (one launch per tree node) on the two-record layout
+    X, y = problem(52, 400, 7)
+    g = B.boruta_fit_regression(X, y, 4, 6, max_iter=3, seed=21, form=B.FORM_PLAIN, trace=True)
+    o = O.boruta_fit_reg(X, y, 4, 6, max_iter=3, seed=21, trace=True)
+    assert_same_run(g, o)
