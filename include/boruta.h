@@ -32,7 +32,9 @@
  * compare integers).
  *
  * Conventions: the caller owns every buffer; the library never frees caller
- * memory.  Host pointers unless stated otherwise.  All entry points are
+ * memory.  Entry points that allocate device memory (all but the ones given a
+ * workspace) fail with BORUTA_E_OOM when the environment variable
+ * BORUTA_FAIL_ALLOC is "1" (a hook for failure tests).  Host pointers unless stated otherwise.  All entry points are
  * blocking.  On error the return value is negative and boruta_last_error()
  * (thread-local) describes it; output buffers are then unspecified.
  */

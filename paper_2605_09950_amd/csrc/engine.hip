@@ -9,6 +9,7 @@
 #include <climits>
 #include <memory>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <stdexcept>
 #include <string>
@@ -1207,8 +1208,13 @@ std::unique_ptr<Context> prepare(const std::vector<Spec>& specs, const boruta_op
         if (ws_bytes < need) throw Error(BORUTA_E_OOM, "workspace smaller than boruta_workspace_size");
         base = (char*)ws;
     } else {
-        if (hipMalloc(&c->reg.p, need) != hipSuccess) {
+        // BORUTA_FAIL_ALLOC=1 in the environment makes this allocation fail
+        // (failure tests: the call must return BORUTA_E_OOM and leak nothing)
+        const char* fail = std::getenv("BORUTA_FAIL_ALLOC");
+        if ((fail && std::strcmp(fail, "1") == 0) ||
+            hipMalloc(&c->reg.p, need) != hipSuccess) {
             (void)hipGetLastError();
+            c->reg.p = nullptr;
             throw Error(BORUTA_E_OOM, "hipMalloc of " + std::to_string(need) + " bytes failed");
         }
         base = c->reg.p;

@@ -157,6 +157,36 @@ def test_batch_jobs_sharing_inputs_equal_single_jobs():
     assert e.value.code == B.BORUTA_E_NONFINITE
 
 
+def test_allocation_failure_returns_oom_and_leaks_nothing(monkeypatch):
+    # the failure hook makes the library's device allocation fail: every entry
+    # point that allocates returns BORUTA_E_OOM, device memory does not
+    # shrink over repeated failures, and later calls give the usual results
+    import torch
+    X, y = problem(24, 700, 9, 2)
+    kw = dict(max_iter=3, seed=5)
+    want = B.boruta_fit_ex(X, y, 2, 5, 7, **kw)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    monkeypatch.setenv("BORUTA_FAIL_ALLOC", "1")
+    calls = [lambda: B.boruta_fit_ex(X, y, 2, 5, 7, **kw),
+             lambda: B.boruta_fit_batch([dict(X=X, y=y, n_classes=2, n_trees=5, max_depth=7,
+                                              **kw)]),
+             lambda: B.boruta_fit_seeds(X, y, 2, 5, 7, [1, 2], max_iter=3),
+             lambda: B.boruta_fit_regression(X, X[:, 0].copy(), 5, 7, **kw),
+             lambda: B.Session([dict(X=X, y=y, n_classes=2, n_trees=5, max_depth=7, **kw)])]
+    for _ in range(5):
+        for call in calls:
+            with pytest.raises(B.BorutaError) as e:
+                call()
+            assert e.value.code == B.BORUTA_E_OOM
+    monkeypatch.delenv("BORUTA_FAIL_ALLOC")
+    torch.cuda.synchronize()
+    assert free0 - torch.cuda.mem_get_info()[0] < (16 << 20)
+    again = B.boruta_fit_ex(X, y, 2, 5, 7, **kw)
+    assert np.array_equal(again["decision"], want["decision"])
+    assert np.array_equal(again["imp_history"], want["imp_history"], equal_nan=True)
+
+
 def test_device_entry_point_matches_host_entry_point():
     import torch
     X, y = problem(23, 1000, 12, 2)
