@@ -358,6 +358,14 @@ void boruta_session_destroy(boruta_session* s);
  * hardware byte counters); returns BORUTA_OK or an error code. */
 int boruta_probe_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
 
+/* The binning step alone (the quantile bins that every run starts from):
+ * X [n][p] float32 host, row-major; bins_out [p][n] uint8 host, column-major:
+ * per column, the order statistics of rank ceil(k n / n_bins) - 1 (k = 1 ..
+ * n_bins - 1) are candidate cuts, the strictly increasing distinct ones form
+ * the cut list U, and x gets bin #{u in U : u < x}.  Runs on the device;
+ * BORUTA_E_NONFINITE for NaN/Inf in X. */
+int boruta_bin(const float* X, int64_t n, int64_t p, int32_t n_bins, uint8_t* bins_out);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char* boruta_last_error(void);
 

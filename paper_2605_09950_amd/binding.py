@@ -90,7 +90,7 @@ EXPORTS = ["boruta_default_options", "boruta_fit", "boruta_fit_ex", "boruta_fit_
            "boruta_fit_seeds", "boruta_fit_regression",
            "boruta_workspace_size", "boruta_fit_device", "boruta_session_create",
            "boruta_session_step", "boruta_session_run", "boruta_session_result",
-           "boruta_session_resume",
+           "boruta_session_resume", "boruta_bin",
            "boruta_session_destroy", "boruta_probe_copy", "boruta_last_error"]
 
 _lib = None
@@ -152,6 +152,8 @@ def lib():
         L.boruta_session_resume.restype = ctypes.c_int
         L.boruta_session_destroy.argtypes = [P]
         L.boruta_session_destroy.restype = None
+        L.boruta_bin.argtypes = [P, i64, i64, i32, P]
+        L.boruta_bin.restype = ctypes.c_int
         L.boruta_probe_copy.argtypes = [P, P, ctypes.c_size_t, P]
         L.boruta_probe_copy.restype = ctypes.c_int
         L.boruta_last_error.argtypes = []
@@ -441,6 +443,15 @@ def boruta_fit_device(dX, dy, n_classes, n_trees, max_depth, workspace, stream=N
            "n_iter": int(n_iter[0]), "traces": keep["iters"]}
     if stats:
         out["stats"] = keep["stats"]
+    return out
+
+
+def boruta_bin(X, n_bins=256):
+    """Quantile bins of X [n][p] computed on the device: uint8 [p][n]."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    n, p = X.shape
+    out = np.zeros((p, n), np.uint8)
+    _check(lib().boruta_bin(_ptr(X), n, p, n_bins, _ptr(out)))
     return out
 
 

@@ -1492,6 +1492,51 @@ int boruta_fit_device(const float* dX, const int32_t* dy, int64_t n, int64_t p,
     return finish_single(rc, outs, n_iter_out);
 }
 
+int boruta_bin(const float* X, int64_t n, int64_t p, int32_t n_bins, uint8_t* bins_out) {
+    g_err.clear();
+    if (!X || !bins_out || n < 1 || n > (int64_t(1) << 24) || p < 1 ||
+        p > (int64_t(1) << 24) || n_bins < 2 || n_bins > 256) {
+        g_err = "X and bins_out non-null, n and p in [1, 2^24], n_bins in [2, 256]";
+        return BORUTA_E_INVALID_ARG;
+    }
+    try {
+        require_device();
+        const int64_t n_pad = round_up(n, 256), P = pow2_at_least(n);
+        const size_t bx = (size_t)n * p * 4, bk = (size_t)p * P * 4, bb = (size_t)p * n_pad;
+        DeviceRegion reg;
+        const char* fail = std::getenv("BORUTA_FAIL_ALLOC");
+        if ((fail && std::strcmp(fail, "1") == 0) ||
+            hipMalloc(&reg.p, bx + bk + bb + 256) != hipSuccess) {
+            (void)hipGetLastError();
+            reg.p = nullptr;
+            throw Error(BORUTA_E_OOM, "hipMalloc for the binning failed");
+        }
+        float* dX = reinterpret_cast<float*>(reg.p);
+        uint32_t* keys = reinterpret_cast<uint32_t*>(reg.p + bx);
+        uint8_t* bins = reinterpret_cast<uint8_t*>(reg.p + bx + bk);
+        uint32_t* flags = reinterpret_cast<uint32_t*>(reg.p + ((bx + bk + bb + 3) & ~size_t(3)));
+        hipStream_t st = nullptr;
+        HIPC(hipMemcpyAsync(dX, X, bx, hipMemcpyHostToDevice, st));
+        launch_fill_u32(flags, 1, 0u, st);
+        launch_validate_reg(dX, (size_t)n * p, dX, 0, flags, st);  // X finite
+        uint32_t f = 0;
+        HIPC(hipMemcpyAsync(&f, flags, 4, hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+        if (f) throw Error(BORUTA_E_NONFINITE, "X holds NaN or Inf");
+        launch_binning(dX, n, p, n_bins, bins, n_pad, keys, P, st);
+        HIPC(hipMemcpy2DAsync(bins_out, (size_t)n, bins, (size_t)n_pad, (size_t)n, (size_t)p,
+                              hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+        return BORUTA_OK;
+    } catch (const Error& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return BORUTA_E_DEVICE;
+    }
+}
+
 int boruta_probe_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
     g_err.clear();
     if (!dst || !src || bytes % 16) {

@@ -187,6 +187,29 @@ def test_allocation_failure_returns_oom_and_leaks_nothing(monkeypatch):
     assert np.array_equal(again["imp_history"], want["imp_history"], equal_nan=True)
 
 
+@pytest.mark.parametrize("n,n_bins", [(1, 2), (300, 16), (1000, 256), (70000, 256)],
+                         ids=["n1", "n300_b16", "n1000", "n70000"])
+def test_device_binning_equals_oracle_bins(n, n_bins):
+    # the binning step alone: every byte against the oracle's bins (ragged n,
+    # several sort tiles at n = 70000, ties, categorical codes, a constant
+    # column, signed zeros, heavy tails)
+    rng = np.random.default_rng(n)
+    X = rng.standard_normal((n, 7)).astype(np.float32)
+    X[:, 1] = rng.integers(0, 5, n)
+    X[:, 2] = 1.5
+    X[:, 3] = np.where(rng.random(n) < 0.5, -0.0, 0.0)
+    X[:, 4] = np.round(X[:, 4], 1)
+    X[:, 5] = np.exp(3 * X[:, 5])
+    print(f"binning n={n} p=7 bins={n_bins}", flush=True)
+    got = B.boruta_bin(X, n_bins)
+    want, _, _ = O.bin_matrix(X, n_bins)
+    assert np.array_equal(got, want)
+    X[n // 2, 6] = np.nan
+    with pytest.raises(B.BorutaError) as e:
+        B.boruta_bin(X, n_bins)
+    assert e.value.code == B.BORUTA_E_NONFINITE
+
+
 def test_device_entry_point_matches_host_entry_point():
     import torch
     X, y = problem(23, 1000, 12, 2)
