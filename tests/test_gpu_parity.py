@@ -448,6 +448,15 @@ def test_percentile_shadow_threshold_matches_oracle(mode, perc):
     assert (g["hits"] > 0).any()
 
 
+@pytest.mark.parametrize("perc", [1, 37, 99])
+def test_percentile_threshold_over_many_shadows(perc):
+    # ~600 shadow columns (several candidates per radix digit) and Permut's
+    # signed importances (negative keys)
+    X, y = problem(62, 400, 600, 2)
+    g, o = both(X, y, 2, 6, 6, importance_mode=B.PERMUT, max_iter=2, seed=32, perc=perc)
+    assert_same_run(g, o)
+
+
 def test_rough_fix_matches_oracle_and_leaves_the_session_state():
     # tentative features resolved by the rough fix in the reported decision
     # and rank (batch of two modes; multi-seed aggregate); a session read
