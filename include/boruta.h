@@ -301,6 +301,15 @@ int boruta_fit_seeds(const float* X, const int32_t* y, int64_t n, int64_t p, int
                      const boruta_options* opt, double* median_importance_out,
                      int8_t* decision_out, boruta_result* results);
 
+/* boruta_fit_seeds for a regression problem (float targets y, as in
+ * boruta_fit_regression). */
+int boruta_fit_seeds_regression(const float* X, const float* y, int64_t n, int64_t p,
+                                int32_t n_trees, int32_t max_depth, int32_t mtry,
+                                int32_t importance_mode, int32_t max_iter, double alpha,
+                                const uint64_t* seeds, int32_t n_seeds,
+                                const boruta_options* opt, double* median_importance_out,
+                                int8_t* decision_out, boruta_result* results);
+
 /* Device bytes a call with these jobs needs (for boruta_fit_device). */
 int boruta_workspace_size(const boruta_job* jobs, int32_t n_jobs, const boruta_options* opt,
                           size_t* bytes);

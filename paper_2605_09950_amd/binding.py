@@ -87,7 +87,7 @@ class Result(ctypes.Structure):
 
 
 EXPORTS = ["boruta_default_options", "boruta_fit", "boruta_fit_ex", "boruta_fit_batch",
-           "boruta_fit_seeds", "boruta_fit_regression",
+           "boruta_fit_seeds", "boruta_fit_seeds_regression", "boruta_fit_regression",
            "boruta_workspace_size", "boruta_fit_device", "boruta_session_create",
            "boruta_session_step", "boruta_session_run", "boruta_session_result",
            "boruta_session_resume", "boruta_bin",
@@ -131,6 +131,10 @@ def lib():
                                        i32, ctypes.POINTER(Options), P, P,
                                        ctypes.POINTER(Result)]
         L.boruta_fit_seeds.restype = ctypes.c_int
+        L.boruta_fit_seeds_regression.argtypes = [P, P, i64, i64, i32, i32, i32, i32, i32, f64,
+                                                  P, i32, ctypes.POINTER(Options), P, P,
+                                                  ctypes.POINTER(Result)]
+        L.boruta_fit_seeds_regression.restype = ctypes.c_int
         L.boruta_workspace_size.argtypes = [ctypes.POINTER(Job), i32, ctypes.POINTER(Options),
                                             ctypes.POINTER(ctypes.c_size_t)]
         L.boruta_workspace_size.restype = ctypes.c_int
@@ -362,9 +366,11 @@ def boruta_fit_seeds(X, y, n_classes, n_trees, max_depth, seeds, mtry=0,
                      rough_fix=False):
     """One problem run once per seed (as one batch) and the multi-seed aggregate:
     returns {"median_importance", "decision", "runs"} where runs (if asked for)
-    holds each seed's own results as boruta_fit_batch does."""
+    holds each seed's own results as boruta_fit_batch does.  n_classes=None:
+    a regression problem with float targets y."""
     X = np.ascontiguousarray(X, dtype=np.float32)
-    y = np.ascontiguousarray(y, dtype=np.int32)
+    regression = n_classes is None
+    y = np.ascontiguousarray(y, dtype=np.float32 if regression else np.int32)
     n, p = X.shape
     sd = np.ascontiguousarray(seeds, dtype=np.uint64)
     med = np.zeros(p, np.float64)
@@ -385,9 +391,15 @@ def boruta_fit_seeds(X, y, n_classes, n_trees, max_depth, seeds, mtry=0,
             outs.append(o)
     opt, _ = make_options(n_bins, n_perm, split_rank, form, tune=tune, perc=perc,
                           rough_fix=rough_fix)
-    rc = lib().boruta_fit_seeds(_ptr(X), _ptr(y), n, p, n_classes, n_trees, max_depth, mtry,
-                                importance_mode, max_iter, alpha, _ptr(sd), len(sd),
-                                ctypes.byref(opt), _ptr(med), _ptr(dec), res)
+    if regression:
+        rc = lib().boruta_fit_seeds_regression(_ptr(X), _ptr(y), n, p, n_trees, max_depth, mtry,
+                                               importance_mode, max_iter, alpha, _ptr(sd),
+                                               len(sd), ctypes.byref(opt), _ptr(med), _ptr(dec),
+                                               res)
+    else:
+        rc = lib().boruta_fit_seeds(_ptr(X), _ptr(y), n, p, n_classes, n_trees, max_depth, mtry,
+                                    importance_mode, max_iter, alpha, _ptr(sd), len(sd),
+                                    ctypes.byref(opt), _ptr(med), _ptr(dec), res)
     for i, o in enumerate(outs):
         o["n_iter"], o["status"] = res[i].n_iter, res[i].status
     _check(rc)

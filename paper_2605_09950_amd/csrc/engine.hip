@@ -1259,6 +1259,72 @@ int finish_single(int rc, const std::vector<Out>& outs, int32_t* n_iter_out) {
     return rc;
 }
 
+
+// The repeated-seed protocol: one problem (classification labels y, or
+// regression targets y_reg) run once per seed as one batch, then the median
+// aggregate on the device.
+int fit_seeds(const float* X, const int32_t* y, const float* y_reg, int64_t n, int64_t p,
+              int32_t n_classes, int32_t n_trees, int32_t max_depth, int32_t mtry,
+              int32_t importance_mode, int32_t max_iter, double alpha, const uint64_t* seeds,
+              int32_t n_seeds, const boruta_options* opt, double* median_importance_out,
+              int8_t* decision_out, boruta_result* results) {
+    g_err.clear();
+    if (!seeds || n_seeds < 1 || n_seeds > 64 || !median_importance_out || !decision_out) {
+        g_err = "seeds (1..64 of them), median_importance_out and decision_out are required";
+        return BORUTA_E_INVALID_ARG;
+    }
+    if (p < 1) {
+        g_err = "p must be positive";
+        return BORUTA_E_INVALID_ARG;
+    }
+    std::vector<Spec> specs;
+    for (int i = 0; i < n_seeds; ++i) {
+        specs.push_back(spec_from(X, y, n, p, n_classes, n_trees, max_depth, mtry,
+                                  importance_mode, max_iter, alpha, seeds[i]));
+        specs.back().yr = y_reg;
+    }
+    // per-run outputs: the caller's, or a decision scratch (the aggregate reads
+    // the histories on the device)
+    std::vector<std::vector<int8_t>> dec_s((size_t)n_seeds);
+    std::vector<Out> outs(n_seeds);
+    for (int i = 0; i < n_seeds; ++i) {
+        if (results && results[i].decision && results[i].imp_history) {
+            outs[i].decision = results[i].decision;
+            outs[i].hist = results[i].imp_history;
+            outs[i].hits = results[i].hits;
+            outs[i].smax = results[i].shadow_max;
+            outs[i].rank = results[i].rank;
+        } else {
+            dec_s[i].resize((size_t)p);
+            outs[i].decision = dec_s[i].data();
+            outs[i].hist = nullptr;
+        }
+    }
+    std::vector<int> status(n_seeds, BORUTA_OK);
+    try {
+        std::unique_ptr<Context> c = prepare(specs, opt, false, nullptr, 0, nullptr);
+        c->eng->run(outs, status);
+        if (results)
+            for (int i = 0; i < n_seeds; ++i) {
+                results[i].n_iter = outs[i].n_iter;
+                results[i].status = status[i];
+            }
+        for (int s2 : status)
+            if (s2 != BORUTA_OK) {
+                g_err = "the problem failed validation";
+                return s2;
+            }
+        c->eng->seed_median(p, median_importance_out, decision_out);
+        HIPC(hipStreamSynchronize(c->st));
+        return BORUTA_OK;
+    } catch (const Error& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return BORUTA_E_DEVICE;
+    }
+}
 }  // namespace
 }  // namespace boruta
 
@@ -1332,65 +1398,25 @@ int boruta_fit_regression(const float* X, const float* y, int64_t n, int64_t p, 
     return finish_single(rc, outs, n_iter_out);
 }
 
+
 int boruta_fit_seeds(const float* X, const int32_t* y, int64_t n, int64_t p, int32_t n_classes,
                      int32_t n_trees, int32_t max_depth, int32_t mtry, int32_t importance_mode,
                      int32_t max_iter, double alpha, const uint64_t* seeds, int32_t n_seeds,
                      const boruta_options* opt, double* median_importance_out,
                      int8_t* decision_out, boruta_result* results) {
-    g_err.clear();
-    if (!seeds || n_seeds < 1 || n_seeds > 64 || !median_importance_out || !decision_out) {
-        g_err = "seeds (1..64 of them), median_importance_out and decision_out are required";
-        return BORUTA_E_INVALID_ARG;
-    }
-    if (p < 1) {
-        g_err = "p must be positive";
-        return BORUTA_E_INVALID_ARG;
-    }
-    std::vector<Spec> specs;
-    for (int i = 0; i < n_seeds; ++i)
-        specs.push_back(spec_from(X, y, n, p, n_classes, n_trees, max_depth, mtry,
-                                  importance_mode, max_iter, alpha, seeds[i]));
-    // per-run outputs: the caller's, or a decision scratch (the aggregate reads
-    // the histories on the device)
-    std::vector<std::vector<int8_t>> dec_s((size_t)n_seeds);
-    std::vector<Out> outs(n_seeds);
-    for (int i = 0; i < n_seeds; ++i) {
-        if (results && results[i].decision && results[i].imp_history) {
-            outs[i].decision = results[i].decision;
-            outs[i].hist = results[i].imp_history;
-            outs[i].hits = results[i].hits;
-            outs[i].smax = results[i].shadow_max;
-            outs[i].rank = results[i].rank;
-        } else {
-            dec_s[i].resize((size_t)p);
-            outs[i].decision = dec_s[i].data();
-            outs[i].hist = nullptr;
-        }
-    }
-    std::vector<int> status(n_seeds, BORUTA_OK);
-    try {
-        std::unique_ptr<Context> c = prepare(specs, opt, false, nullptr, 0, nullptr);
-        c->eng->run(outs, status);
-        if (results)
-            for (int i = 0; i < n_seeds; ++i) {
-                results[i].n_iter = outs[i].n_iter;
-                results[i].status = status[i];
-            }
-        for (int s2 : status)
-            if (s2 != BORUTA_OK) {
-                g_err = "the problem failed validation";
-                return s2;
-            }
-        c->eng->seed_median(p, median_importance_out, decision_out);
-        HIPC(hipStreamSynchronize(c->st));
-        return BORUTA_OK;
-    } catch (const Error& e) {
-        g_err = e.what();
-        return e.code;
-    } catch (const std::exception& e) {
-        g_err = e.what();
-        return BORUTA_E_DEVICE;
-    }
+    return fit_seeds(X, y, nullptr, n, p, n_classes, n_trees, max_depth, mtry, importance_mode,
+                     max_iter, alpha, seeds, n_seeds, opt, median_importance_out, decision_out,
+                     results);
+}
+
+int boruta_fit_seeds_regression(const float* X, const float* y, int64_t n, int64_t p,
+                                int32_t n_trees, int32_t max_depth, int32_t mtry,
+                                int32_t importance_mode, int32_t max_iter, double alpha,
+                                const uint64_t* seeds, int32_t n_seeds,
+                                const boruta_options* opt, double* median_importance_out,
+                                int8_t* decision_out, boruta_result* results) {
+    return fit_seeds(X, nullptr, y, n, p, 2, n_trees, max_depth, mtry, importance_mode, max_iter,
+                     alpha, seeds, n_seeds, opt, median_importance_out, decision_out, results);
 }
 
 int boruta_fit(const float* X, const int32_t* y, int64_t n, int64_t p, int32_t n_classes,

@@ -163,3 +163,17 @@ def test_regression_plain_per_node_form_matches_oracle():
     g = B.boruta_fit_regression(X, y, 4, 6, max_iter=3, seed=21, form=B.FORM_PLAIN, trace=True)
     o = O.boruta_fit_reg(X, y, 4, 6, max_iter=3, seed=21, trace=True)
     assert_same_run(g, o)
+
+
+def test_regression_multi_seed_median_matches_oracle():
+    # the paper's repeated-seed protocol on a regression problem
+    X, y = problem(53, 600, 8)
+    seeds = [4, 9, 13]
+    g = B.boruta_fit_seeds(X, y, None, 6, 8, seeds, importance_mode=B.PERMUT, max_iter=6)
+    runs = [O.boruta_fit_reg(X, y, 6, 8, importance_mode=1, max_iter=6, seed=s) for s in seeds]
+    for r, o in zip(g["runs"], runs):
+        assert r["n_iter"] == o["n_iter"]
+        assert np.array_equal(r["decision"], o["decision"])
+    med, dec = O.seed_median(runs)
+    assert np.array_equal(g["median_importance"], med)
+    assert np.array_equal(g["decision"], dec)
