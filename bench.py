@@ -296,11 +296,19 @@ def cpu_baseline(name, jobs, pr):
         r = O.boruta_fit_reg(jd["X"], jd["y_reg"], jd["n_trees"], jd["max_depth"], max_iter=it,
                              seed=jd["seed"], n_bins=pr["n_bins"], n_threads=cores)
         spent = time.perf_counter() - t0 - t_bin
+        # one core: iteration 1 on one thread
+        t0 = time.perf_counter()
+        O.boruta_fit_reg(jd["X"], jd["y_reg"], jd["n_trees"], jd["max_depth"], max_iter=1,
+                         seed=jd["seed"], n_bins=pr["n_bins"], n_threads=1)
+        one = max(1e-3, time.perf_counter() - t0 - t_bin)
         return {"value": round(r["n_iter"] / spent, 5), "unit": "iters/s", "cores": cores,
                 "kind": "oracle",
                 "sample": f"iterations 1..{r['n_iter']} in sequence (all {jd['n_trees']} "
                           f"trees each) on {cores} threads: {spent:.2f}s; the binning "
-                          f"({t_bin:.2f}s) is left out"}
+                          f"({t_bin:.2f}s) is left out",
+                "one_core": {"value": round(1.0 / one, 5), "unit": "iters/s",
+                             "sample": f"iteration 1 (all {jd['n_trees']} trees) on one "
+                                       f"thread in {one:.2f}s"}}
     if name in ("omics", "scale"):
         jd = jobs[0]
         p = jd["X"].shape[1]
