@@ -3,20 +3,31 @@ algorithmic bandwidth against the HBM roofline and the CPU oracle beside it.
 
 A step is one Boruta iteration (shadow widening, bootstrap, random forest,
 importance, hits, decision) of every live job of the workload.  The default
-workload is the MADELON-like one: n=10,000 rows, p=500 float32 features (20
-informative, 80 noisy mixes, 400 noise), 3 classes, 256 quantile bins, 200
-trees of depth 12, mtry = floor(sqrt(p_w)).  Inputs are resident in device
-memory (torch tensors) before the timed region; binning happens once per
-job, at session creation, outside it.
+workload is the mixed-type one, the largest that one GPU holds: n=100,000
+rows, p=2,000 float32 features (45% N(0,1), 45% U(0,1), 10% categorical
+codes; 40 informative), 4 classes from a random depth-6 tree, 256 quantile
+bins, 300 trees of depth 16, mtry = floor(sqrt(p_w)), TreeImp; its widened
+bin matrix (400 MB) exceeds the 256 MB last-level cache.  Inputs are resident
+in device memory (torch tensors) before the timed region; binning happens
+once per job, at session creation, outside it.
+
+Besides the timed batched/FP32-ranked leg the line carries: an event-timed
+eager leg (per-kernel durations, algorithmic bytes: the roofline), the
+library's streaming-copy bandwidth (the attainable figure), the exact-only
+ranking and the plain per-node form (both checked equal to the FP32 leg), the
+other importance mode, Algorithm 3's divergence mode, the MADELON-like
+workload's rate, roofline and whole-run time, and the CPU oracle.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload madelon|planted|omics|manyjob|scale|regression]
+                    [--workload scale|madelon|planted|omics|manyjob|regression]
 """
 import argparse
 import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -35,9 +46,15 @@ def parse():
                          "prediction divergence")
     ap.add_argument("--workload", choices=["madelon", "planted", "omics", "manyjob", "scale",
                                            "regression"],
-                    default="madelon")
+                    default="scale")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the other-mode / exact / plain comparison legs")
+    ap.add_argument("--no-madelon", action="store_true",
+                    help="skip the MADELON-like legs reported beside another workload")
+    ap.add_argument("--profile-leg", action="store_true",
+                    help="run only the event-timed leg (no warmup) and print its per-kernel "
+                         "launches and algorithmic bytes: the command that hardware counters "
+                         "are collected over")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--set", default="", metavar="KEY=V,...",
                     help="launch tuning values (boruta_options fields), instead of the autotuner")
@@ -167,9 +184,10 @@ def run_gpu(jobs, pr, steps, warmup, form, rank, stats, graph=True, tune=None):
             done += 1
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-    decisions = [sess.result(j)["decision"] for j in range(len(jobs))]
+    results = [sess.result(j) for j in range(len(jobs))]
     out = dict(steps=done, job_iters=job_iters, seconds=el, stats=sess.stats,
-               decisions=decisions, setup_s=t_setup, upload_s=t_up)
+               decisions=[r["decision"] for r in results], results=results, setup_s=t_setup,
+               upload_s=t_up)
     sess.close()
     return out
 
@@ -200,11 +218,12 @@ def roofline(stats):
         for f in KERNELS}
 
 
-def measured_traffic(workload_name, kernel):
-    """HBM-side traffic per launch of the histogram kernel (bytes), from the
-    calibrated FETCH_SIZE + WRITE_SIZE counter summary committed under
-    profiles/, or None when there is none for this workload or the kernel
-    source has changed since the counters were taken."""
+def counter_summary(workload_name, kernel):
+    """The machine-read fields of the calibrated FETCH_SIZE + WRITE_SIZE
+    counter summary committed under profiles/ for this kernel and workload:
+    traffic per launch (bytes) and the algorithmic bytes per launch of the
+    same launches; None when there is none, or when the kernel source has
+    changed since the counters were taken."""
     if kernel not in KERNEL_NAMES:
         return None
     path = os.path.join(ROOT, "profiles", f"{KERNEL_NAMES[kernel]}_{workload_name}_traffic.md")
@@ -214,13 +233,46 @@ def measured_traffic(workload_name, kernel):
     with open(path) as f:
         for line in f:
             if ":" in line and line.strip().startswith(("traffic_bytes_per_launch",
-                                                        "kernel_code_sha256")):
+                                                        "kernel_code_sha256",
+                                                        "alg_bytes_per_launch")):
                 k, v = line.strip().split(":", 1)
                 fields[k.strip()] = v.strip()
     if fields.get("kernel_code_sha256") != kernel_code_digest() or \
             "traffic_bytes_per_launch" not in fields:
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    out = {"traffic": float(fields["traffic_bytes_per_launch"])}
+    if "alg_bytes_per_launch" in fields:
+        out["alg"] = float(fields["alg_bytes_per_launch"])
+    return out
+
+
+def measured_traffic(workload_name, kernel):
+    """HBM-side traffic per launch of the histogram kernel (bytes), or None
+    (see counter_summary)."""
+    c = counter_summary(workload_name, kernel)
+    return None if c is None else c["traffic"]
+
+
+def copy_bandwidth(nbytes=1 << 30, launches=10):
+    """Attainable HBM bandwidth: the library's streaming copy kernel over
+    nbytes (read once, written once) timed with HIP events on the launching
+    stream; GB/s of read + write bytes."""
+    import torch
+    from paper_2605_09950_amd import binding as B
+    src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    st = torch.cuda.current_stream()
+    B.boruta_probe_copy(dst, src, nbytes, stream=st)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(launches):
+        B.boruta_probe_copy(dst, src, nbytes, stream=st)
+    b.record(st)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / launches
+    del src, dst
+    return {"GB_per_s": round(2 * nbytes / (ms * 1e-3) / 1e9, 1), "bytes": nbytes,
+            "launches": launches, "avg_launch_ms": round(ms, 4)}
 
 
 def kernel_code_digest():
@@ -341,6 +393,50 @@ def cpu_baseline(name, jobs, pr):
                       f"per job) in {spent:.2f}s; binning left out"}
 
 
+def same_results(a, b, iters):
+    """Equal decisions, hits, and history and shadow maxima of the first
+    `iters` iterations, job by job (the history holds the exact integer
+    importances divided once in IEEE double, so equal rows mean equal
+    integers)."""
+    for ra, rb in zip(a["results"], b["results"]):
+        k = min(iters, ra["n_iter"], rb["n_iter"])
+        ha, hb = ra["imp_history"][:k], rb["imp_history"][:k]
+        if not (np.array_equal(np.isnan(ha), np.isnan(hb)) and
+                np.array_equal(ha[~np.isnan(ha)], hb[~np.isnan(hb)]) and
+                np.array_equal(ra["shadow_max"][:k], rb["shadow_max"][:k])):
+            return False
+        if ra["n_iter"] == rb["n_iter"] and not (
+                np.array_equal(ra["decision"], rb["decision"]) and
+                np.array_equal(ra["hits"], rb["hits"])):
+            return False
+    return True
+
+
+def rate(leg):
+    return round(leg["job_iters"] / leg["seconds"], 4) if leg["seconds"] > 0 else None
+
+
+def roofline_legs(jobs, pr, steps, warmup, tune, workload_name):
+    """The timed graph leg and the event-timed eager leg of one workload;
+    returns (main leg, event leg, roofline dict, per-kernel figures)."""
+    from paper_2605_09950_amd import binding as B
+    main_leg = run_gpu(jobs, pr, steps, warmup, B.FORM_BATCHED, B.RANK_FP32, stats=False,
+                       graph=True, tune=tune)
+    ev_leg = run_gpu(jobs, pr, steps, warmup, B.FORM_BATCHED, B.RANK_FP32, stats=True,
+                     graph=False, tune=tune)
+    assert ev_leg["job_iters"] == main_leg["job_iters"]
+    assert same_results(ev_leg, main_leg, warmup + steps), "event leg differs from graph leg"
+    roof, kernels = roofline(ev_leg["stats"])
+    if roof is not None:
+        c = counter_summary(workload_name, roof["kernel"])
+        roof["traffic"] = None if c is None else c["traffic"]
+        if c is not None and c.get("alg"):
+            # waste ratio of the profiled launches (traffic and algorithmic
+            # bytes of the same iterations)
+            roof["traffic_over_alg"] = round(c["traffic"] / c["alg"], 3)
+    return main_leg, ev_leg, roof, kernels
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -361,6 +457,7 @@ def main():
                                      "kl": B.PERMUT_KL}[args.mode]
     mode = jobs[0]["importance_mode"]
     unit = "job-iters/s" if len(jobs) > 1 else "iters/s"
+    ukey = unit.replace("/", "_per_")
     tune, tune_s, tune_report = None, 0.0, {}
     if args.set:
         tune = {k: int(v) for k, v in (kv.split("=") for kv in args.set.split(","))}
@@ -369,19 +466,28 @@ def main():
         t0 = time.perf_counter()
         tune = autotune(jobs, n_bins=pr["n_bins"], n_perm=pr["n_perm"], report=tune_report)
         tune_s = time.perf_counter() - t0
-    # timed region: iterations replayed from the captured HIP graph
-    main_leg = run_gpu(jobs, pr, args.steps, args.warmup, B.FORM_BATCHED, B.RANK_FP32,
-                       stats=False, graph=True, tune=tune)
+    if args.profile_leg:
+        # the counters' command: exactly the event leg's launches, no warmup
+        leg = run_gpu(jobs, pr, args.steps, 0, B.FORM_BATCHED, B.RANK_FP32, stats=True,
+                      graph=False, tune=tune)
+        st = leg["stats"]
+        print(json.dumps({"profile_leg": args.workload, "steps": leg["steps"], "tune": tune,
+                          "kernels": {f: {"launches": int(getattr(st, f).launches),
+                                          "alg_bytes_per_launch":
+                                              getattr(st, f).alg_bytes /
+                                              max(1, getattr(st, f).launches)}
+                                      for f in KERNELS}}), flush=True)
+        return
+    # timed region: iterations replayed from the captured HIP graph; then the
+    # same iterations launched eagerly with HIP events around every forest
+    # kernel (per-kernel durations and algorithmic bytes)
+    main_leg, ev_leg, roof, kernels = roofline_legs(jobs, pr, args.steps, args.warmup, tune,
+                                                    args.workload)
     value = main_leg["job_iters"] / main_leg["seconds"]
-    # the same iterations launched eagerly with HIP events around every
-    # forest kernel: per-kernel durations and algorithmic bytes
-    ev_leg = run_gpu(jobs, pr, args.steps, args.warmup, B.FORM_BATCHED, B.RANK_FP32,
-                     stats=True, graph=False, tune=tune)
-    assert ev_leg["job_iters"] == main_leg["job_iters"]
-    assert all((a == b).all() for a, b in zip(ev_leg["decisions"], main_leg["decisions"]))
-    roof, kernels = roofline(ev_leg["stats"])
+    copy = copy_bandwidth()
     if roof is not None:
-        roof["traffic"] = measured_traffic(args.workload, roof["kernel"])
+        roof["attainable_GBs"] = copy["GB_per_s"]
+        roof["frac_of_attainable"] = round(roof["achieved"] / copy["GB_per_s"], 4)
     st = ev_leg["stats"]
     n_steps = max(1, ev_leg["steps"])
     extra = {"kernels": kernels, "timed_iterations": f"{args.warmup + 1}.."
@@ -390,11 +496,11 @@ def main():
              # per run, before the iterations: validation, labels, binning
              "setup_ms_binning": round(main_leg["setup_s"] * 1e3, 2),
              "upload_ms_pcie": round(main_leg["upload_s"] * 1e3, 2),
+             "copy_probe": copy,
              "tune": dict(tune or {}, **({"search_s": round(tune_s, 2),
                                           "sessions": tune_report.get("sessions", 0)}
                                          if tune is not None else {})),
-             "eager_" + unit.replace("/", "_per_"): round(ev_leg["job_iters"] /
-                                                         ev_leg["seconds"], 3),
+             "eager_" + ukey: round(ev_leg["job_iters"] / ev_leg["seconds"], 3),
              # Permut's out-of-bag walks: tree nodes visited per second of its kernel
              "permut_node_visits_per_s": (round(st.permut_visits / (st.permut.ms * 1e-3), 1)
                                           if st.permut.ms > 0 else None),
@@ -403,33 +509,33 @@ def main():
                            for d in range(max(j["max_depth"] for j in jobs))],
                  "large": [round(st.level_large[d] / n_steps, 1)
                            for d in range(max(j["max_depth"] for j in jobs))]}}
-    regression = any("y_reg" in jd for jd in jobs)
     if not args.no_compare:
-        k = max(1, min(5, args.steps))
-        if not regression:  # the regression forest has TreeImp only
-            other = [dict(jd, importance_mode=B.PERMUT if jd["importance_mode"] == B.TREEIMP
-                          else B.TREEIMP) for jd in jobs]
-            leg = run_gpu(other, pr, k, args.warmup, B.FORM_BATCHED, B.RANK_FP32,
-                          stats=False, tune=tune)
-            extra["other_mode_" + unit.replace("/", "_per_")] = round(
-                leg["job_iters"] / leg["seconds"], 3)
-        if mode != B.PERMUT_KL and not regression:
+        k, w = max(1, min(3, args.steps)), args.warmup
+        # the reference for the equality checks: the same iterations, FP32 ranking
+        ref = run_gpu(jobs, pr, k, w, B.FORM_BATCHED, B.RANK_FP32, stats=False, tune=tune)
+        leg = run_gpu(jobs, pr, k, w, B.FORM_BATCHED, B.RANK_EXACT, stats=False, tune=tune)
+        assert same_results(leg, ref, w + k), "exact-only ranking differs from FP32 ranking"
+        extra["exact_rank_" + ukey] = rate(leg)
+        extra["exact_rank_equal_to_fp32"] = f"iterations 1..{w + k}: identical"
+        # the plain per-node form: one launch per tree node, iteration 1
+        leg = run_gpu(jobs, pr, 1, 0, B.FORM_PLAIN, B.RANK_FP32, stats=False)
+        assert same_results(leg, ref, 1), "plain per-node form differs from the batched form"
+        extra["plain_form_" + ukey] = rate(leg)
+        extra["plain_form_note"] = ("iteration 1, one launch per tree node (histogram and "
+                                    "split/partition launches per large node), identical "
+                                    "to the batched form")
+        other = [dict(jd, importance_mode=B.PERMUT if jd["importance_mode"] == B.TREEIMP
+                      else B.TREEIMP) for jd in jobs]
+        leg = run_gpu(other, pr, k, w, B.FORM_BATCHED, B.RANK_FP32, stats=False, tune=tune)
+        extra["other_mode_" + ukey] = rate(leg)
+        extra["other_mode"] = ("Permut" if other[0]["importance_mode"] == B.PERMUT
+                               else "TreeImp") + f", R={pr['n_perm']}"
+        if mode != B.PERMUT_KL:
             kl = [dict(jd, importance_mode=B.PERMUT_KL) for jd in jobs]
-            leg = run_gpu(kl, pr, k, args.warmup, B.FORM_BATCHED, B.RANK_FP32, stats=False,
-                          tune=tune)
-            extra["permut_kl_" + unit.replace("/", "_per_")] = round(
-                leg["job_iters"] / leg["seconds"], 3)
-        leg = run_gpu(jobs, pr, k, args.warmup, B.FORM_BATCHED, B.RANK_EXACT, stats=False,
-                      tune=tune)
-        extra["exact_rank_" + unit.replace("/", "_per_")] = round(
-            leg["job_iters"] / leg["seconds"], 3)
-        if args.workload == "scale":
-            # one launch per node: about a million launches per iteration here
-            extra["plain_form_note"] = "not run on this workload (one launch per tree node)"
-        else:
-            leg = run_gpu(jobs, pr, 1, 1, B.FORM_PLAIN, B.RANK_FP32, stats=False)
-            extra["plain_form_" + unit.replace("/", "_per_")] = round(
-                leg["job_iters"] / leg["seconds"], 4)
+            leg = run_gpu(kl, pr, k, w, B.FORM_BATCHED, B.RANK_FP32, stats=False, tune=tune)
+            extra["permut_kl_" + ukey] = rate(leg)
+    if args.workload != "madelon" and not args.no_madelon:
+        extra["madelon"] = madelon_legs()
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": unit, "n_gpus": 1,
         "steps": main_leg["steps"], "warmup": args.warmup,
@@ -450,6 +556,39 @@ def main():
     elif not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, jobs, pr)
     print(json.dumps(line), flush=True)
+
+
+def madelon_legs():
+    """The MADELON-like workload beside the headline: its iteration rate and
+    roofline over iterations 3..22 (library defaults, no tuning), and one
+    whole run (iterations until every feature is decided or 100) timed on the
+    host clock, the quantity the paper's tables report per run."""
+    import torch
+    from paper_2605_09950_amd import binding as B
+    jobs, pr, desc, _ = workload("madelon")
+    main_leg, _, roof, _ = roofline_legs(jobs, pr, 20, 2, None, "madelon")
+    dev = [dict(jobs[0], X=torch.from_numpy(jobs[0]["X"]).cuda(),
+                y=torch.from_numpy(jobs[0]["y"]).cuda())]
+    shapes = [dict(n=dev[0]["X"].shape[0], p=dev[0]["X"].shape[1],
+                   **{k: v for k, v in dev[0].items() if k not in ("X", "y")})]
+    ws = torch.empty(B.boruta_workspace_size(shapes, n_bins=pr["n_bins"]), dtype=torch.uint8,
+                     device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with B.Session(dev, n_bins=pr["n_bins"], inputs_on_device=True, workspace=ws,
+                   stream=torch.cuda.current_stream()) as s:
+        t1 = time.perf_counter()
+        _, its = s.run(jobs[0]["max_iter"])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        r = s.result(0)
+    return {"workload": desc + ", TreeImp", "iters_per_s": round(rate(main_leg), 3),
+            "roofline": roof,
+            "whole_run": {"iterations": int(its), "seconds": round(t2 - t0, 4),
+                          "set_up_seconds": round(t1 - t0, 4),
+                          "confirmed": int((r["decision"] == 1).sum()),
+                          "rejected": int((r["decision"] == -1).sum()),
+                          "tentative": int((r["decision"] == 0).sum())}}
 
 
 if __name__ == "__main__":

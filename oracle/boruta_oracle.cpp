@@ -181,79 +181,296 @@ uint64_t gain_fixed(const Cand& c, uint64_t s, uint64_t n) {
     return (uint64_t)((num << 32) / den);
 }
 
-// Regression forest (the paper's regression experiments; reading): targets
-// quantised to integer levels y in [0, Q], Q = 255.  A node with bootstrap
-// weights w has W = sum w and T = sum w y; the split minimising the weighted
-// squared error of the children maximises  T_L^2/W_L + T_R^2/W_R,  which is
-// the same exact comparison as the Gini rule with (n, s) = (W, T^2).  Its
-// decrease  D = T_L^2/W_L + T_R^2/W_R - T^2/W  (the weighted squared-error
-// decrease in level units) is held in fixed point as floor(2^33 D / Q).
-constexpr int kLevels = 255;
-constexpr int64_t kRegMaxRows = 65536;  // keeps Q * (weighted rows) below 2^24
+// ---------------------------------------------------------------------------
+// Minimal unsigned big integer (little-endian 32-bit limbs): the exact
+// regression split comparison and the exact binomial test.
+struct Big {
+    std::vector<uint32_t> v;
+    explicit Big(uint64_t x = 0) {
+        while (x) {
+            v.push_back((uint32_t)x);
+            x >>= 32;
+        }
+    }
+    static Big of128(u128 x) {
+        Big b((uint64_t)(x >> 64));
+        b.shl(64);
+        b.add(Big((uint64_t)x));
+        return b;
+    }
+    void trim() {
+        while (!v.empty() && v.back() == 0) v.pop_back();
+    }
+    void add(const Big& o) {
+        if (o.v.size() > v.size()) v.resize(o.v.size(), 0);
+        uint64_t carry = 0;
+        for (size_t i = 0; i < v.size(); ++i) {
+            const uint64_t s = (uint64_t)v[i] + (i < o.v.size() ? o.v[i] : 0) + carry;
+            v[i] = (uint32_t)s;
+            carry = s >> 32;
+        }
+        if (carry) v.push_back((uint32_t)carry);
+    }
+    // this -= o, for o <= this
+    void sub(const Big& o) {
+        int64_t borrow = 0;
+        for (size_t i = 0; i < v.size(); ++i) {
+            int64_t d = (int64_t)v[i] - (i < o.v.size() ? (int64_t)o.v[i] : 0) - borrow;
+            borrow = d < 0 ? 1 : 0;
+            if (d < 0) d += (int64_t(1) << 32);
+            v[i] = (uint32_t)d;
+        }
+        trim();
+    }
+    void mul(uint32_t m) {
+        uint64_t carry = 0;
+        for (auto& x : v) {
+            const uint64_t pr = (uint64_t)x * m + carry;
+            x = (uint32_t)pr;
+            carry = pr >> 32;
+        }
+        if (carry) v.push_back((uint32_t)carry);
+        trim();
+    }
+    // this *= m for a 64-bit m: (this * hi) << 32 + this * lo
+    void mul64(uint64_t m) {
+        Big hi = *this;
+        hi.mul((uint32_t)(m >> 32));
+        hi.shl(32);
+        mul((uint32_t)m);
+        add(hi);
+        trim();
+    }
+    void div_exact(uint32_t m) {
+        uint64_t rem = 0;
+        for (size_t i = v.size(); i-- > 0;) {
+            const uint64_t cur = (rem << 32) | v[i];
+            v[i] = (uint32_t)(cur / m);
+            rem = cur % m;
+        }
+        trim();
+    }
+    void shl(int s) {
+        const int limbs = s / 32, bits = s % 32;
+        if (bits) {
+            uint32_t carry = 0;
+            for (auto& x : v) {
+                const uint32_t nx = (x << bits) | carry;
+                carry = x >> (32 - bits);
+                x = nx;
+            }
+            if (carry) v.push_back(carry);
+        }
+        v.insert(v.begin(), (size_t)limbs, 0u);
+        trim();
+    }
+    int bits() const {
+        if (v.empty()) return 0;
+        int b = 32 * (int)(v.size() - 1);
+        uint32_t top = v.back();
+        while (top) {
+            ++b;
+            top >>= 1;
+        }
+        return b;
+    }
+    bool bit(int i) const { return (size_t)(i / 32) < v.size() && ((v[i / 32] >> (i % 32)) & 1u); }
+    static int cmp(Big a, Big b) {
+        a.trim();
+        b.trim();
+        if (a.v.size() != b.v.size()) return a.v.size() < b.v.size() ? -1 : 1;
+        for (size_t i = a.v.size(); i-- > 0;)
+            if (a.v[i] != b.v[i]) return a.v[i] < b.v[i] ? -1 : 1;
+        return 0;
+    }
+    // floor(a / d), d > 0, by binary long division (bit by bit from the top)
+    static Big div(const Big& a, const Big& d) {
+        Big q, r;
+        for (int i = a.bits() - 1; i >= 0; --i) {
+            r.shl(1);
+            if (a.bit(i)) r.add(Big(1));
+            q.shl(1);
+            if (cmp(r, d) >= 0) {
+                r.sub(d);
+                q.add(Big(1));
+            }
+        }
+        return q;
+    }
+    uint64_t low64() const {
+        return (v.size() > 0 ? v[0] : 0) | ((uint64_t)(v.size() > 1 ? v[1] : 0) << 32);
+    }
+};
 
-uint64_t gain_fixed_reg(const Cand& c, uint64_t s, uint64_t n) {
-    const u128 num = ((u128)c.sl * c.nr + (u128)c.sr * c.nl) * n - (u128)s * c.nl * c.nr;
-    const u128 den = (u128)c.nl * c.nr * n * (u128)kLevels;
-    return (uint64_t)((num << 33) / den);
+// ---------------------------------------------------------------------------
+// Regression forest (reading of the paper's regression experiments, Sec. 3,
+// which run Boruta on a random-forest regressor with squared-error loss,
+// Sec. 2.2).
+//
+// Targets.  Each float32 target y is held exactly as the integer
+// y_fix = rint(y * 2^(38 - e)), with e the smallest integer such that every
+// |y| < 2^e (e = 0 for an all-zero target): a power-of-two scaling, exact for
+// every target with |y| >= 2^(e - 15) (the 15 binades below 2^e), and within
+// half a unit of 2^(e - 38) below that; |y_fix| < 2^38.
+//
+// Split rule.  A node with bootstrap weights w has W = sum w and
+// T = sum w y_fix; the split that minimises the children's weighted squared
+// error maximises Q = T_L^2/W_L + T_R^2/W_R (compared as exact rationals,
+// with big integers), ties as for classification, and splits only when the
+// decrease D = Q - T^2/W is strictly positive.  D equals
+// (T_L W - T W_L)^2 / (W_L W_R W).
+//
+// Fixed point.  With R = max y_fix - min y_fix and n rows, a tree's summed
+// decrease is at most n R^2 / 4; Algorithm 2 accumulates
+// floor(D / 2^s_gain), s_gain = max(0, bits(n) + 2 bits(R) - 64), so a
+// tree's sum stays below 2^62.  A leaf predicts floor(T / W).  The
+// permutation importance scores a row by floor((y_fix - pred)^2 / 2^s_perm),
+// s_perm = max(0, bits(n_trees n_perm n) + 2 bits(R + 1) - 63), so the summed
+// increases stay within 64 bits; Algorithm 3 scores a row by
+// floor(Dsum^2 / (n_trees^2 2^s_kl)), Dsum the change of the row's summed
+// leaf predictions, s_kl = max(0, bits(n) + 2 bits(R + 1) - 63).  The
+// reported importances are in squared target units.
+int bit_length(uint64_t v) {
+    int b = 0;
+    while (v) {
+        ++b;
+        v >>= 1;
+    }
+    return b;
 }
 
-// Target quantisation: y -> floor((y - min) Q / (max - min) + 1/2) in double,
-// 0 for a constant target.
-void quantize_target(const float* y, int64_t n, int32_t* out) {
-    double lo = y[0], hi = y[0];
+struct RegScale {
+    int e = 0;          // targets scaled by 2^(38 - e)
+    int64_t range = 0;  // max y_fix - min y_fix
+    int s_gain = 0, s_perm = 0, s_kl = 0;
+};
+
+void fix_targets(const float* y, int64_t n, int64_t* out, int* e_out) {
+    double m = 0.0;
+    for (int64_t i = 0; i < n; ++i) m = std::max(m, std::fabs((double)y[i]));
+    int e = 0;
+    if (m > 0.0) std::frexp(m, &e);  // m = f 2^e with f in [1/2, 1): m < 2^e
+    for (int64_t i = 0; i < n; ++i) out[i] = (int64_t)std::rint(std::ldexp((double)y[i], 38 - e));
+    *e_out = e;
+}
+
+RegScale reg_scale(const int64_t* yfix, int64_t n, int e, int n_trees, int n_perm) {
+    RegScale s;
+    s.e = e;
+    int64_t lo = yfix[0], hi = yfix[0];
     for (int64_t i = 1; i < n; ++i) {
-        lo = std::min(lo, (double)y[i]);
-        hi = std::max(hi, (double)y[i]);
+        lo = std::min(lo, yfix[i]);
+        hi = std::max(hi, yfix[i]);
     }
-    const double range = hi - lo;
-    for (int64_t i = 0; i < n; ++i) {
-        if (!(range > 0.0)) {
-            out[i] = 0;
-            continue;
-        }
-        const double v = ((double)y[i] - lo) * (double)kLevels / range;
-        out[i] = (int32_t)std::floor(v + 0.5);
-    }
+    s.range = hi - lo;
+    const int br = bit_length((uint64_t)s.range), br1 = bit_length((uint64_t)s.range + 1);
+    s.s_gain = std::max(0, bit_length((uint64_t)n) + 2 * br - 64);
+    s.s_perm = std::max(0, bit_length((uint64_t)n_trees * (uint64_t)n_perm * (uint64_t)n) +
+                               2 * br1 - 63);
+    s.s_kl = std::max(0, bit_length((uint64_t)n) + 2 * br1 - 63);
+    return s;
+}
+
+// Regression split candidate: left/right weights and weighted target sums.
+struct RegCand {
+    bool valid = false;
+    int q = -1, b = -1;
+    uint64_t wl = 0, wr = 0;
+    int64_t tl = 0, tr = 0;
+};
+
+Big sq_big(int64_t t) {
+    const uint64_t a = (uint64_t)(t < 0 ? -t : t);
+    return Big::of128((u128)a * a);
+}
+
+// Q_a > Q_b exactly: (TLa^2 WRa + TRa^2 WLa) WLb WRb > (TLb^2 WRb + TRb^2 WLb) WLa WRa.
+bool better_reg(const RegCand& a, const RegCand& b) {
+    Big lhs = sq_big(a.tl), t2 = sq_big(a.tr);
+    lhs.mul64(a.wr);
+    t2.mul64(a.wl);
+    lhs.add(t2);
+    lhs.mul64(b.wl);
+    lhs.mul64(b.wr);
+    Big rhs = sq_big(b.tl), u2 = sq_big(b.tr);
+    rhs.mul64(b.wr);
+    u2.mul64(b.wl);
+    rhs.add(u2);
+    rhs.mul64(a.wl);
+    rhs.mul64(a.wr);
+    return Big::cmp(lhs, rhs) > 0;
+}
+
+// |T_L W - T W_L|: the decrease is its square over W_L W_R W, positive iff it
+// is nonzero.
+u128 reg_gap(const RegCand& c) {
+    const __int128 W = (__int128)(c.wl + c.wr), T = (__int128)c.tl + c.tr;
+    const __int128 g = (__int128)c.tl * W - T * (__int128)c.wl;
+    return (u128)(g < 0 ? -g : g);
+}
+
+// floor(D / 2^s) = floor(gap^2 / (W_L W_R W 2^s)).
+uint64_t gain_fixed_reg(const RegCand& c, int s) {
+    const u128 g = reg_gap(c);
+    Big num = Big::of128(g), hi = Big::of128(g);  // g^2 = g lo + (g hi) 2^64
+    num.mul64((uint64_t)g);
+    hi.mul64((uint64_t)(g >> 64));
+    hi.shl(64);
+    num.add(hi);
+    Big den = Big::of128((u128)c.wl * c.wr);
+    den.mul64(c.wl + c.wr);
+    den.shl(s);
+    return Big::div(num, den).low64();
+}
+
+// floor(T / W) toward minus infinity.
+int64_t floor_div(int64_t t, uint64_t w) {
+    const int64_t q = t / (int64_t)w;
+    return (q * (int64_t)w != t && t < 0) ? q - 1 : q;
 }
 
 struct Data {
     int64_t n = 0;
     int64_t p_w = 0;
     std::vector<const uint8_t*> col;  // [p_w] column base pointers, each [n]
-    const int32_t* y = nullptr;  // class labels, or quantised targets (reg)
+    const int32_t* y = nullptr;  // class labels (classification)
     int K = 2;
     int B = 256;
     bool reg = false;
+    const int64_t* yfix = nullptr;  // regression: fixed-point targets
+    RegScale rs;                    // regression: scale and fixed-point shifts
 };
 
-// Regression form of best_split: per bin the weight W and the weighted target
-// sum T; candidates carry (nl, sl, nr, sr) = (W_L, T_L^2, W_R, T_R^2).
-Cand best_split_reg(const Data& d, const std::vector<uint32_t>& rows, const uint32_t* w,
-                    const std::vector<int32_t>& feats, uint64_t W, uint64_t T) {
-    std::vector<uint64_t> hw((size_t)d.B), ht((size_t)d.B);
-    Cand best;
+// Regression form of best_split: per bin the weight and the weighted target
+// sum; the first best in (draw position, threshold) order by the exact rule.
+RegCand best_split_reg(const Data& d, const std::vector<uint32_t>& rows, const uint32_t* w,
+                       const std::vector<int32_t>& feats, uint64_t W, int64_t T) {
+    std::vector<uint64_t> hw((size_t)d.B);
+    std::vector<int64_t> ht((size_t)d.B);
+    RegCand best;
     for (size_t q = 0; q < feats.size(); ++q) {
         const uint8_t* col = d.col[feats[q]];
         std::fill(hw.begin(), hw.end(), 0);
         std::fill(ht.begin(), ht.end(), 0);
         for (uint32_t i : rows) {
             hw[col[i]] += w[i];
-            ht[col[i]] += (uint64_t)w[i] * (uint64_t)d.y[i];
+            ht[col[i]] += (int64_t)w[i] * d.yfix[i];
         }
-        uint64_t lw = 0, lt = 0;
+        uint64_t lw = 0;
+        int64_t lt = 0;
         for (int b = 0; b + 1 < d.B; ++b) {
             lw += hw[(size_t)b];
             lt += ht[(size_t)b];
-            Cand c;
+            RegCand c;
             c.valid = true;
             c.q = (int)q;
             c.b = b;
-            c.nl = lw;
-            c.sl = lt * lt;
-            c.nr = W - lw;
-            c.sr = (T - lt) * (T - lt);
-            if (c.nl == 0 || c.nr == 0) continue;
-            if (!best.valid || better(c, best)) best = c;
+            c.wl = lw;
+            c.wr = W - lw;
+            c.tl = lt;
+            c.tr = T - lt;
+            if (c.wl == 0 || c.wr == 0) continue;
+            if (!best.valid || better_reg(c, best)) best = c;
         }
     }
     return best;
@@ -296,8 +513,9 @@ struct TNode {
     int depth = 0;
     int32_t feat = -1;  // -1: leaf
     int32_t thr = 0;
-    int32_t leaf_class = 0;
-    uint64_t n = 0;
+    int64_t leaf_class = 0;  // regression: the prediction floor(T / W)
+    uint64_t n = 0;          // weighted rows (regression: W)
+    int64_t tsum = 0;        // regression: T
     uint64_t gain = 0;  // floor(2^32 * Gini decrease), split nodes only
     int32_t left = -1, right = -1;
     std::vector<uint64_t> counts;  // weighted in-bag class counts
@@ -323,51 +541,65 @@ int32_t grow(TreeCtx& c, const std::vector<uint32_t>& rows, int depth, int64_t h
     c.nodes.emplace_back();
     std::vector<uint64_t> counts(d.K, 0);
     uint64_t n = 0, s = 0;
+    int64_t T = 0;
     if (d.reg) {
-        // (n, s) = (W, T^2); the node's reported weighted count is Q W and its
-        // "class" counts (Q W - T, T)
-        uint64_t W = 0, T = 0;
         for (uint32_t i : rows) {
-            W += c.w[i];
-            T += (uint64_t)c.w[i] * (uint64_t)d.y[i];
+            n += c.w[i];
+            T += (int64_t)c.w[i] * d.yfix[i];
         }
-        counts[0] = (uint64_t)kLevels * W - T;
-        counts[1] = T;
-        n = W;
-        s = T * T;
-        c.nodes[idx].n = (uint64_t)kLevels * W;
+        c.nodes[idx].tsum = T;
     } else {
         for (uint32_t i : rows) counts[d.y[i]] += c.w[i];
         for (uint64_t v : counts) {
             n += v;
             s += v * v;
         }
-        c.nodes[idx].n = n;
     }
+    c.nodes[idx].n = n;
     c.nodes[idx].heap = heap;
     c.nodes[idx].depth = depth;
     c.nodes[idx].counts = counts;
 
-    Cand best;
     std::vector<int32_t> feats;
-    if (depth < c.D) {
+    if (depth < c.D)
         for (int q = 0; q < c.mtry; ++q)
             feats.push_back((int32_t)keyed_perm(c.seed, kStreamMtry, c.t, c.tree, (uint32_t)heap,
                                                 0u, (uint64_t)d.p_w, (uint64_t)q));
-        best = d.reg ? best_split_reg(d, rows, c.w, feats, n, counts[1])
-                     : best_split(d, rows, c.w, feats, counts);
+    // the chosen split: feature, threshold, decrease in fixed point
+    bool split = false;
+    int32_t f = -1, thr = 0;
+    uint64_t gain = 0;
+    if (d.reg) {
+        RegCand best;
+        if (!feats.empty()) best = best_split_reg(d, rows, c.w, feats, n, T);
+        if (best.valid && reg_gap(best) != 0) {
+            split = true;
+            f = feats[best.q];
+            thr = best.b;
+            gain = gain_fixed_reg(best, d.rs.s_gain);
+        }
+    } else {
+        Cand best;
+        if (!feats.empty()) best = best_split(d, rows, c.w, feats, counts);
+        if (best.valid && positive_gain(best, s, n)) {
+            split = true;
+            f = feats[best.q];
+            thr = best.b;
+            gain = gain_fixed(best, s, n);
+        }
     }
-    if (best.valid && positive_gain(best, s, n)) {
-        const int32_t f = feats[best.q];
+    if (split) {
         std::vector<uint32_t> lrows, rrows;
-        for (uint32_t i : rows) (d.col[f][i] <= best.b ? lrows : rrows).push_back(i);
+        for (uint32_t i : rows) (d.col[f][i] <= thr ? lrows : rrows).push_back(i);
         c.nodes[idx].feat = f;
-        c.nodes[idx].thr = best.b;
-        c.nodes[idx].gain = d.reg ? gain_fixed_reg(best, s, n) : gain_fixed(best, s, n);
+        c.nodes[idx].thr = thr;
+        c.nodes[idx].gain = gain;
         const int32_t l = grow(c, lrows, depth + 1, 2 * heap);
         const int32_t r = grow(c, rrows, depth + 1, 2 * heap + 1);
         c.nodes[idx].left = l;
         c.nodes[idx].right = r;
+    } else if (d.reg) {
+        c.nodes[idx].leaf_class = floor_div(T, n);
     } else {
         int arg = 0;
         for (int k = 1; k < d.K; ++k)
@@ -401,17 +633,12 @@ int32_t predict_leaf(const std::vector<TNode>& nodes, const Data& d, uint32_t ro
     return i;
 }
 
-// Regression prediction of a leaf: its mean target level T/W in 1/256 level
-// units, floor(256 T / W) (with the node's counts (255 W - T, T)), and the
-// squared error of a row of level y against it, in 1/65536 level^2 units.
-int64_t leaf_level_fix(const TNode& nd) {
-    const uint64_t N = nd.counts[0] + nd.counts[1];  // 255 W
-    return (int64_t)((256ull * (uint64_t)kLevels * nd.counts[1]) / N);
-}
-
-int64_t sq_error_fix(const TNode& nd, int32_t y) {
-    const int64_t e = leaf_level_fix(nd) - 256 * (int64_t)y;
-    return e * e;
+// Regression: a row's squared error against its leaf's prediction, shifted
+// right by s_perm bits (floor).
+int64_t sq_error_fix(const TNode& leaf, int64_t yfix, int s_perm) {
+    const __int128 e = (__int128)yfix - leaf.leaf_class;
+    const u128 sq = (u128)(e * e);
+    return (int64_t)(sq >> s_perm);
 }
 
 struct TreeResult {
@@ -451,14 +678,14 @@ void run_tree(const Data& d, const IterParams& ip, uint32_t tree, TreeResult& ou
     // set; replica r of column f moves the bin of o_pi(j) into row o_j, with
     // pi the keyed bijection of [0, m) for (t, tree, f, r).
     // For a regression forest the score of a row is the negated squared error
-    // of its leaf's mean level (sq_error_fix), so the drop is the increase of
-    // the squared error.
+    // against its leaf's prediction (sq_error_fix, in 2^s_perm units), so the
+    // drop is the increase of the squared error.
     const uint64_t m = oob.size();
     std::vector<int64_t> base(m);
     for (uint64_t j = 0; j < m; ++j) {
         if (d.reg) {
             base[j] = -sq_error_fix(out.nodes[predict_leaf(out.nodes, d, oob[j], -1, 0)],
-                                    d.y[oob[j]]);
+                                    d.yfix[oob[j]], d.rs.s_perm);
         } else {
             base[j] = predict(out.nodes, d, oob[j], -1, 0) == d.y[oob[j]];
             out.oob_correct += base[j];
@@ -471,7 +698,7 @@ void run_tree(const Data& d, const IterParams& ip, uint32_t tree, TreeResult& ou
         const int sb = d.col[f][oob[src]];
         if (d.reg)
             return -sq_error_fix(out.nodes[predict_leaf(out.nodes, d, oob[j], f, sb)],
-                                 d.y[oob[j]]);
+                                 d.yfix[oob[j]], d.rs.s_perm);
         return (int64_t)(predict(out.nodes, d, oob[j], f, sb) == d.y[oob[j]]);
     };
     if (ip.naive) {
@@ -573,15 +800,15 @@ void forest_predict(const std::vector<std::vector<TNode>*>& forest, const Data& 
 // against those of the unpermuted matrix (Algorithm 3, one predict call
 // per column).
 // Regression form (reading): the forest's prediction of a row is the mean
-// over trees of its leaves' mean levels; with S the sum over trees of the
-// leaves' floor(256 T / W) and D = S(permuted) - S(unpermuted), a row's loss
-// is floor(D^2 / n_trees^2), the squared difference of the two mean
-// predictions in 1/65536 level^2 units.
-int64_t forest_level_sum(const std::vector<std::vector<TNode>*>& forest, const Data& d,
-                         uint32_t row, int32_t sub_f, int sub_b) {
+// over trees of its leaves' predictions; with S the sum over trees of the
+// leaves' floor(T / W) and Dsum = S(permuted) - S(unpermuted), a row's loss
+// is floor(Dsum^2 / (n_trees^2 2^s_kl)), the squared difference of the two
+// mean predictions in 2^s_kl units of squared fixed-point target units.
+int64_t forest_pred_sum(const std::vector<std::vector<TNode>*>& forest, const Data& d,
+                        uint32_t row, int32_t sub_f, int sub_b) {
     int64_t s = 0;
     for (const std::vector<TNode>* tree : forest)
-        s += leaf_level_fix((*tree)[leaf_of_row(*tree, d, row, sub_f, sub_b)]);
+        s += (*tree)[leaf_of_row(*tree, d, row, sub_f, sub_b)].leaf_class;
     return s;
 }
 
@@ -592,7 +819,7 @@ void forest_divergence(const std::vector<std::vector<TNode>*>& forest, const Dat
     std::vector<uint64_t> base((size_t)d.n * K);
     std::vector<uint32_t> pi((size_t)d.n);
     for (int64_t r = 0; r < d.n; ++r) {
-        forest_predict(forest, d, (uint32_t)r, -1, 0, &base[(size_t)r * K]);
+        if (!d.reg) forest_predict(forest, d, (uint32_t)r, -1, 0, &base[(size_t)r * K]);
         pi[r] = (uint32_t)keyed_perm(seed, kStreamFlush, t, 0u, 0u, 0u, (uint64_t)d.n, (uint64_t)r);
     }
     // the columns to score: all, or (checks at full size) the listed ones
@@ -611,11 +838,11 @@ void forest_divergence(const std::vector<std::vector<TNode>*>& forest, const Dat
                 for (int64_t r = 0; r < d.n; ++r) {
                     if (d.reg) {
                         const int64_t diff =
-                            forest_level_sum(forest, d, (uint32_t)r, (int32_t)f, d.col[f][pi[r]]) -
-                            forest_level_sum(forest, d, (uint32_t)r, -1, 0);
-                        const uint64_t a = (uint64_t)(diff < 0 ? -diff : diff);
-                        const uint64_t T = forest.size();
-                        acc += (int64_t)((a * a) / (T * T));
+                            forest_pred_sum(forest, d, (uint32_t)r, (int32_t)f, d.col[f][pi[r]]) -
+                            forest_pred_sum(forest, d, (uint32_t)r, -1, 0);
+                        const u128 a = (u128)(diff < 0 ? -diff : diff);
+                        const u128 T = forest.size();
+                        acc += (int64_t)((a * a / (T * T)) >> d.rs.s_kl);
                         continue;
                     }
                     forest_predict(forest, d, (uint32_t)r, (int32_t)f, d.col[f][pi[r]], q.data());
@@ -626,73 +853,6 @@ void forest_divergence(const std::vector<std::vector<TNode>*>& forest, const Dat
         });
     for (auto& th : pool) th.join();
 }
-
-// ---------------------------------------------------------------------------
-// Minimal unsigned big integer (little-endian 32-bit limbs) for the exact
-// binomial test.
-struct Big {
-    std::vector<uint32_t> v;
-    explicit Big(uint64_t x = 0) {
-        while (x) {
-            v.push_back((uint32_t)x);
-            x >>= 32;
-        }
-    }
-    void trim() {
-        while (!v.empty() && v.back() == 0) v.pop_back();
-    }
-    void add(const Big& o) {
-        if (o.v.size() > v.size()) v.resize(o.v.size(), 0);
-        uint64_t carry = 0;
-        for (size_t i = 0; i < v.size(); ++i) {
-            const uint64_t s = (uint64_t)v[i] + (i < o.v.size() ? o.v[i] : 0) + carry;
-            v[i] = (uint32_t)s;
-            carry = s >> 32;
-        }
-        if (carry) v.push_back((uint32_t)carry);
-    }
-    void mul(uint32_t m) {
-        uint64_t carry = 0;
-        for (auto& x : v) {
-            const uint64_t pr = (uint64_t)x * m + carry;
-            x = (uint32_t)pr;
-            carry = pr >> 32;
-        }
-        if (carry) v.push_back((uint32_t)carry);
-        trim();
-    }
-    void div_exact(uint32_t m) {
-        uint64_t rem = 0;
-        for (size_t i = v.size(); i-- > 0;) {
-            const uint64_t cur = (rem << 32) | v[i];
-            v[i] = (uint32_t)(cur / m);
-            rem = cur % m;
-        }
-        trim();
-    }
-    void shl(int s) {
-        const int limbs = s / 32, bits = s % 32;
-        if (bits) {
-            uint32_t carry = 0;
-            for (auto& x : v) {
-                const uint32_t nx = (x << bits) | carry;
-                carry = x >> (32 - bits);
-                x = nx;
-            }
-            if (carry) v.push_back(carry);
-        }
-        v.insert(v.begin(), (size_t)limbs, 0u);
-        trim();
-    }
-    static int cmp(Big a, Big b) {
-        a.trim();
-        b.trim();
-        if (a.v.size() != b.v.size()) return a.v.size() < b.v.size() ? -1 : 1;
-        for (size_t i = a.v.size(); i-- > 0;)
-            if (a.v[i] != b.v[i]) return a.v[i] < b.v[i] ? -1 : 1;
-        return 0;
-    }
-};
 
 // Reading of the unspecified test() of Algorithm 1: two one-sided exact
 // binomial tails with success probability 1/2 after t trials, Bonferroni
@@ -744,8 +904,10 @@ struct Run {
     bool naive;
     std::vector<int32_t> kl_cols;  // mode 2: score only these columns (empty: all)
     int perc = 100;                // hit threshold: percentile of the shadow importances
-    bool reg = false;              // regression forest (y holds quantised targets)
-    std::vector<int32_t> yq;       // regression: quantised targets
+    bool reg = false;              // regression forest
+    std::vector<int64_t> yfix;     // regression: fixed-point targets
+    std::vector<int32_t> yzero;    // regression: placeholder labels (all 0)
+    RegScale rs;
 };
 
 // Hit threshold of an iteration: the perc-th percentile of the m shadow
@@ -846,6 +1008,8 @@ void iteration(const Run& run, int t, int8_t* state, int32_t* hits,
     d.K = run.K;
     d.B = run.B;
     d.reg = run.reg;
+    d.yfix = run.yfix.data();
+    d.rs = run.rs;
     std::vector<int32_t> col_src(d.p_w);
     for (int c = 0; c < p_cur; ++c) {
         d.col.push_back(run.orig.data() + (size_t)active[c] * n);
@@ -878,6 +1042,7 @@ void iteration(const Run& run, int t, int8_t* state, int32_t* hits,
     std::vector<int64_t> imp(d.p_w, 0);
     if (full) {
         double denom = 0.0;
+        int scale_exp = 0;  // reported value = ldexp(v / denom, scale_exp)
         if (run.mode == 0) {
             // Algorithm 2: per-tree normalisation of the accumulated decreases
             // (a tree without any split contributes zeros), mean over trees,
@@ -902,8 +1067,9 @@ void iteration(const Run& run, int t, int8_t* state, int32_t* hits,
             forest_divergence(forest, d, run.seed, (uint32_t)t, run.n_threads, imp.data(),
                               run.kl_cols);
             // mean divergence per row in bits (regression: mean squared
-            // difference in level^2 units)
-            denom = (double)d.n * (run.reg ? 65536.0 : 4294967296.0);
+            // difference of the predictions in squared target units)
+            denom = (double)d.n * (run.reg ? 1.0 : 4294967296.0);
+            if (run.reg) scale_exp = run.rs.s_kl - 2 * (38 - run.rs.e);
         } else {
             int64_t oob_total = 0;
             for (const TreeResult& r : res) {
@@ -911,9 +1077,12 @@ void iteration(const Run& run, int t, int8_t* state, int32_t* hits,
                 for (int64_t f = 0; f < d.p_w; ++f) imp[f] += r.drop[f];
             }
             denom = (double)((int64_t)run.R * oob_total);
-            if (run.reg) denom *= 65536.0;  // squared errors in 1/65536 level^2 units
+            // regression: squared errors in squared target units
+            if (run.reg) scale_exp = run.rs.s_perm - 2 * (38 - run.rs.e);
         }
-        auto report = [&](int64_t v) { return denom > 0.0 ? (double)v / denom : 0.0; };
+        auto report = [&](int64_t v) {
+            return denom > 0.0 ? std::ldexp((double)v / denom, scale_exp) : 0.0;
+        };
         // Hit: strictly above the best shadow (Algorithm 1), or above the
         // shadows' perc-th percentile when that option is set.
         const int64_t best_shadow = shadow_threshold(&imp[p_cur], n_sha, run.perc);
@@ -1147,56 +1316,74 @@ int oracle_boruta_fit_reg(const float* X, const float* y, int64_t n, int64_t p,
                           int32_t* hits_out, double* shadow_max_out, int32_t* n_iter_out,
                           oracle_trace_fn trace, void* trace_user) {
     if (!decision_out || !imp_history_out || !n_iter_out || !y) return -1;
-    if (n < 2 || n > kRegMaxRows || importance_mode < 0 || importance_mode > 2) return -1;
-    // the summed squared-error drops stay below 2^63
-    if (importance_mode == 1 && (int64_t)n_trees * n * n_perm > (int64_t(1) << 31)) return -1;
+    if (n < 2 || importance_mode < 0 || importance_mode > 2) return -1;
     for (int64_t i = 0; i < n; ++i)
         if (!std::isfinite(y[i])) return -2;
     Run run;
     run.reg = true;
-    run.yq.resize((size_t)n);
-    quantize_target(y, n, run.yq.data());
-    const int rc = setup(run, X, run.yq.data(), n, p, 2, n_trees, max_depth, mtry,
+    run.yfix.resize((size_t)n);
+    int e = 0;
+    fix_targets(y, n, run.yfix.data(), &e);
+    run.yzero.assign((size_t)n, 0);
+    const int rc = setup(run, X, run.yzero.data(), n, p, 2, n_trees, max_depth, mtry,
                          importance_mode, max_iter, alpha, seed, n_bins, n_perm, n_threads,
-                         permut_naive, kLevels + 1);
+                         permut_naive);
     if (rc) return rc;
+    run.rs = reg_scale(run.yfix.data(), n, e, n_trees, n_perm);
     return fit_run(run, n_trees, max_iter, 0, decision_out, imp_history_out, hits_out,
                    shadow_max_out, n_iter_out, trace, trace_user);
 }
 
-void oracle_quantize_target(const float* y, int64_t n, int32_t* out) { quantize_target(y, n, out); }
+// The fixed-point targets and the scale exponent e (see fix_targets); shifts
+// out[0..3] = (s_gain, s_perm, s_kl, range) for n_trees trees and n_perm
+// replicas.
+int32_t oracle_fix_targets(const float* y, int64_t n, int32_t n_trees, int32_t n_perm,
+                           int64_t* yfix_out, int64_t* shifts_out) {
+    int e = 0;
+    fix_targets(y, n, yfix_out, &e);
+    const RegScale rs = reg_scale(yfix_out, n, e, n_trees, n_perm);
+    if (shifts_out) {
+        shifts_out[0] = rs.s_gain;
+        shifts_out[1] = rs.s_perm;
+        shifts_out[2] = rs.s_kl;
+        shifts_out[3] = rs.range;
+    }
+    return e;
+}
 
-int oracle_best_split_reg(const uint8_t* bins, int64_t n, const int32_t* yq, const uint32_t* w,
+// Best regression split of one node: out = (found, q, b, W_L, W_R, T_L, T_R,
+// floor(D / 2^s_gain)).
+int oracle_best_split_reg(const uint8_t* bins, int64_t n, const int64_t* yfix, const uint32_t* w,
                           const uint32_t* rows, int64_t n_rows, const int32_t* feats,
-                          int32_t n_feats, int32_t n_bins, uint64_t out[8]) {
-    if (!bins || !yq || !w || !rows || !feats || n_feats < 1 || n_bins < 2) return -1;
+                          int32_t n_feats, int32_t n_bins, int32_t s_gain, int64_t out[8]) {
+    if (!bins || !yfix || !w || !rows || !feats || n_feats < 1 || n_bins < 2) return -1;
     Data d;
     d.n = n;
-    d.y = yq;
-    d.K = 2;
     d.B = n_bins;
     d.reg = true;
+    d.yfix = yfix;
     int32_t maxf = 0;
     for (int q = 0; q < n_feats; ++q) maxf = std::max(maxf, feats[q]);
     d.p_w = maxf + 1;
     for (int64_t f = 0; f < d.p_w; ++f) d.col.push_back(bins + f * n);
     std::vector<uint32_t> rv(rows, rows + n_rows);
     std::vector<int32_t> fv(feats, feats + n_feats);
-    uint64_t W = 0, T = 0;
+    uint64_t W = 0;
+    int64_t T = 0;
     for (uint32_t i : rv) {
         W += w[i];
-        T += (uint64_t)w[i] * (uint64_t)yq[i];
+        T += (int64_t)w[i] * yfix[i];
     }
-    const Cand c = best_split_reg(d, rv, w, fv, W, T);
-    const bool found = c.valid && positive_gain(c, T * T, W);
+    const RegCand c = best_split_reg(d, rv, w, fv, W, T);
+    const bool found = c.valid && reg_gap(c) != 0;
     out[0] = found;
-    out[1] = (uint64_t)c.q;
-    out[2] = (uint64_t)c.b;
-    out[3] = c.nl;
-    out[4] = c.sl;
-    out[5] = c.nr;
-    out[6] = c.sr;
-    out[7] = found ? gain_fixed_reg(c, T * T, W) : 0;
+    out[1] = c.q;
+    out[2] = c.b;
+    out[3] = (int64_t)c.wl;
+    out[4] = (int64_t)c.wr;
+    out[5] = c.tl;
+    out[6] = c.tr;
+    out[7] = found ? (int64_t)gain_fixed_reg(c, s_gain) : 0;
     return 0;
 }
 

@@ -145,20 +145,25 @@ int oracle_boruta_fit_ext(const float* X, const int32_t* y, int64_t n, int64_t p
                           double* shadow_max_out, int32_t* n_iter_out, oracle_trace_fn trace,
                           void* trace_user);
 
-/* Regression Boruta (the paper's regression experiments): y [n] float
- * targets, quantised to levels 0..255 by oracle_quantize_target; the split
- * maximises T_L^2/W_L + T_R^2/W_R (W the bootstrap weight, T the weighted
- * level sum of a child) and the fixed-point decrease is floor(2^33 D / 255),
- * D the weighted squared-error decrease.  importance_mode 0 (TreeImp), 1
- * (Permut: a leaf predicts floor(256 T / W), its mean level in 1/256 units;
- * a column's drop is the increase of the OOB rows' squared error under the
- * permutation, reported per row and replica in level^2 units; needs
- * n_trees * n * n_perm <= 2^31) or 2 (Algorithm 3: per row
- * floor(D^2 / n_trees^2), D the change of the summed leaf levels under the
- * shared row permutation, summed over rows and reported per row in level^2
- * units).  n <= 65536.  The trace's node columns hold
- * 255 W as the weighted count and, for a leaf, 1 if T > 255 W - T else 0; its
- * OOB-correct count is 0.  Other outputs as oracle_boruta_fit. */
+/* Regression Boruta (the paper's regression experiments run Boruta on a
+ * random-forest regressor with squared-error loss): y [n] float32 targets,
+ * finite (else -2).  Each target is held exactly as the integer
+ * y_fix = rint(y 2^(38 - e)), e the smallest integer with every |y| < 2^e
+ * (oracle_fix_targets).  A node with bootstrap weights w has W = sum w and
+ * T = sum w y_fix; the split maximises T_L^2/W_L + T_R^2/W_R exactly (ties
+ * to the earlier draw, then the smaller bin) and needs a strictly positive
+ * decrease D = (T_L W - T W_L)^2 / (W_L W_R W); Algorithm 2 accumulates
+ * floor(D / 2^s_gain).  A leaf predicts floor(T / W).  importance_mode 0
+ * (TreeImp), 1 (Permut: a row scores floor((y_fix - pred)^2 / 2^s_perm); a
+ * column's drop is the increase of the OOB rows' summed score under the
+ * permutation, reported per OOB row and replica in squared target units) or
+ * 2 (Algorithm 3: a row scores floor(Dsum^2 / (n_trees^2 2^s_kl)), Dsum the
+ * change of its summed leaf predictions under the shared row permutation,
+ * summed over rows and reported per row in squared target units).  The
+ * shifts keep every sum within 64 bits (see oracle_fix_targets).  The
+ * trace's node columns hold W as the weighted count and, for a leaf, its
+ * prediction floor(T / W); its OOB-correct count is 0.  Other outputs as
+ * oracle_boruta_fit. */
 int oracle_boruta_fit_reg(const float* X, const float* y, int64_t n, int64_t p,
                           int32_t n_trees, int32_t max_depth, int32_t mtry,
                           int32_t importance_mode, int32_t max_iter, double alpha, uint64_t seed,
@@ -167,16 +172,18 @@ int oracle_boruta_fit_reg(const float* X, const float* y, int64_t n, int64_t p,
                           int32_t* hits_out, double* shadow_max_out, int32_t* n_iter_out,
                           oracle_trace_fn trace, void* trace_user);
 
-/* Target quantisation: floor((y - min) 255 / (max - min) + 1/2) in double (0
- * for a constant target). */
-void oracle_quantize_target(const float* y, int64_t n, int32_t* out);
+/* Fixed-point targets yfix_out[n] and the scale exponent e (returned); with
+ * R = max y_fix - min y_fix, shifts_out (nullable) = s_gain = max(0, bits(n) +
+ * 2 bits(R) - 64), s_perm = max(0, bits(n_trees n_perm n) + 2 bits(R + 1) -
+ * 63), s_kl = max(0, bits(n) + 2 bits(R + 1) - 63), and R. */
+int32_t oracle_fix_targets(const float* y, int64_t n, int32_t n_trees, int32_t n_perm,
+                           int64_t* yfix_out, int64_t* shifts_out);
 
-/* The regression split search of one node (as oracle_best_split, with
- * quantised targets yq): out = found, draw position, bin, W_L, T_L^2, W_R,
- * T_R^2, fixed-point decrease. */
-int oracle_best_split_reg(const uint8_t* bins, int64_t n, const int32_t* yq, const uint32_t* w,
+/* The regression split search of one node with fixed-point targets yfix:
+ * out = found, draw position, bin, W_L, W_R, T_L, T_R, floor(D / 2^s_gain). */
+int oracle_best_split_reg(const uint8_t* bins, int64_t n, const int64_t* yfix, const uint32_t* w,
                           const uint32_t* rows, int64_t n_rows, const int32_t* feats,
-                          int32_t n_feats, int32_t n_bins, uint64_t out[8]);
+                          int32_t n_feats, int32_t n_bins, int32_t s_gain, int64_t out[8]);
 
 /* Hit threshold over m >= 1 shadow importances at percentile perc (above). */
 int64_t oracle_shadow_threshold(const int64_t* sha, int32_t m, int32_t perc);

@@ -89,9 +89,9 @@ def lib():
         L.oracle_boruta_fit_reg.argtypes = [P, P, i64, i64, i32, i32, i32, i32, i32, f64, u64,
                                             i32, i32, i32, i32, P, P, P, P, P, TRACE_FN, P]
         L.oracle_boruta_fit_reg.restype = i32
-        L.oracle_quantize_target.argtypes = [P, i64, P]
-        L.oracle_quantize_target.restype = None
-        L.oracle_best_split_reg.argtypes = [P, i64, P, P, P, i64, P, i32, i32, P]
+        L.oracle_fix_targets.argtypes = [P, i64, i32, i32, P, P]
+        L.oracle_fix_targets.restype = i32
+        L.oracle_best_split_reg.argtypes = [P, i64, P, P, P, i64, P, i32, i32, i32, P]
         L.oracle_best_split_reg.restype = i32
         L.oracle_shadow_threshold.argtypes = [P, i32, i32]
         L.oracle_shadow_threshold.restype = i64
@@ -167,26 +167,33 @@ def best_split(bins, y, w, rows, feats, n_classes, n_bins):
     return {k: int(v) for k, v in zip(keys, out)}
 
 
-def best_split_reg(bins, yq, w, rows, feats, n_bins):
+def best_split_reg(bins, yfix, w, rows, feats, n_bins, s_gain=0):
+    """Best regression split of one node with fixed-point targets yfix (int64):
+    found, draw position q, bin b, W_L (wl), W_R (wr), T_L (tl), T_R (tr) and
+    floor(D / 2^s_gain)."""
     bins = np.ascontiguousarray(bins, dtype=np.uint8)
-    yq = np.ascontiguousarray(yq, dtype=np.int32)
+    yfix = np.ascontiguousarray(yfix, dtype=np.int64)
     w = np.ascontiguousarray(w, dtype=np.uint32)
     rows = np.ascontiguousarray(rows, dtype=np.uint32)
     feats = np.ascontiguousarray(feats, dtype=np.int32)
-    out = np.zeros(8, dtype=np.uint64)
-    rc = lib().oracle_best_split_reg(_ptr(bins), bins.shape[1], _ptr(yq), _ptr(w), _ptr(rows),
-                                     len(rows), _ptr(feats), len(feats), n_bins, _ptr(out))
+    out = np.zeros(8, dtype=np.int64)
+    rc = lib().oracle_best_split_reg(_ptr(bins), bins.shape[1], _ptr(yfix), _ptr(w), _ptr(rows),
+                                     len(rows), _ptr(feats), len(feats), n_bins, s_gain,
+                                     _ptr(out))
     if rc:
         raise ValueError("oracle_best_split_reg failed")
-    keys = ["found", "q", "b", "nl", "sl", "nr", "sr", "gain_fix"]
+    keys = ["found", "q", "b", "wl", "wr", "tl", "tr", "gain_fix"]
     return {k: int(v) for k, v in zip(keys, out)}
 
 
-def quantize_target(y):
+def fix_targets(y, n_trees=1, n_perm=1):
+    """Fixed-point targets of float32 y: (y_fix int64, e, shifts) with
+    y_fix = rint(y 2^(38 - e)) and shifts = dict(s_gain, s_perm, s_kl, range)."""
     y = np.ascontiguousarray(y, dtype=np.float32)
-    out = np.zeros(y.shape[0], dtype=np.int32)
-    lib().oracle_quantize_target(_ptr(y), y.shape[0], _ptr(out))
-    return out
+    out = np.zeros(y.shape[0], dtype=np.int64)
+    sh = np.zeros(4, dtype=np.int64)
+    e = lib().oracle_fix_targets(_ptr(y), y.shape[0], n_trees, n_perm, _ptr(out), _ptr(sh))
+    return out, int(e), dict(zip(("s_gain", "s_perm", "s_kl", "range"), map(int, sh)))
 
 
 def grow_tree(bins, y, w, n_classes, n_bins, max_depth, mtry, seed, t, tree):
@@ -208,7 +215,10 @@ def binom_decide(hits, t, p, alpha):
     return int(lib().oracle_binom_decide(hits, t, p, alpha))
 
 
-def _trace_collector(store):
+def _trace_collector(store, p=None):
+    """Copies each iteration record into the list `store`, or, when `store`
+    is a callable, hands the record to it (and keeps nothing).  p: the
+    feature count (hits and state are copied when given)."""
     def cb(_user, trp):
         tr = trp.contents
         p_w, nt, nn = tr.p_w, tr.n_trees, tr.n_nodes
@@ -221,8 +231,21 @@ def _trace_collector(store):
             "nodes": np.ctypeslib.as_array(tr.nodes, (nn, 6)).copy() if nn else
             np.zeros((0, 6), np.int64),
         }
-        store.append(rec)
+        if p is not None:
+            rec["hits"] = np.ctypeslib.as_array(tr.hits, (p,)).copy()
+            rec["state"] = np.ctypeslib.as_array(tr.state, (p,)).copy()
+        if callable(store):
+            store(rec)
+        else:
+            store.append(rec)
     return TRACE_FN(cb)
+
+
+def _collector_for(trace, traces, p):
+    """trace: False, True (records kept in `traces`) or a callable."""
+    if callable(trace):
+        return _trace_collector(trace, p)
+    return _trace_collector(traces, p) if trace else TRACE_FN()
 
 
 def boruta_fit(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=0, max_iter=20,
@@ -237,7 +260,7 @@ def boruta_fit(X, y, n_classes, n_trees, max_depth, mtry=0, importance_mode=0, m
     smax = np.full(max_iter, np.nan)
     n_iter = ctypes.c_int32(0)
     traces = []
-    cb = _trace_collector(traces) if trace else TRACE_FN()
+    cb = _collector_for(trace, traces, p)
     rc = lib().oracle_boruta_fit_ext(_ptr(X), _ptr(y), n, p, n_classes, n_trees, max_depth,
                                      mtry, importance_mode, max_iter, alpha, seed, n_bins,
                                      n_perm, n_threads, int(permut_naive), perc,
@@ -267,7 +290,7 @@ def boruta_fit_reg(X, y, n_trees, max_depth, mtry=0, importance_mode=0, max_iter
     smax = np.full(max_iter, np.nan)
     n_iter = ctypes.c_int32(0)
     traces = []
-    cb = _trace_collector(traces) if trace else TRACE_FN()
+    cb = _collector_for(trace, traces, p)
     rc = lib().oracle_boruta_fit_reg(_ptr(X), _ptr(y), n, p, n_trees, max_depth, mtry,
                                      importance_mode, max_iter, alpha, seed, n_bins, n_perm,
                                      n_threads, int(permut_naive),
@@ -338,7 +361,7 @@ def boruta_step(X, y, n_classes, n_trees, max_depth, t, state, hits, mtry=0,
     if sub is not None and n_sub == 0:
         sub = np.zeros(1, np.int32)  # non-null pointer, zero trees: widening only
     traces = []
-    cb = _trace_collector(traces) if trace else TRACE_FN()
+    cb = _collector_for(trace, traces, p)
     kc = None if kl_cols is None else np.ascontiguousarray(kl_cols, dtype=np.int32)
     rc = lib().oracle_boruta_step_cols(_ptr(X), _ptr(y), n, p, n_classes, n_trees, max_depth,
                                        mtry, importance_mode, alpha, seed, n_bins, n_perm, t,

@@ -196,7 +196,8 @@ def _trace_collector(store, p, keep_iters=None):
         p_w, nt, nn = tr.p_w, tr.n_trees, tr.n_nodes
         if keep_iters is not None and tr.t not in keep_iters:
             return
-        store["iters"].append({
+        sink = store["sink"] if "sink" in store else store["iters"].append
+        sink({
             "hits": np.ctypeslib.as_array(tr.hits, (p,)).copy(),
             "state": np.ctypeslib.as_array(tr.state, (p,)).copy(),
             "job": tr.job, "t": tr.t, "p_cur": tr.p_cur, "n_sha": tr.n_sha, "p_w": p_w,
@@ -218,7 +219,8 @@ TUNE_KEYS = ("small_rows", "grid_small", "grid_hist", "grid_finalize", "col_leve
 def make_options(n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED, trace=False,
                  stats=False, p=0, graph=True, tune=None, perc=100, rough_fix=False):
     """Options plus the Python objects that must stay alive during the call.
-    trace: False, True (every iteration) or a set of iterations to keep.
+    trace: False, True (every iteration), a set of iterations to keep, or a
+    callable that receives each iteration's record (nothing is kept).
     perc / rough_fix: the two options outside Algorithm 1 (boruta_options)."""
     o = boruta_default_options()
     o.n_bins, o.n_perm, o.split_rank, o.form = n_bins, n_perm, split_rank, form
@@ -229,7 +231,11 @@ def make_options(n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED, 
             raise ValueError(f"unknown tuning key {k}")
         setattr(o, k, int(v))
     keep = {"iters": []}
-    if trace is not False:
+    if callable(trace):
+        keep["sink"] = trace
+        keep["cb"] = _trace_collector(keep, p, None)
+        o.trace = keep["cb"]
+    elif trace is not False:
         keep["cb"] = _trace_collector(keep, p, None if trace is True else set(trace))
         o.trace = keep["cb"]
     if stats:
