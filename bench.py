@@ -126,10 +126,10 @@ def run_gpu(jobs, pr, steps, warmup, form, rank, stats, graph=True, tune=None):
     t_up = time.perf_counter()  # host-to-device upload of the inputs (PCIe)
     for jd in jobs:
         d = dict(jd)
-        d["X"] = torch.from_numpy(jd["X"]).cuda()
+        d["X"] = torch.from_numpy(np.ascontiguousarray(jd["X"])).cuda()
         for key in ("y", "y_reg"):
             if key in jd:
-                d[key] = torch.from_numpy(jd[key]).cuda()
+                d[key] = torch.from_numpy(np.ascontiguousarray(jd[key])).cuda()
         d["max_iter"] = min(jd["max_iter"], 1000, warmup + steps)
         dev.append(d)
         shapes.append(dict(n=d["X"].shape[0], p=d["X"].shape[1], regression="y_reg" in jd,
@@ -567,8 +567,8 @@ def madelon_legs():
     from paper_2605_09950_amd import binding as B
     jobs, pr, desc, _ = workload("madelon")
     main_leg, _, roof, _ = roofline_legs(jobs, pr, 20, 2, None, "madelon")
-    dev = [dict(jobs[0], X=torch.from_numpy(jobs[0]["X"]).cuda(),
-                y=torch.from_numpy(jobs[0]["y"]).cuda())]
+    dev = [dict(jobs[0], X=torch.from_numpy(np.ascontiguousarray(jobs[0]["X"])).cuda(),
+                y=torch.from_numpy(np.ascontiguousarray(jobs[0]["y"])).cuda())]
     shapes = [dict(n=dev[0]["X"].shape[0], p=dev[0]["X"].shape[1],
                    **{k: v for k, v in dev[0].items() if k not in ("X", "y")})]
     ws = torch.empty(B.boruta_workspace_size(shapes, n_bins=pr["n_bins"]), dtype=torch.uint8,

@@ -16,6 +16,8 @@ import json
 import os
 import time
 
+import numpy as np
+
 from paper_2605_09950_amd import binding as B
 
 # candidate values per parameter, in search order (0 = library default).
@@ -85,10 +87,10 @@ def autotune(jobs, n_bins=256, n_perm=1, steps=3, warmup=2, cache=None, log=None
     dev, shapes = [], []
     for jd in jobs:
         d = dict(jd)
-        d["X"] = torch.from_numpy(jd["X"]).cuda()
+        d["X"] = torch.from_numpy(np.ascontiguousarray(jd["X"])).cuda()
         for key in ("y", "y_reg"):
             if key in jd:
-                d[key] = torch.from_numpy(jd[key]).cuda()
+                d[key] = torch.from_numpy(np.ascontiguousarray(jd[key])).cuda()
         d["max_iter"] = min(jd.get("max_iter", 20), warmup + steps)
         dev.append(d)
         shapes.append(dict(n=d["X"].shape[0], p=d["X"].shape[1], regression="y_reg" in jd,

@@ -480,6 +480,15 @@ def boruta_probe_copy(dst, src, nbytes, stream=None):
     _check(lib().boruta_probe_copy(dst.data_ptr(), src.data_ptr(), nbytes, st.cuda_stream))
 
 
+def _check_device_input(t, dtype, ndim, name):
+    """A device input is handed over as a raw pointer: it must be a contiguous
+    CUDA tensor of the stated dtype and rank (a strided view would be read
+    as if it were row-major)."""
+    if not (getattr(t, "is_cuda", False) and str(t.dtype) == "torch." + dtype and
+            t.dim() == ndim and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor of rank {ndim}")
+
+
 class Session:
     """boruta_session_* wrapper.  jobs as for boruta_fit_batch; with
     inputs_on_device, X/y are torch CUDA tensors (float32 [n][p], int32 [n])."""
@@ -493,6 +502,11 @@ class Session:
             yr, rp = jd.get("y_reg"), None
             if inputs_on_device:
                 X, y = jd["X"], jd.get("y")
+                _check_device_input(X, "float32", 2, "X")
+                if y is not None:
+                    _check_device_input(y, "int32", 1, "y")
+                if yr is not None:
+                    _check_device_input(yr, "float32", 1, "y_reg")
                 xp = X.data_ptr()
                 yp = y.data_ptr() if y is not None else None
                 rp = yr.data_ptr() if yr is not None else None

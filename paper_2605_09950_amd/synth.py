@@ -54,7 +54,7 @@ def madelon_like(seed=1001, n=10000, n_inf=20, n_mix=80, n_noise=400, n_classes=
     noise = rng.standard_normal((n, n_noise))
     full = np.concatenate([XI, mixes, noise], axis=1)
     order = rng.permutation(full.shape[1])
-    X = full[:, order].astype(np.float32)
+    X = np.ascontiguousarray(full[:, order], dtype=np.float32)
     inv = np.argsort(order)
     inf = np.sort(inv[:n_inf])
     mix_cols = np.sort(inv[n_inf:n_inf + n_mix])
