@@ -214,30 +214,30 @@ int boruta_fit_ex(const float* X, const int32_t* y, int64_t n, int64_t p, int32_
                   double* shadow_max_out, int32_t* n_iter_out);
 
 /* Regression Boruta (the paper's regression experiments run Boruta on a
- * random-forest regressor): importance_mode 0 (TreeImp), 1 (Permut) or 2
- * (Algorithm 3).  y: [n] float32 targets, finite, n <= 65536
- * (else BORUTA_E_INVALID_ARG; non-finite X or y: BORUTA_E_NONFINITE).  The
- * targets are quantised to levels 0..255, floor((y - min) 255 / (max - min) +
- * 1/2) in double (all 0 for a constant target); a split maximises
- * T_L^2/W_L + T_R^2/W_R (W: bootstrap weight, T: weighted level sum of a
- * child), i.e. minimises the children's weighted squared error, with the
- * exact comparison and tie-break of the classification rule, and Algorithm 2
- * accumulates floor(2^33 D / 255) per split, D the squared-error decrease.
- * Each in-bag row is held as two records, class 0 with weight w (255 - y) and
- * class 1 with weight w y, whose Gini decrease equals 2 D / 255, so the
- * classification kernels grow the forest unchanged.  Arguments and outputs
- * otherwise as boruta_fit_ex; in a trace a node's weighted count is 255 W and
- * a leaf's class is 1 when T > 255 W - T, else 0.  Permut: a leaf predicts
- * its mean level floor(256 T / W) (in 1/256 level units); a column's drop is
- * the increase of the out-of-bag rows' squared error under the column's
- * permutation (1/65536 level^2 units), reported per OOB row and replica in
- * level^2 units; n_trees * n * n_perm must not exceed 2^31
- * (BORUTA_E_INVALID_ARG); the trace's OOB-correct count is 0.  Algorithm 3
- * (importance_mode 2): with S a row's sum over trees of its leaves' mean
- * levels and D the change of S when the column is permuted by the
- * iteration's shared row permutation, the row's loss is floor(D^2 /
- * n_trees^2), the squared difference of the mean predictions in 1/65536
- * level^2 units; reported per row in level^2 units. */
+ * random-forest regressor with squared-error loss, Sec. 2.2 and Sec. 3):
+ * importance_mode 0 (TreeImp), 1 (Permut) or 2 (Algorithm 3).  y: [n] float32
+ * targets, finite (non-finite X or y: BORUTA_E_NONFINITE); n in [2, 2^24].
+ * Each target is held exactly as the integer y_fix = rint(y 2^(38 - e)), e the
+ * smallest integer with every |y| < 2^e (exact for |y| >= 2^(e - 15)).  A node
+ * with bootstrap weights w has W = sum w and T = sum w y_fix; a split
+ * maximises T_L^2/W_L + T_R^2/W_R exactly (ties to the earlier draw, then the
+ * smaller bin) and needs a strictly positive decrease
+ * D = (T_L W - T W_L)^2 / (W_L W_R W); Algorithm 2 accumulates
+ * floor(D / 2^s_gain).  A leaf predicts floor(T / W).  Permut: a row scores
+ * floor((y_fix - pred)^2 / 2^s_perm) and a column's drop is the increase of
+ * the out-of-bag rows' summed score under its permutation, reported per OOB
+ * row and replica in squared target units.  Algorithm 3: a row scores
+ * floor(Dsum^2 / (n_trees^2 2^s_kl)), Dsum the change of its summed leaf
+ * predictions under the iteration's shared row permutation, reported per row
+ * in squared target units.  With R the range of y_fix, s_gain =
+ * max(0, bits(n) + 2 bits(R) - 64), s_perm = max(0, bits(n_trees n_perm n) +
+ * 2 bits(R + 1) - 63) and s_kl = max(0, bits(n) + 2 bits(R + 1) - 63) keep
+ * every sum within 64 bits.  Arguments and outputs otherwise as boruta_fit_ex;
+ * in a trace a node's weighted count is W, a leaf's class column holds its
+ * prediction floor(T / W), and the OOB-correct count is 0.  Regression nodes
+ * always take the histogram path (small_rows does not apply), and a batch
+ * with a regression job keeps every tree level node-major (col_level does not
+ * apply). */
 int boruta_fit_regression(const float* X, const float* y, int64_t n, int64_t p, int32_t n_trees,
                           int32_t max_depth, int32_t mtry, int32_t importance_mode,
                           int32_t max_iter, double alpha, uint64_t seed, const boruta_options* opt,

@@ -230,10 +230,13 @@ struct JobDev {
     int32_t pw_cap;        // p + max_sha
     uint32_t gbase;        // first global column id of the job (column-major histogram path)
     uint32_t gq;           // 16-byte words of one bin column (n_pad / 16)
-    uint32_t rstride;      // row records per tree: n, or 2n for a regression job
-    int32_t reg;           // regression: y holds target levels 0..255, and each in-bag
-                           // row is two records (class 0 weight w(255 - y), class 1 w y)
-    const uint8_t* y;      // [n]
+    uint32_t rstride;      // row records per tree (n)
+    int32_t reg;           // regression job: targets in yfix, labels unused
+    // regression: fixed-point shifts of the decrease, the Permut and the
+    // divergence scores, and the binary exponent of the reported importance
+    int32_t s_gain, s_perm, s_kl, rep_exp;
+    const int64_t* yfix;   // [n] regression: targets rint(y 2^(38 - e))
+    const uint8_t* y;      // [n] class labels
     uint8_t* orig;         // [p][n_pad] binned originals
     uint8_t* sha;          // [max_sha][n_pad] shadows of the current iteration
     const uint8_t** colptr;// [pw_cap] widened column -> bins
@@ -277,11 +280,13 @@ struct NodeDev {
 // level so that an item's first loads do not depend on each other.
 struct SlotRec {
     const uint64_t* recs;  // the node's row records (this level's parity)
+    const int64_t* yfix;   // regression job: its fixed-point targets (else null)
     uint32_t id;           // node index
     uint32_t len, n;       // distinct rows, weighted rows
     uint32_t mtry;         // features drawn this iteration
-    uint32_t B, pad;
-    uint32_t cnode[16];    // weighted class counts (zero past K)
+    uint32_t B, reg;       // bins; 1 for a regression job
+    uint32_t cnode[16];    // weighted class counts (zero past K); regression: the
+                           // weighted target sum T in words 0 (low) and 1 (high)
 };
 
 // Per-level counters: the lists of tree level d (small nodes, large-node

@@ -23,7 +23,8 @@ namespace boruta {
 // launchers (k_prep.hip)
 void launch_validate(const float*, size_t, const int32_t*, size_t, int, uint32_t*, hipStream_t);
 void launch_validate_reg(const float*, size_t, const float*, size_t, uint32_t*, hipStream_t);
-void launch_target_levels(const float*, size_t, uint8_t*, hipStream_t);
+void launch_target_range(const float*, size_t, float*, hipStream_t);
+void launch_target_fix(const float*, size_t, int, int64_t*, hipStream_t);
 void launch_labels(const int32_t*, size_t, uint8_t*, hipStream_t);
 void launch_binning(const float*, int64_t, int64_t, int, uint8_t*, int64_t, uint32_t*, int64_t,
                     hipStream_t);
@@ -76,9 +77,6 @@ constexpr size_t kColAutoBytes = size_t(128) << 20;
 constexpr int kColNever = 64;
 // KL importance: bound of its per-block difference buffer.
 constexpr uint64_t kKlDeltaBytes = uint64_t(256) << 20;
-// Regression jobs: at most this many rows, so that the channel counts of a
-// node (255 times its bootstrap weight) stay below 2^24.
-constexpr int64_t kRegMaxRows = 65536;
 
 struct Error : std::runtime_error {
     int code;
@@ -182,9 +180,6 @@ Opts read_opts(const boruta_options* o) {
 void check_spec(const Spec& s) {
     auto bad = [](const char* m) { throw Error(BORUTA_E_INVALID_ARG, m); };
     if (!s.X || (!s.y && !s.yr)) bad("X and y must be non-null");
-    if (s.yr) {
-        if (s.n > kRegMaxRows) bad("regression: n outside [2, 65536]");
-    }
     if (s.n < 2 || s.n > (int64_t(1) << 24)) bad("n outside [2, 2^24]");
     if (s.p < 1 || s.p > (int64_t(1) << 24)) bad("p outside [1, 2^24]");
     if (s.K < 2 || s.K > 16) bad("n_classes outside [2, 16]");
@@ -197,6 +192,33 @@ void check_spec(const Spec& s) {
 }
 
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+int bit_len(uint64_t v) { return v ? 64 - __builtin_clzll(v) : 0; }
+
+// Fixed-point scale of a regression job's float targets, from their minimum
+// and maximum: e is the smallest integer with every |y| < 2^e and the
+// targets are held as y_fix = rint(y 2^(38 - e)) (exact for |y| >= 2^(e-15));
+// with R the range of y_fix, the split decreases, the Permut squared errors
+// and the divergence scores are shifted right by s_gain, s_perm and s_kl bits
+// so that a tree's decreases (at most n R^2 / 4), the n_trees n_perm n Permut
+// terms and the n divergence terms (each at most (R + 1)^2) sum within 64 bits.
+struct RegShift {
+    int e = 0, s_gain = 0, s_perm = 0, s_kl = 0;
+};
+
+RegShift reg_shift(float lo, float hi, int64_t n, int T, int R) {
+    RegShift r;
+    const double m = std::max(std::fabs((double)lo), std::fabs((double)hi));
+    if (m > 0.0) std::frexp(m, &r.e);
+    const int64_t flo = (int64_t)std::rint(std::ldexp((double)lo, 38 - r.e));
+    const int64_t fhi = (int64_t)std::rint(std::ldexp((double)hi, 38 - r.e));
+    const uint64_t range = (uint64_t)(fhi - flo);
+    r.s_gain = std::max(0, bit_len((uint64_t)n) + 2 * bit_len(range) - 64);
+    r.s_perm = std::max(0, bit_len((uint64_t)T * (uint64_t)R * (uint64_t)n) +
+                               2 * bit_len(range + 1) - 63);
+    r.s_kl = std::max(0, bit_len((uint64_t)n) + 2 * bit_len(range + 1) - 63);
+    return r;
+}
 int64_t pow2_at_least(int64_t v) {
     int64_t P = 1;
     while (P < v) P <<= 1;
@@ -229,6 +251,7 @@ struct JobPlan {
     int max_sha, pw_cap, mtry_max;
     size_t X, y32, y8, orig, sha, colptr, colsrc, act, state, hits, hist, smax, hconf, hrej, G,
         imp, wbuf, rec0, rec1, oob, tstat;
+    size_t yfix = 0, yrange = 0;  // regression: fixed-point targets, target minimum/maximum
 };
 
 struct Plan {
@@ -292,10 +315,12 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
         j.G = s.mode == 0 ? r.take(T * j.pw_cap * 8) : 0;
         j.imp = r.take((size_t)j.pw_cap * 8);
         j.wbuf = r.take(T * n * 4);
-        // regression rows are two records each
-        const size_t rs = s.yr ? 2 * n : n;
-        j.rec0 = r.take(T * rs * 8);
-        j.rec1 = r.take(T * rs * 8);
+        j.rec0 = r.take(T * n * 8);
+        j.rec1 = r.take(T * n * 8);
+        if (s.yr) {
+            j.yfix = sh ? sh->yfix : r.take(n * 8);
+            j.yrange = sh ? sh->yrange : r.take(8);
+        }
         j.oob = r.take(T * n * 4);
         j.tstat = r.take(T * 16);
         j.rmean = r.take(p * 8);
@@ -319,7 +344,10 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
         // every searched node reserves a pair of child slots (a leaf leaves its
         // pair unused), so the pool holds up to twice the nodes of the trees
         node_cap += T + 2 * T * per_tree_nodes;
-        const uint64_t large_per_tree = (uint64_t)(s.n + o.small_rows) / (o.small_rows + 1);
+        // a regression node of two or more distinct rows always takes the
+        // histogram path
+        const uint64_t large_per_tree = s.yr ? (uint64_t)(s.n + 1) / 2
+                                             : (uint64_t)(s.n + o.small_rows) / (o.small_rows + 1);
         slot_cap += T * large_per_tree;
         small_cap += T * (uint64_t)((s.n + 1) / 2);
         pl.max_sha = std::max(pl.max_sha, j.max_sha);
@@ -331,8 +359,12 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     }
     // The column-major path (batched form) stages a whole bin column in LDS
     // beside its waves' histograms: it is planned when a column and two
-    // waves fit the workgroup's LDS, with up to kColWavesMax waves.
-    int col_level = o.col_level;
+    // waves fit the workgroup's LDS, with up to kColWavesMax waves.  A plan
+    // with a regression job stays node-major: its items need the node-major
+    // item layout (an LDS region of at least 768 words per wave).
+    bool any_reg = false;
+    for (const Spec& s : specs) any_reg |= s.yr != nullptr;
+    int col_level = any_reg ? kColNever : o.col_level;
     if (col_level == 0) {
         size_t widest = 0;
         for (const JobPlan& j : pl.jp) widest = std::max(widest, (size_t)j.pw_cap * j.n_pad);
@@ -601,10 +633,16 @@ void Engine::setup(std::vector<int>& status) {
                 status[j] = BORUTA_E_INVALID_ARG;
                 continue;
             }
-            if (s.yr)
-                launch_target_levels(yr, (size_t)s.n, at<uint8_t>(jp.y8), st);
-            else
+            if (s.yr) {
+                // the targets' range picks the fixed-point scale
+                launch_target_range(yr, (size_t)s.n, at<float>(jp.yrange), st);
+                float lh[2];
+                d2h(lh, at<float>(jp.yrange), 8);
+                const RegShift rs = reg_shift(lh[0], lh[1], s.n, s.T, O.R);
+                launch_target_fix(yr, (size_t)s.n, 38 - rs.e, at<int64_t>(jp.yfix), st);
+            } else {
                 launch_labels(y, (size_t)s.n, at<uint8_t>(jp.y8), st);
+            }
             launch_binning(X, s.n, s.p, O.B, at<uint8_t>(jp.orig), jp.n_pad,
                            at<uint32_t>(pl.keys), jp.P, st);
         }
@@ -632,7 +670,20 @@ void Engine::setup(std::vector<int>& status) {
         J.gbase = jp.gbase;
         J.gq = (uint32_t)(jp.n_pad / 16);
         J.reg = s.yr ? 1 : 0;
-        J.rstride = (uint32_t)(s.yr ? 2 * s.n : s.n);
+        J.rstride = (uint32_t)s.n;
+        J.yfix = s.yr ? at<int64_t>(jp.yfix) : nullptr;
+        J.s_gain = J.s_perm = J.s_kl = J.rep_exp = 0;
+        if (s.yr) {
+            float lh[2];
+            d2h(lh, at<float>(jp.yrange), 8);
+            const RegShift rs = reg_shift(lh[0], lh[1], s.n, s.T, O.R);
+            J.s_gain = rs.s_gain;
+            J.s_perm = rs.s_perm;
+            J.s_kl = rs.s_kl;
+            // reported regression scores in squared target units
+            J.rep_exp = s.mode == 1 ? rs.s_perm - 2 * (38 - rs.e)
+                                    : (s.mode == 2 ? rs.s_kl - 2 * (38 - rs.e) : 0);
+        }
         J.y = at<uint8_t>(jp.y8);
         J.orig = at<uint8_t>(jp.orig);
         J.sha = at<uint8_t>(jp.sha);
@@ -976,6 +1027,15 @@ void Engine::emit_trace(const std::vector<int>& live, uint32_t n_nodes) {
     std::vector<uint64_t> gains(n_nodes);
     d2h(nodes.data(), at<NodeDev>(pl.nodes), (size_t)n_nodes * sizeof(NodeDev));
     d2h(gains.data(), at<uint64_t>(pl.ngain), (size_t)n_nodes * 8);
+    // regression leaves report their prediction floor(T / W), T in the
+    // node's first two class words
+    bool any_reg = false;
+    for (int j : live) any_reg |= hj[j].reg != 0;
+    std::vector<uint32_t> cls;
+    if (any_reg) {
+        cls.resize((size_t)n_nodes * pl.kmax);
+        d2h(cls.data(), at<uint32_t>(pl.cls), cls.size() * 4);
+    }
     for (size_t li = 0; li < live.size(); ++li) {
         const int j = live[li];
         const JobDev& J = hj[j];
@@ -1001,9 +1061,17 @@ void Engine::emit_trace(const std::vector<int>& live, uint32_t n_nodes) {
                       [&](uint32_t a, uint32_t b) { return nodes[a].heap < nodes[b].heap; });
             for (uint32_t i : v) {
                 const NodeDev& nd = nodes[i];
+                int64_t leaf = nd.leaf_class;
+                if (J.reg && nd.feat < 0) {
+                    const int64_t T = (int64_t)((uint64_t)cls[(size_t)i * pl.kmax] |
+                                                ((uint64_t)cls[(size_t)i * pl.kmax + 1] << 32));
+                    const int64_t W = (int64_t)nd.n;
+                    leaf = T / W;
+                    if (leaf * W != T && T < 0) --leaf;  // floor
+                }
                 rows.insert(rows.end(), {(int64_t)tau, (int64_t)nd.heap, (int64_t)nd.feat,
-                                         (int64_t)(nd.feat >= 0 ? nd.thr : nd.leaf_class),
-                                         (int64_t)nd.n, (int64_t)gains[i]});
+                                         (int64_t)(nd.feat >= 0 ? nd.thr : leaf), (int64_t)nd.n,
+                                         (int64_t)gains[i]});
             }
             stats.insert(stats.end(), {(int64_t)tau, (int64_t)tstat[tau * 4 + 0],
                                        (int64_t)tstat[tau * 4 + 1],
@@ -1189,9 +1257,6 @@ std::unique_ptr<Context> prepare(const std::vector<Spec>& specs, const boruta_op
     const Opts o = read_opts(opt);
     for (const Spec& s : specs) {
         check_spec(s);
-        // regression Permut: the summed squared-error drops stay below 2^63
-        if (s.yr && s.mode == 1 && (int64_t)s.T * s.n * o.R > (int64_t(1) << 31))
-            throw Error(BORUTA_E_INVALID_ARG, "regression Permut needs n_trees * n * n_perm <= 2^31");
     }
     require_device();
     std::unique_ptr<Context> c(new Context);

@@ -5,6 +5,7 @@
 #include <climits>
 
 #include "dev_common.hpp"
+#include "reg_dev.hpp"
 
 namespace boruta {
 
@@ -267,6 +268,39 @@ __device__ inline int write_node(const ForestDev& F, const JobDev& J, uint32_t i
     return (len <= F.small_rows && n < F.small_ncap) ? kSmall : kLarge;
 }
 
+// Regression node: weight W and weighted target sum T (kept in the node's
+// first two class words); it is a final leaf at the maximum depth or with
+// fewer than two distinct rows, else it takes the histogram path (its split
+// search ranks exact weighted target sums, which the wave path does not keep).
+// A leaf's prediction floor(T / W) is read from these fields.
+__device__ inline int write_node_reg(const ForestDev& F, const JobDev& J, uint32_t idx,
+                                     uint32_t tree, uint32_t heap, uint32_t seg, uint32_t len,
+                                     uint32_t W, int64_t T, uint32_t depth) {
+    F.cls[(size_t)idx * F.kmax] = (uint32_t)(uint64_t)T;
+    F.cls[(size_t)idx * F.kmax + 1] = (uint32_t)((uint64_t)T >> 32);
+    NodeDev nd;
+    nd.tree = tree;
+    nd.heap = heap;
+    nd.seg = seg;
+    nd.len = len;
+    nd.n = W;
+    nd.feat = -1;
+    nd.left = 0;
+    nd.thr = 0;
+    nd.leaf_class = 0;
+    nd.depth = (uint8_t)depth;
+    F.nodes[idx] = nd;
+    F.ngain[idx] = 0;
+    if ((int)depth >= J.D || len < 2) return kLeaf;
+    return kLarge;
+}
+
+// Weighted target sum of a regression node from its class words.
+__device__ __forceinline__ int64_t node_tsum(const uint32_t* cls, int kmax, uint32_t idx) {
+    return (int64_t)((uint64_t)cls[(size_t)idx * kmax] |
+                     ((uint64_t)cls[(size_t)idx * kmax + 1] << 32));
+}
+
 // Place node idx in the next level's lists at already reserved positions.
 __device__ inline void put_small(const ForestDev& F, uint32_t pos, uint32_t idx) {
     if (pos < F.small_cap)
@@ -332,6 +366,30 @@ __device__ inline void split_node(const ForestDev& F, JobDev& J, const TreeDev& 
                           nd.depth + 1u, cl);
     kinds[1] = write_node(F, J, child + 1, nd.tree, 2 * nd.heap + 1, nd.seg + nl_rows,
                           nd.len - nl_rows, best.nr, nd.depth + 1u, cr);
+}
+
+// Regression form of split_node: the children's weights and target sums
+// come from the winning candidate.
+__device__ inline void split_node_reg(const ForestDev& F, JobDev& J, const TreeDev& tr,
+                                      uint32_t id, const NodeDev& nd, const Cand& best,
+                                      uint32_t nl_rows, uint64_t gain, uint32_t child,
+                                      int* kinds) {
+    kinds[0] = kinds[1] = kLeaf;
+    if (child + 2 > F.node_cap) {
+        atomicOr(&F.ctr->overflow, 4u);
+        return;
+    }
+    F.nodes[id].feat = best.f;
+    F.nodes[id].thr = (uint16_t)best.b;
+    F.nodes[id].left = child;
+    F.ngain[id] = gain;
+    if (J.mode == 0)
+        atomicAdd((unsigned long long*)&J.G[(size_t)tr.tau * J.pw_cap + best.f],
+                  (unsigned long long)gain);
+    kinds[0] = write_node_reg(F, J, child, nd.tree, 2 * nd.heap, nd.seg, nl_rows, best.nl,
+                              reg_tl(best), nd.depth + 1u);
+    kinds[1] = write_node_reg(F, J, child + 1, nd.tree, 2 * nd.heap + 1, nd.seg + nl_rows,
+                              nd.len - nl_rows, best.nr, reg_tr(best), nd.depth + 1u);
 }
 
 }  // namespace boruta

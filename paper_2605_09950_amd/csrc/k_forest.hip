@@ -34,13 +34,12 @@ namespace boruta {
 // ---------------------------------------------------------------------------
 // Per tree: compact the in-bag rows (multiplicity > 0, ascending) into row
 // records and the out-of-bag rows into a list; create the root node.  The
-// multiplicities are cleared behind the read.  A regression row of level y
-// and multiplicity w becomes two records, class 0 with weight w (255 - y) and
-// class 1 with weight w y (a zero-weight one is left out): the Gini rule on
-// these two classes orders splits exactly as the weighted squared error does.
+// multiplicities are cleared behind the read.  A regression root keeps its
+// bootstrap weight W and weighted fixed-point target sum T.
 __global__ __launch_bounds__(1024) void k_boot_compact(ForestDev F0) {
     __shared__ uint32_t s_win[16], s_wout[16], s_rin[16];
     __shared__ uint32_t s_cls[16];
+    __shared__ unsigned long long s_tsum;
     __shared__ uint32_t s_base_in, s_base_out, s_base_rows;
     ForestDev F = F0;
     F.ctr = F0.ctrs;  // the roots form the lists of level 0
@@ -59,6 +58,7 @@ __global__ __launch_bounds__(1024) void k_boot_compact(ForestDev F0) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid < 16) s_cls[tid] = 0;
     if (tid == 0) {
+        s_tsum = 0;
         s_base_in = 0;
         s_base_out = 0;
         s_base_rows = 0;
@@ -70,15 +70,10 @@ __global__ __launch_bounds__(1024) void k_boot_compact(ForestDev F0) {
         const uint32_t wi = i < n ? w[i] : 0u;
         if (i < n) w[i] = 0;  // multiplicities start from zero next iteration
         const bool inb = i < n && wi > 0, isoob = i < n && wi == 0;
-        const uint32_t yi = inb ? (uint32_t)J.y[i] : 0u;
-        // the row's records: one (class yi, weight wi), or for regression up
-        // to two (class 0, weight w0) and (class 1, weight w1)
-        const uint32_t w0 = reg ? wi * (255u - yi) : wi, w1 = reg ? wi * yi : 0u;
-        const bool h0 = inb && w0 != 0, h1 = inb && w1 != 0;
-        const uint64_t m0 = __ballot(h0), m1 = __ballot(h1), mo = __ballot(isoob);
-        const uint64_t mi = __ballot(inb);
+        const uint32_t yi = inb && !reg ? (uint32_t)J.y[i] : 0u;
+        const uint64_t mi = __ballot(inb), mo = __ballot(isoob);
         if (lane == 0) {
-            s_win[wave] = __popcll(m0) + __popcll(m1);
+            s_win[wave] = __popcll(mi);
             s_wout[wave] = __popcll(mo);
             s_rin[wave] = __popcll(mi);
         }
@@ -89,12 +84,15 @@ __global__ __launch_bounds__(1024) void k_boot_compact(ForestDev F0) {
             pout += s_wout[v];
         }
         if (inb) {
-            if (w0 > 0xFFFFu || w1 > 0xFFFFu) atomicOr(&F.ctr->overflow, 8u);
-            const uint32_t at = pin + __popcll(m0 & below) + __popcll(m1 & below);
-            if (h0) recs[at] = rec_pack(i, w0, reg ? 0u : yi);
-            if (h1) recs[at + (h0 ? 1u : 0u)] = rec_pack(i, w1, 1u);
-            if (h0) atomicAdd(&s_cls[reg ? 0u : yi], w0);
-            if (h1) atomicAdd(&s_cls[1], w1);
+            if (wi > 0xFFFFu) atomicOr(&F.ctr->overflow, 8u);
+            recs[pin + __popcll(mi & below)] = rec_pack(i, wi, yi);
+            atomicAdd(&s_cls[yi], wi);
+        }
+        if (reg) {  // the root's weighted target sum: one LDS atomic per wave
+            long long tv = inb ? (long long)wi * (long long)ldg(J.yfix + i) : 0ll;
+#pragma unroll
+            for (int m = 1; m < 64; m <<= 1) tv += __shfl_xor(tv, m);
+            if (lane == 0 && tv) atomicAdd(&s_tsum, (unsigned long long)tv);
         }
         if (isoob) oob[pout + __popcll(mo & below)] = i;
         __syncthreads();
@@ -120,7 +118,9 @@ __global__ __launch_bounds__(1024) void k_boot_compact(ForestDev F0) {
             counts[k] = s_cls[k];
             tot += s_cls[k];
         }
-        const int kind = write_node(F, J, g, g, 1u, 0u, s_base_in, tot, 0u, counts);
+        const int kind = reg ? write_node_reg(F, J, g, g, 1u, 0u, s_base_in, tot,
+                                              (int64_t)s_tsum, 0u)
+                             : write_node(F, J, g, g, 1u, 0u, s_base_in, tot, 0u, counts);
         enqueue_nodes(F, J, g, &kind, 1);
     }
 }
@@ -710,6 +710,141 @@ __device__ Cand feature_best_compact(uint32_t* h, int B, int q, int f, const uin
     return w;
 }
 
+// ---------------------------------------------------------------------------
+// Regression items (a job of the float-target regressor).  For each of the
+// item's drawn features in turn: an LDS histogram of the bootstrap weights
+// W[256] (32-bit) and the weighted fixed-point target sums T[256] (64-bit LDS
+// atomics, two's complement) over the node's rows, then the threshold scan.
+// Lane l owns bins 4l .. 4l+3; prefix sums over the lanes give each
+// threshold's left (W_L, T_L).  Thresholds are ranked by the FP64 score
+// g^2 / (W_L W_R) (g = T_L W_R - T_R W_L) and every threshold within the
+// ranking margin of the maximum is compared exactly (reg_better); with exact
+// ranking every valid threshold is.
+__device__ __forceinline__ long long wave_excl_sum64(long long x) {
+    long long incl = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const long long o = __shfl_up(incl, d);
+        if ((int)(threadIdx.x & 63) >= d) incl += o;
+    }
+    return incl - x;
+}
+
+__device__ Cand reg_feature_best(const uint32_t* hw, const long long* ht, int B, int q, int f,
+                                 uint32_t W, int64_t T, int split_rank) {
+    const int lane = threadIdx.x & 63;
+    const uint4 wv = reinterpret_cast<const uint4*>(hw)[lane];
+    const uint32_t w4[4] = {wv.x, wv.y, wv.z, wv.w};
+    long long t4[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) t4[u] = ht[lane * 4 + u];
+    const uint32_t wsum = w4[0] + w4[1] + w4[2] + w4[3];
+    const long long tsum = t4[0] + t4[1] + t4[2] + t4[3];
+    uint32_t wl = wave_incl_sum(wsum) - wsum;
+    long long tl = wave_excl_sum64(tsum);
+    Cand c[4];
+    double qc[4];
+    double q1 = -1.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        wl += w4[u];
+        tl += t4[u];
+        const int b = lane * 4 + u;
+        c[u].q = q;
+        c[u].f = f;
+        c[u].b = b;
+        c[u].pad = 0;
+        const bool ok = b <= B - 2 && w4[u] != 0 && wl != 0 && wl != W;
+        c[u].nl = ok ? wl : 0u;
+        c[u].nr = W - wl;
+        c[u].sl = (uint64_t)tl;
+        c[u].sr = (uint64_t)(T - (int64_t)tl);
+        qc[u] = ok ? reg_q64(c[u]) : -1.0;
+        q1 = qc[u] > q1 ? qc[u] : q1;
+    }
+    double qmax = q1;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        const double o = __shfl_xor(qmax, m);
+        qmax = o > qmax ? o : qmax;
+    }
+    Cand lb;
+    lb.nl = 0;
+    lb.b = 0x7FFFFFFF;
+    lb.q = q;
+    lb.f = f;
+    lb.nr = 0;
+    lb.pad = 0;
+    lb.sl = lb.sr = 0;
+    if (qmax < 0.0) return lb;
+    const double floor64 = split_rank ? fp64_floor(qmax) : 0.0;
+    // the lane's finalists in ascending threshold order: a strictly better
+    // one replaces, so ties keep the smaller threshold
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (c[u].nl != 0 && qc[u] >= floor64 && (lb.nl == 0 || reg_better(c[u], lb))) lb = c[u];
+    const unsigned long long finm = __ballot(lb.nl != 0);
+    if (__popcll(finm) == 1) return shfl_cand(lb, (int)__ffsll(finm) - 1);
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        const Cand o = shfl_xor_cand(lb, m);
+        if (reg_wins_same_feature(o, lb)) lb = o;
+    }
+    return lb;
+}
+
+// One regression item: draws q0 .. q0 + nf - 1 of the node, one after the
+// other in the wave's LDS region (256 words of W, then 256 64-bit sums).
+template <int RB>
+__device__ Cand reg_item(const ForestDev& F, const SlotRec& sr, int q0, int nf, const int* fq,
+                         const uint8_t* const* col, uint32_t* hist) {
+    const int lane = threadIdx.x & 63;
+    uint32_t* hw = hist;
+    long long* ht = reinterpret_cast<long long*>(hist + 256);
+    const int64_t T = (int64_t)((uint64_t)sr.cnode[0] | ((uint64_t)sr.cnode[1] << 32));
+    const uint32_t W = sr.n, len = sr.len;
+    const int64_t* yfix = sr.yfix;
+    const uint64_t* recs = sr.recs;
+    Cand best;
+    best.nl = 0;
+    for (int v = 0; v < nf; ++v) {
+        reinterpret_cast<uint4*>(hw)[lane] = make_uint4(0u, 0u, 0u, 0u);
+        reinterpret_cast<uint4*>(ht)[2 * lane] = make_uint4(0u, 0u, 0u, 0u);
+        reinterpret_cast<uint4*>(ht)[2 * lane + 1] = make_uint4(0u, 0u, 0u, 0u);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (uint32_t i0 = 0; i0 < len; i0 += 64 * RB) {
+            uint64_t r[RB];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const uint32_t i = i0 + u * 64 + lane;
+                r[u] = i < len ? ldg(recs + i) : 0ull;
+            }
+            uint32_t b[RB];
+            long long yv[RB];
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                b[u] = ldg(col[v] + rec_row(r[u]));
+                yv[u] = ldg(yfix + rec_row(r[u]));
+            }
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                const uint32_t w = rec_w(r[u]);  // padding rows: w = 0
+                if (w) {
+                    atomicAdd(&hw[b[u]], w);
+                    atomicAdd(reinterpret_cast<unsigned long long*>(&ht[b[u]]),
+                              (unsigned long long)((long long)w * yv[u]));
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const Cand fb = reg_feature_best(hw, ht, (int)sr.B, q0 + v, fq[v], W, T, F.split_rank);
+        // draws in order: a strictly better score replaces
+        if (fb.nl != 0 && (best.nl == 0 || reg_better(fb, best))) best = fb;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the next draw rewrites
+    }
+    return best;
+}
+
 // Large nodes, phase 0: one wavefront per node draws its mtry features
 // (the keyed permutation of the node's heap id, in draw order), resolves
 // their bin columns and writes the node's SlotRec.
@@ -738,12 +873,13 @@ __global__ __launch_bounds__(256) void k_draws(ForestDev F, int level) {
         if (lane < 16) sr->cnode[lane] = lane < J.K ? F.cls[(size_t)id * F.kmax + lane] : 0u;
         if (lane == 0) {
             sr->recs = J.rec[F.parity] + (size_t)tr.tau * J.rstride + nd.seg;
+            sr->yfix = J.reg ? J.yfix : nullptr;
             sr->id = id;
             sr->len = nd.len;
             sr->n = nd.n;
             sr->mtry = (uint32_t)J.mtry;
             sr->B = (uint32_t)J.B;
-            sr->pad = 0;
+            sr->reg = (uint32_t)J.reg;
         }
     }
 }
@@ -797,6 +933,12 @@ __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint3
         for (int u = 0; u < FW; ++u) {
             fq[u] = (int)drawn[u < nf ? u : 0];
             col[u] = dcol[u < nf ? u : 0];
+        }
+        if (sr.reg) {  // a regression job's node (uniform over the wave)
+            const Cand best = reg_item<RB>(F, sr, q0, nf, fq, col, hist);
+            if (lane == 0) F.cand[item] = best;
+            alg += (unsigned long long)sr.len * (unsigned long long)(nf + (j == 0 ? 6 : 0));
+            continue;
         }
 #pragma unroll
         for (int i = 0; i < WORDS / 256; ++i)
@@ -1099,6 +1241,85 @@ __global__ __launch_bounds__(1024) void k_hist_col(ForestDev F, int level) {
                   alg);
 }
 
+// Partition of a split node's first `len` row records in one pass: left rows
+// (bin <= b) from the front in row order, right rows from the back in reverse
+// row order (no result depends on a node's row order, and each child segment
+// stays monotone in row index for the next level's gathers); returns the
+// left rows.  len = 0 when neither child is searched again.
+__device__ uint32_t partition_rows(const ForestDev& F, const JobDev& J, const TreeDev& tr,
+                                   const NodeDev& nd, const SlotRec& sr, const Cand& best,
+                                   uint32_t len) {
+    const int lane = threadIdx.x & 63;
+    const uint8_t* col = ldg(J.colptr + best.f);
+    const uint64_t* recs = sr.recs;
+    uint64_t* rout = J.rec[F.parity ^ 1] + (size_t)tr.tau * J.rstride + nd.seg;
+    constexpr int kR = 8;  // rows per lane per block: lane l owns rows [l kR, l kR + kR)
+    uint32_t runl = 0, runr = 0;
+    for (uint32_t blk = 0; blk < len; blk += 64 * kR) {
+        const uint32_t i0 = blk + (uint32_t)lane * kR;
+        uint64_t r[kR];
+#pragma unroll
+        for (int u = 0; u < kR; ++u) r[u] = i0 + u < len ? ldg(recs + i0 + u) : 0ull;
+        int bb[kR];
+#pragma unroll
+        for (int u = 0; u < kR; ++u) bb[u] = i0 + u < len ? (int)ldg(col + rec_row(r[u])) : 0x7FFF;
+        uint32_t nlm = 0, nrm = 0;
+#pragma unroll
+        for (int u = 0; u < kR; ++u) {
+            nlm += bb[u] <= best.b;
+            nrm += i0 + u < len && bb[u] > best.b;
+        }
+        // exclusive prefix of (left, right) over the lanes, both packed in one
+        // word (a block holds 512 rows)
+        const uint32_t mine = nlm | (nrm << 16);
+        const uint32_t incl = wave_incl_sum(mine);
+        const uint32_t pre = incl - mine;
+        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        uint32_t lrow = runl + (pre & 0xFFFFu), rrow = runr + (pre >> 16);
+#pragma unroll
+        for (int u = 0; u < kR; ++u) {
+            if (i0 + u >= len) break;
+            if (bb[u] <= best.b)
+                rout[lrow++] = r[u];
+            else
+                rout[len - 1 - rrow++] = r[u];
+        }
+        runl += tot & 0xFFFFu;
+        runr += tot >> 16;
+    }
+    return runl;
+}
+
+// Regression form of the split choice and partition: the node's best
+// candidate (exact total order), a split when its gap is nonzero, the rows
+// partitioned as for classification when the children are searched next.
+__device__ void finalize_reg(const ForestDev& F, JobDev& J, const TreeDev& tr, uint32_t slot,
+                             const SlotRec& sr, const NodeDev& nd, Cand c) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        const Cand o = shfl_xor_cand(c, m);
+        if (reg_wins_total(o, c)) c = o;
+    }
+    const Cand best = c;
+    const uint32_t child = F.next_base + 2u * (F.n_small_cur + slot);
+    if (best.nl == 0 || reg_gap(best) == 0) {  // no decrease: stays the leaf it was created as
+        if (lane == 0) {
+            mark_unused_pair(F, child);
+            F.kinds[F.n_small_cur + slot] = 0;
+        }
+        return;
+    }
+    const bool part = (int)nd.depth + 1 < J.D;
+    const uint32_t runl = partition_rows(F, J, tr, nd, sr, best, part ? sr.len : 0u);
+    if (lane == 0) {
+        int kinds[2];
+        split_node_reg(F, J, tr, sr.id, nd, best, runl, reg_gain_fix(best, J.s_gain), child,
+                       kinds);
+        F.kinds[F.n_small_cur + slot] = (uint8_t)(kinds[0] | kinds[1] << 2);
+    }
+}
+
 // Large nodes, phase 2: one wavefront per node (four per workgroup, no
 // barriers).  The node's split is the best of its histogram items' candidates
 // (exact score, then draw position, then threshold); a strictly positive
@@ -1130,6 +1351,7 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
             S += (uint64_t)cnode[c] * cnode[c];
         }
         const uint32_t N = sr.n;
+        const bool reg = sr.reg != 0;  // uniform over the wave
         // rank the items' candidates: each lane keeps the best of its items
         const int ni = ((int)sr.mtry + F.fw - 1) / F.fw;
         Cand c;
@@ -1143,10 +1365,14 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
         int ci = -1;
         for (int t = lane; t < ni; t += 64) {
             const Cand d = F.cand[(size_t)slot * F.npi + t];
-            if (d.nl != 0 && (c.nl == 0 || cand_wins_total(d, c))) {
+            if (d.nl != 0 && (c.nl == 0 || (reg ? reg_wins_total(d, c) : cand_wins_total(d, c)))) {
                 c = d;
                 ci = t;
             }
+        }
+        if (reg) {
+            finalize_reg(F, J, tr, slot, sr, nd, c);
+            continue;
         }
         const Cand best = wave_best_total_exact(c);
         const unsigned long long hit =
@@ -1175,45 +1401,7 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
         // the maximum depth with two or more classes (which implies two or
         // more distinct rows); other children are final leaves.
         const bool part = (int)nd.depth + 1 < J.D && (nzl >= 2 || nzr >= 2);
-        const uint8_t* col = ldg(J.colptr + best.f);
-        const uint64_t* recs = sr.recs;
-        uint64_t* rout = J.rec[F.parity ^ 1] + (size_t)tr.tau * J.rstride + nd.seg;
-        constexpr int kR = 8;  // rows per lane per block: lane l owns rows [l kR, l kR + kR)
-        const uint32_t len = part ? sr.len : 0u;
-        uint32_t runl = 0, runr = 0;
-        for (uint32_t blk = 0; blk < len; blk += 64 * kR) {
-            const uint32_t i0 = blk + (uint32_t)lane * kR;
-            uint64_t r[kR];
-#pragma unroll
-            for (int u = 0; u < kR; ++u) r[u] = i0 + u < len ? ldg(recs + i0 + u) : 0ull;
-            int bb[kR];
-#pragma unroll
-            for (int u = 0; u < kR; ++u)
-                bb[u] = i0 + u < len ? (int)ldg(col + rec_row(r[u])) : 0x7FFF;
-            uint32_t nlm = 0, nrm = 0;
-#pragma unroll
-            for (int u = 0; u < kR; ++u) {
-                nlm += bb[u] <= best.b;
-                nrm += i0 + u < len && bb[u] > best.b;
-            }
-            // exclusive prefix of (left, right) over the lanes, both packed in
-            // one word (a block holds 512 rows)
-            const uint32_t mine = nlm | (nrm << 16);
-            const uint32_t incl = wave_incl_sum(mine);
-            const uint32_t pre = incl - mine;
-            const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-            uint32_t lrow = runl + (pre & 0xFFFFu), rrow = runr + (pre >> 16);
-#pragma unroll
-            for (int u = 0; u < kR; ++u) {
-                if (i0 + u >= len) break;
-                if (bb[u] <= best.b)
-                    rout[lrow++] = r[u];
-                else
-                    rout[len - 1 - rrow++] = r[u];
-            }
-            runl += tot & 0xFFFFu;
-            runr += tot >> 16;
-        }
+        const uint32_t runl = partition_rows(F, J, tr, nd, sr, best, part ? sr.len : 0u);
         if (lane == 0) {
             int kinds[2];
             split_node(F, J, tr, id, nd, best, runl, cl, cr, cand_gain_fix(best, S, N), child,

@@ -25,6 +25,7 @@
 //     by descending historical importance (the mean of the feature's finite
 //     history entries, summed in iteration order; equal means share a rank).
 #include "dev_common.hpp"
+#include "reg_dev.hpp"
 
 namespace boruta {
 
@@ -69,19 +70,24 @@ __global__ __launch_bounds__(256) void k_treeimp(JobDev* jobs, const TreeDev* tr
 // decided, few remain and per-row atomics would all meet on them (with many
 // columns the per-row atomics are spread out and cheaper than a flush per
 // workgroup).  For a regression job a row's score is the negated squared
-// error of its leaf's mean level, sq_error_fix below, and the per-column sums
-// in LDS are 64-bit (a row's drop reaches 2^32).
-// Mean target level of a regression leaf in 1/256 level units: its counts
-// are (255 W - T, T), so floor(256 T / W) = floor(65280 c1 / (c0 + c1)).
-__device__ __forceinline__ long long leaf_level_fix(const uint32_t* cls, int kmax, uint32_t node) {
-    const uint64_t c0 = cls[(size_t)node * kmax], c1 = cls[(size_t)node * kmax + 1];
-    return (long long)((65280ull * c1) / (c0 + c1));
+// error against its leaf's prediction, sq_error_fix below, and the
+// per-column sums in LDS are 64-bit.
+// Prediction of a regression leaf: floor(T / W), T in the node's first two
+// class words and W its weighted count.
+__device__ __forceinline__ long long leaf_pred(const NodeDev* nodes, const uint32_t* cls, int kmax,
+                                               uint32_t node) {
+    const int64_t T = (int64_t)((uint64_t)cls[(size_t)node * kmax] |
+                                ((uint64_t)cls[(size_t)node * kmax + 1] << 32));
+    return (long long)reg_pred(T, nodes[node].n);
 }
 
-__device__ __forceinline__ long long sq_error_fix(const uint32_t* cls, int kmax, uint32_t node,
-                                                  uint32_t level) {
-    const long long e = leaf_level_fix(cls, kmax, node) - 256ll * (long long)level;
-    return e * e;
+// floor((y_fix - pred)^2 / 2^s_perm) (|y_fix - pred| < 2^40).
+__device__ __forceinline__ long long sq_error_fix(const NodeDev* nodes, const uint32_t* cls,
+                                                  int kmax, uint32_t node, long long yfix,
+                                                  int s_perm) {
+    const long long e = yfix - leaf_pred(nodes, cls, kmax, node);
+    const u128 a = (u128)(uint64_t)(e < 0 ? -e : e);
+    return (long long)((a * a) >> s_perm);
 }
 
 __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* trees,
@@ -113,7 +119,8 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
     const bool active = j < m;
     const uint32_t* oob = J.oob + (size_t)tr.tau * J.n;
     const uint32_t row = active ? oob[j] : 0u;
-    const uint32_t yv = J.y[row];
+    const uint32_t yv = reg ? 0u : (uint32_t)J.y[row];
+    const long long yfv = reg ? (long long)J.yfix[row] : 0ll;
     uint32_t* pn = s_path;
     uint32_t* pf = s_path + max_depth * 256;
     int len = 0;
@@ -132,7 +139,7 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
         }
         nv += (unsigned long long)len + 1u;
         if (reg)
-            base_err = sq_error_fix(cls, kmax, node, yv);
+            base_err = sq_error_fix(nodes, cls, kmax, node, yfv, J.s_perm);
         else
             base_ok = nd.leaf_class == yv;
     }
@@ -161,7 +168,7 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
                 ++nv;
             }
             if (reg)
-                drop_sq += sq_error_fix(cls, kmax, nd_i, yv) - base_err;
+                drop_sq += sq_error_fix(nodes, cls, kmax, nd_i, yfv, J.s_perm) - base_err;
             else
                 drop += (int)base_ok - (int)(nd.leaf_class == yv);
         }
@@ -368,8 +375,8 @@ __global__ __launch_bounds__(256) void k_kl_delta(JobDev* jobs, int j, const Nod
         }
         if (ni == leaf0) continue;
         unsigned long long* d = delta + ((size_t)f * rb + rr) * K;
-        if (J.reg) {  // change of the leaf's mean level, in the first slot
-            const long long dv = leaf_level_fix(cls, kmax, ni) - leaf_level_fix(cls, kmax, leaf0);
+        if (J.reg) {  // change of the leaf's prediction, in the first slot
+            const long long dv = leaf_pred(nodes, cls, kmax, ni) - leaf_pred(nodes, cls, kmax, leaf0);
             if (dv) atomicAdd(d, (unsigned long long)dv);
             continue;
         }
@@ -396,12 +403,21 @@ __global__ __launch_bounds__(256) void k_kl_reduce(JobDev* jobs, int j, uint32_t
     const int K = J.K;
     long long kl = 0;
     if (J.reg && f < (uint32_t)J.p_w && rr < rb && r0 + rr < (uint32_t)J.n) {
-        // regression: floor(D^2 / T^2), D the change of the summed leaf levels
+        // regression: floor(D^2 / n_trees^2) >> s_kl, D the change of the summed
+        // leaf predictions (|D| < 2^56); the 128-bit quotient by 32-bit limbs
         unsigned long long* d = delta + ((size_t)f * rb + rr) * K;
         const long long D = (long long)d[0];
         if (D) {
-            const uint64_t a = (uint64_t)(D < 0 ? -D : D), T = (uint64_t)J.T;
-            kl = (long long)((a * a) / (T * T));
+            const uint64_t a = (uint64_t)(D < 0 ? -D : D), T2 = (uint64_t)J.T * (uint64_t)J.T;
+            const u128 num = (u128)a * a;
+            u128 q = 0;
+            uint64_t rem = 0;
+            for (int i = 3; i >= 0; --i) {
+                const uint64_t cur = (rem << 32) | (uint32_t)(num >> (32 * i));
+                q |= (u128)(cur / T2) << (32 * i);
+                rem = cur % T2;
+            }
+            kl = (long long)(q >> J.s_kl);
             d[0] = 0;
         }
     } else if (f < (uint32_t)J.p_w && rr < rb && r0 + rr < (uint32_t)J.n) {
@@ -508,27 +524,29 @@ __global__ __launch_bounds__(256) void k_hits_decide(JobDev* jobs, int perc) {
         const int rank = (int)(((long long)perc * J.n_sha + 99) / 100);  // 1-based
         best = shadow_select(J, rank - 1, s_hist, s_sel);
     }
+    // reported value = ldexp(v / denom, rep_exp): regression scores come back
+    // to squared target units (rep_exp is 0 for classification and TreeImp)
     double denom;
     if (J.mode == 0) {
         denom = (double)total;
-    } else if (J.mode == 2) {  // mean divergence per row, in bits (regression: level^2)
-        denom = (double)J.n * (J.reg ? 65536.0 : 4294967296.0);
+    } else if (J.mode == 2) {  // mean divergence per row, in bits
+        denom = (double)J.n * (J.reg ? 1.0 : 4294967296.0);
     } else {
         long long oob = 0;
         for (int tau = 0; tau < J.T; ++tau) oob += J.tstat[tau * 4 + 1];
         denom = (double)((long long)J.R * oob);
-        if (J.reg) denom *= 65536.0;  // squared errors in 1/65536 level^2 units
     }
+    const int rexp = J.reg ? J.rep_exp : 0;
     double* hrow = J.hist + (size_t)(t - 1) * J.p;
     for (int j = tid; j < J.p; j += 256)
         if (J.state[j] < 0) hrow[j] = __longlong_as_double(0x7FF8000000000000ll);
     for (int c = tid; c < p_cur; c += 256) {
         const int j = J.act[c];
         const long long v = J.imp[c];
-        hrow[j] = denom > 0.0 ? (double)v / denom : 0.0;
+        hrow[j] = denom > 0.0 ? ldexp((double)v / denom, rexp) : 0.0;
         if (v > best) J.hits[j] += 1;
     }
-    if (tid == 0) J.shadow_max[t - 1] = denom > 0.0 ? (double)best / denom : 0.0;
+    if (tid == 0) J.shadow_max[t - 1] = denom > 0.0 ? ldexp((double)best / denom, rexp) : 0.0;
     __syncthreads();
     int und = 0;
     const int hc = J.h_conf[t], hr = J.h_rej[t];

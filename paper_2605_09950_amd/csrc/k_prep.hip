@@ -33,11 +33,10 @@ __global__ void k_validate_reg(const float* X, size_t nx, const float* y, size_t
     if (bad) atomicOr(flags, bad);
 }
 
-// Regression targets to levels 0..255 (reading of the paper's regression
-// forest): floor((y - min) 255 / (max - min) + 1/2) in double, 0 for a
-// constant target.  One workgroup (n <= 65536): the exact minimum and
-// maximum, then the levels.
-__global__ __launch_bounds__(1024) void k_target_levels(const float* y, size_t n, uint8_t* out) {
+// Regression targets (reading of the paper's float-target regressor): the
+// exact minimum and maximum of y (one workgroup), from which the host picks
+// the scale exponent e (every |y| < 2^e) and the fixed-point shifts.
+__global__ __launch_bounds__(1024) void k_target_range(const float* y, size_t n, float* out) {
     __shared__ float s_lo[16], s_hi[16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     float lo = y[0], hi = y[0];
@@ -55,21 +54,24 @@ __global__ __launch_bounds__(1024) void k_target_levels(const float* y, size_t n
         s_hi[wave] = hi;
     }
     __syncthreads();
-    lo = s_lo[0];
-    hi = s_hi[0];
-    for (int v = 1; v < 16; ++v) {
-        lo = fminf(lo, s_lo[v]);
-        hi = fmaxf(hi, s_hi[v]);
-    }
-    const double dlo = (double)lo, range = (double)hi - dlo;
-    for (size_t i = (size_t)tid; i < n; i += 1024) {
-        uint8_t q = 0;
-        if (range > 0.0) {
-            const double v = ((double)y[i] - dlo) * 255.0 / range;
-            q = (uint8_t)floor(v + 0.5);
+    if (tid == 0) {
+        for (int v = 1; v < 16; ++v) {
+            lo = fminf(lo, s_lo[v]);
+            hi = fmaxf(hi, s_hi[v]);
         }
-        out[i] = q;
+        lo = fminf(lo, s_lo[0]);
+        hi = fmaxf(hi, s_hi[0]);
+        out[0] = lo;
+        out[1] = hi;
     }
+}
+
+// y_fix = rint(y 2^sh): an exact power-of-two scaling in double, rounded to
+// the nearest integer (ties to even); |y_fix| < 2^38 for sh = 38 - e.
+__global__ void k_target_fix(const float* y, size_t n, int sh, int64_t* out) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = (int64_t)rint(ldexp((double)y[i], sh));
 }
 
 __global__ void k_labels_u8(const int32_t* y, size_t n, uint8_t* out) {
@@ -428,8 +430,14 @@ void launch_validate_reg(const float* X, size_t nx, const float* y, size_t n, ui
                        0, st, X, nx, y, n, flags);
 }
 
-void launch_target_levels(const float* y, size_t n, uint8_t* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_target_levels, dim3(1), dim3(1024), 0, st, y, n, out);
+void launch_target_range(const float* y, size_t n, float* out2, hipStream_t st) {
+    hipLaunchKernelGGL(k_target_range, dim3(1), dim3(1024), 0, st, y, n, out2);
+}
+
+void launch_target_fix(const float* y, size_t n, int sh, int64_t* out, hipStream_t st) {
+    const size_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_target_fix, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256),
+                       0, st, y, n, sh, out);
 }
 
 void launch_labels(const int32_t* y, size_t n, uint8_t* out, hipStream_t st) {

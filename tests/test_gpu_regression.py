@@ -1,8 +1,8 @@
-"""HIP path vs CPU oracle for the regression forest (TreeImp): tree
-structure, in-bag / OOB counts, integer importances, hits, decisions and
-reported importances are identical.  The device holds each in-bag row as two
-class records (the two-channel encoding of the target level); the oracle
-applies the squared-error rule directly."""
+"""HIP path vs CPU oracle for the regression forest (float targets held as
+exact fixed point, squared-error splits, all three importance modes): tree
+structure (a leaf's prediction floor(T / W) in the trace), in-bag / OOB
+counts, integer importances, hits, decisions and reported importances are
+identical."""
 import numpy as np
 import pytest
 
@@ -17,10 +17,12 @@ def problem(seed, n, p, kind="smooth"):
     rng = np.random.default_rng(seed)
     X = rng.random((n, p)).astype(np.float32)
     y = 3 * X[:, 0] + 2 * np.sin(4 * X[:, 1]) + (X[:, 2] > 0.6) + 0.4 * rng.standard_normal(n)
-    if kind == "ties":  # few distinct targets: many levels 0 and 255, equal scores
+    if kind == "ties":  # few distinct targets: equal scores between thresholds
         y = np.round(y)
-    if kind == "outlier":  # most rows share a few low levels
+    if kind == "outlier":  # one far target: the others use few fixed-point bits
         y[rng.integers(0, n)] = 40.0
+    if kind == "wide":  # negative targets over 60 binades, many rounded in fixed point
+        y = (y - 2.5) * np.exp(rng.uniform(-40, 0, n))
     return X, y.astype(np.float32)
 
 
@@ -36,7 +38,7 @@ def both(X, y, T, D, **kw):
 
 
 @pytest.mark.parametrize("split_rank", [B.RANK_FP32, B.RANK_EXACT], ids=["fp32", "exact"])
-@pytest.mark.parametrize("kind", ["smooth", "ties", "outlier"])
+@pytest.mark.parametrize("kind", ["smooth", "ties", "outlier", "wide"])
 def test_regression_run_matches_oracle(kind, split_rank):
     X, y = problem(41, 900, 11, kind)
     g, o = both(X, y, 9, 9, max_iter=6, seed=12, split_rank=split_rank)
@@ -144,21 +146,21 @@ def test_regression_degenerate_shapes(n, p, D):
         assert_same_run(g, o)
 
 
-def test_regression_at_the_row_limit():
-    # n = 65536, where 255 times a node's bootstrap weight comes closest to
-    # the 2^24 bound of the exact arithmetic
+def test_regression_past_65536_rows():
+    # n = 100,000: the fixed-point sums have no row cap short of n <= 2^24
     rng = np.random.default_rng(51)
-    n, p = 65536, 4
+    n, p = 100000, 4
     X = rng.random((n, p)).astype(np.float32)
     y = (X[:, 0] + 0.1 * rng.standard_normal(n)).astype(np.float32)
-    g, o = both(X, y, 3, 6, max_iter=2, seed=20, n_bins=64)
-    assert_same_run(g, o)
-    root_n = max(int(t["nodes"][t["nodes"][:, 1] == 1, 4].max()) for t in g["traces"])
-    assert root_n == 255 * n  # the root's weighted count: 255 x (the n bootstrap draws)
+    for mode in (B.TREEIMP, B.PERMUT):
+        g, o = both(X, y, 3, 6, importance_mode=mode, max_iter=2, seed=20, n_bins=64)
+        assert_same_run(g, o)
+        root_w = max(int(t["nodes"][t["nodes"][:, 1] == 1, 4].max()) for t in g["traces"])
+        assert root_w == n  # the root's bootstrap weight: the n draws
 
 
 def test_regression_plain_per_node_form_matches_oracle():
-    # the plain form (one launch per tree node) on the two-record layout
+    # the plain form (one launch per tree node)
     X, y = problem(52, 400, 7)
     g = B.boruta_fit_regression(X, y, 4, 6, max_iter=3, seed=21, form=B.FORM_PLAIN, trace=True)
     o = O.boruta_fit_reg(X, y, 4, 6, max_iter=3, seed=21, trace=True)
