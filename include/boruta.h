@@ -327,6 +327,27 @@ int boruta_fit_device(const float* dX, const int32_t* dy, int64_t n, int64_t p,
                       void* hip_stream, int8_t* decision_out, double* imp_history_out,
                       int32_t* hits_out, double* shadow_max_out, int32_t* n_iter_out);
 
+/* boruta_fit_device for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): no workspace argument; the library's own device scratch array
+ * of 64 MiB (a file-scope array that each GPU the library runs on holds until
+ * the process ends) serves as the workspace, and the call makes no hipMalloc,
+ * creates no stream, event or graph and launches eagerly on hip_stream
+ * (nullable = the default stream).  dX [n][p] float32 and dy [n] int32 are
+ * device pointers, outputs host pointers, as in boruta_fit_device; results are
+ * identical to it.  A problem whose boruta_workspace_size exceeds 64 MiB
+ * returns BORUTA_E_INVALID_ARG (with the sizes in boruta_last_error()), and
+ * so do options with kernel statistics (they need HIP events).  Every call on
+ * one GPU uses that GPU's one scratch array: calls that overlap on one GPU (from
+ * several threads or streams) race and give undefined results.  The scratch
+ * keeps the previous call's contents; the call initialises whatever it reads. */
+int boruta_fit_device_noalloc(const float* dX, const int32_t* dy, int64_t n, int64_t p,
+                              int32_t n_classes, int32_t n_trees, int32_t max_depth,
+                              int32_t mtry, int32_t importance_mode, int32_t max_iter,
+                              double alpha, uint64_t seed, const boruta_options* opt,
+                              void* hip_stream, int8_t* decision_out, double* imp_history_out,
+                              int32_t* hits_out, double* shadow_max_out, int32_t* n_iter_out);
+
 /* Incremental form of the same computation: create a session (upload,
  * validation, binning, decision thresholds), then advance every live job
  * one Boruta iteration per boruta_session_step, read results at any time,

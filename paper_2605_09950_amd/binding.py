@@ -88,7 +88,8 @@ class Result(ctypes.Structure):
 
 EXPORTS = ["boruta_default_options", "boruta_fit", "boruta_fit_ex", "boruta_fit_batch",
            "boruta_fit_seeds", "boruta_fit_seeds_regression", "boruta_fit_regression",
-           "boruta_workspace_size", "boruta_fit_device", "boruta_session_create",
+           "boruta_workspace_size", "boruta_fit_device", "boruta_fit_device_noalloc",
+           "boruta_session_create",
            "boruta_session_step", "boruta_session_run", "boruta_session_result",
            "boruta_session_resume", "boruta_bin",
            "boruta_session_destroy", "boruta_probe_copy", "boruta_last_error"]
@@ -141,6 +142,9 @@ def lib():
         L.boruta_fit_device.argtypes = prob + [ctypes.POINTER(Options), P, ctypes.c_size_t, P,
                                                P, P, P, P, P]
         L.boruta_fit_device.restype = ctypes.c_int
+        L.boruta_fit_device_noalloc.argtypes = prob + [ctypes.POINTER(Options), P, P, P, P, P,
+                                                       P]
+        L.boruta_fit_device_noalloc.restype = ctypes.c_int
         L.boruta_session_create.argtypes = [ctypes.POINTER(Job), i32, ctypes.POINTER(Options),
                                             i32, P, ctypes.c_size_t, P,
                                             ctypes.POINTER(ctypes.c_void_p)]
@@ -462,6 +466,35 @@ def boruta_fit_device(dX, dy, n_classes, n_trees, max_depth, workspace, stream=N
     if stats:
         out["stats"] = keep["stats"]
     return out
+
+
+def boruta_fit_device_noalloc(dX, dy, n_classes, n_trees, max_depth, stream=None, mtry=0,
+                              importance_mode=TREEIMP, max_iter=20, alpha=0.05, seed=0,
+                              n_bins=256, n_perm=1, split_rank=RANK_FP32, perc=100,
+                              rough_fix=False):
+    """boruta_fit_device without a workspace: the library's static device
+    scratch serves (see include/boruta.h).  dX [n][p] float32 and dy [n] int32
+    are contiguous torch CUDA tensors."""
+    import torch
+    _check_device_input(dX, "float32", 2, "X")
+    _check_device_input(dy, "int32", 1, "y")
+    n, p = dX.shape
+    st = stream if stream is not None else torch.cuda.current_stream(dX.device)
+    dec = np.zeros(p, np.int8)
+    hist = np.full((max_iter, p), np.nan)
+    hits = np.zeros(p, np.int32)
+    smax = np.full(max_iter, np.nan)
+    n_iter = np.zeros(1, np.int32)
+    opt, _ = make_options(n_bins, n_perm, split_rank, FORM_BATCHED, False, False, p, perc=perc,
+                          rough_fix=rough_fix)
+    rc = lib().boruta_fit_device_noalloc(dX.data_ptr(), dy.data_ptr(), n, p, n_classes,
+                                         n_trees, max_depth, mtry, importance_mode, max_iter,
+                                         alpha, seed, ctypes.byref(opt), st.cuda_stream,
+                                         _ptr(dec), _ptr(hist), _ptr(hits), _ptr(smax),
+                                         _ptr(n_iter))
+    _check(rc)
+    return {"decision": dec, "imp_history": hist, "hits": hits, "shadow_max": smax,
+            "n_iter": int(n_iter[0])}
 
 
 def boruta_bin(X, n_bins=256):

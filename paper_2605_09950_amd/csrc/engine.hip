@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <climits>
 #include <memory>
+#include <mutex>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -126,6 +127,8 @@ struct Opts {
     int small_rows = 32, grid_small = 0, grid_hist = 0, grid_finalize = 0;
     int col_level = 0, col_unit = 512, grid_col = 0, kl_rows = 0;
     int perc = 100, rough_fix = 0;
+    // allocation-free calls: no second stream, no events, no graph
+    bool no_alloc = false;
     boruta_trace_fn trace = nullptr;
     void* trace_user = nullptr;
     boruta_stats* stats = nullptr;
@@ -591,7 +594,7 @@ private:
 
 void Engine::setup(std::vector<int>& status) {
     const int nj = (int)S.size();
-    if (O.form == BORUTA_FORM_BATCHED) {
+    if (O.form == BORUTA_FORM_BATCHED && !O.no_alloc) {
         HIPC(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
         HIPC(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
         HIPC(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
@@ -1253,8 +1256,15 @@ struct Context {
 
 std::unique_ptr<Context> prepare(const std::vector<Spec>& specs, const boruta_options* opt,
                                  bool dev_inputs, void* ws, size_t ws_bytes,
-                                 hipStream_t user_stream) {
-    const Opts o = read_opts(opt);
+                                 hipStream_t user_stream, bool no_alloc = false) {
+    Opts o = read_opts(opt);
+    if (no_alloc) {
+        if (o.stats)
+            throw Error(BORUTA_E_INVALID_ARG,
+                        "kernel statistics need HIP events: not in the allocation-free call");
+        o.no_alloc = true;
+        o.graph = 0;  // launched eagerly: no graph is instantiated
+    }
     for (const Spec& s : specs) {
         check_spec(s);
     }
@@ -1292,10 +1302,11 @@ std::unique_ptr<Context> prepare(const std::vector<Spec>& specs, const boruta_op
 
 int run_jobs(const std::vector<Spec>& specs, const boruta_options* opt, std::vector<Out>& outs,
              std::vector<int>& status, bool dev_inputs, void* ws, size_t ws_bytes,
-             hipStream_t user_stream) {
+             hipStream_t user_stream, bool no_alloc = false) {
     g_err.clear();
     try {
-        std::unique_ptr<Context> c = prepare(specs, opt, dev_inputs, ws, ws_bytes, user_stream);
+        std::unique_ptr<Context> c =
+            prepare(specs, opt, dev_inputs, ws, ws_bytes, user_stream, no_alloc);
         c->eng->run(outs, status);
         HIPC(hipStreamSynchronize(c->st));
         for (int s : status)
@@ -1580,6 +1591,81 @@ int boruta_fit_device(const float* dX, const int32_t* dy, int64_t n, int64_t p,
     std::vector<int> status(1, BORUTA_OK);
     const int rc = run_jobs(specs, opt, outs, status, true, workspace, ws_bytes,
                             (hipStream_t)hip_stream);
+    return finish_single(rc, outs, n_iter_out);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of the allocation-free entry point: a file-scope device array of
+// kScratchBytes that every GPU the library runs on holds until the process
+// ends.  Host code never uses the array's name as an address (on the host it
+// only stands in for the symbol); the device address is taken once per device,
+// with that device current, by hipGetSymbolAddress and kept in g_scratch.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch;  // [device] scratch's device address (null: not yet taken)
+
+void* scratch_address() {
+    int dev = 0;
+    HIPC(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch.size() <= dev) g_scratch.resize((size_t)dev + 1, nullptr);
+    if (!g_scratch[(size_t)dev]) {
+        void* p = nullptr;
+        HIPC(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw Error(BORUTA_E_DEVICE, "hipGetSymbolAddress returned no address");
+        g_scratch[(size_t)dev] = p;
+    }
+    return g_scratch[(size_t)dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+int boruta_fit_device_noalloc(const float* dX, const int32_t* dy, int64_t n, int64_t p,
+                              int32_t n_classes, int32_t n_trees, int32_t max_depth,
+                              int32_t mtry, int32_t importance_mode, int32_t max_iter,
+                              double alpha, uint64_t seed, const boruta_options* opt,
+                              void* hip_stream, int8_t* decision_out, double* imp_history_out,
+                              int32_t* hits_out, double* shadow_max_out, int32_t* n_iter_out) {
+    g_err.clear();
+    if (!decision_out || !imp_history_out || !n_iter_out) {
+        g_err = "decision_out, imp_history_out and n_iter_out must be non-null";
+        return BORUTA_E_INVALID_ARG;
+    }
+    std::vector<Spec> specs{spec_from(dX, dy, n, p, n_classes, n_trees, max_depth, mtry,
+                                      importance_mode, max_iter, alpha, seed)};
+    void* ws = nullptr;
+    try {
+        const Opts o = read_opts(opt);
+        check_spec(specs[0]);
+        require_device();
+        // the problem must fit the scratch (the workspace plan of boruta_fit_device,
+        // plus the alignment slack of its base)
+        const size_t need = make_plan(specs, o, true).total;
+        if (need > kScratchBytes)
+            throw Error(BORUTA_E_INVALID_ARG,
+                        "problem needs " + std::to_string(need) +
+                            " bytes of device scratch; the allocation-free call holds " +
+                            std::to_string(kScratchBytes));
+        ws = scratch_address();
+    } catch (const Error& e) {
+        g_err = e.what();
+        return e.code;
+    }
+    std::vector<Out> outs(1);
+    outs[0].decision = decision_out;
+    outs[0].hist = imp_history_out;
+    outs[0].hits = hits_out;
+    outs[0].smax = shadow_max_out;
+    std::vector<int> status(1, BORUTA_OK);
+    const int rc = run_jobs(specs, opt, outs, status, true, ws, kScratchBytes,
+                            (hipStream_t)hip_stream, true);
     return finish_single(rc, outs, n_iter_out);
 }
 
