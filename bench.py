@@ -472,7 +472,9 @@ def main():
                       graph=False, tune=tune)
         st = leg["stats"]
         print(json.dumps({"profile_leg": args.workload, "steps": leg["steps"], "tune": tune,
+                          "device_iter_ms": round(st.iter_ms / max(1, leg["steps"]), 3),
                           "kernels": {f: {"launches": int(getattr(st, f).launches),
+                                          "ms": round(getattr(st, f).ms, 3),
                                           "alg_bytes_per_launch":
                                               getattr(st, f).alg_bytes /
                                               max(1, getattr(st, f).launches)}

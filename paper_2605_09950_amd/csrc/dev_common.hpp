@@ -120,6 +120,20 @@ __device__ __forceinline__ T ldg(const T* p) {
     return *(const __attribute__((address_space(1))) T*)p;
 }
 
+// Row record i of a node's len >= 1 records, 0 (weight 0) past the end: the
+// load itself is unconditional (clamped to the last record), so a batch of
+// them issues back to back instead of one branch per load.
+__device__ __forceinline__ uint64_t rec_at(const uint64_t* recs, uint32_t i, uint32_t len) {
+    const uint64_t v = ldg(recs + (i < len ? i : len - 1u));
+    return i < len ? v : 0ull;
+}
+// The same load without the mask, for records loaded ahead of their use (a
+// prefetch): the caller masks past-the-end records when it uses them, so the
+// load need not complete at the point of the call.
+__device__ __forceinline__ uint64_t rec_raw(const uint64_t* recs, uint32_t i, uint32_t len) {
+    return ldg(recs + (i < len ? i : len - 1u));
+}
+
 // Wave-uniform values: the compiler cannot see that e.g. threadIdx.x / 64 is
 // the same in every lane; readfirstlane moves such values to scalar registers.
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {

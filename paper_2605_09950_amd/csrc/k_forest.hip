@@ -817,7 +817,7 @@ __device__ Cand reg_item(const ForestDev& F, const SlotRec& sr, int q0, int nf, 
 #pragma unroll
             for (int u = 0; u < RB; ++u) {
                 const uint32_t i = i0 + u * 64 + lane;
-                r[u] = i < len ? ldg(recs + i) : 0ull;
+                r[u] = rec_at(recs, i, len);
             }
             uint32_t b[RB];
             long long yv[RB];
@@ -950,7 +950,7 @@ __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint3
 #pragma unroll
             for (int u = 0; u < RB; ++u) {
                 const uint32_t i = i0 + u * 64 + lane;
-                r[u] = i < len ? ldg(recs + i) : 0ull;
+                r[u] = rec_at(recs, i, len);
             }
             uint32_t b[RB][FW];
 #pragma unroll
@@ -1158,7 +1158,7 @@ __global__ __launch_bounds__(1024) void k_hist_col(ForestDev F, int level) {
 #pragma unroll
                 for (int v = 0; v < RB; ++v) {
                     const uint32_t i = v * 64 + lane;
-                    rn[v] = i < len ? ldg(recs + i) : 0ull;
+                    rn[v] = rec_raw(recs, i, len);
                 }
             }
             for (uint32_t t = 0; t < n_here; ++t) {
@@ -1176,24 +1176,31 @@ __global__ __launch_bounds__(1024) void k_hist_col(ForestDev F, int level) {
 #pragma unroll
                     for (int v = 0; v < RB; ++v) {
                         const uint32_t i = v * 64 + lane;
-                        rn[v] = i < nlen ? ldg(nrecs + i) : 0ull;
+                        rn[v] = rec_raw(nrecs, i, nlen);
                     }
                 }
 #pragma unroll
                 for (int i = 0; i < WORDS / 256; ++i)
                     reinterpret_cast<uint4*>(hist)[i * 64 + lane] = make_uint4(0u, 0u, 0u, 0u);
                 for (uint32_t i0 = 0;;) {
+                    // all bins of the batch first (padding rows read row 0), then
+                    // the atomics: one LDS round trip for the batch, not one per row
+                    // (records past the node's end repeat its last record and are
+                    // masked here)
+                    uint32_t bb[RB];
+#pragma unroll
+                    for (int v = 0; v < RB; ++v) bb[v] = colb[rec_row(r[v])];
 #pragma unroll
                     for (int v = 0; v < RB; ++v) {
-                        const uint32_t w = rec_w(r[v]);  // padding rows: w = 0
-                        if (w) atomicAdd(&hist[rec_y(r[v]) * 256 + colb[rec_row(r[v])]], w);
+                        if (i0 + (uint32_t)(v * 64 + lane) < len)
+                            atomicAdd(&hist[rec_y(r[v]) * 256 + bb[v]], rec_w(r[v]));
                     }
                     i0 += 64 * RB;
                     if (i0 >= len) break;
 #pragma unroll
                     for (int v = 0; v < RB; ++v) {
                         const uint32_t i = i0 + v * 64 + lane;
-                        r[v] = i < len ? ldg(recs + i) : 0ull;
+                        r[v] = rec_raw(recs, i, len);
                     }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
