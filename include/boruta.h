@@ -146,7 +146,7 @@ typedef struct {
                              histograms in one workgroup's LDS; where it does
                              not fit, every level stays node-major.              */
     int32_t col_unit;     /* items (node, draw) per unit of that path, [1, 65536];
-                             default 512                                          */
+                             default 2048                                         */
     int32_t grid_col;     /* workgroups of its histogram launch (one unit at a
                              time, grid-stride); default min(2048, needed)      */
     int32_t kl_rows;      /* BORUTA_PERMUT_KL: rows per block of the divergence

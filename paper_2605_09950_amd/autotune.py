@@ -26,7 +26,7 @@ from paper_2605_09950_amd import binding as B
 # measurements stay comparable between tuned runs.
 CANDIDATES = (
     ("col_level", (64, 5, 3, 7)),
-    ("col_unit", (256, 1024)),
+    ("col_unit", (512, 4096)),
     ("grid_col", (1024, 4096)),
     ("grid_hist", (0, 4096, 32768, 65536)),
     ("grid_small", (0, 1024, 2048, 8192, 16384)),

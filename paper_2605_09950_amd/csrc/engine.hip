@@ -125,7 +125,7 @@ void mark_shared_inputs(std::vector<Spec>& specs) {
 struct Opts {
     int B = 256, R = 1, split_rank = 1, form = 1, graph = 1;
     int small_rows = 32, grid_small = 0, grid_hist = 0, grid_finalize = 0;
-    int col_level = 0, col_unit = 512, grid_col = 0, kl_rows = 0;
+    int col_level = 0, col_unit = 2048, grid_col = 0, kl_rows = 0;
     int perc = 100, rough_fix = 0;
     // allocation-free calls: no second stream, no events, no graph
     bool no_alloc = false;
@@ -1420,7 +1420,7 @@ void boruta_default_options(boruta_options* opt) {
     opt->grid_hist = 0;
     opt->grid_finalize = 0;
     opt->col_level = 0;
-    opt->col_unit = 512;
+    opt->col_unit = 2048;
     opt->grid_col = 0;
     opt->kl_rows = 0;
     opt->perc = 100;

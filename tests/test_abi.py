@@ -36,7 +36,7 @@ def test_default_options():
     o = B.boruta_default_options()
     assert (o.n_bins, o.n_perm, o.split_rank, o.form) == (256, 1, B.RANK_FP32, B.FORM_BATCHED)
     assert (o.graph, o.small_rows, o.grid_small, o.grid_hist, o.grid_finalize) == (1, 32, 0, 0, 0)
-    assert (o.col_level, o.col_unit, o.grid_col, o.kl_rows) == (0, 512, 0, 0)
+    assert (o.col_level, o.col_unit, o.grid_col, o.kl_rows) == (0, 2048, 0, 0)
     assert (o.perc, o.rough_fix) == (100, 0)
     assert not o.trace and not o.stats
 
