@@ -372,6 +372,8 @@ struct ForestDev {
     int32_t fw;           // draws per histogram item
     uint32_t small_rows;  // a node takes the wave path only up to this many distinct rows
     int32_t mtry_cap;     // row stride of feat
+    uint32_t draw_seg;    // lanes per node in k_draws: mtry_cap rounded up to a power
+                          // of two, at most 64
     // column-major histogram path (null when the plan has none)
     uint32_t* fcnt;       // [n_gcol] items per global column, zero between levels
     uint32_t* fpos;       // [slot][mtry_cap] an item's place within its column's items,

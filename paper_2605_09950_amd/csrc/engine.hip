@@ -793,6 +793,8 @@ ForestDev Engine::forest() const {
     }
     F.small_rows = (uint32_t)O.small_rows;
     F.mtry_cap = pl.mtry_cap;
+    F.draw_seg = 1;
+    while (F.draw_seg < (uint32_t)pl.mtry_cap && F.draw_seg < 64u) F.draw_seg <<= 1;
     F.ctrs = at<LevelCtr>(pl.ctrs);
     F.ctr = F.ctrs;
     F.n_roots = (uint32_t)pl.T_total;
@@ -866,7 +868,8 @@ void Engine::enqueue_iteration() {
     const uint32_t g_tile =
         ((O.grid_hist ? (uint32_t)O.grid_hist : level_grid((uint64_t)pl.slot_cap * pl.npi, 4, 16384)) +
          7) / 8 * 8;
-    const uint32_t g_draw = level_grid(pl.slot_cap, 4, 16384);
+    // k_draws serves 64 / draw_seg nodes per wavefront, four wavefronts per workgroup
+    const uint32_t g_draw = level_grid(pl.slot_cap, 4 * (64u / F.draw_seg), 16384);
     const uint32_t g_list = level_grid((uint64_t)pl.small_cap + pl.slot_cap, 4096, 1024);
     const uint32_t g_fin =
         O.grid_finalize ? (uint32_t)O.grid_finalize : level_grid(pl.slot_cap, 4, 4096);
@@ -904,7 +907,7 @@ void Engine::enqueue_iteration() {
             ForestDev Fc = F;
             Fc.col_count = 1;
             launch_draws(Fc, d, g_draw, st);
-            launch_col_sort(F, d, g_draw, st);
+            launch_col_sort(F, d, level_grid(pl.slot_cap, 4, 16384), st);
             h = clock.begin(stats ? &stats->hist_col : nullptr, st);
             launch_hist_col(F, d, g_col, pl.col_waves, pl.gq_max, st);
             HIPC(hipGetLastError());  // a refused launch would leave stale candidates

@@ -845,15 +845,22 @@ __device__ Cand reg_item(const ForestDev& F, const SlotRec& sr, int q0, int nf, 
     return best;
 }
 
-// Large nodes, phase 0: one wavefront per node draws its mtry features
-// (the keyed permutation of the node's heap id, in draw order), resolves
-// their bin columns and writes the node's SlotRec.
+// Large nodes, phase 0: each node's mtry drawn features (the keyed
+// permutation of its heap id, in draw order), their bin columns and the
+// node's slot record.  A wavefront serves 64 / S nodes at once, S = the
+// plan's draws per node rounded up to a power of two (at most 64): lane l
+// takes the draws l mod S, l mod S + S, ... of node l / S, so few draws per
+// node do not leave most of the lanes idle.
 __global__ __launch_bounds__(256) void k_draws(ForestDev F, int level) {
     const uint32_t count = level_slots(F, level);
-    const int lane = threadIdx.x & 63;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t S = F.draw_seg, G = 64u / S;
+    const uint32_t sub = lane / S, ql = lane % S;
     const uint32_t w0 = blockIdx.x * 4u + uniform(threadIdx.x >> 6);
-    for (uint32_t slot = w0; slot < count; slot += gridDim.x * 4u) {
-        const uint32_t id = uniform(F.slot_node_in[slot]);
+    for (uint32_t base = w0 * G; base < count; base += gridDim.x * 4u * G) {
+        const uint32_t slot = base + sub;
+        if (slot >= count) continue;
+        const uint32_t id = F.slot_node_in[slot];
         const NodeDev nd = F.nodes[id];
         const TreeDev tr = F.trees[nd.tree];
         const JobDev& J = F.jobs[tr.job];
@@ -862,16 +869,17 @@ __global__ __launch_bounds__(256) void k_draws(ForestDev F, int level) {
         uint32_t* out = F.feat + (size_t)slot * F.mtry_cap;
         const uint8_t** oc = F.fcol + (size_t)slot * F.mtry_cap;
         uint32_t* pos = F.fpos + (size_t)slot * F.mtry_cap;
-        for (int q = lane; q < J.mtry; q += 64) {
-            const uint32_t f = perm_apply(P, (uint32_t)q);
+        for (uint32_t q = ql; q < (uint32_t)J.mtry; q += S) {
+            const uint32_t f = perm_apply(P, q);
             out[q] = f;
             oc[q] = ldg(J.colptr + f);
             // column-major path: the item's place among its column's items
             if (F.col_count) pos[q] = atomicAdd(F.fcnt + J.gbase + f, 1u);
         }
         SlotRec* sr = F.srec + slot;
-        if (lane < 16) sr->cnode[lane] = lane < J.K ? F.cls[(size_t)id * F.kmax + lane] : 0u;
-        if (lane == 0) {
+        for (uint32_t c = ql; c < 16u; c += S)
+            sr->cnode[c] = c < (uint32_t)J.K ? F.cls[(size_t)id * F.kmax + c] : 0u;
+        if (ql == 0) {
             sr->recs = J.rec[F.parity] + (size_t)tr.tau * J.rstride + nd.seg;
             sr->yfix = J.reg ? J.yfix : nullptr;
             sr->id = id;

@@ -132,12 +132,49 @@ __device__ __forceinline__ double reg_q64(const Cand& c) {
 // FP64 maximum, far above (1 - 2^-40).
 __device__ __forceinline__ double fp64_floor(double qmax) { return qmax * (1.0 - 0x1.0p-40); }
 
+__device__ __forceinline__ double u256_to_double(const U256& a) {
+    return (((double)a.w[3] * 18446744073709551616.0 + (double)a.w[2]) * 18446744073709551616.0 +
+            (double)a.w[1]) * 18446744073709551616.0 + (double)a.w[0];
+}
+
+// floor(num / den) for a quotient below 2^63: an FP64 estimate (relative
+// error a few units of 2^-53), one FP64 correction from the exact 256-bit
+// remainder, then at most a few exact +-1 steps; should those not settle the
+// quotient, the restoring division gives it.
+__device__ inline uint64_t udiv256_128_est(const U256& num, u128 den) {
+    const double dd = u128_to_double(den);
+    double qd = u256_to_double(num) / dd;
+    qd = qd < 9.2e18 ? qd : 9.2e18;
+    uint64_t q = (uint64_t)qd;
+    U256 prod = mul128_full((u128)q, den);
+    const bool over = cmp256(prod, num) > 0;
+    const U256 diff = over ? sub256(prod, num) : sub256(num, prod);
+    const uint64_t c = (uint64_t)(u256_to_double(diff) / dd);
+    q = over ? q - (c < q ? c : q) : q + c;
+    prod = mul128_full((u128)q, den);
+    for (int step = 0; step < 4; ++step) {
+        if (cmp256(prod, num) > 0) {  // q too large
+            --q;
+            prod = sub256(prod, shl128(den, 0));
+            continue;
+        }
+        const U256 next = mul128_full((u128)q + 1, den);
+        if (cmp256(next, num) <= 0) {  // q too small
+            ++q;
+            prod = next;
+            continue;
+        }
+        return q;
+    }
+    return udiv256_128(num, den);
+}
+
 // floor(D / 2^s) = floor(g^2 / (W_L W_R W 2^s)); W_L W_R W 2^s < 2^128 and the
 // quotient < 2^63 for the shifts the engine chooses.
 __device__ inline uint64_t reg_gain_fix(const Cand& c, int s) {
     const u128 g = reg_gap(c);
     const u128 den = ((u128)((uint64_t)c.nl * c.nr) * (c.nl + c.nr)) << s;
-    return udiv256_128(mul128_full(g, g), den);
+    return udiv256_128_est(mul128_full(g, g), den);
 }
 
 // floor(T / W), toward minus infinity.
