@@ -170,6 +170,29 @@ typedef struct {
     boruta_trace_fn trace;/* nullable                                              */
     void* trace_user;
     boruta_stats* stats;  /* nullable                                              */
+    /* Histogram shapes (launch tuning: every choice gives identical results). */
+    int32_t hist_rb;      /* rows per lane per batch of the node-major histogram
+                             kernel at tree levels below band_level (larger
+                             nodes): 4, 8 or 16; default 8                        */
+    int32_t hist_rb_deep; /* the same from band_level on; default 8                */
+    int32_t band_level;   /* first tree level of the deep band, [1, 64]; default 6 */
+    int32_t hist_fw;      /* drawn features per node-major histogram item: 0
+                             (default: 2 for two classes, else 1), 1, 2 or 4;
+                             reduced to at most 8 class rows of LDS per wavefront,
+                             raised to 768 LDS words per wavefront for a batch
+                             with a regression job, and 1 whenever the plan has
+                             column-major levels                                  */
+    int32_t col_waves;    /* wavefronts per workgroup of the column-major kernel,
+                             [2, 16]; 0 (default) = as many as its LDS holds      */
+    const char* tune_cache; /* nullable: path of a tuning cache written by the
+                             project's autotuner (one line per workload: its
+                             signature "B<bins>|R<replicas>" followed, per job, by
+                             "|<n>x<p>K<classes or reg>T<trees>D<depth>m<mtry>
+                             i<mode>", a tab, then "key=value" pairs separated
+                             by spaces, keys among the launch tuning fields
+                             above).  The entry of this call's workload sets every
+                             tuning field left at its default; a missing file or
+                             signature changes nothing.                           */
 } boruta_options;
 
 /* Fills *opt with the defaults above. */

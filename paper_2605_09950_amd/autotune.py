@@ -1,18 +1,22 @@
 """Device-timed search over the launch parameters of the batched form.
 
 The tunable parameters (boruta_options.small_rows, grid_small, grid_hist,
-grid_finalize, col_level, col_unit, grid_col) change only how the work of a
-tree level is spread over workgroups, which of the two split-search paths a
-node takes and which of the two histogram layouts a level uses; every choice
-gives identical results.  The search is a coordinate descent: each
-parameter in turn is set to each of its candidate values, a session over the
-workload is stepped a few times (graph replays, inputs resident on the
-device), and the fastest value is kept.  The outcome can be cached as JSON,
-keyed by a signature of the workload's shapes.
+grid_finalize, col_level, col_unit, grid_col, and the histogram shapes
+hist_rb / hist_rb_deep / band_level -- rows per lane per batch of the
+node-major histogram for the large nodes of the first tree levels and for the
+smaller nodes of the deeper ones --, hist_fw -- drawn features per histogram
+item -- and col_waves -- wavefronts per workgroup of the column-major
+histogram) change only how the work of a tree level is spread over
+workgroups and lanes, which of the two split-search paths a node takes and
+which of the two histogram layouts a level uses; every choice gives identical
+results.  The search is a coordinate descent: each parameter in turn is set
+to each of its candidate values, a session over the workload is stepped a few
+times (graph replays, inputs resident on the device), and the fastest value
+is kept.  The outcome can be cached in a text file, one line per workload
+signature, which the library itself also reads (boruta_options.tune_cache).
 
     tune = autotune(jobs, n_bins=256)             # dict for Session(tune=...)
 """
-import json
 import os
 import time
 
@@ -28,20 +32,52 @@ CANDIDATES = (
     ("col_level", (64, 5, 3, 7)),
     ("col_unit", (512, 4096)),
     ("grid_col", (1024, 4096)),
+    ("col_waves", (8, 12)),
+    ("hist_fw", (1, 2, 4)),
+    ("hist_rb", (4, 16)),
+    ("hist_rb_deep", (4, 16)),
+    ("band_level", (3, 9)),
     ("grid_hist", (0, 4096, 32768, 65536)),
     ("grid_small", (0, 1024, 2048, 8192, 16384)),
     ("grid_finalize", (0, 1024, 2048, 8192)),
 )
+# the library's default of each parameter (boruta_default_options)
+DEFAULTS = {"small_rows": 32, "col_unit": 2048, "hist_rb": 8, "hist_rb_deep": 8,
+            "band_level": 6}
 
 
 def signature(jobs, n_bins=256, n_perm=1):
-    """Shape signature of a workload: what the launch parameters depend on."""
+    """Shape signature of a workload: what the launch parameters depend on (the
+    same string the library computes for boruta_options.tune_cache)."""
     parts = [f"B{n_bins}", f"R{n_perm}"]
     for jd in jobs:
         n, p = jd["X"].shape
-        parts.append(f"{n}x{p}K{jd.get('n_classes', 'reg')}T{jd['n_trees']}D{jd['max_depth']}"
+        k = "reg" if "y_reg" in jd else jd.get("n_classes", 2)
+        parts.append(f"{n}x{p}K{k}T{jd['n_trees']}D{jd['max_depth']}"
                      f"m{jd.get('mtry', 0)}i{jd.get('importance_mode', 0)}")
     return "|".join(parts)
+
+
+def read_cache(path):
+    """{signature: tuning dict} of a cache file (missing file: empty)."""
+    out = {}
+    if not path or not os.path.exists(path):
+        return out
+    with open(path) as f:
+        for line in f:
+            line = line.rstrip("\n")
+            if not line or line.startswith("#") or "\t" not in line:
+                continue
+            sig, kv = line.split("\t", 1)
+            out[sig] = {k: int(v) for k, v in (t.split("=", 1) for t in kv.split() if "=" in t)}
+    return out
+
+
+def write_cache(path, entries):
+    with open(path, "w") as f:
+        f.write("# launch tuning cache: workload signature, tab, key=value pairs\n")
+        for sig, tune in sorted(entries.items()):
+            f.write(sig + "\t" + " ".join(f"{k}={v}" for k, v in sorted(tune.items())) + "\n")
 
 
 def _time_session(dev_jobs, shapes, n_bins, n_perm, tune, steps, warmup):
@@ -79,11 +115,9 @@ def autotune(jobs, n_bins=256, n_perm=1, steps=3, warmup=2, cache=None, log=None
     receives the number of timed sessions and their times."""
     import torch
     sig = signature(jobs, n_bins, n_perm)
-    if cache and os.path.exists(cache):
-        with open(cache) as f:
-            stored = json.load(f)
-        if sig in stored:
-            return dict(stored[sig]["tune"])
+    stored = read_cache(cache)
+    if sig in stored:
+        return dict(stored[sig])
     dev, shapes = [], []
     for jd in jobs:
         d = dict(jd)
@@ -100,7 +134,7 @@ def autotune(jobs, n_bins=256, n_perm=1, steps=3, warmup=2, cache=None, log=None
     trials = [({}, best_ms)]
     for key, values in ((SMALL_ROWS,) if tune_small_rows else ()) + CANDIDATES:
         for v in values:
-            if best.get(key, 0 if key != "small_rows" else 32) == v:
+            if best.get(key, DEFAULTS.get(key, 0)) == v:
                 continue
             cand = dict(best, **{key: v})
             ms = _time_session(dev, shapes, n_bins, n_perm, cand, steps, warmup)
@@ -113,12 +147,7 @@ def autotune(jobs, n_bins=256, n_perm=1, steps=3, warmup=2, cache=None, log=None
         report["sessions"] = len(trials)
         report["trials"] = [{"tune": t, "ms_per_step": round(m, 4)} for t, m in trials]
     if cache:
-        stored = {}
-        if os.path.exists(cache):
-            with open(cache) as f:
-                stored = json.load(f)
-        stored[sig] = {"tune": best, "ms_per_step": best_ms,
-                       "trials": [{"tune": t, "ms_per_step": m} for t, m in trials]}
-        with open(cache, "w") as f:
-            json.dump(stored, f, indent=1)
+        stored = read_cache(cache)
+        stored[sig] = best
+        write_cache(cache, stored)
     return best

@@ -67,7 +67,10 @@ class Options(ctypes.Structure):
                 ("kl_rows", ctypes.c_int32),
                 ("perc", ctypes.c_int32), ("rough_fix", ctypes.c_int32),
                 ("trace", TRACE_FN), ("trace_user", ctypes.c_void_p),
-                ("stats", ctypes.POINTER(Stats))]
+                ("stats", ctypes.POINTER(Stats)),
+                ("hist_rb", ctypes.c_int32), ("hist_rb_deep", ctypes.c_int32),
+                ("band_level", ctypes.c_int32), ("hist_fw", ctypes.c_int32),
+                ("col_waves", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
 
 
 class Job(ctypes.Structure):
@@ -217,7 +220,8 @@ def _trace_collector(store, p, keep_iters=None):
 
 
 TUNE_KEYS = ("small_rows", "grid_small", "grid_hist", "grid_finalize", "col_level", "col_unit",
-             "grid_col", "kl_rows")
+             "grid_col", "kl_rows", "hist_rb", "hist_rb_deep", "band_level", "hist_fw",
+             "col_waves")
 
 
 def make_options(n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED, trace=False,
@@ -231,10 +235,14 @@ def make_options(n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED, 
     o.graph = int(bool(graph))
     o.perc, o.rough_fix = int(perc), int(bool(rough_fix))
     for k, v in (tune or {}).items():
+        if k == "tune_cache":  # a path (see include/boruta.h)
+            keep_cache = str(v).encode()
+            o.tune_cache = keep_cache
+            continue
         if k not in TUNE_KEYS:
             raise ValueError(f"unknown tuning key {k}")
         setattr(o, k, int(v))
-    keep = {"iters": []}
+    keep = {"iters": [], "cache_path": o.tune_cache}
     if callable(trace):
         keep["sink"] = trace
         keep["cb"] = _trace_collector(keep, p, None)

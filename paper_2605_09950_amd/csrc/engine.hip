@@ -12,6 +12,8 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -127,6 +129,10 @@ struct Opts {
     int small_rows = 32, grid_small = 0, grid_hist = 0, grid_finalize = 0;
     int col_level = 0, col_unit = 2048, grid_col = 0, kl_rows = 0;
     int perc = 100, rough_fix = 0;
+    // histogram shapes: rows per lane per batch of the node-major kernel before
+    // and from band_level on, its draws per item, and the waves per workgroup
+    // of the column-major kernel (0 = the library's choice)
+    int hist_rb = 8, hist_rb_deep = 8, band_level = 6, hist_fw = 0, col_waves = 0;
     // allocation-free calls: no second stream, no events, no graph
     bool no_alloc = false;
     boruta_trace_fn trace = nullptr;
@@ -152,6 +158,11 @@ Opts read_opts(const boruta_options* o) {
         r.kl_rows = o->kl_rows;
         if (o->perc) r.perc = o->perc;
         r.rough_fix = o->rough_fix;
+        if (o->hist_rb) r.hist_rb = o->hist_rb;
+        if (o->hist_rb_deep) r.hist_rb_deep = o->hist_rb_deep;
+        if (o->band_level) r.band_level = o->band_level;
+        r.hist_fw = o->hist_fw;
+        r.col_waves = o->col_waves;
         r.trace = o->trace;
         r.trace_user = o->trace_user;
         r.stats = o->stats;
@@ -177,7 +188,101 @@ Opts read_opts(const boruta_options* o) {
     if (r.perc < 1 || r.perc > 100) throw Error(BORUTA_E_INVALID_ARG, "perc outside [1, 100]");
     if (r.rough_fix != 0 && r.rough_fix != 1)
         throw Error(BORUTA_E_INVALID_ARG, "rough_fix must be 0 or 1");
+    auto rb_ok = [](int v) { return v == 4 || v == 8 || v == 16; };
+    if (!rb_ok(r.hist_rb) || !rb_ok(r.hist_rb_deep))
+        throw Error(BORUTA_E_INVALID_ARG, "hist_rb and hist_rb_deep must be 4, 8 or 16");
+    if (r.band_level < 1 || r.band_level > 64)
+        throw Error(BORUTA_E_INVALID_ARG, "band_level outside [1, 64]");
+    if (r.hist_fw != 0 && r.hist_fw != 1 && r.hist_fw != 2 && r.hist_fw != 4)
+        throw Error(BORUTA_E_INVALID_ARG, "hist_fw must be 0, 1, 2 or 4");
+    if (r.col_waves < 0 || r.col_waves > (int)kColWavesMax)
+        throw Error(BORUTA_E_INVALID_ARG, "col_waves outside [0, 16]");
     return r;
+}
+
+// Workload signature of a tuning cache entry: "B<bins>|R<replicas>" and, per
+// job, "|<n>x<p>K<classes or reg>T<trees>D<depth>m<mtry>i<mode>".
+std::string tune_signature(const std::vector<Spec>& specs, const Opts& o) {
+    std::string sig = "B" + std::to_string(o.B) + "|R" + std::to_string(o.R);
+    for (const Spec& s : specs)
+        sig += "|" + std::to_string(s.n) + "x" + std::to_string(s.p) + "K" +
+               (s.yr ? std::string("reg") : std::to_string(s.K)) + "T" + std::to_string(s.T) +
+               "D" + std::to_string(s.D) + "m" + std::to_string(s.mtry) + "i" +
+               std::to_string(s.mode);
+    return sig;
+}
+
+// The tuning cache's entry for this workload sets every launch tuning field
+// that the caller left at its default (boruta_default_options); the values are
+// validated as the caller's would be.  A missing file or signature changes
+// nothing.
+void apply_tune_cache(Opts& r, const boruta_options* o, const std::vector<Spec>& specs) {
+    if (!o || !o->tune_cache) return;
+    std::ifstream in(o->tune_cache);
+    if (!in) return;
+    const std::string sig = tune_signature(specs, r);
+    boruta_options d;
+    boruta_default_options(&d);
+    std::string line;
+    while (std::getline(in, line)) {
+        const size_t tab = line.find('\t');
+        if (line.empty() || line[0] == '#' || tab == std::string::npos) continue;
+        if (line.compare(0, tab, sig) != 0 || tab != sig.size()) continue;
+        std::istringstream kv(line.substr(tab + 1));
+        std::string tok;
+        while (kv >> tok) {
+            const size_t eq = tok.find('=');
+            if (eq == std::string::npos) continue;
+            const std::string key = tok.substr(0, eq);
+            int v = 0;
+            try {
+                v = std::stoi(tok.substr(eq + 1));
+            } catch (...) {
+                continue;
+            }
+            // a field the caller left at its default takes the cached value
+#define BORUTA_TUNE_FIELD(name)                                        \
+    if (key == #name) {                                                 \
+        if (o->name == d.name) r.name = v;                              \
+        continue;                                                       \
+    }
+            BORUTA_TUNE_FIELD(small_rows)
+            BORUTA_TUNE_FIELD(grid_small)
+            BORUTA_TUNE_FIELD(grid_hist)
+            BORUTA_TUNE_FIELD(grid_finalize)
+            BORUTA_TUNE_FIELD(col_level)
+            BORUTA_TUNE_FIELD(col_unit)
+            BORUTA_TUNE_FIELD(grid_col)
+            BORUTA_TUNE_FIELD(kl_rows)
+            BORUTA_TUNE_FIELD(hist_rb)
+            BORUTA_TUNE_FIELD(hist_rb_deep)
+            BORUTA_TUNE_FIELD(band_level)
+            BORUTA_TUNE_FIELD(hist_fw)
+            BORUTA_TUNE_FIELD(col_waves)
+#undef BORUTA_TUNE_FIELD
+        }
+        break;
+    }
+    // a cached value must pass the checks the caller's value would
+    boruta_options c = *o;
+    c.small_rows = r.small_rows;
+    c.grid_small = r.grid_small;
+    c.grid_hist = r.grid_hist;
+    c.grid_finalize = r.grid_finalize;
+    c.col_level = r.col_level;
+    c.col_unit = r.col_unit;
+    c.grid_col = r.grid_col;
+    c.kl_rows = r.kl_rows;
+    c.hist_rb = r.hist_rb;
+    c.hist_rb_deep = r.hist_rb_deep;
+    c.band_level = r.band_level;
+    c.hist_fw = r.hist_fw;
+    c.col_waves = r.col_waves;
+    c.tune_cache = nullptr;
+    const Opts checked = read_opts(&c);
+    const bool no_alloc = r.no_alloc;
+    r = checked;
+    r.no_alloc = no_alloc;
 }
 
 void check_spec(const Spec& s) {
@@ -378,11 +483,23 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
         if (col + 2 * per_wave <= kLdsPerWorkgroup) {
             pl.col_level = col_level;
             pl.col_waves = (int)std::min<size_t>(kColWavesMax, (kLdsPerWorkgroup - col) / per_wave);
+            if (o.col_waves >= 2) pl.col_waves = std::min(pl.col_waves, o.col_waves);
         }
     }
     // histogram items per large node: fw draws each (the column-major path
-    // takes one draw per item, and both paths then share that layout)
-    pl.fw = pl.col_level < pl.max_D ? 1 : hist_fw(pl.kmax);
+    // takes one draw per item, and both paths then share that layout).  A
+    // chosen hist_fw is kept within 8 class rows of LDS per wave, and a plan
+    // with a regression job keeps at least 768 words per wave (its items hold
+    // 256 weights and 256 64-bit sums); none of this changes any result.
+    if (pl.col_level < pl.max_D) {
+        pl.fw = 1;
+    } else {
+        int fw = o.hist_fw ? o.hist_fw : hist_fw(pl.kmax);
+        while (fw > 1 && fw * pl.kmax > 8) fw >>= 1;
+        if (any_reg)
+            while (fw * pl.kmax * 256 < 768) fw <<= 1;
+        pl.fw = fw;
+    }
     pl.npi = (pl.mtry_cap + pl.fw - 1) / pl.fw;
     if (node_cap >= 0xFFFFFFF0ull || slot_cap * (uint64_t)pl.mtry_cap + n_gcol >= 0xFFFFFFF0ull ||
         small_cap >= 0xFFFFFFF0ull)
@@ -820,7 +937,8 @@ void Engine::grow_level_plain(const ForestDev& F, int level) {
     for (uint32_t i = 0; i < c.n_small; ++i) launch_split_small(F, level, i, 1, 1, st);
     if (c.n_slots) launch_draws(F, level, 1, st);
     for (uint32_t sl = 0; sl < c.n_slots; ++sl) {
-        launch_hist_tile(F, level, sl * pl.npi, pl.npi, (pl.npi + 3) / 4, O.B, st);
+        launch_hist_tile(F, level, sl * pl.npi, pl.npi, (pl.npi + 3) / 4,
+                         level < O.band_level ? O.hist_rb : O.hist_rb_deep, st);
         launch_split_finalize(F, level, sl, 1, 1, st);
     }
     const uint32_t chunks = (c.n_small + c.n_slots + 4095) / 4096;
@@ -915,7 +1033,8 @@ void Engine::enqueue_iteration() {
         } else {
             launch_draws(F, d, g_draw, st);
             h = clock.begin(stats ? &stats->hist_large : nullptr, st);
-            launch_hist_tile(F, d, 0, kAll, g_tile, O.B, st);
+            launch_hist_tile(F, d, 0, kAll, g_tile, d < O.band_level ? O.hist_rb : O.hist_rb_deep,
+                             st);
             clock.end(h, st);
         }
         h = clock.begin(stats ? &stats->finalize : nullptr, st);
@@ -1261,6 +1380,7 @@ std::unique_ptr<Context> prepare(const std::vector<Spec>& specs, const boruta_op
                                  bool dev_inputs, void* ws, size_t ws_bytes,
                                  hipStream_t user_stream, bool no_alloc = false) {
     Opts o = read_opts(opt);
+    apply_tune_cache(o, opt, specs);
     if (no_alloc) {
         if (o.stats)
             throw Error(BORUTA_E_INVALID_ARG,
@@ -1431,6 +1551,12 @@ void boruta_default_options(boruta_options* opt) {
     opt->trace = nullptr;
     opt->trace_user = nullptr;
     opt->stats = nullptr;
+    opt->hist_rb = 8;
+    opt->hist_rb_deep = 8;
+    opt->band_level = 6;
+    opt->hist_fw = 0;
+    opt->col_waves = 0;
+    opt->tune_cache = nullptr;
 }
 
 int boruta_fit_ex(const float* X, const int32_t* y, int64_t n, int64_t p, int32_t n_classes,
@@ -1558,8 +1684,9 @@ int boruta_workspace_size(const boruta_job* jobs, int32_t n_jobs, const boruta_o
         return BORUTA_E_INVALID_ARG;
     }
     try {
-        const Opts o = read_opts(opt);
+        Opts o = read_opts(opt);
         std::vector<Spec> specs = specs_of(jobs, n_jobs);
+        apply_tune_cache(o, opt, specs);
         for (const Spec& s : specs) {
             if (s.n < 2 || s.n > (int64_t(1) << 24) || s.p < 1 || s.p > (int64_t(1) << 24) ||
                 s.T < 1 || s.D < 1 || s.D > 30 || s.max_iter < 1 || s.max_iter > 1000 ||
@@ -1645,7 +1772,8 @@ int boruta_fit_device_noalloc(const float* dX, const int32_t* dy, int64_t n, int
                                       importance_mode, max_iter, alpha, seed)};
     void* ws = nullptr;
     try {
-        const Opts o = read_opts(opt);
+        Opts o = read_opts(opt);
+        apply_tune_cache(o, opt, specs);
         check_spec(specs[0]);
         require_device();
         // the problem must fit the scratch (the workspace plan of boruta_fit_device,

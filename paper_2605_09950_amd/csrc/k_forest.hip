@@ -730,8 +730,9 @@ __device__ __forceinline__ long long wave_excl_sum64(long long x) {
     return incl - x;
 }
 
-__device__ Cand reg_feature_best(const uint32_t* hw, const long long* ht, int B, int q, int f,
-                                 uint32_t W, int64_t T, int split_rank) {
+__device__ __forceinline__ Cand reg_feature_best(const uint32_t* hw, const long long* ht, int B,
+                                                 int q, int f, uint32_t W, int64_t T,
+                                                 int split_rank) {
     const int lane = threadIdx.x & 63;
     const uint4 wv = reinterpret_cast<const uint4*>(hw)[lane];
     const uint32_t w4[4] = {wv.x, wv.y, wv.z, wv.w};
@@ -796,8 +797,9 @@ __device__ Cand reg_feature_best(const uint32_t* hw, const long long* ht, int B,
 // One regression item: draws q0 .. q0 + nf - 1 of the node, one after the
 // other in the wave's LDS region (256 words of W, then 256 64-bit sums).
 template <int RB>
-__device__ Cand reg_item(const ForestDev& F, const SlotRec& sr, int q0, int nf, const int* fq,
-                         const uint8_t* const* col, uint32_t* hist) {
+__device__ __forceinline__ Cand reg_item(const ForestDev& F, const SlotRec& sr, int q0, int nf,
+                                         const int* fq, const uint8_t* const* col,
+                                         uint32_t* hist) {
     const int lane = threadIdx.x & 63;
     uint32_t* hw = hist;
     long long* ht = reinterpret_cast<long long*>(hist + 256);
@@ -899,11 +901,12 @@ __global__ __launch_bounds__(256) void k_draws(ForestDev F, int level) {
 // spread a wave's atomics over the banks by bin), scans each feature and
 // writes the item's best candidate and its left class counts.  No barriers:
 // the four waves of a workgroup are independent.
-template <int KMAX, int FW>
+template <int KMAX, int FW, int RB>
 __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint32_t first,
                                                    uint32_t count) {
+    // RB rows per lane per batch: RB record loads and RB * FW bin gathers in
+    // flight (a launch tuning choice; every RB gives the same histograms)
     constexpr int WORDS = FW * KMAX * 256;
-    constexpr int RB = 8;  // rows per lane per batch: RB record loads, RB * FW gathers in flight
     extern __shared__ uint4 lds_raw[];
     const int lane = threadIdx.x & 63, wave = (int)uniform(threadIdx.x >> 6);
     uint32_t* hist = reinterpret_cast<uint32_t*>(lds_raw) + wave * WORDS;
@@ -1560,19 +1563,34 @@ void launch_draws(const ForestDev& F, int level, uint32_t grid_wg, hipStream_t s
     hipLaunchKernelGGL(k_draws, dim3(grid_wg), dim3(256), 0, st, F, level);
 }
 
+template <int KMAX, int FW>
+static void launch_tile_rb(const ForestDev& F, int level, uint32_t first, uint32_t count,
+                           dim3 grid, size_t lds, int rb, hipStream_t st) {
+    switch (rb) {
+        case 4: hipLaunchKernelGGL((k_hist_tile<KMAX, FW, 4>), grid, dim3(256), lds, st, F, level, first, count); break;
+        case 16: hipLaunchKernelGGL((k_hist_tile<KMAX, FW, 16>), grid, dim3(256), lds, st, F, level, first, count); break;
+        default: hipLaunchKernelGGL((k_hist_tile<KMAX, FW, 8>), grid, dim3(256), lds, st, F, level, first, count); break;
+    }
+}
+
+// rb: rows per lane per batch (4, 8 or 16); F.fw draws per item with
+// F.fw * F.kmax <= 8 (the engine validates both).
 void launch_hist_tile(const ForestDev& F, int level, uint32_t first, uint32_t count,
-                      uint32_t grid_wg, int B, hipStream_t st) {
+                      uint32_t grid_wg, int rb, hipStream_t st) {
     if (!count) return;
     // four waves of fw * KMAX * 256 words
     const size_t lds = (size_t)4 * F.fw * F.kmax * 256 * sizeof(uint32_t);
     const dim3 grid(grid_wg);
-    switch (F.kmax * 4 + F.fw) {
-        case 2 * 4 + 2: hipLaunchKernelGGL((k_hist_tile<2, 2>), grid, dim3(256), lds, st, F, level, first, count); break;
-        case 2 * 4 + 1: hipLaunchKernelGGL((k_hist_tile<2, 1>), grid, dim3(256), lds, st, F, level, first, count); break;
-        case 3 * 4 + 1: hipLaunchKernelGGL((k_hist_tile<3, 1>), grid, dim3(256), lds, st, F, level, first, count); break;
-        case 4 * 4 + 1: hipLaunchKernelGGL((k_hist_tile<4, 1>), grid, dim3(256), lds, st, F, level, first, count); break;
-        case 8 * 4 + 1: hipLaunchKernelGGL((k_hist_tile<8, 1>), grid, dim3(256), lds, st, F, level, first, count); break;
-        default: hipLaunchKernelGGL((k_hist_tile<16, 1>), grid, dim3(256), lds, st, F, level, first, count); break;
+    switch (F.kmax * 8 + F.fw) {
+        case 2 * 8 + 4: launch_tile_rb<2, 4>(F, level, first, count, grid, lds, rb, st); break;
+        case 2 * 8 + 2: launch_tile_rb<2, 2>(F, level, first, count, grid, lds, rb, st); break;
+        case 2 * 8 + 1: launch_tile_rb<2, 1>(F, level, first, count, grid, lds, rb, st); break;
+        case 3 * 8 + 2: launch_tile_rb<3, 2>(F, level, first, count, grid, lds, rb, st); break;
+        case 3 * 8 + 1: launch_tile_rb<3, 1>(F, level, first, count, grid, lds, rb, st); break;
+        case 4 * 8 + 2: launch_tile_rb<4, 2>(F, level, first, count, grid, lds, rb, st); break;
+        case 4 * 8 + 1: launch_tile_rb<4, 1>(F, level, first, count, grid, lds, rb, st); break;
+        case 8 * 8 + 1: launch_tile_rb<8, 1>(F, level, first, count, grid, lds, rb, st); break;
+        default: launch_tile_rb<16, 1>(F, level, first, count, grid, lds, rb, st); break;
     }
 }
 
