@@ -281,7 +281,7 @@ def kernel_code_digest():
     summary in profiles/ stays valid."""
     import hashlib
     lines = []
-    for name in ("k_forest.hip", "forest_dev.hpp", "dev_common.hpp"):
+    for name in ("k_forest.hip", "forest_dev.hpp", "dev_common.hpp", "reg_dev.hpp"):
         with open(os.path.join(ROOT, "paper_2605_09950_amd", "csrc", name)) as f:
             for line in f:
                 code = line.split("//", 1)[0].rstrip()

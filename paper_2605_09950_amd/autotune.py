@@ -110,7 +110,8 @@ SMALL_ROWS = ("small_rows", (32, 64, 48, 16))
 def autotune(jobs, n_bins=256, n_perm=1, steps=3, warmup=2, cache=None, log=None, report=None,
              tune_small_rows=False):
     """Returns the fastest tuning dict for `jobs` (host arrays, as for
-    boruta_fit_batch).  With `cache` (a JSON file path) a stored result for
+    boruta_fit_batch).  With `cache` (a tuning cache file, the format
+    boruta_options.tune_cache reads) a stored result for
     the same signature is reused and a new one is stored.  `report` (a dict)
     receives the number of timed sessions and their times."""
     import torch

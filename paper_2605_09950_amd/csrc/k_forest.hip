@@ -956,21 +956,29 @@ __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint3
             reinterpret_cast<uint4*>(hist)[i * 64 + lane] = make_uint4(0u, 0u, 0u, 0u);
         const uint64_t* recs = sr.recs;
         const uint32_t len = sr.len;
+        // record batches stream one ahead of the bin gathers that need them
+        uint64_t rn[RB];
+#pragma unroll
+        for (int u = 0; u < RB; ++u) rn[u] = rec_raw(recs, u * 64 + lane, len);
         for (uint32_t i0 = 0; i0 < len; i0 += 64 * RB) {
             uint64_t r[RB];
 #pragma unroll
-            for (int u = 0; u < RB; ++u) {
-                const uint32_t i = i0 + u * 64 + lane;
-                r[u] = rec_at(recs, i, len);
-            }
+            for (int u = 0; u < RB; ++u) r[u] = rn[u];
             uint32_t b[RB][FW];
 #pragma unroll
             for (int u = 0; u < RB; ++u)
 #pragma unroll
                 for (int v = 0; v < FW; ++v) b[u][v] = ldg(col[v] + rec_row(r[u]));
+            const uint32_t i1 = i0 + 64 * RB;
+            if (i1 < len) {
+#pragma unroll
+                for (int u = 0; u < RB; ++u) rn[u] = rec_raw(recs, i1 + u * 64 + lane, len);
+            }
 #pragma unroll
             for (int u = 0; u < RB; ++u) {
-                const uint32_t w = rec_w(r[u]), y = rec_y(r[u]);  // padding rows: w = 0
+                // records past the node's end repeat its last record: masked
+                const uint32_t w = i0 + (uint32_t)(u * 64 + lane) < len ? rec_w(r[u]) : 0u;
+                const uint32_t y = rec_y(r[u]);
 #pragma unroll
                 for (int v = 0; v < FW; ++v)
                     if (v < nf && w) atomicAdd(&hist[(v * KMAX + y) * 256 + b[u][v]], w);
@@ -1160,8 +1168,10 @@ __global__ __launch_bounds__(1024) void k_hist_col(ForestDev F, int level) {
 #pragma unroll
             for (int c = 0; c < KMAX; ++c) my_cn[c] = have ? msr->cnode[c] : 0u;
             const uint32_t n_here = min(64u, (cu.end - k0 + nw - 1u) / nw);
-            // the first record batch of the next item is loaded while this
-            // item is counted and scanned
+            // Record batches stream one ahead: while a batch is counted, the
+            // next one is in flight -- the item's next batch, or after its
+            // last batch the first batch of the wave's next item (hidden
+            // behind that item's scan).
             uint64_t rn[RB];
             {
                 const uint64_t* recs = reinterpret_cast<const uint64_t*>(readlane64(my_recs, 0));
@@ -1177,42 +1187,37 @@ __global__ __launch_bounds__(1024) void k_hist_col(ForestDev F, int level) {
                 const uint32_t q = item - (item / mc) * mc;
                 const uint64_t* recs = reinterpret_cast<const uint64_t*>(readlane64(my_recs, (int)t));
                 const uint32_t len = readlane_w(my_len, (int)t);
-                uint64_t r[RB];
-#pragma unroll
-                for (int v = 0; v < RB; ++v) r[v] = rn[v];
-                if (t + 1 < n_here) {
-                    const uint64_t* nrecs =
-                        reinterpret_cast<const uint64_t*>(readlane64(my_recs, (int)t + 1));
-                    const uint32_t nlen = readlane_w(my_len, (int)t + 1);
-#pragma unroll
-                    for (int v = 0; v < RB; ++v) {
-                        const uint32_t i = v * 64 + lane;
-                        rn[v] = rec_raw(nrecs, i, nlen);
-                    }
-                }
 #pragma unroll
                 for (int i = 0; i < WORDS / 256; ++i)
                     reinterpret_cast<uint4*>(hist)[i * 64 + lane] = make_uint4(0u, 0u, 0u, 0u);
                 for (uint32_t i0 = 0;;) {
-                    // all bins of the batch first (padding rows read row 0), then
-                    // the atomics: one LDS round trip for the batch, not one per row
-                    // (records past the node's end repeat its last record and are
-                    // masked here)
+                    uint64_t r[RB];
+#pragma unroll
+                    for (int v = 0; v < RB; ++v) r[v] = rn[v];
+                    // all bins of the batch first (records past the node's end
+                    // repeat its last record and are masked below), then the
+                    // atomics: one LDS round trip for the batch, not one per row
                     uint32_t bb[RB];
 #pragma unroll
                     for (int v = 0; v < RB; ++v) bb[v] = colb[rec_row(r[v])];
+                    const uint32_t i1 = i0 + 64 * RB;
+                    if (i1 < len) {
+#pragma unroll
+                        for (int v = 0; v < RB; ++v) rn[v] = rec_raw(recs, i1 + v * 64 + lane, len);
+                    } else if (t + 1 < n_here) {
+                        const uint64_t* nrecs =
+                            reinterpret_cast<const uint64_t*>(readlane64(my_recs, (int)t + 1));
+                        const uint32_t nlen = readlane_w(my_len, (int)t + 1);
+#pragma unroll
+                        for (int v = 0; v < RB; ++v) rn[v] = rec_raw(nrecs, v * 64 + lane, nlen);
+                    }
 #pragma unroll
                     for (int v = 0; v < RB; ++v) {
                         if (i0 + (uint32_t)(v * 64 + lane) < len)
                             atomicAdd(&hist[rec_y(r[v]) * 256 + bb[v]], rec_w(r[v]));
                     }
-                    i0 += 64 * RB;
-                    if (i0 >= len) break;
-#pragma unroll
-                    for (int v = 0; v < RB; ++v) {
-                        const uint32_t i = i0 + v * 64 + lane;
-                        r[v] = rec_raw(recs, i, len);
-                    }
+                    if (i1 >= len) break;
+                    i0 = i1;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 uint32_t cnode[KMAX];

@@ -80,6 +80,20 @@ def test_parity_cases(case, mode, path):
     assert_same_run(g, o)
 
 
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("case", CASES, ids=[str(c[0]) for c in CASES])
+def test_plain_form_matches_oracle(case, mode):
+    # the plain form (one launch per tree node: histogram, then split and
+    # partition, per large node) against the oracle directly
+    seed, n, p, K, T, D, kw = case
+    kw = dict(kw)
+    X, y = problem(seed, n, p, K, kw.pop("kind", "normal"))
+    extra = dict(n_perm=2) if mode == 1 else {}
+    g, o = both(X, y, K, T, D, importance_mode=mode, seed=200 + seed, form=B.FORM_PLAIN,
+                **extra, **kw)
+    assert_same_run(g, o)
+
+
 def test_many_classes_and_tiny_n():
     X, y = problem(12, 3000, 20, 16)
     for tune in PATHS.values():
