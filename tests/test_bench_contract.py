@@ -56,7 +56,7 @@ def test_digest_ignores_comments_and_blank_lines(tmp_path, monkeypatch):
     src = os.path.join(bench.ROOT, "paper_2605_09950_amd", "csrc")
     dst = tmp_path / "paper_2605_09950_amd" / "csrc"
     dst.mkdir(parents=True)
-    for name in ("k_forest.hip", "forest_dev.hpp", "dev_common.hpp"):
+    for name in ("k_forest.hip", "forest_dev.hpp", "dev_common.hpp", "reg_dev.hpp"):
         shutil.copy(os.path.join(src, name), dst / name)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     d0 = bench.kernel_code_digest()
