@@ -322,6 +322,9 @@ __device__ __forceinline__ uint32_t rec_row(uint64_t r) { return (uint32_t)r; }
 __device__ __forceinline__ uint32_t rec_w(uint64_t r) { return (uint32_t)(r >> 32) & 0xFFFFu; }
 __device__ __forceinline__ uint32_t rec_y(uint64_t r) { return (uint32_t)(r >> 48) & 0xFFu; }
 
+// k_col_count: columns counted in LDS (64 KB) and its workgroups
+constexpr uint32_t kColCountLds = 16384;
+constexpr uint32_t kColCountGrid = 512;
 constexpr int kSmallRows = 64;  // nodes with at most this many distinct rows take the wave path
 constexpr int kWave = 64;
 constexpr uint32_t kAlgWords = 1024;  // statistics words per kernel
@@ -382,7 +385,8 @@ struct ForestDev {
     uint32_t* fitems;     // [slot * mtry_cap] items sorted by column
     ColUnit* units;       // [unit_cap]
     uint32_t n_gcol, unit_cap, col_unit;  // columns, unit capacity, items per unit
-    int32_t col_count;    // this level takes the column path: k_draws counts items
+    int32_t col_count;    // this level takes the column path: its items' places in their
+                          // columns are counted by k_draws (1) or k_col_count (2)
 };
 
 }  // namespace boruta

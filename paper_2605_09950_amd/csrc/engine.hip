@@ -1023,9 +1023,9 @@ void Engine::enqueue_iteration() {
         if (col) {
             // items bucketed by column, one LDS-staged column per unit
             ForestDev Fc = F;
-            Fc.col_count = 1;
+            Fc.col_count = pl.n_gcol <= kColCountLds ? 2 : 1;
             launch_draws(Fc, d, g_draw, st);
-            launch_col_sort(F, d, level_grid(pl.slot_cap, 4, 16384), st);
+            launch_col_sort(Fc, d, level_grid(pl.slot_cap, 4, 16384), st);
             h = clock.begin(stats ? &stats->hist_col : nullptr, st);
             launch_hist_col(F, d, g_col, pl.col_waves, pl.gq_max, st);
             HIPC(hipGetLastError());  // a refused launch would leave stale candidates

@@ -875,8 +875,9 @@ __global__ __launch_bounds__(256) void k_draws(ForestDev F, int level) {
             const uint32_t f = perm_apply(P, q);
             out[q] = f;
             oc[q] = ldg(J.colptr + f);
-            // column-major path: the item's place among its column's items
-            if (F.col_count) pos[q] = atomicAdd(F.fcnt + J.gbase + f, 1u);
+            // column-major path without k_col_count: the item's place among
+            // its column's items
+            if (F.col_count == 1) pos[q] = atomicAdd(F.fcnt + J.gbase + f, 1u);
         }
         SlotRec* sr = F.srec + slot;
         for (uint32_t c = ql; c < 16u; c += S)
@@ -1107,6 +1108,47 @@ __global__ __launch_bounds__(256) void k_col_scan(ForestDev F, int level) {
     if (tid == 0) {
         if (tu > F.unit_cap) atomicOr(&F.ctrs[level].overflow, 16u);
         F.ctrs[level].n_units = min(tu, F.unit_cap);
+    }
+}
+
+// k_col_count: the items' places within their columns, counted per workgroup
+// in LDS.  Workgroup w takes a contiguous run of the level's node slots,
+// ranks each item among the workgroup's items of its column (LDS atomics),
+// reserves one run per touched column in the global per-column counts (one
+// global atomic per column and workgroup, not one per item), then adds the
+// run's start to its items' places.  The places of a column's items are
+// unique and dense; their order is immaterial.
+__global__ __launch_bounds__(256) void k_col_count(ForestDev F, int level) {
+    extern __shared__ uint32_t lcnt[];  // [n_gcol]
+    const uint32_t count = level_slots(F, level);
+    const uint32_t G = F.n_gcol;
+    const uint32_t per = (count + gridDim.x - 1u) / gridDim.x;
+    const uint32_t s0 = min(count, blockIdx.x * per), s1 = min(count, s0 + per);
+    if (s0 >= s1) return;  // the whole workgroup: no barrier is skipped by part of it
+    for (uint32_t g = threadIdx.x; g < G; g += blockDim.x) lcnt[g] = 0u;
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u, wave = uniform(threadIdx.x >> 6);
+    for (uint32_t slot = s0 + wave; slot < s1; slot += 4u) {
+        const SlotRec& sr = F.srec[slot];
+        const NodeDev nd = F.nodes[uniform(sr.id)];
+        const uint32_t gb = F.jobs[F.trees[nd.tree].job].gbase;
+        const size_t row = (size_t)slot * F.mtry_cap;
+        for (uint32_t q = lane; q < sr.mtry; q += 64u)
+            F.fpos[row + q] = atomicAdd(&lcnt[gb + F.feat[row + q]], 1u);
+    }
+    __syncthreads();
+    for (uint32_t g = threadIdx.x; g < G; g += blockDim.x) {
+        const uint32_t c = lcnt[g];
+        lcnt[g] = c ? atomicAdd(F.fcnt + g, c) : 0u;
+    }
+    __syncthreads();
+    for (uint32_t slot = s0 + wave; slot < s1; slot += 4u) {
+        const SlotRec& sr = F.srec[slot];
+        const NodeDev nd = F.nodes[uniform(sr.id)];
+        const uint32_t gb = F.jobs[F.trees[nd.tree].job].gbase;
+        const size_t row = (size_t)slot * F.mtry_cap;
+        for (uint32_t q = lane; q < sr.mtry; q += 64u)
+            F.fpos[row + q] += lcnt[gb + F.feat[row + q]];
     }
 }
 
@@ -1603,7 +1645,11 @@ size_t hist_col_lds(int kmax, int waves, uint32_t gq_max) {
     return (size_t)waves * kmax * 256 * sizeof(uint32_t) + (size_t)gq_max * 16;
 }
 
+// F.col_count == 2: the places are counted by k_col_count (n_gcol <= kColCountLds)
 void launch_col_sort(const ForestDev& F, int level, uint32_t grid_wg, hipStream_t st) {
+    if (F.col_count == 2)
+        hipLaunchKernelGGL(k_col_count, dim3(kColCountGrid), dim3(256),
+                           (size_t)F.n_gcol * sizeof(uint32_t), st, F, level);
     hipLaunchKernelGGL(k_col_scan, dim3(1), dim3(256), 0, st, F, level);
     hipLaunchKernelGGL(k_col_scatter, dim3(grid_wg), dim3(256), 0, st, F, level);
 }
