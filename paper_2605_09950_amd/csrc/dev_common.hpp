@@ -371,6 +371,7 @@ struct ForestDev {
     uint32_t n_small_cur; // small nodes searched in this level
     uint32_t small_ncap;  // a node takes the wave path only below this weighted count
     int32_t kmax, parity, split_rank;
+    int32_t has_cls, has_reg;  // the plan holds classification / regression jobs
     int32_t npi;          // histogram items per large node (draw positions / fw)
     int32_t fw;           // draws per histogram item
     uint32_t small_rows;  // a node takes the wave path only up to this many distinct rows

@@ -375,6 +375,7 @@ struct Plan {
         npi = 1, fw = 1;
     // column-major histogram path: levels >= col_level (col_level >= max_D: none)
     int col_level = kColNever, col_waves = 0;
+    bool has_cls = false, has_reg = false;
     uint32_t n_gcol = 0, unit_cap = 0, gq_max = 0;
     int64_t max_n = 0;
     size_t total = 0;
@@ -471,7 +472,11 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     // with a regression job stays node-major: its items need the node-major
     // item layout (an LDS region of at least 768 words per wave).
     bool any_reg = false;
-    for (const Spec& s : specs) any_reg |= s.yr != nullptr;
+    for (const Spec& s : specs) {
+        any_reg |= s.yr != nullptr;
+        pl.has_cls |= s.yr == nullptr;
+    }
+    pl.has_reg = any_reg;
     int col_level = any_reg ? kColNever : o.col_level;
     if (col_level == 0) {
         size_t widest = 0;
@@ -921,6 +926,8 @@ ForestDev Engine::forest() const {
     F.small_cap = pl.small_cap;
     F.kmax = pl.kmax;
     F.split_rank = O.split_rank;
+    F.has_cls = pl.has_cls ? 1 : 0;
+    F.has_reg = pl.has_reg ? 1 : 0;
     // the wave path packs class counters in 32/kmax-bit fields up to 4 classes
     // (16-bit for 2, 10-bit for 3, 8-bit for 4), 16-bit fields beyond
     F.small_ncap = pl.kmax == 4 ? 256u : (pl.kmax == 3 ? 1024u : 65536u);

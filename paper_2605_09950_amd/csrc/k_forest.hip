@@ -902,6 +902,81 @@ __global__ __launch_bounds__(256) void k_draws(ForestDev F, int level) {
 // spread a wave's atomics over the banks by bin), scans each feature and
 // writes the item's best candidate and its left class counts.  No barriers:
 // the four waves of a workgroup are independent.
+// Work of a level for the node-major histogram kernels: node slots [0, n)
+// with npi items each.  Workgroup b takes the slots congruent to b mod 8 (the
+// grid is a multiple of 8), and its waves walk those slots' items in order,
+// so a node's items run side by side in one XCD and share its records
+// through that XCD's L2 when the hardware deals workgroups round-robin to the
+// 8 XCDs (any mapping gives the same results: every item is visited once).
+// With an explicit count, items [first, first + count) are walked directly
+// (plain form).
+struct ItemWalk {
+    bool dyn;
+    uint32_t x, r, R, m_end, first, npi;
+    __device__ ItemWalk(const ForestDev& F, int level, uint32_t first_, uint32_t count,
+                        uint32_t wave) {
+        npi = (uint32_t)F.npi;
+        first = first_;
+        dyn = count == 0xFFFFFFFFu;
+        x = 0;
+        r = blockIdx.x * 4u + wave;
+        R = gridDim.x * 4u;
+        m_end = count;
+        if (dyn) {
+            const uint32_t n_slots = level_slots(F, level);
+            x = blockIdx.x % 8u;
+            r = (blockIdx.x / 8u) * 4u + wave;
+            R = (gridDim.x / 8u) * 4u;
+            m_end = n_slots > x ? (n_slots - x + 7u) / 8u * npi : 0u;
+        }
+    }
+    __device__ uint32_t item(uint32_t cur) const {
+        return dyn ? (8u * (cur / npi) + x) * npi + cur % npi : first + cur;
+    }
+};
+
+// Regression nodes of the node-major levels: one wavefront per (node, F.fw
+// consecutive draws) item, the histograms and scan of reg_item in the wave's
+// LDS region (F.fw * F.kmax * 256 words, at least 768).  Items of
+// classification nodes are left to k_hist_tile, which in turn skips these:
+// the regression item's registers and code stay out of the classification
+// kernel.
+template <int RB>
+__global__ __launch_bounds__(256) void k_hist_reg(ForestDev F, int level, uint32_t first,
+                                                  uint32_t count) {
+    extern __shared__ uint4 lds_raw[];
+    const int lane = threadIdx.x & 63, wave = (int)uniform(threadIdx.x >> 6);
+    const int fw = F.fw;
+    uint32_t* hist = reinterpret_cast<uint32_t*>(lds_raw) + (size_t)wave * fw * F.kmax * 256;
+    const ItemWalk wk(F, level, first, count, (uint32_t)wave);
+    unsigned long long alg = 0;
+    for (uint32_t cur = wk.r; cur < wk.m_end; cur += wk.R) {
+        const uint32_t item = wk.item(cur);
+        const uint32_t slot = item / wk.npi, j = item % wk.npi;
+        const SlotRec& sr = F.srec[slot];
+        if (!sr.reg) continue;  // a classification node: k_hist_tile
+        const int q0 = (int)j * fw;
+        const int mtry = (int)sr.mtry;
+        if (q0 >= mtry) continue;  // the job draws fewer features this iteration
+        const int nf = min(fw, mtry - q0);
+        const uint32_t* drawn = F.feat + (size_t)slot * F.mtry_cap + q0;
+        const uint8_t* const* dcol = F.fcol + (size_t)slot * F.mtry_cap + q0;
+        int fq[4];
+        const uint8_t* col[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            fq[u] = (int)drawn[u < nf ? u : 0];
+            col[u] = dcol[u < nf ? u : 0];
+        }
+        const Cand best = reg_item<RB>(F, sr, q0, nf, fq, col, hist);
+        if (lane == 0) F.cand[item] = best;
+        alg += (unsigned long long)sr.len * (unsigned long long)(nf + (j == 0 ? 6 : 0));
+    }
+    if (F.alg_bytes && lane == 0 && alg)
+        atomicAdd((unsigned long long*)&F.alg_bytes[(blockIdx.x * 4u + wave) & (kAlgWords - 1)],
+                  alg);
+}
+
 template <int KMAX, int FW, int RB>
 __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint32_t first,
                                                    uint32_t count) {
@@ -911,28 +986,14 @@ __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint3
     extern __shared__ uint4 lds_raw[];
     const int lane = threadIdx.x & 63, wave = (int)uniform(threadIdx.x >> 6);
     uint32_t* hist = reinterpret_cast<uint32_t*>(lds_raw) + wave * WORDS;
-    const uint32_t npi = (uint32_t)F.npi;
-    // Work of a level: node slots [0, n) with npi items each.  Workgroup b
-    // takes the slots congruent to b mod 8 (the grid is a multiple of 8), and
-    // its waves walk those slots' items in order, so a node's items run side
-    // by side in one XCD and share its records through that XCD's L2 when the
-    // hardware deals workgroups round-robin to the 8 XCDs (any mapping gives
-    // the same results: every item is visited once).  With an explicit count,
-    // items [first, first + count) are walked directly (plain form).
-    const bool dyn = count == 0xFFFFFFFFu;
-    uint32_t x = 0, r = blockIdx.x * 4u + (uint32_t)wave, R = gridDim.x * 4u, m_end = count;
-    if (dyn) {
-        const uint32_t n_slots = level_slots(F, level);
-        x = blockIdx.x % 8u;
-        r = (blockIdx.x / 8u) * 4u + (uint32_t)wave;
-        R = (gridDim.x / 8u) * 4u;
-        m_end = n_slots > x ? (n_slots - x + 7u) / 8u * npi : 0u;
-    }
+    const ItemWalk wk(F, level, first, count, (uint32_t)wave);
+    const uint32_t npi = wk.npi;
     unsigned long long alg = 0;
-    for (uint32_t cur = r; cur < m_end; cur += R) {
-        const uint32_t item = dyn ? (8u * (cur / npi) + x) * npi + cur % npi : first + cur;
+    for (uint32_t cur = wk.r; cur < wk.m_end; cur += wk.R) {
+        const uint32_t item = wk.item(cur);
         const uint32_t slot = item / npi, j = item % npi;
         const SlotRec& sr = F.srec[slot];
+        if (sr.reg) continue;  // a regression node: k_hist_reg
         const int q0 = (int)j * FW;
         const int mtry = (int)sr.mtry;
         if (q0 >= mtry) continue;  // the job draws fewer features this iteration
@@ -946,40 +1007,28 @@ __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint3
             fq[u] = (int)drawn[u < nf ? u : 0];
             col[u] = dcol[u < nf ? u : 0];
         }
-        if (sr.reg) {  // a regression job's node (uniform over the wave)
-            const Cand best = reg_item<RB>(F, sr, q0, nf, fq, col, hist);
-            if (lane == 0) F.cand[item] = best;
-            alg += (unsigned long long)sr.len * (unsigned long long)(nf + (j == 0 ? 6 : 0));
-            continue;
-        }
 #pragma unroll
         for (int i = 0; i < WORDS / 256; ++i)
             reinterpret_cast<uint4*>(hist)[i * 64 + lane] = make_uint4(0u, 0u, 0u, 0u);
         const uint64_t* recs = sr.recs;
         const uint32_t len = sr.len;
-        // record batches stream one ahead of the bin gathers that need them
-        uint64_t rn[RB];
-#pragma unroll
-        for (int u = 0; u < RB; ++u) rn[u] = rec_raw(recs, u * 64 + lane, len);
+        // (loading the next batch's records ahead of this batch's gathers was
+        // measured slower here: the other waves of the SIMD hide the latency)
         for (uint32_t i0 = 0; i0 < len; i0 += 64 * RB) {
             uint64_t r[RB];
 #pragma unroll
-            for (int u = 0; u < RB; ++u) r[u] = rn[u];
+            for (int u = 0; u < RB; ++u) {
+                const uint32_t i = i0 + u * 64 + lane;
+                r[u] = i < len ? ldg(recs + i) : 0ull;
+            }
             uint32_t b[RB][FW];
 #pragma unroll
             for (int u = 0; u < RB; ++u)
 #pragma unroll
                 for (int v = 0; v < FW; ++v) b[u][v] = ldg(col[v] + rec_row(r[u]));
-            const uint32_t i1 = i0 + 64 * RB;
-            if (i1 < len) {
-#pragma unroll
-                for (int u = 0; u < RB; ++u) rn[u] = rec_raw(recs, i1 + u * 64 + lane, len);
-            }
 #pragma unroll
             for (int u = 0; u < RB; ++u) {
-                // records past the node's end repeat its last record: masked
-                const uint32_t w = i0 + (uint32_t)(u * 64 + lane) < len ? rec_w(r[u]) : 0u;
-                const uint32_t y = rec_y(r[u]);
+                const uint32_t w = rec_w(r[u]), y = rec_y(r[u]);  // padding rows: w = 0
 #pragma unroll
                 for (int v = 0; v < FW; ++v)
                     if (v < nf && w) atomicAdd(&hist[(v * KMAX + y) * 256 + b[u][v]], w);
@@ -1392,6 +1441,41 @@ __device__ void finalize_reg(const ForestDev& F, JobDev& J, const TreeDev& tr, u
 // rows from the front in row order, right rows from the back in reverse row
 // order.  No result depends on the order of a node's rows, and each child
 // segment stays monotone in row index for the next level's gathers.
+// Phase 2 for the regression nodes of a level (k_split_finalize skips them,
+// so that the 256-bit arithmetic stays out of the classification kernel).
+__global__ __launch_bounds__(256) void k_split_finalize_reg(ForestDev F0, int level,
+                                                            uint32_t first, uint32_t count) {
+    const ForestDev F = level_view(F0, level);
+    if (count == 0xFFFFFFFFu) {
+        first = 0;
+        count = level_slots(F0, level);
+    }
+    const int lane = threadIdx.x & 63, wave = (int)uniform(threadIdx.x >> 6);
+    for (uint32_t k = blockIdx.x * 4u + (uint32_t)wave; k < count; k += gridDim.x * 4u) {
+        const uint32_t slot = first + k;
+        const SlotRec& sr = F.srec[slot];
+        if (!sr.reg) continue;  // a classification node: k_split_finalize
+        const NodeDev nd = F.nodes[sr.id];
+        const TreeDev tr = F.trees[nd.tree];
+        JobDev& J = F.jobs[tr.job];
+        // rank the items' candidates: each lane keeps the best of its items
+        const int ni = ((int)sr.mtry + F.fw - 1) / F.fw;
+        Cand c;
+        c.nl = 0;
+        c.q = 0x7FFFFFFF;
+        c.b = 0x7FFFFFFF;
+        c.f = 0;
+        c.nr = 0;
+        c.pad = 0;
+        c.sl = c.sr = 0;
+        for (int t = lane; t < ni; t += 64) {
+            const Cand d = F.cand[(size_t)slot * F.npi + t];
+            if (d.nl != 0 && (c.nl == 0 || reg_wins_total(d, c))) c = d;
+        }
+        finalize_reg(F, J, tr, slot, sr, nd, c);
+    }
+}
+
 template <int KMAX>
 __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level, uint32_t first,
                                                         uint32_t count) {
@@ -1404,6 +1488,7 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
     for (uint32_t k = blockIdx.x * 4u + (uint32_t)wave; k < count; k += gridDim.x * 4u) {
         const uint32_t slot = first + k;
         const SlotRec& sr = F.srec[slot];
+        if (sr.reg) continue;  // a regression node: k_split_finalize_reg
         const uint32_t id = sr.id;
         const NodeDev nd = F.nodes[id];
         const TreeDev tr = F.trees[nd.tree];
@@ -1416,7 +1501,6 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
             S += (uint64_t)cnode[c] * cnode[c];
         }
         const uint32_t N = sr.n;
-        const bool reg = sr.reg != 0;  // uniform over the wave
         // rank the items' candidates: each lane keeps the best of its items
         const int ni = ((int)sr.mtry + F.fw - 1) / F.fw;
         Cand c;
@@ -1430,14 +1514,10 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
         int ci = -1;
         for (int t = lane; t < ni; t += 64) {
             const Cand d = F.cand[(size_t)slot * F.npi + t];
-            if (d.nl != 0 && (c.nl == 0 || (reg ? reg_wins_total(d, c) : cand_wins_total(d, c)))) {
+            if (d.nl != 0 && (c.nl == 0 || cand_wins_total(d, c))) {
                 c = d;
                 ci = t;
             }
-        }
-        if (reg) {
-            finalize_reg(F, J, tr, slot, sr, nd, c);
-            continue;
         }
         const Cand best = wave_best_total_exact(c);
         const unsigned long long hit =
@@ -1621,13 +1701,23 @@ static void launch_tile_rb(const ForestDev& F, int level, uint32_t first, uint32
 }
 
 // rb: rows per lane per batch (4, 8 or 16); F.fw draws per item with
-// F.fw * F.kmax <= 8 (the engine validates both).
+// F.fw * F.kmax <= 8 (the engine validates both).  Regression items run in
+// k_hist_reg, classification items in k_hist_tile: two launches over the
+// same items for a plan holding both kinds of job.
 void launch_hist_tile(const ForestDev& F, int level, uint32_t first, uint32_t count,
                       uint32_t grid_wg, int rb, hipStream_t st) {
     if (!count) return;
     // four waves of fw * KMAX * 256 words
     const size_t lds = (size_t)4 * F.fw * F.kmax * 256 * sizeof(uint32_t);
     const dim3 grid(grid_wg);
+    if (F.has_reg) {
+        switch (rb) {
+            case 4: hipLaunchKernelGGL((k_hist_reg<4>), grid, dim3(256), lds, st, F, level, first, count); break;
+            case 16: hipLaunchKernelGGL((k_hist_reg<16>), grid, dim3(256), lds, st, F, level, first, count); break;
+            default: hipLaunchKernelGGL((k_hist_reg<8>), grid, dim3(256), lds, st, F, level, first, count); break;
+        }
+    }
+    if (!F.has_cls) return;
     switch (F.kmax * 8 + F.fw) {
         case 2 * 8 + 4: launch_tile_rb<2, 4>(F, level, first, count, grid, lds, rb, st); break;
         case 2 * 8 + 2: launch_tile_rb<2, 2>(F, level, first, count, grid, lds, rb, st); break;
@@ -1685,6 +1775,9 @@ void launch_split_finalize(const ForestDev& F, int level, uint32_t first, uint32
                            uint32_t grid_wg, hipStream_t st) {
     if (!count) return;
     const dim3 grid(grid_wg);
+    if (F.has_reg)
+        hipLaunchKernelGGL(k_split_finalize_reg, grid, dim3(256), 0, st, F, level, first, count);
+    if (!F.has_cls) return;
     switch (F.kmax) {
         case 2: hipLaunchKernelGGL(k_split_finalize<2>, grid, dim3(256), 0, st, F, level, first, count); break;
         case 3: hipLaunchKernelGGL(k_split_finalize<3>, grid, dim3(256), 0, st, F, level, first, count); break;

@@ -14,6 +14,10 @@ Parts (each writes tests/golden/<part>.json):
   iter1_omics        omics-shaped n=2,000, p=20,000: iteration 1, all 500 trees
   iter1_scale        mixed-type n=100,000, p=2,000: iteration 1, all 300 trees,
                      TreeImp and Permut with five replicas
+  wholerun_omics     omics-shaped n=2,000, p=20,000: the whole TreeImp run
+  iters4_scale       mixed-type n=100,000, p=2,000: TreeImp iterations 1..4
+                     (a run stopped at max_iter = 4)
+  wholerun_scale     mixed-type n=100,000, p=2,000: the whole TreeImp run
 """
 import json
 import os
@@ -84,6 +88,25 @@ def part(name, threads):
         for mode, n_perm in ((0, 1), (1, 5)):
             out["legs"].append(first_iteration(c, mode, n_perm, threads))
             print(name, "mode", mode, f"{time.time() - t0:.0f}s", flush=True)
+    elif name == "wholerun_omics":
+        c = synth.config(2)
+        out = {"workload": "omics-shaped n=2000 p=20000 K=2, 256 bins, 500 trees depth 12",
+               "seed": c["seed"],
+               "runs": {"0": whole_run(c["X"], c["y"], c["n_classes"], c["params"], c["seed"],
+                                       0, threads)}}
+    elif name == "iters4_scale":
+        c = synth.config(4)
+        pr = dict(c["params"], max_iter=4)
+        out = {"workload": "mixed-type n=100000 p=2000 K=4, 256 bins, 300 trees depth 16",
+               "seed": c["seed"], "max_iter": 4,
+               "runs": {"0": whole_run(c["X"], c["y"], c["n_classes"], pr, c["seed"], 0,
+                                       threads)}}
+    elif name == "wholerun_scale":
+        c = synth.config(4)
+        out = {"workload": "mixed-type n=100000 p=2000 K=4, 256 bins, 300 trees depth 16",
+               "seed": c["seed"],
+               "runs": {"0": whole_run(c["X"], c["y"], c["n_classes"], c["params"], c["seed"],
+                                       0, threads)}}
     else:
         raise SystemExit(f"unknown part {name}")
     out["oracle_seconds"] = round(time.time() - t0, 1)

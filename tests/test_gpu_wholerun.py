@@ -11,7 +11,8 @@ iterations replayed from the captured graph.
   * the 64-job batch: every job's whole run, all jobs in one session;
   * omics-shaped n=2,000, p=20,000 and mixed-type n=100,000, p=2,000: the
     whole first iteration (every tree), both ranking modes; mixed-type also
-    with Permut and five replicas.
+    with Permut and five replicas;
+  * omics-shaped: the whole TreeImp run; mixed-type: TreeImp iterations 1-4.
 """
 import json
 import os
@@ -158,3 +159,28 @@ def test_scale_first_iteration(leg_i, rank):
     dig, res = run_session([job(c, leg["mode"])], 256, n_perm=leg["n_perm"], rank=rank, steps=1)
     compare_iterations(dig[0], leg["iterations"], f"mixed-type iteration 1 mode {leg['mode']}")
     assert res[0]["hits"].tolist() == leg["hits"]
+
+
+@pytest.mark.parametrize("rank", [B.RANK_FP32, B.RANK_EXACT])
+def test_omics_whole_run(rank):
+    g = golden("wholerun_omics")
+    want = g["runs"]["0"]
+    c = synth.config(2)
+    print(f"omics whole run rank {rank}", flush=True)
+    dig, res = run_session([job(c, 0)], c["params"]["n_bins"], rank=rank)
+    compare_iterations(dig[0], want["iterations"], "omics whole run")
+    compare_run(res[0], want, "omics whole run")
+
+
+@pytest.mark.parametrize("rank", [B.RANK_FP32, B.RANK_EXACT])
+def test_scale_first_four_iterations(rank):
+    # a run stopped at max_iter = 4: decisions, hits, rank and history of the
+    # truncated run, and every iteration's trace digest
+    g = golden("iters4_scale")
+    want = g["runs"]["0"]
+    c = synth.config(4)
+    jd = dict(job(c, 0), max_iter=g["max_iter"])
+    print(f"mixed-type iterations 1-4 rank {rank}", flush=True)
+    dig, res = run_session([jd], c["params"]["n_bins"], rank=rank)
+    compare_iterations(dig[0], want["iterations"], "mixed-type iterations 1-4")
+    compare_run(res[0], want, "mixed-type iterations 1-4")
