@@ -1519,7 +1519,10 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
                 ci = t;
             }
         }
-        const Cand best = wave_best_total_exact(c);
+        // FP32 ranking with the exact recheck of the finalists (as in the
+        // histogram scans), or exact throughout
+        const Cand best = F.split_rank ? wave_best_total_fp32(c, c.nl != 0 ? cand_q32(c) : -1.0f)
+                                       : wave_best_total_exact(c);
         const unsigned long long hit =
             __ballot(best.nl != 0 && c.nl != 0 && c.q == best.q && c.b == best.b);
         const int bt = hit ? __shfl(ci, (int)__ffsll(hit) - 1) : -1;
