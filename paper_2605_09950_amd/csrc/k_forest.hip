@@ -547,7 +547,7 @@ __device__ Cand feature_best_compact(uint32_t* h, int B, int q, int f, const uin
     static_assert(KMAX <= 4, "compact scan keeps four bins per class in registers");
     const int lane = threadIdx.x & 63;
     const int b0 = lane * 4;
-    uint32_t hv[KMAX][4], excl[KMAX];
+    uint32_t hv[KMAX][4], excl[KMAX], a[KMAX];
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
         const uint4 v = *reinterpret_cast<const uint4*>(h + k * 256 + b0);
@@ -555,8 +555,26 @@ __device__ Cand feature_best_compact(uint32_t* h, int B, int q, int f, const uin
         hv[k][1] = v.y;
         hv[k][2] = v.z;
         hv[k][3] = v.w;
-        const uint32_t a = v.x + v.y + v.z + v.w;
-        excl[k] = wave_incl_sum(a) - a;
+        a[k] = v.x + v.y + v.z + v.w;
+    }
+    bool packed = false;
+    if constexpr (KMAX == 4) {
+        if (N < 65536u) {
+            // every prefix of a class count is below N: two classes per word,
+            // one wave scan per pair (measured faster for four classes only)
+#pragma unroll
+            for (int k = 0; k < 4; k += 2) {
+                const uint32_t pk = a[k] | (a[k + 1] << 16);
+                const uint32_t ex = wave_incl_sum(pk) - pk;
+                excl[k] = ex & 0xFFFFu;
+                excl[k + 1] = ex >> 16;
+            }
+            packed = true;
+        }
+    }
+    if (!packed) {
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) excl[k] = wave_incl_sum(a[k]) - a[k];
     }
     // the lane's thresholds worth scoring: a non-empty bin below B - 1 with
     // rows on both sides (prefix counts are rebuilt in the writing pass)
