@@ -1428,10 +1428,33 @@ __device__ uint32_t partition_rows(const ForestDev& F, const JobDev& J, const Tr
 __device__ void finalize_reg(const ForestDev& F, JobDev& J, const TreeDev& tr, uint32_t slot,
                              const SlotRec& sr, const NodeDev& nd, Cand c) {
     const int lane = threadIdx.x & 63;
+    if (F.split_rank) {
+        // FP64 ranking: only the candidates within the margin of the wave's
+        // maximum take part in the exact comparison
+        const double q = c.nl != 0 ? reg_q64(c) : -1.0;
+        double qmax = q;
 #pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-        const Cand o = shfl_xor_cand(c, m);
-        if (reg_wins_total(o, c)) c = o;
+        for (int m = 1; m < 64; m <<= 1) {
+            const double o = __shfl_xor(qmax, m);
+            qmax = o > qmax ? o : qmax;
+        }
+        if (c.nl != 0 && q < fp64_floor(qmax)) c.nl = 0;
+        const unsigned long long fin = __ballot(c.nl != 0);
+        if (__popcll(fin) == 1) {
+            c = shfl_cand(c, (int)__ffsll(fin) - 1);
+        } else {
+#pragma unroll
+            for (int m = 1; m < 64; m <<= 1) {
+                const Cand o = shfl_xor_cand(c, m);
+                if (reg_wins_total(o, c)) c = o;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) {
+            const Cand o = shfl_xor_cand(c, m);
+            if (reg_wins_total(o, c)) c = o;
+        }
     }
     const Cand best = c;
     const uint32_t child = F.next_base + 2u * (F.n_small_cur + slot);
