@@ -920,6 +920,81 @@ __global__ __launch_bounds__(256) void k_draws(ForestDev F, int level) {
 // spread a wave's atomics over the banks by bin), scans each feature and
 // writes the item's best candidate and its left class counts.  No barriers:
 // the four waves of a workgroup are independent.
+// Regression item of a node with at most kRegWaveRows distinct rows: lane i
+// holds row i (its weight w_i and w_i y_fix_i), and for each drawn feature
+// the left sums of the threshold at lane i's bin, (W_L, T_L) = the sums of
+// (w_j, w_j y_fix_j) over the rows j with bin <= b_i, come from one pass over
+// the rows with their values broadcast -- no histogram to clear and scan.
+// The thresholds scored are the occupied bins, as in reg_feature_best, and
+// ranking, margin and tie-breaks are the same, so both give one candidate.
+constexpr uint32_t kRegWaveRows = 24;
+
+__device__ __forceinline__ Cand reg_item_wave(const ForestDev& F, const SlotRec& sr, int q0,
+                                              int nf, const int* fq,
+                                              const uint8_t* const* col) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t len = sr.len, W = sr.n;
+    const int64_t T = (int64_t)((uint64_t)sr.cnode[0] | ((uint64_t)sr.cnode[1] << 32));
+    const bool have = (uint32_t)lane < len;
+    const uint64_t r = have ? ldg(sr.recs + lane) : 0ull;
+    const uint32_t row = rec_row(r), w = have ? rec_w(r) : 0u;
+    const int64_t yw = have ? (int64_t)w * ldg(sr.yfix + row) : 0;
+    Cand best;
+    best.nl = 0;
+    for (int v = 0; v < nf; ++v) {
+        const int b = have ? (int)ldg(col[v] + row) : 0x7FFF;
+        uint32_t wl = 0;
+        int64_t tl = 0;
+        for (uint32_t j = 0; j < len; ++j) {
+            const int bj = __builtin_amdgcn_readlane(b, (int)j);
+            const uint32_t wj = readlane_w(w, (int)j);
+            const int64_t tj = (int64_t)readlane64((uint64_t)yw, (int)j);
+            if (bj <= b) {
+                wl += wj;
+                tl += tj;
+            }
+        }
+        Cand c;
+        c.q = q0 + v;
+        c.f = fq[v];
+        c.b = b;
+        c.pad = 0;
+        const bool ok = have && b <= (int)sr.B - 2 && wl != W;  // wl >= w_i > 0
+        c.nl = ok ? wl : 0u;
+        c.nr = W - wl;
+        c.sl = (uint64_t)tl;
+        c.sr = (uint64_t)(T - tl);
+        const double qc = ok ? reg_q64(c) : -1.0;
+        double qmax = qc;
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) {
+            const double o = __shfl_xor(qmax, m);
+            qmax = o > qmax ? o : qmax;
+        }
+        if (qmax < 0.0) continue;
+        const double floor64 = F.split_rank ? fp64_floor(qmax) : 0.0;
+        if (!(ok && qc >= floor64)) {
+            c.nl = 0;
+            c.b = 0x7FFFFFFF;
+        }
+        const unsigned long long finm = __ballot(c.nl != 0);
+        Cand fb;
+        if (__popcll(finm) == 1) {
+            fb = shfl_cand(c, (int)__ffsll(finm) - 1);
+        } else {
+#pragma unroll
+            for (int m = 1; m < 64; m <<= 1) {
+                const Cand o = shfl_xor_cand(c, m);
+                if (reg_wins_same_feature(o, c)) c = o;
+            }
+            fb = c;
+        }
+        // draws in order: a strictly better score replaces
+        if (fb.nl != 0 && (best.nl == 0 || reg_better(fb, best))) best = fb;
+    }
+    return best;
+}
+
 // Work of a level for the node-major histogram kernels: node slots [0, n)
 // with npi items each.  Workgroup b takes the slots congruent to b mod 8 (the
 // grid is a multiple of 8), and its waves walk those slots' items in order,
@@ -986,7 +1061,8 @@ __global__ __launch_bounds__(256) void k_hist_reg(ForestDev F, int level, uint32
             fq[u] = (int)drawn[u < nf ? u : 0];
             col[u] = dcol[u < nf ? u : 0];
         }
-        const Cand best = reg_item<RB>(F, sr, q0, nf, fq, col, hist);
+        const Cand best = sr.len <= kRegWaveRows ? reg_item_wave(F, sr, q0, nf, fq, col)
+                                                 : reg_item<RB>(F, sr, q0, nf, fq, col, hist);
         if (lane == 0) F.cand[item] = best;
         alg += (unsigned long long)sr.len * (unsigned long long)(nf + (j == 0 ? 6 : 0));
     }
