@@ -100,8 +100,8 @@ struct Spec {
     int K, T, D, mtry, mode, max_iter;
     double alpha;
     uint64_t seed;
-    // regression: float targets [n] (y is null and K = 2, the two channels of
-    // the target levels); null for classification
+    // regression: float targets [n] (y is null and K = 2: a node's weighted
+    // target sum T is kept in its two class words); null for classification
     const float* yr = nullptr;
     // an earlier job of the same batch with the same inputs (X, y, n, p, K):
     // its input copy, labels and binned matrix serve this job too (-1: none)
