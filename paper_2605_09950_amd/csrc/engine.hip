@@ -917,6 +917,8 @@ ForestDev Engine::forest() const {
     F.mtry_cap = pl.mtry_cap;
     F.draw_seg = 1;
     while (F.draw_seg < (uint32_t)pl.mtry_cap && F.draw_seg < 64u) F.draw_seg <<= 1;
+    // round tables of (256 / draw_seg) node segments: at most 48 KB of LDS
+    F.draw_tab = F.draw_seg >= 8u ? 1 : 0;
     F.ctrs = at<LevelCtr>(pl.ctrs);
     F.ctr = F.ctrs;
     F.n_roots = (uint32_t)pl.T_total;
