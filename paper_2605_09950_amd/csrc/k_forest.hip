@@ -159,8 +159,10 @@ __device__ __forceinline__ uint32_t readlane_w(uint32_t v, int src) {
 }
 __device__ __forceinline__ uint64_t readlane_w(uint64_t v, int src) { return readlane64(v, src); }
 
+// tab: the wave's kDrawTab-entry LDS region for the node's permutation
+// round table (as in k_draws)
 template <int KMAX>
-__device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out) {
+__device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out, uint16_t* tab) {
     typedef Pack<KMAX> PK;
     typedef typename PK::word word;
     const int lane = threadIdx.x & 63;
@@ -200,6 +202,15 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out) {
     const uint32_t N = nd.n;
     const KeyedPerm P = make_perm(J.seed_lo, J.seed_hi, kMtry, (uint32_t)J.t, (uint32_t)tr.tau,
                                   nd.heap, 0u, (uint64_t)J.p_w);
+    // halves of at most 7 bits: the wave tabulates the round functions once,
+    // evenly, instead of every lane walking its draw through all rounds
+    const bool use_tab = P.half <= 7u;
+    if (use_tab) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the previous node's lookups
+        for (uint32_t e = (uint32_t)lane; e < (P.rounds << P.half); e += 64u)
+            tab[e] = (uint16_t)perm_round(P, e >> P.half, e & P.mask);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
     // Each lane keeps the best of its own candidates over the passes (they
     // arrive in increasing draw position, so an exact tie keeps the earlier
     // one); one wave-wide reduction per node picks the winner.  With FP32
@@ -218,7 +229,10 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out) {
     const int abase = (lane - i) << 2;  // ds_bpermute byte address of the segment's lane 0
     for (int q0 = 0; q0 < J.mtry; q0 += 64) {
         const int nq = min(64, J.mtry - q0);
-        const int myf = lane < nq ? (int)perm_apply(P, (uint32_t)(q0 + lane)) : 0;
+        const int myf =
+            lane < nq ? (int)(use_tab ? perm_apply_tab(P, tab, (uint32_t)(q0 + lane))
+                                      : perm_apply(P, (uint32_t)(q0 + lane)))
+                      : 0;
         const unsigned long long mycol =
             lane < nq ? (unsigned long long)ldg(J.colptr + myf) : 0ull;
         const int passes = (nq + G - 1) / G;
@@ -360,6 +374,7 @@ __global__ __launch_bounds__(256) void k_split_small(ForestDev F0, int level, ui
         first = 0;
         count = level_small(F0, level);
     }
+    extern __shared__ uint16_t stab[];  // [4][kDrawTab] permutation round tables
     const int lane = threadIdx.x & 63, wave = (int)uniform(threadIdx.x >> 6);
     unsigned long long alg = 0;  // statistics
     for (uint32_t li = blockIdx.x * 4u + (uint32_t)wave; li < count; li += gridDim.x * 4u) {
@@ -367,7 +382,7 @@ __global__ __launch_bounds__(256) void k_split_small(ForestDev F0, int level, ui
         o.kinds[0] = o.kinds[1] = kLeaf;
         o.child = 0;
         o.alg = 0;
-        small_node<KMAX>(F, first + li, o);
+        small_node<KMAX>(F, first + li, o, stab + (size_t)wave * kDrawTab);
         // what the children need next; the next level's lists are built from these
         if (lane == 0) F.kinds[first + li] = (uint8_t)(o.kinds[0] | o.kinds[1] << 2);
         alg += o.alg;
@@ -1807,12 +1822,13 @@ void launch_split_small(const ForestDev& F, int level, uint32_t first, uint32_t 
                         uint32_t grid_wg, hipStream_t st) {
     if (!count) return;
     const dim3 grid(grid_wg);
+    const size_t lds = (size_t)4 * kDrawTab * sizeof(uint16_t);  // four waves' round tables
     switch (F.kmax) {
-        case 2: hipLaunchKernelGGL(k_split_small<2>, grid, dim3(256), 0, st, F, level, first, count); break;
-        case 3: hipLaunchKernelGGL(k_split_small<3>, grid, dim3(256), 0, st, F, level, first, count); break;
-        case 4: hipLaunchKernelGGL(k_split_small<4>, grid, dim3(256), 0, st, F, level, first, count); break;
-        case 8: hipLaunchKernelGGL(k_split_small<8>, grid, dim3(256), 0, st, F, level, first, count); break;
-        default: hipLaunchKernelGGL(k_split_small<16>, grid, dim3(256), 0, st, F, level, first, count); break;
+        case 2: hipLaunchKernelGGL(k_split_small<2>, grid, dim3(256), lds, st, F, level, first, count); break;
+        case 3: hipLaunchKernelGGL(k_split_small<3>, grid, dim3(256), lds, st, F, level, first, count); break;
+        case 4: hipLaunchKernelGGL(k_split_small<4>, grid, dim3(256), lds, st, F, level, first, count); break;
+        case 8: hipLaunchKernelGGL(k_split_small<8>, grid, dim3(256), lds, st, F, level, first, count); break;
+        default: hipLaunchKernelGGL(k_split_small<16>, grid, dim3(256), lds, st, F, level, first, count); break;
     }
 }
 
