@@ -325,9 +325,9 @@ __device__ __forceinline__ uint32_t rec_y(uint64_t r) { return (uint32_t)(r >> 4
 // k_col_count: columns counted in LDS (64 KB) and its workgroups
 constexpr uint32_t kColCountLds = 16384;
 constexpr uint32_t kColCountGrid = 512;
-// k_draws: 16-bit round-table entries per node segment (rounds << half for
-// halves of at most 7 bits: 6 rounds of 128 entries at most)
-constexpr uint32_t kDrawTab = 768;
+// Keyed-permutation round tables in LDS: 16-bit entries per table, rounds
+// << half for halves of at most 8 bits (6 rounds of 256 entries at most)
+constexpr uint32_t kDrawTab = 1536;
 constexpr int kSmallRows = 64;  // nodes with at most this many distinct rows take the wave path
 constexpr int kWave = 64;
 constexpr uint32_t kAlgWords = 1024;  // statistics words per kernel
@@ -381,7 +381,8 @@ struct ForestDev {
     int32_t mtry_cap;     // row stride of feat
     uint32_t draw_seg;    // lanes per node in k_draws: mtry_cap rounded up to a power
                           // of two, at most 64
-    int32_t draw_tab;     // k_draws tabulates small permutations in LDS (draw_seg >= 8)
+    uint32_t draw_tab;    // k_draws: round-table entries per node segment (0: no tables;
+                          // a permutation with more entries is walked directly)
     // column-major histogram path (null when the plan has none)
     uint32_t* fcnt;       // [n_gcol] items per global column, zero between levels
     uint32_t* fpos;       // [slot][mtry_cap] an item's place within its column's items,

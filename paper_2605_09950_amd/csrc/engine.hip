@@ -917,8 +917,9 @@ ForestDev Engine::forest() const {
     F.mtry_cap = pl.mtry_cap;
     F.draw_seg = 1;
     while (F.draw_seg < (uint32_t)pl.mtry_cap && F.draw_seg < 64u) F.draw_seg <<= 1;
-    // round tables of (256 / draw_seg) node segments: at most 48 KB of LDS
-    F.draw_tab = F.draw_seg >= 8u ? 1 : 0;
+    // round tables of (256 / draw_seg) node segments, at most 48 KB of LDS:
+    // 1536 entries from 16 lanes per node, 768 for 8 lanes, none below
+    F.draw_tab = F.draw_seg >= 16u ? kDrawTab : (F.draw_seg == 8u ? kDrawTab / 2 : 0u);
     F.ctrs = at<LevelCtr>(pl.ctrs);
     F.ctr = F.ctrs;
     F.n_roots = (uint32_t)pl.T_total;

@@ -202,9 +202,9 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out, uint
     const uint32_t N = nd.n;
     const KeyedPerm P = make_perm(J.seed_lo, J.seed_hi, kMtry, (uint32_t)J.t, (uint32_t)tr.tau,
                                   nd.heap, 0u, (uint64_t)J.p_w);
-    // halves of at most 7 bits: the wave tabulates the round functions once,
-    // evenly, instead of every lane walking its draw through all rounds
-    const bool use_tab = P.half <= 7u;
+    // the wave tabulates the round functions once, evenly, instead of every
+    // lane walking its draw through all rounds (halves of up to 8 bits)
+    const bool use_tab = (P.rounds << P.half) <= kDrawTab;
     if (use_tab) {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the previous node's lookups
         for (uint32_t e = (uint32_t)lane; e < (P.rounds << P.half); e += 64u)
@@ -885,20 +885,21 @@ __device__ __forceinline__ Cand reg_item(const ForestDev& F, const SlotRec& sr, 
 // node's slot record.  A wavefront serves 64 / S nodes at once, S = the
 // plan's draws per node rounded up to a power of two (at most 64): lane l
 // takes the draws l mod S, l mod S + S, ... of node l / S, so few draws per
-// node do not leave most of the lanes idle.  With S >= 8 (F.draw_tab) and a
-// permutation of halves of at most 7 bits (at most 2^14 widened columns) the
-// node's lane segment first tabulates the round functions in LDS (rounds <<
-// half 16-bit entries, at most kDrawTab): each lane then evaluates a few
-// round functions, uniformly, instead of every round of every cycle-walking
-// step of its draws, where the segment waits for its longest walk.
+// node do not leave most of the lanes idle.  When the permutation's round
+// functions fit the segment's table (rounds << half 16-bit entries, at most
+// F.draw_tab: halves of up to 8 bits, at most 2^16 widened columns), the
+// node's lane segment first tabulates them in LDS: each lane then evaluates
+// a few round functions, uniformly, instead of every round of every
+// cycle-walking step of its draws, where the segment waits for its longest
+// walk.
 __global__ __launch_bounds__(256) void k_draws(ForestDev F, int level) {
-    extern __shared__ uint16_t dtab[];  // [256 / S][kDrawTab] when F.draw_tab
+    extern __shared__ uint16_t dtab[];  // [256 / S][F.draw_tab]
     const uint32_t count = level_slots(F, level);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t S = F.draw_seg, G = 64u / S;
     const uint32_t sub = lane / S, ql = lane % S;
     const uint32_t w0 = blockIdx.x * 4u + uniform(threadIdx.x >> 6);
-    uint16_t* tab = dtab + (size_t)(threadIdx.x / S) * kDrawTab;
+    uint16_t* tab = dtab + (size_t)(threadIdx.x / S) * F.draw_tab;
     for (uint32_t base = w0 * G; base < count; base += gridDim.x * 4u * G) {
         const uint32_t slot = base + sub;
         if (slot >= count) continue;
@@ -911,7 +912,7 @@ __global__ __launch_bounds__(256) void k_draws(ForestDev F, int level) {
         uint32_t* out = F.feat + (size_t)slot * F.mtry_cap;
         const uint8_t** oc = F.fcol + (size_t)slot * F.mtry_cap;
         uint32_t* pos = F.fpos + (size_t)slot * F.mtry_cap;
-        const bool use_tab = F.draw_tab != 0 && P.half <= 7u;  // uniform over the segment
+        const bool use_tab = (P.rounds << P.half) <= F.draw_tab;  // uniform over the segment
         if (use_tab) {
             // the previous node's lookups of this segment are done (program order)
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1838,7 +1839,7 @@ void launch_lists(const ForestDev& F, int level, uint32_t grid_wg, hipStream_t s
 }
 
 void launch_draws(const ForestDev& F, int level, uint32_t grid_wg, hipStream_t st) {
-    const size_t lds = F.draw_tab ? (size_t)(256u / F.draw_seg) * kDrawTab * sizeof(uint16_t) : 0;
+    const size_t lds = (size_t)(256u / F.draw_seg) * F.draw_tab * sizeof(uint16_t);
     hipLaunchKernelGGL(k_draws, dim3(grid_wg), dim3(256), lds, st, F, level);
 }
 
