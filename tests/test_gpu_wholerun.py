@@ -12,7 +12,8 @@ iterations replayed from the captured graph.
   * omics-shaped n=2,000, p=20,000 and mixed-type n=100,000, p=2,000: the
     whole first iteration (every tree), both ranking modes; mixed-type also
     with Permut and five replicas;
-  * omics-shaped: the whole TreeImp run; mixed-type: TreeImp iterations 1-4.
+  * omics-shaped and mixed-type: the whole TreeImp run (mixed-type also its
+    iterations 1-4 as a run stopped at max_iter = 4).
 """
 import json
 import os
@@ -184,3 +185,14 @@ def test_scale_first_four_iterations(rank):
     dig, res = run_session([jd], c["params"]["n_bins"], rank=rank)
     compare_iterations(dig[0], want["iterations"], "mixed-type iterations 1-4")
     compare_run(res[0], want, "mixed-type iterations 1-4")
+
+
+@pytest.mark.parametrize("rank", [B.RANK_FP32, B.RANK_EXACT])
+def test_scale_whole_run(rank):
+    g = golden("wholerun_scale")
+    want = g["runs"]["0"]
+    c = synth.config(4)
+    print(f"mixed-type whole run rank {rank}", flush=True)
+    dig, res = run_session([job(c, 0)], c["params"]["n_bins"], rank=rank)
+    compare_iterations(dig[0], want["iterations"], "mixed-type whole run")
+    compare_run(res[0], want, "mixed-type whole run")
