@@ -95,6 +95,19 @@ __device__ __forceinline__ uint32_t perm_apply(const KeyedPerm& P, uint32_t x) {
     return x;
 }
 
+// One pass of the Feistel network (no cycle walking): perm_apply repeats it
+// from x until the value falls below m.
+__device__ __forceinline__ uint32_t perm_pass(const KeyedPerm& P, uint32_t x) {
+    uint32_t left = x >> P.half, right = x & P.mask;
+    for (uint32_t r = 0; r < P.rounds; ++r) {
+        const uint32_t f = perm_round(P, r, right);
+        const uint32_t nl = right;
+        right = left ^ f;
+        left = nl;
+    }
+    return (left << P.half) | right;
+}
+
 // Same bijection with the round functions tabulated: tab[r << half | R].
 __device__ __forceinline__ uint32_t perm_apply_tab(const KeyedPerm& P, const uint16_t* tab,
                                                    uint32_t x) {

@@ -90,11 +90,16 @@ __device__ __forceinline__ long long sq_error_fix(const NodeDev* nodes, const ui
     return (long long)((a * a) >> s_perm);
 }
 
+// (path column, replica) pairs whose OOB sources are walked together
+constexpr int kPermGroup = 8;
+
 __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* trees,
                                                 const NodeDev* nodes, const uint32_t* cls,
                                                 int kmax, int max_depth, int lds_cols,
-                                                unsigned long long* visits) {
-    extern __shared__ uint32_t s_path[];  // [2][max_depth][256]: node, feature; [lds_cols] drops
+                                                int lds_words, unsigned long long* visits) {
+    // [2][max_depth][256]: node, feature; [lds_words]: the column drops
+    // (lds_cols of them); [kPermGroup][256]: a group's source rows
+    extern __shared__ uint32_t s_path[];
     const uint32_t g = blockIdx.y;
     const TreeDev tr = trees[g];
     JobDev& J = jobs[tr.job];
@@ -145,20 +150,54 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
     }
     const unsigned long long okm = __ballot(active && base_ok);
     if ((tid & 63) == 0 && okm) atomicAdd(&J.tstat[tr.tau * 4 + 2], (int)__popcll(okm));
-    for (int pi = 0; active && pi < len; ++pi) {
-        const uint32_t f = pf[pi * 256 + tid];
-        bool dup = false;
-        for (int pj = 0; pj < pi; ++pj) dup |= pf[pj * 256 + tid] == f;
-        if (dup) continue;
-        const uint8_t* fcol = J.colptr[f];
-        const uint32_t start = pn[pi * 256 + tid];
+    // The row's (path column, replica) pairs in order -- path positions in
+    // order, a column already on the path skipped, replicas 0..R-1 -- taken
+    // kPermGroup at a time.  First the group's source rows, pi(j) of each
+    // pair's keyed OOB permutation, by walks interleaved in one loop (a lane
+    // starts its next pair's walk as soon as one ends, so the wave waits for
+    // the lane with the longest total rather than for the longest walk of
+    // every pair), kept in LDS; then each pair's re-routing.
+    uint32_t* g_src = s_path + 2 * max_depth * 256 + lds_words;  // [kPermGroup][256]
+    const int R = J.R;
+    // next pair at or after (pi, r): a column already on the path is skipped
+    auto next_pair = [&](int& pi, int& r) {
+        if (++r < R) return;
+        r = 0;
+        for (++pi; pi < len; ++pi) {
+            const uint32_t f = pf[pi * 256 + tid];
+            bool dup = false;
+            for (int pj = 0; pj < pi; ++pj) dup |= pf[pj * 256 + tid] == f;
+            if (!dup) return;
+        }
+    };
+    auto pair_perm = [&](int pi, int r) {
+        return make_perm(J.seed_lo, J.seed_hi, kOobPerm, (uint32_t)J.t, (uint32_t)tr.tau,
+                         pf[pi * 256 + tid], (uint32_t)r << 16, (uint64_t)m);
+    };
+    int cpi = 0, cr = 0;  // the next pair to score (position 0 is never a duplicate)
+    while (active && cpi < len) {
+        // walks of the group's pairs
+        int wpi = cpi, wr = cr, k = 0;
+        KeyedPerm P = pair_perm(wpi, wr);
+        uint32_t x = j;
+        while (k < kPermGroup && wpi < len) {
+            if (m > 1u) x = perm_pass(P, x);
+            if (m <= 1u || x < m) {
+                g_src[k * 256 + tid] = m <= 1u ? 0u : x;
+                ++k;
+                next_pair(wpi, wr);
+                x = j;
+                if (wpi < len) P = pair_perm(wpi, wr);
+            }
+        }
+        // re-routing of the group's pairs; a column's drops are added when
+        // its pairs end or the group does
         int drop = 0;
         long long drop_sq = 0;  // regression: increase of the squared error
-        for (int r = 0; r < J.R; ++r) {
-            const KeyedPerm P = make_perm(J.seed_lo, J.seed_hi, kOobPerm, (uint32_t)J.t,
-                                          (uint32_t)tr.tau, f, (uint32_t)r << 16, (uint64_t)m);
-            const int sb = fcol[oob[perm_apply(P, j)]];
-            uint32_t nd_i = start;
+        for (int g = 0; g < k; ++g) {
+            const uint32_t f = pf[cpi * 256 + tid];
+            const int sb = J.colptr[f][oob[g_src[g * 256 + tid]]];
+            uint32_t nd_i = pn[cpi * 256 + tid];
             NodeDev nd = nodes[nd_i];
             ++nv;
             while (nd.feat >= 0) {
@@ -171,18 +210,25 @@ __global__ __launch_bounds__(256) void k_permut(JobDev* jobs, const TreeDev* tre
                 drop_sq += sq_error_fix(nodes, cls, kmax, nd_i, yfv, J.s_perm) - base_err;
             else
                 drop += (int)base_ok - (int)(nd.leaf_class == yv);
-        }
-        if (drop_sq) {
-            if (lds)
-                atomicAdd((unsigned long long*)&s_drop64[f], (unsigned long long)drop_sq);
-            else
-                atomicAdd((unsigned long long*)&J.imp[f], (unsigned long long)drop_sq);
-        }
-        if (drop) {
-            if (lds)
-                atomicAdd(&s_drop[f], drop);
-            else
-                atomicAdd((unsigned long long*)&J.imp[f], (unsigned long long)(int64_t)drop);
+            const int opi = cpi;
+            next_pair(cpi, cr);
+            if (cpi != opi || g + 1 == k) {
+                if (drop_sq) {
+                    if (lds)
+                        atomicAdd((unsigned long long*)&s_drop64[f], (unsigned long long)drop_sq);
+                    else
+                        atomicAdd((unsigned long long*)&J.imp[f], (unsigned long long)drop_sq);
+                }
+                if (drop) {
+                    if (lds)
+                        atomicAdd(&s_drop[f], drop);
+                    else
+                        atomicAdd((unsigned long long*)&J.imp[f],
+                                  (unsigned long long)(int64_t)drop);
+                }
+                drop = 0;
+                drop_sq = 0;
+            }
         }
     }
     if (lds) {
@@ -740,11 +786,12 @@ void launch_permut(JobDev* jobs, const TreeDev* trees, const NodeDev* nodes, con
     // per-column drop sums in LDS for jobs of at most 1024 widened columns
     // (64-bit when the batch has a regression job)
     const int lds_cols = max_pw < 1024 ? max_pw : 1024;
-    const size_t lds = (size_t)2 * max_depth * 256 * sizeof(uint32_t) +
-                       (size_t)lds_cols * (any_reg ? 8 : 4);
+    const int lds_words = lds_cols * (any_reg ? 2 : 1);
+    const size_t lds = ((size_t)2 * max_depth * 256 + lds_words + (size_t)kPermGroup * 256) *
+                       sizeof(uint32_t);
     hipLaunchKernelGGL(k_permut, dim3((unsigned)((max_n + 255) / 256), (unsigned)n_trees),
                        dim3(256), lds, st, jobs, trees, nodes, cls, kmax, max_depth, lds_cols,
-                       visits);
+                       lds_words, visits);
 }
 
 // The KL importance of job j over rows [r0, r0 + rb): base, deltas, reduce.
