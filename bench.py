@@ -440,8 +440,9 @@ def roofline_legs(jobs, pr, steps, warmup, tune, workload_name):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              "design is described in DESIGN.md and is not run.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); a run over "
+              "several GPUs (trees split across them, one all-reduce of the integer "
+              "importances per iteration) is not built.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2605_09950_amd import binding as B
