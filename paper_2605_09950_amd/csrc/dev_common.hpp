@@ -312,6 +312,7 @@ struct SlotRec {
     uint32_t len, n;       // distinct rows, weighted rows
     uint32_t mtry;         // features drawn this iteration
     uint32_t B, reg;       // bins; 1 for a regression job
+    uint32_t K, pad;       // the job's classes
     uint32_t cnode[16];    // weighted class counts (zero past K); regression: the
                            // weighted target sum T in words 0 (low) and 1 (high)
 };
@@ -388,6 +389,8 @@ struct ForestDev {
     uint32_t small_ncap;  // a node takes the wave path only below this weighted count
     int32_t kmax, parity, split_rank;
     int32_t has_cls, has_reg;  // the plan holds classification / regression jobs
+    int32_t split_k;      // a plan of more than 4 class planes that also holds jobs of at
+                          // most 4 classes: their node-major items take the 4-plane kernel
     int32_t npi;          // histogram items per large node (draw positions / fw)
     int32_t fw;           // draws per histogram item
     uint32_t small_rows;  // a node takes the wave path only up to this many distinct rows

@@ -376,6 +376,7 @@ struct Plan {
     // column-major histogram path: levels >= col_level (col_level >= max_D: none)
     int col_level = kColNever, col_waves = 0;
     bool has_cls = false, has_reg = false;
+    bool has_small_k = false;  // a classification job of at most 4 classes
     uint32_t n_gcol = 0, unit_cap = 0, gq_max = 0;
     int64_t max_n = 0;
     size_t total = 0;
@@ -475,6 +476,7 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
     for (const Spec& s : specs) {
         any_reg |= s.yr != nullptr;
         pl.has_cls |= s.yr == nullptr;
+        pl.has_small_k |= s.yr == nullptr && s.K <= 4;
     }
     pl.has_reg = any_reg;
     int col_level = any_reg ? kColNever : o.col_level;
@@ -931,6 +933,7 @@ ForestDev Engine::forest() const {
     F.split_rank = O.split_rank;
     F.has_cls = pl.has_cls ? 1 : 0;
     F.has_reg = pl.has_reg ? 1 : 0;
+    F.split_k = pl.kmax > 4 && pl.has_small_k ? 1 : 0;
     // the wave path packs class counters in 32/kmax-bit fields up to 4 classes
     // (16-bit for 2, 10-bit for 3, 8-bit for 4), 16-bit fields beyond
     F.small_ncap = pl.kmax == 4 ? 256u : (pl.kmax == 3 ? 1024u : 65536u);

@@ -940,6 +940,7 @@ __global__ __launch_bounds__(256) void k_draws(ForestDev F, int level) {
             sr->mtry = (uint32_t)J.mtry;
             sr->B = (uint32_t)J.B;
             sr->reg = (uint32_t)J.reg;
+            sr->K = (uint32_t)J.K;
         }
     }
 }
@@ -1119,6 +1120,8 @@ __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint3
         const uint32_t slot = item / npi, j = item % npi;
         const SlotRec& sr = F.srec[slot];
         if (sr.reg) continue;  // a regression node: k_hist_reg
+        // with split_k, jobs of at most 4 classes take the 4-plane instance
+        if (F.split_k && ((sr.K <= 4u) != (KMAX <= 4))) continue;
         const int q0 = (int)j * FW;
         const int mtry = (int)sr.mtry;
         if (q0 >= mtry) continue;  // the job draws fewer features this iteration
@@ -1199,6 +1202,8 @@ __global__ __launch_bounds__(256) void k_hist_tile(ForestDev F, int level, uint3
 #pragma unroll
                 for (int c = 0; c < KMAX; ++c)
                     if (lane == c) out[c] = best.nl != 0 ? best_cl[c] : 0u;
+            } else if (lane < F.kmax) {
+                out[lane] = 0u;  // the plan's class planes past this instance's
             }
         } else {
             const int bt = best.nl != 0 ? best.b : -1;
@@ -1871,6 +1876,11 @@ void launch_hist_tile(const ForestDev& F, int level, uint32_t first, uint32_t co
         }
     }
     if (!F.has_cls) return;
+    if (F.split_k) {  // the items of jobs of at most 4 classes (FW = 1 for these plans)
+        const size_t lds4 = (size_t)4 * F.fw * 4 * 256 * sizeof(uint32_t);
+        if (F.fw == 1) launch_tile_rb<4, 1>(F, level, first, count, grid, lds4, rb, st);
+        else launch_tile_rb<4, 2>(F, level, first, count, grid, lds4, rb, st);
+    }
     switch (F.kmax * 8 + F.fw) {
         case 2 * 8 + 4: launch_tile_rb<2, 4>(F, level, first, count, grid, lds, rb, st); break;
         case 2 * 8 + 2: launch_tile_rb<2, 2>(F, level, first, count, grid, lds, rb, st); break;
