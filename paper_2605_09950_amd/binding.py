@@ -338,10 +338,11 @@ def _job(X, y, n_classes, n_trees, max_depth, mtry, importance_mode, max_iter, a
 
 
 def boruta_fit_batch(jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM_BATCHED,
-                     trace=False, stats=False, perc=100, rough_fix=False):
+                     trace=False, stats=False, perc=100, rough_fix=False, tune=None):
     """jobs: list of dicts with X, y, n_classes, n_trees, max_depth and optional mtry,
     importance_mode, max_iter, alpha, seed; a regression job has y_reg (float
-    targets) instead of y and n_classes."""
+    targets) instead of y and n_classes.  tune: launch-shape fields as for
+    boruta_fit_ex."""
     arrs, cj, res, outs = [], (Job * len(jobs))(), (Result * len(jobs))(), []
     for i, jd in enumerate(jobs):
         X = np.ascontiguousarray(jd["X"], dtype=np.float32)
@@ -370,7 +371,7 @@ def boruta_fit_batch(jobs, n_bins=256, n_perm=1, split_rank=RANK_FP32, form=FORM
         outs.append(o)
     p_all = [int(np.shape(jd["X"])[1]) for jd in jobs]
     opt, keep = make_options(n_bins, n_perm, split_rank, form, trace, stats, p_all,
-                             perc=perc, rough_fix=rough_fix)
+                             tune=tune, perc=perc, rough_fix=rough_fix)
     rc = lib().boruta_fit_batch(cj, len(jobs), ctypes.byref(opt), res)
     for i, o in enumerate(outs):
         o["n_iter"], o["status"] = res[i].n_iter, res[i].status

@@ -18,6 +18,8 @@ Parts (each writes tests/golden/<part>.json):
   iters4_scale       mixed-type n=100,000, p=2,000: TreeImp iterations 1..4
                      (a run stopped at max_iter = 4)
   wholerun_scale     mixed-type n=100,000, p=2,000: the whole TreeImp run
+  wholerun_omics_permut   omics-shaped: the whole Permut run (one replica)
+  wholerun_scale_permut   mixed-type: the whole Permut run (five replicas)
 """
 import json
 import os
@@ -107,6 +109,14 @@ def part(name, threads):
                "seed": c["seed"],
                "runs": {"0": whole_run(c["X"], c["y"], c["n_classes"], c["params"], c["seed"],
                                        0, threads)}}
+    elif name in ("wholerun_omics_permut", "wholerun_scale_permut"):
+        c = synth.config(2 if "omics" in name else 4)
+        out = {"workload": ("omics-shaped n=2000 p=20000 K=2, 256 bins, 500 trees depth 12"
+                            if "omics" in name else
+                            "mixed-type n=100000 p=2000 K=4, 256 bins, 300 trees depth 16"),
+               "seed": c["seed"], "n_perm": c["params"]["n_perm"],
+               "runs": {"1": whole_run(c["X"], c["y"], c["n_classes"], c["params"], c["seed"],
+                                       1, threads)}}
     else:
         raise SystemExit(f"unknown part {name}")
     out["oracle_seconds"] = round(time.time() - t0, 1)

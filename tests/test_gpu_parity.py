@@ -125,6 +125,27 @@ def test_plain_and_batched_forms_identical():
     assert_same_run(a, b)
 
 
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_batch_mixing_class_counts_matches_oracle(path):
+    # jobs of 2, 3 and 4 classes beside one of 6 (8 class planes for the
+    # batch): the small-class jobs' node-major items take the 4-plane kernel
+    jobs = []
+    for j, K in enumerate((2, 6, 3, 4)):
+        X, y = problem(60 + j, 900 + 400 * j, 18, K)
+        jobs.append(dict(X=X, y=y, n_classes=K, n_trees=5, max_depth=9, importance_mode=j % 2,
+                         max_iter=3, seed=70 + j))
+    print(f"mixed-class batch, path {path}", flush=True)
+    batch = B.boruta_fit_batch(jobs, trace=True, tune=PATHS[path])
+    for j, jd in enumerate(jobs):
+        o = O.boruta_fit(jd["X"], jd["y"], jd["n_classes"], jd["n_trees"], jd["max_depth"],
+                         importance_mode=jd["importance_mode"], max_iter=jd["max_iter"],
+                         seed=jd["seed"], trace=True)
+        r = dict(batch["results"][j])
+        r["traces"] = [t for t in batch["traces"] if t["job"] == j]
+        assert r["status"] == 0
+        assert_same_run(r, o)
+
+
 def test_batch_equals_single_jobs():
     jobs = []
     for j in range(6):

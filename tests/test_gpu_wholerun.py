@@ -13,7 +13,7 @@ iterations replayed from the captured graph.
     whole first iteration (every tree), both ranking modes; mixed-type also
     with Permut and five replicas;
   * omics-shaped and mixed-type: the whole TreeImp run (mixed-type also its
-    iterations 1-4 as a run stopped at max_iter = 4).
+    iterations 1-4 as a run stopped at max_iter = 4) and the whole Permut run.
 """
 import json
 import os
@@ -196,3 +196,18 @@ def test_scale_whole_run(rank):
     dig, res = run_session([job(c, 0)], c["params"]["n_bins"], rank=rank)
     compare_iterations(dig[0], want["iterations"], "mixed-type whole run")
     compare_run(res[0], want, "mixed-type whole run")
+
+
+@pytest.mark.parametrize("name,cfg", [("wholerun_omics_permut", 2),
+                                      ("wholerun_scale_permut", 4)])
+def test_permut_whole_run(name, cfg):
+    # the whole Permut run with the workload's own replica count (one for the
+    # omics shape, five for mixed-type)
+    g = golden(name)
+    want = g["runs"]["1"]
+    c = synth.config(cfg)
+    assert g["n_perm"] == c["params"]["n_perm"]
+    print(f"{name}: whole Permut run, {g['n_perm']} replicas", flush=True)
+    dig, res = run_session([job(c, 1)], c["params"]["n_bins"], n_perm=g["n_perm"])
+    compare_iterations(dig[0], want["iterations"], name)
+    compare_run(res[0], want, name)
