@@ -129,6 +129,9 @@ typedef struct {
     int32_t small_rows;   /* nodes with at most this many distinct rows (and a
                              weighted count below the packed-counter limit) take
                              the wavefront path, [2, 64]; default 32              */
+    /* "needed" below: for the nodes tree level d can hold, at most the
+     * plan's capacity and n_trees * 2^d; a chosen grid size is an upper
+     * limit, lowered to what a level needs.                                */
     int32_t grid_small;   /* workgroups of the wavefront-path launch (4 nodes
                              each, grid-stride); default min(4096, needed)       */
     int32_t grid_hist;    /* workgroups of the histogram launch (4 items each),

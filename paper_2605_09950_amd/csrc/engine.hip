@@ -993,19 +993,26 @@ void Engine::enqueue_iteration() {
     F.small_out = small[0];
     F.slot_node_out = slots[0];
     launch_boot_compact(F, n_trees, st);
-    const uint32_t g_small =
-        O.grid_small ? (uint32_t)O.grid_small : level_grid(pl.small_cap, 4, 4096);
-    // a multiple of 8: workgroup b serves the node slots congruent to b mod 8
-    const uint32_t g_tile =
-        ((O.grid_hist ? (uint32_t)O.grid_hist : level_grid((uint64_t)pl.slot_cap * pl.npi, 4, 16384)) +
-         7) / 8 * 8;
-    // k_draws serves 64 / draw_seg nodes per wavefront, four wavefronts per workgroup
-    const uint32_t g_draw = level_grid(pl.slot_cap, 4 * (64u / F.draw_seg), 16384);
-    const uint32_t g_list = level_grid((uint64_t)pl.small_cap + pl.slot_cap, 4096, 1024);
-    const uint32_t g_fin =
-        O.grid_finalize ? (uint32_t)O.grid_finalize : level_grid(pl.slot_cap, 4, 4096);
     const uint32_t g_col = O.grid_col ? (uint32_t)O.grid_col : level_grid(pl.unit_cap, 1, 2048);
     for (int d = 0; d < n_levels; ++d) {
+        // Level d holds at most n_trees * 2^d nodes: the shallow levels launch
+        // no more workgroups than that bound can use (a chosen grid size is
+        // an upper limit), the deep ones are held to the plan's capacities.
+        const auto at_level = [&](uint64_t cap) {
+            return d < 32 ? std::min<uint64_t>(cap, (uint64_t)n_trees << d) : cap;
+        };
+        const uint64_t lv_small = at_level(pl.small_cap), lv_slots = at_level(pl.slot_cap);
+        const auto capped = [](int chosen, uint32_t need) {
+            return chosen ? std::min<uint32_t>((uint32_t)chosen, need) : need;
+        };
+        const uint32_t g_small = capped(O.grid_small, level_grid(lv_small, 4, 4096));
+        // a multiple of 8: workgroup b serves the node slots congruent to b mod 8
+        const uint32_t g_tile =
+            (capped(O.grid_hist, level_grid(lv_slots * pl.npi, 4, 16384)) + 7) / 8 * 8;
+        // k_draws serves 64 / draw_seg nodes per wavefront, four wavefronts per workgroup
+        const uint32_t g_draw = level_grid(lv_slots, 4 * (64u / F.draw_seg), 16384);
+        const uint32_t g_list = level_grid(lv_small + lv_slots, 4096, 1024);
+        const uint32_t g_fin = capped(O.grid_finalize, level_grid(lv_slots, 4, 4096));
         // lists, slots and row records of level d are read from parity d & 1
         // and the children of level d go to the other parity
         F.small_in = small[d & 1];
@@ -1021,16 +1028,21 @@ void Engine::enqueue_iteration() {
         // nodes, child pairs, row segments and kinds entries: without kernel
         // statistics the small-node launch runs on a second stream, beside
         // the large-node kernels, and rejoins before the lists are built.
-        const bool fork = !stats && side != nullptr;
+        // Regression nodes all take the histogram path: a plan of regression
+        // jobs alone has no small-node work.
+        const bool fork = !stats && side != nullptr && pl.has_cls;
         hipStream_t ss = st;
         if (fork) {
             HIPC(hipEventRecord(ev_fork, st));
             HIPC(hipStreamWaitEvent(side, ev_fork, 0));
             ss = side;
         }
-        size_t h = clock.begin(stats ? &stats->hist_small : nullptr, ss);
-        launch_split_small(F, d, 0, kAll, g_small, ss);
-        clock.end(h, ss);
+        size_t h = 0;
+        if (pl.has_cls) {
+            h = clock.begin(stats ? &stats->hist_small : nullptr, ss);
+            launch_split_small(F, d, 0, kAll, g_small, ss);
+            clock.end(h, ss);
+        }
         if (fork) HIPC(hipEventRecord(ev_join, side));
         const bool col = d >= pl.col_level;
         if (col) {
@@ -1038,7 +1050,7 @@ void Engine::enqueue_iteration() {
             ForestDev Fc = F;
             Fc.col_count = pl.n_gcol <= kColCountLds ? 2 : 1;
             launch_draws(Fc, d, g_draw, st);
-            launch_col_sort(Fc, d, level_grid(pl.slot_cap, 4, 16384), st);
+            launch_col_sort(Fc, d, level_grid(lv_slots, 4, 16384), st);
             h = clock.begin(stats ? &stats->hist_col : nullptr, st);
             launch_hist_col(F, d, g_col, pl.col_waves, pl.gq_max, st);
             HIPC(hipGetLastError());  // a refused launch would leave stale candidates
