@@ -34,7 +34,8 @@ void launch_binning(const float*, int64_t, int64_t, int, uint8_t*, int64_t, uint
 void launch_thresholds(int32_t, int64_t, uint64_t, int32_t, int32_t*, int32_t*, hipStream_t);
 void launch_active(JobDev*, int, hipStream_t);
 void launch_shadow(JobDev*, int, int64_t, int, hipStream_t);
-void launch_boot_draw(JobDev*, const TreeDev*, int, int64_t, hipStream_t);
+uint32_t prepare_boot_draw(int64_t);
+void launch_boot_draw(JobDev*, const TreeDev*, int, int64_t, uint32_t, hipStream_t);
 void launch_fill_u32(uint32_t*, size_t, uint32_t, hipStream_t);
 // k_forest.hip
 void launch_boot_compact(const ForestDev&, uint32_t, hipStream_t);
@@ -379,6 +380,7 @@ struct Plan {
     bool has_small_k = false;  // a classification job of at most 4 classes
     uint32_t n_gcol = 0, unit_cap = 0, gq_max = 0;
     int64_t max_n = 0;
+    uint32_t boot_chunk = 0;  // rows per workgroup of the LDS bootstrap counts (0: atomics)
     size_t total = 0;
 };
 
@@ -864,6 +866,7 @@ void Engine::setup(std::vector<int>& status) {
                 words = std::max(words, (size_t)pl.jp[j].kl_rb * pl.jp[j].pw_cap * S[j].K * 2);
         launch_fill_u32(at<uint32_t>(pl.kl_delta), words, 0u, st);
     }
+    pl.boot_chunk = prepare_boot_draw(pl.max_n);
     if (pl.col_level < pl.max_D) {
         int dev = 0, lds_max = 0;
         HIPC(hipGetDevice(&dev));
@@ -981,7 +984,7 @@ void Engine::enqueue_iteration() {
     const size_t h_whole = clock.begin(&iter_stat, st);
     launch_active(djobs, nj, st);
     launch_shadow(djobs, nj, pl.max_n, pl.max_sha, st);
-    launch_boot_draw(djobs, dtrees, (int)n_trees, pl.max_n, st);
+    launch_boot_draw(djobs, dtrees, (int)n_trees, pl.max_n, pl.boot_chunk, st);
 
     ForestDev F = forest();
     // levels 0 .. max_D - 1 search splits; nodes of depth max_D are leaves

@@ -354,16 +354,18 @@ __global__ __launch_bounds__(256) void k_active(JobDev* jobs) {
 
 // Shadow columns (Algorithm 1, "shuffle by rows"): shadow s copies active
 // column s mod p_cur through its own keyed permutation of the n rows:
-// sha[s][i] = orig[src][pi_s(i)].  One workgroup per (chunk, shadow, job);
-// the Feistel round functions are tabulated in LDS first.
-constexpr int kShadowChunk = 2048;  // rows per workgroup: 256 threads x 4 rows x 2
+// sha[s][i] = orig[src][pi_s(i)].  One workgroup per (chunk of `chunk` rows,
+// shadow, job); the Feistel round functions are tabulated in LDS first, once
+// per workgroup, so long chunks spread that cost over more rows.
+constexpr int kShadowChunk = 2048;      // shortest chunk: 256 threads x 4 rows x 2
+constexpr int kShadowChunkMax = 16384;  // longest chunk
 
-__global__ __launch_bounds__(256) void k_shadow(JobDev* jobs) {
+__global__ __launch_bounds__(256) void k_shadow(JobDev* jobs, int chunk) {
     extern __shared__ uint16_t tab[];  // rounds x 2^half round-function values
     JobDev& J = jobs[blockIdx.z];
     const int s = blockIdx.y;
     if (!J.live || s >= J.n_sha) return;
-    const int64_t r0 = (int64_t)blockIdx.x * kShadowChunk;
+    const int64_t r0 = (int64_t)blockIdx.x * chunk;
     if (r0 >= J.n) return;
     const KeyedPerm P = make_perm(J.seed_lo, J.seed_hi, kShadow, (uint32_t)J.t, (uint32_t)s, 0u,
                                   0u, (uint64_t)J.n);
@@ -375,7 +377,7 @@ __global__ __launch_bounds__(256) void k_shadow(JobDev* jobs) {
     uint8_t* dst = J.sha + (size_t)s * J.n_pad;
     // four consecutive rows per thread, one 32-bit store (rows are padded to
     // a multiple of 256; pad rows get 0)
-    for (int64_t i = r0 + 4 * (int64_t)threadIdx.x; i < r0 + kShadowChunk && i < J.n; i += 1024) {
+    for (int64_t i = r0 + 4 * (int64_t)threadIdx.x; i < r0 + chunk && i < J.n; i += 1024) {
         uint32_t v = 0;
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -388,6 +390,42 @@ __global__ __launch_bounds__(256) void k_shadow(JobDev* jobs) {
 // Bootstrap draws: draw j of tree tau is floor(u * n / 2^64) with u the
 // 64-bit half (j even: words 0-1, odd: words 2-3) of
 // Philox(word0(BOOT, 0, t), tau, j / 2, 0); multiplicities by atomics.
+// k_boot_draw_lds (n up to kBootLdsRows * kBootLdsChunks): workgroup
+// (c, tau) evaluates every draw of tree tau, counts the draws that fall in
+// its chunk of `chunk` rows with LDS atomics, then writes the chunk's
+// multiplicities, zeros included -- no global atomics.  k_boot_draw (any n):
+// one global atomic per draw into multiplicities that start from zero.
+constexpr uint32_t kBootLdsRows = 32768;  // longest chunk: 128 KB of counters
+constexpr uint32_t kBootLdsChunks = 4;    // each chunk evaluates all n draws
+
+__global__ __launch_bounds__(1024) void k_boot_draw_lds(JobDev* jobs, const TreeDev* trees,
+                                                        uint32_t chunk) {
+    extern __shared__ uint32_t cnt[];  // [chunk]
+    const TreeDev tr = trees[blockIdx.y];
+    const JobDev& J = jobs[tr.job];
+    const uint32_t n = (uint32_t)J.n;
+    const uint32_t r0 = blockIdx.x * chunk;
+    if (!J.live || r0 >= n) return;  // the whole workgroup
+    const uint32_t rows = min(chunk, n - r0);
+    for (uint32_t i = threadIdx.x; i < rows; i += blockDim.x) cnt[i] = 0u;
+    __syncthreads();
+    const uint32_t w0 = ctr_word0(kBoot, 0, (uint32_t)J.t);
+    const uint32_t pairs = (n + 1u) / 2u;
+    for (uint32_t pair = threadIdx.x; pair < pairs; pair += blockDim.x) {
+        const Philox4 o = philox4x32_10(w0, (uint32_t)tr.tau, pair, 0u, J.seed_lo, J.seed_hi);
+        // rows below r0 wrap to large values and fail the bound
+        const uint32_t a = (uint32_t)__umul64hi((uint64_t)o.y << 32 | o.x, n) - r0;
+        if (a < rows) atomicAdd(&cnt[a], 1u);
+        if (2u * pair + 1u < n) {
+            const uint32_t b = (uint32_t)__umul64hi((uint64_t)o.w << 32 | o.z, n) - r0;
+            if (b < rows) atomicAdd(&cnt[b], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t* w = J.wbuf + (size_t)tr.tau * n + r0;
+    for (uint32_t i = threadIdx.x; i < rows; i += blockDim.x) w[i] = cnt[i];
+}
+
 __global__ void k_boot_draw(JobDev* jobs, const TreeDev* trees) {
     const TreeDev tr = trees[blockIdx.y];
     const JobDev& J = jobs[tr.job];
@@ -486,14 +524,48 @@ void launch_shadow(JobDev* jobs, int n_jobs, int64_t max_n, int max_sha, hipStre
     k += k & 1u;
     const uint32_t half = k >> 1, rounds = std::max(6u, (24u + half - 1u) / half);
     const size_t lds = (size_t)(rounds << half) * sizeof(uint16_t);
+    // longer chunks while the grid keeps at least 2048 workgroups
+    int64_t chunk = kShadowChunk;
+    while (chunk < kShadowChunkMax &&
+           (max_n + 2 * chunk - 1) / (2 * chunk) * max_sha * n_jobs >= 2048)
+        chunk *= 2;
     hipLaunchKernelGGL(k_shadow,
-                       dim3((unsigned)((max_n + kShadowChunk - 1) / kShadowChunk),
-                            (unsigned)max_sha, (unsigned)n_jobs),
-                       dim3(256), lds, st, jobs);
+                       dim3((unsigned)((max_n + chunk - 1) / chunk), (unsigned)max_sha,
+                            (unsigned)n_jobs),
+                       dim3(256), lds, st, jobs, (int)chunk);
+}
+
+// Rows per workgroup of k_boot_draw_lds for jobs of at most max_n rows (the
+// chunks split max_n evenly, in multiples of 256), or 0 when max_n is beyond
+// its reach or its LDS cannot be granted (the global-atomic kernel then runs).
+uint32_t prepare_boot_draw(int64_t max_n) {
+    if (max_n < 1 || max_n > (int64_t)kBootLdsRows * kBootLdsChunks) return 0;
+    const uint32_t nc = (uint32_t)((max_n + kBootLdsRows - 1) / kBootLdsRows);
+    const uint32_t chunk = (uint32_t)(((max_n + nc - 1) / nc + 255) / 256 * 256);
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+            hipSuccess ||
+        (size_t)lds_max < chunk * sizeof(uint32_t) ||
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_boot_draw_lds),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(chunk * sizeof(uint32_t))) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return chunk;
 }
 
 void launch_boot_draw(JobDev* jobs, const TreeDev* trees, int n_trees, int64_t max_n,
-                      hipStream_t st) {
+                      uint32_t lds_chunk, hipStream_t st) {
+    if (lds_chunk) {
+        hipLaunchKernelGGL(k_boot_draw_lds,
+                           dim3((unsigned)((max_n + lds_chunk - 1) / lds_chunk),
+                                (unsigned)n_trees),
+                           dim3(1024), (size_t)lds_chunk * sizeof(uint32_t), st, jobs, trees,
+                           lds_chunk);
+        return;
+    }
     hipLaunchKernelGGL(k_boot_draw,
                        dim3((unsigned)(((max_n + 1) / 2 + 255) / 256), (unsigned)n_trees),
                        dim3(256), 0, st, jobs, trees);

@@ -146,6 +146,24 @@ def test_batch_mixing_class_counts_matches_oracle(path):
         assert_same_run(r, o)
 
 
+def test_batch_of_long_and_short_jobs_matches_oracle():
+    # bootstrap multiplicities of n = 70,001 rows are counted in three row
+    # chunks (every chunk evaluates all draws), beside a job of 3,000 rows in
+    # the same launches
+    jobs = []
+    for j, (n, K) in enumerate(((70001, 2), (3000, 3))):
+        X, y = problem(80 + j, n, 6, K)
+        jobs.append(dict(X=X, y=y, n_classes=K, n_trees=3, max_depth=5, max_iter=2, seed=90 + j))
+    batch = B.boruta_fit_batch(jobs, trace=True)
+    for j, jd in enumerate(jobs):
+        o = O.boruta_fit(jd["X"], jd["y"], jd["n_classes"], jd["n_trees"], jd["max_depth"],
+                         max_iter=jd["max_iter"], seed=jd["seed"], trace=True)
+        r = dict(batch["results"][j])
+        r["traces"] = [t for t in batch["traces"] if t["job"] == j]
+        assert r["status"] == 0
+        assert_same_run(r, o)
+
+
 def test_batch_equals_single_jobs():
     jobs = []
     for j in range(6):
