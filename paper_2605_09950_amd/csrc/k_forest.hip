@@ -1489,7 +1489,10 @@ __global__ __launch_bounds__(1024) void k_hist_col(ForestDev F, int level) {
 // (bin <= b) from the front in row order, right rows from the back in reverse
 // row order (no result depends on a node's row order, and each child segment
 // stays monotone in row index for the next level's gathers); returns the
-// left rows.  len = 0 when neither child is searched again.
+// left rows.  len = 0 when neither child is searched again.  AHEAD: the next
+// block's records are loaded while a block is placed (classification nodes;
+// the regression finalize, at more registers, measured slower with it).
+template <bool AHEAD>
 __device__ uint32_t partition_rows(const ForestDev& F, const JobDev& J, const TreeDev& tr,
                                    const NodeDev& nd, const SlotRec& sr, const Cand& best,
                                    uint32_t len) {
@@ -1499,14 +1502,33 @@ __device__ uint32_t partition_rows(const ForestDev& F, const JobDev& J, const Tr
     uint64_t* rout = J.rec[F.parity ^ 1] + (size_t)tr.tau * J.rstride + nd.seg;
     constexpr int kR = 8;  // rows per lane per block: lane l owns rows [l kR, l kR + kR)
     uint32_t runl = 0, runr = 0;
+    uint64_t rn[kR];  // with AHEAD: the next block's records, loaded one block ahead
+    if constexpr (AHEAD) {
+#pragma unroll
+        for (int u = 0; u < kR; ++u) {
+            const uint32_t i = (uint32_t)lane * kR + u;
+            rn[u] = i < len ? ldg(recs + i) : 0ull;
+        }
+    }
     for (uint32_t blk = 0; blk < len; blk += 64 * kR) {
         const uint32_t i0 = blk + (uint32_t)lane * kR;
         uint64_t r[kR];
 #pragma unroll
-        for (int u = 0; u < kR; ++u) r[u] = i0 + u < len ? ldg(recs + i0 + u) : 0ull;
+        for (int u = 0; u < kR; ++u) {
+            if constexpr (AHEAD)
+                r[u] = rn[u];
+            else
+                r[u] = i0 + u < len ? ldg(recs + i0 + u) : 0ull;
+        }
         int bb[kR];
 #pragma unroll
         for (int u = 0; u < kR; ++u) bb[u] = i0 + u < len ? (int)ldg(col + rec_row(r[u])) : 0x7FFF;
+        if constexpr (AHEAD) {
+            // the next block's records are in flight while this block is placed
+            const uint32_t j0 = i0 + 64 * kR;
+#pragma unroll
+            for (int u = 0; u < kR; ++u) rn[u] = j0 + u < len ? ldg(recs + j0 + u) : 0ull;
+        }
         uint32_t nlm = 0, nrm = 0;
 #pragma unroll
         for (int u = 0; u < kR; ++u) {
@@ -1578,7 +1600,7 @@ __device__ void finalize_reg(const ForestDev& F, JobDev& J, const TreeDev& tr, u
         return;
     }
     const bool part = (int)nd.depth + 1 < J.D;
-    const uint32_t runl = partition_rows(F, J, tr, nd, sr, best, part ? sr.len : 0u);
+    const uint32_t runl = partition_rows<false>(F, J, tr, nd, sr, best, part ? sr.len : 0u);
     if (lane == 0) {
         int kinds[2];
         split_node_reg(F, J, tr, sr.id, nd, best, runl, reg_gain_fix(best, J.s_gain), child,
@@ -1702,7 +1724,7 @@ __global__ __launch_bounds__(256) void k_split_finalize(ForestDev F0, int level,
         // the maximum depth with two or more classes (which implies two or
         // more distinct rows); other children are final leaves.
         const bool part = (int)nd.depth + 1 < J.D && (nzl >= 2 || nzr >= 2);
-        const uint32_t runl = partition_rows(F, J, tr, nd, sr, best, part ? sr.len : 0u);
+        const uint32_t runl = partition_rows<true>(F, J, tr, nd, sr, best, part ? sr.len : 0u);
         if (lane == 0) {
             int kinds[2];
             split_node(F, J, tr, id, nd, best, runl, cl, cr, cand_gain_fix(best, S, N), child,
