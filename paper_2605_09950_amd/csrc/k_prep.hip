@@ -354,18 +354,19 @@ __global__ __launch_bounds__(256) void k_active(JobDev* jobs) {
 
 // Shadow columns (Algorithm 1, "shuffle by rows"): shadow s copies active
 // column s mod p_cur through its own keyed permutation of the n rows:
-// sha[s][i] = orig[src][pi_s(i)].  One workgroup per (chunk of `chunk` rows,
-// shadow, job); the Feistel round functions are tabulated in LDS first, once
-// per workgroup, so long chunks spread that cost over more rows.
-constexpr int kShadowChunk = 2048;      // shortest chunk: 256 threads x 4 rows x 2
-constexpr int kShadowChunkMax = 16384;  // longest chunk
+// sha[s][i] = orig[src][pi_s(i)].  One workgroup per (chunk, shadow, job);
+// the Feistel round functions are tabulated in LDS first.  Short chunks keep
+// many workgroups in flight for the latency-bound cycle walks: chunks of
+// 16,384 rows (one table per 8x more rows) made the kernel 50% slower on a
+// 100,000-row job.
+constexpr int kShadowChunk = 2048;  // rows per workgroup: 256 threads x 4 rows x 2
 
-__global__ __launch_bounds__(256) void k_shadow(JobDev* jobs, int chunk) {
+__global__ __launch_bounds__(256) void k_shadow(JobDev* jobs) {
     extern __shared__ uint16_t tab[];  // rounds x 2^half round-function values
     JobDev& J = jobs[blockIdx.z];
     const int s = blockIdx.y;
     if (!J.live || s >= J.n_sha) return;
-    const int64_t r0 = (int64_t)blockIdx.x * chunk;
+    const int64_t r0 = (int64_t)blockIdx.x * kShadowChunk;
     if (r0 >= J.n) return;
     const KeyedPerm P = make_perm(J.seed_lo, J.seed_hi, kShadow, (uint32_t)J.t, (uint32_t)s, 0u,
                                   0u, (uint64_t)J.n);
@@ -377,7 +378,7 @@ __global__ __launch_bounds__(256) void k_shadow(JobDev* jobs, int chunk) {
     uint8_t* dst = J.sha + (size_t)s * J.n_pad;
     // four consecutive rows per thread, one 32-bit store (rows are padded to
     // a multiple of 256; pad rows get 0)
-    for (int64_t i = r0 + 4 * (int64_t)threadIdx.x; i < r0 + chunk && i < J.n; i += 1024) {
+    for (int64_t i = r0 + 4 * (int64_t)threadIdx.x; i < r0 + kShadowChunk && i < J.n; i += 1024) {
         uint32_t v = 0;
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -524,15 +525,10 @@ void launch_shadow(JobDev* jobs, int n_jobs, int64_t max_n, int max_sha, hipStre
     k += k & 1u;
     const uint32_t half = k >> 1, rounds = std::max(6u, (24u + half - 1u) / half);
     const size_t lds = (size_t)(rounds << half) * sizeof(uint16_t);
-    // longer chunks while the grid keeps at least 2048 workgroups
-    int64_t chunk = kShadowChunk;
-    while (chunk < kShadowChunkMax &&
-           (max_n + 2 * chunk - 1) / (2 * chunk) * max_sha * n_jobs >= 2048)
-        chunk *= 2;
     hipLaunchKernelGGL(k_shadow,
-                       dim3((unsigned)((max_n + chunk - 1) / chunk), (unsigned)max_sha,
-                            (unsigned)n_jobs),
-                       dim3(256), lds, st, jobs, (int)chunk);
+                       dim3((unsigned)((max_n + kShadowChunk - 1) / kShadowChunk),
+                            (unsigned)max_sha, (unsigned)n_jobs),
+                       dim3(256), lds, st, jobs);
 }
 
 // Rows per workgroup of k_boot_draw_lds for jobs of at most max_n rows (the
