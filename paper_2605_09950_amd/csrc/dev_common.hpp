@@ -281,6 +281,10 @@ struct JobDev {
     uint64_t* rec[2];      // [T][rstride] row records, ping-pong by level parity
     uint32_t* oob;         // [T][n] out-of-bag rows, ascending
     int32_t* tstat;        // [T][4] distinct in-bag, OOB rows, OOB correct, spare
+    uint8_t* rowmaj;       // [n_pad][rm_stride] the widened bins row-major, rebuilt every
+                           // iteration (null: the job keeps none)
+    uint32_t rm_stride;    // pw_cap rounded up to 64
+    uint32_t pad_rm;
     // per iteration, written on the device
     int32_t t, p_cur, n_sha, p_w, mtry, pad_i, n_undecided, live;
 };

@@ -34,6 +34,7 @@ void launch_binning(const float*, int64_t, int64_t, int, uint8_t*, int64_t, uint
 void launch_thresholds(int32_t, int64_t, uint64_t, int32_t, int32_t*, int32_t*, hipStream_t);
 void launch_active(JobDev*, int, hipStream_t);
 void launch_shadow(JobDev*, int, int64_t, int, hipStream_t);
+void launch_rowmaj(JobDev*, int, int64_t, int, hipStream_t);
 uint32_t prepare_boot_draw(int64_t);
 void launch_boot_draw(JobDev*, const TreeDev*, int, int64_t, uint32_t, hipStream_t);
 void launch_fill_u32(uint32_t*, size_t, uint32_t, hipStream_t);
@@ -353,6 +354,8 @@ struct Region {
 
 struct JobPlan {
     int64_t n_pad, P;
+    size_t rowmaj = 0;        // row-major widened bins (column-path plans)
+    uint32_t rm_stride = 0;
     uint32_t gbase;
     uint32_t kl_rb;  // KL importance: rows per block (0: the job does not use it)
     size_t rmean, rank;  // final ranking: per-feature mean history, rank
@@ -561,6 +564,12 @@ Plan make_plan(const std::vector<Spec>& specs, const Opts& o, bool inputs_on_dev
         pl.fitems = r.take(items * 4);
         pl.units = r.take((size_t)pl.unit_cap * sizeof(ColUnit));
         pl.gcolq = r.take(n_gcol * 4);
+        // small nodes gather many drawn columns at few rows: a row-major copy
+        // puts a row's columns in a few cache lines
+        for (JobPlan& j : pl.jp) {
+            j.rm_stride = (uint32_t)((j.pw_cap + 63) / 64 * 64);
+            j.rowmaj = r.take((size_t)j.n_pad * j.rm_stride);
+        }
     }
     pl.total = r.total + 256;
     return pl;
@@ -832,6 +841,8 @@ void Engine::setup(std::vector<int>& status) {
         J.rec[1] = at<uint64_t>(jp.rec1);
         J.oob = at<uint32_t>(jp.oob);
         J.tstat = at<int32_t>(jp.tstat);
+        J.rowmaj = jp.rm_stride ? at<uint8_t>(jp.rowmaj) : nullptr;
+        J.rm_stride = jp.rm_stride;
         J.t = 0;
         J.live = 1;
         launch_fill_u32((uint32_t*)J.state, ((size_t)s.p + 3) / 4, 0u, st);
@@ -984,6 +995,7 @@ void Engine::enqueue_iteration() {
     const size_t h_whole = clock.begin(&iter_stat, st);
     launch_active(djobs, nj, st);
     launch_shadow(djobs, nj, pl.max_n, pl.max_sha, st);
+    if (pl.col_level < pl.max_D) launch_rowmaj(djobs, nj, pl.max_n, pl.max_pw, st);
     launch_boot_draw(djobs, dtrees, (int)n_trees, pl.max_n, pl.boot_chunk, st);
 
     ForestDev F = forest();

@@ -241,6 +241,10 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out, uint
         // issue back to back; eval() masks what does not count.
         auto gather = [&](int pass) {
             const int qq = pass * G + seg;
+            if (J.rowmaj) {  // the row's drawn columns share cache lines
+                const int fq = __shfl(myf, qq < nq ? qq : 0);
+                return (int)ldg(J.rowmaj + (size_t)row * J.rm_stride + (uint32_t)fq);
+            }
             const uint8_t* col = (const uint8_t*)__shfl(mycol, qq < nq ? qq : 0);
             return (int)ldg(col + row);
         };

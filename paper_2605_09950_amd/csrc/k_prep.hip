@@ -388,6 +388,47 @@ __global__ __launch_bounds__(256) void k_shadow(JobDev* jobs) {
     }
 }
 
+// Row-major copy of the widened bins (jobs with rowmaj): rowmaj[i][c] =
+// colptr[c][i] for the iteration's p_w widened columns.  Workgroup (row tile,
+// column tile, job) moves a 64 x 64 byte tile through LDS: 16-byte column
+// reads, 16-byte row writes.
+__global__ __launch_bounds__(256) void k_rowmaj(JobDev* jobs) {
+    __shared__ uint32_t tile[64][17];  // [column][4-row words], padded
+    const JobDev& J = jobs[blockIdx.z];
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    const int c0 = (int)blockIdx.y * 64;
+    if (!J.live || !J.rowmaj || r0 >= J.n || c0 >= J.p_w) return;  // the whole workgroup
+    const int t = (int)threadIdx.x, g = t & 3;
+    {
+        const int c = c0 + (t >> 2);
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        // columns are n_pad (a multiple of 256) bytes: the 64 rows are in bounds
+        if (c < J.p_w) v = *reinterpret_cast<const uint4*>(J.colptr[c] + r0 + 16 * g);
+        uint32_t* w = &tile[t >> 2][4 * g];
+        w[0] = v.x;
+        w[1] = v.y;
+        w[2] = v.z;
+        w[3] = v.w;
+    }
+    __syncthreads();
+    const int r = t >> 2;
+    if (r0 + r >= J.n) return;
+    uint32_t o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        uint32_t x = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t word = tile[16 * g + 4 * k + u][r >> 2];
+            x |= ((word >> (8 * (r & 3))) & 0xFFu) << (8 * u);
+        }
+        o[k] = x;
+    }
+    // rm_stride is a multiple of 64: the tile's 64 columns stay in the row
+    *reinterpret_cast<uint4*>(J.rowmaj + (size_t)(r0 + r) * J.rm_stride + c0 + 16 * g) =
+        make_uint4(o[0], o[1], o[2], o[3]);
+}
+
 // Bootstrap draws: draw j of tree tau is floor(u * n / 2^64) with u the
 // 64-bit half (j even: words 0-1, odd: words 2-3) of
 // Philox(word0(BOOT, 0, t), tau, j / 2, 0); multiplicities by atomics.
@@ -529,6 +570,13 @@ void launch_shadow(JobDev* jobs, int n_jobs, int64_t max_n, int max_sha, hipStre
                        dim3((unsigned)((max_n + kShadowChunk - 1) / kShadowChunk),
                             (unsigned)max_sha, (unsigned)n_jobs),
                        dim3(256), lds, st, jobs);
+}
+
+void launch_rowmaj(JobDev* jobs, int n_jobs, int64_t max_n, int max_pw, hipStream_t st) {
+    hipLaunchKernelGGL(k_rowmaj,
+                       dim3((unsigned)((max_n + 63) / 64), (unsigned)((max_pw + 63) / 64),
+                            (unsigned)n_jobs),
+                       dim3(256), 0, st, jobs);
 }
 
 // Rows per workgroup of k_boot_draw_lds for jobs of at most max_n rows (the
