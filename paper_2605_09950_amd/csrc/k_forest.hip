@@ -160,9 +160,11 @@ __device__ __forceinline__ uint32_t readlane_w(uint32_t v, int src) {
 __device__ __forceinline__ uint64_t readlane_w(uint64_t v, int src) { return readlane64(v, src); }
 
 // tab: the wave's kDrawTab-entry LDS region for the node's permutation
-// round table (as in k_draws)
+// round table (as in k_draws); scnt: the wave's 64 LDS words for the rows'
+// one-word class counters
 template <int KMAX>
-__device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out, uint16_t* tab) {
+__device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out, uint16_t* tab,
+                           uint32_t* scnt) {
     typedef Pack<KMAX> PK;
     typedef typename PK::word word;
     const int lane = threadIdx.x & 63;
@@ -227,6 +229,14 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out, uint
     float lq = -1.0f;
     const bool fp32 = F.split_rank != 0;
     const int abase = (lane - i) << 2;  // ds_bpermute byte address of the segment's lane 0
+    if constexpr (PK::kWords == 1) {
+        // row j's counter word at scnt[j] (lane j holds row j in segment 0;
+        // every other lane holds zero): the passes read four rows' counters
+        // per LDS broadcast instead of one lane read per row
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the previous node's reads
+        scnt[lane] = (uint32_t)cv[0];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
     for (int q0 = 0; q0 < J.mtry; q0 += 64) {
         const int nq = min(64, J.mtry - q0);
         const int myf =
@@ -263,6 +273,14 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out, uint
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
                     bj[u] = __builtin_amdgcn_ds_bpermute(abase + ((j0 + u) << 2), b);
+                if constexpr (PK::kWords == 1) {
+                    const uint4 c0 = *reinterpret_cast<const uint4*>(scnt + j0);
+                    const uint4 c1 = *reinterpret_cast<const uint4*>(scnt + j0 + 4);
+                    const uint32_t cj[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc[0] += bj[u] <= b ? (word)cj[u] : (word)0;
+                    continue;
+                }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const bool take = bj[u] <= b;
@@ -379,6 +397,7 @@ __global__ __launch_bounds__(256) void k_split_small(ForestDev F0, int level, ui
         count = level_small(F0, level);
     }
     extern __shared__ uint16_t stab[];  // [4][kDrawTab] permutation round tables
+    __shared__ __align__(16) uint32_t s_cnt[4][64];  // per wave: the node's row counters
     const int lane = threadIdx.x & 63, wave = (int)uniform(threadIdx.x >> 6);
     unsigned long long alg = 0;  // statistics
     for (uint32_t li = blockIdx.x * 4u + (uint32_t)wave; li < count; li += gridDim.x * 4u) {
@@ -386,7 +405,7 @@ __global__ __launch_bounds__(256) void k_split_small(ForestDev F0, int level, ui
         o.kinds[0] = o.kinds[1] = kLeaf;
         o.child = 0;
         o.alg = 0;
-        small_node<KMAX>(F, first + li, o, stab + (size_t)wave * kDrawTab);
+        small_node<KMAX>(F, first + li, o, stab + (size_t)wave * kDrawTab, s_cnt[wave]);
         // what the children need next; the next level's lists are built from these
         if (lane == 0) F.kinds[first + li] = (uint8_t)(o.kinds[0] | o.kinds[1] << 2);
         alg += o.alg;
