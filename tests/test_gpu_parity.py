@@ -164,6 +164,16 @@ def test_batch_of_long_and_short_jobs_matches_oracle():
         assert_same_run(r, o)
 
 
+def test_job_beyond_the_lds_bootstrap_counts_matches_oracle():
+    # n = 140,000 rows: more than the LDS row chunks cover, so the bootstrap
+    # multiplicities take the global-atomic kernel
+    X, y = problem(85, 140000, 5, 2)
+    kw = dict(max_iter=2, seed=11)
+    print("n = 140,000 bootstrap by global atomics", flush=True)
+    g, o = both(X, y, 2, 3, 4, **kw)
+    assert_same_run(g, o)
+
+
 def test_batch_equals_single_jobs():
     jobs = []
     for j in range(6):
