@@ -13,7 +13,8 @@ iterations replayed from the captured graph.
     whole first iteration (every tree), both ranking modes; mixed-type also
     with Permut and five replicas;
   * omics-shaped and mixed-type: the whole TreeImp run (mixed-type also its
-    iterations 1-4 as a run stopped at max_iter = 4) and the whole Permut run.
+    iterations 1-4 as a run stopped at max_iter = 4) and the whole Permut run
+    (one replica for the omics shape, five for mixed-type).
 """
 import json
 import os
