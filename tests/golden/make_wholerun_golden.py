@@ -20,6 +20,7 @@ Parts (each writes tests/golden/<part>.json):
   wholerun_scale     mixed-type n=100,000, p=2,000: the whole TreeImp run
   wholerun_omics_permut   omics-shaped: the whole Permut run (one replica)
   wholerun_scale_permut   mixed-type: the whole Permut run (five replicas)
+  wholerun_madelon_kl     MADELON-like: the whole Permut-KL run (Algorithm 3)
 """
 import json
 import os
@@ -117,6 +118,12 @@ def part(name, threads):
                "seed": c["seed"], "n_perm": c["params"]["n_perm"],
                "runs": {"1": whole_run(c["X"], c["y"], c["n_classes"], c["params"], c["seed"],
                                        1, threads)}}
+    elif name == "wholerun_madelon_kl":
+        c = synth.config(1)
+        out = {"workload": "MADELON-like n=10000 p=500 K=3, 256 bins, 200 trees depth 12",
+               "seed": c["seed"],
+               "runs": {"2": whole_run(c["X"], c["y"], c["n_classes"], c["params"], c["seed"],
+                                       2, threads)}}
     else:
         raise SystemExit(f"unknown part {name}")
     out["oracle_seconds"] = round(time.time() - t0, 1)

@@ -38,11 +38,13 @@ def problem(seed, n, p, K, kind="normal"):
     return X, y
 
 
-def test_planted_small_workload():
+@pytest.mark.parametrize("mode", [B.TREEIMP, B.PERMUT, B.PERMUT_KL])
+def test_planted_small_workload(mode):
+    # the small planted workload's whole run (20 iterations) in each mode
     c = synth.config(0)
     pr = c["params"]
     g, o = both(c["X"], c["y"], 2, pr["n_trees"], pr["max_depth"], max_iter=pr["max_iter"],
-                seed=c["seed"], n_bins=pr["n_bins"])
+                seed=c["seed"], n_bins=pr["n_bins"], importance_mode=mode)
     assert_same_run(g, o)
 
 
