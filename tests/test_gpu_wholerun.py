@@ -7,7 +7,7 @@ bench.py: a session over device-resident inputs and a caller workspace,
 iterations replayed from the captured graph.
 
   * MADELON-like n=10,000, p=500: whole runs in TreeImp and Permut, FP32 and
-    exact-only ranking;
+    exact-only ranking, and in Permut-KL;
   * the 64-job batch: every job's whole run, all jobs in one session;
   * omics-shaped n=2,000, p=20,000 and mixed-type n=100,000, p=2,000: the
     whole first iteration (every tree), both ranking modes; mixed-type also
@@ -96,6 +96,17 @@ def test_madelon_whole_run(mode, rank):
     dig, res = run_session([job(c, mode)], c["params"]["n_bins"], rank=rank)
     compare_iterations(dig[0], want["iterations"], f"madelon mode {mode}")
     compare_run(res[0], want, f"madelon mode {mode}")
+
+
+def test_madelon_whole_run_permut_kl():
+    # the whole run with Algorithm 3's importance
+    g = golden("wholerun_madelon_kl")
+    want = g["runs"]["2"]
+    c = synth.config(1)
+    print("madelon whole run Permut-KL", flush=True)
+    dig, res = run_session([job(c, 2)], c["params"]["n_bins"])
+    compare_iterations(dig[0], want["iterations"], "madelon Permut-KL")
+    compare_run(res[0], want, "madelon Permut-KL")
 
 
 def test_madelon_whole_run_back_to_back():
