@@ -329,7 +329,7 @@ __device__ void small_node(const ForestDev& F, uint32_t idx, SmallOut& out, uint
             }
         };
         // bins of kPF passes are in flight while the previous kPF are scored
-        constexpr int kPF = 4;
+        constexpr int kPF = 2;
         int bq[kPF];
 #pragma unroll
         for (int u = 0; u < kPF; ++u) bq[u] = gather(u);
